@@ -1,0 +1,81 @@
+"""Pins for the oracle's finite-difference gradient of 2F.
+
+* in f and fdot the resampled series is fixed, so the derivative has a
+  closed form (the single-bin sum differentiated under the sum), derived
+  here independently of the finite differences;
+* in alpha and delta the series is re-resampled; the Richardson value must
+  agree with plain central differences at two step sizes;
+* at the noise-free peak of an on-bin matched injection of a stationary
+  detector, d2F/df vanishes by symmetry.
+"""
+import numpy as np
+
+from oracle import fstat as of
+from oracle import grad as og
+from oracle.inject import signal
+from oracle.interp import KERNEL_LANCZOS
+from paper_0912_4255_amd.synth import DET_H, Ephemeris, Injection, Segment, gaussian_noise
+
+EPH = Ephemeris()
+SEG = Segment(n=21600, dt=4.0, t_start=0.0, f_het=100.0)
+DF = 1.0 / (2 * SEG.n * SEG.dt)
+NOGAP = np.zeros((0, 2), np.int64)
+
+
+def _problem(seed=1, h0=0.5, eph=EPH):
+    inj = Injection(h0=h0, cosi=0.2, psi=-0.3, phi0=2.0, f0=SEG.f_het + 3000.3 * DF,
+                    fdot=-4e-10, alpha=2.1, delta=-0.4)
+    x = gaussian_noise(np.random.default_rng(seed), SEG.n, 1.0) + signal(SEG, inj, eph, DET_H)
+    return og.PointProblem([x], [NOGAP], SEG, [DET_H], eph, KERNEL_LANCZOS, 8), inj
+
+
+def _analytic_f_fdot(problem, theta):
+    f, fdot, alpha, delta = theta
+    rs = problem.resampled(alpha, delta)
+    A, B, C = of.antenna_sums(rs, problem.dets)
+    D = A * B - C * C
+    ya, yb = of.integrands(rs, problem.dets, fdot)
+    t = np.arange(SEG.n) * SEG.dt
+    e = np.exp(-2j * np.pi * (f - SEG.f_het) * t)
+    u = rs[0]["T"] ** 2 / 2 + rs[0]["tm"] * rs[0]["T"]
+    fa, fb = np.sum(ya * e), np.sum(yb * e)
+    out = []
+    for w in (-2j * np.pi * t, -2j * np.pi * u):
+        dfa, dfb = np.sum(w * ya * e), np.sum(w * yb * e)
+        d = 2.0 * (2 * B * np.real(np.conj(fa) * dfa) + 2 * A * np.real(np.conj(fb) * dfb)
+                   - 2 * C * np.real(dfa * np.conj(fb) + fa * np.conj(dfb))) / D
+        out.append(d)
+    return np.array(out)
+
+
+def test_fd_matches_closed_form_in_f_and_fdot():
+    prob, inj = _problem()
+    theta = np.array([inj.f0 + 0.2 * DF, inj.fdot + 3e-12, inj.alpha, inj.delta])
+    g = og.gradient(prob, theta)
+    ref = _analytic_f_fdot(prob, theta)
+    assert np.max(np.abs(g[:2] - ref) / np.abs(ref)) < 1e-6
+
+
+def test_richardson_consistent_in_sky():
+    prob, inj = _problem(seed=2)
+    theta = np.array([inj.f0, inj.fdot, inj.alpha + 2e-4, inj.delta - 1e-4])
+    h = og.default_steps(SEG)
+    g = og.gradient(prob, theta)
+    for i in (2, 3):
+        c1 = og.central(prob.twoF, theta, i, h[i])
+        c2 = og.central(prob.twoF, theta, i, h[i] / 4)
+        assert abs(c1 - g[i]) < 1e-4 * abs(g[i]) + 1e-3
+        assert abs(c2 - g[i]) < 1e-4 * abs(g[i]) + 1e-3
+
+
+def test_peak_has_zero_frequency_derivative():
+    eph0 = Ephemeris(au_c=0.0, re_c=0.0)
+    inj = Injection(h0=1.0, cosi=0.5, psi=0.1, phi0=0.3, f0=SEG.f_het + 2000 * DF,
+                    fdot=0.0, alpha=1.0, delta=0.5)
+    x = signal(SEG, inj, eph0, DET_H)
+    prob = og.PointProblem([x], [NOGAP], SEG, [DET_H], eph0, KERNEL_LANCZOS, 8)
+    theta = np.array([inj.f0, 0.0, inj.alpha, inj.delta])
+    g = og.gradient(prob, theta)
+    F = prob.twoF(theta)
+    T0 = SEG.n * SEG.dt
+    assert abs(g[0]) * (1.0 / T0) < 1e-6 * F
