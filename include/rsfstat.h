@@ -1,0 +1,211 @@
+/*
+ * rsfstat.h -- C ABI of librsfstat: barycentric resampling and the FFT
+ * F-statistic on AMD gfx950 (MI355X).
+ *
+ * Method: Patel, Siemens, Dupuis & Betzwieser, "Implementation of barycentric
+ * resampling for continuous wave searches in gravitational wave data"
+ * (arXiv:0912.4255), Sec. III.A.2 (the seven-step resampling procedure) and
+ * Sec. II (the F-statistic, eqs. eq6, eq9, eq10).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Time t is measured from the segment start; the segment starts t_start
+ *   seconds after the ephemeris epoch.  Samples are x_h[j] at t_j = j dt.
+ * - x_h is the heterodyned, downsampled complex series x(t) exp(-2 pi i f_het t)
+ *   (heterodyne sign of the worked example in Sec. III.A.1), complex64
+ *   interleaved (re, im), zero-filled inside gaps (Sec. III.B, "Gaps in the
+ *   data").
+ * - The SSB grid is t_b^k = k dt, k = 0..n-1.  T^k is the detector time with
+ *   T^k + t_m(T^k) = t_b^k (eq. eq21), t_m = n0 . r_d / c (eq. eq4pt2).
+ * - Spindown phase Phi_s = 2 pi fdot (T^2/2 + t_m T) (eq. eq4pt1, s = 1),
+ *   applied as exp(-i Phi_s).
+ * - Output bin s (signed) is the frequency f_het + s / (n_fft dt); bands are
+ *   reported in ascending s.
+ * - 2F = 2 (B'|f_a|^2 + A'|f_b|^2 - 2 C' Re(f_a f_b^*)) / D' with
+ *   noise-weighted sums (weights 1/sigma_X^2) over detectors (eq. eq6).
+ *
+ * Memory and streams
+ * ------------------
+ * Every array argument is caller-owned DEVICE memory unless marked "host".
+ * The library allocates device memory only in rsf_plan_create (constant
+ * tables); every other call uses the caller's workspace `ws` of at least the
+ * size reported by rsf_workspace_size.  `stream` is a hipStream_t passed as
+ * void* (NULL = the default stream); all work is enqueued asynchronously on
+ * it and no call synchronises the device.
+ *
+ * Errors
+ * ------
+ * Every call returns RSF_OK (0) or a negative rsf_status; the message of the
+ * last failure on the calling thread is available from rsf_last_error().
+ * Nothing aborts or throws across this interface.  A template whose Gram
+ * determinant D' is not positive (e.g. an all-gap segment) yields NaN outputs
+ * and sets RSF_FLAG_DEGENERATE in the flags word readable with rsf_get_flags.
+ */
+#ifndef RSFSTAT_H
+#define RSFSTAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RSF_MAX_DET 4
+#define RSF_MAX_TAPS 32
+
+typedef enum rsf_status {
+    RSF_OK = 0,
+    RSF_EINVAL = -1,        /* null pointer, non-positive size, non-finite parameter, band outside data */
+    RSF_EUNSUPPORTED = -2,  /* FFT length not 7-smooth or not decomposable; taps odd or > 32 */
+    RSF_EWORKSPACE = -3,    /* workspace smaller than rsf_workspace_size */
+    RSF_EHIP = -4           /* HIP runtime or launch error (message kept) */
+} rsf_status;
+
+enum { RSF_KERNEL_LANCZOS = 0, RSF_KERNEL_DIRICHLET = 1 };
+enum { RSF_NFFT_TWICE = 0, RSF_NFFT_SMOOTH7 = 1 };
+enum { RSF_STORE_F32 = 0, RSF_STORE_F16 = 1 };
+enum { RSF_MODE_PLAIN = 0, RSF_MODE_BATCHED = 1 };
+enum { RSF_ENTRY_RESAMPLE = 0, RSF_ENTRY_FSTAT = 1, RSF_ENTRY_POINT = 2, RSF_ENTRY_BACKWARD = 3 };
+enum { RSF_FLAG_DEGENERATE = 1, RSF_FLAG_WINDOW = 2 };
+
+/* Interferometer site: latitude, longitude (rad, east positive), azimuth of
+ * the arm bisector counter-clockwise from local East (rad; arms at +-45 deg),
+ * and the noise variance sigma^2 = E|n|^2 per complex sample. */
+typedef struct rsf_detector {
+    double lat, lon, gamma, sigma2;
+} rsf_detector;
+
+/* Analytic ephemeris: circular orbit of radius au_c light-seconds in the
+ * ecliptic (obliquity eps) with period p_orb, spherical Earth of radius re_c
+ * light-seconds rotating with sidereal period p_sid; lambda0 and theta0 are
+ * the orbital longitude and Greenwich sidereal angle at the epoch. */
+typedef struct rsf_ephemeris {
+    double au_c, re_c, p_orb, p_sid, eps, lambda0, theta0;
+} rsf_ephemeris;
+
+typedef struct rsf_plan_desc {
+    int32_t n_det;                   /* 1..RSF_MAX_DET */
+    int32_t nfft_policy;             /* RSF_NFFT_TWICE: 2n; RSF_NFFT_SMOOTH7: smallest 2^a3^b5^c7^d >= 2n */
+    int32_t kernel;                  /* RSF_KERNEL_LANCZOS or RSF_KERNEL_DIRICHLET */
+    int32_t taps;                    /* even, 2..RSF_MAX_TAPS */
+    int32_t storage;                 /* RSF_STORE_F32 or RSF_STORE_F16 (resampled series kept as half2) */
+    int32_t reserved;
+    int64_t n;                       /* samples per detector */
+    double dt;                       /* sampling interval, s */
+    double t_start;                  /* segment start after the ephemeris epoch, s */
+    double f_het;                    /* heterodyne frequency, Hz */
+    double f_lo, f_hi;               /* reported band [f_lo, f_hi), Hz, inside f_het +- 1/(2 dt) */
+    rsf_ephemeris eph;
+    rsf_detector det[RSF_MAX_DET];
+} rsf_plan_desc;
+
+/* One data segment: per detector a device pointer to complex64[n] and a
+ * device int64[n_gaps][2] list of half-open, sorted, disjoint gap ranges in
+ * samples (may be NULL when n_gaps is 0). */
+typedef struct rsf_segment {
+    const void* x[RSF_MAX_DET];
+    const int64_t* gaps[RSF_MAX_DET];
+    int32_t n_gaps[RSF_MAX_DET];
+} rsf_segment;
+
+/* Outputs of rsf_resample for one detector, each [n_sky][...] row-major:
+ * z: complex64[n] resampled series z~(t_b^k) (eq. eq19's z(t_b^k));
+ * a, b: float32[n] beam patterns at T^k; tm: float64[n] t_m,k = t_b^k - T^k;
+ * mask: uint32[ceil(n/32)] bit k = nearest-sample mask m~_k;
+ * abc: float64[3] unweighted A' = sum m~ a^2, B' = sum m~ b^2, C' = sum m~ a b.
+ * Any pointer may be NULL to skip that output. */
+typedef struct rsf_resampled {
+    void* z;
+    float* a;
+    float* b;
+    double* tm;
+    uint32_t* mask;
+    double* abc;
+} rsf_resampled;
+
+typedef struct rsf_topk_entry {
+    float twoF;
+    int32_t sky;
+    int32_t fdot;
+    int32_t bin;     /* index into the ascending band, 0..n_out-1 */
+} rsf_topk_entry;
+
+typedef struct rsf_plan rsf_plan;
+
+/* Create a plan: validates the descriptor, chooses the FFT factorisation
+ * n_fft = L1 * L2 and uploads constant tables (the only device allocation
+ * the library makes).  *out is NULL on failure. */
+int rsf_plan_create(rsf_plan** out, const rsf_plan_desc* desc);
+int rsf_plan_destroy(rsf_plan* plan);
+
+/* Host outputs (any may be NULL): FFT length, first signed bin and number of
+ * bins of the reported band, FFT factors (L1 = first-pass length over the
+ * slow input index, L2 = second-pass length), frequency spacing df. */
+int rsf_plan_query(const rsf_plan* plan, int64_t* n_fft, int64_t* bin_lo, int64_t* n_out,
+                   int32_t* l1, int32_t* l2, double* df);
+
+/* Workspace bytes for an entry point (RSF_ENTRY_*) with the given numbers of
+ * sky positions, spindowns (or candidates for POINT/BACKWARD) and mode. */
+int rsf_workspace_size(const rsf_plan* plan, int entry, int64_t n_sky, int64_t n_fdot, int mode,
+                       size_t* bytes);
+
+/* Steps 1-5 of Sec. III.A.2 for every sky position and detector:
+ * heterodyne correction on the detector grid (z = x_h exp(-2 pi i f_het t_m),
+ * eqs. absorb/Fa3), inversion of eq. eq21, interpolation of z at T^k, beam
+ * patterns a, b at T^k and the masked antenna sums (eqs. eq9/eq10).
+ * sky: device float64[n_sky][2] = (alpha, delta) in rad (equatorial).
+ * out: host array of n_det rsf_resampled descriptors. */
+int rsf_resample(const rsf_plan* plan, const rsf_segment* seg, const double* sky, int64_t n_sky,
+                 const rsf_resampled* out, void* ws, size_t ws_bytes, void* stream);
+
+/* The full path (Sec. III.A.2 steps 1-7) for n_sky x n_fdot templates:
+ * 2F over the reported band for every (sky, fdot).
+ * fdot: device float64[n_fdot] (Hz/s).  twoF: device float32
+ * [n_sky * n_fdot][n_out], row = sky * n_fdot + fdot, ascending frequency.
+ * mode RSF_MODE_PLAIN launches the two FFT passes once per template;
+ * RSF_MODE_BATCHED shares the resampled inputs between spindowns and groups
+ * templates into fewer, larger launches.  Both give identical results. */
+int rsf_fstat(const rsf_plan* plan, const rsf_segment* seg, const double* sky, int64_t n_sky,
+              const double* fdot, int64_t n_fdot, int mode, float* twoF,
+              void* ws, size_t ws_bytes, void* stream);
+
+/* As rsf_fstat (batched) but returning only the k largest 2F values over all
+ * templates and bins, descending, ties broken by lower (sky, fdot, bin).
+ * topk: device rsf_topk_entry[k], 1 <= k <= 64. */
+int rsf_fstat_topk(const rsf_plan* plan, const rsf_segment* seg, const double* sky, int64_t n_sky,
+                   const double* fdot, int64_t n_fdot, int k, rsf_topk_entry* topk,
+                   void* ws, size_t ws_bytes, void* stream);
+
+/* 2F at continuous parameters: theta device float64[n][4] = (f Hz, fdot Hz/s,
+ * alpha, delta rad); f_a(f) = sum_k y^a_k exp(-2 pi i (f - f_het) k dt) on the
+ * resampled series of each candidate's own sky (equal to FFT bin s when
+ * f = f_het + s df).  twoF: device float32[n]. */
+int rsf_fstat_point(const rsf_plan* plan, const rsf_segment* seg, const double* theta, int64_t n,
+                    float* twoF, void* ws, size_t ws_bytes, void* stream);
+
+/* Vector-Jacobian product of rsf_fstat_point: g_theta[i][:] = g_twoF[i] *
+ * d2F/d(f, fdot, alpha, delta) at theta[i], through the F-statistic, the
+ * Fourier sum, the spindown phase, the interpolation, the heterodyne
+ * correction, the beam patterns and the timing inversion (dT/dtheta =
+ * -(dt_m/dtheta)/(1 + dt_m/dt)).  The resampled series is recomputed, never
+ * stored.  g_twoF: device float32[n]; twoF: device float32[n] or NULL;
+ * g_theta: device float64[n][4]. */
+int rsf_fstat_backward(const rsf_plan* plan, const rsf_segment* seg, const double* theta, int64_t n,
+                       const float* g_twoF, float* twoF, double* g_theta,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/* Copy the device flags word (RSF_FLAG_*) of the workspace to *flags (host)
+ * and clear it; synchronises `stream`. */
+int rsf_get_flags(const rsf_plan* plan, void* ws, uint32_t* flags, void* stream);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* rsf_last_error(void);
+
+/* ABI version, currently 1. */
+int rsf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RSFSTAT_H */

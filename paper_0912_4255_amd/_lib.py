@@ -1,0 +1,99 @@
+"""ctypes mirror of include/rsfstat.h and the loader of librsfstat.so.
+
+Argument marshalling only: no arithmetic of the method happens here.  The
+loader raises if the shared library is missing; there is no fallback path.
+"""
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librsfstat.so")
+
+RSF_MAX_DET = 4
+RSF_OK, RSF_EINVAL, RSF_EUNSUPPORTED, RSF_EWORKSPACE, RSF_EHIP = 0, -1, -2, -3, -4
+RSF_MODE_PLAIN, RSF_MODE_BATCHED = 0, 1
+RSF_ENTRY_RESAMPLE, RSF_ENTRY_FSTAT, RSF_ENTRY_POINT, RSF_ENTRY_BACKWARD = 0, 1, 2, 3
+RSF_FLAG_DEGENERATE, RSF_FLAG_WINDOW = 1, 2
+
+EXPORTS = [
+    "rsf_plan_create", "rsf_plan_destroy", "rsf_plan_query", "rsf_workspace_size",
+    "rsf_resample", "rsf_fstat", "rsf_fstat_topk", "rsf_fstat_point", "rsf_fstat_backward",
+    "rsf_get_flags", "rsf_last_error", "rsf_version",
+]
+
+
+class Detector(C.Structure):
+    _fields_ = [("lat", C.c_double), ("lon", C.c_double), ("gamma", C.c_double), ("sigma2", C.c_double)]
+
+
+class Ephemeris(C.Structure):
+    _fields_ = [("au_c", C.c_double), ("re_c", C.c_double), ("p_orb", C.c_double), ("p_sid", C.c_double),
+                ("eps", C.c_double), ("lambda0", C.c_double), ("theta0", C.c_double)]
+
+
+class PlanDesc(C.Structure):
+    _fields_ = [("n_det", C.c_int32), ("nfft_policy", C.c_int32), ("kernel", C.c_int32),
+                ("taps", C.c_int32), ("storage", C.c_int32), ("reserved", C.c_int32),
+                ("n", C.c_int64), ("dt", C.c_double), ("t_start", C.c_double), ("f_het", C.c_double),
+                ("f_lo", C.c_double), ("f_hi", C.c_double), ("eph", Ephemeris),
+                ("det", Detector * RSF_MAX_DET)]
+
+
+class Segment(C.Structure):
+    _fields_ = [("x", C.c_void_p * RSF_MAX_DET), ("gaps", C.c_void_p * RSF_MAX_DET),
+                ("n_gaps", C.c_int32 * RSF_MAX_DET)]
+
+
+class Resampled(C.Structure):
+    _fields_ = [("z", C.c_void_p), ("a", C.c_void_p), ("b", C.c_void_p), ("tm", C.c_void_p),
+                ("mask", C.c_void_p), ("abc", C.c_void_p)]
+
+
+class TopkEntry(C.Structure):
+    _fields_ = [("twoF", C.c_float), ("sky", C.c_int32), ("fdot", C.c_int32), ("bin", C.c_int32)]
+
+
+_lib = None
+
+
+def load(path=None):
+    """Load librsfstat.so (built in-tree by paper_0912_4255_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise RuntimeError(f"librsfstat.so not found at {path}: build it with "
+                           "`python -m paper_0912_4255_amd.build` (no fallback path exists)")
+    lib = C.CDLL(path)
+    vp, i64, i32, sz = C.c_void_p, C.c_int64, C.c_int, C.c_size_t
+    lib.rsf_plan_create.argtypes = [C.POINTER(vp), C.POINTER(PlanDesc)]
+    lib.rsf_plan_destroy.argtypes = [vp]
+    lib.rsf_plan_query.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64),
+                                   C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double)]
+    lib.rsf_workspace_size.argtypes = [vp, i32, i64, i64, i32, C.POINTER(sz)]
+    lib.rsf_resample.argtypes = [vp, C.POINTER(Segment), vp, i64, C.POINTER(Resampled), vp, sz, vp]
+    lib.rsf_fstat.argtypes = [vp, C.POINTER(Segment), vp, i64, vp, i64, i32, vp, vp, sz, vp]
+    lib.rsf_fstat_topk.argtypes = [vp, C.POINTER(Segment), vp, i64, vp, i64, i32, vp, vp, sz, vp]
+    lib.rsf_fstat_point.argtypes = [vp, C.POINTER(Segment), vp, i64, vp, vp, sz, vp]
+    lib.rsf_fstat_backward.argtypes = [vp, C.POINTER(Segment), vp, i64, vp, vp, vp, vp, sz, vp]
+    lib.rsf_get_flags.argtypes = [vp, vp, C.POINTER(C.c_uint32), vp]
+    lib.rsf_last_error.restype = C.c_char_p
+    lib.rsf_last_error.argtypes = []
+    lib.rsf_version.argtypes = []
+    for name in EXPORTS:
+        getattr(lib, name).restype = C.c_int if name != "rsf_last_error" else C.c_char_p
+    _lib = lib
+    return lib
+
+
+class RsfError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"rsf error {code}: {msg}")
+        self.code = code
+
+
+def check(rc):
+    if rc != RSF_OK:
+        raise RsfError(rc, load().rsf_last_error().decode())
+    return rc

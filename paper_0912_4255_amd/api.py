@@ -1,0 +1,155 @@
+"""Thin Python binding of librsfstat: the same entry points as the C ABI
+(rsf_resample, rsf_fstat, rsf_fstat_topk, rsf_fstat_point,
+rsf_fstat_backward), with torch tensors supplying device memory and the
+current stream.  Only argument marshalling happens here; every step of the
+method runs in the HIP kernels behind the C ABI.
+"""
+import ctypes as C
+
+import torch
+
+from . import _lib as L
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def _need_cuda(t, dtype, name):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous CUDA tensor of dtype {dtype}")
+
+
+def plan_desc_from_workload(w):
+    """rsf_plan_desc from a paper_0912_4255_amd.synth.Workload."""
+    d = L.PlanDesc()
+    d.n_det = len(w.detectors)
+    d.nfft_policy = w.nfft_policy
+    d.kernel = w.kernel
+    d.taps = w.taps
+    d.storage = w.storage
+    d.n = w.segment.n
+    d.dt = w.segment.dt
+    d.t_start = w.segment.t_start
+    d.f_het = w.segment.f_het
+    d.f_lo = w.f_lo
+    d.f_hi = w.f_hi
+    e = w.eph
+    d.eph = L.Ephemeris(e.au_c, e.re_c, e.p_orb, e.p_sid, e.eps, e.lambda0, e.theta0)
+    for i, det in enumerate(w.detectors):
+        d.det[i] = L.Detector(det.lat, det.lon, det.gamma, det.sigma2)
+    return d
+
+
+class Plan:
+    """An rsf_plan: FFT factorisation and constant tables for one segment
+    shape, detector set and interpolation kernel."""
+
+    def __init__(self, workload=None, desc=None):
+        self.lib = L.load()
+        self.desc = desc if desc is not None else plan_desc_from_workload(workload)
+        self.n_det = self.desc.n_det
+        self.n = self.desc.n
+        self._p = C.c_void_p()
+        L.check(self.lib.rsf_plan_create(C.byref(self._p), C.byref(self.desc)))
+        n_fft, s_lo, n_out = C.c_int64(), C.c_int64(), C.c_int64()
+        l1, l2, df = C.c_int32(), C.c_int32(), C.c_double()
+        L.check(self.lib.rsf_plan_query(self._p, C.byref(n_fft), C.byref(s_lo), C.byref(n_out),
+                                        C.byref(l1), C.byref(l2), C.byref(df)))
+        self.n_fft, self.s_lo, self.n_out = n_fft.value, s_lo.value, n_out.value
+        self.fft_l1, self.fft_l2, self.df = l1.value, l2.value, df.value
+
+    def close(self):
+        if self._p:
+            self.lib.rsf_plan_destroy(self._p)
+            self._p = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers ---------------------------------------------------------
+    def workspace_bytes(self, entry, n_sky=1, n_fdot=1, mode=L.RSF_MODE_BATCHED):
+        b = C.c_size_t()
+        L.check(self.lib.rsf_workspace_size(self._p, entry, n_sky, n_fdot, mode, C.byref(b)))
+        return b.value
+
+    def workspace(self, entry, n_sky=1, n_fdot=1, mode=L.RSF_MODE_BATCHED, device="cuda"):
+        return torch.empty(max(1, self.workspace_bytes(entry, n_sky, n_fdot, mode)), dtype=torch.uint8,
+                           device=device)
+
+    def segment(self, xs, gaps=None):
+        """rsf_segment from per-detector complex64 series and int64 [g][2] gap lists."""
+        if len(xs) != self.n_det:
+            raise ValueError("one series per detector is required")
+        seg = L.Segment()
+        keep = []
+        for i, x in enumerate(xs):
+            _need_cuda(x, torch.complex64, "x")
+            if x.numel() != self.n:
+                raise ValueError("series length does not match the plan")
+            seg.x[i] = x.data_ptr()
+            g = None if gaps is None else gaps[i]
+            if g is not None and g.numel() > 0:
+                _need_cuda(g, torch.int64, "gaps")
+                seg.gaps[i] = g.data_ptr()
+                seg.n_gaps[i] = g.shape[0]
+                keep.append(g)
+            else:
+                seg.gaps[i] = None
+                seg.n_gaps[i] = 0
+        return seg, keep
+
+    # -- entry points ----------------------------------------------------
+    def resample(self, xs, gaps, sky, ws=None):
+        """rsf_resample: per detector dict(z, a, b, tm, mask, abc) of [n_sky, ...] tensors."""
+        _need_cuda(sky, torch.float64, "sky")
+        n_sky = sky.shape[0]
+        seg, keep = self.segment(xs, gaps)
+        dev = xs[0].device
+        f16 = self.desc.storage == 1
+        outs, descs = [], (L.Resampled * self.n_det)()
+        for i in range(self.n_det):
+            o = dict(z=torch.empty((n_sky, self.n), dtype=torch.int32 if f16 else torch.complex64, device=dev),
+                     a=torch.empty((n_sky, self.n), dtype=torch.float32, device=dev),
+                     b=torch.empty((n_sky, self.n), dtype=torch.float32, device=dev),
+                     tm=torch.empty((n_sky, self.n), dtype=torch.float64, device=dev),
+                     mask=torch.empty((n_sky, (self.n + 31) // 32), dtype=torch.int32, device=dev),
+                     abc=torch.empty((n_sky, 3), dtype=torch.float64, device=dev))
+            descs[i] = L.Resampled(o["z"].data_ptr(), o["a"].data_ptr(), o["b"].data_ptr(),
+                                   o["tm"].data_ptr(), o["mask"].data_ptr(), o["abc"].data_ptr())
+            outs.append(o)
+        if ws is None:
+            ws = self.workspace(L.RSF_ENTRY_RESAMPLE, n_sky, 1, device=dev)
+        L.check(self.lib.rsf_resample(self._p, C.byref(seg), _ptr(sky), n_sky, descs, _ptr(ws),
+                                      ws.numel(), _stream()))
+        return outs
+
+    def fstat(self, xs, gaps, sky, fdot, mode=L.RSF_MODE_BATCHED, out=None, ws=None):
+        """rsf_fstat: 2F [n_sky * n_fdot, n_out] (float32), ascending frequency."""
+        _need_cuda(sky, torch.float64, "sky")
+        _need_cuda(fdot, torch.float64, "fdot")
+        n_sky, n_fdot = sky.shape[0], fdot.shape[0]
+        seg, keep = self.segment(xs, gaps)
+        dev = xs[0].device
+        if out is None:
+            out = torch.empty((n_sky * n_fdot, self.n_out), dtype=torch.float32, device=dev)
+        _need_cuda(out, torch.float32, "out")
+        if out.numel() < n_sky * n_fdot * self.n_out:
+            raise ValueError("output too small")
+        if ws is None:
+            ws = self.workspace(L.RSF_ENTRY_FSTAT, 1, n_fdot, mode, device=dev)
+        L.check(self.lib.rsf_fstat(self._p, C.byref(seg), _ptr(sky), n_sky, _ptr(fdot), n_fdot, mode,
+                                   _ptr(out), _ptr(ws), ws.numel(), _stream()))
+        return out
+
+    def flags(self, ws):
+        f = C.c_uint32()
+        L.check(self.lib.rsf_get_flags(self._p, _ptr(ws), C.byref(f), _stream()))
+        return f.value

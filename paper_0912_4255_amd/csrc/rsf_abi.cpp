@@ -1,0 +1,576 @@
+// C ABI of librsfstat: plans, argument validation, workspace layout and the
+// launch sequences of the resampling F-statistic (declared in rsfstat.h).
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/rsfstat.h"
+#include "rsf_launch.h"
+#include "rsf_params.h"
+
+using namespace rsf;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(RSF_EHIP, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+}
+
+#define RSF_HIP(call, what)                          \
+    do {                                             \
+        hipError_t e_ = (call);                      \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+bool is_7smooth(int64_t n) {
+    if (n < 1) return false;
+    for (int p : {2, 3, 5, 7})
+        while (n % p == 0) n /= p;
+    return n == 1;
+}
+
+int64_t next_7smooth(int64_t n) {
+    int64_t m = std::max<int64_t>(1, n);
+    while (!is_7smooth(m)) ++m;
+    return m;
+}
+
+// Radix sequence for a length-len transform over a batch of B interleaved
+// columns: fewest stages with radices whose butterfly count len*B/R fits the
+// per-stage register capacity of the FFT kernels, ties broken by the largest
+// smallest radix.
+bool radix_plan(int len, int B, FftStages* st) {
+    static const int all_radices[] = {16, 15, 14, 12, 10, 9, 8, 7, 6, 5, 4, 3, 2};
+    std::vector<int> radices;
+    for (int r : all_radices)
+        if ((int64_t)len * B / r <= fft_radix_cap(r)) radices.push_back(r);
+    st->len = len;
+    st->n_stages = 0;
+    if (len == 1) return true;
+    // dp over divisors: best[m] = (stages, -minradix) for a length m
+    std::vector<int> stages(len + 1, 1 << 20), minr(len + 1, 0), choice(len + 1, 0);
+    stages[1] = 0;
+    minr[1] = 1 << 20;
+    for (int m = 2; m <= len; ++m) {
+        if (len % m) continue;
+        for (int r : radices) {
+            if (m % r) continue;
+            const int rest = m / r;
+            if (stages[rest] >= (1 << 20)) continue;
+            const int s = stages[rest] + 1;
+            const int mr = std::min(minr[rest], r);
+            if (s < stages[m] || (s == stages[m] && mr > minr[m])) {
+                stages[m] = s;
+                minr[m] = mr;
+                choice[m] = r;
+            }
+        }
+    }
+    if (stages[len] >= (1 << 20) || stages[len] > kMaxStages) return false;
+    int m = len;
+    std::vector<int> seq;
+    while (m > 1) {
+        seq.push_back(choice[m]);
+        m /= choice[m];
+    }
+    // larger radices first
+    std::sort(seq.begin(), seq.end(), [](int a, int b) { return a > b; });
+    st->n_stages = (int)seq.size();
+    for (size_t i = 0; i < seq.size(); ++i) st->radix[i] = seq[i];
+    return true;
+}
+
+}  // namespace
+
+struct rsf_plan {
+    rsf_plan_desc d;
+    int device;
+    int64_t n, n_fft, s_lo, n_out;
+    double df;
+    int LA, LB;          // first-pass length (over n_a), second-pass length (over n_b)
+    int64_t P;           // rows of the transposed series: ceil(n / LB)
+    int n_groups;        // ceil(LA / 8)
+    FftStages stA, stB;
+    float2* twA;
+    float2* twB;
+    float2* tw_lo;
+    float2* tw_hi;
+    EphDev eph;
+    DetDev det[RSF_MAX_DET];
+    InterpDev ip;
+};
+
+namespace {
+
+struct WsLayout {
+    size_t flags, rs_main[RSF_MAX_DET], rs_tm[RSF_MAX_DET], partials, coef, abc_w, spill, total;
+    int n_blocks;
+    int64_t G;
+};
+
+int64_t batch_templates(const rsf_plan* p, int64_t n_fdot, int mode) {
+    if (mode == RSF_MODE_PLAIN) return 1;
+    (void)p;
+    return std::max<int64_t>(1, std::min<int64_t>(n_fdot, 16));
+}
+
+WsLayout fstat_layout(const rsf_plan* p, int64_t n_fdot, int mode) {
+    WsLayout L{};
+    size_t off = 0;
+    L.flags = off;
+    off = align_up(off + 64);
+    const size_t elems = (size_t)p->LB * (size_t)p->P;
+    for (int X = 0; X < p->d.n_det; ++X) {
+        L.rs_main[X] = off;
+        off = align_up(off + elems * sizeof(float4));
+        if (p->d.storage == RSF_STORE_F32) {
+            L.rs_tm[X] = off;
+            off = align_up(off + elems * sizeof(float));
+        }
+    }
+    L.n_blocks = resample_blocks(p->LB, p->P);
+    L.partials = off;
+    off = align_up(off + (size_t)p->d.n_det * L.n_blocks * 3 * sizeof(double));
+    L.coef = off;
+    off = align_up(off + 4 * sizeof(float));
+    L.abc_w = off;
+    off = align_up(off + 3 * sizeof(double));
+    L.G = batch_templates(p, n_fdot, mode);
+    L.spill = off;
+    off = align_up(off + (size_t)L.G * p->n_groups * p->LB * kPassBCols * sizeof(float4));
+    L.total = off;
+    return L;
+}
+
+struct ResLayout {
+    size_t flags, partials, coef, total;
+    int n_blocks;
+};
+
+ResLayout resample_layout(const rsf_plan* p, int64_t n_sky) {
+    ResLayout L{};
+    size_t off = 0;
+    L.flags = off;
+    off = align_up(off + 64);
+    const int64_t P = (p->n + 63) / 64;
+    L.n_blocks = resample_blocks(64, P);
+    L.partials = off;
+    off = align_up(off + (size_t)p->d.n_det * n_sky * L.n_blocks * 3 * sizeof(double));
+    L.coef = off;
+    off = align_up(off + (size_t)n_sky * 4 * sizeof(float));
+    L.total = off;
+    return L;
+}
+
+bool is_fin(double x) { return std::isfinite(x); }
+
+ResampleArgs base_resample_args(const rsf_plan* p, const rsf_segment* seg, int X) {
+    ResampleArgs a{};
+    a.n = p->n;
+    a.dt = p->d.dt;
+    a.t_start = p->d.t_start;
+    a.f_het = p->d.f_het;
+    a.eph = p->eph;
+    a.det = p->det[X];
+    a.ip = p->ip;
+    a.x = (const float2*)seg->x[X];
+    a.gaps = seg->gaps[X];
+    a.n_gaps = seg->n_gaps[X];
+    return a;
+}
+
+int check_segment(const rsf_plan* p, const rsf_segment* seg) {
+    if (!seg) return fail(RSF_EINVAL, "segment is NULL");
+    for (int X = 0; X < p->d.n_det; ++X) {
+        if (!seg->x[X]) return fail(RSF_EINVAL, "segment x[%d] is NULL", X);
+        if (seg->n_gaps[X] < 0) return fail(RSF_EINVAL, "segment n_gaps[%d] < 0", X);
+        if (seg->n_gaps[X] > 0 && !seg->gaps[X]) return fail(RSF_EINVAL, "segment gaps[%d] is NULL", X);
+    }
+    return RSF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rsf_last_error(void) { return g_last_error.c_str(); }
+
+int rsf_version(void) { return 1; }
+
+int rsf_plan_create(rsf_plan** out, const rsf_plan_desc* d) {
+    if (!out) return fail(RSF_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!d) return fail(RSF_EINVAL, "descriptor is NULL");
+    if (d->n_det < 1 || d->n_det > RSF_MAX_DET) return fail(RSF_EINVAL, "n_det must be in 1..%d", RSF_MAX_DET);
+    if (d->n < 2 || d->n > (int64_t)1 << 30) return fail(RSF_EINVAL, "n must be in 2..2^30");
+    if (!is_fin(d->dt) || d->dt <= 0) return fail(RSF_EINVAL, "dt must be positive and finite");
+    if (!is_fin(d->t_start) || !is_fin(d->f_het) || !is_fin(d->f_lo) || !is_fin(d->f_hi))
+        return fail(RSF_EINVAL, "non-finite t_start/f_het/band");
+    if (d->kernel != RSF_KERNEL_LANCZOS && d->kernel != RSF_KERNEL_DIRICHLET)
+        return fail(RSF_EINVAL, "unknown kernel");
+    if (d->taps < 2 || d->taps > RSF_MAX_TAPS || (d->taps & 1))
+        return fail(RSF_EUNSUPPORTED, "taps must be even and in 2..%d", RSF_MAX_TAPS);
+    if (d->storage != RSF_STORE_F32 && d->storage != RSF_STORE_F16) return fail(RSF_EINVAL, "unknown storage");
+    if (d->nfft_policy != RSF_NFFT_TWICE && d->nfft_policy != RSF_NFFT_SMOOTH7)
+        return fail(RSF_EINVAL, "unknown FFT length policy");
+    const rsf_ephemeris& E = d->eph;
+    if (!is_fin(E.au_c) || !is_fin(E.re_c) || !is_fin(E.eps) || !is_fin(E.lambda0) || !is_fin(E.theta0) ||
+        !(E.p_orb > 0) || !(E.p_sid > 0) || !is_fin(E.p_orb) || !is_fin(E.p_sid))
+        return fail(RSF_EINVAL, "invalid ephemeris");
+    for (int X = 0; X < d->n_det; ++X) {
+        const rsf_detector& D = d->det[X];
+        if (!is_fin(D.lat) || !is_fin(D.lon) || !is_fin(D.gamma) || !(D.sigma2 > 0) || !is_fin(D.sigma2))
+            return fail(RSF_EINVAL, "invalid detector %d", X);
+    }
+
+    rsf_plan* p = new rsf_plan();
+    p->d = *d;
+    p->n = d->n;
+    p->n_fft = (d->nfft_policy == RSF_NFFT_TWICE) ? 2 * d->n : next_7smooth(2 * d->n);
+    if (!is_7smooth(p->n_fft)) {
+        delete p;
+        return fail(RSF_EUNSUPPORTED, "FFT length %lld has a prime factor above 7", (long long)(2 * d->n));
+    }
+    p->df = 1.0 / ((double)p->n_fft * d->dt);
+    p->s_lo = (int64_t)llround((d->f_lo - d->f_het) / p->df);
+    p->n_out = (int64_t)llround((d->f_hi - d->f_lo) / p->df);
+    if (p->n_out < 1 || p->s_lo < -(p->n_fft / 2) || p->s_lo + p->n_out - 1 > (p->n_fft + 1) / 2 - 1) {
+        delete p;
+        return fail(RSF_EINVAL, "band [%g, %g) is empty or outside the data band", d->f_lo, d->f_hi);
+    }
+
+    // device limits
+    RSF_HIP(hipGetDevice(&p->device), "hipGetDevice");
+    int lds_max = 0;
+    if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device) != hipSuccess ||
+        lds_max <= 0)
+        lds_max = 65536;
+    const int max_elems = fft_pass_max_elems();
+    const int64_t la_max = std::min<int64_t>(max_elems, lds_max / (int)sizeof(float4));
+    const int64_t lb_max = std::min<int64_t>(max_elems / kPassBCols, lds_max / (kPassBCols * (int)sizeof(float4)));
+
+    // factorisation n_fft = LA * LB: fewest total stages, LA a multiple of 8,
+    // then the most balanced LDS footprints
+    int best_la = -1, best_lb = -1;
+    double best_score = 1e300;
+    for (int64_t lb = 1; lb <= lb_max; ++lb) {
+        if (p->n_fft % lb) continue;
+        const int64_t la = p->n_fft / lb;
+        if (la > la_max) continue;
+        FftStages sa, sb;
+        if (!radix_plan((int)la, 1, &sa) || !radix_plan((int)lb, kPassBCols, &sb)) continue;
+        const double lds_a = (double)la * 16, lds_b = (double)lb * 128;
+        double score = (sa.n_stages + sb.n_stages) * 1e9 + ((la % 8) ? 1e8 : 0.0) + std::max(lds_a, lds_b);
+        if (score < best_score) {
+            best_score = score;
+            best_la = (int)la;
+            best_lb = (int)lb;
+        }
+    }
+    if (best_la < 0) {
+        delete p;
+        return fail(RSF_EUNSUPPORTED, "no two-pass factorisation of n_fft = %lld fits the LDS (%d bytes)",
+                    (long long)p->n_fft, lds_max);
+    }
+    p->LA = best_la;
+    p->LB = best_lb;
+    radix_plan(p->LA, 1, &p->stA);
+    radix_plan(p->LB, kPassBCols, &p->stB);
+    p->P = (p->n + p->LB - 1) / p->LB;
+    p->n_groups = (p->LA + kPassBCols - 1) / kPassBCols;
+    if (p->P > p->LA) {
+        delete p;
+        return fail(RSF_EUNSUPPORTED, "internal: rows exceed first-pass length");
+    }
+    const size_t lds_need = std::max<size_t>((size_t)p->LA * 16, (size_t)p->LB * 128);
+    if (lds_need > 65536) fft_set_lds_limits(lds_need);
+
+    // twiddle tables, built in FP64 and stored as FP32
+    auto table = [](int64_t len, int64_t count, int64_t step) {
+        std::vector<float2> t((size_t)count);
+        for (int64_t m = 0; m < count; ++m) {
+            const long double a = -2.0L * 3.14159265358979323846264338327950288L *
+                                  (long double)((m * step) % len) / (long double)len;
+            t[(size_t)m] = make_float2((float)std::cos((double)a), (float)std::sin((double)a));
+        }
+        return t;
+    };
+    std::vector<float2> ta = table(p->LA, p->LA, 1), tb = table(p->LB, p->LB, 1);
+    const int64_t nlo = 1 << kTwSplitBits;
+    std::vector<float2> tlo = table(p->n_fft, nlo, 1);
+    const int64_t nhi = p->n_fft / nlo + 1;
+    std::vector<float2> thi = table(p->n_fft, nhi, nlo);
+    auto upload = [&](float2** dst, const std::vector<float2>& src) -> int {
+        RSF_HIP(hipMalloc((void**)dst, src.size() * sizeof(float2)), "hipMalloc(table)");
+        RSF_HIP(hipMemcpy(*dst, src.data(), src.size() * sizeof(float2), hipMemcpyHostToDevice), "hipMemcpy(table)");
+        return RSF_OK;
+    };
+    int rc;
+    if ((rc = upload(&p->twA, ta)) || (rc = upload(&p->twB, tb)) || (rc = upload(&p->tw_lo, tlo)) ||
+        (rc = upload(&p->tw_hi, thi))) {
+        rsf_plan_destroy(p);
+        return rc;
+    }
+
+    // constants of the timing model and the kernel
+    p->eph.au_c = E.au_c;
+    p->eph.re_c = E.re_c;
+    p->eph.inv_p_orb = 1.0 / E.p_orb;
+    p->eph.inv_p_sid = 1.0 / E.p_sid;
+    p->eph.ceps = std::cos(E.eps);
+    p->eph.seps = std::sin(E.eps);
+    p->eph.lambda0 = E.lambda0;
+    p->eph.theta0 = E.theta0;
+    for (int X = 0; X < d->n_det; ++X) {
+        const rsf_detector& D = d->det[X];
+        DetDev& o = p->det[X];
+        o.lon = D.lon;
+        o.clat = std::cos(D.lat);
+        o.slat = std::sin(D.lat);
+        o.cgu = std::cos(D.gamma + M_PI / 4);
+        o.sgu = std::sin(D.gamma + M_PI / 4);
+        o.cgv = std::cos(D.gamma - M_PI / 4);
+        o.sgv = std::sin(D.gamma - M_PI / 4);
+        o.w = 1.0 / D.sigma2;
+    }
+    p->ip.kernel = d->kernel;
+    p->ip.taps = d->taps;
+    p->ip.n = (int)d->n;
+    p->ip.n_odd = (int)(d->n & 1);
+    for (int i = 0; i <= kMaxTaps; ++i) {
+        const double phi = M_PI * (1.0 - 2.0 * i / (double)d->taps);
+        p->ip.cphi[i] = (float)std::cos(phi);
+        p->ip.sphi[i] = (float)std::sin(phi);
+    }
+    *out = p;
+    return RSF_OK;
+}
+
+int rsf_plan_destroy(rsf_plan* p) {
+    if (!p) return RSF_OK;
+    hipFree(p->twA);
+    hipFree(p->twB);
+    hipFree(p->tw_lo);
+    hipFree(p->tw_hi);
+    delete p;
+    return RSF_OK;
+}
+
+int rsf_plan_query(const rsf_plan* p, int64_t* n_fft, int64_t* bin_lo, int64_t* n_out, int32_t* l1,
+                   int32_t* l2, double* df) {
+    if (!p) return fail(RSF_EINVAL, "plan is NULL");
+    if (n_fft) *n_fft = p->n_fft;
+    if (bin_lo) *bin_lo = p->s_lo;
+    if (n_out) *n_out = p->n_out;
+    if (l1) *l1 = p->LA;
+    if (l2) *l2 = p->LB;
+    if (df) *df = p->df;
+    return RSF_OK;
+}
+
+int rsf_workspace_size(const rsf_plan* p, int entry, int64_t n_sky, int64_t n_fdot, int mode, size_t* bytes) {
+    if (!p || !bytes) return fail(RSF_EINVAL, "plan or bytes is NULL");
+    if (n_sky < 1 || n_fdot < 1) return fail(RSF_EINVAL, "n_sky and n_fdot must be positive");
+    switch (entry) {
+        case RSF_ENTRY_RESAMPLE:
+            *bytes = resample_layout(p, n_sky).total;
+            return RSF_OK;
+        case RSF_ENTRY_FSTAT:
+            if (mode != RSF_MODE_PLAIN && mode != RSF_MODE_BATCHED) return fail(RSF_EINVAL, "unknown mode");
+            *bytes = fstat_layout(p, n_fdot, mode).total;
+            return RSF_OK;
+        default:
+            return fail(RSF_EUNSUPPORTED, "entry %d not available", entry);
+    }
+}
+
+int rsf_resample(const rsf_plan* p, const rsf_segment* seg, const double* sky, int64_t n_sky,
+                 const rsf_resampled* out, void* ws, size_t ws_bytes, void* stream) {
+    if (!p) return fail(RSF_EINVAL, "plan is NULL");
+    int rc = check_segment(p, seg);
+    if (rc) return rc;
+    if (!sky || !out || n_sky < 1 || n_sky > 65535) return fail(RSF_EINVAL, "sky/out NULL or n_sky outside 1..65535");
+    if (!ws) return fail(RSF_EINVAL, "workspace is NULL");
+    const ResLayout L = resample_layout(p, n_sky);
+    if (ws_bytes < L.total) return fail(RSF_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, L.total);
+    hipStream_t s = (hipStream_t)stream;
+    char* w = (char*)ws;
+    unsigned int* flags = (unsigned int*)(w + L.flags);
+    RSF_HIP(hipMemsetAsync(flags, 0, 64, s), "hipMemsetAsync(flags)");
+    const int64_t P = (p->n + 63) / 64;
+    for (int X = 0; X < p->d.n_det; ++X) {
+        ResampleArgs a = base_resample_args(p, seg, X);
+        a.sky = sky;
+        a.LB = 64;
+        a.P = P;
+        a.layout = 0;
+        if (p->d.storage == RSF_STORE_F16) {
+            a.f16 = 1;
+            a.out_zh = (uint32_t*)out[X].z;
+        } else {
+            a.out_z = (float2*)out[X].z;
+        }
+        a.out_a = out[X].a;
+        a.out_b = out[X].b;
+        a.out_tm = out[X].tm;
+        a.out_mask = out[X].mask;
+        a.n_words = (p->n + 31) / 32;
+        a.partials = (double*)(w + L.partials) + (size_t)X * n_sky * L.n_blocks * 3;
+        a.n_blocks = L.n_blocks;
+        a.flags = flags;
+        RSF_HIP(launch_resample(a, (int)n_sky, s), "resample launch");
+    }
+    ReduceArgs r{};
+    r.partials = (const double*)(w + L.partials);
+    r.n_blocks = L.n_blocks;
+    r.n_det = p->d.n_det;
+    r.n_sky = (int)n_sky;
+    for (int X = 0; X < p->d.n_det; ++X) {
+        r.w[X] = p->det[X].w;
+        r.abc_det[X] = out[X].abc;
+    }
+    r.coef = (float*)(w + L.coef);
+    r.flags = flags;
+    RSF_HIP(launch_antenna_reduce(r, s), "antenna reduce launch");
+    return RSF_OK;
+}
+
+int rsf_fstat(const rsf_plan* p, const rsf_segment* seg, const double* sky, int64_t n_sky, const double* fdot,
+              int64_t n_fdot, int mode, float* twoF, void* ws, size_t ws_bytes, void* stream) {
+    if (!p) return fail(RSF_EINVAL, "plan is NULL");
+    int rc = check_segment(p, seg);
+    if (rc) return rc;
+    if (!sky || !fdot || !twoF) return fail(RSF_EINVAL, "sky, fdot or twoF is NULL");
+    if (n_sky < 1 || n_fdot < 1) return fail(RSF_EINVAL, "n_sky and n_fdot must be positive");
+    if (mode != RSF_MODE_PLAIN && mode != RSF_MODE_BATCHED) return fail(RSF_EINVAL, "unknown mode");
+    if (!ws) return fail(RSF_EINVAL, "workspace is NULL");
+    const WsLayout L = fstat_layout(p, n_fdot, mode);
+    if (ws_bytes < L.total) return fail(RSF_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, L.total);
+    hipStream_t s = (hipStream_t)stream;
+    char* w = (char*)ws;
+    unsigned int* flags = (unsigned int*)(w + L.flags);
+    RSF_HIP(hipMemsetAsync(flags, 0, 64, s), "hipMemsetAsync(flags)");
+    const int fb = (mode == RSF_MODE_BATCHED) ? 4 : 1;
+    float4* spill = (float4*)(w + L.spill);
+    const int64_t spill_stride = (int64_t)p->n_groups * p->LB * kPassBCols;
+
+    for (int64_t sk = 0; sk < n_sky; ++sk) {
+        for (int X = 0; X < p->d.n_det; ++X) {
+            ResampleArgs a = base_resample_args(p, seg, X);
+            a.sky = sky + 2 * sk;
+            a.LB = p->LB;
+            a.P = p->P;
+            a.layout = 1;
+            a.f16 = p->d.storage == RSF_STORE_F16;
+            a.rs_main = (float4*)(w + L.rs_main[X]);
+            a.rs_tm = a.f16 ? nullptr : (float*)(w + L.rs_tm[X]);
+            a.rs_sky_stride = 0;
+            a.partials = (double*)(w + L.partials) + (size_t)X * L.n_blocks * 3;
+            a.n_blocks = L.n_blocks;
+            a.flags = flags;
+            RSF_HIP(launch_resample(a, 1, s), "resample launch");
+        }
+        ReduceArgs r{};
+        r.partials = (const double*)(w + L.partials);
+        r.n_blocks = L.n_blocks;
+        r.n_det = p->d.n_det;
+        r.n_sky = 1;
+        for (int X = 0; X < p->d.n_det; ++X) r.w[X] = p->det[X].w;
+        r.abc_w = (double*)(w + L.abc_w);
+        r.coef = (float*)(w + L.coef);
+        r.flags = flags;
+        RSF_HIP(launch_antenna_reduce(r, s), "antenna reduce launch");
+
+        for (int64_t f0 = 0; f0 < n_fdot; f0 += L.G) {
+            const int g = (int)std::min<int64_t>(L.G, n_fdot - f0);
+            PassAArgs A{};
+            A.n = p->n;
+            A.n_fft = p->n_fft;
+            A.dt = p->d.dt;
+            A.LA = p->LA;
+            A.LB = p->LB;
+            A.P = p->P;
+            A.n_det = p->d.n_det;
+            for (int X = 0; X < p->d.n_det; ++X) {
+                A.w[X] = p->det[X].w;
+                A.rs_main[X] = (const float4*)(w + L.rs_main[X]);
+                A.rs_tm[X] = (p->d.storage == RSF_STORE_F32) ? (const float*)(w + L.rs_tm[X]) : nullptr;
+            }
+            A.f16 = p->d.storage == RSF_STORE_F16;
+            A.fdot = fdot + f0;
+            A.n_tmpl = g;
+            A.fb = fb;
+            A.st = p->stA;
+            A.tw = p->twA;
+            A.tw_lo = p->tw_lo;
+            A.tw_hi = p->tw_hi;
+            A.spill = spill;
+            A.spill_tmpl_stride = spill_stride;
+            RSF_HIP(launch_fft_pass_a(A, s), "pass A launch");
+
+            PassBArgs B{};
+            B.n_fft = p->n_fft;
+            B.LA = p->LA;
+            B.LB = p->LB;
+            B.n_groups = p->n_groups;
+            B.st = p->stB;
+            B.tw = p->twB;
+            B.spill = spill;
+            B.spill_tmpl_stride = spill_stride;
+            B.coef = (const float*)(w + L.coef);
+            B.s_lo = p->s_lo;
+            B.n_out = p->n_out;
+            B.twoF = twoF;
+            B.out_row0 = sk * n_fdot + f0;
+            B.n_tmpl = g;
+            RSF_HIP(launch_fft_pass_b(B, s), "pass B launch");
+        }
+    }
+    return RSF_OK;
+}
+
+int rsf_fstat_topk(const rsf_plan*, const rsf_segment*, const double*, int64_t, const double*, int64_t, int,
+                   rsf_topk_entry*, void*, size_t, void*) {
+    return fail(RSF_EUNSUPPORTED, "rsf_fstat_topk not built yet");
+}
+
+int rsf_fstat_point(const rsf_plan*, const rsf_segment*, const double*, int64_t, float*, void*, size_t, void*) {
+    return fail(RSF_EUNSUPPORTED, "rsf_fstat_point not built yet");
+}
+
+int rsf_fstat_backward(const rsf_plan*, const rsf_segment*, const double*, int64_t, const float*, float*, double*,
+                       void*, size_t, void*) {
+    return fail(RSF_EUNSUPPORTED, "rsf_fstat_backward not built yet");
+}
+
+int rsf_get_flags(const rsf_plan* p, void* ws, uint32_t* flags, void* stream) {
+    if (!p || !ws || !flags) return fail(RSF_EINVAL, "plan, ws or flags is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    RSF_HIP(hipMemcpyAsync(flags, ws, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "hipMemcpyAsync(flags)");
+    RSF_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+    RSF_HIP(hipMemsetAsync(ws, 0, sizeof(uint32_t), s), "hipMemsetAsync(flags)");
+    return RSF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,363 @@
+// Device helpers for librsfstat (gfx950): complex-pair arithmetic, small
+// DFT butterflies with compile-time constants, and the analytic timing model.
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rsf_params.h"
+
+namespace rsf {
+
+// ---------------------------------------------------------------------------
+// Compile-time sin/cos of 2 pi m / R (for butterfly constants).  Range
+// reduction to [-pi/2, pi/2] and a Taylor series accurate to double precision.
+// ---------------------------------------------------------------------------
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+constexpr double cx_sin_series(double x) {
+    double x2 = x * x, term = x, sum = x;
+    for (int n = 1; n < 14; ++n) {
+        term *= -x2 / double((2 * n) * (2 * n + 1));
+        sum += term;
+    }
+    return sum;
+}
+constexpr double cx_sin(double x) {  // x in [-pi, pi]
+    if (x > kPi / 2) x = kPi - x;
+    else if (x < -kPi / 2) x = -kPi - x;
+    return cx_sin_series(x);
+}
+constexpr double cx_wrap(double x) {  // to [-pi, pi]
+    while (x > kPi) x -= 2 * kPi;
+    while (x < -kPi) x += 2 * kPi;
+    return x;
+}
+constexpr double cx_cos(double x) { return cx_sin(cx_wrap(x + kPi / 2)); }
+constexpr double cx_angle(int m, int R) {  // 2 pi m / R reduced to (-pi, pi]
+    int r = ((m % R) + R) % R;
+    double f = double(r) / double(R);
+    if (f > 0.5) f -= 1.0;
+    return 2 * kPi * f;
+}
+
+// Forward roots W_R^m = exp(-2 pi i m / R): re = cos, im = -sin.
+template <int R>
+struct Roots {
+    float re[R];
+    float im[R];
+    constexpr Roots() : re(), im() {
+        for (int m = 0; m < R; ++m) {
+            double a = cx_angle(m, R);
+            double c = cx_cos(a), s = cx_sin(a);
+            // exact values on the axes
+            if (4 * m % R == 0) {
+                int q = (4 * m / R) % 4;
+                c = (q == 0) ? 1.0 : (q == 2 ? -1.0 : 0.0);
+                s = (q == 1) ? 1.0 : (q == 3 ? -1.0 : 0.0);
+            }
+            re[m] = float(c);
+            im[m] = float(-s);
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// A complex pair (f_a, f_b) in one float4: (a.re, a.im, b.re, b.im).  Every
+// butterfly of the FFT acts on both spectra with the same index arithmetic.
+// ---------------------------------------------------------------------------
+typedef float4 cp;
+
+__device__ __forceinline__ cp cp_add(cp a, cp b) { return make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w); }
+__device__ __forceinline__ cp cp_sub(cp a, cp b) { return make_float4(a.x - b.x, a.y - b.y, a.z - b.z, a.w - b.w); }
+__device__ __forceinline__ cp cp_scale(cp a, float s) { return make_float4(a.x * s, a.y * s, a.z * s, a.w * s); }
+// multiply both members by (c + i s)
+__device__ __forceinline__ cp cp_rot(cp a, float c, float s) {
+    return make_float4(a.x * c - a.y * s, a.x * s + a.y * c, a.z * c - a.w * s, a.z * s + a.w * c);
+}
+__device__ __forceinline__ cp cp_rot(cp a, float2 w) { return cp_rot(a, w.x, w.y); }
+// multiply by -i
+__device__ __forceinline__ cp cp_mul_mi(cp a) { return make_float4(a.y, -a.x, a.w, -a.z); }
+// multiply by +i
+__device__ __forceinline__ cp cp_mul_pi(cp a) { return make_float4(-a.y, a.x, -a.w, a.z); }
+__device__ __forceinline__ float2 c_mul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// ---------------------------------------------------------------------------
+// Small forward DFTs, in place, natural order: y_k = sum_n x_n W_R^{nk}.
+// ---------------------------------------------------------------------------
+template <int R>
+struct Dft;
+
+template <>
+struct Dft<1> {
+    __device__ __forceinline__ static void run(cp*) {}
+};
+
+template <>
+struct Dft<2> {
+    __device__ __forceinline__ static void run(cp* x) {
+        cp a = x[0], b = x[1];
+        x[0] = cp_add(a, b);
+        x[1] = cp_sub(a, b);
+    }
+};
+
+template <>
+struct Dft<3> {
+    __device__ __forceinline__ static void run(cp* x) {
+        constexpr float s3 = 0.866025403784438646763723170752936183f;  // sin(2 pi / 3)
+        cp t1 = cp_add(x[1], x[2]);
+        cp t2 = cp_sub(x[0], cp_scale(t1, 0.5f));
+        cp t3 = cp_scale(cp_sub(x[1], x[2]), s3);
+        x[0] = cp_add(x[0], t1);
+        x[1] = cp_add(t2, cp_mul_mi(t3));
+        x[2] = cp_sub(t2, cp_mul_mi(t3));
+    }
+};
+
+template <>
+struct Dft<4> {
+    __device__ __forceinline__ static void run(cp* x) {
+        cp s02 = cp_add(x[0], x[2]), d02 = cp_sub(x[0], x[2]);
+        cp s13 = cp_add(x[1], x[3]), d13 = cp_mul_mi(cp_sub(x[1], x[3]));
+        x[0] = cp_add(s02, s13);
+        x[2] = cp_sub(s02, s13);
+        x[1] = cp_add(d02, d13);
+        x[3] = cp_sub(d02, d13);
+    }
+};
+
+template <>
+struct Dft<5> {
+    __device__ __forceinline__ static void run(cp* x) {
+        constexpr float c1 = float(cx_cos(2 * kPi / 5)), c2 = float(cx_cos(4 * kPi / 5));
+        constexpr float s1 = float(cx_sin(2 * kPi / 5)), s2 = float(cx_sin(4 * kPi / 5));
+        cp t1 = cp_add(x[1], x[4]), t2 = cp_add(x[2], x[3]);
+        cp t3 = cp_sub(x[1], x[4]), t4 = cp_sub(x[2], x[3]);
+        cp a1 = cp_add(x[0], cp_add(cp_scale(t1, c1), cp_scale(t2, c2)));
+        cp a2 = cp_add(x[0], cp_add(cp_scale(t1, c2), cp_scale(t2, c1)));
+        cp b1 = cp_add(cp_scale(t3, s1), cp_scale(t4, s2));
+        cp b2 = cp_sub(cp_scale(t3, s2), cp_scale(t4, s1));
+        x[0] = cp_add(x[0], cp_add(t1, t2));
+        x[1] = cp_add(a1, cp_mul_mi(b1));
+        x[4] = cp_sub(a1, cp_mul_mi(b1));
+        x[2] = cp_add(a2, cp_mul_mi(b2));
+        x[3] = cp_sub(a2, cp_mul_mi(b2));
+    }
+};
+
+template <>
+struct Dft<7> {
+    __device__ __forceinline__ static void run(cp* x) {
+        constexpr float c1 = float(cx_cos(2 * kPi / 7)), c2 = float(cx_cos(4 * kPi / 7)),
+                        c3 = float(cx_cos(6 * kPi / 7));
+        constexpr float s1 = float(cx_sin(2 * kPi / 7)), s2 = float(cx_sin(4 * kPi / 7)),
+                        s3 = float(cx_sin(6 * kPi / 7));
+        cp p1 = cp_add(x[1], x[6]), p2 = cp_add(x[2], x[5]), p3 = cp_add(x[3], x[4]);
+        cp m1 = cp_sub(x[1], x[6]), m2 = cp_sub(x[2], x[5]), m3 = cp_sub(x[3], x[4]);
+        // y_m = x0 + sum_k cos(2 pi k m/7) p_k - i sum_k sin(2 pi k m/7) m_k
+        cp a1 = cp_add(x[0], cp_add(cp_scale(p1, c1), cp_add(cp_scale(p2, c2), cp_scale(p3, c3))));
+        cp a2 = cp_add(x[0], cp_add(cp_scale(p1, c2), cp_add(cp_scale(p2, c3), cp_scale(p3, c1))));
+        cp a3 = cp_add(x[0], cp_add(cp_scale(p1, c3), cp_add(cp_scale(p2, c1), cp_scale(p3, c2))));
+        // sin(2 pi k m / 7) for (m, k): m=1: s1 s2 s3; m=2: s2 -s3 -s1; m=3: s3 -s1 s2
+        cp b1 = cp_add(cp_scale(m1, s1), cp_add(cp_scale(m2, s2), cp_scale(m3, s3)));
+        cp b2 = cp_sub(cp_scale(m1, s2), cp_add(cp_scale(m2, s3), cp_scale(m3, s1)));
+        cp b3 = cp_add(cp_sub(cp_scale(m1, s3), cp_scale(m2, s1)), cp_scale(m3, s2));
+        x[0] = cp_add(x[0], cp_add(p1, cp_add(p2, p3)));
+        x[1] = cp_add(a1, cp_mul_mi(b1));
+        x[6] = cp_sub(a1, cp_mul_mi(b1));
+        x[2] = cp_add(a2, cp_mul_mi(b2));
+        x[5] = cp_sub(a2, cp_mul_mi(b2));
+        x[3] = cp_add(a3, cp_mul_mi(b3));
+        x[4] = cp_sub(a3, cp_mul_mi(b3));
+    }
+};
+
+// Composite radix R = P * Q in registers (Cooley-Tukey): n = Q n1 + n2,
+// k = k1 + P k2; P-point DFTs over n1, twiddle W_R^{n2 k1}, Q-point DFTs
+// over n2.
+template <int P, int Q>
+struct DftCT {
+    __device__ __forceinline__ static void run(cp* x) {
+        constexpr int R = P * Q;
+        constexpr Roots<R> w{};
+        cp u[R];
+#pragma unroll
+        for (int n2 = 0; n2 < Q; ++n2) {
+            cp t[P];
+#pragma unroll
+            for (int n1 = 0; n1 < P; ++n1) t[n1] = x[Q * n1 + n2];
+            Dft<P>::run(t);
+#pragma unroll
+            for (int k1 = 0; k1 < P; ++k1) {
+                const int m = (n2 * k1) % R;
+                u[n2 * P + k1] = (m == 0) ? t[k1] : cp_rot(t[k1], w.re[m], w.im[m]);
+            }
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < P; ++k1) {
+            cp t[Q];
+#pragma unroll
+            for (int n2 = 0; n2 < Q; ++n2) t[n2] = u[n2 * P + k1];
+            Dft<Q>::run(t);
+#pragma unroll
+            for (int k2 = 0; k2 < Q; ++k2) x[k1 + P * k2] = t[k2];
+        }
+    }
+};
+
+template <> struct Dft<6> : DftCT<2, 3> {};
+template <> struct Dft<8> : DftCT<2, 4> {};
+template <> struct Dft<9> : DftCT<3, 3> {};
+template <> struct Dft<10> : DftCT<2, 5> {};
+template <> struct Dft<12> : DftCT<3, 4> {};
+template <> struct Dft<14> : DftCT<2, 7> {};
+template <> struct Dft<15> : DftCT<3, 5> {};
+template <> struct Dft<16> : DftCT<4, 4> {};
+
+// ---------------------------------------------------------------------------
+// One Stockham stage of a batch of B interleaved transforms of length L kept
+// in LDS (element (n, b) at n*B + b).  Stage with radix R after Ns points have
+// been combined: butterfly j reads n = j + r L/R, multiplies input r by
+// W_{Ns R}^{r (j mod Ns)}, takes the R-point DFT and writes output r to
+// (j div Ns) Ns R + (j mod Ns) + r Ns.  In place: all butterflies of the
+// thread are read into registers, the block synchronises, then they are
+// written.  tw is the length-L table W_L^m; W_{Ns R}^{x} = W_L^{x L/(Ns R)}.
+// ---------------------------------------------------------------------------
+template <int R, int NT, int EPT, int B>
+__device__ __forceinline__ void stockham_stage(cp* __restrict__ s, int L, int Ns,
+                                               const float2* __restrict__ tw) {
+    constexpr int MAXB = (EPT / R) > 0 ? (EPT / R) : 1;  // the planner keeps L*B/R <= MAXB*NT
+    const int tid = threadIdx.x;
+    const int LR = L / R;
+    const int nb = LR * B;
+    const int tstride = L / (Ns * R);
+    cp v[MAXB][R];
+#pragma unroll
+    for (int q = 0; q < MAXB; ++q) {
+        const int bf = tid + q * NT;
+        if (bf < nb) {
+            const int j = bf / B, b = bf - j * B;
+            const int k = j % Ns;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[q][r] = s[(j + r * LR) * B + b];
+            if (Ns > 1) {
+                const float2 w1 = tw[k * tstride];
+                float2 w = w1;
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    v[q][r] = cp_rot(v[q][r], w);
+                    if (r + 1 < R) w = c_mul(w, w1);
+                }
+            }
+            Dft<R>::run(v[q]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < MAXB; ++q) {
+        const int bf = tid + q * NT;
+        if (bf < nb) {
+            const int j = bf / B, b = bf - j * B;
+            const int k = j % Ns;
+            const int base = (j / Ns) * Ns * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) s[(base + r * Ns) * B + b] = v[q][r];
+        }
+    }
+    __syncthreads();
+}
+
+// Run all stages of a planned transform (radix sequence in st).
+template <int NT, int EPT, int B>
+__device__ void lds_fft(cp* __restrict__ s, const FftStages& st, const float2* __restrict__ tw) {
+    int Ns = 1;
+    for (int i = 0; i < st.n_stages; ++i) {
+        const int R = st.radix[i];
+        switch (R) {
+            case 2: stockham_stage<2, NT, EPT, B>(s, st.len, Ns, tw); break;
+            case 3: stockham_stage<3, NT, EPT, B>(s, st.len, Ns, tw); break;
+            case 4: stockham_stage<4, NT, EPT, B>(s, st.len, Ns, tw); break;
+            case 5: stockham_stage<5, NT, EPT, B>(s, st.len, Ns, tw); break;
+            case 6: stockham_stage<6, NT, EPT, B>(s, st.len, Ns, tw); break;
+            case 7: stockham_stage<7, NT, EPT, B>(s, st.len, Ns, tw); break;
+            case 8: stockham_stage<8, NT, EPT, B>(s, st.len, Ns, tw); break;
+            case 9: stockham_stage<9, NT, EPT, B>(s, st.len, Ns, tw); break;
+            case 10: stockham_stage<10, NT, EPT, B>(s, st.len, Ns, tw); break;
+            case 12: stockham_stage<12, NT, EPT, B>(s, st.len, Ns, tw); break;
+            case 14: stockham_stage<14, NT, EPT, B>(s, st.len, Ns, tw); break;
+            case 15: stockham_stage<15, NT, EPT, B>(s, st.len, Ns, tw); break;
+            case 16: stockham_stage<16, NT, EPT, B>(s, st.len, Ns, tw); break;
+            default: break;
+        }
+        Ns *= R;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Analytic timing model (FP64).  Angles are 2 pi times the fractional number
+// of revolutions, so large epochs keep full precision.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double frac_rev(double x) { return x - floor(x); }
+
+struct SiteAngles {
+    double sth, cth;  // local sidereal angle
+};
+
+// t_m(tau) = n0 . r_d(tau) / c; also returns sin/cos of the local sidereal angle.
+__device__ __forceinline__ double roemer(double tau, const double3 n0, const EphDev& e, const DetDev& d,
+                                         SiteAngles* ang) {
+    const double lam = e.lambda0 + 2.0 * kPi * frac_rev(tau * e.inv_p_orb);
+    const double th = e.theta0 + 2.0 * kPi * frac_rev(tau * e.inv_p_sid) + d.lon;
+    double sl, cl, st, ct;
+    sincos(lam, &sl, &cl);
+    sincos(th, &st, &ct);
+    ang->sth = st;
+    ang->cth = ct;
+    const double x = e.au_c * cl + e.re_c * d.clat * ct;
+    const double y = e.au_c * e.ceps * sl + e.re_c * d.clat * st;
+    const double z = e.au_c * e.seps * sl + e.re_c * d.slat;
+    return n0.x * x + n0.y * y + n0.z * z;
+}
+
+__device__ __forceinline__ double3 sky_unit(double alpha, double delta) {
+    double sa, ca, sd, cd;
+    sincos(alpha, &sa, &ca);
+    sincos(delta, &sd, &cd);
+    return make_double3(cd * ca, cd * sa, sd);
+}
+
+// Beam patterns a = d:e+, b = d:ex from the local sidereal angle, using
+// u^T e+ u = (u.p)^2 - (u.q)^2 and u^T ex u = 2 (u.p)(u.q).
+struct SkyFrame {
+    double3 p, q;
+};
+__device__ __forceinline__ SkyFrame sky_frame(double alpha, double delta) {
+    double sa, ca, sd, cd;
+    sincos(alpha, &sa, &ca);
+    sincos(delta, &sd, &cd);
+    SkyFrame f;
+    f.p = make_double3(-sa, ca, 0.0);
+    f.q = make_double3(-sd * ca, -sd * sa, cd);
+    return f;
+}
+__device__ __forceinline__ void beam_ab(const SiteAngles& g, const DetDev& d, const SkyFrame& f,
+                                        double* a, double* b) {
+    const double3 eE = make_double3(-g.sth, g.cth, 0.0);
+    const double3 eN = make_double3(-d.slat * g.cth, -d.slat * g.sth, d.clat);
+    const double3 u = make_double3(d.cgu * eE.x + d.sgu * eN.x, d.cgu * eE.y + d.sgu * eN.y,
+                                   d.cgu * eE.z + d.sgu * eN.z);
+    const double3 v = make_double3(d.cgv * eE.x + d.sgv * eN.x, d.cgv * eE.y + d.sgv * eN.y,
+                                   d.cgv * eE.z + d.sgv * eN.z);
+    const double up = u.x * f.p.x + u.y * f.p.y + u.z * f.p.z;
+    const double uq = u.x * f.q.x + u.y * f.q.y + u.z * f.q.z;
+    const double vp = v.x * f.p.x + v.y * f.p.y + v.z * f.p.z;
+    const double vq = v.x * f.q.x + v.y * f.q.y + v.z * f.q.z;
+    *a = 0.5 * (up * up - uq * uq - vp * vp + vq * vq);
+    *b = up * uq - vp * vq;
+}
+
+}  // namespace rsf

@@ -1,0 +1,19 @@
+// Host-side launchers of the librsfstat kernels (defined in the .hip files).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include "rsf_params.h"
+
+namespace rsf {
+
+hipError_t launch_resample(const ResampleArgs& a, int n_sky, hipStream_t s);
+int resample_blocks(int LB, int64_t P);
+hipError_t launch_antenna_reduce(const ReduceArgs& r, hipStream_t s);
+
+hipError_t launch_fft_pass_a(const PassAArgs& a, hipStream_t s);
+hipError_t launch_fft_pass_b(const PassBArgs& b, hipStream_t s);
+hipError_t fft_set_lds_limits(size_t bytes);
+int fft_pass_max_elems();
+
+}  // namespace rsf

@@ -1,0 +1,141 @@
+// Plain-old-data parameter blocks passed by value from the host launcher to
+// the kernels of librsfstat.
+#pragma once
+
+#include <stdint.h>
+
+#ifndef __HIP__
+#include <hip/hip_runtime_api.h>
+#endif
+#include <hip/hip_vector_types.h>
+
+namespace rsf {
+
+constexpr int kMaxStages = 12;
+constexpr int kMaxTaps = 32;
+constexpr int kMaxDet = 4;
+constexpr int kPassBCols = 8;       // columns per second-pass workgroup (8 x 16 B = 128 B rows)
+constexpr int kTwSplitBits = 12;    // inter-pass twiddle W_N^m = hi[m >> 12] * lo[m & 4095]
+constexpr int kFftThreads = 512;    // threads of an FFT-pass workgroup
+constexpr int kFftEPT = 20;         // complex pairs held per thread in a stage (L * B <= 10240)
+
+// Butterflies of radix R one thread holds in a stage: never more than kFftEPT
+// elements, so a stage of radix R covers at most fft_radix_cap(R) butterflies.
+constexpr int fft_bfly_per_thread(int R) { return (kFftEPT / R) > 0 ? (kFftEPT / R) : 1; }
+constexpr int fft_radix_cap(int R) { return fft_bfly_per_thread(R) * kFftThreads; }
+
+struct FftStages {
+    int len;
+    int n_stages;
+    int radix[kMaxStages];
+};
+
+struct EphDev {
+    double au_c, re_c, inv_p_orb, inv_p_sid, ceps, seps, lambda0, theta0;
+};
+
+struct DetDev {
+    double lon, clat, slat;
+    double cgu, sgu, cgv, sgv;  // cos/sin of the arm azimuths gamma +- pi/4
+    double w;                   // 1 / sigma^2
+};
+
+// Interpolation kernel description.
+struct InterpDev {
+    int kernel;   // 0 Lanczos, 1 Dirichlet
+    int taps;     // W (even)
+    int n;        // series length (Dirichlet period)
+    int n_odd;    // Dirichlet: sin instead of tan in the denominator
+    // Lanczos: sin(2 pi x_i / W) = sin(2 pi frac/W) cos(phi_i) + cos(2 pi frac/W) sin(phi_i),
+    // phi_i = pi (1 - 2 i / W), i = 1..W
+    float cphi[kMaxTaps + 1];
+    float sphi[kMaxTaps + 1];
+};
+
+// Resampling kernel (one detector, a batch of sky positions).
+struct ResampleArgs {
+    int64_t n;
+    double dt, t_start, f_het;
+    EphDev eph;
+    DetDev det;
+    InterpDev ip;
+    const float2* x;
+    const int64_t* gaps;
+    int n_gaps;
+    const double* sky;        // [n_sky][2]
+    // tile geometry: k = LB * n_a + n_b, 0 <= n_b < LB, 0 <= n_a < P
+    int LB;
+    int64_t P;
+    int layout;               // 0: natural (API outputs), 1: FFT layout (internal)
+    // natural-layout outputs, each with a per-sky stride of n (mask: n_words)
+    float2* out_z;
+    uint32_t* out_zh;         // half2 storage of z (if not null)
+    float* out_a;
+    float* out_b;
+    double* out_tm;
+    uint32_t* out_mask;
+    int64_t n_words;
+    // FFT-layout outputs: main = {z.re, z.im, a, b} (F32) or {z as half2, a, b, tm} (F16)
+    float4* rs_main;
+    float* rs_tm;
+    int64_t rs_sky_stride;    // elements between skies
+    int f16;
+    // antenna-sum partials [n_sky][n_blocks][3]
+    double* partials;
+    int n_blocks;
+    unsigned int* flags;
+};
+
+// Reduction of antenna-sum partials into F-statistic coefficients.
+struct ReduceArgs {
+    const double* partials;   // [n_det][n_sky][n_blocks][3]
+    int n_blocks;
+    int n_det;
+    int n_sky;
+    double w[kMaxDet];        // 1 / sigma_X^2
+    double* abc_det[kMaxDet]; // per detector [n_sky][3] unweighted (each may be null)
+    double* abc_w;            // [n_sky][3] weighted (may be null)
+    float* coef;              // [n_sky][4] = 2B/D, 2A/D, -4C/D, degenerate flag
+    unsigned int* flags;
+};
+
+// First FFT pass: for a sky, n_tmpl spindowns, each workgroup one input row
+// n_b and up to fb spindowns that share it.
+struct PassAArgs {
+    int64_t n, n_fft;
+    double dt;
+    int LA, LB;
+    int64_t P;
+    int n_det;
+    double w[kMaxDet];
+    const float4* rs_main[kMaxDet];
+    const float* rs_tm[kMaxDet];
+    int f16;
+    const double* fdot;       // spindowns of this group
+    int n_tmpl;
+    int fb;
+    FftStages st;
+    const float2* tw;         // W_LA^m
+    const float2* tw_lo;
+    const float2* tw_hi;
+    float4* spill;            // [n_tmpl][ceil(LA/8)][LB][8]
+    int64_t spill_tmpl_stride;
+};
+
+// Second FFT pass and F-statistic.
+struct PassBArgs {
+    int64_t n_fft;
+    int LA, LB;
+    int n_groups;             // ceil(LA / 8)
+    FftStages st;
+    const float2* tw;         // W_LB^m
+    const float4* spill;
+    int64_t spill_tmpl_stride;
+    const float* coef;        // {2B/D, 2A/D, -4C/D, flag}
+    int64_t s_lo, n_out;
+    float* twoF;              // rows of n_out
+    int64_t out_row0;
+    int n_tmpl;
+};
+
+}  // namespace rsf

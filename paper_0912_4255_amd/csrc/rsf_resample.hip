@@ -1,0 +1,324 @@
+// Barycentric resampling (paper Sec. III.A.2, steps 1-5) for gfx950.
+//
+// One workgroup (4 waves) resamples a 16 x 64 tile of the SSB grid
+// k = LB * n_a + n_b (n_a = tile row, n_b = lane).  Each wave handles four
+// runs of 64 consecutive k:
+//   1. every lane inverts eq. eq21 for its k by fixed-point iteration in FP64
+//      (T <- k dt - t_m(T), 5 iterations: the contraction is |dt_m/dt| <= 1e-4);
+//   2. the wave loads the detector-grid window its 64 outputs need into LDS,
+//      applying the heterodyne correction z = x_h exp(-2 pi i f_h t_m) on the
+//      way (eqs. absorb/Fa3; the phase f_h t_m is reduced mod 1 in FP64);
+//   3. every lane interpolates z at T^k with the W-tap kernel in FP32;
+//   4. a(T^k), b(T^k) come from the detector tensor in FP64, and the masked
+//      antenna sums A', B', C' (eqs. eq9/eq10) accumulate in FP64.
+// The tile is then written either in natural order (API outputs) or
+// transposed to row n_b (the layout the first FFT pass reads contiguously).
+#include <climits>
+
+#include "rsf_device.h"
+#include "rsf_launch.h"
+
+namespace rsf {
+
+namespace {
+constexpr int kTileB = 64;
+constexpr int kTileA = 16;
+constexpr int kThreads = 256;
+constexpr int kWinMax = kTileB + kMaxTaps + 8;
+constexpr float kPiF = 3.14159265358979323846f;
+
+__device__ __forceinline__ bool in_gap(const int64_t* __restrict__ gaps, int n_gaps, int64_t j) {
+    int lo = 0, hi = n_gaps - 1, best = -1;
+    while (lo <= hi) {
+        const int mid = (lo + hi) >> 1;
+        if (gaps[2 * mid] <= j) {
+            best = mid;
+            lo = mid + 1;
+        } else {
+            hi = mid - 1;
+        }
+    }
+    return best >= 0 && j < gaps[2 * best + 1];
+}
+
+__device__ __forceinline__ uint32_t pack_half2(float re, float im) {
+    const __half2 h = __floats2half2_rn(re, im);
+    return *reinterpret_cast<const uint32_t*>(&h);
+}
+}  // namespace
+
+__global__ __launch_bounds__(kThreads) void rsf_resample_k(ResampleArgs A) {
+    __shared__ float2 win[4][kWinMax];
+    __shared__ float4 tile_main[kTileA][kTileB + 1];
+    __shared__ double tile_tm[kTileA][kTileB + 1];
+    __shared__ uint32_t tile_mask[kTileA][2];
+    __shared__ double red[4][3];
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int b0 = blockIdx.x * kTileB;
+    const int64_t a0 = (int64_t)blockIdx.y * kTileA;
+    const int sky = blockIdx.z;
+    const double alpha = A.sky[2 * sky], delta = A.sky[2 * sky + 1];
+    const double3 n0 = sky_unit(alpha, delta);
+    const SkyFrame fr = sky_frame(alpha, delta);
+    const int W = A.ip.taps;
+    const int hw = W / 2;
+    double sA = 0.0, sB = 0.0, sC = 0.0;
+    bool window_overflow = false;
+
+    for (int r = 0; r < kTileA / 4; ++r) {
+        const int ia = wave + 4 * r;
+        const int64_t n_a = a0 + ia;
+        const int n_b = b0 + lane;
+        const int64_t k = (int64_t)A.LB * n_a + n_b;
+        const bool valid = (n_b < A.LB) && (n_a < A.P) && (k < A.n);
+
+        int j = 0;
+        float frac = 0.f;
+        double tm = 0.0, av = 0.0, bv = 0.0;
+        bool mk = false;
+        if (valid) {
+            const double tb = (double)k * A.dt;
+            double T = tb;
+            SiteAngles g;
+            for (int it = 0; it < 5; ++it) T = tb - roemer(A.t_start + T, n0, A.eph, A.det, &g);
+            tm = tb - T;
+            const double u = T / A.dt;
+            const double fl = floor(u);
+            j = (int)fl;
+            frac = (float)(u - fl);
+            beam_ab(g, A.det, fr, &av, &bv);
+            const int64_t jn = (int64_t)floor(u + 0.5);
+            mk = (jn >= 0) && (jn < A.n) && !in_gap(A.gaps, A.n_gaps, jn);
+        }
+
+        // window of detector samples needed by this run
+        int jmin = valid ? j : INT_MAX;
+        int jmax = valid ? j : INT_MIN;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            jmin = min(jmin, __shfl_xor(jmin, off));
+            jmax = max(jmax, __shfl_xor(jmax, off));
+        }
+        const bool any = jmin != INT_MAX;
+        const int w0 = any ? jmin - hw + 1 : 0;
+        const int wlen = any ? (jmax - jmin + W) : 0;
+        const bool ok = wlen <= kWinMax;
+        if (any && ok) {
+            for (int p = lane; p < wlen; p += 64) {
+                const int64_t jj = (int64_t)w0 + p;
+                float2 z = make_float2(0.f, 0.f);
+                if (jj >= 0 && jj < A.n) {
+                    const float2 xv = A.x[jj];
+                    SiteAngles gg;
+                    const double tmj = roemer(A.t_start + (double)jj * A.dt, n0, A.eph, A.det, &gg);
+                    const double cyc = A.f_het * tmj;
+                    const float ph = (float)(cyc - rint(cyc));
+                    float s, c;
+                    sincospif(2.f * ph, &s, &c);
+                    z = make_float2(xv.x * c + xv.y * s, xv.y * c - xv.x * s);  // x * (c - i s)
+                }
+                win[wave][p] = z;
+            }
+        }
+        if (any && !ok) window_overflow = true;
+        __syncthreads();
+
+        float2 zt = make_float2(0.f, 0.f);
+        if (valid) {
+            if (ok) {
+                const float sf = sinpif(frac);
+                float sw = 0.f, cw = 0.f;
+                if (A.ip.kernel == 0) sincospif(2.f * frac / (float)W, &sw, &cw);
+                const int base = j - hw + 1 - w0;
+                for (int i = 1; i <= W; ++i) {
+                    const float x = frac + (float)(hw - i);
+                    float w;
+                    if (x == 0.f) {
+                        w = 1.f;
+                    } else {
+                        const float sx = ((hw - i) & 1) ? -sf : sf;  // sin(pi x)
+                        if (A.ip.kernel == 0) {
+                            const float s2 = sw * A.ip.cphi[i] + cw * A.ip.sphi[i];  // sin(2 pi x / W)
+                            w = sx * s2 * (float)W / (2.f * kPiF * kPiF * x * x);
+                        } else {
+                            const float y = kPiF * x / (float)A.ip.n;
+                            const float den = (float)A.ip.n * (A.ip.n_odd ? sinf(y) : tanf(y));
+                            w = sx / den;
+                        }
+                    }
+                    const float2 zz = win[wave][base + i - 1];
+                    zt.x += w * zz.x;
+                    zt.y += w * zz.y;
+                }
+            } else {
+                zt = make_float2(__int_as_float(0x7fc00000), __int_as_float(0x7fc00000));
+            }
+            if (mk) {
+                sA += av * av;
+                sB += bv * bv;
+                sC += av * bv;
+            }
+        }
+        if (A.f16) {
+            tile_main[ia][lane] = valid ? make_float4(__uint_as_float(pack_half2(zt.x, zt.y)), (float)av,
+                                                      (float)bv, (float)tm)
+                                        : make_float4(0.f, 0.f, 0.f, 0.f);
+        } else {
+            tile_main[ia][lane] = valid ? make_float4(zt.x, zt.y, (float)av, (float)bv)
+                                        : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        tile_tm[ia][lane] = valid ? tm : 0.0;
+        const uint64_t bal = __ballot(valid && mk);
+        if (lane == 0) {
+            tile_mask[ia][0] = (uint32_t)bal;
+            tile_mask[ia][1] = (uint32_t)(bal >> 32);
+        }
+        __syncthreads();
+    }
+
+    if (window_overflow && lane == 0) atomicOr(A.flags, 2u);
+
+    // write the tile
+    if (A.layout == 1) {
+        const int64_t sky_off = (int64_t)sky * A.rs_sky_stride;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int nb_off = (threadIdx.x >> 4) + 16 * q;
+            const int na_off = threadIdx.x & 15;
+            const int n_b = b0 + nb_off;
+            const int64_t n_a = a0 + na_off;
+            if (n_b < A.LB && n_a < A.P) {
+                const int64_t idx = sky_off + (int64_t)n_b * A.P + n_a;
+                A.rs_main[idx] = tile_main[na_off][nb_off];
+                if (!A.f16) A.rs_tm[idx] = (float)tile_tm[na_off][nb_off];
+            }
+        }
+    } else {
+        const int64_t sky_off = (int64_t)sky * A.n;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int ia = (threadIdx.x >> 6) + 4 * q;
+            const int64_t k = (int64_t)A.LB * (a0 + ia) + b0 + lane;
+            if (b0 + lane < A.LB && a0 + ia < A.P && k < A.n) {
+                const float4 m = tile_main[ia][lane];
+                if (A.out_z) A.out_z[sky_off + k] = A.f16 ? make_float2(0.f, 0.f) : make_float2(m.x, m.y);
+                if (A.out_zh) A.out_zh[sky_off + k] = __float_as_uint(m.x);
+                if (A.out_a) A.out_a[sky_off + k] = A.f16 ? m.y : m.z;
+                if (A.out_b) A.out_b[sky_off + k] = A.f16 ? m.z : m.w;
+                if (A.out_tm) A.out_tm[sky_off + k] = tile_tm[ia][lane];
+            }
+        }
+        if (A.out_mask && threadIdx.x < kTileA && A.LB == 64) {
+            const int ia = threadIdx.x;
+            const int64_t word = ((a0 + ia) * 64) / 32;
+            const int64_t moff = (int64_t)sky * A.n_words;
+            if (a0 + ia < A.P) {
+                if (word < A.n_words) A.out_mask[moff + word] = tile_mask[ia][0];
+                if (word + 1 < A.n_words) A.out_mask[moff + word + 1] = tile_mask[ia][1];
+            }
+        }
+    }
+
+    // antenna-sum partials, fixed reduction order
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        sA += __shfl_xor(sA, off);
+        sB += __shfl_xor(sB, off);
+        sC += __shfl_xor(sC, off);
+    }
+    if (lane == 0) {
+        red[wave][0] = sA;
+        red[wave][1] = sB;
+        red[wave][2] = sC;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const int c = threadIdx.x;
+        const double tot = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+        const int blk = blockIdx.y * gridDim.x + blockIdx.x;
+        A.partials[((int64_t)sky * A.n_blocks + blk) * 3 + c] = tot;
+    }
+}
+
+// One workgroup per sky: sums the block partials of every detector in a
+// fixed order and forms the F-statistic coefficients 2B'/D', 2A'/D', -4C'/D'
+// (eq. eq6 with noise-weighted sums) in FP64.
+__global__ __launch_bounds__(256) void rsf_antenna_reduce_k(ReduceArgs R) {
+    __shared__ double red[256][3];
+    const int sky = blockIdx.x;
+    double wsum[3] = {0.0, 0.0, 0.0};
+    for (int X = 0; X < R.n_det; ++X) {
+        double s[3] = {0.0, 0.0, 0.0};
+        const double* p = R.partials + ((int64_t)X * R.n_sky + sky) * (int64_t)R.n_blocks * 3;
+        for (int i = threadIdx.x; i < R.n_blocks; i += 256) {
+            s[0] += p[3 * i + 0];
+            s[1] += p[3 * i + 1];
+            s[2] += p[3 * i + 2];
+        }
+        red[threadIdx.x][0] = s[0];
+        red[threadIdx.x][1] = s[1];
+        red[threadIdx.x][2] = s[2];
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if (threadIdx.x < h) {
+                red[threadIdx.x][0] += red[threadIdx.x + h][0];
+                red[threadIdx.x][1] += red[threadIdx.x + h][1];
+                red[threadIdx.x][2] += red[threadIdx.x + h][2];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            if (R.abc_det[X]) {
+                double* o = R.abc_det[X] + (int64_t)sky * 3;
+                o[0] = red[0][0];
+                o[1] = red[0][1];
+                o[2] = red[0][2];
+            }
+            wsum[0] += R.w[X] * red[0][0];
+            wsum[1] += R.w[X] * red[0][1];
+            wsum[2] += R.w[X] * red[0][2];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double A = wsum[0], B = wsum[1], C = wsum[2];
+        const double D = A * B - C * C;
+        if (R.abc_w) {
+            R.abc_w[3 * sky + 0] = A;
+            R.abc_w[3 * sky + 1] = B;
+            R.abc_w[3 * sky + 2] = C;
+        }
+        float* cf = R.coef + 4 * sky;
+        if (D > 0.0 && A > 0.0 && B > 0.0) {
+            cf[0] = (float)(2.0 * B / D);
+            cf[1] = (float)(2.0 * A / D);
+            cf[2] = (float)(-4.0 * C / D);
+            cf[3] = 0.f;
+        } else {
+            const float nan = __int_as_float(0x7fc00000);
+            cf[0] = cf[1] = cf[2] = nan;
+            cf[3] = 1.f;
+            atomicOr(R.flags, 1u);
+        }
+    }
+}
+
+hipError_t launch_resample(const ResampleArgs& a, int n_sky, hipStream_t s) {
+    const unsigned gx = (unsigned)((a.LB + kTileB - 1) / kTileB);
+    const unsigned gy = (unsigned)((a.P + kTileA - 1) / kTileA);
+    hipLaunchKernelGGL(rsf_resample_k, dim3(gx, gy, (unsigned)n_sky), dim3(kThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+int resample_blocks(int LB, int64_t P) {
+    return ((LB + kTileB - 1) / kTileB) * (int)((P + kTileA - 1) / kTileA);
+}
+
+hipError_t launch_antenna_reduce(const ReduceArgs& r, hipStream_t s) {
+    hipLaunchKernelGGL(rsf_antenna_reduce_k, dim3((unsigned)r.n_sky), dim3(256), 0, s, r);
+    return hipGetLastError();
+}
+
+}  // namespace rsf

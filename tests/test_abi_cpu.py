@@ -1,0 +1,76 @@
+"""CPU-side checks of the C ABI: the library builds, loads and exports every
+symbol declared in include/rsfstat.h; the ctypes mirror has the header's
+layout.  No compute call is made (there is no GPU here)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_0912_4255_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rsfstat.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"^(?:int|const char\*)\s+(rsf_\w+)\s*\(", src, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(L.LIB_PATH):
+        from paper_0912_4255_amd import build
+        build.build()
+    return L.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 12
+    assert set(names) == set(L.EXPORTS)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_version_and_error_string(lib):
+    assert lib.rsf_version() == 1
+    assert isinstance(lib.rsf_last_error(), bytes)
+
+
+def test_struct_sizes_match_header_layout():
+    # rsf_plan_desc: 6 int32 + int64 + 5 double + ephemeris (7 double) + 4 detectors (4 double)
+    assert C.sizeof(L.PlanDesc) == 6 * 4 + 8 + 5 * 8 + 7 * 8 + 4 * 4 * 8
+    assert C.sizeof(L.Segment) == 4 * 8 + 4 * 8 + 4 * 4
+    assert C.sizeof(L.Resampled) == 6 * 8
+    assert C.sizeof(L.TopkEntry) == 16
+
+
+def test_null_arguments_rejected_without_gpu(lib):
+    p = C.c_void_p()
+    assert lib.rsf_plan_create(C.byref(p), None) == L.RSF_EINVAL
+    assert b"NULL" in lib.rsf_last_error()
+    b = C.c_size_t()
+    assert lib.rsf_workspace_size(None, 0, 1, 1, 0, C.byref(b)) == L.RSF_EINVAL
+    assert lib.rsf_fstat(None, None, None, 1, None, 1, 0, None, None, 0, None) == L.RSF_EINVAL
+
+
+def test_invalid_descriptors_rejected_before_device_use(lib):
+    from paper_0912_4255_amd import synth
+    from paper_0912_4255_amd.api import plan_desc_from_workload
+    w = synth.small_workload(n=1000, dt=1.0)
+    cases = []
+    d = plan_desc_from_workload(w); d.taps = 7; cases.append((d, L.RSF_EUNSUPPORTED))
+    d = plan_desc_from_workload(w); d.taps = 40; cases.append((d, L.RSF_EUNSUPPORTED))
+    d = plan_desc_from_workload(w); d.dt = -1.0; cases.append((d, L.RSF_EINVAL))
+    d = plan_desc_from_workload(w); d.n = 0; cases.append((d, L.RSF_EINVAL))
+    d = plan_desc_from_workload(w); d.n_det = 0; cases.append((d, L.RSF_EINVAL))
+    d = plan_desc_from_workload(w); d.det[0].sigma2 = 0.0; cases.append((d, L.RSF_EINVAL))
+    d = plan_desc_from_workload(w); d.f_het = float("nan"); cases.append((d, L.RSF_EINVAL))
+    d = plan_desc_from_workload(w); d.n = 1001; cases.append((d, L.RSF_EUNSUPPORTED))   # 2002 = 2 * 7 * 11 * 13
+    d = plan_desc_from_workload(w); d.f_lo, d.f_hi = 99.0, 99.2; cases.append((d, L.RSF_EINVAL))
+    for desc, code in cases:
+        p = C.c_void_p()
+        assert lib.rsf_plan_create(C.byref(p), C.byref(desc)) == code, lib.rsf_last_error()
+        assert not p.value
