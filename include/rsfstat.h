@@ -195,6 +195,20 @@ int rsf_fstat_backward(const rsf_plan* plan, const rsf_segment* seg, const doubl
                        const float* g_twoF, float* twoF, double* g_theta,
                        void* ws, size_t ws_bytes, void* stream);
 
+/* Instrumentation (not part of the method): when enabled, every kernel the
+ * plan launches is bracketed by hipEvents recorded on the launch stream.
+ * rsf_profile_read synchronises on those events, writes up to max_kinds
+ * records {kernel name, launches, summed milliseconds} (host memory), sets
+ * *n_kinds and clears the counters. */
+typedef struct rsf_kernel_time {
+    char name[32];
+    int64_t launches;
+    double total_ms;
+} rsf_kernel_time;
+
+int rsf_profile_enable(rsf_plan* plan, int on);
+int rsf_profile_read(rsf_plan* plan, rsf_kernel_time* out, int max_kinds, int* n_kinds);
+
 /* Copy the device flags word (RSF_FLAG_*) of the workspace to *flags (host)
  * and clear it; synchronises `stream`. */
 int rsf_get_flags(const rsf_plan* plan, void* ws, uint32_t* flags, void* stream);

@@ -18,7 +18,7 @@ RSF_FLAG_DEGENERATE, RSF_FLAG_WINDOW = 1, 2
 EXPORTS = [
     "rsf_plan_create", "rsf_plan_destroy", "rsf_plan_query", "rsf_workspace_size",
     "rsf_resample", "rsf_fstat", "rsf_fstat_topk", "rsf_fstat_point", "rsf_fstat_backward",
-    "rsf_get_flags", "rsf_last_error", "rsf_version",
+    "rsf_get_flags", "rsf_last_error", "rsf_version", "rsf_profile_enable", "rsf_profile_read",
 ]
 
 
@@ -53,6 +53,10 @@ class TopkEntry(C.Structure):
     _fields_ = [("twoF", C.c_float), ("sky", C.c_int32), ("fdot", C.c_int32), ("bin", C.c_int32)]
 
 
+class KernelTime(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64), ("total_ms", C.c_double)]
+
+
 _lib = None
 
 
@@ -78,6 +82,8 @@ def load(path=None):
     lib.rsf_fstat_point.argtypes = [vp, C.POINTER(Segment), vp, i64, vp, vp, sz, vp]
     lib.rsf_fstat_backward.argtypes = [vp, C.POINTER(Segment), vp, i64, vp, vp, vp, vp, sz, vp]
     lib.rsf_get_flags.argtypes = [vp, vp, C.POINTER(C.c_uint32), vp]
+    lib.rsf_profile_enable.argtypes = [vp, i32]
+    lib.rsf_profile_read.argtypes = [vp, C.POINTER(KernelTime), i32, C.POINTER(C.c_int)]
     lib.rsf_last_error.restype = C.c_char_p
     lib.rsf_last_error.argtypes = []
     lib.rsf_version.argtypes = []

@@ -149,6 +149,17 @@ class Plan:
                                    _ptr(out), _ptr(ws), ws.numel(), _stream()))
         return out
 
+    def profile(self, on=True):
+        """Bracket every launch of this plan with hipEvents (instrumentation)."""
+        L.check(self.lib.rsf_profile_enable(self._p, 1 if on else 0))
+
+    def profile_read(self):
+        """{kernel: (launches, total_ms)} since the last read; synchronises."""
+        buf = (L.KernelTime * 8)()
+        n = C.c_int()
+        L.check(self.lib.rsf_profile_read(self._p, buf, 8, C.byref(n)))
+        return {buf[i].name.decode(): (buf[i].launches, buf[i].total_ms) for i in range(min(n.value, 8))}
+
     def flags(self, ws):
         f = C.c_uint32()
         L.check(self.lib.rsf_get_flags(self._p, _ptr(ws), C.byref(f), _stream()))

@@ -103,8 +103,45 @@ bool radix_plan(int len, int B, FftStages* st) {
 
 }  // namespace
 
+namespace {
+// Launch timing with hipEvents (instrumentation only).
+struct Profiler {
+    bool on = false;
+    struct Rec {
+        int kind;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> pending;
+    std::vector<hipEvent_t> pool;
+    static constexpr int kKinds = 4;
+    const char* names[kKinds] = {"rsf_resample_k", "rsf_antenna_reduce_k", "rsf_fft_pass_a_k", "rsf_fft_pass_b_k"};
+    int64_t launches[kKinds] = {0, 0, 0, 0};
+    double ms[kKinds] = {0, 0, 0, 0};
+
+    hipEvent_t get() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    ~Profiler() {
+        for (auto& r : pending) {
+            hipEventDestroy(r.a);
+            hipEventDestroy(r.b);
+        }
+        for (auto e : pool) hipEventDestroy(e);
+    }
+};
+enum { K_RESAMPLE = 0, K_REDUCE = 1, K_PASS_A = 2, K_PASS_B = 3 };
+}  // namespace
+
 struct rsf_plan {
     rsf_plan_desc d;
+    Profiler* prof;
     int device;
     int64_t n, n_fft, s_lo, n_out;
     double df;
@@ -210,6 +247,19 @@ int check_segment(const rsf_plan* p, const rsf_segment* seg) {
     return RSF_OK;
 }
 
+// Launch through fn(); with profiling on, bracket it with events on s.
+template <typename Fn>
+hipError_t timed(const rsf_plan* p, int kind, hipStream_t s, Fn fn) {
+    Profiler* pr = p->prof;
+    if (!pr || !pr->on) return fn();
+    hipEvent_t a = pr->get(), b = pr->get();
+    if (a) hipEventRecord(a, s);
+    hipError_t e = fn();
+    if (b) hipEventRecord(b, s);
+    if (a && b) pr->pending.push_back({kind, a, b});
+    return e;
+}
+
 }  // namespace
 
 extern "C" {
@@ -246,6 +296,7 @@ int rsf_plan_create(rsf_plan** out, const rsf_plan_desc* d) {
 
     rsf_plan* p = new rsf_plan();
     p->d = *d;
+    p->prof = new Profiler();
     p->n = d->n;
     p->n_fft = (d->nfft_policy == RSF_NFFT_TWICE) ? 2 * d->n : next_7smooth(2 * d->n);
     if (!is_7smooth(p->n_fft)) {
@@ -358,11 +409,6 @@ int rsf_plan_create(rsf_plan** out, const rsf_plan_desc* d) {
     p->ip.taps = d->taps;
     p->ip.n = (int)d->n;
     p->ip.n_odd = (int)(d->n & 1);
-    for (int i = 0; i <= kMaxTaps; ++i) {
-        const double phi = M_PI * (1.0 - 2.0 * i / (double)d->taps);
-        p->ip.cphi[i] = (float)std::cos(phi);
-        p->ip.sphi[i] = (float)std::sin(phi);
-    }
     *out = p;
     return RSF_OK;
 }
@@ -373,6 +419,7 @@ int rsf_plan_destroy(rsf_plan* p) {
     hipFree(p->twB);
     hipFree(p->tw_lo);
     hipFree(p->tw_hi);
+    delete p->prof;
     delete p;
     return RSF_OK;
 }
@@ -439,7 +486,7 @@ int rsf_resample(const rsf_plan* p, const rsf_segment* seg, const double* sky, i
         a.partials = (double*)(w + L.partials) + (size_t)X * n_sky * L.n_blocks * 3;
         a.n_blocks = L.n_blocks;
         a.flags = flags;
-        RSF_HIP(launch_resample(a, (int)n_sky, s), "resample launch");
+        RSF_HIP(timed(p, K_RESAMPLE, s, [&] { return launch_resample(a, (int)n_sky, s); }), "resample launch");
     }
     ReduceArgs r{};
     r.partials = (const double*)(w + L.partials);
@@ -452,7 +499,7 @@ int rsf_resample(const rsf_plan* p, const rsf_segment* seg, const double* sky, i
     }
     r.coef = (float*)(w + L.coef);
     r.flags = flags;
-    RSF_HIP(launch_antenna_reduce(r, s), "antenna reduce launch");
+    RSF_HIP(timed(p, K_REDUCE, s, [&] { return launch_antenna_reduce(r, s); }), "antenna reduce launch");
     return RSF_OK;
 }
 
@@ -489,7 +536,7 @@ int rsf_fstat(const rsf_plan* p, const rsf_segment* seg, const double* sky, int6
             a.partials = (double*)(w + L.partials) + (size_t)X * L.n_blocks * 3;
             a.n_blocks = L.n_blocks;
             a.flags = flags;
-            RSF_HIP(launch_resample(a, 1, s), "resample launch");
+            RSF_HIP(timed(p, K_RESAMPLE, s, [&] { return launch_resample(a, 1, s); }), "resample launch");
         }
         ReduceArgs r{};
         r.partials = (const double*)(w + L.partials);
@@ -500,7 +547,7 @@ int rsf_fstat(const rsf_plan* p, const rsf_segment* seg, const double* sky, int6
         r.abc_w = (double*)(w + L.abc_w);
         r.coef = (float*)(w + L.coef);
         r.flags = flags;
-        RSF_HIP(launch_antenna_reduce(r, s), "antenna reduce launch");
+        RSF_HIP(timed(p, K_REDUCE, s, [&] { return launch_antenna_reduce(r, s); }), "antenna reduce launch");
 
         for (int64_t f0 = 0; f0 < n_fdot; f0 += L.G) {
             const int g = (int)std::min<int64_t>(L.G, n_fdot - f0);
@@ -527,7 +574,7 @@ int rsf_fstat(const rsf_plan* p, const rsf_segment* seg, const double* sky, int6
             A.tw_hi = p->tw_hi;
             A.spill = spill;
             A.spill_tmpl_stride = spill_stride;
-            RSF_HIP(launch_fft_pass_a(A, s), "pass A launch");
+            RSF_HIP(timed(p, K_PASS_A, s, [&] { return launch_fft_pass_a(A, s); }), "pass A launch");
 
             PassBArgs B{};
             B.n_fft = p->n_fft;
@@ -544,7 +591,7 @@ int rsf_fstat(const rsf_plan* p, const rsf_segment* seg, const double* sky, int6
             B.twoF = twoF;
             B.out_row0 = sk * n_fdot + f0;
             B.n_tmpl = g;
-            RSF_HIP(launch_fft_pass_b(B, s), "pass B launch");
+            RSF_HIP(timed(p, K_PASS_B, s, [&] { return launch_fft_pass_b(B, s); }), "pass B launch");
         }
     }
     return RSF_OK;
@@ -562,6 +609,41 @@ int rsf_fstat_point(const rsf_plan*, const rsf_segment*, const double*, int64_t,
 int rsf_fstat_backward(const rsf_plan*, const rsf_segment*, const double*, int64_t, const float*, float*, double*,
                        void*, size_t, void*) {
     return fail(RSF_EUNSUPPORTED, "rsf_fstat_backward not built yet");
+}
+
+int rsf_profile_enable(rsf_plan* p, int on) {
+    if (!p) return fail(RSF_EINVAL, "plan is NULL");
+    p->prof->on = on != 0;
+    return RSF_OK;
+}
+
+int rsf_profile_read(rsf_plan* p, rsf_kernel_time* out, int max_kinds, int* n_kinds) {
+    if (!p || !n_kinds) return fail(RSF_EINVAL, "plan or n_kinds is NULL");
+    Profiler* pr = p->prof;
+    for (auto& r : pr->pending) {
+        RSF_HIP(hipEventSynchronize(r.b), "hipEventSynchronize");
+        float ms = 0.f;
+        RSF_HIP(hipEventElapsedTime(&ms, r.a, r.b), "hipEventElapsedTime");
+        pr->ms[r.kind] += ms;
+        pr->launches[r.kind] += 1;
+        pr->pool.push_back(r.a);
+        pr->pool.push_back(r.b);
+    }
+    pr->pending.clear();
+    int n = 0;
+    for (int k = 0; k < Profiler::kKinds; ++k) {
+        if (!pr->launches[k]) continue;
+        if (out && n < max_kinds) {
+            std::snprintf(out[n].name, sizeof(out[n].name), "%s", pr->names[k]);
+            out[n].launches = pr->launches[k];
+            out[n].total_ms = pr->ms[k];
+        }
+        ++n;
+        pr->launches[k] = 0;
+        pr->ms[k] = 0;
+    }
+    *n_kinds = n;
+    return RSF_OK;
 }
 
 int rsf_get_flags(const rsf_plan* p, void* ws, uint32_t* flags, void* stream) {

@@ -46,10 +46,6 @@ struct InterpDev {
     int taps;     // W (even)
     int n;        // series length (Dirichlet period)
     int n_odd;    // Dirichlet: sin instead of tan in the denominator
-    // Lanczos: sin(2 pi x_i / W) = sin(2 pi frac/W) cos(phi_i) + cos(2 pi frac/W) sin(phi_i),
-    // phi_i = pi (1 - 2 i / W), i = 1..W
-    float cphi[kMaxTaps + 1];
-    float sphi[kMaxTaps + 1];
 };
 
 // Resampling kernel (one detector, a batch of sky positions).

@@ -129,8 +129,6 @@ __global__ __launch_bounds__(kThreads) void rsf_resample_k(ResampleArgs A) {
         if (valid) {
             if (ok) {
                 const float sf = sinpif(frac);
-                float sw = 0.f, cw = 0.f;
-                if (A.ip.kernel == 0) sincospif(2.f * frac / (float)W, &sw, &cw);
                 const int base = j - hw + 1 - w0;
                 for (int i = 1; i <= W; ++i) {
                     const float x = frac + (float)(hw - i);
@@ -140,7 +138,9 @@ __global__ __launch_bounds__(kThreads) void rsf_resample_k(ResampleArgs A) {
                     } else {
                         const float sx = ((hw - i) & 1) ? -sf : sf;  // sin(pi x)
                         if (A.ip.kernel == 0) {
-                            const float s2 = sw * A.ip.cphi[i] + cw * A.ip.sphi[i];  // sin(2 pi x / W)
+                            // sin(2 pi x / W) straight from x: x is exact (frac + integer) and
+                            // an angle-addition form would cancel when x -> 0 off the centre tap
+                            const float s2 = sinpif(2.f * x / (float)W);
                             w = sx * s2 * (float)W / (2.f * kPiF * kPiF * x * x);
                         } else {
                             const float y = kPiF * x / (float)A.ip.n;
