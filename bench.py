@@ -163,8 +163,8 @@ def main():
            "value": round(value, 2), "unit": "templates/s", "n_gpus": 1, "steps": a.steps,
            "warmup": a.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": "T=10d dt=0.25s N=3456000 10% gaps, 1 sky x %d fdot, "
-                                  "Dirichlet-16, N_fft=6912000, band [100,102) Hz" % n_t,
+           "config": {"workload": f"T=10d dt=0.25s N=3456000 10pct gaps, 1 sky x {n_t} fdot, "
+                                  "Dirichlet-16, N_fft=6912000, band [100,102) Hz",
                       "templates_per_step": n_t, "n_fft": Nf, "n_out": No,
                       "fft_factors": [plan.fft_l1, plan.fft_l2]},
            "plain_templates_per_s": round(plain_rate, 2),

@@ -138,5 +138,20 @@ def test_c1_full_size(gpu_lib):
     rss = _oracle_rs(w, xs, gaps, inj.alpha, inj.delta)
     ref = of.fstat_band(rss, w.detectors, inj.fdot, plan.n_fft, plan.s_lo, plan.n_out)
     assert np.all(np.abs(got - ref) <= twoF_tol(ref))
-    # f0 = 100.25 Hz is bin 43,200 above f_het
+
+
+def test_c1_noise_free_peak(gpu_lib):
+    """C1's injection (rho^2 ~ 10 in unit noise) without the noise: the
+    matched template peaks at f0 = 100.25 Hz, bin 43,200 above f_het."""
+    import torch
+    w = synth.workload_c1()
+    xs, gaps = make_inputs(w, seed=0, injections=w.injections, noise=False)
+    plan = gpu_lib.Plan(w)
+    tx, tg = to_gpu(xs, gaps)
+    got = plan.fstat(tx, tg, torch.from_numpy(w.skies).cuda(), torch.from_numpy(w.fdots).cuda())
+    got = got.cpu().numpy()[0]
     assert int(np.argmax(got)) == 43200 - plan.s_lo
+    inj = w.injections[0]
+    rss = _oracle_rs(w, xs, gaps, inj.alpha, inj.delta)
+    ref = of.fstat_bins(rss, w.detectors, inj.fdot, plan.n_fft, [43200])[0]
+    assert abs(got[43200 - plan.s_lo] - ref) <= 1e-4 * max(ref, 4.0)
