@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--plain-templates", type=int, default=32)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-templates", type=int, default=2)
+    ap.add_argument("--copy-check", action="store_true",
+                    help="also run one 1 GiB device-to-device copy (counter calibration under a profiler)")
     return ap.parse_args()
 
 
@@ -100,6 +102,13 @@ def main():
     n_t = a.n_fdot
     out = torch.empty((n_t, plan.n_out), dtype=torch.float32, device=dev)
     ws = plan.workspace(rsf.RSF_ENTRY_FSTAT, 1, n_t, rsf.RSF_MODE_BATCHED, device=dev)
+
+    if a.copy_check:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def step():
         plan.fstat(tx, tg, sky, fd, mode=rsf.RSF_MODE_BATCHED, out=out, ws=ws)

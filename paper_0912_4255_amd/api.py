@@ -149,6 +149,35 @@ class Plan:
                                    _ptr(out), _ptr(ws), ws.numel(), _stream()))
         return out
 
+    def point(self, xs, gaps, theta, out=None, ws=None):
+        """rsf_fstat_point: 2F [n] at continuous theta [n, 4] = (f, fdot, alpha, delta)."""
+        _need_cuda(theta, torch.float64, "theta")
+        n = theta.shape[0]
+        seg, keep = self.segment(xs, gaps)
+        dev = xs[0].device
+        if out is None:
+            out = torch.empty(n, dtype=torch.float32, device=dev)
+        if ws is None:
+            ws = self.workspace(L.RSF_ENTRY_POINT, 1, n, device=dev)
+        L.check(self.lib.rsf_fstat_point(self._p, C.byref(seg), _ptr(theta), n, _ptr(out), _ptr(ws),
+                                         ws.numel(), _stream()))
+        return out
+
+    def backward(self, xs, gaps, theta, g_twoF, ws=None):
+        """rsf_fstat_backward: (2F [n], g_twoF * d2F/dtheta [n, 4])."""
+        _need_cuda(theta, torch.float64, "theta")
+        _need_cuda(g_twoF, torch.float32, "g_twoF")
+        n = theta.shape[0]
+        seg, keep = self.segment(xs, gaps)
+        dev = xs[0].device
+        twoF = torch.empty(n, dtype=torch.float32, device=dev)
+        g_theta = torch.empty((n, 4), dtype=torch.float64, device=dev)
+        if ws is None:
+            ws = self.workspace(L.RSF_ENTRY_BACKWARD, 1, n, device=dev)
+        L.check(self.lib.rsf_fstat_backward(self._p, C.byref(seg), _ptr(theta), n, _ptr(g_twoF), _ptr(twoF),
+                                            _ptr(g_theta), _ptr(ws), ws.numel(), _stream()))
+        return twoF, g_theta
+
     def profile(self, on=True):
         """Bracket every launch of this plan with hipEvents (instrumentation)."""
         L.check(self.lib.rsf_profile_enable(self._p, 1 if on else 0))
@@ -164,3 +193,27 @@ class Plan:
         f = C.c_uint32()
         L.check(self.lib.rsf_get_flags(self._p, _ptr(ws), C.byref(f), _stream()))
         return f.value
+
+
+class FStatFn(torch.autograd.Function):
+    """2F(theta) at continuous (f, fdot, alpha, delta) with a hand-written
+    adjoint: forward calls rsf_fstat_point, backward rsf_fstat_backward (which
+    recomputes the resampled series).  theta: float64 [n, 4] on the GPU."""
+
+    @staticmethod
+    def forward(ctx, theta, plan, xs, gaps):
+        theta = theta.detach().contiguous()
+        ctx.save_for_backward(theta)
+        ctx.plan, ctx.xs, ctx.gaps = plan, xs, gaps
+        return plan.point(xs, gaps, theta)
+
+    @staticmethod
+    def backward(ctx, g):
+        (theta,) = ctx.saved_tensors
+        _, g_theta = ctx.plan.backward(ctx.xs, ctx.gaps, theta, g.detach().float().contiguous())
+        return g_theta, None, None, None
+
+
+def fstat_point(plan, xs, gaps, theta):
+    """Differentiable 2F at continuous parameters (see FStatFn)."""
+    return FStatFn.apply(theta, plan, xs, gaps)

@@ -113,10 +113,11 @@ struct Profiler {
     };
     std::vector<Rec> pending;
     std::vector<hipEvent_t> pool;
-    static constexpr int kKinds = 4;
-    const char* names[kKinds] = {"rsf_resample_k", "rsf_antenna_reduce_k", "rsf_fft_pass_a_k", "rsf_fft_pass_b_k"};
-    int64_t launches[kKinds] = {0, 0, 0, 0};
-    double ms[kKinds] = {0, 0, 0, 0};
+    static constexpr int kKinds = 7;
+    const char* names[kKinds] = {"rsf_resample_k", "rsf_antenna_reduce_k", "rsf_fft_pass_a_k", "rsf_fft_pass_b_k",
+                                 "rsf_point_k",    "rsf_point_reduce_k",   "rsf_topk_k"};
+    int64_t launches[kKinds] = {};
+    double ms[kKinds] = {};
 
     hipEvent_t get() {
         if (!pool.empty()) {
@@ -136,7 +137,7 @@ struct Profiler {
         for (auto e : pool) hipEventDestroy(e);
     }
 };
-enum { K_RESAMPLE = 0, K_REDUCE = 1, K_PASS_A = 2, K_PASS_B = 3 };
+enum { K_RESAMPLE = 0, K_REDUCE = 1, K_PASS_A = 2, K_PASS_B = 3, K_POINT = 4, K_POINT_REDUCE = 5, K_TOPK = 6 };
 }  // namespace
 
 struct rsf_plan {
@@ -216,6 +217,23 @@ ResLayout resample_layout(const rsf_plan* p, int64_t n_sky) {
     off = align_up(off + (size_t)p->d.n_det * n_sky * L.n_blocks * 3 * sizeof(double));
     L.coef = off;
     off = align_up(off + (size_t)n_sky * 4 * sizeof(float));
+    L.total = off;
+    return L;
+}
+
+struct PointLayout {
+    size_t flags, partials, total;
+    int n_blocks;
+};
+
+PointLayout point_layout(const rsf_plan* p, int64_t n_cand) {
+    PointLayout L{};
+    size_t off = 0;
+    L.flags = off;
+    off = align_up(off + 64);
+    L.n_blocks = point_blocks((p->n + 63) / 64);
+    L.partials = off;
+    off = align_up(off + (size_t)n_cand * L.n_blocks * kPointSums * sizeof(double));
     L.total = off;
     return L;
 }
@@ -447,8 +465,12 @@ int rsf_workspace_size(const rsf_plan* p, int entry, int64_t n_sky, int64_t n_fd
             if (mode != RSF_MODE_PLAIN && mode != RSF_MODE_BATCHED) return fail(RSF_EINVAL, "unknown mode");
             *bytes = fstat_layout(p, n_fdot, mode).total;
             return RSF_OK;
+        case RSF_ENTRY_POINT:
+        case RSF_ENTRY_BACKWARD:
+            *bytes = point_layout(p, n_fdot).total;
+            return RSF_OK;
         default:
-            return fail(RSF_EUNSUPPORTED, "entry %d not available", entry);
+            return fail(RSF_EINVAL, "unknown entry %d", entry);
     }
 }
 
@@ -602,13 +624,67 @@ int rsf_fstat_topk(const rsf_plan*, const rsf_segment*, const double*, int64_t, 
     return fail(RSF_EUNSUPPORTED, "rsf_fstat_topk not built yet");
 }
 
-int rsf_fstat_point(const rsf_plan*, const rsf_segment*, const double*, int64_t, float*, void*, size_t, void*) {
-    return fail(RSF_EUNSUPPORTED, "rsf_fstat_point not built yet");
+namespace {
+int point_common(const rsf_plan* p, const rsf_segment* seg, const double* theta, int64_t n, const float* g_twoF,
+                 float* twoF, double* g_theta, void* ws, size_t ws_bytes, void* stream, bool grad) {
+    if (!p) return fail(RSF_EINVAL, "plan is NULL");
+    int rc = check_segment(p, seg);
+    if (rc) return rc;
+    if (!theta) return fail(RSF_EINVAL, "theta is NULL");
+    if (n < 1 || n > 65535) return fail(RSF_EINVAL, "number of candidates must be in 1..65535");
+    if (grad && (!g_twoF || !g_theta)) return fail(RSF_EINVAL, "g_twoF or g_theta is NULL");
+    if (!grad && !twoF) return fail(RSF_EINVAL, "twoF is NULL");
+    if (!ws) return fail(RSF_EINVAL, "workspace is NULL");
+    const PointLayout L = point_layout(p, n);
+    if (ws_bytes < L.total) return fail(RSF_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, L.total);
+    hipStream_t s = (hipStream_t)stream;
+    char* w = (char*)ws;
+    unsigned int* flags = (unsigned int*)(w + L.flags);
+    RSF_HIP(hipMemsetAsync(flags, 0, 64, s), "hipMemsetAsync(flags)");
+    PointArgs a{};
+    a.n = p->n;
+    a.dt = p->d.dt;
+    a.t_start = p->d.t_start;
+    a.f_het = p->d.f_het;
+    a.eph = p->eph;
+    a.n_det = p->d.n_det;
+    for (int X = 0; X < p->d.n_det; ++X) {
+        a.det[X] = p->det[X];
+        a.x[X] = (const float2*)seg->x[X];
+        a.gaps[X] = seg->gaps[X];
+        a.n_gaps[X] = seg->n_gaps[X];
+    }
+    a.ip = p->ip;
+    a.theta = theta;
+    a.n_cand = (int)n;
+    a.P = (p->n + 63) / 64;
+    a.n_blocks = L.n_blocks;
+    a.partials = (double*)(w + L.partials);
+    a.flags = flags;
+    RSF_HIP(timed(p, K_POINT, s, [&] { return launch_point(a, grad, s); }), "point launch");
+    PointReduceArgs r{};
+    r.partials = a.partials;
+    r.n_blocks = L.n_blocks;
+    r.n_cand = (int)n;
+    r.grad = grad ? 1 : 0;
+    r.g_twoF = g_twoF;
+    r.twoF = twoF;
+    r.g_theta = g_theta;
+    r.flags = flags;
+    RSF_HIP(timed(p, K_POINT_REDUCE, s, [&] { return launch_point_reduce(r, s); }), "point reduce launch");
+    return RSF_OK;
+}
+}  // namespace
+
+int rsf_fstat_point(const rsf_plan* p, const rsf_segment* seg, const double* theta, int64_t n, float* twoF, void* ws,
+                    size_t ws_bytes, void* stream) {
+    return point_common(p, seg, theta, n, nullptr, twoF, nullptr, ws, ws_bytes, stream, false);
 }
 
-int rsf_fstat_backward(const rsf_plan*, const rsf_segment*, const double*, int64_t, const float*, float*, double*,
-                       void*, size_t, void*) {
-    return fail(RSF_EUNSUPPORTED, "rsf_fstat_backward not built yet");
+int rsf_fstat_backward(const rsf_plan* p, const rsf_segment* seg, const double* theta, int64_t n,
+                       const float* g_twoF, float* twoF, double* g_theta, void* ws, size_t ws_bytes,
+                       void* stream) {
+    return point_common(p, seg, theta, n, g_twoF, twoF, g_theta, ws, ws_bytes, stream, true);
 }
 
 int rsf_profile_enable(rsf_plan* p, int on) {

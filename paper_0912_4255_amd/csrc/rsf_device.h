@@ -227,6 +227,20 @@ template <> struct Dft<16> : DftCT<4, 4> {};
 // thread are read into registers, the block synchronises, then they are
 // written.  tw is the length-L table W_L^m; W_{Ns R}^{x} = W_L^{x L/(Ns R)}.
 // ---------------------------------------------------------------------------
+// q = j / d and r = j % d for 0 <= j < 2^22 from a float reciprocal: the
+// product is off by at most one, which the correction step removes.
+__device__ __forceinline__ void divmod_small(int j, int d, float inv_d, int& q, int& r) {
+    q = (int)((float)j * inv_d);
+    r = j - q * d;
+    if (r < 0) {
+        --q;
+        r += d;
+    } else if (r >= d) {
+        ++q;
+        r -= d;
+    }
+}
+
 template <int R, int NT, int EPT, int B>
 __device__ __forceinline__ void stockham_stage(cp* __restrict__ s, int L, int Ns,
                                                const float2* __restrict__ tw) {
@@ -235,13 +249,15 @@ __device__ __forceinline__ void stockham_stage(cp* __restrict__ s, int L, int Ns
     const int LR = L / R;
     const int nb = LR * B;
     const int tstride = L / (Ns * R);
+    const float inv_ns = 1.0f / (float)Ns;
     cp v[MAXB][R];
 #pragma unroll
     for (int q = 0; q < MAXB; ++q) {
         const int bf = tid + q * NT;
         if (bf < nb) {
             const int j = bf / B, b = bf - j * B;
-            const int k = j % Ns;
+            int jq, k;
+            divmod_small(j, Ns, inv_ns, jq, k);
 #pragma unroll
             for (int r = 0; r < R; ++r) v[q][r] = s[(j + r * LR) * B + b];
             if (Ns > 1) {
@@ -262,8 +278,9 @@ __device__ __forceinline__ void stockham_stage(cp* __restrict__ s, int L, int Ns
         const int bf = tid + q * NT;
         if (bf < nb) {
             const int j = bf / B, b = bf - j * B;
-            const int k = j % Ns;
-            const int base = (j / Ns) * Ns * R + k;
+            int jq, k;
+            divmod_small(j, Ns, inv_ns, jq, k);
+            const int base = jq * Ns * R + k;
 #pragma unroll
             for (int r = 0; r < R; ++r) s[(base + r * Ns) * B + b] = v[q][r];
         }

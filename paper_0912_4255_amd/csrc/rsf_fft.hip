@@ -24,6 +24,43 @@ constexpr int kNT = kFftThreads;
 constexpr int kEPT = kFftEPT;  // max LA (pass A) or 8 LB (pass B) = kNT * kEPT = 10240
 }  // namespace
 
+// Integrand of one detector for one sample (see the header comment).
+__device__ __forceinline__ void accumulate_integrand(cp& y, float4 m, float tmf, bool f16, double tb, double fd,
+                                                     float w) {
+    float zr, zi, av, bv;
+    if (f16) {
+        const uint32_t bits = __float_as_uint(m.x);
+        const __half2 h = *reinterpret_cast<const __half2*>(&bits);
+        const float2 z = __half22float2(h);
+        zr = z.x;
+        zi = z.y;
+        av = m.y;
+        bv = m.z;
+        tmf = m.w;
+    } else {
+        zr = m.x;
+        zi = m.y;
+        av = m.z;
+        bv = m.w;
+    }
+    // Phi_s = 2 pi fdot (T^2/2 + t_m T) = 2 pi fdot (t_b^2 - t_m^2)/2 with T = t_b - t_m
+    const double tm = (double)tmf;
+    const double cyc = fd * 0.5 * (tb * tb - tm * tm);
+    const float ph = (float)(cyc - rint(cyc));
+    float s, c;
+    sincospif(2.f * ph, &s, &c);
+    const float er = zr * c + zi * s;  // z exp(-i Phi_s)
+    const float ei = zi * c - zr * s;
+    const float wa = w * av, wb = w * bv;
+    y.x += wa * er;
+    y.y += wa * ei;
+    y.z += wb * er;
+    y.w += wb * ei;
+}
+
+// Inputs of one row held per thread: n_a = tid + q * kNT, q < kInPer (P <= LA/2 <= 5120).
+constexpr int kInPer = (kNT * kEPT / 2 + kNT - 1) / kNT;
+
 __global__ __launch_bounds__(kNT) void rsf_fft_pass_a_k(PassAArgs A) {
     extern __shared__ float4 lds[];
     const int n_b = blockIdx.x;
@@ -32,58 +69,56 @@ __global__ __launch_bounds__(kNT) void rsf_fft_pass_a_k(PassAArgs A) {
     const int tid = threadIdx.x;
     const int64_t row = (int64_t)n_b * A.P;
 
+    // first detector's row: all loads issued before any is used, kept for every spindown
+    float4 m0[kInPer];
+    float tm0[kInPer];
+#pragma unroll
+    for (int q = 0; q < kInPer; ++q) {
+        const int n_a = tid + q * kNT;
+        const int64_t k = (int64_t)A.LB * n_a + n_b;
+        if (n_a < A.P && k < A.n) {
+            m0[q] = A.rs_main[0][row + n_a];
+            tm0[q] = A.f16 ? 0.f : A.rs_tm[0][row + n_a];
+        } else {
+            m0[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+            tm0[q] = 0.f;
+        }
+    }
+
+    // inter-pass twiddle W_N^{n_b k_a} for k_a = tid + q kNT: base W^{n_b tid}, step W^{n_b kNT}
+    const int64_t mb = ((int64_t)n_b * tid) % A.n_fft;
+    const int64_t ms = ((int64_t)n_b * kNT) % A.n_fft;
+    const int msk = (1 << kTwSplitBits) - 1;
+    const float2 w_base = c_mul(A.tw_hi[mb >> kTwSplitBits], A.tw_lo[mb & msk]);
+    const float2 w_step = c_mul(A.tw_hi[ms >> kTwSplitBits], A.tw_lo[ms & msk]);
+
     for (int t = t0; t < t1; ++t) {
         const double fd = A.fdot[t];
-        for (int n_a = tid; n_a < A.LA; n_a += kNT) {
-            cp y = make_float4(0.f, 0.f, 0.f, 0.f);
-            const int64_t k = (int64_t)A.LB * n_a + n_b;
-            if (n_a < A.P && k < A.n) {
-                const double tb = (double)k * A.dt;
-                for (int X = 0; X < A.n_det; ++X) {
-                    const float4 m = A.rs_main[X][row + n_a];
-                    float zr, zi, av, bv, tmf;
-                    if (A.f16) {
-                        const uint32_t bits = __float_as_uint(m.x);
-                        const __half2 h = *reinterpret_cast<const __half2*>(&bits);
-                        const float2 z = __half22float2(h);
-                        zr = z.x;
-                        zi = z.y;
-                        av = m.y;
-                        bv = m.z;
-                        tmf = m.w;
-                    } else {
-                        zr = m.x;
-                        zi = m.y;
-                        av = m.z;
-                        bv = m.w;
-                        tmf = A.rs_tm[X][row + n_a];
-                    }
-                    // Phi_s = 2 pi fdot (T^2/2 + t_m T) = 2 pi fdot (t_b^2 - t_m^2)/2, T = t_b - t_m
-                    const double tm = (double)tmf;
-                    const double cyc = fd * 0.5 * (tb * tb - tm * tm);
-                    const float ph = (float)(cyc - rint(cyc));
-                    float s, c;
-                    sincospif(2.f * ph, &s, &c);
-                    const float er = zr * c + zi * s;  // z exp(-i Phi_s)
-                    const float ei = zi * c - zr * s;
-                    const float wa = (float)A.w[X] * av, wb = (float)A.w[X] * bv;
-                    y.x += wa * er;
-                    y.y += wa * ei;
-                    y.z += wb * er;
-                    y.w += wb * ei;
+#pragma unroll
+        for (int q = 0; q < kInPer; ++q) {
+            const int n_a = tid + q * kNT;
+            if (n_a < A.LA) {
+                cp y = make_float4(0.f, 0.f, 0.f, 0.f);
+                const int64_t k = (int64_t)A.LB * n_a + n_b;
+                if (n_a < A.P && k < A.n) {
+                    const double tb = (double)k * A.dt;
+                    accumulate_integrand(y, m0[q], tm0[q], A.f16, tb, fd, (float)A.w[0]);
+                    for (int X = 1; X < A.n_det; ++X)
+                        accumulate_integrand(y, A.rs_main[X][row + n_a], A.f16 ? 0.f : A.rs_tm[X][row + n_a],
+                                             A.f16, tb, fd, (float)A.w[X]);
                 }
+                lds[n_a] = y;
             }
-            lds[n_a] = y;
         }
+        for (int n_a = tid + kInPer * kNT; n_a < A.LA; n_a += kNT) lds[n_a] = make_float4(0.f, 0.f, 0.f, 0.f);
         __syncthreads();
         lds_fft<kNT, kEPT, 1>(lds, A.st, A.tw);
         float4* out = A.spill + (int64_t)t * A.spill_tmpl_stride;
+        float2 w = w_base;
         for (int ka = tid; ka < A.LA; ka += kNT) {
-            cp v = lds[ka];
-            const int64_t m = ((int64_t)n_b * ka) % A.n_fft;
-            const float2 w = c_mul(A.tw_hi[m >> kTwSplitBits], A.tw_lo[m & ((1 << kTwSplitBits) - 1)]);
-            v = cp_rot(v, w);
+            const cp v = cp_rot(lds[ka], w);
             out[((int64_t)(ka >> 3) * A.LB + n_b) * kPassBCols + (ka & 7)] = v;
+            w = c_mul(w, w_step);
         }
         __syncthreads();
     }
@@ -96,22 +131,38 @@ __global__ __launch_bounds__(kNT) void rsf_fft_pass_b_k(PassBArgs B) {
     const int tid = threadIdx.x;
     const float4* in = B.spill + (int64_t)t * B.spill_tmpl_stride + (int64_t)c * B.LB * kPassBCols;
     const int tot = B.LB * kPassBCols;
-    for (int e = tid; e < tot; e += kNT) lds[e] = in[e];
+    // loads issued in batches of kEPT/2 before their LDS stores
+#pragma unroll
+    for (int q0 = 0; q0 < kEPT; q0 += kEPT / 2) {
+        float4 v[kEPT / 2];
+#pragma unroll
+        for (int q = 0; q < kEPT / 2; ++q) {
+            const int e = tid + (q0 + q) * kNT;
+            v[q] = in[e < tot ? e : 0];
+        }
+#pragma unroll
+        for (int q = 0; q < kEPT / 2; ++q) {
+            const int e = tid + (q0 + q) * kNT;
+            if (e < tot) lds[e] = v[q];
+        }
+    }
     __syncthreads();
     lds_fft<kNT, kEPT, kPassBCols>(lds, B.st, B.tw);
     const float cA = B.coef[0], cB = B.coef[1], cC = B.coef[2];
     float* out = B.twoF + (B.out_row0 + t) * B.n_out;
+    // 32-bit bin arithmetic (n_fft < 2^31)
+    const int nf = (int)B.n_fft, s_lo = (int)B.s_lo, n_out = (int)B.n_out;
     for (int e = tid; e < tot; e += kNT) {
         const int kb = e >> 3;
         const int ka = c * kPassBCols + (e & 7);
         if (ka < B.LA) {
-            const int64_t k = (int64_t)ka + (int64_t)B.LA * kb;
-            const int64_t s = (2 * k < B.n_fft) ? k : k - B.n_fft;
-            const int64_t o = s - B.s_lo;
-            if (o >= 0 && o < B.n_out) {
-                const cp v = lds[e];
-                out[o] = cA * (v.x * v.x + v.y * v.y) + cB * (v.z * v.z + v.w * v.w) +
-                         cC * (v.x * v.z + v.y * v.w);
+            const int k = ka + B.LA * kb;
+            const int s = (2 * k < nf) ? k : k - nf;
+            const int o = s - s_lo;
+            if (o >= 0 && o < n_out) {
+                const cp u = lds[e];
+                out[o] = cA * (u.x * u.x + u.y * u.y) + cB * (u.z * u.z + u.w * u.w) +
+                         cC * (u.x * u.z + u.y * u.w);
             }
         }
     }

@@ -16,4 +16,8 @@ hipError_t launch_fft_pass_b(const PassBArgs& b, hipStream_t s);
 hipError_t fft_set_lds_limits(size_t bytes);
 int fft_pass_max_elems();
 
+int point_blocks(int64_t P);
+hipError_t launch_point(const PointArgs& a, bool grad, hipStream_t s);
+hipError_t launch_point_reduce(const PointReduceArgs& r, hipStream_t s);
+
 }  // namespace rsf

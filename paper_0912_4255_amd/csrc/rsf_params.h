@@ -134,4 +134,38 @@ struct PassBArgs {
     int n_tmpl;
 };
 
+// Continuous-parameter 2F and its gradient (one detector set, a batch of
+// candidates theta = (f, fdot, alpha, delta)).
+constexpr int kPointSums = 32;      // FP64 partial sums per (block, candidate)
+constexpr int kPointTiles = 8;      // 1024-sample tiles per block
+
+struct PointArgs {
+    int64_t n;
+    double dt, t_start, f_het;
+    EphDev eph;
+    int n_det;
+    DetDev det[kMaxDet];
+    InterpDev ip;
+    const float2* x[kMaxDet];
+    const int64_t* gaps[kMaxDet];
+    int n_gaps[kMaxDet];
+    const double* theta;      // [n_cand][4]
+    int n_cand;
+    int64_t P;                // 64-sample rows: ceil(n / 64)
+    int n_blocks;             // blocks per candidate
+    double* partials;         // [n_cand][n_blocks][kPointSums]
+    unsigned int* flags;
+};
+
+struct PointReduceArgs {
+    const double* partials;
+    int n_blocks;
+    int n_cand;
+    int grad;
+    const float* g_twoF;      // [n_cand] (grad)
+    float* twoF;              // [n_cand] (may be null)
+    double* g_theta;          // [n_cand][4] (grad)
+    unsigned int* flags;
+};
+
 }  // namespace rsf

@@ -1,0 +1,448 @@
+// 2F at continuous parameters and its gradient (project addition on top of
+// paper Sec. III.A.2): for every candidate theta = (f, fdot, alpha, delta)
+// the resampled series of the candidate's own sky is recomputed on the fly
+// (never stored) and reduced to
+//   F_a = sum_k y^a_k exp(-2 pi i (f - f_het) t_b^k),   F_b likewise,
+//   A', B', C'  (masked antenna sums),
+// plus, for the gradient, the derivatives of all five with respect to
+// theta, following every dependence of the resampling chain:
+//   * f:     d/df exp(-2 pi i (f - f_het) t_b) = -2 pi i t_b (...);
+//   * fdot:  Phi_s = pi fdot (t_b^2 - t_m^2)  (eq. eq4pt1 with T = t_b - t_m);
+//   * sky:   t_m(tau) = n0 . r_d(tau) (eq. eq4pt2); the inversion of eq. eq21
+//            gives dT/dtheta = -(dt_m/dtheta)/(1 + dt_m/dt); the
+//            interpolated series changes through the kernel derivative
+//            w'(u - p) dT/dtheta / dt and through the heterodyne correction
+//            dz_p/dtheta = -2 pi i f_het (dt_m/dtheta)(t_p) z_p (eq. absorb);
+//            the beam patterns change through p, q(alpha, delta) and T; the
+//            spindown phase through t_m.
+// Each block accumulates FP64 partial sums over 8 tiles of 1024 samples;
+// rsf_point_reduce_k sums the blocks of a candidate in a fixed order and
+// forms 2F (eq. eq6) and the vector-Jacobian product g * d2F/dtheta.
+#include <climits>
+
+#include "rsf_device.h"
+#include "rsf_launch.h"
+
+namespace rsf {
+
+namespace {
+constexpr int kTileB = 64;
+constexpr int kTileA = 16;
+constexpr int kThreads = 256;
+constexpr int kWinMax = kTileB + kMaxTaps + 8;
+constexpr float kPiF = 3.14159265358979323846f;
+
+// partial-sum slots
+enum {
+    S_FA = 0, S_FB = 2, S_A = 4, S_B = 5, S_C = 6,
+    S_DFA = 7,   // 4 parameters x (re, im)
+    S_DFB = 15,
+    S_DA = 23,   // (alpha, delta)
+    S_DB = 25,
+    S_DC = 27,
+    S_USED = 29
+};
+
+struct Orbit {
+    double3 r;     // r_d / c (s)
+    double3 v;     // v_d / c
+    double sth, cth;
+};
+
+__device__ __forceinline__ Orbit orbit_at(double tau, const EphDev& e, const DetDev& d) {
+    const double lam = e.lambda0 + 2.0 * kPi * frac_rev(tau * e.inv_p_orb);
+    const double th = e.theta0 + 2.0 * kPi * frac_rev(tau * e.inv_p_sid) + d.lon;
+    double sl, cl, st, ct;
+    sincos(lam, &sl, &cl);
+    sincos(th, &st, &ct);
+    const double wo = 2.0 * kPi * e.inv_p_orb, ws = 2.0 * kPi * e.inv_p_sid;
+    Orbit o;
+    o.r = make_double3(e.au_c * cl + e.re_c * d.clat * ct, e.au_c * e.ceps * sl + e.re_c * d.clat * st,
+                       e.au_c * e.seps * sl + e.re_c * d.slat);
+    o.v = make_double3(-e.au_c * wo * sl - e.re_c * ws * d.clat * st, e.au_c * wo * e.ceps * cl + e.re_c * ws * d.clat * ct,
+                       e.au_c * wo * e.seps * cl);
+    o.sth = st;
+    o.cth = ct;
+    return o;
+}
+
+__device__ __forceinline__ double dot3(double3 a, double3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+
+__device__ __forceinline__ bool in_gap(const int64_t* __restrict__ gaps, int n_gaps, int64_t j) {
+    int lo = 0, hi = n_gaps - 1, best = -1;
+    while (lo <= hi) {
+        const int mid = (lo + hi) >> 1;
+        if (gaps[2 * mid] <= j) {
+            best = mid;
+            lo = mid + 1;
+        } else {
+            hi = mid - 1;
+        }
+    }
+    return best >= 0 && j < gaps[2 * best + 1];
+}
+
+// sinc(x) = sin(pi x)/(pi x) and its derivative from accurate sin(pi x), cos(pi x);
+// a series near 0 avoids the cancellation in (cos(pi x) - sinc(x)) / x.
+__device__ __forceinline__ void sinc_d(float x, float sx, float cx, float& s, float& ds) {
+    if (fabsf(x) < 0.05f) {
+        const float p2 = kPiF * kPiF * x * x;
+        s = 1.f - p2 / 6.f + p2 * p2 / 120.f - p2 * p2 * p2 / 5040.f;
+        ds = -(kPiF * kPiF * x / 3.f) * (1.f - p2 / 10.f + p2 * p2 / 280.f);
+    } else {
+        s = sx / (kPiF * x);
+        ds = (cx - s) / x;
+    }
+}
+
+// Interpolation weight w(x) and w'(x) (Lanczos-W or the periodic Dirichlet
+// kernel of length n written as sinc(x) g(pi x / n)); sx, cx = sin/cos(pi x).
+template <bool GRAD>
+__device__ __forceinline__ void kernel_w(const InterpDev& ip, float x, float sx, float cx, float& w, float& dw) {
+    const int W = ip.taps;
+    float s0, ds0;
+    sinc_d(x, sx, cx, s0, ds0);
+    if (ip.kernel == 0) {
+        if (fabsf(x) >= 0.5f * (float)W) {
+            w = 0.f;
+            dw = 0.f;
+            return;
+        }
+        const float v = 2.f * x / (float)W;
+        float sv, cv, s1, ds1;
+        sincospif(v, &sv, &cv);
+        sinc_d(v, sv, cv, s1, ds1);
+        w = s0 * s1;
+        if (GRAD) dw = ds0 * s1 + s0 * ds1 * (2.f / (float)W);
+    } else {
+        const float y = kPiF * x / (float)ip.n;
+        float g, dg;
+        if (fabsf(y) < 0.01f) {
+            const float y2 = y * y;
+            if (ip.n_odd) {  // y / sin(y)
+                g = 1.f + y2 / 6.f + 7.f * y2 * y2 / 360.f;
+                dg = y / 3.f + 7.f * y * y2 / 90.f;
+            } else {         // y / tan(y)
+                g = 1.f - y2 / 3.f - y2 * y2 / 45.f;
+                dg = -2.f * y / 3.f - 4.f * y * y2 / 45.f;
+            }
+        } else {
+            float sy, cy;
+            sincosf(y, &sy, &cy);
+            if (ip.n_odd) {
+                g = y / sy;
+                dg = 1.f / sy - y * cy / (sy * sy);
+            } else {
+                g = y * cy / sy;
+                dg = cy / sy - y / (sy * sy);
+            }
+        }
+        w = s0 * g;
+        if (GRAD) dw = ds0 * g + s0 * dg * (kPiF / (float)ip.n);
+    }
+}
+
+}  // namespace
+
+template <bool GRAD>
+__global__ __launch_bounds__(kThreads) void rsf_point_k(PointArgs A) {
+    __shared__ float4 win[4][kWinMax];  // z (re, im), 2 pi f_het dt_m/dalpha, 2 pi f_het dt_m/ddelta
+    __shared__ double red[4][kPointSums];
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int cand = blockIdx.y;
+    const double f = A.theta[4 * cand + 0], fd = A.theta[4 * cand + 1];
+    const double al = A.theta[4 * cand + 2], de = A.theta[4 * cand + 3];
+    double sa, ca, sd, cd;
+    sincos(al, &sa, &ca);
+    sincos(de, &sd, &cd);
+    const double3 n0 = make_double3(cd * ca, cd * sa, sd);
+    const double3 n0a = make_double3(-cd * sa, cd * ca, 0.0);
+    const double3 n0d = make_double3(-sd * ca, -sd * sa, cd);
+    const double3 pp = make_double3(-sa, ca, 0.0);
+    const double3 qq = make_double3(-sd * ca, -sd * sa, cd);
+    const double3 pa = make_double3(-ca, -sa, 0.0);          // dp/dalpha (dp/ddelta = 0)
+    const double3 qa = make_double3(sd * sa, -sd * ca, 0.0);  // dq/dalpha
+    const double3 qd = make_double3(-cd * ca, -cd * sa, -sd); // dq/ddelta
+    const double w_sid = 2.0 * kPi * A.eph.inv_p_sid;
+    const int W = A.ip.taps;
+    const int hw = W / 2;
+
+    double acc[S_USED];
+#pragma unroll
+    for (int i = 0; i < S_USED; ++i) acc[i] = 0.0;
+    bool overflow = false;
+
+    for (int tile = 0; tile < kPointTiles; ++tile) {
+        const int64_t a0 = ((int64_t)blockIdx.x * kPointTiles + tile) * kTileA;
+        for (int r = 0; r < kTileA / 4; ++r) {
+            const int64_t row = a0 + wave + 4 * r;
+            const int64_t k = row * kTileB + lane;
+            const bool valid = (row < A.P) && (k < A.n);
+            const double tb = (double)k * A.dt;
+            for (int X = 0; X < A.n_det; ++X) {
+                const DetDev& D = A.det[X];
+                int j = 0;
+                float frac = 0.f;
+                double T = tb, tm = 0.0, dTa = 0.0, dTd = 0.0;
+                double av = 0.0, bv = 0.0, daa = 0.0, dad = 0.0, dba = 0.0, dbd = 0.0;
+                bool mk = false;
+                if (valid) {
+                    Orbit o;
+                    for (int it = 0; it < 5; ++it) {
+                        o = orbit_at(A.t_start + T, A.eph, D);
+                        T = tb - dot3(n0, o.r);
+                    }
+                    tm = tb - T;
+                    const double u = T / A.dt;
+                    const double fl = floor(u);
+                    j = (int)fl;
+                    frac = (float)(u - fl);
+                    const int64_t jn = (int64_t)floor(u + 0.5);
+                    mk = (jn >= 0) && (jn < A.n) && !in_gap(A.gaps[X], A.n_gaps[X], jn);
+                    // arms at the local sidereal angle, and their rate of change
+                    const double3 eE = make_double3(-o.sth, o.cth, 0.0);
+                    const double3 eN = make_double3(-D.slat * o.cth, -D.slat * o.sth, D.clat);
+                    const double3 eEt = make_double3(-o.cth, -o.sth, 0.0);
+                    const double3 eNt = make_double3(D.slat * o.sth, -D.slat * o.cth, 0.0);
+                    const double3 uu = make_double3(D.cgu * eE.x + D.sgu * eN.x, D.cgu * eE.y + D.sgu * eN.y,
+                                                    D.cgu * eE.z + D.sgu * eN.z);
+                    const double3 vv = make_double3(D.cgv * eE.x + D.sgv * eN.x, D.cgv * eE.y + D.sgv * eN.y,
+                                                    D.cgv * eE.z + D.sgv * eN.z);
+                    const double up = dot3(uu, pp), uq = dot3(uu, qq), vp = dot3(vv, pp), vq = dot3(vv, qq);
+                    av = 0.5 * (up * up - uq * uq - vp * vp + vq * vq);
+                    bv = up * uq - vp * vq;
+                    if (GRAD) {
+                        const double tmdot = dot3(n0, o.v);
+                        dTa = -dot3(n0a, o.r) / (1.0 + tmdot);
+                        dTd = -dot3(n0d, o.r) / (1.0 + tmdot);
+                        const double3 ut = make_double3(D.cgu * eEt.x + D.sgu * eNt.x, D.cgu * eEt.y + D.sgu * eNt.y, 0.0);
+                        const double3 vt = make_double3(D.cgv * eEt.x + D.sgv * eNt.x, D.cgv * eEt.y + D.sgv * eNt.y, 0.0);
+                        // d/dT through the sidereal rotation (per second)
+                        const double upt = dot3(ut, pp) * w_sid, uqt = dot3(ut, qq) * w_sid;
+                        const double vpt = dot3(vt, pp) * w_sid, vqt = dot3(vt, qq) * w_sid;
+                        const double adT = up * upt - uq * uqt - vp * vpt + vq * vqt;
+                        const double bdT = upt * uq + up * uqt - vpt * vq - vp * vqt;
+                        // d/dalpha, d/ddelta at fixed T through p and q
+                        const double upa = dot3(uu, pa), uqa = dot3(uu, qa), vpa = dot3(vv, pa), vqa = dot3(vv, qa);
+                        const double uqd = dot3(uu, qd), vqd = dot3(vv, qd);
+                        daa = up * upa - uq * uqa - vp * vpa + vq * vqa + adT * dTa;
+                        dba = upa * uq + up * uqa - vpa * vq - vp * vqa + bdT * dTa;
+                        dad = -uq * uqd + vq * vqd + adT * dTd;
+                        dbd = up * uqd - vp * vqd + bdT * dTd;
+                    }
+                }
+                // detector-grid window of this run, heterodyne-corrected
+                int jmin = valid ? j : INT_MAX;
+                int jmax = valid ? j : INT_MIN;
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) {
+                    jmin = min(jmin, __shfl_xor(jmin, off));
+                    jmax = max(jmax, __shfl_xor(jmax, off));
+                }
+                const bool any = jmin != INT_MAX;
+                const int w0 = any ? jmin - hw + 1 : 0;
+                const int wlen = any ? (jmax - jmin + W) : 0;
+                const bool ok = wlen <= kWinMax;
+                if (any && ok) {
+                    for (int p = lane; p < wlen; p += 64) {
+                        const int64_t jj = (int64_t)w0 + p;
+                        float4 e = make_float4(0.f, 0.f, 0.f, 0.f);
+                        if (jj >= 0 && jj < A.n) {
+                            const float2 xv = A.x[X][jj];
+                            const Orbit o = orbit_at(A.t_start + (double)jj * A.dt, A.eph, D);
+                            const double tmj = dot3(n0, o.r);
+                            const double cyc = A.f_het * tmj;
+                            const float ph = (float)(cyc - rint(cyc));
+                            float s, c;
+                            sincospif(2.f * ph, &s, &c);
+                            e.x = xv.x * c + xv.y * s;
+                            e.y = xv.y * c - xv.x * s;
+                            if (GRAD) {
+                                e.z = (float)(2.0 * kPi * A.f_het * dot3(n0a, o.r));
+                                e.w = (float)(2.0 * kPi * A.f_het * dot3(n0d, o.r));
+                            }
+                        }
+                        win[wave][p] = e;
+                    }
+                }
+                if (any && !ok) overflow = true;
+                __syncthreads();
+                if (valid && ok) {
+                    // interpolation (and derivative pieces)
+                    float sf, cf;
+                    sincospif(frac, &sf, &cf);
+                    float2 zt = make_float2(0.f, 0.f), s1 = zt, sza = zt, szd = zt;
+                    const int base = j - hw + 1 - w0;
+                    for (int i = 1; i <= W; ++i) {
+                        const float x = frac + (float)(hw - i);
+                        const bool odd = (hw - i) & 1;
+                        float w, dw = 0.f;
+                        if (x == 0.f) {
+                            w = 1.f;
+                            dw = 0.f;
+                        } else {
+                            kernel_w<GRAD>(A.ip, x, odd ? -sf : sf, odd ? -cf : cf, w, dw);
+                        }
+                        const float4 zz = win[wave][base + i - 1];
+                        zt.x += w * zz.x;
+                        zt.y += w * zz.y;
+                        if (GRAD) {
+                            s1.x += dw * zz.x;
+                            s1.y += dw * zz.y;
+                            sza.x += w * zz.z * zz.x;
+                            sza.y += w * zz.z * zz.y;
+                            szd.x += w * zz.w * zz.x;
+                            szd.y += w * zz.w * zz.y;
+                        }
+                    }
+                    // total phase: spindown Phi_s and the Fourier kernel at f
+                    const double cyc = fd * 0.5 * (tb * tb - tm * tm) + (f - A.f_het) * tb;
+                    const float ph = (float)(cyc - rint(cyc));
+                    float s, c;
+                    sincospif(2.f * ph, &s, &c);
+                    // ze = z~ exp(-2 pi i cyc)
+                    const float zer = zt.x * c + zt.y * s, zei = zt.y * c - zt.x * s;
+                    const double w = D.w;
+                    acc[S_FA + 0] += w * av * zer;
+                    acc[S_FA + 1] += w * av * zei;
+                    acc[S_FB + 0] += w * bv * zer;
+                    acc[S_FB + 1] += w * bv * zei;
+                    if (mk) {
+                        acc[S_A] += w * av * av;
+                        acc[S_B] += w * bv * bv;
+                        acc[S_C] += w * av * bv;
+                    }
+                    if (GRAD) {
+                        // d/df: -2 pi i t_b ; d/dfdot: -i pi (t_b^2 - t_m^2)
+                        const double cf_ = 2.0 * kPi * tb;
+                        const double cfd = kPi * (tb * tb - tm * tm);
+                        // (-i c) (x + i y) = c y - i c x
+                        acc[S_DFA + 0] += w * av * cf_ * zei;
+                        acc[S_DFA + 1] -= w * av * cf_ * zer;
+                        acc[S_DFB + 0] += w * bv * cf_ * zei;
+                        acc[S_DFB + 1] -= w * bv * cf_ * zer;
+                        acc[S_DFA + 2] += w * av * cfd * zei;
+                        acc[S_DFA + 3] -= w * av * cfd * zer;
+                        acc[S_DFB + 2] += w * bv * cfd * zei;
+                        acc[S_DFB + 3] -= w * bv * cfd * zer;
+                        // sky: dz~/dth = s1 dT/dth / dt - i sz_th ; dPhi/dth = 2 pi fdot t_m dT/dth
+                        const float dTa_u = (float)(dTa / A.dt), dTd_u = (float)(dTd / A.dt);
+                        const float dpa = (float)(2.0 * kPi * fd * tm * dTa);
+                        const float dpd = (float)(2.0 * kPi * fd * tm * dTd);
+                        // dz~_alpha = (s1.x dTa_u + sza.y, s1.y dTa_u - sza.x)
+                        const float dza_r = s1.x * dTa_u + sza.y, dza_i = s1.y * dTa_u - sza.x;
+                        const float dzd_r = s1.x * dTd_u + szd.y, dzd_i = s1.y * dTd_u - szd.x;
+                        // rotate by exp(-2 pi i cyc)
+                        const float ea_r = dza_r * c + dza_i * s, ea_i = dza_i * c - dza_r * s;
+                        const float ed_r = dzd_r * c + dzd_i * s, ed_i = dzd_i * c - dzd_r * s;
+                        // d(a ze)/dth = da ze + a (dz~ e) + a ze (-i dPhi)
+                        acc[S_DFA + 4] += w * (daa * zer + av * ea_r + av * dpa * zei);
+                        acc[S_DFA + 5] += w * (daa * zei + av * ea_i - av * dpa * zer);
+                        acc[S_DFA + 6] += w * (dad * zer + av * ed_r + av * dpd * zei);
+                        acc[S_DFA + 7] += w * (dad * zei + av * ed_i - av * dpd * zer);
+                        acc[S_DFB + 4] += w * (dba * zer + bv * ea_r + bv * dpa * zei);
+                        acc[S_DFB + 5] += w * (dba * zei + bv * ea_i - bv * dpa * zer);
+                        acc[S_DFB + 6] += w * (dbd * zer + bv * ed_r + bv * dpd * zei);
+                        acc[S_DFB + 7] += w * (dbd * zei + bv * ed_i - bv * dpd * zer);
+                        if (mk) {
+                            acc[S_DA + 0] += w * 2.0 * av * daa;
+                            acc[S_DA + 1] += w * 2.0 * av * dad;
+                            acc[S_DB + 0] += w * 2.0 * bv * dba;
+                            acc[S_DB + 1] += w * 2.0 * bv * dbd;
+                            acc[S_DC + 0] += w * (daa * bv + av * dba);
+                            acc[S_DC + 1] += w * (dad * bv + av * dbd);
+                        }
+                    }
+                } else if (valid && !ok) {
+                    acc[S_FA] = __longlong_as_double(0x7ff8000000000000LL);
+                }
+                __syncthreads();
+            }
+        }
+    }
+    if (overflow && lane == 0) atomicOr(A.flags, 2u);
+
+    // block reduction in a fixed order
+    const int nsum = GRAD ? S_USED : S_DFA;
+    for (int i = 0; i < nsum; ++i) {
+        double v = acc[i];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        if (lane == 0) red[wave][i] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < nsum) {
+        const int i = threadIdx.x;
+        const double t = ((red[0][i] + red[1][i]) + red[2][i]) + red[3][i];
+        A.partials[((int64_t)cand * A.n_blocks + blockIdx.x) * kPointSums + i] = t;
+    }
+}
+
+// One workgroup per candidate: fixed-order sum of the block partials, then
+// 2F = 2Q/D with Q = B|Fa|^2 + A|Fb|^2 - 2C Re(Fa Fb^*), D = AB - C^2, and
+// d2F = 2 (dQ D - Q dD) / D^2.
+__global__ __launch_bounds__(256) void rsf_point_reduce_k(PointReduceArgs R) {
+    __shared__ double red[256];
+    __shared__ double tot[kPointSums];
+    const int cand = blockIdx.x;
+    const int nsum = R.grad ? S_USED : S_DFA;
+    const double* p = R.partials + (int64_t)cand * R.n_blocks * kPointSums;
+    for (int i = 0; i < nsum; ++i) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < R.n_blocks; b += 256) s += p[(int64_t)b * kPointSums + i];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) tot[i] = red[0];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const double Far = tot[S_FA], Fai = tot[S_FA + 1], Fbr = tot[S_FB], Fbi = tot[S_FB + 1];
+    const double Aa = tot[S_A], Bb = tot[S_B], Cc = tot[S_C];
+    const double D = Aa * Bb - Cc * Cc;
+    const double fa2 = Far * Far + Fai * Fai, fb2 = Fbr * Fbr + Fbi * Fbi;
+    const double reab = Far * Fbr + Fai * Fbi;
+    const double Q = Bb * fa2 + Aa * fb2 - 2.0 * Cc * reab;
+    const bool degenerate = !(D > 0.0);
+    const double F2 = degenerate ? __longlong_as_double(0x7ff8000000000000LL) : 2.0 * Q / D;
+    if (degenerate) atomicOr(R.flags, 1u);
+    if (R.twoF) R.twoF[cand] = (float)F2;
+    if (!R.grad) return;
+    const double g = (double)R.g_twoF[cand];
+    for (int i = 0; i < 4; ++i) {
+        const double dar = tot[S_DFA + 2 * i], dai = tot[S_DFA + 2 * i + 1];
+        const double dbr = tot[S_DFB + 2 * i], dbi = tot[S_DFB + 2 * i + 1];
+        const double dA = (i >= 2) ? tot[S_DA + i - 2] : 0.0;
+        const double dB = (i >= 2) ? tot[S_DB + i - 2] : 0.0;
+        const double dC = (i >= 2) ? tot[S_DC + i - 2] : 0.0;
+        const double dQ = dB * fa2 + 2.0 * Bb * (Far * dar + Fai * dai) + dA * fb2 +
+                          2.0 * Aa * (Fbr * dbr + Fbi * dbi) - 2.0 * dC * reab -
+                          2.0 * Cc * (dar * Fbr + dai * Fbi + Far * dbr + Fai * dbi);
+        const double dD = dA * Bb + Aa * dB - 2.0 * Cc * dC;
+        const double d2F = degenerate ? F2 : 2.0 * (dQ * D - Q * dD) / (D * D);
+        R.g_theta[4 * cand + i] = g * d2F;
+    }
+}
+
+int point_blocks(int64_t P) { return (int)((P + kTileA * kPointTiles - 1) / (kTileA * kPointTiles)); }
+
+hipError_t launch_point(const PointArgs& a, bool grad, hipStream_t s) {
+    const dim3 grid((unsigned)a.n_blocks, (unsigned)a.n_cand);
+    if (grad)
+        hipLaunchKernelGGL(rsf_point_k<true>, grid, dim3(kThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL(rsf_point_k<false>, grid, dim3(kThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_point_reduce(const PointReduceArgs& r, hipStream_t s) {
+    hipLaunchKernelGGL(rsf_point_reduce_k, dim3((unsigned)r.n_cand), dim3(256), 0, s, r);
+    return hipGetLastError();
+}
+
+}  // namespace rsf
