@@ -66,7 +66,7 @@ enum { RSF_KERNEL_LANCZOS = 0, RSF_KERNEL_DIRICHLET = 1 };
 enum { RSF_NFFT_TWICE = 0, RSF_NFFT_SMOOTH7 = 1 };
 enum { RSF_STORE_F32 = 0, RSF_STORE_F16 = 1 };
 enum { RSF_MODE_PLAIN = 0, RSF_MODE_BATCHED = 1 };
-enum { RSF_ENTRY_RESAMPLE = 0, RSF_ENTRY_FSTAT = 1, RSF_ENTRY_POINT = 2, RSF_ENTRY_BACKWARD = 3 };
+enum { RSF_ENTRY_RESAMPLE = 0, RSF_ENTRY_FSTAT = 1, RSF_ENTRY_POINT = 2, RSF_ENTRY_BACKWARD = 3, RSF_ENTRY_TOPK = 4 };
 enum { RSF_FLAG_DEGENERATE = 1, RSF_FLAG_WINDOW = 2 };
 
 /* Interferometer site: latitude, longitude (rad, east positive), azimuth of
@@ -164,15 +164,18 @@ int rsf_resample(const rsf_plan* plan, const rsf_segment* seg, const double* sky
  * fdot: device float64[n_fdot] (Hz/s).  twoF: device float32
  * [n_sky * n_fdot][n_out], row = sky * n_fdot + fdot, ascending frequency.
  * mode RSF_MODE_PLAIN launches the two FFT passes once per template;
- * RSF_MODE_BATCHED shares the resampled inputs between spindowns and groups
- * templates into fewer, larger launches.  Both give identical results. */
+ * RSF_MODE_BATCHED resamples several sky positions per launch, shares each
+ * resampled series between up to 4 spindowns in the first FFT pass and runs
+ * up to 64 templates per launch.  Both give identical results. */
 int rsf_fstat(const rsf_plan* plan, const rsf_segment* seg, const double* sky, int64_t n_sky,
               const double* fdot, int64_t n_fdot, int mode, float* twoF,
               void* ws, size_t ws_bytes, void* stream);
 
 /* As rsf_fstat (batched) but returning only the k largest 2F values over all
- * templates and bins, descending, ties broken by lower (sky, fdot, bin).
- * topk: device rsf_topk_entry[k], 1 <= k <= 64. */
+ * templates and bins of the band, descending, ties broken by the lower
+ * (sky, fdot, bin); NaN values never enter; missing entries (fewer than k
+ * finite values) have twoF = -inf and indices -1.  Workspace: entry
+ * RSF_ENTRY_TOPK.  topk: device rsf_topk_entry[k], 1 <= k <= 64. */
 int rsf_fstat_topk(const rsf_plan* plan, const rsf_segment* seg, const double* sky, int64_t n_sky,
                    const double* fdot, int64_t n_fdot, int k, rsf_topk_entry* topk,
                    void* ws, size_t ws_bytes, void* stream);

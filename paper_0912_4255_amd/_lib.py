@@ -12,7 +12,7 @@ LIB_PATH = os.path.join(HERE, "librsfstat.so")
 RSF_MAX_DET = 4
 RSF_OK, RSF_EINVAL, RSF_EUNSUPPORTED, RSF_EWORKSPACE, RSF_EHIP = 0, -1, -2, -3, -4
 RSF_MODE_PLAIN, RSF_MODE_BATCHED = 0, 1
-RSF_ENTRY_RESAMPLE, RSF_ENTRY_FSTAT, RSF_ENTRY_POINT, RSF_ENTRY_BACKWARD = 0, 1, 2, 3
+RSF_ENTRY_RESAMPLE, RSF_ENTRY_FSTAT, RSF_ENTRY_POINT, RSF_ENTRY_BACKWARD, RSF_ENTRY_TOPK = 0, 1, 2, 3, 4
 RSF_FLAG_DEGENERATE, RSF_FLAG_WINDOW = 1, 2
 
 EXPORTS = [

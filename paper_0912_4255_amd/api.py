@@ -144,10 +144,25 @@ class Plan:
         if out.numel() < n_sky * n_fdot * self.n_out:
             raise ValueError("output too small")
         if ws is None:
-            ws = self.workspace(L.RSF_ENTRY_FSTAT, 1, n_fdot, mode, device=dev)
+            ws = self.workspace(L.RSF_ENTRY_FSTAT, n_sky, n_fdot, mode, device=dev)
         L.check(self.lib.rsf_fstat(self._p, C.byref(seg), _ptr(sky), n_sky, _ptr(fdot), n_fdot, mode,
                                    _ptr(out), _ptr(ws), ws.numel(), _stream()))
         return out
+
+    def topk(self, xs, gaps, sky, fdot, k=10, ws=None):
+        """rsf_fstat_topk: the k best (2F, sky, fdot, bin) over all templates
+        and bins; returns (values float32 [k], indices int32 [k, 3])."""
+        _need_cuda(sky, torch.float64, "sky")
+        _need_cuda(fdot, torch.float64, "fdot")
+        n_sky, n_fdot = sky.shape[0], fdot.shape[0]
+        seg, keep = self.segment(xs, gaps)
+        dev = xs[0].device
+        out = torch.empty((k, 4), dtype=torch.int32, device=dev)
+        if ws is None:
+            ws = self.workspace(L.RSF_ENTRY_TOPK, n_sky, n_fdot, device=dev)
+        L.check(self.lib.rsf_fstat_topk(self._p, C.byref(seg), _ptr(sky), n_sky, _ptr(fdot), n_fdot, k,
+                                        _ptr(out), _ptr(ws), ws.numel(), _stream()))
+        return out[:, 0].view(torch.float32), out[:, 1:]
 
     def point(self, xs, gaps, theta, out=None, ws=None):
         """rsf_fstat_point: 2F [n] at continuous theta [n, 4] = (f, fdot, alpha, delta)."""

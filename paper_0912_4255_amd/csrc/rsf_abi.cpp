@@ -162,23 +162,36 @@ struct rsf_plan {
 namespace {
 
 struct WsLayout {
-    size_t flags, rs_main[RSF_MAX_DET], rs_tm[RSF_MAX_DET], partials, coef, abc_w, spill, total;
+    size_t flags, rs_main[RSF_MAX_DET], rs_tm[RSF_MAX_DET], partials, coef, abc_w, spill, map, cand, run, total;
     int n_blocks;
-    int64_t G;
+    int64_t G;        // templates per FFT launch
+    int64_t S;        // sky positions per resampling chunk
+    int64_t rs_stride;
 };
 
-int64_t batch_templates(const rsf_plan* p, int64_t n_fdot, int mode) {
+// Templates per FFT launch: 1 (plain) or 16..64 (batched, more for short
+// segments so that every launch carries a similar amount of work).
+int64_t batch_templates(const rsf_plan* p, int mode) {
     if (mode == RSF_MODE_PLAIN) return 1;
-    (void)p;
-    return std::max<int64_t>(1, std::min<int64_t>(n_fdot, 16));
+    const int64_t scale = std::max<int64_t>(1, 3456000 / std::max<int64_t>(1, p->n));
+    return std::min<int64_t>(64, 16 * scale);
 }
 
-WsLayout fstat_layout(const rsf_plan* p, int64_t n_fdot, int mode) {
+int64_t batch_skies(int64_t n_sky, int64_t n_fdot, int64_t G, int mode) {
+    if (mode == RSF_MODE_PLAIN) return 1;
+    const int64_t per = std::max<int64_t>(1, (4 * G) / std::max<int64_t>(1, n_fdot));
+    return std::max<int64_t>(1, std::min<int64_t>({n_sky, per, 64}));
+}
+
+WsLayout fstat_layout(const rsf_plan* p, int64_t n_sky, int64_t n_fdot, int mode, bool topk) {
     WsLayout L{};
     size_t off = 0;
     L.flags = off;
     off = align_up(off + 64);
-    const size_t elems = (size_t)p->LB * (size_t)p->P;
+    L.G = batch_templates(p, mode);
+    L.S = batch_skies(n_sky, n_fdot, L.G, mode);
+    L.rs_stride = (int64_t)p->LB * p->P;
+    const size_t elems = (size_t)L.rs_stride * (size_t)L.S;
     for (int X = 0; X < p->d.n_det; ++X) {
         L.rs_main[X] = off;
         off = align_up(off + elems * sizeof(float4));
@@ -189,14 +202,21 @@ WsLayout fstat_layout(const rsf_plan* p, int64_t n_fdot, int mode) {
     }
     L.n_blocks = resample_blocks(p->LB, p->P);
     L.partials = off;
-    off = align_up(off + (size_t)p->d.n_det * L.n_blocks * 3 * sizeof(double));
+    off = align_up(off + (size_t)p->d.n_det * L.S * L.n_blocks * 3 * sizeof(double));
     L.coef = off;
-    off = align_up(off + 4 * sizeof(float));
+    off = align_up(off + (size_t)L.S * 4 * sizeof(float));
     L.abc_w = off;
-    off = align_up(off + 3 * sizeof(double));
-    L.G = batch_templates(p, n_fdot, mode);
+    off = align_up(off + (size_t)L.S * 3 * sizeof(double));
     L.spill = off;
     off = align_up(off + (size_t)L.G * p->n_groups * p->LB * kPassBCols * sizeof(float4));
+    if (topk) {
+        L.map = off;
+        off = align_up(off + (size_t)L.G * p->n_out * sizeof(float));
+        L.cand = off;
+        off = align_up(off + (size_t)topk_scan_blocks(L.G * p->n_out) * kTopkMax * sizeof(TopkItem));
+        L.run = off;
+        off = align_up(off + 2 * kTopkMax * sizeof(TopkItem));
+    }
     L.total = off;
     return L;
 }
@@ -463,7 +483,10 @@ int rsf_workspace_size(const rsf_plan* p, int entry, int64_t n_sky, int64_t n_fd
             return RSF_OK;
         case RSF_ENTRY_FSTAT:
             if (mode != RSF_MODE_PLAIN && mode != RSF_MODE_BATCHED) return fail(RSF_EINVAL, "unknown mode");
-            *bytes = fstat_layout(p, n_fdot, mode).total;
+            *bytes = fstat_layout(p, n_sky, n_fdot, mode, false).total;
+            return RSF_OK;
+        case RSF_ENTRY_TOPK:
+            *bytes = fstat_layout(p, n_sky, n_fdot, RSF_MODE_BATCHED, true).total;
             return RSF_OK;
         case RSF_ENTRY_POINT:
         case RSF_ENTRY_BACKWARD:
@@ -486,7 +509,7 @@ int rsf_resample(const rsf_plan* p, const rsf_segment* seg, const double* sky, i
     hipStream_t s = (hipStream_t)stream;
     char* w = (char*)ws;
     unsigned int* flags = (unsigned int*)(w + L.flags);
-    RSF_HIP(hipMemsetAsync(flags, 0, 64, s), "hipMemsetAsync(flags)");
+    RSF_HIP(launch_fill_u32(flags, 16, 0u, s), "flags clear");
     const int64_t P = (p->n + 63) / 64;
     for (int X = 0; X < p->d.n_det; ++X) {
         ResampleArgs a = base_resample_args(p, seg, X);
@@ -525,54 +548,83 @@ int rsf_resample(const rsf_plan* p, const rsf_segment* seg, const double* sky, i
     return RSF_OK;
 }
 
-int rsf_fstat(const rsf_plan* p, const rsf_segment* seg, const double* sky, int64_t n_sky, const double* fdot,
-              int64_t n_fdot, int mode, float* twoF, void* ws, size_t ws_bytes, void* stream) {
+namespace {
+// The full path over n_sky x n_fdot templates; writes the 2F map (twoF) or,
+// when topk is not null, only the k best entries.
+int run_fstat(const rsf_plan* p, const rsf_segment* seg, const double* sky, int64_t n_sky, const double* fdot,
+              int64_t n_fdot, int mode, float* twoF, int k, rsf_topk_entry* topk, void* ws, size_t ws_bytes,
+              void* stream) {
     if (!p) return fail(RSF_EINVAL, "plan is NULL");
     int rc = check_segment(p, seg);
     if (rc) return rc;
-    if (!sky || !fdot || !twoF) return fail(RSF_EINVAL, "sky, fdot or twoF is NULL");
+    const bool want_topk = topk != nullptr;
+    if (!sky || !fdot || (!twoF && !want_topk)) return fail(RSF_EINVAL, "sky, fdot or output is NULL");
     if (n_sky < 1 || n_fdot < 1) return fail(RSF_EINVAL, "n_sky and n_fdot must be positive");
     if (mode != RSF_MODE_PLAIN && mode != RSF_MODE_BATCHED) return fail(RSF_EINVAL, "unknown mode");
+    if (want_topk && (k < 1 || k > kTopkMax)) return fail(RSF_EINVAL, "k must be in 1..%d", kTopkMax);
     if (!ws) return fail(RSF_EINVAL, "workspace is NULL");
-    const WsLayout L = fstat_layout(p, n_fdot, mode);
+    const WsLayout L = fstat_layout(p, n_sky, n_fdot, mode, want_topk);
     if (ws_bytes < L.total) return fail(RSF_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, L.total);
     hipStream_t s = (hipStream_t)stream;
     char* w = (char*)ws;
     unsigned int* flags = (unsigned int*)(w + L.flags);
-    RSF_HIP(hipMemsetAsync(flags, 0, 64, s), "hipMemsetAsync(flags)");
+    RSF_HIP(launch_fill_u32(flags, 16, 0u, s), "flags clear");
     const int fb = (mode == RSF_MODE_BATCHED) ? 4 : 1;
     float4* spill = (float4*)(w + L.spill);
     const int64_t spill_stride = (int64_t)p->n_groups * p->LB * kPassBCols;
+    const bool f16 = p->d.storage == RSF_STORE_F16;
+    TopkItem* run[2] = {nullptr, nullptr};
+    int cur = 0;
+    bool have_run = false;
+    if (want_topk) {
+        run[0] = (TopkItem*)(w + L.run);
+        run[1] = run[0] + kTopkMax;
+    }
 
-    for (int64_t sk = 0; sk < n_sky; ++sk) {
+    for (int64_t c0 = 0; c0 < n_sky; c0 += L.S) {
+        const int sc = (int)std::min<int64_t>(L.S, n_sky - c0);
         for (int X = 0; X < p->d.n_det; ++X) {
             ResampleArgs a = base_resample_args(p, seg, X);
-            a.sky = sky + 2 * sk;
+            a.sky = sky + 2 * c0;
             a.LB = p->LB;
             a.P = p->P;
             a.layout = 1;
-            a.f16 = p->d.storage == RSF_STORE_F16;
+            a.f16 = f16;
             a.rs_main = (float4*)(w + L.rs_main[X]);
-            a.rs_tm = a.f16 ? nullptr : (float*)(w + L.rs_tm[X]);
-            a.rs_sky_stride = 0;
-            a.partials = (double*)(w + L.partials) + (size_t)X * L.n_blocks * 3;
+            a.rs_tm = f16 ? nullptr : (float*)(w + L.rs_tm[X]);
+            a.rs_sky_stride = L.rs_stride;
+            a.partials = (double*)(w + L.partials) + (size_t)X * sc * L.n_blocks * 3;
             a.n_blocks = L.n_blocks;
             a.flags = flags;
-            RSF_HIP(timed(p, K_RESAMPLE, s, [&] { return launch_resample(a, 1, s); }), "resample launch");
+            RSF_HIP(timed(p, K_RESAMPLE, s, [&] { return launch_resample(a, sc, s); }), "resample launch");
         }
         ReduceArgs r{};
         r.partials = (const double*)(w + L.partials);
         r.n_blocks = L.n_blocks;
         r.n_det = p->d.n_det;
-        r.n_sky = 1;
+        r.n_sky = sc;
         for (int X = 0; X < p->d.n_det; ++X) r.w[X] = p->det[X].w;
         r.abc_w = (double*)(w + L.abc_w);
         r.coef = (float*)(w + L.coef);
         r.flags = flags;
         RSF_HIP(timed(p, K_REDUCE, s, [&] { return launch_antenna_reduce(r, s); }), "antenna reduce launch");
 
-        for (int64_t f0 = 0; f0 < n_fdot; f0 += L.G) {
-            const int g = (int)std::min<int64_t>(L.G, n_fdot - f0);
+        // launches: (first sky of the chunk, skies, first spindown, spindowns)
+        struct Launch {
+            int s, ns;
+            int64_t f0;
+            int nf;
+        };
+        std::vector<Launch> launches;
+        if (n_fdot >= L.G) {
+            for (int sk = 0; sk < sc; ++sk)
+                for (int64_t f0 = 0; f0 < n_fdot; f0 += L.G)
+                    launches.push_back({sk, 1, f0, (int)std::min<int64_t>(L.G, n_fdot - f0)});
+        } else {
+            const int per = (int)(L.G / n_fdot);
+            for (int sk = 0; sk < sc; sk += per) launches.push_back({sk, std::min(per, sc - sk), 0, (int)n_fdot});
+        }
+        for (const Launch& q : launches) {
             PassAArgs A{};
             A.n = p->n;
             A.n_fft = p->n_fft;
@@ -583,12 +635,14 @@ int rsf_fstat(const rsf_plan* p, const rsf_segment* seg, const double* sky, int6
             A.n_det = p->d.n_det;
             for (int X = 0; X < p->d.n_det; ++X) {
                 A.w[X] = p->det[X].w;
-                A.rs_main[X] = (const float4*)(w + L.rs_main[X]);
-                A.rs_tm[X] = (p->d.storage == RSF_STORE_F32) ? (const float*)(w + L.rs_tm[X]) : nullptr;
+                A.rs_main[X] = (const float4*)(w + L.rs_main[X]) + (int64_t)q.s * L.rs_stride;
+                A.rs_tm[X] = f16 ? nullptr : (const float*)(w + L.rs_tm[X]) + (int64_t)q.s * L.rs_stride;
             }
-            A.f16 = p->d.storage == RSF_STORE_F16;
-            A.fdot = fdot + f0;
-            A.n_tmpl = g;
+            A.rs_sky_stride = L.rs_stride;
+            A.f16 = f16;
+            A.fdot = fdot + q.f0;
+            A.nf_l = q.nf;
+            A.n_sky_l = q.ns;
             A.fb = fb;
             A.st = p->stA;
             A.tw = p->twA;
@@ -607,21 +661,70 @@ int rsf_fstat(const rsf_plan* p, const rsf_segment* seg, const double* sky, int6
             B.tw = p->twB;
             B.spill = spill;
             B.spill_tmpl_stride = spill_stride;
-            B.coef = (const float*)(w + L.coef);
+            B.coef = (const float*)(w + L.coef) + 4 * q.s;
             B.s_lo = p->s_lo;
             B.n_out = p->n_out;
-            B.twoF = twoF;
-            B.out_row0 = sk * n_fdot + f0;
-            B.n_tmpl = g;
+            B.map_rows = want_topk ? 1 : 0;
+            B.twoF = want_topk ? (float*)(w + L.map) : twoF;
+            B.sky0 = c0 + q.s;
+            B.n_fdot = n_fdot;
+            B.f0 = q.f0;
+            B.nf_l = q.nf;
+            B.n_tmpl = q.ns * q.nf;
             RSF_HIP(timed(p, K_PASS_B, s, [&] { return launch_fft_pass_b(B, s); }), "pass B launch");
+
+            if (want_topk) {
+                TopkScanArgs ta{};
+                ta.map = (const float*)(w + L.map);
+                ta.n_vals = (int64_t)B.n_tmpl * p->n_out;
+                ta.n_out = p->n_out;
+                ta.sky0 = B.sky0;
+                ta.n_fdot = n_fdot;
+                ta.f0 = q.f0;
+                ta.nf_l = q.nf;
+                ta.k = k;
+                ta.cand = (TopkItem*)(w + L.cand);
+                RSF_HIP(timed(p, K_TOPK, s, [&] { return launch_topk_scan(ta, s); }), "topk scan launch");
+                TopkMergeArgs ma{};
+                ma.cand = ta.cand;
+                ma.n_cand = (int64_t)topk_scan_blocks(ta.n_vals) * k;
+                ma.run_in = have_run ? run[cur] : nullptr;
+                ma.run_out = run[cur ^ 1];
+                ma.k = k;
+                ma.n_fdot = n_fdot;
+                ma.n_out = p->n_out;
+                RSF_HIP(timed(p, K_TOPK, s, [&] { return launch_topk_merge(ma, s); }), "topk merge launch");
+                cur ^= 1;
+                have_run = true;
+            }
         }
+    }
+    if (want_topk) {
+        TopkMergeArgs ma{};
+        ma.cand = run[cur];
+        ma.n_cand = 0;
+        ma.run_in = run[cur];
+        ma.run_out = run[cur ^ 1];
+        ma.k = k;
+        ma.n_fdot = n_fdot;
+        ma.n_out = p->n_out;
+        ma.entries = topk;
+        RSF_HIP(timed(p, K_TOPK, s, [&] { return launch_topk_merge(ma, s); }), "topk final merge launch");
     }
     return RSF_OK;
 }
+}  // namespace
 
-int rsf_fstat_topk(const rsf_plan*, const rsf_segment*, const double*, int64_t, const double*, int64_t, int,
-                   rsf_topk_entry*, void*, size_t, void*) {
-    return fail(RSF_EUNSUPPORTED, "rsf_fstat_topk not built yet");
+int rsf_fstat(const rsf_plan* p, const rsf_segment* seg, const double* sky, int64_t n_sky, const double* fdot,
+              int64_t n_fdot, int mode, float* twoF, void* ws, size_t ws_bytes, void* stream) {
+    if (!twoF) return fail(RSF_EINVAL, "twoF is NULL");
+    return run_fstat(p, seg, sky, n_sky, fdot, n_fdot, mode, twoF, 0, nullptr, ws, ws_bytes, stream);
+}
+
+int rsf_fstat_topk(const rsf_plan* p, const rsf_segment* seg, const double* sky, int64_t n_sky, const double* fdot,
+                   int64_t n_fdot, int k, rsf_topk_entry* topk, void* ws, size_t ws_bytes, void* stream) {
+    if (!topk) return fail(RSF_EINVAL, "topk is NULL");
+    return run_fstat(p, seg, sky, n_sky, fdot, n_fdot, RSF_MODE_BATCHED, nullptr, k, topk, ws, ws_bytes, stream);
 }
 
 namespace {
@@ -640,7 +743,7 @@ int point_common(const rsf_plan* p, const rsf_segment* seg, const double* theta,
     hipStream_t s = (hipStream_t)stream;
     char* w = (char*)ws;
     unsigned int* flags = (unsigned int*)(w + L.flags);
-    RSF_HIP(hipMemsetAsync(flags, 0, 64, s), "hipMemsetAsync(flags)");
+    RSF_HIP(launch_fill_u32(flags, 16, 0u, s), "flags clear");
     PointArgs a{};
     a.n = p->n;
     a.dt = p->d.dt;
@@ -727,7 +830,7 @@ int rsf_get_flags(const rsf_plan* p, void* ws, uint32_t* flags, void* stream) {
     hipStream_t s = (hipStream_t)stream;
     RSF_HIP(hipMemcpyAsync(flags, ws, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "hipMemcpyAsync(flags)");
     RSF_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
-    RSF_HIP(hipMemsetAsync(ws, 0, sizeof(uint32_t), s), "hipMemsetAsync(flags)");
+    RSF_HIP(launch_fill_u32((unsigned int*)ws, 1, 0u, s), "flags clear");
     return RSF_OK;
 }
 

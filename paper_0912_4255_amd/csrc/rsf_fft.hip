@@ -64,10 +64,12 @@ constexpr int kInPer = (kNT * kEPT / 2 + kNT - 1) / kNT;
 __global__ __launch_bounds__(kNT) void rsf_fft_pass_a_k(PassAArgs A) {
     extern __shared__ float4 lds[];
     const int n_b = blockIdx.x;
-    const int t0 = blockIdx.y * A.fb;
-    const int t1 = min(t0 + A.fb, A.n_tmpl);
+    const int gpf = (A.nf_l + A.fb - 1) / A.fb;       // spindown groups per sky
+    const int s_l = blockIdx.y / gpf;
+    const int f_lo = (blockIdx.y - s_l * gpf) * A.fb;
+    const int f_hi = min(f_lo + A.fb, A.nf_l);
     const int tid = threadIdx.x;
-    const int64_t row = (int64_t)n_b * A.P;
+    const int64_t row = (int64_t)s_l * A.rs_sky_stride + (int64_t)n_b * A.P;
 
     // first detector's row: all loads issued before any is used, kept for every spindown
     float4 m0[kInPer];
@@ -92,8 +94,9 @@ __global__ __launch_bounds__(kNT) void rsf_fft_pass_a_k(PassAArgs A) {
     const float2 w_base = c_mul(A.tw_hi[mb >> kTwSplitBits], A.tw_lo[mb & msk]);
     const float2 w_step = c_mul(A.tw_hi[ms >> kTwSplitBits], A.tw_lo[ms & msk]);
 
-    for (int t = t0; t < t1; ++t) {
-        const double fd = A.fdot[t];
+    for (int f = f_lo; f < f_hi; ++f) {
+        const int t = s_l * A.nf_l + f;
+        const double fd = A.fdot[f];
 #pragma unroll
         for (int q = 0; q < kInPer; ++q) {
             const int n_a = tid + q * kNT;
@@ -148,8 +151,12 @@ __global__ __launch_bounds__(kNT) void rsf_fft_pass_b_k(PassBArgs B) {
     }
     __syncthreads();
     lds_fft<kNT, kEPT, kPassBCols>(lds, B.st, B.tw);
-    const float cA = B.coef[0], cB = B.coef[1], cC = B.coef[2];
-    float* out = B.twoF + (B.out_row0 + t) * B.n_out;
+    const int s_l = t / B.nf_l;
+    const int f = t - s_l * B.nf_l;
+    const float* cf = B.coef + 4 * s_l;
+    const float cA = cf[0], cB = cf[1], cC = cf[2];
+    const int64_t out_row = B.map_rows ? (int64_t)t : (B.sky0 + s_l) * B.n_fdot + B.f0 + f;
+    float* out = B.twoF + out_row * B.n_out;
     // 32-bit bin arithmetic (n_fft < 2^31)
     const int nf = (int)B.n_fft, s_lo = (int)B.s_lo, n_out = (int)B.n_out;
     for (int e = tid; e < tot; e += kNT) {
@@ -172,7 +179,7 @@ int fft_pass_max_elems() { return kNT * kEPT; }
 
 hipError_t launch_fft_pass_a(const PassAArgs& a, hipStream_t s) {
     const size_t lds = (size_t)a.LA * sizeof(float4);
-    const unsigned gy = (unsigned)((a.n_tmpl + a.fb - 1) / a.fb);
+    const unsigned gy = (unsigned)(a.n_sky_l * ((a.nf_l + a.fb - 1) / a.fb));
     hipLaunchKernelGGL(rsf_fft_pass_a_k, dim3((unsigned)a.LB, gy), dim3(kNT), lds, s, a);
     return hipGetLastError();
 }

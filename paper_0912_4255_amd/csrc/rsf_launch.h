@@ -16,6 +16,11 @@ hipError_t launch_fft_pass_b(const PassBArgs& b, hipStream_t s);
 hipError_t fft_set_lds_limits(size_t bytes);
 int fft_pass_max_elems();
 
+int topk_scan_blocks(int64_t n_vals);
+hipError_t launch_topk_scan(const TopkScanArgs& a, hipStream_t s);
+hipError_t launch_topk_merge(const TopkMergeArgs& a, hipStream_t s);
+hipError_t launch_fill_u32(unsigned int* p, int n, unsigned int v, hipStream_t s);
+
 int point_blocks(int64_t P);
 hipError_t launch_point(const PointArgs& a, bool grad, hipStream_t s);
 hipError_t launch_point_reduce(const PointReduceArgs& r, hipStream_t s);

@@ -95,8 +95,10 @@ struct ReduceArgs {
     unsigned int* flags;
 };
 
-// First FFT pass: for a sky, n_tmpl spindowns, each workgroup one input row
-// n_b and up to fb spindowns that share it.
+// First FFT pass over the templates of one launch: n_sky_l sky positions
+// (resampled series at rs_* + sky * rs_sky_stride) times nf_l spindowns
+// (fdot[0..nf_l)).  Each workgroup transforms one input row n_b for up to fb
+// spindowns of one sky, which share the row's inputs.  Template t = s nf_l + f.
 struct PassAArgs {
     int64_t n, n_fft;
     double dt;
@@ -106,19 +108,23 @@ struct PassAArgs {
     double w[kMaxDet];
     const float4* rs_main[kMaxDet];
     const float* rs_tm[kMaxDet];
+    int64_t rs_sky_stride;
     int f16;
-    const double* fdot;       // spindowns of this group
-    int n_tmpl;
+    const double* fdot;
+    int nf_l;
+    int n_sky_l;
     int fb;
     FftStages st;
     const float2* tw;         // W_LA^m
     const float2* tw_lo;
     const float2* tw_hi;
-    float4* spill;            // [n_tmpl][ceil(LA/8)][LB][8]
+    float4* spill;            // [n_sky_l * nf_l][ceil(LA/8)][LB][8]
     int64_t spill_tmpl_stride;
 };
 
-// Second FFT pass and F-statistic.
+// Second FFT pass and F-statistic for the launch's n_sky_l * nf_l templates;
+// template t = s nf_l + f goes to output row (sky0 + s) * n_fdot + f0 + f, or
+// to row t of a scratch map (map_rows = 1).
 struct PassBArgs {
     int64_t n_fft;
     int LA, LB;
@@ -127,11 +133,43 @@ struct PassBArgs {
     const float2* tw;         // W_LB^m
     const float4* spill;
     int64_t spill_tmpl_stride;
-    const float* coef;        // {2B/D, 2A/D, -4C/D, flag}
+    const float* coef;        // per sky of the launch {2B/D, 2A/D, -4C/D, flag}
     int64_t s_lo, n_out;
-    float* twoF;              // rows of n_out
-    int64_t out_row0;
+    float* twoF;
+    int map_rows;
+    int64_t sky0, n_fdot, f0;
+    int nf_l;
     int n_tmpl;
+};
+
+// Top-k over a scratch map of 2F rows (template t = s nf_l + f of a launch):
+// order by 2F descending, ties by the lower key (sky, fdot, bin) packed as
+// ((sky * n_fdot) + fdot) * n_out + bin.
+constexpr int kTopkMax = 64;
+struct TopkItem {
+    float v;
+    int pad;
+    unsigned long long key;
+};
+
+struct TopkScanArgs {
+    const float* map;
+    int64_t n_vals;           // rows * n_out
+    int64_t n_out;
+    int64_t sky0, n_fdot, f0;
+    int nf_l;
+    int k;
+    TopkItem* cand;           // [gridDim.x][k]
+};
+
+struct TopkMergeArgs {
+    const TopkItem* cand;     // n_cand items
+    int64_t n_cand;
+    const TopkItem* run_in;   // k items (may be null: start empty)
+    TopkItem* run_out;        // k items
+    int k;
+    int64_t n_fdot, n_out;
+    void* entries;            // rsf_topk_entry[k] written if not null
 };
 
 // Continuous-parameter 2F and its gradient (one detector set, a batch of

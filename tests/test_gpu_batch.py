@@ -1,0 +1,115 @@
+"""Batched search on the GPU: several sky positions per launch, plain vs
+batched identity, per-segment top-k with the (2F desc, then lower
+(sky, fdot, bin)) order, and segments of uneven length with 7-smooth FFTs."""
+import numpy as np
+import pytest
+
+from oracle import fstat as of
+from paper_0912_4255_amd import synth
+from paper_0912_4255_amd.synth import Injection
+from tests.helpers import make_inputs, to_gpu, twoF_tol
+
+pytestmark = pytest.mark.gpu
+
+
+def numpy_topk(maps, k):
+    """Reference selection on a [n_sky * n_fdot, n_out] map: 2F descending,
+    ties by lower flat index (= lower (sky, fdot, bin)); NaN excluded."""
+    flat = maps.reshape(-1).astype(np.float64)
+    idx = np.flatnonzero(~np.isnan(flat))
+    order = np.lexsort((idx, -flat[idx]))
+    return idx[order[:k]]
+
+
+def _workload(n, dt, n_gaps=3, seed=0, policy=synth.NFFT_TWICE, t_start=0.0):
+    w = synth.small_workload(n=n, dt=dt, kernel=synth.KERNEL_DIRICHLET, taps=16, nfft_policy=policy,
+                             t_start=t_start)
+    rng = np.random.default_rng(seed)
+    w.gaps = [synth.random_gaps(rng, n, max(1, n // 50), n_gaps)]
+    return w
+
+
+def test_multi_sky_batched_equals_plain_and_oracle(gpu_lib):
+    import torch
+    w = _workload(21600, 4.0)
+    df = 1.0 / (2 * w.segment.n * w.segment.dt)
+    sky = np.array([[1.2, 0.3], [4.0, -1.0], [0.2, 0.8], [2.9, -0.1]])
+    fdot = synth.fdot_grid(5)
+    inj = Injection(h0=1.5, cosi=0.1, psi=0.2, phi0=0.3, f0=w.segment.f_het + 1000 * df,
+                    fdot=float(fdot[2]), alpha=0.2, delta=0.8)
+    xs, gaps = make_inputs(w, seed=1, injections=[inj])
+    plan = gpu_lib.Plan(w)
+    tx, tg = to_gpu(xs, gaps)
+    ts, tf = torch.from_numpy(sky).cuda(), torch.from_numpy(fdot).cuda()
+    b = plan.fstat(tx, tg, ts, tf, mode=gpu_lib.RSF_MODE_BATCHED).cpu().numpy()
+    pl = plan.fstat(tx, tg, ts, tf, mode=gpu_lib.RSF_MODE_PLAIN).cpu().numpy()
+    assert np.array_equal(b, pl)
+    for si in (0, 2):
+        rss = [of.resample(xs[0], gaps[0], w.segment, *sky[si], w.eph, w.detectors[0], w.kernel, w.taps)]
+        for fi in (0, 2, 4):
+            ref = of.fstat_band(rss, w.detectors, fdot[fi], plan.n_fft, plan.s_lo, plan.n_out)
+            assert np.all(np.abs(b[si * 5 + fi] - ref) <= twoF_tol(ref))
+
+
+@pytest.mark.parametrize("k", [1, 10, 37])
+def test_topk_matches_map_selection(gpu_lib, k):
+    import torch
+    w = _workload(21600, 4.0, seed=2)
+    sky = synth.uniform_sky(np.random.default_rng(4), 6)
+    fdot = synth.fdot_grid(7)
+    xs, gaps = make_inputs(w, seed=3)
+    plan = gpu_lib.Plan(w)
+    tx, tg = to_gpu(xs, gaps)
+    ts, tf = torch.from_numpy(sky).cuda(), torch.from_numpy(fdot).cuda()
+    maps = plan.fstat(tx, tg, ts, tf).cpu().numpy()
+    vals, ids = plan.topk(tx, tg, ts, tf, k=k)
+    vals, ids = vals.cpu().numpy(), ids.cpu().numpy()
+    flat = numpy_topk(maps, k)
+    n_out = plan.n_out
+    exp_ids = np.stack([flat // (n_out * 7), (flat // n_out) % 7, flat % n_out], axis=1)
+    assert np.array_equal(ids, exp_ids)
+    assert np.array_equal(vals, maps.reshape(-1)[flat])
+
+
+def test_topk_uneven_segments_against_oracle(gpu_lib):
+    """Three back-to-back segments of different lengths (7-smooth FFT
+    lengths), each with an injection: every entry of a segment's top-10
+    matches the oracle value at its (sky, fdot, bin), an unambiguous oracle
+    maximum comes first, and no oracle value clearly above the 10th GPU value
+    is missing."""
+    import torch
+    lengths = [10007, 15120, 8642]
+    t0 = 0.0
+    fdot = synth.fdot_grid(4, lo=-2e-9)
+    sky = np.array([[1.0, 0.2], [3.5, -0.7], [5.0, 1.1]])
+    for i, n in enumerate(lengths):
+        w = _workload(n, 2.0, seed=10 + i, policy=synth.NFFT_SMOOTH7, t_start=t0)
+        t0 += n * 2.0
+        df = 1.0 / (2 * n * w.segment.dt)
+        si, fi = i % 3, (i + 1) % 4
+        inj = Injection(h0=2.0, cosi=0.4, psi=0.1, phi0=1.0, f0=w.segment.f_het + (300 + 50 * i) * df,
+                        fdot=float(fdot[fi]), alpha=float(sky[si, 0]), delta=float(sky[si, 1]))
+        xs, gaps = make_inputs(w, seed=20 + i, injections=[inj])
+        plan = gpu_lib.Plan(w)
+        tx, tg = to_gpu(xs, gaps)
+        vals, ids = plan.topk(tx, tg, torch.from_numpy(sky).cuda(), torch.from_numpy(fdot).cuda(), k=10)
+        vals, ids = vals.cpu().numpy(), ids.cpu().numpy()
+        assert np.all(np.diff(vals) <= 0)
+        ref_all = np.empty((3, 4, plan.n_out))
+        for s in range(3):
+            rss = [of.resample(xs[0], gaps[0], w.segment, *sky[s], w.eph, w.detectors[0], w.kernel, w.taps)]
+            for f in range(4):
+                ref_all[s, f] = of.fstat_band(rss, w.detectors, fdot[f], plan.n_fft, plan.s_lo, plan.n_out)
+        for v, (s, f, b) in zip(vals, ids):
+            r = ref_all[s, f, b]
+            assert abs(v - r) <= 1e-4 * max(r, 4.0)
+        # an unambiguous oracle maximum is the GPU's first entry
+        flat = np.sort(ref_all.reshape(-1))
+        if flat[-1] - flat[-2] > 2e-4 * flat[-1]:
+            assert tuple(ids[0]) == np.unravel_index(np.argmax(ref_all), ref_all.shape)
+        kth = vals[-1]
+        missing = ref_all > kth + 1e-4 * max(kth, 4.0) * 2
+        chosen = np.zeros_like(missing)
+        for s, f, b in ids:
+            chosen[s, f, b] = True
+        assert not np.any(missing & ~chosen)
