@@ -65,7 +65,7 @@ def load(path=None):
     global _lib
     if _lib is not None:
         return _lib
-    path = path or LIB_PATH
+    path = path or os.environ.get("RSF_LIB") or LIB_PATH
     if not os.path.exists(path):
         raise RuntimeError(f"librsfstat.so not found at {path}: build it with "
                            "`python -m paper_0912_4255_amd.build` (no fallback path exists)")

@@ -6,11 +6,12 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
 
-#include "../../include/rsfstat.h"
+#include "rsfstat.h"
 #include "rsf_launch.h"
 #include "rsf_params.h"
 
@@ -60,11 +61,12 @@ int64_t next_7smooth(int64_t n) {
 // columns: fewest stages with radices whose butterfly count len*B/R fits the
 // per-stage register capacity of the FFT kernels, ties broken by the largest
 // smallest radix.
-bool radix_plan(int len, int B, FftStages* st) {
+bool radix_plan(int len, int B, int NT, int EPT, FftStages* st) {
     static const int all_radices[] = {16, 15, 14, 12, 10, 9, 8, 7, 6, 5, 4, 3, 2};
     std::vector<int> radices;
+    if ((int64_t)len * B > (int64_t)NT * EPT) return false;
     for (int r : all_radices)
-        if ((int64_t)len * B / r <= fft_radix_cap(r)) radices.push_back(r);
+        if ((int64_t)len * B / r <= fft_radix_cap(r, NT, EPT)) radices.push_back(r);
     st->len = len;
     st->n_stages = 0;
     if (len == 1) return true;
@@ -149,9 +151,11 @@ struct rsf_plan {
     int LA, LB;          // first-pass length (over n_a), second-pass length (over n_b)
     int64_t P;           // rows of the transposed series: ceil(n / LB)
     int n_groups;        // ceil(LA / 8)
+    int n_cu;            // compute units (persistent second-pass grid)
     FftStages stA, stB;
     float2* twA;
     float2* twB;
+    float2* twB_hi;
     float2* tw_lo;
     float2* tw_hi;
     EphDev eph;
@@ -368,7 +372,10 @@ int rsf_plan_create(rsf_plan** out, const rsf_plan_desc* d) {
         const int64_t la = p->n_fft / lb;
         if (la > la_max) continue;
         FftStages sa, sb;
-        if (!radix_plan((int)la, 1, &sa) || !radix_plan((int)lb, kPassBCols, &sb)) continue;
+        if (!radix_plan((int)la, 1, kFftThreads, kFftEPT, &sa) ||
+            !radix_plan((int)lb, kPassBCols / 2, kFftThreads, kPassBEPT, &sb) ||
+            fft_pass_b_lds((int)lb, 64) > (size_t)lds_max)
+            continue;
         const double lds_a = (double)la * 16, lds_b = (double)lb * 128;
         double score = (sa.n_stages + sb.n_stages) * 1e9 + ((la % 8) ? 1e8 : 0.0) + std::max(lds_a, lds_b);
         if (score < best_score) {
@@ -384,15 +391,18 @@ int rsf_plan_create(rsf_plan** out, const rsf_plan_desc* d) {
     }
     p->LA = best_la;
     p->LB = best_lb;
-    radix_plan(p->LA, 1, &p->stA);
-    radix_plan(p->LB, kPassBCols, &p->stB);
+    radix_plan(p->LA, 1, kFftThreads, kFftEPT, &p->stA);
+    radix_plan(p->LB, kPassBCols / 2, kFftThreads, kPassBEPT, &p->stB);
     p->P = (p->n + p->LB - 1) / p->LB;
     p->n_groups = (p->LA + kPassBCols - 1) / kPassBCols;
     if (p->P > p->LA) {
         delete p;
         return fail(RSF_EUNSUPPORTED, "internal: rows exceed first-pass length");
     }
-    const size_t lds_need = std::max<size_t>((size_t)p->LA * 16, (size_t)p->LB * 128);
+    const size_t lds_need = std::max<size_t>((size_t)p->LA * 16, fft_pass_b_lds(p->LB, 64));
+    if (hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess ||
+        p->n_cu <= 0)
+        p->n_cu = 256;
     if (lds_need > 65536) fft_set_lds_limits(lds_need);
 
     // twiddle tables, built in FP64 and stored as FP32
@@ -405,7 +415,9 @@ int rsf_plan_create(rsf_plan** out, const rsf_plan_desc* d) {
         }
         return t;
     };
-    std::vector<float2> ta = table(p->LA, p->LA, 1), tb = table(p->LB, p->LB, 1);
+    std::vector<float2> ta = table(p->LA, p->LA, 1);
+    // second-pass stage twiddles as two levels: W_LB^m = lo[m % 32] * hi[m / 32]
+    std::vector<float2> tb = table(p->LB, 32, 1), tbh = table(p->LB, (p->LB + 31) / 32, 32);
     const int64_t nlo = 1 << kTwSplitBits;
     std::vector<float2> tlo = table(p->n_fft, nlo, 1);
     const int64_t nhi = p->n_fft / nlo + 1;
@@ -416,8 +428,8 @@ int rsf_plan_create(rsf_plan** out, const rsf_plan_desc* d) {
         return RSF_OK;
     };
     int rc;
-    if ((rc = upload(&p->twA, ta)) || (rc = upload(&p->twB, tb)) || (rc = upload(&p->tw_lo, tlo)) ||
-        (rc = upload(&p->tw_hi, thi))) {
+    if ((rc = upload(&p->twA, ta)) || (rc = upload(&p->twB, tb)) || (rc = upload(&p->twB_hi, tbh)) ||
+        (rc = upload(&p->tw_lo, tlo)) || (rc = upload(&p->tw_hi, thi))) {
         rsf_plan_destroy(p);
         return rc;
     }
@@ -455,6 +467,7 @@ int rsf_plan_destroy(rsf_plan* p) {
     if (!p) return RSF_OK;
     hipFree(p->twA);
     hipFree(p->twB);
+    hipFree(p->twB_hi);
     hipFree(p->tw_lo);
     hipFree(p->tw_hi);
     delete p->prof;
@@ -658,10 +671,12 @@ int run_fstat(const rsf_plan* p, const rsf_segment* seg, const double* sky, int6
             B.LB = p->LB;
             B.n_groups = p->n_groups;
             B.st = p->stB;
-            B.tw = p->twB;
+            B.tw_lo = p->twB;
+            B.tw_hi = p->twB_hi;
             B.spill = spill;
             B.spill_tmpl_stride = spill_stride;
             B.coef = (const float*)(w + L.coef) + 4 * q.s;
+            B.n_sky_l = q.ns;
             B.s_lo = p->s_lo;
             B.n_out = p->n_out;
             B.map_rows = want_topk ? 1 : 0;
@@ -671,7 +686,7 @@ int run_fstat(const rsf_plan* p, const rsf_segment* seg, const double* sky, int6
             B.f0 = q.f0;
             B.nf_l = q.nf;
             B.n_tmpl = q.ns * q.nf;
-            RSF_HIP(timed(p, K_PASS_B, s, [&] { return launch_fft_pass_b(B, s); }), "pass B launch");
+            RSF_HIP(timed(p, K_PASS_B, s, [&] { return launch_fft_pass_b(B, p->n_cu, s); }), "pass B launch");
 
             if (want_topk) {
                 TopkScanArgs ta{};

@@ -176,15 +176,16 @@ struct Dft<7> {
     }
 };
 
-// Composite radix R = P * Q in registers (Cooley-Tukey): n = Q n1 + n2,
-// k = k1 + P k2; P-point DFTs over n1, twiddle W_R^{n2 k1}, Q-point DFTs
-// over n2.
+// Composite radix R = P * Q in registers (Cooley-Tukey), in place: with
+// n = Q n1 + n2 and k = k1 + P k2, P-point DFTs over n1 are written back to
+// x[Q k1 + n2] times W_R^{n2 k1}; Q-point DFTs then run on the contiguous
+// runs x[Q k1 .. Q k1 + Q-1], leaving y[k1 + P k2] at x[Q k1 + k2]; a final
+// register permutation restores natural order.  Peak liveness R + P values.
 template <int P, int Q>
 struct DftCT {
     __device__ __forceinline__ static void run(cp* x) {
         constexpr int R = P * Q;
         constexpr Roots<R> w{};
-        cp u[R];
 #pragma unroll
         for (int n2 = 0; n2 < Q; ++n2) {
             cp t[P];
@@ -194,18 +195,18 @@ struct DftCT {
 #pragma unroll
             for (int k1 = 0; k1 < P; ++k1) {
                 const int m = (n2 * k1) % R;
-                u[n2 * P + k1] = (m == 0) ? t[k1] : cp_rot(t[k1], w.re[m], w.im[m]);
+                x[Q * k1 + n2] = (m == 0) ? t[k1] : cp_rot(t[k1], w.re[m], w.im[m]);
             }
         }
 #pragma unroll
-        for (int k1 = 0; k1 < P; ++k1) {
-            cp t[Q];
+        for (int k1 = 0; k1 < P; ++k1) Dft<Q>::run(x + Q * k1);
+        cp y[R];
 #pragma unroll
-            for (int n2 = 0; n2 < Q; ++n2) t[n2] = u[n2 * P + k1];
-            Dft<Q>::run(t);
+        for (int k1 = 0; k1 < P; ++k1)
 #pragma unroll
-            for (int k2 = 0; k2 < Q; ++k2) x[k1 + P * k2] = t[k2];
-        }
+            for (int k2 = 0; k2 < Q; ++k2) y[k1 + P * k2] = x[Q * k1 + k2];
+#pragma unroll
+        for (int i = 0; i < R; ++i) x[i] = y[i];
     }
 };
 
@@ -241,9 +242,20 @@ __device__ __forceinline__ void divmod_small(int j, int d, float inv_d, int& q, 
     }
 }
 
-template <int R, int NT, int EPT, int B>
-__device__ __forceinline__ void stockham_stage(cp* __restrict__ s, int L, int Ns,
-                                               const float2* __restrict__ tw) {
+// Twiddle sources for the stages: W_L^m from a length-L table in global
+// memory, or from a two-level table in LDS, W_L^m = lo[m % 32] * hi[m / 32].
+struct TwGlobal {
+    const float2* __restrict__ t;
+    __device__ __forceinline__ float2 operator()(int m) const { return t[m]; }
+};
+struct TwLds {
+    const float2* lo;  // 32 entries
+    const float2* hi;  // ceil(L / 32) entries
+    __device__ __forceinline__ float2 operator()(int m) const { return c_mul(lo[m & 31], hi[m >> 5]); }
+};
+
+template <int R, int NT, int EPT, int B, typename TW>
+__device__ __forceinline__ void stockham_stage(cp* __restrict__ s, int L, int Ns, const TW& tw) {
     constexpr int MAXB = (EPT / R) > 0 ? (EPT / R) : 1;  // the planner keeps L*B/R <= MAXB*NT
     const int tid = threadIdx.x;
     const int LR = L / R;
@@ -261,7 +273,7 @@ __device__ __forceinline__ void stockham_stage(cp* __restrict__ s, int L, int Ns
 #pragma unroll
             for (int r = 0; r < R; ++r) v[q][r] = s[(j + r * LR) * B + b];
             if (Ns > 1) {
-                const float2 w1 = tw[k * tstride];
+                const float2 w1 = tw(k * tstride);
                 float2 w = w1;
 #pragma unroll
                 for (int r = 1; r < R; ++r) {
@@ -289,25 +301,25 @@ __device__ __forceinline__ void stockham_stage(cp* __restrict__ s, int L, int Ns
 }
 
 // Run all stages of a planned transform (radix sequence in st).
-template <int NT, int EPT, int B>
-__device__ void lds_fft(cp* __restrict__ s, const FftStages& st, const float2* __restrict__ tw) {
+template <int NT, int EPT, int B, typename TW>
+__device__ void lds_fft(cp* __restrict__ s, const FftStages& st, const TW& tw) {
     int Ns = 1;
     for (int i = 0; i < st.n_stages; ++i) {
         const int R = st.radix[i];
         switch (R) {
-            case 2: stockham_stage<2, NT, EPT, B>(s, st.len, Ns, tw); break;
-            case 3: stockham_stage<3, NT, EPT, B>(s, st.len, Ns, tw); break;
-            case 4: stockham_stage<4, NT, EPT, B>(s, st.len, Ns, tw); break;
-            case 5: stockham_stage<5, NT, EPT, B>(s, st.len, Ns, tw); break;
-            case 6: stockham_stage<6, NT, EPT, B>(s, st.len, Ns, tw); break;
-            case 7: stockham_stage<7, NT, EPT, B>(s, st.len, Ns, tw); break;
-            case 8: stockham_stage<8, NT, EPT, B>(s, st.len, Ns, tw); break;
-            case 9: stockham_stage<9, NT, EPT, B>(s, st.len, Ns, tw); break;
-            case 10: stockham_stage<10, NT, EPT, B>(s, st.len, Ns, tw); break;
-            case 12: stockham_stage<12, NT, EPT, B>(s, st.len, Ns, tw); break;
-            case 14: stockham_stage<14, NT, EPT, B>(s, st.len, Ns, tw); break;
-            case 15: stockham_stage<15, NT, EPT, B>(s, st.len, Ns, tw); break;
-            case 16: stockham_stage<16, NT, EPT, B>(s, st.len, Ns, tw); break;
+            case 2: stockham_stage<2, NT, EPT, B, TW>(s, st.len, Ns, tw); break;
+            case 3: stockham_stage<3, NT, EPT, B, TW>(s, st.len, Ns, tw); break;
+            case 4: stockham_stage<4, NT, EPT, B, TW>(s, st.len, Ns, tw); break;
+            case 5: stockham_stage<5, NT, EPT, B, TW>(s, st.len, Ns, tw); break;
+            case 6: stockham_stage<6, NT, EPT, B, TW>(s, st.len, Ns, tw); break;
+            case 7: stockham_stage<7, NT, EPT, B, TW>(s, st.len, Ns, tw); break;
+            case 8: stockham_stage<8, NT, EPT, B, TW>(s, st.len, Ns, tw); break;
+            case 9: stockham_stage<9, NT, EPT, B, TW>(s, st.len, Ns, tw); break;
+            case 10: stockham_stage<10, NT, EPT, B, TW>(s, st.len, Ns, tw); break;
+            case 12: stockham_stage<12, NT, EPT, B, TW>(s, st.len, Ns, tw); break;
+            case 14: stockham_stage<14, NT, EPT, B, TW>(s, st.len, Ns, tw); break;
+            case 15: stockham_stage<15, NT, EPT, B, TW>(s, st.len, Ns, tw); break;
+            case 16: stockham_stage<16, NT, EPT, B, TW>(s, st.len, Ns, tw); break;
             default: break;
         }
         Ns *= R;

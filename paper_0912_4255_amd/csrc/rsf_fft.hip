@@ -14,6 +14,8 @@
 // block, transforms the 8 columns over n_b in LDS and reduces every bin to
 // 2F = cA |f_a|^2 + cB |f_b|^2 + cC Re(f_a f_b^*), writing the reported band
 // in ascending frequency.
+#include <algorithm>
+
 #include "rsf_device.h"
 #include "rsf_launch.h"
 
@@ -115,7 +117,7 @@ __global__ __launch_bounds__(kNT) void rsf_fft_pass_a_k(PassAArgs A) {
         }
         for (int n_a = tid + kInPer * kNT; n_a < A.LA; n_a += kNT) lds[n_a] = make_float4(0.f, 0.f, 0.f, 0.f);
         __syncthreads();
-        lds_fft<kNT, kEPT, 1>(lds, A.st, A.tw);
+        lds_fft<kNT, kEPT, 1>(lds, A.st, TwGlobal{A.tw});
         float4* out = A.spill + (int64_t)t * A.spill_tmpl_stride;
         float2 w = w_base;
         for (int ka = tid; ka < A.LA; ka += kNT) {
@@ -127,51 +129,79 @@ __global__ __launch_bounds__(kNT) void rsf_fft_pass_a_k(PassAArgs A) {
     }
 }
 
-__global__ __launch_bounds__(kNT) void rsf_fft_pass_b_k(PassBArgs B) {
-    extern __shared__ float4 lds[];
-    const int c = blockIdx.x;
-    const int t = blockIdx.y;
-    const int tid = threadIdx.x;
-    const float4* in = B.spill + (int64_t)t * B.spill_tmpl_stride + (int64_t)c * B.LB * kPassBCols;
-    const int tot = B.LB * kPassBCols;
-    // loads issued in batches of kEPT/2 before their LDS stores
-#pragma unroll
-    for (int q0 = 0; q0 < kEPT; q0 += kEPT / 2) {
-        float4 v[kEPT / 2];
-#pragma unroll
-        for (int q = 0; q < kEPT / 2; ++q) {
-            const int e = tid + (q0 + q) * kNT;
-            v[q] = in[e < tot ? e : 0];
-        }
-#pragma unroll
-        for (int q = 0; q < kEPT / 2; ++q) {
-            const int e = tid + (q0 + q) * kNT;
-            if (e < tot) lds[e] = v[q];
+// Second pass, persistent and software-pipelined.  Workgroup g handles the
+// spill blocks g, g + grid, ... (block = template * n_groups + group of 8
+// columns), each as two 4-column halves.  Halves go through two LDS buffers:
+// while one half is transformed, the next half is copied global -> LDS by
+// the DMA loads (no registers involved), so memory traffic overlaps the
+// FFT.  The two halves of a 128 B spill row and of a 2F output line are
+// handled back to back by the same workgroup and meet in its L2.
+constexpr int kHalfCols = kPassBCols / 2;
+
+__device__ __forceinline__ void passb_dma(const PassBArgs& B, int unit, int h, float4* dst) {
+    const int t = unit / B.n_groups;
+    const int c = unit - t * B.n_groups;
+    const float4* base = B.spill + (int64_t)t * B.spill_tmpl_stride + (int64_t)c * B.LB * kPassBCols + h * kHalfCols;
+    const int half = B.LB * kHalfCols;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int e0 = wave * 64; e0 < half; e0 += kNT) {
+        const int e = e0 + lane;
+        if (e < half) {
+            const float4* src = base + (e / kHalfCols) * kPassBCols + (e % kHalfCols);
+            __builtin_amdgcn_global_load_lds((const void*)src, (__attribute__((address_space(3))) void*)(dst + e0),
+                                             16, 0, 0);
         }
     }
-    __syncthreads();
-    lds_fft<kNT, kEPT, kPassBCols>(lds, B.st, B.tw);
-    const int s_l = t / B.nf_l;
-    const int f = t - s_l * B.nf_l;
-    const float* cf = B.coef + 4 * s_l;
-    const float cA = cf[0], cB = cf[1], cC = cf[2];
-    const int64_t out_row = B.map_rows ? (int64_t)t : (B.sky0 + s_l) * B.n_fdot + B.f0 + f;
-    float* out = B.twoF + out_row * B.n_out;
-    // 32-bit bin arithmetic (n_fft < 2^31)
+}
+
+__global__ __launch_bounds__(kNT) void rsf_fft_pass_b_k(PassBArgs B) {
+    extern __shared__ float4 lds[];
+    const int half = B.LB * kHalfCols;
+    const int buf_elems = ((half + 63) / 64) * 64;
+    float2* twl = reinterpret_cast<float2*>(lds + 2 * buf_elems);
+    const int n_hi = (B.LB + 31) >> kTwLoBits;
+    float* cfl = reinterpret_cast<float*>(twl + 32 + n_hi);
+    const int tid = threadIdx.x;
+    for (int i = tid; i < 32 + n_hi; i += kNT) twl[i] = (i < 32) ? B.tw_lo[i] : B.tw_hi[i - 32];
+    for (int i = tid; i < 4 * B.n_sky_l; i += kNT) cfl[i] = B.coef[i];
+    const TwLds tw{twl, twl + 32};
+    const int n_units = B.n_tmpl * B.n_groups;
     const int nf = (int)B.n_fft, s_lo = (int)B.s_lo, n_out = (int)B.n_out;
-    for (int e = tid; e < tot; e += kNT) {
-        const int kb = e >> 3;
-        const int ka = c * kPassBCols + (e & 7);
-        if (ka < B.LA) {
-            const int k = ka + B.LA * kb;
-            const int s = (2 * k < nf) ? k : k - nf;
-            const int o = s - s_lo;
-            if (o >= 0 && o < n_out) {
-                const cp u = lds[e];
-                out[o] = cA * (u.x * u.x + u.y * u.y) + cB * (u.z * u.z + u.w * u.w) +
-                         cC * (u.x * u.z + u.y * u.w);
+
+    int unit = blockIdx.x, h = 0, cur = 0;
+    if (unit < n_units) passb_dma(B, unit, 0, lds);
+    while (unit < n_units) {
+        __builtin_amdgcn_s_waitcnt(0);  // this thread's DMA loads and stores are complete
+        __syncthreads();                // ... and everyone's: buffer cur is filled, buffer cur^1 is free
+        const int nunit = h ? unit + (int)gridDim.x : unit;
+        const int nh = h ^ 1;
+        if (nunit < n_units) passb_dma(B, nunit, nh, lds + (cur ^ 1) * buf_elems);
+        cp* x = lds + cur * buf_elems;
+        lds_fft<kNT, kPassBEPT, kHalfCols>(x, B.st, tw);
+        const int t = unit / B.n_groups;
+        const int c = unit - t * B.n_groups;
+        const int s_l = t / B.nf_l;
+        const int f = t - s_l * B.nf_l;
+        const float cA = cfl[4 * s_l], cB = cfl[4 * s_l + 1], cC = cfl[4 * s_l + 2];
+        const int64_t out_row = B.map_rows ? (int64_t)t : (B.sky0 + s_l) * B.n_fdot + B.f0 + f;
+        float* out = B.twoF + out_row * B.n_out;
+        for (int e = tid; e < half; e += kNT) {
+            const int kb = e >> 2;
+            const int ka = c * kPassBCols + h * kHalfCols + (e & 3);
+            if (ka < B.LA) {
+                const int k = ka + B.LA * kb;
+                const int s = (2 * k < nf) ? k : k - nf;
+                const int o = s - s_lo;
+                if (o >= 0 && o < n_out) {
+                    const cp u = x[e];
+                    out[o] = cA * (u.x * u.x + u.y * u.y) + cB * (u.z * u.z + u.w * u.w) +
+                             cC * (u.x * u.z + u.y * u.w);
+                }
             }
         }
+        unit = nunit;
+        h = nh;
+        cur ^= 1;
     }
 }
 
@@ -184,9 +214,16 @@ hipError_t launch_fft_pass_a(const PassAArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_fft_pass_b(const PassBArgs& b, hipStream_t s) {
-    const size_t lds = (size_t)b.LB * kPassBCols * sizeof(float4);
-    hipLaunchKernelGGL(rsf_fft_pass_b_k, dim3((unsigned)b.n_groups, (unsigned)b.n_tmpl), dim3(kNT), lds, s, b);
+size_t fft_pass_b_lds(int LB, int n_sky_l) {
+    const size_t buf = (size_t)((LB * kHalfCols + 63) / 64) * 64;
+    return 2 * buf * sizeof(float4) + (32 + (LB + 31) / 32) * sizeof(float2) + (size_t)4 * n_sky_l * sizeof(float);
+}
+
+hipError_t launch_fft_pass_b(const PassBArgs& b, int n_cu, hipStream_t s) {
+    const size_t lds = fft_pass_b_lds(b.LB, b.n_sky_l);
+    const int n_items = b.n_tmpl * b.n_groups;
+    const unsigned grid = (unsigned)std::max(1, std::min(n_items, n_cu));
+    hipLaunchKernelGGL(rsf_fft_pass_b_k, dim3(grid), dim3(kNT), lds, s, b);
     return hipGetLastError();
 }
 

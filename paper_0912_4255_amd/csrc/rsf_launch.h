@@ -12,7 +12,8 @@ int resample_blocks(int LB, int64_t P);
 hipError_t launch_antenna_reduce(const ReduceArgs& r, hipStream_t s);
 
 hipError_t launch_fft_pass_a(const PassAArgs& a, hipStream_t s);
-hipError_t launch_fft_pass_b(const PassBArgs& b, hipStream_t s);
+hipError_t launch_fft_pass_b(const PassBArgs& b, int n_cu, hipStream_t s);
+size_t fft_pass_b_lds(int LB, int n_sky_l);
 hipError_t fft_set_lds_limits(size_t bytes);
 int fft_pass_max_elems();
 

@@ -19,10 +19,17 @@ constexpr int kTwSplitBits = 12;    // inter-pass twiddle W_N^m = hi[m >> 12] * 
 constexpr int kFftThreads = 512;    // threads of an FFT-pass workgroup
 constexpr int kFftEPT = 20;         // complex pairs held per thread in a stage (L * B <= 10240)
 
-// Butterflies of radix R one thread holds in a stage: never more than kFftEPT
-// elements, so a stage of radix R covers at most fft_radix_cap(R) butterflies.
-constexpr int fft_bfly_per_thread(int R) { return (kFftEPT / R) > 0 ? (kFftEPT / R) : 1; }
-constexpr int fft_radix_cap(int R) { return fft_bfly_per_thread(R) * kFftThreads; }
+// Butterflies of radix R one thread holds in a stage: never more than EPT
+// elements, so a stage of radix R covers at most fft_radix_cap(R) butterflies
+// of a workgroup of NT threads.
+constexpr int fft_bfly_per_thread(int R, int EPT) { return (EPT / R) > 0 ? (EPT / R) : 1; }
+constexpr int fft_radix_cap(int R, int NT, int EPT) { return fft_bfly_per_thread(R, EPT) * NT; }
+
+// Second pass: persistent workgroups, one per CU, transforming 4-column
+// halves of the spill blocks through two LDS buffers filled by DMA loads;
+// the stage capacity is kPassBEPT elements per thread.
+constexpr int kPassBEPT = 16;
+constexpr int kTwLoBits = 5;        // LDS twiddle table W_L^m = lo[m & 31] * hi[m >> 5]
 
 struct FftStages {
     int len;
@@ -130,10 +137,12 @@ struct PassBArgs {
     int LA, LB;
     int n_groups;             // ceil(LA / 8)
     FftStages st;
-    const float2* tw;         // W_LB^m
+    const float2* tw_lo;      // W_LB^m for m < 32
+    const float2* tw_hi;      // W_LB^{32 m} for m < ceil(LB / 32)
     const float4* spill;
     int64_t spill_tmpl_stride;
     const float* coef;        // per sky of the launch {2B/D, 2A/D, -4C/D, flag}
+    int n_sky_l;
     int64_t s_lo, n_out;
     float* twoF;
     int map_rows;
