@@ -154,6 +154,7 @@ struct rsf_plan {
     int n_cu;            // compute units (persistent second-pass grid)
     FftStages stA, stB;
     float2* twA;
+    float2* twA_hi;
     float2* twB;
     float2* twB_hi;
     float2* tw_lo;
@@ -370,7 +371,7 @@ int rsf_plan_create(rsf_plan** out, const rsf_plan_desc* d) {
     for (int64_t lb = 1; lb <= lb_max; ++lb) {
         if (p->n_fft % lb) continue;
         const int64_t la = p->n_fft / lb;
-        if (la > la_max) continue;
+        if (la > la_max || fft_pass_a_lds((int)la) > (size_t)lds_max) continue;
         FftStages sa, sb;
         if (!radix_plan((int)la, 1, kFftThreads, kFftEPT, &sa) ||
             !radix_plan((int)lb, kPassBCols / 2, kFftThreads, kPassBEPT, &sb) ||
@@ -399,7 +400,7 @@ int rsf_plan_create(rsf_plan** out, const rsf_plan_desc* d) {
         delete p;
         return fail(RSF_EUNSUPPORTED, "internal: rows exceed first-pass length");
     }
-    const size_t lds_need = std::max<size_t>((size_t)p->LA * 16, fft_pass_b_lds(p->LB, 64));
+    const size_t lds_need = std::max<size_t>(fft_pass_a_lds(p->LA), fft_pass_b_lds(p->LB, 64));
     if (hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess ||
         p->n_cu <= 0)
         p->n_cu = 256;
@@ -415,7 +416,7 @@ int rsf_plan_create(rsf_plan** out, const rsf_plan_desc* d) {
         }
         return t;
     };
-    std::vector<float2> ta = table(p->LA, p->LA, 1);
+    std::vector<float2> ta = table(p->LA, 32, 1), tah = table(p->LA, (p->LA + 31) / 32, 32);
     // second-pass stage twiddles as two levels: W_LB^m = lo[m % 32] * hi[m / 32]
     std::vector<float2> tb = table(p->LB, 32, 1), tbh = table(p->LB, (p->LB + 31) / 32, 32);
     const int64_t nlo = 1 << kTwSplitBits;
@@ -428,7 +429,7 @@ int rsf_plan_create(rsf_plan** out, const rsf_plan_desc* d) {
         return RSF_OK;
     };
     int rc;
-    if ((rc = upload(&p->twA, ta)) || (rc = upload(&p->twB, tb)) || (rc = upload(&p->twB_hi, tbh)) ||
+    if ((rc = upload(&p->twA, ta)) || (rc = upload(&p->twA_hi, tah)) || (rc = upload(&p->twB, tb)) || (rc = upload(&p->twB_hi, tbh)) ||
         (rc = upload(&p->tw_lo, tlo)) || (rc = upload(&p->tw_hi, thi))) {
         rsf_plan_destroy(p);
         return rc;
@@ -466,6 +467,7 @@ int rsf_plan_create(rsf_plan** out, const rsf_plan_desc* d) {
 int rsf_plan_destroy(rsf_plan* p) {
     if (!p) return RSF_OK;
     hipFree(p->twA);
+    hipFree(p->twA_hi);
     hipFree(p->twB);
     hipFree(p->twB_hi);
     hipFree(p->tw_lo);
@@ -658,7 +660,8 @@ int run_fstat(const rsf_plan* p, const rsf_segment* seg, const double* sky, int6
             A.n_sky_l = q.ns;
             A.fb = fb;
             A.st = p->stA;
-            A.tw = p->twA;
+            A.tws_lo = p->twA;
+            A.tws_hi = p->twA_hi;
             A.tw_lo = p->tw_lo;
             A.tw_hi = p->tw_hi;
             A.spill = spill;

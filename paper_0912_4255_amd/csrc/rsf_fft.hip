@@ -65,6 +65,12 @@ constexpr int kInPer = (kNT * kEPT / 2 + kNT - 1) / kNT;
 
 __global__ __launch_bounds__(kNT) void rsf_fft_pass_a_k(PassAArgs A) {
     extern __shared__ float4 lds[];
+    // stage twiddles in LDS after the row: no global load inside the stages,
+    // so the spill stores of one spindown stay in flight during the next FFT
+    float2* twl = reinterpret_cast<float2*>(lds + A.LA);
+    const int n_hi = (A.LA + 31) >> kTwLoBits;
+    for (int i = threadIdx.x; i < 32 + n_hi; i += kNT) twl[i] = (i < 32) ? A.tws_lo[i] : A.tws_hi[i - 32];
+    const TwLds tws{twl, twl + 32};
     const int n_b = blockIdx.x;
     const int gpf = (A.nf_l + A.fb - 1) / A.fb;       // spindown groups per sky
     const int s_l = blockIdx.y / gpf;
@@ -117,7 +123,7 @@ __global__ __launch_bounds__(kNT) void rsf_fft_pass_a_k(PassAArgs A) {
         }
         for (int n_a = tid + kInPer * kNT; n_a < A.LA; n_a += kNT) lds[n_a] = make_float4(0.f, 0.f, 0.f, 0.f);
         __syncthreads();
-        lds_fft<kNT, kEPT, 1>(lds, A.st, TwGlobal{A.tw});
+        lds_fft<kNT, kEPT, 1>(lds, A.st, tws);
         float4* out = A.spill + (int64_t)t * A.spill_tmpl_stride;
         float2 w = w_base;
         for (int ka = tid; ka < A.LA; ka += kNT) {
@@ -207,8 +213,10 @@ __global__ __launch_bounds__(kNT) void rsf_fft_pass_b_k(PassBArgs B) {
 
 int fft_pass_max_elems() { return kNT * kEPT; }
 
+size_t fft_pass_a_lds(int LA) { return (size_t)LA * sizeof(float4) + (32 + (LA + 31) / 32) * sizeof(float2); }
+
 hipError_t launch_fft_pass_a(const PassAArgs& a, hipStream_t s) {
-    const size_t lds = (size_t)a.LA * sizeof(float4);
+    const size_t lds = fft_pass_a_lds(a.LA);
     const unsigned gy = (unsigned)(a.n_sky_l * ((a.nf_l + a.fb - 1) / a.fb));
     hipLaunchKernelGGL(rsf_fft_pass_a_k, dim3((unsigned)a.LB, gy), dim3(kNT), lds, s, a);
     return hipGetLastError();

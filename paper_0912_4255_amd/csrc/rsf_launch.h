@@ -12,6 +12,7 @@ int resample_blocks(int LB, int64_t P);
 hipError_t launch_antenna_reduce(const ReduceArgs& r, hipStream_t s);
 
 hipError_t launch_fft_pass_a(const PassAArgs& a, hipStream_t s);
+size_t fft_pass_a_lds(int LA);
 hipError_t launch_fft_pass_b(const PassBArgs& b, int n_cu, hipStream_t s);
 size_t fft_pass_b_lds(int LB, int n_sky_l);
 hipError_t fft_set_lds_limits(size_t bytes);

@@ -122,8 +122,9 @@ struct PassAArgs {
     int n_sky_l;
     int fb;
     FftStages st;
-    const float2* tw;         // W_LA^m
-    const float2* tw_lo;
+    const float2* tws_lo;     // stage twiddles W_LA^m = tws_lo[m % 32] * tws_hi[m / 32]
+    const float2* tws_hi;
+    const float2* tw_lo;      // inter-pass twiddle W_N^m = tw_hi[m >> 12] * tw_lo[m & 4095]
     const float2* tw_hi;
     float4* spill;            // [n_sky_l * nf_l][ceil(LA/8)][LB][8]
     int64_t spill_tmpl_stride;
