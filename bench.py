@@ -44,6 +44,12 @@ def parse():
     ap.add_argument("--cpu-templates", type=int, default=2)
     ap.add_argument("--copy-check", action="store_true",
                     help="also run one 1 GiB device-to-device copy (counter calibration under a profiler)")
+    ap.add_argument("--no-autotune", action="store_true", help="use the planner's default configuration")
+    ap.add_argument("--no-grad", action="store_true", help="skip the gradient workload")
+    ap.add_argument("--grad-candidates", type=int, default=1024)
+    ap.add_argument("--no-c3", action="store_true", help="skip the uneven-segment batched search")
+    ap.add_argument("--c3-segments", type=int, default=16)
+    ap.add_argument("--c3-sky", type=int, default=8)
     return ap.parse_args()
 
 
@@ -77,6 +83,73 @@ def cpu_baseline(w, x, gaps, n_templates):
                       f"T=10d workload ({dt:.1f} s, numpy FP64, 1 thread)"}
 
 
+def grad_leg(rsf, synth, torch, dev, n_cand, steps=20):
+    """Gradient workload: T = 10 d at dt = 0.5 s (N = 1,728,000), n_cand
+    candidates spread around 64 points; forward 2F plus the hand-written
+    adjoint per candidate (candidates/s), and 20 gradient-ascent steps."""
+    w = synth.workload_c5()
+    rng = synth.streams(4)[5]
+    x = synth.gaussian_noise(rng, w.segment.n, 1.0)
+    plan = rsf.Plan(w)
+    tx = [torch.from_numpy(x).to(dev)]
+    theta = torch.from_numpy(synth.c5_candidates(w, plan.df)[:n_cand]).to(dev)
+    g1 = torch.ones(theta.shape[0], dtype=torch.float32, device=dev)
+    ws = plan.workspace(rsf.RSF_ENTRY_BACKWARD, 1, theta.shape[0], device=dev)
+    plan.backward(tx, [None], theta, g1, ws=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    F, g = plan.backward(tx, [None], theta, g1, ws=ws)
+    torch.cuda.synchronize()
+    t_one = time.perf_counter() - t0
+    T0 = w.segment.n * w.segment.dt
+    scale = torch.tensor([1 / T0, 1 / T0 ** 2, 1e-5, 1e-5], dtype=torch.float64, device=dev)
+    step = torch.tensor([1e-3 / T0, 1e-3 / T0 ** 2, 1e-7, 1e-7], dtype=torch.float64, device=dev)
+    th = theta.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        F, g = plan.backward(tx, [None], th, g1, ws=ws)
+        gs = g * scale
+        th = th + step * gs / gs.abs().amax(dim=1, keepdim=True).clamp_min(1e-30)
+    torch.cuda.synchronize()
+    t_steps = time.perf_counter() - t0
+    return {"workload": "T=10d dt=0.5s N=1728000, Dirichlet-16, synthetic noise",
+            "candidates": int(theta.shape[0]),
+            "candidates_per_s": round(theta.shape[0] / t_one, 1),
+            "refine_steps": steps, "refine_s": round(t_steps, 4)}
+
+
+def c3_leg(rsf, synth, torch, dev, n_seg, n_sky, n_fdot=16, k=10):
+    """Uneven segments: the first n_seg of the 64 segments (T_i ~ U[1, 30] d,
+    dt = 0.5 s, 5 % gaps, 7-smooth FFT lengths), n_sky sky positions x 16
+    spindowns each, per-segment top-10 (rsf_fstat_topk)."""
+    total_t = 0.0
+    templates = 0
+    samples = 0
+    for i in range(n_seg):
+        w = synth.workload_c3_segment(i, n_sky=max(n_sky, 1))
+        rng = np.random.default_rng([synth.SEED_BASE + 2, 1000 + i])
+        x = synth.zero_gaps(synth.gaussian_noise(rng, w.segment.n, 1.0), w.gaps[0])
+        plan = rsf.Plan(w)
+        tx = [torch.from_numpy(x).to(dev)]
+        tg = [torch.from_numpy(w.gaps[0]).to(dev)]
+        sky = torch.from_numpy(np.ascontiguousarray(w.skies[:n_sky])).to(dev)
+        fd = torch.from_numpy(np.ascontiguousarray(w.fdots[:n_fdot])).to(dev)
+        ws = plan.workspace(rsf.RSF_ENTRY_TOPK, n_sky, n_fdot, device=dev)
+        plan.topk(tx, tg, sky, fd, k=k, ws=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.topk(tx, tg, sky, fd, k=k, ws=ws)
+        torch.cuda.synchronize()
+        total_t += time.perf_counter() - t0
+        templates += n_sky * n_fdot
+        samples += w.segment.n
+        plan.close()
+    return {"workload": f"first {n_seg} of 64 uneven segments (mean N={samples // n_seg}), "
+                        f"{n_sky} sky x {n_fdot} fdot, top-{k} per segment",
+            "segment_templates": templates, "segment_templates_per_s": round(templates / total_t, 1)}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -94,7 +167,12 @@ def main():
     w = synth.workload_c2(n_fdot=a.n_fdot)
     rng = synth.streams(1)[0]
     x = synth.zero_gaps(synth.gaussian_noise(rng, w.segment.n, 1.0), w.gaps[0])
-    plan = rsf.Plan(w)
+    tuned = None
+    if a.no_autotune:
+        plan = rsf.Plan(w)
+    else:
+        from paper_0912_4255_amd import autotune
+        plan, tuned = autotune.tuned_plan(w)
     tx = [torch.from_numpy(x).to(dev)]
     tg = [torch.from_numpy(w.gaps[0]).to(dev)]
     sky = torch.from_numpy(np.ascontiguousarray(w.skies)).to(dev)
@@ -164,6 +242,9 @@ def main():
                                 "share": round(v[1] / sum(t for _, t in prof.values()), 4)}
                             for k, v in prof.items()}}
 
+    grad = None if a.no_grad else grad_leg(rsf, synth, torch, dev, a.grad_candidates)
+    c3 = None if a.no_c3 else c3_leg(rsf, synth, torch, dev, a.c3_segments, a.c3_sky)
+
     cpu = None
     if not a.no_cpu:
         cpu = cpu_baseline(w, x, w.gaps[0], a.cpu_templates)
@@ -177,6 +258,7 @@ def main():
                       "templates_per_step": n_t, "n_fft": Nf, "n_out": No,
                       "fft_factors": [plan.fft_l1, plan.fft_l2]},
            "plain_templates_per_s": round(plain_rate, 2),
+           "autotune": tuned, "grad": grad, "c3": c3,
            "roofline": roofline, "cpu_baseline": cpu}
     print(json.dumps(rec))
 

@@ -90,7 +90,7 @@ typedef struct rsf_plan_desc {
     int32_t kernel;                  /* RSF_KERNEL_LANCZOS or RSF_KERNEL_DIRICHLET */
     int32_t taps;                    /* even, 2..RSF_MAX_TAPS */
     int32_t storage;                 /* RSF_STORE_F32 or RSF_STORE_F16 (resampled series kept as half2) */
-    int32_t reserved;
+    int32_t fft_l1;                  /* first-pass FFT length L1 (a divisor of n_fft), 0 = automatic */
     int64_t n;                       /* samples per detector */
     double dt;                       /* sampling interval, s */
     double t_start;                  /* segment start after the ephemeris epoch, s */
@@ -138,6 +138,11 @@ typedef struct rsf_plan rsf_plan;
  * the library makes).  *out is NULL on failure. */
 int rsf_plan_create(rsf_plan** out, const rsf_plan_desc* desc);
 int rsf_plan_destroy(rsf_plan* plan);
+
+/* Batching knobs of RSF_MODE_BATCHED (0 = keep the automatic value):
+ * fb = spindowns sharing one read of the resampled series in the first FFT
+ * pass (1..16); templates = templates per FFT launch (1..256). */
+int rsf_plan_set_batching(rsf_plan* plan, int fb, int templates);
 
 /* Host outputs (any may be NULL): FFT length, first signed bin and number of
  * bins of the reported band, FFT factors (L1 = first-pass length over the
@@ -197,6 +202,25 @@ int rsf_fstat_point(const rsf_plan* plan, const rsf_segment* seg, const double* 
 int rsf_fstat_backward(const rsf_plan* plan, const rsf_segment* seg, const double* theta, int64_t n,
                        const float* g_twoF, float* twoF, double* g_theta,
                        void* ws, size_t ws_bytes, void* stream);
+
+/* A batched search captured once into a HIP graph and replayed with one
+ * launch (the template loop of Sec. IV.A as a single launchable unit).
+ * rsf_graph_create_fstat / _topk record exactly the work of rsf_fstat
+ * (mode RSF_MODE_BATCHED) / rsf_fstat_topk with the given, fixed pointers,
+ * on a private stream; nothing runs until rsf_graph_launch, which enqueues
+ * the whole graph on `stream`.  Every pointer argument must stay valid and
+ * unchanged while the graph exists; replays overwrite twoF / topk and the
+ * workspace.  Returns RSF_EHIP if capture or instantiation fails. */
+typedef struct rsf_graph rsf_graph;
+
+int rsf_graph_create_fstat(rsf_graph** out, const rsf_plan* plan, const rsf_segment* seg, const double* sky,
+                           int64_t n_sky, const double* fdot, int64_t n_fdot, float* twoF, void* ws,
+                           size_t ws_bytes);
+int rsf_graph_create_topk(rsf_graph** out, const rsf_plan* plan, const rsf_segment* seg, const double* sky,
+                          int64_t n_sky, const double* fdot, int64_t n_fdot, int k, rsf_topk_entry* topk,
+                          void* ws, size_t ws_bytes);
+int rsf_graph_launch(rsf_graph* graph, void* stream);
+int rsf_graph_destroy(rsf_graph* graph);
 
 /* Instrumentation (not part of the method): when enabled, every kernel the
  * plan launches is bracketed by hipEvents recorded on the launch stream.

@@ -16,9 +16,10 @@ RSF_ENTRY_RESAMPLE, RSF_ENTRY_FSTAT, RSF_ENTRY_POINT, RSF_ENTRY_BACKWARD, RSF_EN
 RSF_FLAG_DEGENERATE, RSF_FLAG_WINDOW = 1, 2
 
 EXPORTS = [
-    "rsf_plan_create", "rsf_plan_destroy", "rsf_plan_query", "rsf_workspace_size",
+    "rsf_plan_create", "rsf_plan_destroy", "rsf_plan_query", "rsf_plan_set_batching", "rsf_workspace_size",
     "rsf_resample", "rsf_fstat", "rsf_fstat_topk", "rsf_fstat_point", "rsf_fstat_backward",
     "rsf_get_flags", "rsf_last_error", "rsf_version", "rsf_profile_enable", "rsf_profile_read",
+    "rsf_graph_create_fstat", "rsf_graph_create_topk", "rsf_graph_launch", "rsf_graph_destroy",
 ]
 
 
@@ -33,7 +34,7 @@ class Ephemeris(C.Structure):
 
 class PlanDesc(C.Structure):
     _fields_ = [("n_det", C.c_int32), ("nfft_policy", C.c_int32), ("kernel", C.c_int32),
-                ("taps", C.c_int32), ("storage", C.c_int32), ("reserved", C.c_int32),
+                ("taps", C.c_int32), ("storage", C.c_int32), ("fft_l1", C.c_int32),
                 ("n", C.c_int64), ("dt", C.c_double), ("t_start", C.c_double), ("f_het", C.c_double),
                 ("f_lo", C.c_double), ("f_hi", C.c_double), ("eph", Ephemeris),
                 ("det", Detector * RSF_MAX_DET)]
@@ -75,6 +76,7 @@ def load(path=None):
     lib.rsf_plan_destroy.argtypes = [vp]
     lib.rsf_plan_query.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64),
                                    C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double)]
+    lib.rsf_plan_set_batching.argtypes = [vp, i32, i32]
     lib.rsf_workspace_size.argtypes = [vp, i32, i64, i64, i32, C.POINTER(sz)]
     lib.rsf_resample.argtypes = [vp, C.POINTER(Segment), vp, i64, C.POINTER(Resampled), vp, sz, vp]
     lib.rsf_fstat.argtypes = [vp, C.POINTER(Segment), vp, i64, vp, i64, i32, vp, vp, sz, vp]
@@ -82,6 +84,11 @@ def load(path=None):
     lib.rsf_fstat_point.argtypes = [vp, C.POINTER(Segment), vp, i64, vp, vp, sz, vp]
     lib.rsf_fstat_backward.argtypes = [vp, C.POINTER(Segment), vp, i64, vp, vp, vp, vp, sz, vp]
     lib.rsf_get_flags.argtypes = [vp, vp, C.POINTER(C.c_uint32), vp]
+    lib.rsf_graph_create_fstat.argtypes = [C.POINTER(vp), vp, C.POINTER(Segment), vp, i64, vp, i64, vp, vp, sz]
+    lib.rsf_graph_create_topk.argtypes = [C.POINTER(vp), vp, C.POINTER(Segment), vp, i64, vp, i64, i32, vp, vp,
+                                          sz]
+    lib.rsf_graph_launch.argtypes = [vp, vp]
+    lib.rsf_graph_destroy.argtypes = [vp]
     lib.rsf_profile_enable.argtypes = [vp, i32]
     lib.rsf_profile_read.argtypes = [vp, C.POINTER(KernelTime), i32, C.POINTER(C.c_int)]
     lib.rsf_last_error.restype = C.c_char_p

@@ -63,6 +63,10 @@ class Plan:
         self.n_fft, self.s_lo, self.n_out = n_fft.value, s_lo.value, n_out.value
         self.fft_l1, self.fft_l2, self.df = l1.value, l2.value, df.value
 
+    def set_batching(self, fb=0, templates=0):
+        """rsf_plan_set_batching: spindowns sharing a first-pass row, templates per launch."""
+        L.check(self.lib.rsf_plan_set_batching(self._p, fb, templates))
+
     def close(self):
         if self._p:
             self.lib.rsf_plan_destroy(self._p)
@@ -193,6 +197,36 @@ class Plan:
                                             _ptr(g_theta), _ptr(ws), ws.numel(), _stream()))
         return twoF, g_theta
 
+    def graph_fstat(self, xs, gaps, sky, fdot, out=None, ws=None):
+        """Capture a batched rsf_fstat call into a HIP graph; returns
+        (Graph, out).  Graph.launch() replays it on the current stream."""
+        _need_cuda(sky, torch.float64, "sky")
+        _need_cuda(fdot, torch.float64, "fdot")
+        n_sky, n_fdot = sky.shape[0], fdot.shape[0]
+        seg, keep = self.segment(xs, gaps)
+        dev = xs[0].device
+        if out is None:
+            out = torch.empty((n_sky * n_fdot, self.n_out), dtype=torch.float32, device=dev)
+        if ws is None:
+            ws = self.workspace(L.RSF_ENTRY_FSTAT, n_sky, n_fdot, L.RSF_MODE_BATCHED, device=dev)
+        h = C.c_void_p()
+        L.check(self.lib.rsf_graph_create_fstat(C.byref(h), self._p, C.byref(seg), _ptr(sky), n_sky, _ptr(fdot),
+                                                n_fdot, _ptr(out), _ptr(ws), ws.numel()))
+        return Graph(self.lib, h, (self, xs, gaps, keep, sky, fdot, out, ws)), out
+
+    def graph_topk(self, xs, gaps, sky, fdot, k=10, ws=None):
+        """Capture a rsf_fstat_topk call into a HIP graph; returns (Graph, values, indices)."""
+        n_sky, n_fdot = sky.shape[0], fdot.shape[0]
+        seg, keep = self.segment(xs, gaps)
+        dev = xs[0].device
+        res = torch.empty((k, 4), dtype=torch.int32, device=dev)
+        if ws is None:
+            ws = self.workspace(L.RSF_ENTRY_TOPK, n_sky, n_fdot, device=dev)
+        h = C.c_void_p()
+        L.check(self.lib.rsf_graph_create_topk(C.byref(h), self._p, C.byref(seg), _ptr(sky), n_sky, _ptr(fdot),
+                                               n_fdot, k, _ptr(res), _ptr(ws), ws.numel()))
+        return Graph(self.lib, h, (self, xs, gaps, keep, sky, fdot, res, ws)), res[:, 0].view(torch.float32), res[:, 1:]
+
     def profile(self, on=True):
         """Bracket every launch of this plan with hipEvents (instrumentation)."""
         L.check(self.lib.rsf_profile_enable(self._p, 1 if on else 0))
@@ -208,6 +242,28 @@ class Plan:
         f = C.c_uint32()
         L.check(self.lib.rsf_get_flags(self._p, _ptr(ws), C.byref(f), _stream()))
         return f.value
+
+
+class Graph:
+    """A captured HIP graph of one batched search (rsf_graph_*).  Holds
+    references to every buffer it uses."""
+
+    def __init__(self, lib, handle, keep):
+        self.lib, self._h, self._keep = lib, handle, keep
+
+    def launch(self):
+        L.check(self.lib.rsf_graph_launch(self._h, _stream()))
+
+    def close(self):
+        if self._h:
+            self.lib.rsf_graph_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class FStatFn(torch.autograd.Function):

@@ -1,0 +1,152 @@
+"""Autotuner for librsfstat plans.
+
+Times candidate configurations of the batched search on the GPU with
+synthetic noise of the plan's shape and keeps the fastest:
+
+* the FFT factorisation n_fft = L1 x L2 (rsf_plan_desc.fft_l1);
+* the number of spindowns sharing one read of the resampled series in the
+  first FFT pass, and the templates per FFT launch (rsf_plan_set_batching).
+
+Results are cached in a JSON file keyed by the GPU architecture and the plan
+shape (``$RSF_AUTOTUNE_CACHE``, default ``~/.cache/rsfstat/autotune.json``).
+``choose_taps`` picks the narrowest interpolation kernel whose 2F stays within
+a bound of a 32-tap reference over the central half of the band.
+"""
+import copy
+import json
+import os
+import time
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from . import synth
+from .api import Plan, plan_desc_from_workload
+
+
+def cache_path():
+    return os.environ.get("RSF_AUTOTUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "rsfstat", "autotune.json"))
+
+
+def _key(desc, n_fft):
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0] if torch.cuda.is_available() else "cpu"
+    return f"{arch}|n={desc.n}|nfft={n_fft}|det={desc.n_det}|kernel={desc.kernel}|taps={desc.taps}|store={desc.storage}"
+
+
+def _load():
+    try:
+        with open(cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _save(db):
+    path = cache_path()
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(db, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def _divisors(n, lo, hi):
+    return [d for d in range(max(1, lo), min(n, hi) + 1) if n % d == 0]
+
+
+def candidate_l1(plan, limit=8):
+    """First-pass lengths around the automatic choice that the planner accepts."""
+    n_fft = plan.n_fft
+    cands = _divisors(n_fft, max(8, plan.fft_l1 // 4), min(10240, plan.fft_l1 * 4))
+    cands.sort(key=lambda d: abs(np.log(d / plan.fft_l1)))
+    out = []
+    for d in cands:
+        desc = copy.copy(plan.desc)
+        desc.fft_l1 = d
+        try:
+            p = Plan(desc=desc)
+        except L.RsfError:
+            continue
+        out.append(p)
+        if len(out) >= limit:
+            break
+    return out
+
+
+def _time_plan(plan, xs, gaps, sky, fdot, reps=2):
+    ws = plan.workspace(L.RSF_ENTRY_FSTAT, sky.shape[0], fdot.shape[0], L.RSF_MODE_BATCHED)
+    out = torch.empty((sky.shape[0] * fdot.shape[0], plan.n_out), dtype=torch.float32, device="cuda")
+    plan.fstat(xs, gaps, sky, fdot, out=out, ws=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.fstat(xs, gaps, sky, fdot, out=out, ws=ws)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps / (sky.shape[0] * fdot.shape[0])
+
+
+def tune(workload, n_fdot=32, reps=2, use_cache=True, fbs=(2, 4, 8), templates=(16, 32), verbose=False):
+    """Best {fft_l1, fb, templates, s_per_template} for the workload's plan shape."""
+    base = Plan(workload)
+    key = _key(base.desc, base.n_fft)
+    db = _load() if use_cache else {}
+    if key in db:
+        return db[key]
+    rng = np.random.default_rng(0)
+    xs = [torch.from_numpy(synth.gaussian_noise(rng, base.n, d.sigma2)).cuda() for d in workload.detectors]
+    gaps = [None] * len(xs)
+    sky = torch.tensor([[1.0, 0.3]], dtype=torch.float64, device="cuda")
+    fdot = torch.from_numpy(synth.fdot_grid(n_fdot)).cuda()
+    best = None
+    for p in candidate_l1(base):
+        for fb in fbs:
+            for g in templates:
+                p.set_batching(fb, g)
+                t = _time_plan(p, xs, gaps, sky, fdot, reps)
+                if verbose:
+                    print(f"L1={p.fft_l1} L2={p.fft_l2} fb={fb} G={g}: {t * 1e6:.1f} us/template")
+                if best is None or t < best["s_per_template"]:
+                    best = {"fft_l1": p.fft_l1, "fft_l2": p.fft_l2, "fb": fb, "templates": g, "s_per_template": t}
+        p.close()
+    db[key] = best
+    if use_cache:
+        _save(db)
+    return best
+
+
+def tuned_plan(workload, **kw):
+    """A Plan built with the tuned factorisation and batching."""
+    best = tune(workload, **kw)
+    desc = plan_desc_from_workload(workload)
+    desc.fft_l1 = best["fft_l1"]
+    p = Plan(desc=desc)
+    p.set_batching(best["fb"], best["templates"])
+    return p, best
+
+
+def choose_taps(workload, candidates=(8, 12, 16, 24), bound=1e-2, ref_taps=32, n_fdot=2, seed=0):
+    """Smallest W (same kernel family) whose 2F over the central half of the
+    band is within `bound` * max(2F_ref, 4) of the ref_taps kernel, on
+    synthetic noise.  Returns (W, {W: max relative deviation})."""
+    rng = np.random.default_rng(seed)
+    xs = [torch.from_numpy(synth.gaussian_noise(rng, workload.segment.n, d.sigma2)).cuda()
+          for d in workload.detectors]
+    sky = torch.tensor([[2.0, -0.4]], dtype=torch.float64, device="cuda")
+    fdot = torch.from_numpy(synth.fdot_grid(n_fdot)).cuda()
+
+    def run(taps):
+        d = plan_desc_from_workload(workload)
+        d.taps = taps
+        return Plan(desc=d).fstat(xs, [None] * len(xs), sky, fdot).cpu().numpy()
+
+    ref = run(ref_taps)
+    n = ref.shape[1]
+    mid = slice(n // 4, 3 * n // 4)
+    dev = {}
+    for w in sorted(candidates):
+        got = run(w)
+        dev[w] = float(np.max(np.abs(got[:, mid] - ref[:, mid]) / np.maximum(ref[:, mid], 4.0)))
+    ok = [w for w in sorted(candidates) if dev[w] <= bound]
+    return (ok[0] if ok else max(candidates)), dev

@@ -133,10 +133,10 @@ struct Profiler {
     }
     ~Profiler() {
         for (auto& r : pending) {
-            hipEventDestroy(r.a);
-            hipEventDestroy(r.b);
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
         }
-        for (auto e : pool) hipEventDestroy(e);
+        for (auto e : pool) (void)hipEventDestroy(e);
     }
 };
 enum { K_RESAMPLE = 0, K_REDUCE = 1, K_PASS_A = 2, K_PASS_B = 3, K_POINT = 4, K_POINT_REDUCE = 5, K_TOPK = 6 };
@@ -152,6 +152,8 @@ struct rsf_plan {
     int64_t P;           // rows of the transposed series: ceil(n / LB)
     int n_groups;        // ceil(LA / 8)
     int n_cu;            // compute units (persistent second-pass grid)
+    int fb_override;     // spindowns sharing a row in the first pass (0 = automatic)
+    int g_override;      // templates per FFT launch (0 = automatic)
     FftStages stA, stB;
     float2* twA;
     float2* twA_hi;
@@ -178,6 +180,7 @@ struct WsLayout {
 // segments so that every launch carries a similar amount of work).
 int64_t batch_templates(const rsf_plan* p, int mode) {
     if (mode == RSF_MODE_PLAIN) return 1;
+    if (p->g_override > 0) return p->g_override;
     const int64_t scale = std::max<int64_t>(1, 3456000 / std::max<int64_t>(1, p->n));
     return std::min<int64_t>(64, 16 * scale);
 }
@@ -296,9 +299,9 @@ hipError_t timed(const rsf_plan* p, int kind, hipStream_t s, Fn fn) {
     Profiler* pr = p->prof;
     if (!pr || !pr->on) return fn();
     hipEvent_t a = pr->get(), b = pr->get();
-    if (a) hipEventRecord(a, s);
+    if (a) (void)hipEventRecord(a, s);
     hipError_t e = fn();
-    if (b) hipEventRecord(b, s);
+    if (b) (void)hipEventRecord(b, s);
     if (a && b) pr->pending.push_back({kind, a, b});
     return e;
 }
@@ -325,6 +328,7 @@ int rsf_plan_create(rsf_plan** out, const rsf_plan_desc* d) {
     if (d->taps < 2 || d->taps > RSF_MAX_TAPS || (d->taps & 1))
         return fail(RSF_EUNSUPPORTED, "taps must be even and in 2..%d", RSF_MAX_TAPS);
     if (d->storage != RSF_STORE_F32 && d->storage != RSF_STORE_F16) return fail(RSF_EINVAL, "unknown storage");
+    if (d->fft_l1 < 0) return fail(RSF_EINVAL, "fft_l1 must be 0 (automatic) or positive");
     if (d->nfft_policy != RSF_NFFT_TWICE && d->nfft_policy != RSF_NFFT_SMOOTH7)
         return fail(RSF_EINVAL, "unknown FFT length policy");
     const rsf_ephemeris& E = d->eph;
@@ -372,6 +376,7 @@ int rsf_plan_create(rsf_plan** out, const rsf_plan_desc* d) {
         if (p->n_fft % lb) continue;
         const int64_t la = p->n_fft / lb;
         if (la > la_max || fft_pass_a_lds((int)la) > (size_t)lds_max) continue;
+        if (d->fft_l1 > 0 && la != d->fft_l1) continue;
         FftStages sa, sb;
         if (!radix_plan((int)la, 1, kFftThreads, kFftEPT, &sa) ||
             !radix_plan((int)lb, kPassBCols / 2, kFftThreads, kPassBEPT, &sb) ||
@@ -387,8 +392,8 @@ int rsf_plan_create(rsf_plan** out, const rsf_plan_desc* d) {
     }
     if (best_la < 0) {
         delete p;
-        return fail(RSF_EUNSUPPORTED, "no two-pass factorisation of n_fft = %lld fits the LDS (%d bytes)",
-                    (long long)p->n_fft, lds_max);
+        return fail(RSF_EUNSUPPORTED, "no two-pass factorisation of n_fft = %lld (L1 = %d) fits the LDS (%d bytes)",
+                    (long long)p->n_fft, (int)d->fft_l1, lds_max);
     }
     p->LA = best_la;
     p->LB = best_lb;
@@ -404,7 +409,7 @@ int rsf_plan_create(rsf_plan** out, const rsf_plan_desc* d) {
     if (hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess ||
         p->n_cu <= 0)
         p->n_cu = 256;
-    if (lds_need > 65536) fft_set_lds_limits(lds_need);
+    if (lds_need > 65536) (void)fft_set_lds_limits(lds_need);
 
     // twiddle tables, built in FP64 and stored as FP32
     auto table = [](int64_t len, int64_t count, int64_t step) {
@@ -466,14 +471,23 @@ int rsf_plan_create(rsf_plan** out, const rsf_plan_desc* d) {
 
 int rsf_plan_destroy(rsf_plan* p) {
     if (!p) return RSF_OK;
-    hipFree(p->twA);
-    hipFree(p->twA_hi);
-    hipFree(p->twB);
-    hipFree(p->twB_hi);
-    hipFree(p->tw_lo);
-    hipFree(p->tw_hi);
+    (void)hipFree(p->twA);
+    (void)hipFree(p->twA_hi);
+    (void)hipFree(p->twB);
+    (void)hipFree(p->twB_hi);
+    (void)hipFree(p->tw_lo);
+    (void)hipFree(p->tw_hi);
     delete p->prof;
     delete p;
+    return RSF_OK;
+}
+
+int rsf_plan_set_batching(rsf_plan* p, int fb, int templates) {
+    if (!p) return fail(RSF_EINVAL, "plan is NULL");
+    if (fb < 0 || fb > 16 || templates < 0 || templates > 256)
+        return fail(RSF_EINVAL, "fb must be in 0..16 and templates in 0..256");
+    p->fb_override = fb;
+    p->g_override = templates;
     return RSF_OK;
 }
 
@@ -584,7 +598,7 @@ int run_fstat(const rsf_plan* p, const rsf_segment* seg, const double* sky, int6
     char* w = (char*)ws;
     unsigned int* flags = (unsigned int*)(w + L.flags);
     RSF_HIP(launch_fill_u32(flags, 16, 0u, s), "flags clear");
-    const int fb = (mode == RSF_MODE_BATCHED) ? 4 : 1;
+    const int fb = (mode == RSF_MODE_BATCHED) ? (p->fb_override > 0 ? p->fb_override : 4) : 1;
     float4* spill = (float4*)(w + L.spill);
     const int64_t spill_stride = (int64_t)p->n_groups * p->LB * kPassBCols;
     const bool f16 = p->d.storage == RSF_STORE_F16;
@@ -806,6 +820,84 @@ int rsf_fstat_backward(const rsf_plan* p, const rsf_segment* seg, const double* 
                        const float* g_twoF, float* twoF, double* g_theta, void* ws, size_t ws_bytes,
                        void* stream) {
     return point_common(p, seg, theta, n, g_twoF, twoF, g_theta, ws, ws_bytes, stream, true);
+}
+
+}  // extern "C"
+
+struct rsf_graph {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+namespace {
+template <typename Fn>
+int capture_graph(rsf_graph** out, const rsf_plan* p, Fn body) {
+    if (!out) return fail(RSF_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!p) return fail(RSF_EINVAL, "plan is NULL");
+    hipStream_t cs = nullptr;
+    RSF_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "hipStreamCreate");
+    const bool prof_on = p->prof->on;
+    p->prof->on = false;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        p->prof->on = prof_on;
+        (void)hipStreamDestroy(cs);
+        return hip_fail(e, "hipStreamBeginCapture");
+    }
+    const int rc = body(cs);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(cs, &g);
+    p->prof->on = prof_on;
+    (void)hipStreamDestroy(cs);
+    if (rc != RSF_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    *out = new rsf_graph{g, x};
+    return RSF_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int rsf_graph_create_fstat(rsf_graph** out, const rsf_plan* p, const rsf_segment* seg, const double* sky,
+                           int64_t n_sky, const double* fdot, int64_t n_fdot, float* twoF, void* ws,
+                           size_t ws_bytes) {
+    if (!twoF) return fail(RSF_EINVAL, "twoF is NULL");
+    return capture_graph(out, p, [&](hipStream_t cs) {
+        return run_fstat(p, seg, sky, n_sky, fdot, n_fdot, RSF_MODE_BATCHED, twoF, 0, nullptr, ws, ws_bytes, cs);
+    });
+}
+
+int rsf_graph_create_topk(rsf_graph** out, const rsf_plan* p, const rsf_segment* seg, const double* sky,
+                          int64_t n_sky, const double* fdot, int64_t n_fdot, int k, rsf_topk_entry* topk,
+                          void* ws, size_t ws_bytes) {
+    if (!topk) return fail(RSF_EINVAL, "topk is NULL");
+    return capture_graph(out, p, [&](hipStream_t cs) {
+        return run_fstat(p, seg, sky, n_sky, fdot, n_fdot, RSF_MODE_BATCHED, nullptr, k, topk, ws, ws_bytes, cs);
+    });
+}
+
+int rsf_graph_launch(rsf_graph* g, void* stream) {
+    if (!g) return fail(RSF_EINVAL, "graph is NULL");
+    RSF_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream), "hipGraphLaunch");
+    return RSF_OK;
+}
+
+int rsf_graph_destroy(rsf_graph* g) {
+    if (!g) return RSF_OK;
+    (void)hipGraphExecDestroy(g->exec);
+    (void)hipGraphDestroy(g->graph);
+    delete g;
+    return RSF_OK;
 }
 
 int rsf_profile_enable(rsf_plan* p, int on) {

@@ -70,6 +70,7 @@ def test_invalid_descriptors_rejected_before_device_use(lib):
     d = plan_desc_from_workload(w); d.f_het = float("nan"); cases.append((d, L.RSF_EINVAL))
     d = plan_desc_from_workload(w); d.n = 1001; cases.append((d, L.RSF_EUNSUPPORTED))   # 2002 = 2 * 7 * 11 * 13
     d = plan_desc_from_workload(w); d.f_lo, d.f_hi = 99.0, 99.2; cases.append((d, L.RSF_EINVAL))
+    d = plan_desc_from_workload(w); d.fft_l1 = -5; cases.append((d, L.RSF_EINVAL))
     for desc, code in cases:
         p = C.c_void_p()
         assert lib.rsf_plan_create(C.byref(p), C.byref(desc)) == code, lib.rsf_last_error()

@@ -1,0 +1,64 @@
+"""Tuning knobs and the autotuner: any accepted factorisation and batching
+choice computes the same statistic (bitwise for batching, within the FP32
+tolerance against the oracle for factorisations)."""
+import numpy as np
+import pytest
+
+from oracle import fstat as of
+from paper_0912_4255_amd import synth
+from tests.helpers import make_inputs, to_gpu, twoF_tol
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup():
+    w = synth.small_workload(n=21600, dt=4.0, kernel=synth.KERNEL_DIRICHLET, taps=16)
+    xs, gaps = make_inputs(w, seed=11)
+    return w, xs, gaps
+
+
+def test_batching_knobs_do_not_change_results(gpu_lib):
+    import torch
+    w, xs, gaps = _setup()
+    plan = gpu_lib.Plan(w)
+    tx, tg = to_gpu(xs, gaps)
+    sky = torch.tensor([[1.0, 0.2], [2.0, -0.3]], dtype=torch.float64).cuda()
+    fd = torch.from_numpy(synth.fdot_grid(7)).cuda()
+    ref = plan.fstat(tx, tg, sky, fd).cpu().numpy()
+    for fb, g in [(1, 1), (2, 3), (8, 16), (16, 256)]:
+        plan.set_batching(fb, g)
+        assert np.array_equal(plan.fstat(tx, tg, sky, fd).cpu().numpy(), ref), (fb, g)
+
+
+def test_forced_factorisations_match_oracle(gpu_lib):
+    import torch
+    from paper_0912_4255_amd import autotune
+    w, xs, gaps = _setup()
+    base = gpu_lib.Plan(w)
+    plans = autotune.candidate_l1(base, limit=4)
+    assert len(plans) >= 2
+    tx, tg = to_gpu(xs, gaps)
+    sky = torch.tensor([[1.0, 0.2]], dtype=torch.float64).cuda()
+    fd = torch.tensor([-3e-10], dtype=torch.float64).cuda()
+    rss = [of.resample(xs[0], gaps[0], w.segment, 1.0, 0.2, w.eph, w.detectors[0], w.kernel, w.taps)]
+    ref = of.fstat_band(rss, w.detectors, -3e-10, base.n_fft, base.s_lo, base.n_out)
+    for p in plans:
+        got = p.fstat(tx, tg, sky, fd).cpu().numpy()[0]
+        assert np.all(np.abs(got - ref) <= twoF_tol(ref)), (p.fft_l1, p.fft_l2)
+
+
+def test_autotune_and_taps_choice(gpu_lib, tmp_path, monkeypatch):
+    from paper_0912_4255_amd import autotune
+    monkeypatch.setenv("RSF_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    w, xs, gaps = _setup()
+    best = autotune.tune(w, n_fdot=8, reps=1, fbs=(2, 4), templates=(8, 16))
+    assert best["fft_l1"] * best["fft_l2"] == 2 * w.segment.n
+    assert (tmp_path / "tune.json").exists()
+    again = autotune.tune(w)          # served from the cache
+    assert again == best
+    plan, _ = autotune.tuned_plan(w)
+    assert plan.fft_l1 == best["fft_l1"]
+    wl = synth.small_workload(n=21600, dt=4.0, kernel=synth.KERNEL_LANCZOS, taps=8)
+    W, dev = autotune.choose_taps(wl, candidates=(4, 8, 16), bound=5e-2)
+    assert W in (4, 8, 16)
+    assert dev[16] <= dev[4]
