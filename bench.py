@@ -41,21 +41,23 @@ def parse():
     ap.add_argument("--n-fdot", type=int, default=1000)
     ap.add_argument("--plain-templates", type=int, default=32)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-templates", type=int, default=2)
+    ap.add_argument("--cpu-templates", type=int, default=3)
     ap.add_argument("--copy-check", action="store_true",
                     help="also run one 1 GiB device-to-device copy (counter calibration under a profiler)")
     ap.add_argument("--no-autotune", action="store_true", help="use the planner's default configuration")
     ap.add_argument("--no-grad", action="store_true", help="skip the gradient workload")
     ap.add_argument("--grad-candidates", type=int, default=1024)
     ap.add_argument("--no-c3", action="store_true", help="skip the uneven-segment batched search")
-    ap.add_argument("--c3-segments", type=int, default=16)
+    ap.add_argument("--c3-segments", type=int, default=64)
     ap.add_argument("--c3-sky", type=int, default=8)
     return ap.parse_args()
 
 
-def cpu_baseline(w, x, gaps, n_templates):
+def cpu_baseline(w, x, gaps, n_templates, n_step):
     """The FP64 oracle, as it stands, on a bounded sample: resampling for the
-    sky position plus n_templates full-band templates, single thread."""
+    sky position, then n_templates full-band templates, single thread.  The
+    rate is scaled to a step of n_step templates: one resampling plus n_step
+    templates at the measured per-template time."""
     try:
         from threadpoolctl import threadpool_limits
     except ImportError:  # pragma: no cover
@@ -68,19 +70,22 @@ def cpu_baseline(w, x, gaps, n_templates):
         t0 = time.perf_counter()
         alpha, delta = w.skies[0]
         rss = of.resample_all([x], [gaps], w.segment, alpha, delta, w.eph, w.detectors, w.kernel, w.taps)
+        t_rs = time.perf_counter() - t0
         n_fft = of.fft_length(w.segment.n, w.nfft_policy)
         df = 1.0 / (n_fft * w.segment.dt)
         s_lo = int(round((w.f_lo - w.segment.f_het) / df))
         n_out = int(round((w.f_hi - w.f_lo) / df))
+        t1 = time.perf_counter()
         for i in range(n_templates):
             of.fstat_band(rss, w.detectors, float(w.fdots[i]), n_fft, s_lo, n_out)
-        dt = time.perf_counter() - t0
+        t_tp = (time.perf_counter() - t1) / n_templates
     finally:
         if ctx:
             ctx.__exit__(None, None, None)
-    return {"value": n_templates / dt, "unit": "templates/s", "cores": 1, "kind": "oracle",
-            "sample": f"resampling of 1 sky position + {n_templates} full-band templates of the "
-                      f"T=10d workload ({dt:.1f} s, numpy FP64, 1 thread)"}
+    return {"value": n_step / (t_rs + n_step * t_tp), "unit": "templates/s", "cores": 1, "kind": "oracle",
+            "sample": f"T=10d workload, numpy FP64, 1 thread: resampling of 1 sky position ({t_rs:.1f} s) + "
+                      f"{n_templates} full-band template(s) ({t_tp:.1f} s each); rate for a step of "
+                      f"{n_step} templates = {n_step} / (resampling + {n_step} x template)"}
 
 
 def grad_leg(rsf, synth, torch, dev, n_cand, steps=20):
@@ -218,26 +223,31 @@ def main():
     torch.cuda.synchronize()
     plain_rate = n_p / (time.perf_counter() - tp0)
 
-    # roofline of the dominant kernel: algorithmic bytes per launch / mean duration
+    # roofline of the dominant kernel: algorithmic bytes over the timed region
+    # (per-launch bytes summed over its launches) / summed launch durations,
+    # i.e. mean bytes per launch / mean launch duration
     N, Nf, No = w.segment.n, plan.n_fft, plan.n_out
-    G = min(n_t, 16)
-    fb = 4
-    bytes_per_launch = {
-        # inputs read once per group of fb spindowns (z~ 8 B + a, b, t_m 4 B each), both spectra spilled
-        "rsf_fft_pass_a_k": (G / fb) * 20 * N + G * 16 * Nf,
+    fb, G, _ = plan.batching(1, n_t)
+    sizes = [min(G, n_t - f0) for f0 in range(0, n_t, G)]
+    total_bytes = {
+        # resampled row (z~ 8 B + a, b, t_m 4 B each) read once per group of
+        # fb spindowns, both spectra (2 x 8 B per FFT sample) spilled
+        "rsf_fft_pass_a_k": sum(-(-g // fb) * 20 * N + g * 16 * Nf for g in sizes),
         # both spectra read back, 2F written for the reported band
-        "rsf_fft_pass_b_k": G * (16 * Nf + 4 * No),
-        # series read, resampled series + t_m written
+        "rsf_fft_pass_b_k": sum(g * (16 * Nf + 4 * No) for g in sizes),
+        # series read, resampled series (z~ 8 B, a, b, t_m) written
         "rsf_resample_k": 8 * N + 20 * N,
     }
-    kern = {k: v for k, v in prof.items() if k in bytes_per_launch}
+    kern = {k: v for k, v in prof.items() if k in total_bytes}
     dom = max(kern, key=lambda k: kern[k][1])
     launches, total_ms = kern[dom]
     avg_s = total_ms / launches / 1e3
-    achieved = bytes_per_launch[dom] / avg_s / 1e9
+    bytes_per_launch = total_bytes[dom] * a.steps / launches
+    achieved = bytes_per_launch / avg_s / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                 "kernel": dom, "avg_launch_us": round(avg_s * 1e6, 2),
+                "bytes_per_launch": int(bytes_per_launch), "templates_per_launch": G, "fb": fb,
                 "kernels": {k: {"launches": v[0], "avg_us": round(v[1] / v[0] * 1e3, 2),
                                 "share": round(v[1] / sum(t for _, t in prof.values()), 4)}
                             for k, v in prof.items()}}
@@ -247,7 +257,7 @@ def main():
 
     cpu = None
     if not a.no_cpu:
-        cpu = cpu_baseline(w, x, w.gaps[0], a.cpu_templates)
+        cpu = cpu_baseline(w, x, w.gaps[0], a.cpu_templates, n_t)
 
     rec = {"metric": "F-stat templates/s at T=10d, 2Hz band (batched; plain and %HBM alongside)",
            "value": round(value, 2), "unit": "templates/s", "n_gpus": 1, "steps": a.steps,

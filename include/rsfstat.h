@@ -86,7 +86,7 @@ typedef struct rsf_ephemeris {
 
 typedef struct rsf_plan_desc {
     int32_t n_det;                   /* 1..RSF_MAX_DET */
-    int32_t nfft_policy;             /* RSF_NFFT_TWICE: 2n; RSF_NFFT_SMOOTH7: smallest 2^a3^b5^c7^d >= 2n */
+    int32_t nfft_policy;             /* RSF_NFFT_TWICE: 2n; RSF_NFFT_SMOOTH7: smallest even 2^a3^b5^c7^d >= 2n */
     int32_t kernel;                  /* RSF_KERNEL_LANCZOS or RSF_KERNEL_DIRICHLET */
     int32_t taps;                    /* even, 2..RSF_MAX_TAPS */
     int32_t storage;                 /* RSF_STORE_F32 or RSF_STORE_F16 (resampled series kept as half2) */
@@ -143,6 +143,13 @@ int rsf_plan_destroy(rsf_plan* plan);
  * fb = spindowns sharing one read of the resampled series in the first FFT
  * pass (1..16); templates = templates per FFT launch (1..256). */
 int rsf_plan_set_batching(rsf_plan* plan, int fb, int templates);
+
+/* Effective batching of rsf_fstat / rsf_fstat_topk for n_sky x n_fdot
+ * templates in `mode`: spindowns sharing a first-pass row (*fb), templates
+ * per FFT launch (*templates) and sky positions resampled per launch
+ * (*skies).  Host outputs, any may be NULL. */
+int rsf_plan_batching(const rsf_plan* plan, int64_t n_sky, int64_t n_fdot, int mode, int32_t* fb,
+                      int32_t* templates, int32_t* skies);
 
 /* Host outputs (any may be NULL): FFT length, first signed bin and number of
  * bins of the reported band, FFT factors (L1 = first-pass length over the

@@ -54,10 +54,14 @@ NFFT_SMOOTH7 = 1
 
 
 def fft_length(n, policy):
+    """Zero-padded length of step 5 (Sec. III.A.2): twice the series, or the
+    smallest even 7-smooth length >= 2n.  Even, so that a band reaching the
+    Nyquist edges f_het +- 1/(2 dt) starts and ends on bins; an even
+    7-smooth m >= 2n is 2j with j 7-smooth and j >= n."""
     if policy == NFFT_TWICE:
         return 2 * n
     if policy == NFFT_SMOOTH7:
-        return next_7smooth(2 * n)
+        return 2 * next_7smooth(n)
     raise ValueError("unknown FFT length policy")
 
 

@@ -67,6 +67,12 @@ class Plan:
         """rsf_plan_set_batching: spindowns sharing a first-pass row, templates per launch."""
         L.check(self.lib.rsf_plan_set_batching(self._p, fb, templates))
 
+    def batching(self, n_sky=1, n_fdot=1, mode=L.RSF_MODE_BATCHED):
+        """rsf_plan_batching: effective (fb, templates per launch, skies per launch)."""
+        fb, g, sk = C.c_int32(), C.c_int32(), C.c_int32()
+        L.check(self.lib.rsf_plan_batching(self._p, n_sky, n_fdot, mode, C.byref(fb), C.byref(g), C.byref(sk)))
+        return fb.value, g.value, sk.value
+
     def close(self):
         if self._p:
             self.lib.rsf_plan_destroy(self._p)

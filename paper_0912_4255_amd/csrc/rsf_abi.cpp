@@ -185,6 +185,12 @@ int64_t batch_templates(const rsf_plan* p, int mode) {
     return std::min<int64_t>(64, 16 * scale);
 }
 
+// Spindowns sharing one read of a resampled row in the first FFT pass.
+int first_pass_share(const rsf_plan* p, int mode) {
+    if (mode == RSF_MODE_PLAIN) return 1;
+    return p->fb_override > 0 ? p->fb_override : 4;
+}
+
 int64_t batch_skies(int64_t n_sky, int64_t n_fdot, int64_t G, int mode) {
     if (mode == RSF_MODE_PLAIN) return 1;
     const int64_t per = std::max<int64_t>(1, (4 * G) / std::max<int64_t>(1, n_fdot));
@@ -345,7 +351,8 @@ int rsf_plan_create(rsf_plan** out, const rsf_plan_desc* d) {
     p->d = *d;
     p->prof = new Profiler();
     p->n = d->n;
-    p->n_fft = (d->nfft_policy == RSF_NFFT_TWICE) ? 2 * d->n : next_7smooth(2 * d->n);
+    // even, so that a band reaching f_het +- 1/(2 dt) has its edges on bins
+    p->n_fft = (d->nfft_policy == RSF_NFFT_TWICE) ? 2 * d->n : 2 * next_7smooth(d->n);
     if (!is_7smooth(p->n_fft)) {
         delete p;
         return fail(RSF_EUNSUPPORTED, "FFT length %lld has a prime factor above 7", (long long)(2 * d->n));
@@ -491,6 +498,18 @@ int rsf_plan_set_batching(rsf_plan* p, int fb, int templates) {
     return RSF_OK;
 }
 
+int rsf_plan_batching(const rsf_plan* p, int64_t n_sky, int64_t n_fdot, int mode, int32_t* fb,
+                      int32_t* templates, int32_t* skies) {
+    if (!p) return fail(RSF_EINVAL, "plan is NULL");
+    if (n_sky < 1 || n_fdot < 1) return fail(RSF_EINVAL, "n_sky and n_fdot must be positive");
+    if (mode != RSF_MODE_PLAIN && mode != RSF_MODE_BATCHED) return fail(RSF_EINVAL, "unknown mode");
+    const int64_t G = batch_templates(p, mode);
+    if (fb) *fb = first_pass_share(p, mode);
+    if (templates) *templates = (int32_t)G;
+    if (skies) *skies = (int32_t)batch_skies(n_sky, n_fdot, G, mode);
+    return RSF_OK;
+}
+
 int rsf_plan_query(const rsf_plan* p, int64_t* n_fft, int64_t* bin_lo, int64_t* n_out, int32_t* l1,
                    int32_t* l2, double* df) {
     if (!p) return fail(RSF_EINVAL, "plan is NULL");
@@ -598,7 +617,7 @@ int run_fstat(const rsf_plan* p, const rsf_segment* seg, const double* sky, int6
     char* w = (char*)ws;
     unsigned int* flags = (unsigned int*)(w + L.flags);
     RSF_HIP(launch_fill_u32(flags, 16, 0u, s), "flags clear");
-    const int fb = (mode == RSF_MODE_BATCHED) ? (p->fb_override > 0 ? p->fb_override : 4) : 1;
+    const int fb = first_pass_share(p, mode);
     float4* spill = (float4*)(w + L.spill);
     const int64_t spill_stride = (int64_t)p->n_groups * p->LB * kPassBCols;
     const bool f16 = p->d.storage == RSF_STORE_F16;

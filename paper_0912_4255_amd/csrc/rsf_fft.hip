@@ -23,7 +23,7 @@ namespace rsf {
 
 namespace {
 constexpr int kNT = kFftThreads;
-constexpr int kEPT = kFftEPT;  // max LA (pass A) or 8 LB (pass B) = kNT * kEPT = 10240
+constexpr int kEPT = kFftEPT;
 }  // namespace
 
 // Integrand of one detector for one sample (see the header comment).
@@ -61,7 +61,7 @@ __device__ __forceinline__ void accumulate_integrand(cp& y, float4 m, float tmf,
 }
 
 // Inputs of one row held per thread: n_a = tid + q * kNT, q < kInPer (P <= LA/2 <= 5120).
-constexpr int kInPer = (kNT * kEPT / 2 + kNT - 1) / kNT;
+constexpr int kInPer = (kFftMaxLen / 2 + kNT - 1) / kNT;
 
 __global__ __launch_bounds__(kNT) void rsf_fft_pass_a_k(PassAArgs A) {
     extern __shared__ float4 lds[];
@@ -211,7 +211,7 @@ __global__ __launch_bounds__(kNT) void rsf_fft_pass_b_k(PassBArgs B) {
     }
 }
 
-int fft_pass_max_elems() { return kNT * kEPT; }
+int fft_pass_max_elems() { return kFftMaxLen < kNT * kEPT ? kFftMaxLen : kNT * kEPT; }
 
 size_t fft_pass_a_lds(int LA) { return (size_t)LA * sizeof(float4) + (32 + (LA + 31) / 32) * sizeof(float2); }
 

@@ -17,7 +17,11 @@ constexpr int kMaxDet = 4;
 constexpr int kPassBCols = 8;       // columns per second-pass workgroup (8 x 16 B = 128 B rows)
 constexpr int kTwSplitBits = 12;    // inter-pass twiddle W_N^m = hi[m >> 12] * lo[m & 4095]
 constexpr int kFftThreads = 512;    // threads of an FFT-pass workgroup
-constexpr int kFftEPT = 20;         // complex pairs held per thread in a stage (L * B <= 10240)
+// complex pairs held per thread in a first-pass stage: 21 lets radix 3 and 7
+// stages run 7 and 3 butterflies per thread (lengths with a factor 7 up to
+// 10752); radices 2, 4, 5, 6, 8 ... 16 hold the same number as at 20
+constexpr int kFftEPT = 21;
+constexpr int kFftMaxLen = 10240;   // longest first-pass transform (10240 x 16 B = 160 KiB of LDS)
 
 // Butterflies of radix R one thread holds in a stage: never more than EPT
 // elements, so a stage of radix R covers at most fft_radix_cap(R) butterflies

@@ -54,6 +54,7 @@ def test_null_arguments_rejected_without_gpu(lib):
     b = C.c_size_t()
     assert lib.rsf_workspace_size(None, 0, 1, 1, 0, C.byref(b)) == L.RSF_EINVAL
     assert lib.rsf_fstat(None, None, None, 1, None, 1, 0, None, None, 0, None) == L.RSF_EINVAL
+    assert lib.rsf_plan_batching(None, 1, 1, 0, None, None, None) == L.RSF_EINVAL
 
 
 def test_invalid_descriptors_rejected_before_device_use(lib):

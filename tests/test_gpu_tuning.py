@@ -47,6 +47,28 @@ def test_forced_factorisations_match_oracle(gpu_lib):
         assert np.all(np.abs(got - ref) <= twoF_tol(ref)), (p.fft_l1, p.fft_l2)
 
 
+@pytest.mark.parametrize("n,l1", [(31360, 7840), (38400, 9600)])
+def test_long_first_pass_with_radix7_and_radix3(gpu_lib, n, l1):
+    """First-pass lengths 7840 = 16 x 10 x 7 x 7 and 9600 = 10 x 5 x 4 x 4 x 4 x 3,
+    whose radix-7 and radix-3 stages run 3 and 7 butterflies per thread."""
+    import torch
+    from paper_0912_4255_amd.api import plan_desc_from_workload
+    w = synth.small_workload(n=n, dt=4.0, kernel=synth.KERNEL_DIRICHLET, taps=16)
+    xs, gaps = make_inputs(w, seed=12)
+    d = plan_desc_from_workload(w)
+    d.fft_l1 = l1
+    plan = gpu_lib.Plan(desc=d)
+    assert (plan.fft_l1, plan.fft_l2) == (l1, 2 * n // l1)
+    tx, tg = to_gpu(xs, gaps)
+    sky = torch.tensor([[0.7, -0.5]], dtype=torch.float64).cuda()
+    fd = torch.tensor([-4e-10, 0.0], dtype=torch.float64).cuda()
+    got = plan.fstat(tx, tg, sky, fd).cpu().numpy()
+    rss = [of.resample(xs[0], gaps[0], w.segment, 0.7, -0.5, w.eph, w.detectors[0], w.kernel, w.taps)]
+    for i, f in enumerate((-4e-10, 0.0)):
+        ref = of.fstat_band(rss, w.detectors, f, plan.n_fft, plan.s_lo, plan.n_out)
+        assert np.all(np.abs(got[i] - ref) <= twoF_tol(ref)), (l1, i)
+
+
 def test_autotune_and_taps_choice(gpu_lib, tmp_path, monkeypatch):
     from paper_0912_4255_amd import autotune
     monkeypatch.setenv("RSF_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))

@@ -214,3 +214,29 @@ def test_fstat_bins_equal_fft_bins():
     assert np.max(np.abs(Fb - F[np.mod(bins, NFFT)])) < 1e-9 * max(1.0, F.max())
     fp = of.fstat_point([rs], [DET_H], SEG, SEG.f_het + 123 * DF, -7e-10)
     assert abs(fp - F[123]) < 1e-9 * max(1.0, F[123])
+
+
+def test_smooth7_length_is_least_even_smooth_and_full_band_fits():
+    """The 7-smooth policy returns the least even 2^a3^b5^c7^d >= 2n (brute
+    force), and a band spanning the whole data band [f_het - 1/(2dt),
+    f_het + 1/(2dt)) then maps onto whole bins for every uneven segment
+    length of the batched workload."""
+    from paper_0912_4255_amd.synth import c3_segment_lengths
+
+    def smooth(m):
+        for p in (2, 3, 5, 7):
+            while m % p == 0:
+                m //= p
+        return m == 1
+
+    for n in list(range(1, 400)) + [10007, 86413]:
+        m = of.fft_length(n, of.NFFT_SMOOTH7)
+        want = next(k for k in range(2 * n, 4 * n + 16) if k % 2 == 0 and smooth(k))
+        assert m == want, n
+    for n in c3_segment_lengths():
+        m = of.fft_length(n, of.NFFT_SMOOTH7)
+        df = 1.0 / (m * 0.5)
+        s_lo = int(round(-1.0 / df))
+        n_out = int(round(2.0 / df))
+        assert n_out == m
+        of.band_indices(m, s_lo, n_out)  # raises if outside the data band
