@@ -53,6 +53,37 @@ def parse():
     return ap.parse_args()
 
 
+KERNEL_SOURCES = ("rsf_fft.hip", "rsf_device.h", "rsf_params.h", "rsf_resample.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_fft_T10d.md")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_0912_4255_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic(kernel, config):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by the copy-kernel calibration),
+    or None when the summary is missing, was taken on another configuration,
+    or the kernel sources have changed since."""
+    try:
+        lines = open(TRAFFIC_FILE).read().splitlines()
+    except OSError:
+        return None
+    src = kernel_source_hash()
+    for ln in lines:
+        f = ln.strip().strip("`").split()
+        # traffic <kernel> <bytes per launch> src=<hash> cfg=<L1>x<L2>,fb<fb>,g<G>
+        if len(f) == 5 and f[0] == "traffic" and f[1] == kernel and f[3] == "src=" + src and f[4] == "cfg=" + config:
+            return float(f[2])
+    return None
+
+
 def cpu_baseline(w, x, gaps, n_templates, n_step):
     """The FP64 oracle, as it stands, on a bounded sample: resampling for the
     sky position, then n_templates full-band templates, single thread.  The
@@ -211,17 +242,20 @@ def main():
     ms_step = (t1 - t0) * 1e3 / a.steps
     value = n_t * a.steps / (t1 - t0)
 
-    # plain per-template path on a subset of the spindowns
+    # plain per-template path on a subset of the spindowns (0 skips it)
     n_p = min(a.plain_templates, n_t)
-    fd_p = fd[:n_p].contiguous()
-    out_p = torch.empty((n_p, plan.n_out), dtype=torch.float32, device=dev)
-    ws_p = plan.workspace(rsf.RSF_ENTRY_FSTAT, 1, n_p, rsf.RSF_MODE_PLAIN, device=dev)
-    plan.fstat(tx, tg, sky, fd_p, mode=rsf.RSF_MODE_PLAIN, out=out_p, ws=ws_p)
-    torch.cuda.synchronize()
-    tp0 = time.perf_counter()
-    plan.fstat(tx, tg, sky, fd_p, mode=rsf.RSF_MODE_PLAIN, out=out_p, ws=ws_p)
-    torch.cuda.synchronize()
-    plain_rate = n_p / (time.perf_counter() - tp0)
+    plain_rate = None
+    if n_p > 0:
+        fd_p = fd[:n_p].contiguous()
+        out_p = torch.empty((n_p, plan.n_out), dtype=torch.float32, device=dev)
+        ws_p = plan.workspace(rsf.RSF_ENTRY_FSTAT, 1, n_p, rsf.RSF_MODE_PLAIN, device=dev)
+        plan.fstat(tx, tg, sky, fd_p, mode=rsf.RSF_MODE_PLAIN, out=out_p, ws=ws_p)
+        torch.cuda.synchronize()
+        tp0 = time.perf_counter()
+        plan.fstat(tx, tg, sky, fd_p, mode=rsf.RSF_MODE_PLAIN, out=out_p, ws=ws_p)
+        torch.cuda.synchronize()
+        plain_rate = round(n_p / (time.perf_counter() - tp0), 2)
+        del out_p, ws_p
 
     # roofline of the dominant kernel: algorithmic bytes over the timed region
     # (per-launch bytes summed over its launches) / summed launch durations,
@@ -244,8 +278,11 @@ def main():
     avg_s = total_ms / launches / 1e3
     bytes_per_launch = total_bytes[dom] * a.steps / launches
     achieved = bytes_per_launch / avg_s / 1e9
+    cfg = f"{plan.fft_l1}x{plan.fft_l2},fb{fb},g{G}"
+    traffic = committed_traffic(dom, cfg)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "traffic_unit": "bytes/launch", "config": cfg, "kernel_src": kernel_source_hash(),
                 "kernel": dom, "avg_launch_us": round(avg_s * 1e6, 2),
                 "bytes_per_launch": int(bytes_per_launch), "templates_per_launch": G, "fb": fb,
                 "kernels": {k: {"launches": v[0], "avg_us": round(v[1] / v[0] * 1e3, 2),
@@ -267,7 +304,7 @@ def main():
                                   "Dirichlet-16, N_fft=6912000, band [100,102) Hz",
                       "templates_per_step": n_t, "n_fft": Nf, "n_out": No,
                       "fft_factors": [plan.fft_l1, plan.fft_l2]},
-           "plain_templates_per_s": round(plain_rate, 2),
+           "plain_templates_per_s": plain_rate,
            "autotune": tuned, "grad": grad, "c3": c3,
            "roofline": roofline, "cpu_baseline": cpu}
     print(json.dumps(rec))
