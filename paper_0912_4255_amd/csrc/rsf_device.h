@@ -254,15 +254,67 @@ struct TwLds {
     __device__ __forceinline__ float2 operator()(int m) const { return c_mul(lo[m & 31], hi[m >> 5]); }
 };
 
-template <int R, int NT, int EPT, int B, typename TW>
-__device__ __forceinline__ void stockham_stage(cp* __restrict__ s, int L, int Ns, const TW& tw) {
-    constexpr int MAXB = (EPT / R) > 0 ? (EPT / R) : 1;  // the planner keeps L*B/R <= MAXB*NT
-    const int tid = threadIdx.x;
+// threadIdx.x behind an empty asm: offsets derived from it are recomputed
+// at each use instead of being hoisted out of the callers' loops for every
+// stage variant (where they would be spilled)
+__device__ __forceinline__ int opaque_tid() {
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
+}
+
+// Butterflies of radix R a thread holds in one stage (at least one); the
+// planner keeps L * B / R <= stage_bfly(R, EPT) * NT.
+template <int R, int EPT>
+struct StageShape {
+    static constexpr int MAXB = (EPT / R) > 0 ? (EPT / R) : 1;
+};
+
+// Element (row, column b) of a batch of B columns held in LDS: interleaved
+// (row B + b), or in groups of four columns, group g a contiguous [row][4]
+// block starting at g gs.
+template <int B>
+struct Interleaved {
+    __device__ __forceinline__ int operator()(int row, int b) const { return row * B + b; }
+};
+struct Grouped4 {
+    int gs;
+    __device__ __forceinline__ int operator()(int row, int b) const { return row * 4 + (b >> 2) * gs + (b & 3); }
+};
+
+// One butterfly of a Stockham stage: x[j + r L/R] of column b, r < R ...
+template <int R, typename LAY>
+__device__ __forceinline__ void bfly_load(const cp* __restrict__ s, int j, int b, int LR, const LAY& lay,
+                                          cp (&v)[R]) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = s[lay(j + r * LR, b)];
+}
+// ... times the stage twiddles W_{Ns R}^{k r} (k = j mod Ns), then the radix-R DFT.
+template <int R, typename TW>
+__device__ __forceinline__ void bfly_dft(int k, int Ns, int tstride, const TW& tw, cp (&v)[R]) {
+    if (Ns > 1) {
+        const float2 w1 = tw(k * tstride);
+        float2 w = w1;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+            v[r] = cp_rot(v[r], w);
+            if (r + 1 < R) w = c_mul(w, w1);
+        }
+    }
+    Dft<R>::run(v);
+}
+
+// Read half of a Stockham stage: butterfly bf = tid + q NT (j = bf / B,
+// column b = bf % B) leaves its R outputs in v[q] when bf < L B / R.
+template <int R, int NT, int EPT, int B, typename TW, typename LAY>
+__device__ __forceinline__ void stage_compute(const cp* __restrict__ s, int L, int Ns, const TW& tw, const LAY& lay,
+                                              cp (&v)[StageShape<R, EPT>::MAXB][R]) {
+    constexpr int MAXB = StageShape<R, EPT>::MAXB;
+    const int tid = opaque_tid();
     const int LR = L / R;
     const int nb = LR * B;
     const int tstride = L / (Ns * R);
     const float inv_ns = 1.0f / (float)Ns;
-    cp v[MAXB][R];
 #pragma unroll
     for (int q = 0; q < MAXB; ++q) {
         const int bf = tid + q * NT;
@@ -270,21 +322,23 @@ __device__ __forceinline__ void stockham_stage(cp* __restrict__ s, int L, int Ns
             const int j = bf / B, b = bf - j * B;
             int jq, k;
             divmod_small(j, Ns, inv_ns, jq, k);
-#pragma unroll
-            for (int r = 0; r < R; ++r) v[q][r] = s[(j + r * LR) * B + b];
-            if (Ns > 1) {
-                const float2 w1 = tw(k * tstride);
-                float2 w = w1;
-#pragma unroll
-                for (int r = 1; r < R; ++r) {
-                    v[q][r] = cp_rot(v[q][r], w);
-                    if (r + 1 < R) w = c_mul(w, w1);
-                }
-            }
-            Dft<R>::run(v[q]);
+            bfly_load<R, LAY>(s, j, b, LR, lay, v[q]);
+            bfly_dft<R, TW>(k, Ns, tstride, tw, v[q]);
         }
     }
+}
+
+// One Stockham stage in place: all reads, a barrier, then the outputs of
+// butterfly (j = jq Ns + k) go to x[jq Ns R + k + r Ns].
+template <int R, int NT, int EPT, int B, typename TW, typename LAY>
+__device__ __forceinline__ void stockham_stage(cp* __restrict__ s, int L, int Ns, const TW& tw, const LAY& lay) {
+    constexpr int MAXB = StageShape<R, EPT>::MAXB;
+    cp v[MAXB][R];
+    stage_compute<R, NT, EPT, B, TW, LAY>(s, L, Ns, tw, lay, v);
     __syncthreads();
+    const int tid = opaque_tid();
+    const int nb = (L / R) * B;
+    const float inv_ns = 1.0f / (float)Ns;
 #pragma unroll
     for (int q = 0; q < MAXB; ++q) {
         const int bf = tid + q * NT;
@@ -294,35 +348,102 @@ __device__ __forceinline__ void stockham_stage(cp* __restrict__ s, int L, int Ns
             divmod_small(j, Ns, inv_ns, jq, k);
             const int base = jq * Ns * R + k;
 #pragma unroll
-            for (int r = 0; r < R; ++r) s[(base + r * Ns) * B + b] = v[q][r];
+            for (int r = 0; r < R; ++r) s[lay(base + r * Ns, b)] = v[q][r];
         }
     }
     __syncthreads();
 }
 
-// Run all stages of a planned transform (radix sequence in st).
-template <int NT, int EPT, int B, typename TW>
-__device__ void lds_fft(cp* __restrict__ s, const FftStages& st, const TW& tw) {
+// The last stage (Ns R = L) without the write back: output r of butterfly
+// (j, b) is element j + r L/R of column b, and sink.put<R>(q, j, b, v)
+// receives the R outputs of each valid butterfly, q in increasing order.
+// SPLIT = false: one butterfly at a time (only R outputs live); the caller
+// synchronises before the buffer is rewritten.  SPLIT = true: every input
+// is read first, then mid() runs (all threads; it may synchronise and
+// reuse the buffer), then the butterflies are computed and sunk.
+template <int R, int NT, int EPT, int B, bool SPLIT, typename TW, typename LAY, typename Sink, typename Mid>
+__device__ __forceinline__ void stockham_last(const cp* __restrict__ s, int L, int Ns, const TW& tw, const LAY& lay,
+                                              Sink& sink, const Mid& mid) {
+    constexpr int MAXB = StageShape<R, EPT>::MAXB;
+    const int tid = opaque_tid();
+    const int LR = L / R;
+    const int nb = LR * B;
+    const int tstride = L / (Ns * R);
+    const float inv_ns = 1.0f / (float)Ns;
+    if constexpr (SPLIT) {
+        cp v[MAXB][R];
+#pragma unroll
+        for (int q = 0; q < MAXB; ++q) {
+            const int bf = tid + q * NT;
+            if (bf < nb) {
+                const int j = bf / B, b = bf - j * B;
+                bfly_load<R, LAY>(s, j, b, LR, lay, v[q]);
+            }
+        }
+        mid();
+#pragma unroll
+        for (int q = 0; q < MAXB; ++q) {
+            const int bf = tid + q * NT;
+            if (bf < nb) {
+                const int j = bf / B, b = bf - j * B;
+                int jq, k;
+                divmod_small(j, Ns, inv_ns, jq, k);
+                bfly_dft<R, TW>(k, Ns, tstride, tw, v[q]);
+                sink.template put<R>(q, j, b, v[q]);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < MAXB; ++q) {
+            const int bf = tid + q * NT;
+            if (bf < nb) {
+                const int j = bf / B, b = bf - j * B;
+                cp v[R];
+                int jq, k;
+                divmod_small(j, Ns, inv_ns, jq, k);
+                bfly_load<R, LAY>(s, j, b, LR, lay, v);
+                bfly_dft<R, TW>(k, Ns, tstride, tw, v);
+                sink.template put<R>(q, j, b, v);
+            }
+        }
+        mid();
+    }
+}
+
+#define RSF_RADIX_CASES(M) \
+    M(2) M(3) M(4) M(5) M(6) M(7) M(8) M(9) M(10) M(12) M(14) M(15) M(16)
+
+struct NoMid {
+    __device__ __forceinline__ void operator()() const {}
+};
+
+// Run all stages but the last of a planned transform in LDS, then the last
+// one through sink (see stockham_last).
+template <int NT, int EPT, int B, bool SPLIT, typename TW, typename LAY, typename Sink, typename Mid>
+__device__ __forceinline__ void lds_fft_into(cp* __restrict__ s, const FftStages& st, const TW& tw, const LAY& lay,
+                                             Sink& sink, const Mid& mid) {
+    if (st.n_stages == 0) {  // length 1: the identity
+        stockham_last<1, NT, EPT, B, SPLIT, TW, LAY, Sink, Mid>(s, st.len, 1, tw, lay, sink, mid);
+        return;
+    }
     int Ns = 1;
-    for (int i = 0; i < st.n_stages; ++i) {
+    for (int i = 0; i + 1 < st.n_stages; ++i) {
         const int R = st.radix[i];
         switch (R) {
-            case 2: stockham_stage<2, NT, EPT, B, TW>(s, st.len, Ns, tw); break;
-            case 3: stockham_stage<3, NT, EPT, B, TW>(s, st.len, Ns, tw); break;
-            case 4: stockham_stage<4, NT, EPT, B, TW>(s, st.len, Ns, tw); break;
-            case 5: stockham_stage<5, NT, EPT, B, TW>(s, st.len, Ns, tw); break;
-            case 6: stockham_stage<6, NT, EPT, B, TW>(s, st.len, Ns, tw); break;
-            case 7: stockham_stage<7, NT, EPT, B, TW>(s, st.len, Ns, tw); break;
-            case 8: stockham_stage<8, NT, EPT, B, TW>(s, st.len, Ns, tw); break;
-            case 9: stockham_stage<9, NT, EPT, B, TW>(s, st.len, Ns, tw); break;
-            case 10: stockham_stage<10, NT, EPT, B, TW>(s, st.len, Ns, tw); break;
-            case 12: stockham_stage<12, NT, EPT, B, TW>(s, st.len, Ns, tw); break;
-            case 14: stockham_stage<14, NT, EPT, B, TW>(s, st.len, Ns, tw); break;
-            case 15: stockham_stage<15, NT, EPT, B, TW>(s, st.len, Ns, tw); break;
-            case 16: stockham_stage<16, NT, EPT, B, TW>(s, st.len, Ns, tw); break;
+#define RSF_STAGE_CASE(RR) \
+    case RR: stockham_stage<RR, NT, EPT, B, TW, LAY>(s, st.len, Ns, tw, lay); break;
+            RSF_RADIX_CASES(RSF_STAGE_CASE)
+#undef RSF_STAGE_CASE
             default: break;
         }
         Ns *= R;
+    }
+    switch (st.radix[st.n_stages - 1]) {
+#define RSF_LAST_CASE(RR) \
+    case RR: stockham_last<RR, NT, EPT, B, SPLIT, TW, LAY, Sink, Mid>(s, st.len, Ns, tw, lay, sink, mid); break;
+        RSF_RADIX_CASES(RSF_LAST_CASE)
+#undef RSF_LAST_CASE
+        default: break;
     }
 }
 

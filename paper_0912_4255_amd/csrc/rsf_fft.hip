@@ -48,9 +48,10 @@ __device__ __forceinline__ void accumulate_integrand(cp& y, float4 m, float tmf,
     // Phi_s = 2 pi fdot (T^2/2 + t_m T) = 2 pi fdot (t_b^2 - t_m^2)/2 with T = t_b - t_m
     const double tm = (double)tmf;
     const double cyc = fd * 0.5 * (tb * tb - tm * tm);
+    // reduced to [-1/2, 1/2] cycle; v_sin_f32 / v_cos_f32 take revolutions
     const float ph = (float)(cyc - rint(cyc));
-    float s, c;
-    sincospif(2.f * ph, &s, &c);
+    const float s = __builtin_amdgcn_sinf(ph);
+    const float c = __builtin_amdgcn_cosf(ph);
     const float er = zr * c + zi * s;  // z exp(-i Phi_s)
     const float ei = zi * c - zr * s;
     const float wa = w * av, wb = w * bv;
@@ -59,6 +60,39 @@ __device__ __forceinline__ void accumulate_integrand(cp& y, float4 m, float tmf,
     y.z += wb * er;
     y.w += wb * ei;
 }
+
+// Spill layout: 4-column groups, float4 [template][k_a / 4][n_b][k_a % 4], so
+// that each half of a second-pass block (4 columns x LB rows) is one
+// contiguous run and every cache line is fetched once.
+constexpr int kHalfCols = kPassBCols / 2;
+
+// Writer of the first pass's last stage: output k_a = j + r L1/R of the row
+// transform, times the inter-pass twiddle W_N^{n_b k_a}, goes straight from
+// registers to the spill.  The twiddle of butterfly j = tid + q NT is
+// W^{n_b tid} (W^{n_b NT})^q, advanced once per call (calls come in q order),
+// and steps by W^{n_b L1/R} along r.
+struct SpillSink {
+    char* out;  // this template's spill (< 4 GiB, so byte offsets fit 32 bits)
+    int LB, n_b, LR;
+    float2 wq, w_step, w_lr;
+    template <int R>
+    __device__ __forceinline__ void put(int, int j, int, cp (&v)[R]) {
+        // offsets and twiddles depend only on the thread and the plan; opaque
+        // copies of j and w keep the compiler from hoisting all of them out
+        // of the spindown loop (where they would be spilled)
+        int jv = j;
+        float2 w = wq;
+        asm volatile("" : "+v"(jv), "+v"(w.x), "+v"(w.y));
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t k = (uint32_t)(jv + r * LR);
+            const uint32_t off = (((k >> 2) * (uint32_t)LB + (uint32_t)n_b) * kHalfCols + (k & 3u)) * 16u;
+            *reinterpret_cast<float4*>(out + off) = cp_rot(v[r], w);
+            if (r + 1 < R) w = c_mul(w, w_lr);
+        }
+        wq = c_mul(wq, w_step);
+    }
+};
 
 // Inputs of one row held per thread: n_a = tid + q * kNT, q < kInPer (P <= LA/2 <= 5120).
 constexpr int kInPer = (kFftMaxLen / 2 + kNT - 1) / kNT;
@@ -101,6 +135,10 @@ __global__ __launch_bounds__(kNT) void rsf_fft_pass_a_k(PassAArgs A) {
     const int msk = (1 << kTwSplitBits) - 1;
     const float2 w_base = c_mul(A.tw_hi[mb >> kTwSplitBits], A.tw_lo[mb & msk]);
     const float2 w_step = c_mul(A.tw_hi[ms >> kTwSplitBits], A.tw_lo[ms & msk]);
+    const int r_last = A.st.n_stages ? A.st.radix[A.st.n_stages - 1] : 1;
+    const int lr = A.LA / r_last;
+    const int64_t ml = ((int64_t)n_b * lr) % A.n_fft;
+    const float2 w_lr = c_mul(A.tw_hi[ml >> kTwSplitBits], A.tw_lo[ml & msk]);
 
     for (int f = f_lo; f < f_hi; ++f) {
         const int t = s_l * A.nf_l + f;
@@ -123,91 +161,104 @@ __global__ __launch_bounds__(kNT) void rsf_fft_pass_a_k(PassAArgs A) {
         }
         for (int n_a = tid + kInPer * kNT; n_a < A.LA; n_a += kNT) lds[n_a] = make_float4(0.f, 0.f, 0.f, 0.f);
         __syncthreads();
-        lds_fft<kNT, kEPT, 1>(lds, A.st, tws);
-        float4* out = A.spill + (int64_t)t * A.spill_tmpl_stride;
-        float2 w = w_base;
-        for (int ka = tid; ka < A.LA; ka += kNT) {
-            const cp v = cp_rot(lds[ka], w);
-            out[((int64_t)(ka >> 3) * A.LB + n_b) * kPassBCols + (ka & 7)] = v;
-            w = c_mul(w, w_step);
-        }
+        SpillSink sink{reinterpret_cast<char*>(A.spill + (int64_t)t * A.spill_tmpl_stride), A.LB, n_b, lr, w_base,
+                       w_step, w_lr};
+        lds_fft_into<kNT, kEPT, 1, false>(lds, A.st, tws, Interleaved<1>{}, sink, NoMid{});
         __syncthreads();
     }
 }
 
-// Second pass, persistent and software-pipelined.  Workgroup g handles the
-// spill blocks g, g + grid, ... (block = template * n_groups + group of 8
-// columns), each as two 4-column halves.  Halves go through two LDS buffers:
-// while one half is transformed, the next half is copied global -> LDS by
-// the DMA loads (no registers involved), so memory traffic overlaps the
-// FFT.  The two halves of a 128 B spill row and of a 2F output line are
-// handled back to back by the same workgroup and meet in its L2.
-constexpr int kHalfCols = kPassBCols / 2;
+// Second pass, persistent.  Workgroup g handles the spill blocks g, g +
+// grid, ... (block = template * n_groups + group of 8 columns k_a): the two
+// 4-column groups of a block come into one LDS buffer by DMA loads (global
+// -> LDS, no registers), kept as two contiguous [LB][4] groups; the block is
+// transformed over n_b as 8 columns.  In the last stage every thread reads
+// its inputs, the workgroup synchronises, the DMA of the next block is
+// issued into the same buffer, and the last butterflies, the 2F reduction
+// (eq. eq6 with the noise-weighted A', B', C') and the stores run while it
+// is in flight.  Eight consecutive lanes hold the eight columns of one row,
+// so each store covers 32 contiguous bytes of the output.
 
-__device__ __forceinline__ void passb_dma(const PassBArgs& B, int unit, int h, float4* dst) {
+__device__ __forceinline__ void passb_dma(const PassBArgs& B, int unit, float4* dst) {
     const int t = unit / B.n_groups;
     const int c = unit - t * B.n_groups;
-    const float4* base = B.spill + (int64_t)t * B.spill_tmpl_stride + (int64_t)c * B.LB * kPassBCols + h * kHalfCols;
-    const int half = B.LB * kHalfCols;
+    const int blk = B.LB * kPassBCols;  // both groups of the block, contiguous in the spill
+    const float4* base = B.spill + (int64_t)t * B.spill_tmpl_stride + (int64_t)c * blk;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int e0 = wave * 64; e0 < half; e0 += kNT) {
+    for (int e0 = wave * 64; e0 < blk; e0 += kNT) {
         const int e = e0 + lane;
-        if (e < half) {
-            const float4* src = base + (e / kHalfCols) * kPassBCols + (e % kHalfCols);
-            __builtin_amdgcn_global_load_lds((const void*)src, (__attribute__((address_space(3))) void*)(dst + e0),
+        if (e < blk) {
+            __builtin_amdgcn_global_load_lds((const void*)(base + e), (__attribute__((address_space(3))) void*)(dst + e0),
                                              16, 0, 0);
         }
     }
 }
 
+// 2F of the last stage's outputs: row k_b = j + r LB/R of column b of the
+// block, bin k = 8c + b + LA k_b, reordered to the ascending band.
+struct TwoFSink {
+    float* out;
+    int LA, LR, ka0, nf, s_lo, n_out;
+    float cA, cB, cC;
+    template <int R>
+    __device__ __forceinline__ void put(int, int j, int b, cp (&v)[R]) {
+        const int ka = ka0 + b;
+        if (ka >= LA) return;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int k = ka + LA * (j + r * LR);
+            const int o = ((2 * k < nf) ? k : k - nf) - s_lo;
+            if (o >= 0 && o < n_out) {
+                const cp u = v[r];
+                out[o] = cA * (u.x * u.x + u.y * u.y) + cB * (u.z * u.z + u.w * u.w) + cC * (u.x * u.z + u.y * u.w);
+            }
+        }
+    }
+};
+
+struct PassBMid {
+    const PassBArgs* B;
+    int next;
+    float4* buf;
+    __device__ __forceinline__ void operator()() const {
+        __syncthreads();  // every thread holds its last-stage inputs: the buffer is free
+        if (next >= 0) passb_dma(*B, next, buf);
+    }
+};
+
 __global__ __launch_bounds__(kNT) void rsf_fft_pass_b_k(PassBArgs B) {
     extern __shared__ float4 lds[];
-    const int half = B.LB * kHalfCols;
-    const int buf_elems = ((half + 63) / 64) * 64;
-    float2* twl = reinterpret_cast<float2*>(lds + 2 * buf_elems);
+    const int blk = B.LB * kPassBCols;
+    const int buf_elems = ((blk + 63) / 64) * 64;
+    float2* twl = reinterpret_cast<float2*>(lds + buf_elems);
     const int n_hi = (B.LB + 31) >> kTwLoBits;
     float* cfl = reinterpret_cast<float*>(twl + 32 + n_hi);
     const int tid = threadIdx.x;
     for (int i = tid; i < 32 + n_hi; i += kNT) twl[i] = (i < 32) ? B.tw_lo[i] : B.tw_hi[i - 32];
     for (int i = tid; i < 4 * B.n_sky_l; i += kNT) cfl[i] = B.coef[i];
     const TwLds tw{twl, twl + 32};
+    const Grouped4 lay{B.LB * kHalfCols};
     const int n_units = B.n_tmpl * B.n_groups;
-    const int nf = (int)B.n_fft, s_lo = (int)B.s_lo, n_out = (int)B.n_out;
+    const int r_last = B.st.n_stages ? B.st.radix[B.st.n_stages - 1] : 1;
 
-    int unit = blockIdx.x, h = 0, cur = 0;
-    if (unit < n_units) passb_dma(B, unit, 0, lds);
+    int unit = blockIdx.x;
+    if (unit < n_units) passb_dma(B, unit, lds);
     while (unit < n_units) {
-        __builtin_amdgcn_s_waitcnt(0);  // this thread's DMA loads and stores are complete
-        __syncthreads();                // ... and everyone's: buffer cur is filled, buffer cur^1 is free
-        const int nunit = h ? unit + (int)gridDim.x : unit;
-        const int nh = h ^ 1;
-        if (nunit < n_units) passb_dma(B, nunit, nh, lds + (cur ^ 1) * buf_elems);
-        cp* x = lds + cur * buf_elems;
-        lds_fft<kNT, kPassBEPT, kHalfCols>(x, B.st, tw);
+        // this thread's DMA loads (and last block's stores) are complete;
+        // after the barrier, everyone's
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        const int nunit = unit + (int)gridDim.x;
         const int t = unit / B.n_groups;
         const int c = unit - t * B.n_groups;
         const int s_l = t / B.nf_l;
         const int f = t - s_l * B.nf_l;
-        const float cA = cfl[4 * s_l], cB = cfl[4 * s_l + 1], cC = cfl[4 * s_l + 2];
         const int64_t out_row = B.map_rows ? (int64_t)t : (B.sky0 + s_l) * B.n_fdot + B.f0 + f;
-        float* out = B.twoF + out_row * B.n_out;
-        for (int e = tid; e < half; e += kNT) {
-            const int kb = e >> 2;
-            const int ka = c * kPassBCols + h * kHalfCols + (e & 3);
-            if (ka < B.LA) {
-                const int k = ka + B.LA * kb;
-                const int s = (2 * k < nf) ? k : k - nf;
-                const int o = s - s_lo;
-                if (o >= 0 && o < n_out) {
-                    const cp u = x[e];
-                    out[o] = cA * (u.x * u.x + u.y * u.y) + cB * (u.z * u.z + u.w * u.w) +
-                             cC * (u.x * u.z + u.y * u.w);
-                }
-            }
-        }
+        TwoFSink sink{B.twoF + out_row * B.n_out, B.LA, B.LB / r_last, c * kPassBCols, (int)B.n_fft, (int)B.s_lo,
+                      (int)B.n_out, cfl[4 * s_l], cfl[4 * s_l + 1], cfl[4 * s_l + 2]};
+        const PassBMid mid{&B, nunit < n_units ? nunit : -1, lds};
+        lds_fft_into<kNT, kPassBEPT, kPassBCols, true>(lds, B.st, tw, lay, sink, mid);
         unit = nunit;
-        h = nh;
-        cur ^= 1;
     }
 }
 
@@ -223,8 +274,8 @@ hipError_t launch_fft_pass_a(const PassAArgs& a, hipStream_t s) {
 }
 
 size_t fft_pass_b_lds(int LB, int n_sky_l) {
-    const size_t buf = (size_t)((LB * kHalfCols + 63) / 64) * 64;
-    return 2 * buf * sizeof(float4) + (32 + (LB + 31) / 32) * sizeof(float2) + (size_t)4 * n_sky_l * sizeof(float);
+    const size_t buf = (size_t)((LB * kPassBCols + 63) / 64) * 64;
+    return buf * sizeof(float4) + (32 + (LB + 31) / 32) * sizeof(float2) + (size_t)4 * n_sky_l * sizeof(float);
 }
 
 hipError_t launch_fft_pass_b(const PassBArgs& b, int n_cu, hipStream_t s) {

@@ -29,10 +29,10 @@ constexpr int kFftMaxLen = 10240;   // longest first-pass transform (10240 x 16 
 constexpr int fft_bfly_per_thread(int R, int EPT) { return (EPT / R) > 0 ? (EPT / R) : 1; }
 constexpr int fft_radix_cap(int R, int NT, int EPT) { return fft_bfly_per_thread(R, EPT) * NT; }
 
-// Second pass: persistent workgroups, one per CU, transforming 4-column
-// halves of the spill blocks through two LDS buffers filled by DMA loads;
-// the stage capacity is kPassBEPT elements per thread.
-constexpr int kPassBEPT = 16;
+// Second pass: persistent workgroups, one per CU, transforming 8-column
+// spill blocks in one LDS buffer filled by DMA loads; the stage capacity
+// is kPassBEPT elements per thread (8 LB <= 512 x 20).
+constexpr int kPassBEPT = 20;
 constexpr int kTwLoBits = 5;        // LDS twiddle table W_L^m = lo[m & 31] * hi[m >> 5]
 
 struct FftStages {
@@ -130,7 +130,7 @@ struct PassAArgs {
     const float2* tws_hi;
     const float2* tw_lo;      // inter-pass twiddle W_N^m = tw_hi[m >> 12] * tw_lo[m & 4095]
     const float2* tw_hi;
-    float4* spill;            // [n_sky_l * nf_l][ceil(LA/8)][LB][8]
+    float4* spill;            // [n_sky_l * nf_l][2 * ceil(LA/8)][LB][4]: 4-column groups
     int64_t spill_tmpl_stride;
 };
 
