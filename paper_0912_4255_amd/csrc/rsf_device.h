@@ -283,11 +283,13 @@ struct Grouped4 {
 };
 
 // One butterfly of a Stockham stage: x[j + r L/R] of column b, r < R ...
-template <int R, typename LAY>
+// HZ: the upper half r >= R/2 is known to be zero (first stage of a
+// zero-padded transform); it is not read, and the DFT folds it away.
+template <int R, typename LAY, bool HZ = false>
 __device__ __forceinline__ void bfly_load(const cp* __restrict__ s, int j, int b, int LR, const LAY& lay,
                                           cp (&v)[R]) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = s[lay(j + r * LR, b)];
+    for (int r = 0; r < R; ++r) v[r] = (HZ && 2 * r >= R) ? make_float4(0.f, 0.f, 0.f, 0.f) : s[lay(j + r * LR, b)];
 }
 // ... times the stage twiddles W_{Ns R}^{k r} (k = j mod Ns), then the radix-R DFT.
 template <int R, typename TW>
@@ -306,7 +308,7 @@ __device__ __forceinline__ void bfly_dft(int k, int Ns, int tstride, const TW& t
 
 // Read half of a Stockham stage: butterfly bf = tid + q NT (j = bf / B,
 // column b = bf % B) leaves its R outputs in v[q] when bf < L B / R.
-template <int R, int NT, int EPT, int B, typename TW, typename LAY>
+template <int R, int NT, int EPT, int B, typename TW, typename LAY, bool HZ = false>
 __device__ __forceinline__ void stage_compute(const cp* __restrict__ s, int L, int Ns, const TW& tw, const LAY& lay,
                                               cp (&v)[StageShape<R, EPT>::MAXB][R]) {
     constexpr int MAXB = StageShape<R, EPT>::MAXB;
@@ -322,7 +324,7 @@ __device__ __forceinline__ void stage_compute(const cp* __restrict__ s, int L, i
             const int j = bf / B, b = bf - j * B;
             int jq, k;
             divmod_small(j, Ns, inv_ns, jq, k);
-            bfly_load<R, LAY>(s, j, b, LR, lay, v[q]);
+            bfly_load<R, LAY, HZ>(s, j, b, LR, lay, v[q]);
             bfly_dft<R, TW>(k, Ns, tstride, tw, v[q]);
         }
     }
@@ -330,11 +332,11 @@ __device__ __forceinline__ void stage_compute(const cp* __restrict__ s, int L, i
 
 // One Stockham stage in place: all reads, a barrier, then the outputs of
 // butterfly (j = jq Ns + k) go to x[jq Ns R + k + r Ns].
-template <int R, int NT, int EPT, int B, typename TW, typename LAY>
+template <int R, int NT, int EPT, int B, typename TW, typename LAY, bool HZ = false>
 __device__ __forceinline__ void stockham_stage(cp* __restrict__ s, int L, int Ns, const TW& tw, const LAY& lay) {
     constexpr int MAXB = StageShape<R, EPT>::MAXB;
     cp v[MAXB][R];
-    stage_compute<R, NT, EPT, B, TW, LAY>(s, L, Ns, tw, lay, v);
+    stage_compute<R, NT, EPT, B, TW, LAY, HZ>(s, L, Ns, tw, lay, v);
     __syncthreads();
     const int tid = opaque_tid();
     const int nb = (L / R) * B;
@@ -417,17 +419,33 @@ struct NoMid {
     __device__ __forceinline__ void operator()() const {}
 };
 
+#define RSF_EVEN_RADIX_CASES(M) M(2) M(4) M(6) M(8) M(10) M(12) M(14) M(16)
+
 // Run all stages but the last of a planned transform in LDS, then the last
-// one through sink (see stockham_last).
+// one through sink (see stockham_last).  first_half_zero: the upper half of
+// the input is zero and is neither written nor read (pruned first stage,
+// used when the first radix is even and there is more than one stage).
 template <int NT, int EPT, int B, bool SPLIT, typename TW, typename LAY, typename Sink, typename Mid>
 __device__ __forceinline__ void lds_fft_into(cp* __restrict__ s, const FftStages& st, const TW& tw, const LAY& lay,
-                                             Sink& sink, const Mid& mid) {
+                                             Sink& sink, const Mid& mid, bool first_half_zero = false) {
     if (st.n_stages == 0) {  // length 1: the identity
         stockham_last<1, NT, EPT, B, SPLIT, TW, LAY, Sink, Mid>(s, st.len, 1, tw, lay, sink, mid);
         return;
     }
     int Ns = 1;
-    for (int i = 0; i + 1 < st.n_stages; ++i) {
+    int i0 = 0;
+    if (first_half_zero && st.n_stages > 1 && (st.radix[0] & 1) == 0) {
+        switch (st.radix[0]) {
+#define RSF_STAGE_HZ_CASE(RR) \
+    case RR: stockham_stage<RR, NT, EPT, B, TW, LAY, true>(s, st.len, 1, tw, lay); break;
+            RSF_EVEN_RADIX_CASES(RSF_STAGE_HZ_CASE)
+#undef RSF_STAGE_HZ_CASE
+            default: break;
+        }
+        Ns = st.radix[0];
+        i0 = 1;
+    }
+    for (int i = i0; i + 1 < st.n_stages; ++i) {
         const int R = st.radix[i];
         switch (R) {
 #define RSF_STAGE_CASE(RR) \

@@ -26,39 +26,50 @@ constexpr int kNT = kFftThreads;
 constexpr int kEPT = kFftEPT;
 }  // namespace
 
-// Integrand of one detector for one sample (see the header comment).
-__device__ __forceinline__ void accumulate_integrand(cp& y, float4 m, float tmf, bool f16, double tb, double fd,
-                                                     float w) {
-    float zr, zi, av, bv;
+// One resampled sample of one detector, unpacked for the integrand: z~,
+// the noise-weighted beam patterns w a, w b, and u = (t_b^2 - t_m^2) / 2 in
+// FP64, so that Phi_s = 2 pi fdot (T^2/2 + t_m T) = 2 pi fdot u with
+// T = t_b - t_m (eq. eq4pt1); u does not depend on the spindown.
+struct Sample {
+    float zr, zi, wa, wb;
+    double u;
+};
+
+__device__ __forceinline__ Sample unpack_sample(float4 m, float tmf, bool f16, double tb, float w) {
+    Sample r;
     if (f16) {
         const uint32_t bits = __float_as_uint(m.x);
         const __half2 h = *reinterpret_cast<const __half2*>(&bits);
         const float2 z = __half22float2(h);
-        zr = z.x;
-        zi = z.y;
-        av = m.y;
-        bv = m.z;
+        r.zr = z.x;
+        r.zi = z.y;
+        r.wa = w * m.y;
+        r.wb = w * m.z;
         tmf = m.w;
     } else {
-        zr = m.x;
-        zi = m.y;
-        av = m.z;
-        bv = m.w;
+        r.zr = m.x;
+        r.zi = m.y;
+        r.wa = w * m.z;
+        r.wb = w * m.w;
     }
-    // Phi_s = 2 pi fdot (T^2/2 + t_m T) = 2 pi fdot (t_b^2 - t_m^2)/2 with T = t_b - t_m
     const double tm = (double)tmf;
-    const double cyc = fd * 0.5 * (tb * tb - tm * tm);
+    r.u = 0.5 * (tb * tb - tm * tm);
+    return r;
+}
+
+// y += (w a, w b) z~ exp(-i Phi_s) for one detector (eqs. eq19, eq20).
+__device__ __forceinline__ void accumulate_integrand(cp& y, const Sample& p, double fd) {
+    const double cyc = fd * p.u;
     // reduced to [-1/2, 1/2] cycle; v_sin_f32 / v_cos_f32 take revolutions
     const float ph = (float)(cyc - rint(cyc));
     const float s = __builtin_amdgcn_sinf(ph);
     const float c = __builtin_amdgcn_cosf(ph);
-    const float er = zr * c + zi * s;  // z exp(-i Phi_s)
-    const float ei = zi * c - zr * s;
-    const float wa = w * av, wb = w * bv;
-    y.x += wa * er;
-    y.y += wa * ei;
-    y.z += wb * er;
-    y.w += wb * ei;
+    const float er = p.zr * c + p.zi * s;  // z exp(-i Phi_s)
+    const float ei = p.zi * c - p.zr * s;
+    y.x += p.wa * er;
+    y.y += p.wa * ei;
+    y.z += p.wb * er;
+    y.w += p.wb * ei;
 }
 
 // Spill layout: 4-column groups, float4 [template][k_a / 4][n_b][k_a % 4], so
@@ -113,7 +124,8 @@ __global__ __launch_bounds__(kNT) void rsf_fft_pass_a_k(PassAArgs A) {
     const int tid = threadIdx.x;
     const int64_t row = (int64_t)s_l * A.rs_sky_stride + (int64_t)n_b * A.P;
 
-    // first detector's row: all loads issued before any is used, kept for every spindown
+    // first detector's row: all loads issued before any is used, kept
+    // (unpacked, with u) for every spindown
     float4 m0[kInPer];
     float tm0[kInPer];
 #pragma unroll
@@ -128,6 +140,16 @@ __global__ __launch_bounds__(kNT) void rsf_fft_pass_a_k(PassAArgs A) {
             tm0[q] = 0.f;
         }
     }
+    Sample p0[kInPer];
+#pragma unroll
+    for (int q = 0; q < kInPer; ++q) {
+        const int64_t k = (int64_t)A.LB * (tid + q * kNT) + n_b;
+        p0[q] = unpack_sample(m0[q], tm0[q], A.f16, (double)k * A.dt, (float)A.w[0]);
+    }
+    // the upper half of the row is zero padding when P <= LA/2: it is
+    // neither written nor read (pruned first stage)
+    const bool prune = 2 * A.P <= A.LA && A.st.n_stages > 1 && (A.st.radix[0] & 1) == 0;
+    const int zlim = prune ? A.LA / 2 : A.LA;
 
     // inter-pass twiddle W_N^{n_b k_a} for k_a = tid + q kNT: base W^{n_b tid}, step W^{n_b kNT}
     const int64_t mb = ((int64_t)n_b * tid) % A.n_fft;
@@ -146,24 +168,25 @@ __global__ __launch_bounds__(kNT) void rsf_fft_pass_a_k(PassAArgs A) {
 #pragma unroll
         for (int q = 0; q < kInPer; ++q) {
             const int n_a = tid + q * kNT;
-            if (n_a < A.LA) {
+            if (n_a < zlim) {
                 cp y = make_float4(0.f, 0.f, 0.f, 0.f);
                 const int64_t k = (int64_t)A.LB * n_a + n_b;
                 if (n_a < A.P && k < A.n) {
-                    const double tb = (double)k * A.dt;
-                    accumulate_integrand(y, m0[q], tm0[q], A.f16, tb, fd, (float)A.w[0]);
+                    accumulate_integrand(y, p0[q], fd);
                     for (int X = 1; X < A.n_det; ++X)
-                        accumulate_integrand(y, A.rs_main[X][row + n_a], A.f16 ? 0.f : A.rs_tm[X][row + n_a],
-                                             A.f16, tb, fd, (float)A.w[X]);
+                        accumulate_integrand(y,
+                                             unpack_sample(A.rs_main[X][row + n_a], A.f16 ? 0.f : A.rs_tm[X][row + n_a],
+                                                           A.f16, (double)k * A.dt, (float)A.w[X]),
+                                             fd);
                 }
                 lds[n_a] = y;
             }
         }
-        for (int n_a = tid + kInPer * kNT; n_a < A.LA; n_a += kNT) lds[n_a] = make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int n_a = tid + kInPer * kNT; n_a < zlim; n_a += kNT) lds[n_a] = make_float4(0.f, 0.f, 0.f, 0.f);
         __syncthreads();
         SpillSink sink{reinterpret_cast<char*>(A.spill + (int64_t)t * A.spill_tmpl_stride), A.LB, n_b, lr, w_base,
                        w_step, w_lr};
-        lds_fft_into<kNT, kEPT, 1, false>(lds, A.st, tws, Interleaved<1>{}, sink, NoMid{});
+        lds_fft_into<kNT, kEPT, 1, false>(lds, A.st, tws, Interleaved<1>{}, sink, NoMid{}, prune);
         __syncthreads();
     }
 }
