@@ -144,6 +144,12 @@ int rsf_plan_destroy(rsf_plan* plan);
  * pass (1..16); templates = templates per FFT launch (1..256). */
 int rsf_plan_set_batching(rsf_plan* plan, int fb, int templates);
 
+/* Host only (no device needed): the factorisation n_fft = L1 * L2 that
+ * rsf_plan_create would choose on a device with lds_bytes of LDS per
+ * workgroup (fft_l1 > 0 forces L1), for checking FFT lengths in advance.
+ * RSF_EUNSUPPORTED when n_fft is not 7-smooth or no factorisation fits. */
+int rsf_fft_factor(int64_t n_fft, int lds_bytes, int fft_l1, int32_t* l1, int32_t* l2);
+
 /* Effective batching of rsf_fstat / rsf_fstat_topk for n_sky x n_fdot
  * templates in `mode`: spindowns sharing a first-pass row (*fb), templates
  * per FFT launch (*templates) and sky positions resampled per launch

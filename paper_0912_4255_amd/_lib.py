@@ -16,7 +16,7 @@ RSF_ENTRY_RESAMPLE, RSF_ENTRY_FSTAT, RSF_ENTRY_POINT, RSF_ENTRY_BACKWARD, RSF_EN
 RSF_FLAG_DEGENERATE, RSF_FLAG_WINDOW = 1, 2
 
 EXPORTS = [
-    "rsf_plan_create", "rsf_plan_destroy", "rsf_plan_query", "rsf_plan_set_batching", "rsf_plan_batching",
+    "rsf_plan_create", "rsf_plan_destroy", "rsf_plan_query", "rsf_plan_set_batching", "rsf_plan_batching", "rsf_fft_factor",
     "rsf_workspace_size",
     "rsf_resample", "rsf_fstat", "rsf_fstat_topk", "rsf_fstat_point", "rsf_fstat_backward",
     "rsf_get_flags", "rsf_last_error", "rsf_version", "rsf_profile_enable", "rsf_profile_read",
@@ -78,6 +78,7 @@ def load(path=None):
     lib.rsf_plan_query.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64),
                                    C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double)]
     lib.rsf_plan_set_batching.argtypes = [vp, i32, i32]
+    lib.rsf_fft_factor.argtypes = [i64, i32, i32, C.POINTER(i32), C.POINTER(i32)]
     lib.rsf_plan_batching.argtypes = [vp, i64, i64, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
     lib.rsf_workspace_size.argtypes = [vp, i32, i64, i64, i32, C.POINTER(sz)]
     lib.rsf_resample.argtypes = [vp, C.POINTER(Segment), vp, i64, C.POINTER(Resampled), vp, sz, vp]

@@ -103,6 +103,39 @@ bool radix_plan(int len, int B, int NT, int EPT, FftStages* st) {
     return true;
 }
 
+// Factorisation n_fft = LA * LB for the two FFT passes on a device with
+// lds_max bytes of LDS per workgroup: fewest total stages, LA a multiple of
+// 8, then the most balanced LDS footprints.  fft_l1 > 0 forces LA.
+bool choose_factors(int64_t n_fft, int lds_max, int fft_l1, int* out_la, int* out_lb) {
+    const int max_elems = fft_pass_max_elems();
+    const int64_t la_max = std::min<int64_t>(max_elems, lds_max / (int)sizeof(float4));
+    const int64_t lb_max = std::min<int64_t>(max_elems / kPassBCols, lds_max / (kPassBCols * (int)sizeof(float4)));
+    int best_la = -1, best_lb = -1;
+    double best_score = 1e300;
+    for (int64_t lb = 1; lb <= lb_max; ++lb) {
+        if (n_fft % lb) continue;
+        const int64_t la = n_fft / lb;
+        if (la > la_max || fft_pass_a_lds((int)la) > (size_t)lds_max) continue;
+        if (fft_l1 > 0 && la != fft_l1) continue;
+        FftStages sa, sb;
+        if (!radix_plan((int)la, 1, kFftThreads, kFftEPT, &sa) ||
+            !radix_plan((int)lb, kPassBCols, kFftThreads, kPassBEPT, &sb) ||
+            fft_pass_b_lds((int)lb, 64) > (size_t)lds_max)
+            continue;
+        const double lds_a = (double)la * 16, lds_b = (double)lb * 128;
+        const double score = (sa.n_stages + sb.n_stages) * 1e9 + ((la % 8) ? 1e8 : 0.0) + std::max(lds_a, lds_b);
+        if (score < best_score) {
+            best_score = score;
+            best_la = (int)la;
+            best_lb = (int)lb;
+        }
+    }
+    if (best_la < 0) return false;
+    *out_la = best_la;
+    *out_lb = best_lb;
+    return true;
+}
+
 }  // namespace
 
 namespace {
@@ -371,33 +404,8 @@ int rsf_plan_create(rsf_plan** out, const rsf_plan_desc* d) {
     if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device) != hipSuccess ||
         lds_max <= 0)
         lds_max = 65536;
-    const int max_elems = fft_pass_max_elems();
-    const int64_t la_max = std::min<int64_t>(max_elems, lds_max / (int)sizeof(float4));
-    const int64_t lb_max = std::min<int64_t>(max_elems / kPassBCols, lds_max / (kPassBCols * (int)sizeof(float4)));
-
-    // factorisation n_fft = LA * LB: fewest total stages, LA a multiple of 8,
-    // then the most balanced LDS footprints
     int best_la = -1, best_lb = -1;
-    double best_score = 1e300;
-    for (int64_t lb = 1; lb <= lb_max; ++lb) {
-        if (p->n_fft % lb) continue;
-        const int64_t la = p->n_fft / lb;
-        if (la > la_max || fft_pass_a_lds((int)la) > (size_t)lds_max) continue;
-        if (d->fft_l1 > 0 && la != d->fft_l1) continue;
-        FftStages sa, sb;
-        if (!radix_plan((int)la, 1, kFftThreads, kFftEPT, &sa) ||
-            !radix_plan((int)lb, kPassBCols, kFftThreads, kPassBEPT, &sb) ||
-            fft_pass_b_lds((int)lb, 64) > (size_t)lds_max)
-            continue;
-        const double lds_a = (double)la * 16, lds_b = (double)lb * 128;
-        double score = (sa.n_stages + sb.n_stages) * 1e9 + ((la % 8) ? 1e8 : 0.0) + std::max(lds_a, lds_b);
-        if (score < best_score) {
-            best_score = score;
-            best_la = (int)la;
-            best_lb = (int)lb;
-        }
-    }
-    if (best_la < 0) {
+    if (!choose_factors(p->n_fft, lds_max, d->fft_l1, &best_la, &best_lb)) {
         delete p;
         return fail(RSF_EUNSUPPORTED, "no two-pass factorisation of n_fft = %lld (L1 = %d) fits the LDS (%d bytes)",
                     (long long)p->n_fft, (int)d->fft_l1, lds_max);
@@ -495,6 +503,18 @@ int rsf_plan_set_batching(rsf_plan* p, int fb, int templates) {
         return fail(RSF_EINVAL, "fb must be in 0..16 and templates in 0..256");
     p->fb_override = fb;
     p->g_override = templates;
+    return RSF_OK;
+}
+
+int rsf_fft_factor(int64_t n_fft, int lds_bytes, int fft_l1, int32_t* l1, int32_t* l2) {
+    if (n_fft < 1 || lds_bytes < 1 || fft_l1 < 0) return fail(RSF_EINVAL, "n_fft, lds_bytes must be positive");
+    if (!is_7smooth(n_fft)) return fail(RSF_EUNSUPPORTED, "FFT length %lld has a prime factor above 7", (long long)n_fft);
+    int la = 0, lb = 0;
+    if (!choose_factors(n_fft, lds_bytes, fft_l1, &la, &lb))
+        return fail(RSF_EUNSUPPORTED, "no two-pass factorisation of n_fft = %lld fits %d bytes of LDS", (long long)n_fft,
+                    lds_bytes);
+    if (l1) *l1 = la;
+    if (l2) *l2 = lb;
     return RSF_OK;
 }
 

@@ -491,6 +491,84 @@ __device__ __forceinline__ double roemer(double tau, const double3 n0, const Eph
     return n0.x * x + n0.y * y + n0.z * z;
 }
 
+// t_m(tau) with its first three time derivatives.  Both parts of r_d move
+// on circles at uniform rates w, so per part the second derivative is
+// -w^2 times the position and the third -w^2 times the velocity.
+struct RoemerD {
+    double tm, d1, d2, d3;
+    SiteAngles ang;
+};
+__device__ __forceinline__ RoemerD roemer_d(double tau, const double3 n0, const EphDev& e, const DetDev& d) {
+    const double lam = e.lambda0 + 2.0 * kPi * frac_rev(tau * e.inv_p_orb);
+    const double th = e.theta0 + 2.0 * kPi * frac_rev(tau * e.inv_p_sid) + d.lon;
+    double sl, cl, st, ct;
+    sincos(lam, &sl, &cl);
+    sincos(th, &st, &ct);
+    const double wo = 2.0 * kPi * e.inv_p_orb, ws = 2.0 * kPi * e.inv_p_sid;
+    const double po = e.au_c * (n0.x * cl + (n0.y * e.ceps + n0.z * e.seps) * sl);        // n0 . r_orb
+    const double vo = wo * e.au_c * (-n0.x * sl + (n0.y * e.ceps + n0.z * e.seps) * cl);  // its rate
+    const double rc = e.re_c * d.clat;
+    const double pr = rc * (n0.x * ct + n0.y * st);  // rotating part in the equatorial plane
+    const double vr = ws * rc * (-n0.x * st + n0.y * ct);
+    RoemerD o;
+    o.tm = po + pr + n0.z * e.re_c * d.slat;
+    o.d1 = vo + vr;
+    o.d2 = -wo * wo * po - ws * ws * pr;
+    o.d3 = -wo * wo * vo - ws * ws * vr;
+    o.ang.sth = st;
+    o.ang.cth = ct;
+    return o;
+}
+
+// Solution T of T + t_m(T) = t_b (eq. eq21): one fixed-point step from
+// T = t_b, then one Newton step, T <- T - (T + t_m(T) - t_b) / (1 + t_m'(T)).
+// The fixed-point step leaves |dT| <= |t_m'| |t_m| (about 0.05 s); the Newton
+// step leaves about t_m'' dT^2 / 2, below 1e-12 s.  Also returns the
+// expansion point (T1, t_m and derivatives there) and the sidereal angle
+// carried to T.
+struct Inversion {
+    double T, T1;
+    RoemerD r1;
+    SiteAngles ang;
+};
+__device__ __forceinline__ Inversion invert_ssb(double t_start, double tb, const double3 n0, const EphDev& e,
+                                                const DetDev& d) {
+    SiteAngles g0;
+    Inversion v;
+    v.T1 = tb - roemer(t_start + tb, n0, e, d, &g0);
+    v.r1 = roemer_d(t_start + v.T1, n0, e, d);
+    const double dT = -(v.T1 + v.r1.tm - tb) / (1.0 + v.r1.d1);
+    v.T = v.T1 + dT;
+    // rotate the sidereal angle by w_sid dT (|w_sid dT| < 1e-5)
+    const double a = 2.0 * kPi * e.inv_p_sid * dT;
+    const double sa = a * (1.0 - a * a / 6.0), ca = 1.0 - 0.5 * a * a;
+    v.ang.sth = v.r1.ang.sth * ca + v.r1.ang.cth * sa;
+    v.ang.cth = v.r1.ang.cth * ca - v.r1.ang.sth * sa;
+    return v;
+}
+
+// Lane l's double, read into scalar registers (l must be wave-uniform).
+__device__ __forceinline__ double readlane_d(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ RoemerD readlane_rd(const RoemerD& q, int l) {
+    RoemerD o;
+    o.tm = readlane_d(q.tm, l);
+    o.d1 = readlane_d(q.d1, l);
+    o.d2 = readlane_d(q.d2, l);
+    o.d3 = readlane_d(q.d3, l);
+    return o;
+}
+
+// t_m at T1 + delta from the expansion at T1 (third order; the remainder is
+// about w_sid^4 (R_E/c) delta^4 / 24, 3e-10 s for |delta| = 320 s).
+__device__ __forceinline__ double tm_expand(const RoemerD& r, double delta) {
+    return r.tm + delta * (r.d1 + delta * (0.5 * r.d2 + delta * (r.d3 * (1.0 / 6.0))));
+}
+
 __device__ __forceinline__ double3 sky_unit(double alpha, double delta) {
     double sa, ca, sd, cd;
     sincos(alpha, &sa, &ca);

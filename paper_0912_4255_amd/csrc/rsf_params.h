@@ -31,8 +31,9 @@ constexpr int fft_radix_cap(int R, int NT, int EPT) { return fft_bfly_per_thread
 
 // Second pass: persistent workgroups, one per CU, transforming 8-column
 // spill blocks in one LDS buffer filled by DMA loads; the stage capacity
-// is kPassBEPT elements per thread (8 LB <= 512 x 20).
-constexpr int kPassBEPT = 20;
+// is kPassBEPT elements per thread (8 LB <= 512 x 21; 21 lets radix-7 stages
+// hold 3 butterflies per thread).
+constexpr int kPassBEPT = 21;
 constexpr int kTwLoBits = 5;        // LDS twiddle table W_L^m = lo[m & 31] * hi[m >> 5]
 
 struct FftStages {

@@ -44,8 +44,9 @@ enum {
 };
 
 struct Orbit {
-    double3 r;     // r_d / c (s)
-    double3 v;     // v_d / c
+    double3 r;       // r_d / c (s)
+    double3 v;       // v_d / c
+    double sl, cl;   // orbital angle (the orbital part of r is AU/c (cl, ceps sl, seps sl))
     double sth, cth;
 };
 
@@ -61,12 +62,33 @@ __device__ __forceinline__ Orbit orbit_at(double tau, const EphDev& e, const Det
                        e.au_c * e.seps * sl + e.re_c * d.slat);
     o.v = make_double3(-e.au_c * wo * sl - e.re_c * ws * d.clat * st, e.au_c * wo * e.ceps * cl + e.re_c * ws * d.clat * ct,
                        e.au_c * wo * e.seps * cl);
+    o.sl = sl;
+    o.cl = cl;
     o.sth = st;
     o.cth = ct;
     return o;
 }
 
 __device__ __forceinline__ double dot3(double3 a, double3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+
+// m . r_d / c and its first three time derivatives at the orbit o (each
+// part moves on a circle, so its second derivative is -w^2 times the
+// position and the third -w^2 times the velocity); rez = R_E sin(lat) / c.
+__device__ __forceinline__ RoemerD project(const Orbit& o, double3 m, const EphDev& e, double wo2, double ws2,
+                                           double rez) {
+    RoemerD q;
+    q.tm = dot3(m, o.r);
+    q.d1 = dot3(m, o.v);
+    const double my = m.y * e.ceps + m.z * e.seps;
+    const double pro = e.au_c * (m.x * o.cl + my * o.sl);
+    const double pvo = sqrt(wo2) * e.au_c * (-m.x * o.sl + my * o.cl);
+    const double prr = q.tm - pro - m.z * rez, pvr = q.d1 - pvo;
+    q.d2 = -wo2 * pro - ws2 * prr;
+    q.d3 = -wo2 * pvo - ws2 * pvr;
+    return q;
+}
+
+
 
 __device__ __forceinline__ bool in_gap(const int64_t* __restrict__ gaps, int n_gaps, int64_t j) {
     int lo = 0, hi = n_gaps - 1, best = -1;
@@ -90,8 +112,9 @@ __device__ __forceinline__ void sinc_d(float x, float sx, float cx, float& s, fl
         s = 1.f - p2 / 6.f + p2 * p2 / 120.f - p2 * p2 * p2 / 5040.f;
         ds = -(kPiF * kPiF * x / 3.f) * (1.f - p2 / 10.f + p2 * p2 / 280.f);
     } else {
-        s = sx / (kPiF * x);
-        ds = (cx - s) / x;
+        const float rx = __builtin_amdgcn_rcpf(x);
+        s = sx * rx * (1.f / kPiF);
+        ds = (cx - s) * rx;
     }
 }
 
@@ -109,8 +132,8 @@ __device__ __forceinline__ void kernel_w(const InterpDev& ip, float x, float sx,
             return;
         }
         const float v = 2.f * x / (float)W;
-        float sv, cv, s1, ds1;
-        sincospif(v, &sv, &cv);
+        float s1, ds1;
+        const float sv = __builtin_amdgcn_sinf(0.5f * v), cv = __builtin_amdgcn_cosf(0.5f * v);  // revolutions
         sinc_d(v, sv, cv, s1, ds1);
         w = s0 * s1;
         if (GRAD) dw = ds0 * s1 + s0 * ds1 * (2.f / (float)W);
@@ -145,7 +168,7 @@ __device__ __forceinline__ void kernel_w(const InterpDev& ip, float x, float sx,
 }  // namespace
 
 template <bool GRAD>
-__global__ __launch_bounds__(kThreads) void rsf_point_k(PointArgs A) {
+__global__ __launch_bounds__(kThreads, 2) void rsf_point_k(PointArgs A) {
     __shared__ float4 win[4][kWinMax];  // z (re, im), 2 pi f_het dt_m/dalpha, 2 pi f_het dt_m/ddelta
     __shared__ double red[4][kPointSums];
 
@@ -188,11 +211,33 @@ __global__ __launch_bounds__(kThreads) void rsf_point_k(PointArgs A) {
                 double T = tb, tm = 0.0, dTa = 0.0, dTd = 0.0;
                 double av = 0.0, bv = 0.0, daa = 0.0, dad = 0.0, dba = 0.0, dbd = 0.0;
                 bool mk = false;
+                double T1 = 0.0;
+                RoemerD x0{}, xa{}, xd{};  // expansions of n0.r, n0_alpha.r, n0_delta.r about T1
                 if (valid) {
-                    Orbit o;
-                    for (int it = 0; it < 5; ++it) {
-                        o = orbit_at(A.t_start + T, A.eph, D);
-                        T = tb - dot3(n0, o.r);
+                    // eq. eq21: one fixed-point step and one Newton step (residual below 1e-12 s)
+                    SiteAngles g0;
+                    T1 = tb - roemer(A.t_start + tb, n0, A.eph, D, &g0);
+                    const Orbit o1 = orbit_at(A.t_start + T1, A.eph, D);
+                    {
+                        const double wo2 = 4.0 * kPi * kPi * A.eph.inv_p_orb * A.eph.inv_p_orb;
+                        const double ws2 = w_sid * w_sid;
+                        const double rez = A.eph.re_c * D.slat;
+                        x0 = project(o1, n0, A.eph, wo2, ws2, rez);
+                        if (GRAD) {
+                            xa = project(o1, n0a, A.eph, wo2, ws2, rez);
+                            xd = project(o1, n0d, A.eph, wo2, ws2, rez);
+                        }
+                    }
+                    const double dT = -(T1 + dot3(n0, o1.r) - tb) / (1.0 + dot3(n0, o1.v));
+                    T = T1 + dT;
+                    // the orbit at T: positions moved by v dT, the sidereal angle turned by w_sid dT
+                    Orbit o = o1;
+                    o.r = make_double3(o1.r.x + o1.v.x * dT, o1.r.y + o1.v.y * dT, o1.r.z + o1.v.z * dT);
+                    {
+                        const double a = w_sid * dT;
+                        const double sa = a * (1.0 - a * a / 6.0), ca = 1.0 - 0.5 * a * a;
+                        o.sth = o1.sth * ca + o1.cth * sa;
+                        o.cth = o1.cth * ca - o1.sth * sa;
                     }
                     tm = tb - T;
                     const double u = T / A.dt;
@@ -233,6 +278,17 @@ __global__ __launch_bounds__(kThreads) void rsf_point_k(PointArgs A) {
                         dbd = up * uqd - vp * vqd + bdT * dTd;
                     }
                 }
+                // expansion point of t_m (and of its sky derivatives) for the
+                // window: the first valid lane's fixed-point iterate
+                const uint64_t vmask = __ballot(valid);
+                const int src = vmask ? __ffsll((long long)vmask) - 1 : 0;
+                const double t_ref = readlane_d(T1, src);
+                const RoemerD q0 = readlane_rd(x0, src);
+                RoemerD qa{}, qd{};
+                if (GRAD) {
+                    qa = readlane_rd(xa, src);
+                    qd = readlane_rd(xd, src);
+                }
                 // detector-grid window of this run, heterodyne-corrected
                 int jmin = valid ? j : INT_MAX;
                 int jmax = valid ? j : INT_MIN;
@@ -251,17 +307,16 @@ __global__ __launch_bounds__(kThreads) void rsf_point_k(PointArgs A) {
                         float4 e = make_float4(0.f, 0.f, 0.f, 0.f);
                         if (jj >= 0 && jj < A.n) {
                             const float2 xv = A.x[X][jj];
-                            const Orbit o = orbit_at(A.t_start + (double)jj * A.dt, A.eph, D);
-                            const double tmj = dot3(n0, o.r);
+                            const double dl = (double)jj * A.dt - t_ref;
+                            const double tmj = tm_expand(q0, dl);
                             const double cyc = A.f_het * tmj;
                             const float ph = (float)(cyc - rint(cyc));
-                            float s, c;
-                            sincospif(2.f * ph, &s, &c);
+                            const float s = __builtin_amdgcn_sinf(ph), c = __builtin_amdgcn_cosf(ph);  // revolutions
                             e.x = xv.x * c + xv.y * s;
                             e.y = xv.y * c - xv.x * s;
                             if (GRAD) {
-                                e.z = (float)(2.0 * kPi * A.f_het * dot3(n0a, o.r));
-                                e.w = (float)(2.0 * kPi * A.f_het * dot3(n0d, o.r));
+                                e.z = (float)(2.0 * kPi * A.f_het * tm_expand(qa, dl));
+                                e.w = (float)(2.0 * kPi * A.f_het * tm_expand(qd, dl));
                             }
                         }
                         win[wave][p] = e;
@@ -271,8 +326,7 @@ __global__ __launch_bounds__(kThreads) void rsf_point_k(PointArgs A) {
                 __syncthreads();
                 if (valid && ok) {
                     // interpolation (and derivative pieces)
-                    float sf, cf;
-                    sincospif(frac, &sf, &cf);
+                    const float sf = __builtin_amdgcn_sinf(0.5f * frac), cf = __builtin_amdgcn_cosf(0.5f * frac);
                     float2 zt = make_float2(0.f, 0.f), s1 = zt, sza = zt, szd = zt;
                     const int base = j - hw + 1 - w0;
                     for (int i = 1; i <= W; ++i) {
@@ -300,8 +354,7 @@ __global__ __launch_bounds__(kThreads) void rsf_point_k(PointArgs A) {
                     // total phase: spindown Phi_s and the Fourier kernel at f
                     const double cyc = fd * 0.5 * (tb * tb - tm * tm) + (f - A.f_het) * tb;
                     const float ph = (float)(cyc - rint(cyc));
-                    float s, c;
-                    sincospif(2.f * ph, &s, &c);
+                    const float s = __builtin_amdgcn_sinf(ph), c = __builtin_amdgcn_cosf(ph);  // revolutions
                     // ze = z~ exp(-2 pi i cyc)
                     const float zer = zt.x * c + zt.y * s, zei = zt.y * c - zt.x * s;
                     const double w = D.w;

@@ -3,11 +3,13 @@
 // One workgroup (4 waves) resamples a 16 x 64 tile of the SSB grid
 // k = LB * n_a + n_b (n_a = tile row, n_b = lane).  Each wave handles four
 // runs of 64 consecutive k:
-//   1. every lane inverts eq. eq21 for its k by fixed-point iteration in FP64
-//      (T <- k dt - t_m(T), 5 iterations: the contraction is |dt_m/dt| <= 1e-4);
+//   1. every lane inverts eq. eq21 for its k in FP64 (one fixed-point step
+//      and one Newton step, residual below 1e-12 s);
 //   2. the wave loads the detector-grid window its 64 outputs need into LDS,
 //      applying the heterodyne correction z = x_h exp(-2 pi i f_h t_m) on the
-//      way (eqs. absorb/Fa3; the phase f_h t_m is reduced mod 1 in FP64);
+//      way (eqs. absorb/Fa3; t_m at the detector samples from a third-order
+//      expansion about the first lane's inversion, the phase f_h t_m reduced
+//      mod 1 in FP64);
 //   3. every lane interpolates z at T^k with the W-tap kernel in FP32;
 //   4. a(T^k), b(T^k) come from the detector tensor in FP64, and the masked
 //      antenna sums A', B', C' (eqs. eq9/eq10) accumulate in FP64.
@@ -78,20 +80,25 @@ __global__ __launch_bounds__(kThreads) void rsf_resample_k(ResampleArgs A) {
         float frac = 0.f;
         double tm = 0.0, av = 0.0, bv = 0.0;
         bool mk = false;
+        Inversion inv{};
         if (valid) {
             const double tb = (double)k * A.dt;
-            double T = tb;
-            SiteAngles g;
-            for (int it = 0; it < 5; ++it) T = tb - roemer(A.t_start + T, n0, A.eph, A.det, &g);
+            inv = invert_ssb(A.t_start, tb, n0, A.eph, A.det);
+            const double T = inv.T;
             tm = tb - T;
             const double u = T / A.dt;
             const double fl = floor(u);
             j = (int)fl;
             frac = (float)(u - fl);
-            beam_ab(g, A.det, fr, &av, &bv);
+            beam_ab(inv.ang, A.det, fr, &av, &bv);
             const int64_t jn = (int64_t)floor(u + 0.5);
             mk = (jn >= 0) && (jn < A.n) && !in_gap(A.gaps, A.n_gaps, jn);
         }
+        // expansion point of t_m for this run's window: the first valid lane
+        const uint64_t vmask = __ballot(valid);
+        const int src = vmask ? __ffsll((long long)vmask) - 1 : 0;
+        const RoemerD rref = readlane_rd(inv.r1, src);
+        const double t_ref = readlane_d(inv.T1, src);
 
         // window of detector samples needed by this run
         int jmin = valid ? j : INT_MAX;
@@ -111,12 +118,10 @@ __global__ __launch_bounds__(kThreads) void rsf_resample_k(ResampleArgs A) {
                 float2 z = make_float2(0.f, 0.f);
                 if (jj >= 0 && jj < A.n) {
                     const float2 xv = A.x[jj];
-                    SiteAngles gg;
-                    const double tmj = roemer(A.t_start + (double)jj * A.dt, n0, A.eph, A.det, &gg);
+                    const double tmj = tm_expand(rref, (double)jj * A.dt - t_ref);
                     const double cyc = A.f_het * tmj;
                     const float ph = (float)(cyc - rint(cyc));
-                    float s, c;
-                    sincospif(2.f * ph, &s, &c);
+                    const float s = __builtin_amdgcn_sinf(ph), c = __builtin_amdgcn_cosf(ph);  // revolutions
                     z = make_float2(xv.x * c + xv.y * s, xv.y * c - xv.x * s);  // x * (c - i s)
                 }
                 win[wave][p] = z;
@@ -137,15 +142,25 @@ __global__ __launch_bounds__(kThreads) void rsf_resample_k(ResampleArgs A) {
                         w = 1.f;
                     } else {
                         const float sx = ((hw - i) & 1) ? -sf : sf;  // sin(pi x)
+                        const float rx = __builtin_amdgcn_rcpf(kPiF * x);       // 1 / (pi x)
                         if (A.ip.kernel == 0) {
                             // sin(2 pi x / W) straight from x: x is exact (frac + integer) and
                             // an angle-addition form would cancel when x -> 0 off the centre tap
                             const float s2 = sinpif(2.f * x / (float)W);
-                            w = sx * s2 * (float)W / (2.f * kPiF * kPiF * x * x);
+                            w = sx * s2 * (0.5f * (float)W) * rx * rx;
                         } else {
+                            // sin(pi x) / (n tan(pi x / n)) = sinc(x) g(y), y = pi x / n, with
+                            // g = y / tan(y) (n even) or y / sin(y) (n odd), a series when small
                             const float y = kPiF * x / (float)A.ip.n;
-                            const float den = (float)A.ip.n * (A.ip.n_odd ? sinf(y) : tanf(y));
-                            w = sx / den;
+                            float g;
+                            if (fabsf(y) < 0.01f) {
+                                const float y2 = y * y;
+                                g = A.ip.n_odd ? 1.f + y2 * (1.f / 6.f + y2 * (7.f / 360.f))
+                                               : 1.f - y2 * (1.f / 3.f + y2 * (1.f / 45.f));
+                            } else {
+                                g = A.ip.n_odd ? y / sinf(y) : y / tanf(y);
+                            }
+                            w = sx * rx * g;
                         }
                     }
                     const float2 zz = win[wave][base + i - 1];

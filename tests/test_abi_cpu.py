@@ -76,3 +76,20 @@ def test_invalid_descriptors_rejected_before_device_use(lib):
         p = C.c_void_p()
         assert lib.rsf_plan_create(C.byref(p), C.byref(desc)) == code, lib.rsf_last_error()
         assert not p.value
+
+
+def test_fft_factorisation_covers_every_workload_length(lib):
+    """Every FFT length of the standard workloads, and of all 64 uneven
+    segments (even 7-smooth lengths), has a two-pass factorisation that fits
+    160 KiB of LDS; non-7-smooth lengths are refused."""
+    from oracle.fstat import NFFT_SMOOTH7, fft_length
+    from paper_0912_4255_amd.synth import c3_segment_lengths
+    lengths = [345600, 6912000, 10368000, 3456000]
+    lengths += [fft_length(n, NFFT_SMOOTH7) for n in c3_segment_lengths()]
+    for m in lengths:
+        l1, l2 = C.c_int32(), C.c_int32()
+        assert lib.rsf_fft_factor(m, 163840, 0, C.byref(l1), C.byref(l2)) == L.RSF_OK, (m, lib.rsf_last_error())
+        assert l1.value * l2.value == m and l1.value <= 10240
+    assert lib.rsf_fft_factor(2 * 11 * 1000, 163840, 0, None, None) == L.RSF_EUNSUPPORTED
+    assert lib.rsf_fft_factor(6912000, 163840, 7200, C.byref(l1), None) == L.RSF_OK and l1.value == 7200
+
