@@ -202,26 +202,26 @@ struct rsf_plan {
 namespace {
 
 struct WsLayout {
-    size_t flags, rs_main[RSF_MAX_DET], rs_tm[RSF_MAX_DET], partials, coef, abc_w, spill, map, cand, run, total;
+    size_t flags, rs_main[RSF_MAX_DET], rs_tm[RSF_MAX_DET], partials, coef, abc_w, spill, map, cand, run, mtmp[2],
+        total;
     int n_blocks;
     int64_t G;        // templates per FFT launch
     int64_t S;        // sky positions per resampling chunk
     int64_t rs_stride;
 };
 
-// Templates per FFT launch: 1 (plain) or 16..64 (batched, more for short
-// segments so that every launch carries a similar amount of work).
+// Templates per FFT launch: 1 (plain) or 64 (batched; the autotuned choice
+// for every standard shape on MI355X).
 int64_t batch_templates(const rsf_plan* p, int mode) {
     if (mode == RSF_MODE_PLAIN) return 1;
     if (p->g_override > 0) return p->g_override;
-    const int64_t scale = std::max<int64_t>(1, 3456000 / std::max<int64_t>(1, p->n));
-    return std::min<int64_t>(64, 16 * scale);
+    return 64;
 }
 
 // Spindowns sharing one read of a resampled row in the first FFT pass.
 int first_pass_share(const rsf_plan* p, int mode) {
     if (mode == RSF_MODE_PLAIN) return 1;
-    return p->fb_override > 0 ? p->fb_override : 4;
+    return p->fb_override > 0 ? p->fb_override : 16;
 }
 
 int64_t batch_skies(int64_t n_sky, int64_t n_fdot, int64_t G, int mode) {
@@ -229,6 +229,13 @@ int64_t batch_skies(int64_t n_sky, int64_t n_fdot, int64_t G, int mode) {
     const int64_t per = std::max<int64_t>(1, (4 * G) / std::max<int64_t>(1, n_fdot));
     return std::max<int64_t>(1, std::min<int64_t>({n_sky, per, 64}));
 }
+
+// Merge cand (n_cand items) and run_in (k items, may be null) into the k
+// best, written to run_out (and entries): levels of one-block-per-4096-items
+// reductions through tmp[0], tmp[1] until one block remains.
+hipError_t topk_merge_levels(const rsf_plan* p, hipStream_t s, const TopkItem* cand, int64_t n_cand,
+                             const TopkItem* run_in, TopkItem* run_out, int k, int64_t n_fdot, void* entries,
+                             TopkItem* const tmp[2]);
 
 WsLayout fstat_layout(const rsf_plan* p, int64_t n_sky, int64_t n_fdot, int mode, bool topk) {
     WsLayout L{};
@@ -260,9 +267,16 @@ WsLayout fstat_layout(const rsf_plan* p, int64_t n_sky, int64_t n_fdot, int mode
         L.map = off;
         off = align_up(off + (size_t)L.G * p->n_out * sizeof(float));
         L.cand = off;
-        off = align_up(off + (size_t)topk_scan_blocks(L.G * p->n_out) * kTopkMax * sizeof(TopkItem));
+        off = align_up(off + (size_t)topk_scan_chunks(L.G * p->n_out) * kTopkMax * sizeof(TopkItem));
         L.run = off;
         off = align_up(off + 2 * kTopkMax * sizeof(TopkItem));
+        // outputs of the first merge level (and of any further level)
+        const int64_t n1 = topk_scan_chunks(L.G * p->n_out) * kTopkMax + kTopkMax;
+        const int64_t b1 = (n1 + topk_merge_per_block() - 1) / topk_merge_per_block();
+        for (int i = 0; i < 2; ++i) {
+            L.mtmp[i] = off;
+            off = align_up(off + (size_t)b1 * kTopkMax * sizeof(TopkItem));
+        }
     }
     L.total = off;
     return L;
@@ -756,33 +770,51 @@ int run_fstat(const rsf_plan* p, const rsf_segment* seg, const double* sky, int6
                 ta.k = k;
                 ta.cand = (TopkItem*)(w + L.cand);
                 RSF_HIP(timed(p, K_TOPK, s, [&] { return launch_topk_scan(ta, s); }), "topk scan launch");
-                TopkMergeArgs ma{};
-                ma.cand = ta.cand;
-                ma.n_cand = (int64_t)topk_scan_blocks(ta.n_vals) * k;
-                ma.run_in = have_run ? run[cur] : nullptr;
-                ma.run_out = run[cur ^ 1];
-                ma.k = k;
-                ma.n_fdot = n_fdot;
-                ma.n_out = p->n_out;
-                RSF_HIP(timed(p, K_TOPK, s, [&] { return launch_topk_merge(ma, s); }), "topk merge launch");
+                TopkItem* const tmp[2] = {(TopkItem*)(w + L.mtmp[0]), (TopkItem*)(w + L.mtmp[1])};
+                RSF_HIP(topk_merge_levels(p, s, ta.cand, topk_scan_chunks(ta.n_vals) * k,
+                                          have_run ? run[cur] : nullptr, run[cur ^ 1], k, n_fdot, nullptr, tmp),
+                        "topk merge launch");
                 cur ^= 1;
                 have_run = true;
             }
         }
     }
     if (want_topk) {
+        TopkItem* const tmp[2] = {(TopkItem*)(w + L.mtmp[0]), (TopkItem*)(w + L.mtmp[1])};
+        RSF_HIP(topk_merge_levels(p, s, run[cur], 0, run[cur], run[cur ^ 1], k, n_fdot, topk, tmp),
+                "topk final merge launch");
+    }
+    return RSF_OK;
+}
+
+hipError_t topk_merge_levels(const rsf_plan* p, hipStream_t s, const TopkItem* cand, int64_t n_cand,
+                             const TopkItem* run_in, TopkItem* run_out, int k, int64_t n_fdot, void* entries,
+                             TopkItem* const tmp[2]) {
+    const int64_t per = topk_merge_per_block();
+    int b = 0;
+    for (;;) {
         TopkMergeArgs ma{};
-        ma.cand = run[cur];
-        ma.n_cand = 0;
-        ma.run_in = run[cur];
-        ma.run_out = run[cur ^ 1];
+        ma.cand = cand;
+        ma.n_cand = n_cand;
+        ma.run_in = run_in;
         ma.k = k;
         ma.n_fdot = n_fdot;
         ma.n_out = p->n_out;
-        ma.entries = topk;
-        RSF_HIP(timed(p, K_TOPK, s, [&] { return launch_topk_merge(ma, s); }), "topk final merge launch");
+        const int64_t total = n_cand + (run_in ? k : 0);
+        const int64_t blocks = (total + per - 1) / per;
+        if (blocks <= 1) {
+            ma.run_out = run_out;
+            ma.entries = entries;
+            return timed(p, K_TOPK, s, [&] { return launch_topk_merge(ma, s); });
+        }
+        ma.out_blocks = tmp[b];
+        const hipError_t e = timed(p, K_TOPK, s, [&] { return launch_topk_merge(ma, s); });
+        if (e != hipSuccess) return e;
+        cand = tmp[b];
+        n_cand = blocks * k;
+        run_in = nullptr;
+        b ^= 1;
     }
-    return RSF_OK;
 }
 }  // namespace
 

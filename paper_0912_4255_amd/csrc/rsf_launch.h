@@ -18,9 +18,10 @@ size_t fft_pass_b_lds(int LB, int n_sky_l);
 hipError_t fft_set_lds_limits(size_t bytes);
 int fft_pass_max_elems();
 
-int topk_scan_blocks(int64_t n_vals);
+int64_t topk_scan_chunks(int64_t n_vals);  // candidate groups (k each) of a scan
 hipError_t launch_topk_scan(const TopkScanArgs& a, hipStream_t s);
 hipError_t launch_topk_merge(const TopkMergeArgs& a, hipStream_t s);
+int topk_merge_per_block();
 hipError_t launch_fill_u32(unsigned int* p, int n, unsigned int v, hipStream_t s);
 
 int point_blocks(int64_t P);

@@ -181,7 +181,8 @@ struct TopkMergeArgs {
     const TopkItem* cand;     // n_cand items
     int64_t n_cand;
     const TopkItem* run_in;   // k items (may be null: start empty)
-    TopkItem* run_out;        // k items
+    TopkItem* run_out;        // k items (one-block grid)
+    TopkItem* out_blocks;     // [gridDim.x][k] items (grids of several blocks)
     int k;
     int64_t n_fdot, n_out;
     void* entries;            // rsf_topk_entry[k] written if not null

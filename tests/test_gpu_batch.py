@@ -71,6 +71,30 @@ def test_topk_matches_map_selection(gpu_lib, k):
     assert np.array_equal(vals, maps.reshape(-1)[flat])
 
 
+@pytest.mark.parametrize("k", [10, 37])
+def test_topk_large_map_multilevel_merge(gpu_lib, k):
+    """A full-band map of 42 templates x 432,000 bins (18 M values): the scan
+    leaves more candidates than one merge block takes, so the merge runs in
+    levels; the result equals the selection over the whole map."""
+    import torch
+    w = synth.small_workload(n=216000, dt=0.5, kernel=synth.KERNEL_DIRICHLET, taps=16, band=(99.0, 101.0))
+    sky = synth.uniform_sky(np.random.default_rng(5), 6)
+    fdot = synth.fdot_grid(7)
+    xs, gaps = make_inputs(w, seed=4)
+    plan = gpu_lib.Plan(w)
+    assert plan.n_out == 432000
+    tx, tg = to_gpu(xs, gaps)
+    ts, tf = torch.from_numpy(sky).cuda(), torch.from_numpy(fdot).cuda()
+    maps = plan.fstat(tx, tg, ts, tf).cpu().numpy()
+    vals, ids = plan.topk(tx, tg, ts, tf, k=k)
+    vals, ids = vals.cpu().numpy(), ids.cpu().numpy()
+    flat = numpy_topk(maps, k)
+    n_out = plan.n_out
+    exp_ids = np.stack([flat // (n_out * 7), (flat // n_out) % 7, flat % n_out], axis=1)
+    assert np.array_equal(ids, exp_ids)
+    assert np.array_equal(vals, maps.reshape(-1)[flat])
+
+
 def test_topk_uneven_segments_against_oracle(gpu_lib):
     """Three back-to-back segments of different lengths (7-smooth FFT
     lengths), each with an injection: every entry of a segment's top-10
