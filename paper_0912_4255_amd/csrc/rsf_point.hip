@@ -323,7 +323,9 @@ __global__ __launch_bounds__(kThreads, 2) void rsf_point_k(PointArgs A) {
                     }
                 }
                 if (any && !ok) overflow = true;
-                __syncthreads();
+                // the window is this wave's own: its LDS operations complete in
+                // order, so a wave-level barrier suffices
+                __builtin_amdgcn_wave_barrier();
                 if (valid && ok) {
                     // interpolation (and derivative pieces)
                     const float sf = __builtin_amdgcn_sinf(0.5f * frac), cf = __builtin_amdgcn_cosf(0.5f * frac);
@@ -411,7 +413,7 @@ __global__ __launch_bounds__(kThreads, 2) void rsf_point_k(PointArgs A) {
                 } else if (valid && !ok) {
                     acc[S_FA] = __longlong_as_double(0x7ff8000000000000LL);
                 }
-                __syncthreads();
+                __builtin_amdgcn_wave_barrier();  // the next run rewrites this wave's window
             }
         }
     }

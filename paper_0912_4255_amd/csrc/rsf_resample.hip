@@ -128,7 +128,9 @@ __global__ __launch_bounds__(kThreads) void rsf_resample_k(ResampleArgs A) {
             }
         }
         if (any && !ok) window_overflow = true;
-        __syncthreads();
+        // the window is this wave's own: its LDS operations complete in order,
+        // so a wave-level barrier (no workgroup synchronisation) suffices
+        __builtin_amdgcn_wave_barrier();
 
         float2 zt = make_float2(0.f, 0.f);
         if (valid) {
@@ -190,8 +192,9 @@ __global__ __launch_bounds__(kThreads) void rsf_resample_k(ResampleArgs A) {
             tile_mask[ia][0] = (uint32_t)bal;
             tile_mask[ia][1] = (uint32_t)(bal >> 32);
         }
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();  // the next run rewrites this wave's window
     }
+    __syncthreads();  // the tile rows of all waves are complete
 
     if (window_overflow && lane == 0) atomicOr(A.flags, 2u);
 
