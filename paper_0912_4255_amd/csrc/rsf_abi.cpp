@@ -119,7 +119,7 @@ bool choose_factors(int64_t n_fft, int lds_max, int fft_l1, int* out_la, int* ou
         if (fft_l1 > 0 && la != fft_l1) continue;
         FftStages sa, sb;
         if (!radix_plan((int)la, 1, kFftThreads, kFftEPT, &sa) ||
-            !radix_plan((int)lb, kPassBCols, kFftThreads, kPassBEPT, &sb) ||
+            !radix_plan((int)lb, kPassBCols, kPassBThreads, kPassBEPT, &sb) ||
             fft_pass_b_lds((int)lb, 64) > (size_t)lds_max)
             continue;
         const double lds_a = (double)la * 16, lds_b = (double)lb * 128;
@@ -427,7 +427,7 @@ int rsf_plan_create(rsf_plan** out, const rsf_plan_desc* d) {
     p->LA = best_la;
     p->LB = best_lb;
     radix_plan(p->LA, 1, kFftThreads, kFftEPT, &p->stA);
-    radix_plan(p->LB, kPassBCols, kFftThreads, kPassBEPT, &p->stB);
+    radix_plan(p->LB, kPassBCols, kPassBThreads, kPassBEPT, &p->stB);
     p->P = (p->n + p->LB - 1) / p->LB;
     p->n_groups = (p->LA + kPassBCols - 1) / kPassBCols;
     if (p->P > p->LA) {

@@ -273,13 +273,18 @@ struct StageShape {
 // Element (row, column b) of a batch of B columns held in LDS: interleaved
 // (row B + b), or in groups of four columns, group g a contiguous [row][4]
 // block starting at g gs.
+// Element index = row * rowstride() + col(b).
 template <int B>
 struct Interleaved {
+    __device__ __forceinline__ static constexpr int rowstride() { return B; }
+    __device__ __forceinline__ int col(int b) const { return b; }
     __device__ __forceinline__ int operator()(int row, int b) const { return row * B + b; }
 };
 struct Grouped4 {
     int gs;
-    __device__ __forceinline__ int operator()(int row, int b) const { return row * 4 + (b >> 2) * gs + (b & 3); }
+    __device__ __forceinline__ static constexpr int rowstride() { return 4; }
+    __device__ __forceinline__ int col(int b) const { return (b >> 2) * gs + (b & 3); }
+    __device__ __forceinline__ int operator()(int row, int b) const { return row * 4 + col(b); }
 };
 
 // One butterfly of a Stockham stage: x[j + r L/R] of column b, r < R ...
@@ -288,8 +293,11 @@ struct Grouped4 {
 template <int R, typename LAY, bool HZ = false>
 __device__ __forceinline__ void bfly_load(const cp* __restrict__ s, int j, int b, int LR, const LAY& lay,
                                           cp (&v)[R]) {
+    // element j + r LR of column b: one base and a uniform stride
+    const cp* p = s + (j * LAY::rowstride() + lay.col(b));
+    const int st = LR * LAY::rowstride();
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = (HZ && 2 * r >= R) ? make_float4(0.f, 0.f, 0.f, 0.f) : s[lay(j + r * LR, b)];
+    for (int r = 0; r < R; ++r) v[r] = (HZ && 2 * r >= R) ? make_float4(0.f, 0.f, 0.f, 0.f) : p[r * st];
 }
 // ... times the stage twiddles W_{Ns R}^{k r} (k = j mod Ns), then the radix-R DFT.
 template <int R, typename TW>
@@ -321,7 +329,7 @@ __device__ __forceinline__ void stage_compute(const cp* __restrict__ s, int L, i
     for (int q = 0; q < MAXB; ++q) {
         const int bf = tid + q * NT;
         if (bf < nb) {
-            const int j = bf / B, b = bf - j * B;
+            const int j = (unsigned)bf / B, b = (unsigned)bf % B;
             int jq, k;
             divmod_small(j, Ns, inv_ns, jq, k);
             bfly_load<R, LAY, HZ>(s, j, b, LR, lay, v[q]);
@@ -345,12 +353,14 @@ __device__ __forceinline__ void stockham_stage(cp* __restrict__ s, int L, int Ns
     for (int q = 0; q < MAXB; ++q) {
         const int bf = tid + q * NT;
         if (bf < nb) {
-            const int j = bf / B, b = bf - j * B;
+            const int j = (unsigned)bf / B, b = (unsigned)bf % B;
             int jq, k;
             divmod_small(j, Ns, inv_ns, jq, k);
             const int base = jq * Ns * R + k;
+            cp* p = s + (base * LAY::rowstride() + lay.col(b));
+            const int st = Ns * LAY::rowstride();
 #pragma unroll
-            for (int r = 0; r < R; ++r) s[lay(base + r * Ns, b)] = v[q][r];
+            for (int r = 0; r < R; ++r) p[r * st] = v[q][r];
         }
     }
     __syncthreads();
@@ -378,7 +388,7 @@ __device__ __forceinline__ void stockham_last(const cp* __restrict__ s, int L, i
         for (int q = 0; q < MAXB; ++q) {
             const int bf = tid + q * NT;
             if (bf < nb) {
-                const int j = bf / B, b = bf - j * B;
+                const int j = (unsigned)bf / B, b = (unsigned)bf % B;
                 bfly_load<R, LAY>(s, j, b, LR, lay, v[q]);
             }
         }
@@ -387,7 +397,7 @@ __device__ __forceinline__ void stockham_last(const cp* __restrict__ s, int L, i
         for (int q = 0; q < MAXB; ++q) {
             const int bf = tid + q * NT;
             if (bf < nb) {
-                const int j = bf / B, b = bf - j * B;
+                const int j = (unsigned)bf / B, b = (unsigned)bf % B;
                 int jq, k;
                 divmod_small(j, Ns, inv_ns, jq, k);
                 bfly_dft<R, TW>(k, Ns, tstride, tw, v[q]);
@@ -399,7 +409,7 @@ __device__ __forceinline__ void stockham_last(const cp* __restrict__ s, int L, i
         for (int q = 0; q < MAXB; ++q) {
             const int bf = tid + q * NT;
             if (bf < nb) {
-                const int j = bf / B, b = bf - j * B;
+                const int j = (unsigned)bf / B, b = (unsigned)bf % B;
                 cp v[R];
                 int jq, k;
                 divmod_small(j, Ns, inv_ns, jq, k);

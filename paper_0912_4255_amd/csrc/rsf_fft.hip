@@ -23,6 +23,7 @@ namespace rsf {
 
 namespace {
 constexpr int kNT = kFftThreads;
+constexpr int kNTB = kPassBThreads;
 constexpr int kEPT = kFftEPT;
 }  // namespace
 
@@ -208,7 +209,7 @@ __device__ __forceinline__ void passb_dma(const PassBArgs& B, int unit, float4* 
     const int blk = B.LB * kPassBCols;  // both groups of the block, contiguous in the spill
     const float4* base = B.spill + (int64_t)t * B.spill_tmpl_stride + (int64_t)c * blk;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int e0 = wave * 64; e0 < blk; e0 += kNT) {
+    for (int e0 = wave * 64; e0 < blk; e0 += kNTB) {
         const int e = e0 + lane;
         if (e < blk) {
             __builtin_amdgcn_global_load_lds((const void*)(base + e), (__attribute__((address_space(3))) void*)(dst + e0),
@@ -227,14 +228,18 @@ struct TwoFSink {
     __device__ __forceinline__ void put(int, int j, int b, cp (&v)[R]) {
         const int ka = ka0 + b;
         if (ka >= LA) return;
+        const int hnf = (nf + 1) >> 1;  // k < hnf: non-negative signed bin
+        const int kst = LA * LR;
+        int k = ka + LA * j;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const int k = ka + LA * (j + r * LR);
-            const int o = ((2 * k < nf) ? k : k - nf) - s_lo;
-            if (o >= 0 && o < n_out) {
+            const int o = ((k < hnf) ? k : k - nf) - s_lo;
+            if ((unsigned)o < (unsigned)n_out) {
                 const cp u = v[r];
-                out[o] = cA * (u.x * u.x + u.y * u.y) + cB * (u.z * u.z + u.w * u.w) + cC * (u.x * u.z + u.y * u.w);
+                out[(unsigned)o] =
+                    cA * (u.x * u.x + u.y * u.y) + cB * (u.z * u.z + u.w * u.w) + cC * (u.x * u.z + u.y * u.w);
             }
+            k += kst;
         }
     }
 };
@@ -249,7 +254,7 @@ struct PassBMid {
     }
 };
 
-__global__ __launch_bounds__(kNT) void rsf_fft_pass_b_k(PassBArgs B) {
+__global__ __launch_bounds__(kNTB) void rsf_fft_pass_b_k(PassBArgs B) {
     extern __shared__ float4 lds[];
     const int blk = B.LB * kPassBCols;
     const int buf_elems = ((blk + 63) / 64) * 64;
@@ -257,8 +262,8 @@ __global__ __launch_bounds__(kNT) void rsf_fft_pass_b_k(PassBArgs B) {
     const int n_hi = (B.LB + 31) >> kTwLoBits;
     float* cfl = reinterpret_cast<float*>(twl + 32 + n_hi);
     const int tid = threadIdx.x;
-    for (int i = tid; i < 32 + n_hi; i += kNT) twl[i] = (i < 32) ? B.tw_lo[i] : B.tw_hi[i - 32];
-    for (int i = tid; i < 4 * B.n_sky_l; i += kNT) cfl[i] = B.coef[i];
+    for (int i = tid; i < 32 + n_hi; i += kNTB) twl[i] = (i < 32) ? B.tw_lo[i] : B.tw_hi[i - 32];
+    for (int i = tid; i < 4 * B.n_sky_l; i += kNTB) cfl[i] = B.coef[i];
     const TwLds tw{twl, twl + 32};
     const Grouped4 lay{B.LB * kHalfCols};
     const int n_units = B.n_tmpl * B.n_groups;
@@ -280,7 +285,7 @@ __global__ __launch_bounds__(kNT) void rsf_fft_pass_b_k(PassBArgs B) {
         TwoFSink sink{B.twoF + out_row * B.n_out, B.LA, B.LB / r_last, c * kPassBCols, (int)B.n_fft, (int)B.s_lo,
                       (int)B.n_out, cfl[4 * s_l], cfl[4 * s_l + 1], cfl[4 * s_l + 2]};
         const PassBMid mid{&B, nunit < n_units ? nunit : -1, lds};
-        lds_fft_into<kNT, kPassBEPT, kPassBCols, true>(lds, B.st, tw, lay, sink, mid);
+        lds_fft_into<kNTB, kPassBEPT, kPassBCols, true>(lds, B.st, tw, lay, sink, mid);
         unit = nunit;
     }
 }
@@ -305,7 +310,7 @@ hipError_t launch_fft_pass_b(const PassBArgs& b, int n_cu, hipStream_t s) {
     const size_t lds = fft_pass_b_lds(b.LB, b.n_sky_l);
     const int n_items = b.n_tmpl * b.n_groups;
     const unsigned grid = (unsigned)std::max(1, std::min(n_items, n_cu));
-    hipLaunchKernelGGL(rsf_fft_pass_b_k, dim3(grid), dim3(kNT), lds, s, b);
+    hipLaunchKernelGGL(rsf_fft_pass_b_k, dim3(grid), dim3(kNTB), lds, s, b);
     return hipGetLastError();
 }
 

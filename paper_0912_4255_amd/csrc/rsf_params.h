@@ -16,7 +16,8 @@ constexpr int kMaxTaps = 32;
 constexpr int kMaxDet = 4;
 constexpr int kPassBCols = 8;       // columns per second-pass workgroup (8 x 16 B = 128 B rows)
 constexpr int kTwSplitBits = 12;    // inter-pass twiddle W_N^m = hi[m >> 12] * lo[m & 4095]
-constexpr int kFftThreads = 512;    // threads of an FFT-pass workgroup
+constexpr int kFftThreads = 512;    // threads of a first-pass workgroup
+constexpr int kPassBThreads = 768;  // threads of a second-pass workgroup (3 waves per SIMD)
 // complex pairs held per thread in a first-pass stage: 21 lets radix 3 and 7
 // stages run 7 and 3 butterflies per thread (lengths with a factor 7 up to
 // 10752); radices 2, 4, 5, 6, 8 ... 16 hold the same number as at 20
