@@ -124,6 +124,58 @@ def test_fstat_two_detectors(gpu_lib):
         assert np.all(np.abs(got[i] - ref) <= twoF_tol(ref))
 
 
+def test_fstat_four_detectors(gpu_lib):
+    """The largest detector set the library takes (4): noise-weighted sums of
+    four sites with unequal noise levels against the oracle."""
+    import torch
+    d3 = synth.Detector(lat=43.63 * synth.DEG, lon=10.50 * synth.DEG, gamma=115.6 * synth.DEG, sigma2=0.8)
+    d4 = synth.Detector(lat=36.41 * synth.DEG, lon=137.31 * synth.DEG, gamma=28.3 * synth.DEG, sigma2=2.0)
+    w = synth.with_detectors(_small(synth.KERNEL_DIRICHLET, 16, n_det=2, gaps=False),
+                             [synth.DET_H, synth.DET_L, d3, d4])
+    w.gaps = [np.zeros((0, 2), np.int64)] * 4
+    inj = _inj(w, alpha=2.1, delta=0.4)
+    xs, gaps = make_inputs(w, seed=8, injections=[inj])
+    plan = gpu_lib.Plan(w)
+    tx, tg = to_gpu(xs, gaps)
+    fd = np.array([inj.fdot, 0.0])
+    got = plan.fstat(tx, tg, torch.tensor([[2.1, 0.4]], dtype=torch.float64).cuda(),
+                     torch.from_numpy(fd).cuda()).cpu().numpy()
+    rss = _oracle_rs(w, xs, gaps, 2.1, 0.4)
+    for i in range(2):
+        ref = of.fstat_band(rss, w.detectors, fd[i], plan.n_fft, plan.s_lo, plan.n_out)
+        assert np.all(np.abs(got[i] - ref) <= twoF_tol(ref))
+
+
+def test_length_one_second_pass(gpu_lib):
+    """A tiny segment with the whole transform in the first pass (L2 = 1,
+    forced): the second pass runs no stage, only the 2F reduction."""
+    import torch
+    from paper_0912_4255_amd.api import plan_desc_from_workload
+    w = _small(synth.KERNEL_LANCZOS, 8, n=1000, dt=4.0)
+    xs, gaps = make_inputs(w, seed=9, injections=[_inj(w, f_off_bins=200.5)])
+    d = plan_desc_from_workload(w)
+    d.fft_l1 = 2000
+    plan = gpu_lib.Plan(desc=d)
+    assert (plan.fft_l1, plan.fft_l2) == (2000, 1)
+    tx, tg = to_gpu(xs, gaps)
+    fd = np.array([-3e-10])
+    got = plan.fstat(tx, tg, torch.tensor([[1.2, 0.3]], dtype=torch.float64).cuda(),
+                     torch.from_numpy(fd).cuda()).cpu().numpy()[0]
+    rss = _oracle_rs(w, xs, gaps, 1.2, 0.3)
+    ref = of.fstat_band(rss, w.detectors, fd[0], plan.n_fft, plan.s_lo, plan.n_out)
+    assert np.all(np.abs(got - ref) <= twoF_tol(ref))
+
+
+def test_batching_query(gpu_lib):
+    w = _small(synth.KERNEL_DIRICHLET, 16)
+    plan = gpu_lib.Plan(w)
+    assert plan.batching(1, 1000) == (16, 64, 1)
+    assert plan.batching(1, 1000, gpu_lib.RSF_MODE_PLAIN) == (1, 1, 1)
+    assert plan.batching(8, 16) == (16, 64, 8)
+    plan.set_batching(4, 32)
+    assert plan.batching(100, 16)[:2] == (4, 32)
+
+
 def test_c1_full_size(gpu_lib):
     """Workload C1 end to end: every bin of the full 2 Hz band."""
     import torch
