@@ -220,13 +220,14 @@ template <> struct Dft<15> : DftCT<3, 5> {};
 template <> struct Dft<16> : DftCT<4, 4> {};
 
 // ---------------------------------------------------------------------------
-// One Stockham stage of a batch of B interleaved transforms of length L kept
-// in LDS (element (n, b) at n*B + b).  Stage with radix R after Ns points have
-// been combined: butterfly j reads n = j + r L/R, multiplies input r by
+// One Stockham stage of a batch of B transforms of length L kept in LDS
+// (element (n, b) placed by a layout policy: interleaved columns, or groups
+// of four).  Stage with radix R after Ns points have been combined:
+// butterfly j reads n = j + r L/R, multiplies input r by
 // W_{Ns R}^{r (j mod Ns)}, takes the R-point DFT and writes output r to
 // (j div Ns) Ns R + (j mod Ns) + r Ns.  In place: all butterflies of the
 // thread are read into registers, the block synchronises, then they are
-// written.  tw is the length-L table W_L^m; W_{Ns R}^{x} = W_L^{x L/(Ns R)}.
+// written.  tw(m) = W_L^m, and W_{Ns R}^{x} = W_L^{x L/(Ns R)}.
 // ---------------------------------------------------------------------------
 // q = j / d and r = j % d for 0 <= j < 2^22 from a float reciprocal: the
 // product is off by at most one, which the correction step removes.
@@ -242,12 +243,7 @@ __device__ __forceinline__ void divmod_small(int j, int d, float inv_d, int& q, 
     }
 }
 
-// Twiddle sources for the stages: W_L^m from a length-L table in global
-// memory, or from a two-level table in LDS, W_L^m = lo[m % 32] * hi[m / 32].
-struct TwGlobal {
-    const float2* __restrict__ t;
-    __device__ __forceinline__ float2 operator()(int m) const { return t[m]; }
-};
+// Stage twiddles from a two-level table in LDS, W_L^m = lo[m % 32] * hi[m / 32].
 struct TwLds {
     const float2* lo;  // 32 entries
     const float2* hi;  // ceil(L / 32) entries

@@ -9,11 +9,12 @@
 //   y^a = sum_X w_X a z~ exp(-i Phi_s),  y^b likewise  (eq. eq4pt1, FP64 phase)
 // from the resampled series (stored transposed, so the row is contiguous),
 // transforms the row in LDS (both spectra in one float4 per element), applies
-// W_N^{n_b k_a} and spills in blocks of 8 consecutive k_a (128 B).
-// Pass B: one workgroup per 8 consecutive k_a.  It reads its contiguous
-// block, transforms the 8 columns over n_b in LDS and reduces every bin to
-// 2F = cA |f_a|^2 + cB |f_b|^2 + cC Re(f_a f_b^*), writing the reported band
-// in ascending frequency.
+// W_N^{n_b k_a} and spills in groups of 4 consecutive k_a (64-B rows).
+// Pass B: persistent workgroups over blocks of 8 consecutive k_a (two
+// adjacent spill groups, one contiguous run).  Each block is transformed
+// over n_b in LDS and every bin reduced to
+// 2F = cA |f_a|^2 + cB |f_b|^2 + cC Re(f_a f_b^*), written in ascending
+// frequency over the reported band.
 #include <algorithm>
 
 #include "rsf_device.h"
@@ -73,10 +74,10 @@ __device__ __forceinline__ void accumulate_integrand(cp& y, const Sample& p, dou
     y.w += p.wb * ei;
 }
 
-// Spill layout: 4-column groups, float4 [template][k_a / 4][n_b][k_a % 4], so
-// that each half of a second-pass block (4 columns x LB rows) is one
+// Spill layout: 4-column groups, float4 [template][k_a / 4][n_b][k_a % 4]:
+// the two groups of a second-pass block are adjacent, so the block is one
 // contiguous run and every cache line is fetched once.
-constexpr int kHalfCols = kPassBCols / 2;
+constexpr int kGroupCols = kPassBCols / 2;
 
 // Writer of the first pass's last stage: output k_a = j + r L1/R of the row
 // transform, times the inter-pass twiddle W_N^{n_b k_a}, goes straight from
@@ -98,7 +99,7 @@ struct SpillSink {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const uint32_t k = (uint32_t)(jv + r * LR);
-            const uint32_t off = (((k >> 2) * (uint32_t)LB + (uint32_t)n_b) * kHalfCols + (k & 3u)) * 16u;
+            const uint32_t off = (((k >> 2) * (uint32_t)LB + (uint32_t)n_b) * kGroupCols + (k & 3u)) * 16u;
             *reinterpret_cast<float4*>(out + off) = cp_rot(v[r], w);
             if (r + 1 < R) w = c_mul(w, w_lr);
         }
@@ -265,7 +266,7 @@ __global__ __launch_bounds__(kNTB) void rsf_fft_pass_b_k(PassBArgs B) {
     for (int i = tid; i < 32 + n_hi; i += kNTB) twl[i] = (i < 32) ? B.tw_lo[i] : B.tw_hi[i - 32];
     for (int i = tid; i < 4 * B.n_sky_l; i += kNTB) cfl[i] = B.coef[i];
     const TwLds tw{twl, twl + 32};
-    const Grouped4 lay{B.LB * kHalfCols};
+    const Grouped4 lay{B.LB * kGroupCols};
     const int n_units = B.n_tmpl * B.n_groups;
     const int r_last = B.st.n_stages ? B.st.radix[B.st.n_stages - 1] : 1;
 

@@ -14,7 +14,7 @@ namespace rsf {
 constexpr int kMaxStages = 12;
 constexpr int kMaxTaps = 32;
 constexpr int kMaxDet = 4;
-constexpr int kPassBCols = 8;       // columns per second-pass workgroup (8 x 16 B = 128 B rows)
+constexpr int kPassBCols = 8;       // columns of a second-pass block (two 4-column spill groups)
 constexpr int kTwSplitBits = 12;    // inter-pass twiddle W_N^m = hi[m >> 12] * lo[m & 4095]
 constexpr int kFftThreads = 512;    // threads of a first-pass workgroup
 constexpr int kPassBThreads = 768;  // threads of a second-pass workgroup (3 waves per SIMD)
