@@ -138,7 +138,7 @@ __device__ __forceinline__ void kernel_w(const InterpDev& ip, float x, float sx,
         w = s0 * s1;
         if (GRAD) dw = ds0 * s1 + s0 * ds1 * (2.f / (float)W);
     } else {
-        const float y = kPiF * x / (float)ip.n;
+        const float y = x * (kPiF / (float)ip.n);
         float g, dg;
         if (fabsf(y) < 0.01f) {
             const float y2 = y * y;
@@ -191,6 +191,9 @@ __global__ __launch_bounds__(kThreads, 2) void rsf_point_k(PointArgs A) {
     const double w_sid = 2.0 * kPi * A.eph.inv_p_sid;
     const int W = A.ip.taps;
     const int hw = W / 2;
+    // Dirichlet weights by their small-argument series when pi x / n < 0.01 on every tap
+    const float pin = kPiF / (float)A.ip.n;
+    const bool dir_series = A.ip.kernel == 1 && pin * (float)(hw + 1) < 0.01f;
 
     double acc[S_USED];
 #pragma unroll
@@ -334,12 +337,27 @@ __global__ __launch_bounds__(kThreads, 2) void rsf_point_k(PointArgs A) {
                     for (int i = 1; i <= W; ++i) {
                         const float x = frac + (float)(hw - i);
                         const bool odd = (hw - i) & 1;
+                        const float sx = odd ? -sf : sf, cx = odd ? -cf : cf;  // sin, cos of pi x
                         float w, dw = 0.f;
                         if (x == 0.f) {
                             w = 1.f;
                             dw = 0.f;
+                        } else if (dir_series) {
+                            // Dirichlet kernel of a long series: sinc(x) g(y), y = pi x / n
+                            // small, g = y / tan(y) (n even) or y / sin(y) (n odd) as a series
+                            float s0, ds0;
+                            sinc_d(x, sx, cx, s0, ds0);
+                            const float y = x * pin, y2 = y * y;
+                            const float g = A.ip.n_odd ? 1.f + y2 * (1.f / 6.f + y2 * (7.f / 360.f))
+                                                       : 1.f - y2 * (1.f / 3.f + y2 * (1.f / 45.f));
+                            w = s0 * g;
+                            if (GRAD) {
+                                const float dg = A.ip.n_odd ? y * (1.f / 3.f + y2 * (7.f / 90.f))
+                                                            : -y * (2.f / 3.f + y2 * (4.f / 45.f));
+                                dw = ds0 * g + s0 * dg * pin;
+                            }
                         } else {
-                            kernel_w<GRAD>(A.ip, x, odd ? -sf : sf, odd ? -cf : cf, w, dw);
+                            kernel_w<GRAD>(A.ip, x, sx, cx, w, dw);
                         }
                         const float4 zz = win[wave][base + i - 1];
                         zt.x += w * zz.x;

@@ -66,6 +66,7 @@ __global__ __launch_bounds__(kThreads) void rsf_resample_k(ResampleArgs A) {
     const SkyFrame fr = sky_frame(alpha, delta);
     const int W = A.ip.taps;
     const int hw = W / 2;
+    const float pin = kPiF / (float)A.ip.n;  // pi / n of the Dirichlet kernel
     double sA = 0.0, sB = 0.0, sC = 0.0;
     bool window_overflow = false;
 
@@ -153,7 +154,7 @@ __global__ __launch_bounds__(kThreads) void rsf_resample_k(ResampleArgs A) {
                         } else {
                             // sin(pi x) / (n tan(pi x / n)) = sinc(x) g(y), y = pi x / n, with
                             // g = y / tan(y) (n even) or y / sin(y) (n odd), a series when small
-                            const float y = kPiF * x / (float)A.ip.n;
+                            const float y = x * pin;
                             float g;
                             if (fabsf(y) < 0.01f) {
                                 const float y2 = y * y;
