@@ -482,6 +482,8 @@ int rsf_plan_create(rsf_plan** out, const rsf_plan_desc* d) {
         const rsf_detector& D = d->det[X];
         DetDev& o = p->det[X];
         o.lon = D.lon;
+        o.clon = std::cos(D.lon);
+        o.slon = std::sin(D.lon);
         o.clat = std::cos(D.lat);
         o.slat = std::sin(D.lat);
         o.cgu = std::cos(D.gamma + M_PI / 4);
@@ -841,6 +843,14 @@ int point_common(const rsf_plan* p, const rsf_segment* seg, const double* theta,
     if (grad && (!g_twoF || !g_theta)) return fail(RSF_EINVAL, "g_twoF or g_theta is NULL");
     if (!grad && !twoF) return fail(RSF_EINVAL, "twoF is NULL");
     if (!ws) return fail(RSF_EINVAL, "workspace is NULL");
+    {
+        // the point kernel turns the run's orbital and sidereal angles by
+        // w |delta| with |delta| <= 63 dt + max|t_m|; its series needs <= 0.3
+        const double span = 63.0 * p->d.dt + p->eph.au_c + p->eph.re_c;
+        const double w_max = 2.0 * M_PI * std::max(std::fabs(p->eph.inv_p_sid), std::fabs(p->eph.inv_p_orb));
+        if (!(w_max * span <= 0.3))
+            return fail(RSF_EINVAL, "point search needs (63 dt + max|t_m|) w_sid <= 0.3 (dt up to about 55 s)");
+    }
     const PointLayout L = point_layout(p, n);
     if (ws_bytes < L.total) return fail(RSF_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, L.total);
     hipStream_t s = (hipStream_t)stream;

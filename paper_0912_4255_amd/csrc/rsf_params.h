@@ -49,6 +49,7 @@ struct EphDev {
 
 struct DetDev {
     double lon, clat, slat;
+    double clon, slon;          // cos/sin of the longitude
     double cgu, sgu, cgv, sgv;  // cos/sin of the arm azimuths gamma +- pi/4
     double w;                   // 1 / sigma^2
 };

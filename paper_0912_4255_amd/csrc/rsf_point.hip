@@ -71,6 +71,54 @@ __device__ __forceinline__ Orbit orbit_at(double tau, const EphDev& e, const Det
 
 __device__ __forceinline__ double dot3(double3 a, double3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
 
+// sin and cos of a small angle by their Taylor series through a^11 and
+// a^10; for |a| <= 0.3 the first omitted terms are below 2e-15.
+__device__ __forceinline__ void small_sincos(double a, double& s, double& c) {
+    const double a2 = a * a;
+    s = a * (1.0 - a2 * (1.0 / 6.0) *
+                       (1.0 - a2 * (1.0 / 20.0) *
+                                  (1.0 - a2 * (1.0 / 42.0) * (1.0 - a2 * (1.0 / 72.0) * (1.0 - a2 * (1.0 / 110.0))))));
+    c = 1.0 - a2 * 0.5 *
+                  (1.0 - a2 * (1.0 / 12.0) *
+                             (1.0 - a2 * (1.0 / 30.0) * (1.0 - a2 * (1.0 / 56.0) * (1.0 - a2 * (1.0 / 90.0)))));
+}
+
+// (sin, cos) of x + a from those of x and a
+__device__ __forceinline__ void rot_add(double sx, double cx, double sa, double ca, double& s, double& c) {
+    s = sx * ca + cx * sa;
+    c = cx * ca - sx * sa;
+}
+
+// Orbital and Greenwich sidereal angles at the first sample of the current
+// run of a wave, as (sin, cos) pairs.  A wave's runs start 256 samples apart,
+// so the pairs advance by a fixed rotation; a sample at tau_run + delta turns
+// them by the small angles w delta, with |delta| <= 63 dt + max|t_m| (the
+// host admits dt up to 55 s, which keeps w_sid |delta| below 0.3).
+struct RunAngles {
+    double sl, cl, sg, cg;
+};
+
+// The orbit of detector d at tau_run + delta.
+__device__ __forceinline__ Orbit orbit_from(const RunAngles& ra, double delta, const EphDev& e, const DetDev& d,
+                                            double wo, double ws) {
+    double sa, ca, sb, cb, sl, cl, sg, cg, st, ct;
+    small_sincos(wo * delta, sa, ca);
+    small_sincos(ws * delta, sb, cb);
+    rot_add(ra.sl, ra.cl, sa, ca, sl, cl);
+    rot_add(ra.sg, ra.cg, sb, cb, sg, cg);
+    rot_add(sg, cg, d.slon, d.clon, st, ct);  // local sidereal angle
+    Orbit o;
+    o.r = make_double3(e.au_c * cl + e.re_c * d.clat * ct, e.au_c * e.ceps * sl + e.re_c * d.clat * st,
+                       e.au_c * e.seps * sl + e.re_c * d.slat);
+    o.v = make_double3(-e.au_c * wo * sl - e.re_c * ws * d.clat * st, e.au_c * wo * e.ceps * cl + e.re_c * ws * d.clat * ct,
+                       e.au_c * wo * e.seps * cl);
+    o.sl = sl;
+    o.cl = cl;
+    o.sth = st;
+    o.cth = ct;
+    return o;
+}
+
 // m . r_d / c and its first three time derivatives at the orbit o (each
 // part moves on a circle, so its second derivative is -w^2 times the
 // position and the third -w^2 times the velocity); rez = R_E sin(lat) / c.
@@ -200,6 +248,20 @@ __global__ __launch_bounds__(kThreads, 2) void rsf_point_k(PointArgs A) {
     for (int i = 0; i < S_USED; ++i) acc[i] = 0.0;
     bool overflow = false;
 
+    // angles at this wave's first run, and the rotation to the next run
+    const double wo = 2.0 * kPi * A.eph.inv_p_orb;
+    RunAngles ra;
+    double s_dl, c_dl, s_dg, c_dg;
+    {
+        const int64_t k_first = ((int64_t)blockIdx.x * kPointTiles * kTileA + wave) * kTileB;
+        const double tau0 = A.t_start + (double)k_first * A.dt;
+        sincos(A.eph.lambda0 + 2.0 * kPi * frac_rev(tau0 * A.eph.inv_p_orb), &ra.sl, &ra.cl);
+        sincos(A.eph.theta0 + 2.0 * kPi * frac_rev(tau0 * A.eph.inv_p_sid), &ra.sg, &ra.cg);
+        const double dtau = 4.0 * kTileB * A.dt;
+        sincos(wo * dtau, &s_dl, &c_dl);
+        sincos(w_sid * dtau, &s_dg, &c_dg);
+    }
+
     for (int tile = 0; tile < kPointTiles; ++tile) {
         const int64_t a0 = ((int64_t)blockIdx.x * kPointTiles + tile) * kTileA;
         for (int r = 0; r < kTileA / 4; ++r) {
@@ -218,9 +280,10 @@ __global__ __launch_bounds__(kThreads, 2) void rsf_point_k(PointArgs A) {
                 RoemerD x0{}, xa{}, xd{};  // expansions of n0.r, n0_alpha.r, n0_delta.r about T1
                 if (valid) {
                     // eq. eq21: one fixed-point step and one Newton step (residual below 1e-12 s)
-                    SiteAngles g0;
-                    T1 = tb - roemer(A.t_start + tb, n0, A.eph, D, &g0);
-                    const Orbit o1 = orbit_at(A.t_start + T1, A.eph, D);
+                    const double dl = (double)lane * A.dt;  // offset from the run's first sample
+                    const double tm0 = dot3(n0, orbit_from(ra, dl, A.eph, D, wo, w_sid).r);
+                    T1 = tb - tm0;
+                    const Orbit o1 = orbit_from(ra, dl - tm0, A.eph, D, wo, w_sid);
                     {
                         const double wo2 = 4.0 * kPi * kPi * A.eph.inv_p_orb * A.eph.inv_p_orb;
                         const double ws2 = w_sid * w_sid;
@@ -433,6 +496,8 @@ __global__ __launch_bounds__(kThreads, 2) void rsf_point_k(PointArgs A) {
                 }
                 __builtin_amdgcn_wave_barrier();  // the next run rewrites this wave's window
             }
+            rot_add(ra.sl, ra.cl, s_dl, c_dl, ra.sl, ra.cl);
+            rot_add(ra.sg, ra.cg, s_dg, c_dg, ra.sg, ra.cg);
         }
     }
     if (overflow && lane == 0) atomicOr(A.flags, 2u);
