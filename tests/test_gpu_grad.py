@@ -108,3 +108,32 @@ def test_autograd_function_and_gpu_finite_differences(gpu_lib):
             fd = (Fp - Fm) / (tp[p] - tm[p])
             scale = [1 / T0, 1 / T0 ** 2, 1e-5, 1e-5][p]
             assert abs(fd - g[i, p]) * scale <= 1e-2 * max(abs(g[i, p]) * scale, 1.0), (i, p, fd, g[i, p])
+
+
+def test_point_long_sampling_interval_and_range_check(gpu_lib):
+    """dt = 32 s: a wave's 64 samples plus the Roemer delay span about 2500 s,
+    so the per-sample orbital and sidereal turns reach w_sid * 2500 = 0.18 rad;
+    2F still matches the oracle.  dt = 60 s is past that range and the point
+    search refuses it."""
+    import torch
+    w = synth.small_workload(n=2700, dt=32.0, kernel=synth.KERNEL_DIRICHLET, taps=16)
+    df = 1.0 / (2 * w.segment.n * w.segment.dt)
+    inj = Injection(h0=3.0, cosi=0.2, psi=-0.3, phi0=2.0, f0=w.segment.f_het + 300.2 * df,
+                    fdot=0.0, alpha=0.9, delta=0.5)
+    xs, gaps = make_inputs(w, seed=21, injections=[inj])
+    plan = gpu_lib.Plan(w)
+    tx, tg = to_gpu(xs, gaps)
+    th = np.array([[inj.f0, 0.0, inj.alpha, inj.delta], [inj.f0 + 2.3 * df, 1e-10, 2.5, -1.0]])
+    got = plan.point(tx, tg, torch.from_numpy(th).cuda()).cpu().numpy()
+    prob = og.PointProblem(xs, gaps, w.segment, list(w.detectors), w.eph, w.kernel, w.taps)
+    ref = np.array([prob.twoF(t) for t in th])
+    assert np.all(np.abs(got - ref) <= 1e-4 * np.maximum(ref, 4.0)), (got, ref)
+    plan.close()
+
+    w60 = synth.small_workload(n=1440, dt=60.0, kernel=synth.KERNEL_DIRICHLET, taps=16)
+    xs, gaps = make_inputs(w60, seed=22)
+    plan = gpu_lib.Plan(w60)
+    tx, tg = to_gpu(xs, gaps)
+    with pytest.raises(Exception, match="point search needs"):
+        plan.point(tx, tg, torch.from_numpy(th[:1]).cuda())
+    plan.close()
