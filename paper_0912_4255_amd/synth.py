@@ -329,3 +329,64 @@ def small_workload(n: int = 21600, dt: float = 4.0, f_het: float = 100.0, kernel
 
 def with_detectors(w: Workload, dets) -> Workload:
     return dataclasses.replace(w, detectors=tuple(dets))
+
+
+# ----------------------------------------------------------------------------
+# Short Fourier transforms (the input of the frequency-domain front end)
+# ----------------------------------------------------------------------------
+
+@dataclass
+class SftSet:
+    """A set of SFT bands of one detector: SFT alpha starts at t_sft[alpha]
+    (seconds, same clock as t_start), covers sft_len raw samples of dt_raw,
+    and keeps bins k_lo .. k_lo + n_bins - 1 (frequency k / T_sft).  The front
+    end turns it into x_h[n_out] at t_start + j / band, heterodyned at f_het."""
+    sft_len: int
+    dt_raw: float
+    k_lo: int
+    n_bins: int
+    t_sft: np.ndarray
+    t_start: float
+    f_het: float
+    band: float
+    n_out: int
+    dk: int = 8
+    median_window: int = 101
+    band_taper: float = 0.05
+    edge_taper_s: float = 0.0
+
+    @property
+    def t_sft_len(self) -> float:
+        return self.sft_len * self.dt_raw
+
+
+def sft_noise(rng: np.random.Generator, n_sft: int, n_bins: int, power: float) -> np.ndarray:
+    """SFT bins of white noise: complex Gaussian with E|X|^2 = power, as
+    complex64 [n_sft][n_bins]."""
+    return gaussian_noise(rng, n_sft * n_bins, power).reshape(n_sft, n_bins)
+
+
+def sft_set_c2(n_missing: int = 48, seed_index: int = 6) -> Tuple[SftSet, np.ndarray]:
+    """SFT input of the T = 10 d, dt = 0.25 s segment: 480 slots of 1800 s
+    (raw rate 256 Hz), n_missing whole SFTs absent (placed uniformly by
+    rejection, as the 30-min gaps of the time-domain workload), output band
+    4 Hz around f_h = 101 Hz, kept bins covering the band plus the running
+    median and Dirichlet margins.  Returns (description, noise bins)."""
+    rng = streams(seed_index)[1]
+    T_sft, dt_raw = 1800.0, 1.0 / 256.0
+    n_slots = 480
+    missing = set()
+    while len(missing) < n_missing:
+        missing.add(int(rng.integers(1, n_slots - 1)))
+    t = np.array([a * T_sft for a in range(n_slots) if a not in missing], dtype=np.float64)
+    f_het, band = 101.0, 4.0
+    dk, w = 8, 101
+    margin = w // 2 + dk + 1
+    k_lo = int(round((f_het - band / 2) * T_sft)) - margin
+    n_bins = int(round(band * T_sft)) + 2 * margin
+    sft_len = int(round(T_sft / dt_raw))
+    desc = SftSet(sft_len=sft_len, dt_raw=dt_raw, k_lo=k_lo, n_bins=n_bins, t_sft=t, t_start=0.0,
+                  f_het=f_het, band=band, n_out=int(round(n_slots * T_sft * band)), dk=dk, median_window=w,
+                  band_taper=0.05, edge_taper_s=60.0)
+    X = sft_noise(streams(seed_index)[0], len(t), n_bins, float(sft_len))
+    return desc, X
