@@ -254,6 +254,77 @@ int rsf_profile_read(rsf_plan* plan, rsf_kernel_time* out, int max_kinds, int* n
  * and clear it; synchronises `stream`. */
 int rsf_get_flags(const rsf_plan* plan, void* ws, uint32_t* flags, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * SFT front end (paper Sec. III.B): from short Fourier transforms to the
+ * heterodyned, downsampled series x_h that the entry points above take.
+ *
+ * Input: SFTs X_{alpha,k} = sum_j x_{alpha,j} exp(-2 pi i j k / N) (eq. e25) of
+ * consecutive stretches of N = sft_len raw samples (T_sft = N dt_raw), of
+ * which bins k_lo .. k_lo + n_bins - 1 (frequency k / T_sft) are kept, as
+ * complex64 [n_sft][n_bins]; SFT alpha starts at t_sft[alpha] (host, seconds,
+ * increasing, on the clock of t_start).
+ * Steps (the summary closing Sec. III.B):
+ *   1. normalisation X^ = X / sqrt(S) (eq. dimlessSFTs1), S = running median
+ *      of |X|^2 over median_window bins (window clamped inside the stored
+ *      band) divided by ln 2; median_window = 0 skips it (S = 1);
+ *   2. chunks: SFTs whose start times differ by exactly T_sft;
+ *   3. per chunk of M SFTs, the long-baseline transform on the grid of
+ *      M' = the smallest 7-smooth number >= M (zero SFTs appended; M' = M
+ *      when M is 7-smooth): X_b = sum_alpha e^{-2 pi i b alpha / M'}
+ *      sum_{|k - k*| <= dk} X^_{alpha,k} P_{b,k}, k* = floor(b / M'), with the
+ *      large-N kernel P = sin(y)/y - i (1 - cos y)/y, y = 2 pi (b/M' - k)
+ *      (eqs. e9, e91, e75); terms outside the stored band are absent;
+ *   4. the band of B T_sft M' bins centred on bin f_h T_sft M' is relabelled
+ *      (f_h -> DC), multiplied by a Tukey window (cosine taper over a
+ *      fraction band_taper of the band) and inverse transformed; scale
+ *      1 / sqrt(B T_sft M' M), so normalised white noise has unit power;
+ *   5. the first B T_sft M samples are the chunk at t_c + j / B; they are
+ *      multiplied by exp(-2 pi i f_h (t_c - t_start)) (eq. hetStartCorr with
+ *      this interface's heterodyne sign), tapered over edge_taper_s seconds
+ *      at each chunk edge (Tukey) and written to x_h[(t_c - t_start) B + j];
+ *      samples outside every chunk are zero (gaps).
+ * Requirements: f_het T_sft an integer, B T_sft an even integer, f_het >=
+ * B/2, (t_sft - t_start) B integers, odd median_window <= min(n_bins, 511),
+ * dk <= 16, and every chunk's transform length decomposable (up to about
+ * 10^7 points); otherwise RSF_EINVAL / RSF_EUNSUPPORTED from
+ * rsf_sft_plan_create.
+ * ------------------------------------------------------------------------- */
+typedef struct rsf_sft_desc {
+    int64_t n_sft;          /* number of SFTs */
+    int64_t sft_len;        /* raw samples per SFT, N */
+    double dt_raw;          /* raw sampling interval, s */
+    int64_t k_lo;           /* first stored bin */
+    int64_t n_bins;         /* stored bins per SFT */
+    double t_start;         /* start of the output series, s */
+    double f_het;           /* heterodyne frequency, Hz */
+    double band;            /* output band B, Hz (output dt = 1/B) */
+    int64_t n_out;          /* output samples */
+    int32_t dk;             /* Dirichlet terms on each side of k* */
+    int32_t median_window;  /* running-median bins (odd), 0 = no normalisation */
+    double band_taper;      /* Tukey fraction of the band window, 0..1 */
+    double edge_taper_s;    /* taper at each chunk edge, s */
+} rsf_sft_desc;
+
+typedef struct rsf_sft_plan rsf_sft_plan;
+
+/* Chunking, per-chunk transform plans and their twiddle tables (device
+ * memory owned by the plan).  t_sft: host [n_sft]. */
+int rsf_sft_plan_create(rsf_sft_plan** out, const rsf_sft_desc* desc, const double* t_sft);
+int rsf_sft_plan_destroy(rsf_sft_plan* plan);
+/* Number of chunks and the gaps of the output series as half-open sample
+ * ranges (host [max_gaps][2]; *n_gaps is the full count even when larger
+ * than max_gaps).  Pure host query. */
+int rsf_sft_plan_query(const rsf_sft_plan* plan, int64_t* n_chunks, int64_t* gaps, int64_t max_gaps,
+                       int64_t* n_gaps);
+int rsf_sft_workspace_size(const rsf_sft_plan* plan, size_t* bytes);
+/* sft: complex64 [n_sft][n_bins] (device, read only); x_h: complex64 [n_out]
+ * (device, overwritten, gaps zero).  Asynchronous on `stream`. */
+int rsf_sft_heterodyne(const rsf_sft_plan* plan, const float* sft, float* x_h, void* ws, size_t ws_bytes,
+                       void* stream);
+/* Kernel timing of the plan's launches, as rsf_profile_enable/read. */
+int rsf_sft_profile_enable(rsf_sft_plan* plan, int on);
+int rsf_sft_profile_read(rsf_sft_plan* plan, rsf_kernel_time* out, int max_kinds, int* n_kinds);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* rsf_last_error(void);
 

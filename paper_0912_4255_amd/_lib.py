@@ -21,6 +21,8 @@ EXPORTS = [
     "rsf_resample", "rsf_fstat", "rsf_fstat_topk", "rsf_fstat_point", "rsf_fstat_backward",
     "rsf_get_flags", "rsf_last_error", "rsf_version", "rsf_profile_enable", "rsf_profile_read",
     "rsf_graph_create_fstat", "rsf_graph_create_topk", "rsf_graph_launch", "rsf_graph_destroy",
+    "rsf_sft_plan_create", "rsf_sft_plan_destroy", "rsf_sft_plan_query", "rsf_sft_workspace_size",
+    "rsf_sft_heterodyne", "rsf_sft_profile_enable", "rsf_sft_profile_read",
 ]
 
 
@@ -53,6 +55,13 @@ class Resampled(C.Structure):
 
 class TopkEntry(C.Structure):
     _fields_ = [("twoF", C.c_float), ("sky", C.c_int32), ("fdot", C.c_int32), ("bin", C.c_int32)]
+
+
+class SftDesc(C.Structure):
+    _fields_ = [("n_sft", C.c_int64), ("sft_len", C.c_int64), ("dt_raw", C.c_double), ("k_lo", C.c_int64),
+                ("n_bins", C.c_int64), ("t_start", C.c_double), ("f_het", C.c_double), ("band", C.c_double),
+                ("n_out", C.c_int64), ("dk", C.c_int32), ("median_window", C.c_int32),
+                ("band_taper", C.c_double), ("edge_taper_s", C.c_double)]
 
 
 class KernelTime(C.Structure):
@@ -94,6 +103,14 @@ def load(path=None):
     lib.rsf_graph_destroy.argtypes = [vp]
     lib.rsf_profile_enable.argtypes = [vp, i32]
     lib.rsf_profile_read.argtypes = [vp, C.POINTER(KernelTime), i32, C.POINTER(C.c_int)]
+    dp = C.POINTER(C.c_double)
+    lib.rsf_sft_plan_create.argtypes = [C.POINTER(vp), C.POINTER(SftDesc), dp]
+    lib.rsf_sft_plan_destroy.argtypes = [vp]
+    lib.rsf_sft_plan_query.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), i64, C.POINTER(i64)]
+    lib.rsf_sft_workspace_size.argtypes = [vp, C.POINTER(sz)]
+    lib.rsf_sft_heterodyne.argtypes = [vp, vp, vp, vp, sz, vp]
+    lib.rsf_sft_profile_enable.argtypes = [vp, i32]
+    lib.rsf_sft_profile_read.argtypes = [vp, C.POINTER(KernelTime), i32, C.POINTER(C.c_int)]
     lib.rsf_last_error.restype = C.c_char_p
     lib.rsf_last_error.argtypes = []
     lib.rsf_version.argtypes = []

@@ -294,3 +294,83 @@ class FStatFn(torch.autograd.Function):
 def fstat_point(plan, xs, gaps, theta):
     """Differentiable 2F at continuous parameters (see FStatFn)."""
     return FStatFn.apply(theta, plan, xs, gaps)
+
+
+def sft_desc_from_set(ss):
+    """rsf_sft_desc from a paper_0912_4255_amd.synth.SftSet."""
+    d = L.SftDesc()
+    d.n_sft = len(ss.t_sft)
+    d.sft_len = ss.sft_len
+    d.dt_raw = ss.dt_raw
+    d.k_lo = ss.k_lo
+    d.n_bins = ss.n_bins
+    d.t_start = ss.t_start
+    d.f_het = ss.f_het
+    d.band = ss.band
+    d.n_out = ss.n_out
+    d.dk = ss.dk
+    d.median_window = ss.median_window
+    d.band_taper = ss.band_taper
+    d.edge_taper_s = ss.edge_taper_s
+    return d
+
+
+class SftPlan:
+    """An rsf_sft_plan: chunking and per-chunk transform plans of one set of
+    SFT start times (paper Sec. III.B front end)."""
+
+    def __init__(self, sft_set=None, desc=None, t_sft=None):
+        import numpy as np
+        self.lib = L.load()
+        self.desc = desc if desc is not None else sft_desc_from_set(sft_set)
+        t = np.ascontiguousarray(t_sft if t_sft is not None else sft_set.t_sft, dtype=np.float64)
+        self._t = t
+        self._p = C.c_void_p()
+        L.check(self.lib.rsf_sft_plan_create(C.byref(self._p), C.byref(self.desc),
+                                             t.ctypes.data_as(C.POINTER(C.c_double))))
+        nc, ng = C.c_int64(), C.c_int64()
+        L.check(self.lib.rsf_sft_plan_query(self._p, C.byref(nc), None, 0, C.byref(ng)))
+        self.n_chunks = nc.value
+        g = np.zeros((max(ng.value, 1), 2), dtype=np.int64)
+        L.check(self.lib.rsf_sft_plan_query(self._p, None, g.ctypes.data_as(C.POINTER(C.c_int64)), ng.value,
+                                            C.byref(ng)))
+        self.gaps = g[:ng.value].copy()
+        b = C.c_size_t()
+        L.check(self.lib.rsf_sft_workspace_size(self._p, C.byref(b)))
+        self.ws_bytes = b.value
+
+    def workspace(self, device="cuda"):
+        return torch.empty(max(1, self.ws_bytes), dtype=torch.uint8, device=device)
+
+    def heterodyne(self, sft, out=None, ws=None):
+        """rsf_sft_heterodyne: complex64 [n_sft][n_bins] SFT bands -> x_h [n_out]."""
+        _need_cuda(sft, torch.complex64, "sft")
+        if tuple(sft.shape) != (self.desc.n_sft, self.desc.n_bins):
+            raise ValueError("sft must be [n_sft][n_bins]")
+        out = out if out is not None else torch.empty(self.desc.n_out, dtype=torch.complex64, device=sft.device)
+        _need_cuda(out, torch.complex64, "out")
+        if out.numel() != self.desc.n_out:
+            raise ValueError("out must hold n_out samples")
+        ws = ws if ws is not None else self.workspace(sft.device)
+        L.check(self.lib.rsf_sft_heterodyne(self._p, _ptr(sft), _ptr(out), _ptr(ws), ws.numel(), _stream()))
+        return out
+
+    def profile(self, on=True):
+        L.check(self.lib.rsf_sft_profile_enable(self._p, 1 if on else 0))
+
+    def profile_read(self):
+        buf = (L.KernelTime * 12)()
+        n = C.c_int()
+        L.check(self.lib.rsf_sft_profile_read(self._p, buf, 12, C.byref(n)))
+        return {buf[i].name.decode(): (buf[i].launches, buf[i].total_ms) for i in range(min(n.value, 12))}
+
+    def close(self):
+        if self._p:
+            self.lib.rsf_sft_plan_destroy(self._p)
+            self._p = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -148,9 +148,10 @@ struct Profiler {
     };
     std::vector<Rec> pending;
     std::vector<hipEvent_t> pool;
-    static constexpr int kKinds = 7;
+    static constexpr int kKinds = 11;
     const char* names[kKinds] = {"rsf_resample_k", "rsf_antenna_reduce_k", "rsf_fft_pass_a_k", "rsf_fft_pass_b_k",
-                                 "rsf_point_k",    "rsf_point_reduce_k",   "rsf_topk_k"};
+                                 "rsf_point_k",    "rsf_point_reduce_k",   "rsf_topk_k",       "rsf_sft_norm_k",
+                                 "rsf_sft_merge_k", "rsf_ifft_rows_k",     "rsf_ifft_cols_k"};
     int64_t launches[kKinds] = {};
     double ms[kKinds] = {};
 
@@ -172,7 +173,10 @@ struct Profiler {
         for (auto e : pool) (void)hipEventDestroy(e);
     }
 };
-enum { K_RESAMPLE = 0, K_REDUCE = 1, K_PASS_A = 2, K_PASS_B = 3, K_POINT = 4, K_POINT_REDUCE = 5, K_TOPK = 6 };
+enum {
+    K_RESAMPLE = 0, K_REDUCE = 1, K_PASS_A = 2, K_PASS_B = 3, K_POINT = 4, K_POINT_REDUCE = 5, K_TOPK = 6,
+    K_SFT_NORM = 7, K_SFT_MERGE = 8, K_IFFT_ROWS = 9, K_IFFT_COLS = 10
+};
 }  // namespace
 
 struct rsf_plan {
@@ -348,8 +352,7 @@ int check_segment(const rsf_plan* p, const rsf_segment* seg) {
 
 // Launch through fn(); with profiling on, bracket it with events on s.
 template <typename Fn>
-hipError_t timed(const rsf_plan* p, int kind, hipStream_t s, Fn fn) {
-    Profiler* pr = p->prof;
+hipError_t timed_pr(Profiler* pr, int kind, hipStream_t s, Fn fn) {
     if (!pr || !pr->on) return fn();
     hipEvent_t a = pr->get(), b = pr->get();
     if (a) (void)hipEventRecord(a, s);
@@ -357,6 +360,11 @@ hipError_t timed(const rsf_plan* p, int kind, hipStream_t s, Fn fn) {
     if (b) (void)hipEventRecord(b, s);
     if (a && b) pr->pending.push_back({kind, a, b});
     return e;
+}
+
+template <typename Fn>
+hipError_t timed(const rsf_plan* p, int kind, hipStream_t s, Fn fn) {
+    return timed_pr(p->prof, kind, s, fn);
 }
 
 }  // namespace
@@ -987,9 +995,10 @@ int rsf_profile_enable(rsf_plan* p, int on) {
     return RSF_OK;
 }
 
-int rsf_profile_read(rsf_plan* p, rsf_kernel_time* out, int max_kinds, int* n_kinds) {
-    if (!p || !n_kinds) return fail(RSF_EINVAL, "plan or n_kinds is NULL");
-    Profiler* pr = p->prof;
+}  // extern "C"
+
+namespace {
+int profile_read(Profiler* pr, rsf_kernel_time* out, int max_kinds, int* n_kinds) {
     for (auto& r : pr->pending) {
         RSF_HIP(hipEventSynchronize(r.b), "hipEventSynchronize");
         float ms = 0.f;
@@ -1015,6 +1024,14 @@ int rsf_profile_read(rsf_plan* p, rsf_kernel_time* out, int max_kinds, int* n_ki
     *n_kinds = n;
     return RSF_OK;
 }
+}  // namespace
+
+extern "C" {
+
+int rsf_profile_read(rsf_plan* p, rsf_kernel_time* out, int max_kinds, int* n_kinds) {
+    if (!p || !n_kinds) return fail(RSF_EINVAL, "plan or n_kinds is NULL");
+    return profile_read(p->prof, out, max_kinds, n_kinds);
+}
 
 int rsf_get_flags(const rsf_plan* p, void* ws, uint32_t* flags, void* stream) {
     if (!p || !ws || !flags) return fail(RSF_EINVAL, "plan, ws or flags is NULL");
@@ -1023,6 +1040,328 @@ int rsf_get_flags(const rsf_plan* p, void* ws, uint32_t* flags, void* stream) {
     RSF_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
     RSF_HIP(launch_fill_u32((unsigned int*)ws, 1, 0u, s), "flags clear");
     return RSF_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// SFT front end (paper Sec. III.B)
+// ---------------------------------------------------------------------------
+namespace {
+
+// W_len^{m step} for m < count, built in FP64 (long double angle), as FP32.
+std::vector<float2> root_table(int64_t len, int64_t count, int64_t step) {
+    std::vector<float2> t((size_t)count);
+    for (int64_t m = 0; m < count; ++m) {
+        const long double a = -2.0L * 3.14159265358979323846264338327950288L * (long double)((m * step) % len) /
+                              (long double)len;
+        t[(size_t)m] = make_float2((float)std::cos((double)a), (float)std::sin((double)a));
+    }
+    return t;
+}
+
+int64_t next_7smooth_i(int64_t n) {
+    int64_t m = std::max<int64_t>(1, n);
+    while (!is_7smooth(m)) ++m;
+    return m;
+}
+
+// Transform plan and tables of one chunk length n = B T_sft M'.
+struct SftXform {
+    int64_t n;
+    int L1, L2, n_groups;
+    FftStages st1, st2;
+    float2 *t1, *t1_hi, *t2, *t2_hi, *tw_lo, *tw_hi;
+};
+
+struct SftChunk {
+    int a0, M, Mp, xf;   // first SFT, count, 7-smooth grid, transform index
+    int64_t j0, n_keep;  // output offset and kept samples
+    float2 corr;         // exp(-2 pi i f_h (t_c - t_s))
+};
+
+}  // namespace
+
+struct rsf_sft_plan {
+    rsf_sft_desc d;
+    Profiler* prof;
+    int64_t band_bins, f_het_bins;
+    std::vector<SftXform> xf;
+    std::vector<SftChunk> chunks;
+    std::vector<int64_t> gaps;  // [n][2]
+    int64_t n_max;              // longest transform
+    size_t spill_max;           // float4 elements of the largest spill
+    size_t lds_max;
+};
+
+namespace {
+
+struct SftWs {
+    size_t xh, y, spill, total;
+};
+
+SftWs sft_ws(const rsf_sft_plan* p) {
+    SftWs L{};
+    size_t off = 0;
+    L.xh = off;
+    if (p->d.median_window > 0) off = align_up(off + (size_t)p->d.n_sft * p->d.n_bins * sizeof(float2));
+    L.y = off;
+    off = align_up(off + (size_t)p->n_max * sizeof(float2));
+    L.spill = off;
+    off = align_up(off + p->spill_max * sizeof(float4));
+    L.total = off;
+    return L;
+}
+
+void sft_free(rsf_sft_plan* p) {
+    for (auto& x : p->xf) {
+        (void)hipFree(x.t1);
+        (void)hipFree(x.t1_hi);
+        (void)hipFree(x.t2);
+        (void)hipFree(x.t2_hi);
+        (void)hipFree(x.tw_lo);
+        (void)hipFree(x.tw_hi);
+    }
+    delete p->prof;
+    delete p;
+}
+
+bool near_int(double x, double tol = 1e-6) { return std::fabs(x - std::nearbyint(x)) <= tol * std::max(1.0, std::fabs(x)); }
+
+}  // namespace
+
+extern "C" {
+
+int rsf_sft_plan_create(rsf_sft_plan** out, const rsf_sft_desc* d, const double* t_sft) {
+    if (!out || !d || !t_sft) return fail(RSF_EINVAL, "out, desc or t_sft is NULL");
+    *out = nullptr;
+    if (d->n_sft < 1 || d->sft_len < 1 || d->n_bins < 1 || d->n_out < 1 || d->k_lo < 0)
+        return fail(RSF_EINVAL, "n_sft, sft_len, n_bins and n_out must be positive and k_lo >= 0");
+    if (d->n_sft > INT32_MAX || d->n_bins > INT32_MAX || d->n_out > INT32_MAX / 2)
+        return fail(RSF_EINVAL, "sizes beyond the 32-bit indexing of the kernels");
+    if (!is_fin(d->dt_raw) || d->dt_raw <= 0 || !is_fin(d->band) || d->band <= 0 || !is_fin(d->f_het) ||
+        !is_fin(d->t_start) || !is_fin(d->band_taper) || d->band_taper < 0 || d->band_taper > 1 ||
+        !is_fin(d->edge_taper_s) || d->edge_taper_s < 0)
+        return fail(RSF_EINVAL, "non-finite or out-of-range dt_raw, band, f_het, t_start or tapers");
+    const double T = (double)d->sft_len * d->dt_raw;
+    const double bb = d->band * T, fb = d->f_het * T;
+    if (!near_int(bb) || (int64_t)std::nearbyint(bb) % 2 != 0 || !near_int(fb))
+        return fail(RSF_EINVAL, "B T_sft must be an even integer and f_het T_sft an integer");
+    if (d->f_het < 0.5 * d->band) return fail(RSF_EINVAL, "f_het must be at least B/2");
+    if (d->dk < 0 || 2 * d->dk + 1 > kSftMaxTerms) return fail(RSF_EINVAL, "dk must be in 0..16");
+    if (d->median_window != 0 &&
+        (d->median_window < 1 || d->median_window % 2 == 0 || d->median_window > kSftMaxWindow ||
+         d->median_window > d->n_bins))
+        return fail(RSF_EINVAL, "median_window must be 0 or odd, <= 511 and <= n_bins");
+    for (int64_t a = 0; a < d->n_sft; ++a) {
+        if (!is_fin(t_sft[a]) || (a > 0 && !(t_sft[a] > t_sft[a - 1])))
+            return fail(RSF_EINVAL, "t_sft must be finite and increasing");
+        if (!near_int((t_sft[a] - d->t_start) * d->band)) return fail(RSF_EINVAL, "(t_sft - t_start) B must be integers");
+    }
+
+    auto* p = new rsf_sft_plan();
+    p->d = *d;
+    p->prof = new Profiler();
+    p->band_bins = (int64_t)std::nearbyint(bb);
+    p->f_het_bins = (int64_t)std::nearbyint(fb);
+    p->n_max = 0;
+    p->spill_max = 0;
+    p->lds_max = 0;
+    int dev = 0, lds_dev = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&lds_dev, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || lds_dev <= 0)
+        lds_dev = 65536;
+    const int lds_cap = std::max(lds_dev, 163840);
+
+    // chunks: start times exactly T_sft apart
+    int64_t a0 = 0;
+    for (int64_t a = 1; a <= d->n_sft; ++a) {
+        if (a < d->n_sft && t_sft[a] - t_sft[a - 1] == T) continue;
+        SftChunk c{};
+        c.a0 = (int)a0;
+        c.M = (int)(a - a0);
+        c.Mp = (int)next_7smooth_i(c.M);
+        const int64_t n = p->band_bins * c.Mp;
+        if (c.Mp > kSftMaxGrid || n > INT32_MAX / 2) {
+            sft_free(p);
+            return fail(RSF_EUNSUPPORTED, "chunk transform of %lld points is too long", (long long)n);
+        }
+        int xi = -1;
+        for (size_t i = 0; i < p->xf.size(); ++i)
+            if (p->xf[i].n == n) xi = (int)i;
+        if (xi < 0) {
+            SftXform x{};
+            x.n = n;
+            if (!choose_factors(n, lds_cap, 0, &x.L1, &x.L2)) {
+                sft_free(p);
+                return fail(RSF_EUNSUPPORTED, "chunk transform of %lld points has no factorisation", (long long)n);
+            }
+            radix_plan(x.L1, 1, kFftThreads, kFftEPT, &x.st1);
+            radix_plan(x.L2, kPassBCols, kPassBThreads, kPassBEPT, &x.st2);
+            x.n_groups = (x.L1 + kPassBCols - 1) / kPassBCols;
+            auto upload = [&](float2** dst, const std::vector<float2>& src) -> int {
+                RSF_HIP(hipMalloc((void**)dst, src.size() * sizeof(float2)), "hipMalloc(table)");
+                RSF_HIP(hipMemcpy(*dst, src.data(), src.size() * sizeof(float2), hipMemcpyHostToDevice),
+                        "hipMemcpy(table)");
+                return RSF_OK;
+            };
+            const int64_t nlo = 1 << kTwSplitBits;
+            int rc;
+            p->xf.push_back(x);  // owned from here: freed with the plan
+            SftXform& xr = p->xf.back();
+            if ((rc = upload(&xr.t1, root_table(xr.L1, 32, 1))) ||
+                (rc = upload(&xr.t1_hi, root_table(xr.L1, (xr.L1 + 31) / 32, 32))) ||
+                (rc = upload(&xr.t2, root_table(xr.L2, 32, 1))) ||
+                (rc = upload(&xr.t2_hi, root_table(xr.L2, (xr.L2 + 31) / 32, 32))) ||
+                (rc = upload(&xr.tw_lo, root_table(n, nlo, 1))) ||
+                (rc = upload(&xr.tw_hi, root_table(n, n / nlo + 1, nlo)))) {
+                sft_free(p);
+                return rc;
+            }
+            xi = (int)p->xf.size() - 1;
+            p->lds_max = std::max({p->lds_max, fft_pass_a_lds(xr.L1), fft_pass_b_lds(xr.L2, 0)});
+            p->spill_max = std::max(p->spill_max, (size_t)xr.n_groups * kPassBCols * xr.L2);
+            p->n_max = std::max(p->n_max, n);
+        }
+        c.xf = xi;
+        const double tc = t_sft[a0] - d->t_start;
+        c.j0 = (int64_t)std::nearbyint(tc * d->band);
+        c.n_keep = p->band_bins * c.M;
+        // f_h (t_c - t_s) reduced to cycles in FP64 before the angle is formed
+        const double cyc = d->f_het * tc;
+        const double fr = cyc - std::floor(cyc);
+        c.corr = make_float2((float)std::cos(2.0 * M_PI * fr), (float)(-std::sin(2.0 * M_PI * fr)));
+        p->chunks.push_back(c);
+        a0 = a;
+    }
+    // gaps: output samples outside every chunk
+    std::vector<std::pair<int64_t, int64_t>> cov;
+    for (const auto& c : p->chunks) {
+        const int64_t lo = std::max<int64_t>(c.j0, 0), hi = std::min<int64_t>(c.j0 + c.n_keep, d->n_out);
+        if (lo < hi) cov.push_back({lo, hi});
+    }
+    std::sort(cov.begin(), cov.end());
+    int64_t j = 0;
+    for (const auto& r : cov) {
+        if (r.first > j) {
+            p->gaps.push_back(j);
+            p->gaps.push_back(r.first);
+        }
+        j = std::max(j, r.second);
+    }
+    if (j < d->n_out) {
+        p->gaps.push_back(j);
+        p->gaps.push_back(d->n_out);
+    }
+    if (p->lds_max > 65536) (void)fft_set_lds_limits(p->lds_max);
+    *out = p;
+    return RSF_OK;
+}
+
+int rsf_sft_plan_destroy(rsf_sft_plan* p) {
+    if (p) sft_free(p);
+    return RSF_OK;
+}
+
+int rsf_sft_plan_query(const rsf_sft_plan* p, int64_t* n_chunks, int64_t* gaps, int64_t max_gaps, int64_t* n_gaps) {
+    if (!p) return fail(RSF_EINVAL, "plan is NULL");
+    if (n_chunks) *n_chunks = (int64_t)p->chunks.size();
+    const int64_t ng = (int64_t)p->gaps.size() / 2;
+    if (n_gaps) *n_gaps = ng;
+    if (gaps)
+        for (int64_t i = 0; i < std::min(ng, max_gaps); ++i) {
+            gaps[2 * i] = p->gaps[(size_t)(2 * i)];
+            gaps[2 * i + 1] = p->gaps[(size_t)(2 * i + 1)];
+        }
+    return RSF_OK;
+}
+
+int rsf_sft_workspace_size(const rsf_sft_plan* p, size_t* bytes) {
+    if (!p || !bytes) return fail(RSF_EINVAL, "plan or bytes is NULL");
+    *bytes = sft_ws(p).total;
+    return RSF_OK;
+}
+
+int rsf_sft_heterodyne(const rsf_sft_plan* p, const float* sft, float* x_h, void* ws, size_t ws_bytes, void* stream) {
+    if (!p || !sft || !x_h || !ws) return fail(RSF_EINVAL, "plan, sft, x_h or ws is NULL");
+    const SftWs L = sft_ws(p);
+    if (ws_bytes < L.total) return fail(RSF_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, L.total);
+    hipStream_t s = (hipStream_t)stream;
+    const rsf_sft_desc& d = p->d;
+    char* w = (char*)ws;
+    RSF_HIP(launch_fill_u32((unsigned int*)x_h, (int)(2 * d.n_out), 0u, s), "x_h clear");
+    const float2* xh = reinterpret_cast<const float2*>(sft);
+    if (d.median_window > 0) {
+        SftNormArgs a{};
+        a.in = xh;
+        a.out = reinterpret_cast<float2*>(w + L.xh);
+        a.K = (int)d.n_bins;
+        a.w = d.median_window;
+        RSF_HIP(timed_pr(p->prof, K_SFT_NORM, s, [&] { return launch_sft_norm(a, (int)d.n_sft, s); }),
+                "sft normalisation launch");
+        xh = a.out;
+    }
+    float2* y = reinterpret_cast<float2*>(w + L.y);
+    float4* spill = reinterpret_cast<float4*>(w + L.spill);
+    for (const auto& c : p->chunks) {
+        const SftXform& x = p->xf[(size_t)c.xf];
+        SftMergeArgs m{};
+        m.xh = xh;
+        m.K = (int)d.n_bins;
+        m.k_lo = d.k_lo;
+        m.a0 = c.a0;
+        m.M = c.M;
+        m.Mp = c.Mp;
+        m.b0 = p->f_het_bins * c.Mp;
+        m.n = (int)x.n;
+        m.L1 = x.L1;
+        m.L2 = x.L2;
+        m.dk = d.dk;
+        m.taper = (float)d.band_taper;
+        m.scale = (float)(1.0 / std::sqrt((double)x.n * (double)c.M));
+        m.y = y;
+        RSF_HIP(timed_pr(p->prof, K_SFT_MERGE, s, [&] { return launch_sft_merge(m, s); }), "sft merge launch");
+        IfftRowsArgs r{};
+        r.n = x.n;
+        r.LA = x.L1;
+        r.LB = x.L2;
+        r.st = x.st1;
+        r.tws_lo = x.t1;
+        r.tws_hi = x.t1_hi;
+        r.tw_lo = x.tw_lo;
+        r.tw_hi = x.tw_hi;
+        r.y = y;
+        r.spill = spill;
+        RSF_HIP(timed_pr(p->prof, K_IFFT_ROWS, s, [&] { return launch_ifft_rows(r, s); }), "ifft rows launch");
+        IfftColsArgs k{};
+        k.n = x.n;
+        k.LA = x.L1;
+        k.LB = x.L2;
+        k.n_groups = x.n_groups;
+        k.st = x.st2;
+        k.tw_lo = x.t2;
+        k.tw_hi = x.t2_hi;
+        k.spill = spill;
+        k.x = reinterpret_cast<float2*>(x_h);
+        k.j0 = c.j0;
+        k.n_keep = c.n_keep;
+        k.n_out = d.n_out;
+        k.n_edge = (int)std::nearbyint(d.edge_taper_s * d.band);
+        k.corr = c.corr;
+        RSF_HIP(timed_pr(p->prof, K_IFFT_COLS, s, [&] { return launch_ifft_cols(k, s); }), "ifft cols launch");
+    }
+    return RSF_OK;
+}
+
+int rsf_sft_profile_enable(rsf_sft_plan* p, int on) {
+    if (!p) return fail(RSF_EINVAL, "plan is NULL");
+    p->prof->on = on != 0;
+    return RSF_OK;
+}
+
+int rsf_sft_profile_read(rsf_sft_plan* p, rsf_kernel_time* out, int max_kinds, int* n_kinds) {
+    if (!p || !n_kinds) return fail(RSF_EINVAL, "plan or n_kinds is NULL");
+    return profile_read(p->prof, out, max_kinds, n_kinds);
 }
 
 }  // extern "C"

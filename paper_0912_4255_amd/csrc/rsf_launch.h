@@ -24,6 +24,11 @@ hipError_t launch_topk_merge(const TopkMergeArgs& a, hipStream_t s);
 int topk_merge_per_block();
 hipError_t launch_fill_u32(unsigned int* p, int n, unsigned int v, hipStream_t s);
 
+hipError_t launch_sft_norm(const SftNormArgs& a, int n_sft, hipStream_t s);
+hipError_t launch_sft_merge(const SftMergeArgs& a, hipStream_t s);
+hipError_t launch_ifft_rows(const IfftRowsArgs& a, hipStream_t s);
+hipError_t launch_ifft_cols(const IfftColsArgs& b, hipStream_t s);
+
 int point_blocks(int64_t P);
 hipError_t launch_point(const PointArgs& a, bool grad, hipStream_t s);
 hipError_t launch_point_reduce(const PointReduceArgs& r, hipStream_t s);

@@ -224,4 +224,65 @@ struct PointReduceArgs {
     unsigned int* flags;
 };
 
+
+// ---------------------------------------------------------------------------
+// SFT front end (paper Sec. III.B)
+// ---------------------------------------------------------------------------
+constexpr int kSftMaxWindow = 511;  // longest running-median window
+constexpr int kSftMaxTerms = 33;    // 2 dk + 1 Dirichlet terms at most
+constexpr int kSftMaxGrid = 8192;   // SFTs of one chunk's transform grid M' (its roots sit in LDS)
+
+// Running-median normalisation of SFT bands (eq. dimlessSFTs1).
+struct SftNormArgs {
+    const float2* in;   // [n_sft][K]
+    float2* out;        // [n_sft][K]
+    int K, w;           // bins per SFT, window (odd, <= K)
+};
+
+// Long-baseline transform of one chunk (eqs. e9/e91, kernel of eq. e75),
+// relabelled band, Tukey window and scale, written conjugated (the inverse
+// transform runs as a forward one on conjugates) in the rows layout of the
+// chunk's four-step transform: element m = L2 m1 + m2 at m2 L1 + m1.
+struct SftMergeArgs {
+    const float2* xh;   // normalised SFT bands [n_sft][K]
+    int K;
+    int64_t k_lo;
+    int a0, M, Mp;      // first SFT of the chunk, its count, the 7-smooth grid M' >= M
+    int64_t b0;         // long-baseline bin of relabelled bin 0: f_h T_sft M'
+    int n;              // transform length B T_sft M'
+    int L1, L2;
+    int dk;
+    float taper;        // Tukey fraction over the band
+    float scale;        // 1 / sqrt(n M)
+    float2* y;          // [L2][L1]
+};
+
+// Rows pass of a chunk's transform (one workgroup per row m2).
+struct IfftRowsArgs {
+    int64_t n;
+    int LA, LB;
+    FftStages st;
+    const float2* tws_lo;   // W_LA^m = tws_lo[m % 32] * tws_hi[m / 32]
+    const float2* tws_hi;
+    const float2* tw_lo;    // W_n^m = tw_hi[m >> 12] * tw_lo[m & 4095]
+    const float2* tw_hi;
+    const float2* y;        // [LB][LA]
+    float4* spill;          // [ceil(LA/8) * 2][LB][4]
+};
+
+// Columns pass: output j = k_a + LA k_b; the first n_keep samples, conjugated,
+// times the chunk's phase correction and the edge taper, go to x[j0 + j].
+struct IfftColsArgs {
+    int64_t n;
+    int LA, LB, n_groups;
+    FftStages st;
+    const float2* tw_lo;    // W_LB^m = tw_lo[m % 32] * tw_hi[m / 32]
+    const float2* tw_hi;
+    const float4* spill;
+    float2* x;
+    int64_t j0, n_keep, n_out;
+    int n_edge;
+    float2 corr;            // exp(-2 pi i f_h (t_c - t_s))
+};
+
 }  // namespace rsf

@@ -45,6 +45,8 @@ def test_struct_sizes_match_header_layout():
     assert C.sizeof(L.Segment) == 4 * 8 + 4 * 8 + 4 * 4
     assert C.sizeof(L.Resampled) == 6 * 8
     assert C.sizeof(L.TopkEntry) == 16
+    # rsf_sft_desc: 5 int64 + 6 double + 2 int32
+    assert C.sizeof(L.SftDesc) == 5 * 8 + 6 * 8 + 2 * 4
 
 
 def test_null_arguments_rejected_without_gpu(lib):
@@ -93,3 +95,31 @@ def test_fft_factorisation_covers_every_workload_length(lib):
     assert lib.rsf_fft_factor(2 * 11 * 1000, 163840, 0, None, None) == L.RSF_EUNSUPPORTED
     assert lib.rsf_fft_factor(6912000, 163840, 7200, C.byref(l1), None) == L.RSF_OK and l1.value == 7200
 
+
+
+def test_invalid_sft_descriptors_rejected_before_device_use(lib):
+    """The SFT front end checks its descriptor and start times on the host
+    before any device call: B T_sft even, f_h T_sft whole, f_h >= B/2, odd
+    median window within the band, increasing start times on the output grid."""
+    import numpy as np
+    from paper_0912_4255_amd import synth
+    from paper_0912_4255_amd.api import sft_desc_from_set
+    ss = synth.SftSet(sft_len=256, dt_raw=1.0 / 64.0, k_lo=30, n_bins=200, t_sft=np.arange(4) * 4.0, t_start=0.0,
+                      f_het=10.25, band=2.0, n_out=64, dk=8, median_window=51)
+    t_ok = np.ascontiguousarray(ss.t_sft)
+    cases = []
+    d = sft_desc_from_set(ss); d.band = 2.25; cases.append((d, t_ok))             # B T_sft = 9, odd
+    d = sft_desc_from_set(ss); d.f_het = 10.1; cases.append((d, t_ok))            # f_h T_sft = 40.4
+    d = sft_desc_from_set(ss); d.f_het = 0.75; cases.append((d, t_ok))            # below B/2
+    d = sft_desc_from_set(ss); d.median_window = 50; cases.append((d, t_ok))
+    d = sft_desc_from_set(ss); d.median_window = 201; cases.append((d, t_ok))     # wider than the band
+    d = sft_desc_from_set(ss); d.dk = 17; cases.append((d, t_ok))
+    d = sft_desc_from_set(ss); d.band_taper = 1.5; cases.append((d, t_ok))
+    d = sft_desc_from_set(ss); cases.append((d, np.array([0.0, 4.0, 4.0, 8.0])))  # not increasing
+    d = sft_desc_from_set(ss); cases.append((d, np.array([0.0, 4.0, 8.3, 12.3])))  # off the output grid
+    for desc, t in cases:
+        p = C.c_void_p()
+        t = np.ascontiguousarray(t, dtype=np.float64)
+        rc = lib.rsf_sft_plan_create(C.byref(p), C.byref(desc), t.ctypes.data_as(C.POINTER(C.c_double)))
+        assert rc == L.RSF_EINVAL, lib.rsf_last_error()
+        assert not p.value

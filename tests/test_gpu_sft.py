@@ -1,0 +1,151 @@
+"""SFT front end on the GPU (paper Sec. III.B) against the FP64 oracle.
+
+Bar: |x_gpu - x_oracle| <= 1e-4 max|x_oracle| on every sample (FP32
+accumulation over at most M (2 dk + 1) merge terms and two FFT passes), gaps
+identical.  Inputs: SFTs of seeded raw series (tone + white noise) made with
+numpy's FFT, with missing SFTs, chunks whose SFT count is not 7-smooth,
+single-SFT chunks, an analysis start before the data and an end that cuts
+the last chunk."""
+import numpy as np
+import pytest
+
+from oracle import sft as osft
+from paper_0912_4255_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def make_sfts(x, N, starts, k_lo, K):
+    return np.stack([np.fft.fft(x[s:s + N])[k_lo:k_lo + K] for s in starts]).astype(np.complex64)
+
+
+def _case(slots, n_slots, seed, median_window=51, dk=8, band_taper=0.05, edge_taper_s=2.0, t_start=0.0,
+          n_out=None, N=512, dt_raw=1.0 / 64.0, f_het=12.0, band=4.0):
+    rng = np.random.default_rng(seed)
+    T_sft = N * dt_raw
+    t = np.arange(n_slots * N) * dt_raw
+    x = rng.standard_normal(n_slots * N) + 0.2 * np.cos(2 * np.pi * 12.4 * t + 0.3)
+    margin = (median_window // 2 if median_window else 0) + dk + 1
+    k_lo = int(round((f_het - band / 2) * T_sft)) - margin
+    K = int(round(band * T_sft)) + 2 * margin
+    X = make_sfts(x, N, [s * N for s in slots], k_lo, K)
+    t_sft = np.array([s * T_sft for s in slots], dtype=np.float64)
+    if n_out is None:
+        n_out = int(round((n_slots * T_sft - t_start) * band))
+    ss = synth.SftSet(sft_len=N, dt_raw=dt_raw, k_lo=k_lo, n_bins=K, t_sft=t_sft, t_start=t_start, f_het=f_het,
+                      band=band, n_out=n_out, dk=dk, median_window=median_window, band_taper=band_taper,
+                      edge_taper_s=edge_taper_s)
+    return ss, X
+
+
+def _oracle(ss, X):
+    return osft.heterodyne_from_sfts(X.astype(np.complex128), ss.t_sft, ss.t_sft_len, ss.k_lo, ss.t_start,
+                                     ss.f_het, ss.band, ss.n_out, dk=ss.dk, median_window=ss.median_window or 1,
+                                     band_taper=ss.band_taper, edge_taper_s=ss.edge_taper_s,
+                                     normalise_sfts=ss.median_window > 0)
+
+
+def _gpu(gpu_lib, ss, X):
+    import torch
+    plan = gpu_lib.SftPlan(ss)
+    out = plan.heterodyne(torch.from_numpy(X).cuda()).cpu().numpy()
+    gaps = plan.gaps
+    plan.close()
+    return out, gaps
+
+
+@pytest.mark.parametrize("slots,n_slots", [
+    ([0, 1, 2, 4, 5, 6, 7, 8, 10], 11),          # chunks of 3, 5 (grid 6), 1; trailing gap
+    ([1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11], 12),   # one chunk of 11 (grid 12), leading gap
+])
+def test_front_end_matches_oracle(gpu_lib, slots, n_slots):
+    ss, X = _case(slots, n_slots, seed=len(slots))
+    ref, gref = _oracle(ss, X)
+    got, gaps = _gpu(gpu_lib, ss, X)
+    assert np.array_equal(gaps, gref)
+    scale = np.max(np.abs(ref))
+    err = np.max(np.abs(got - ref))
+    print(f"sft front end {len(slots)} SFTs: max|d| / max|x| = {err / scale:.2e}", flush=True)
+    assert err <= 1e-4 * scale
+    for a, b in gaps:
+        assert np.all(got[a:b] == 0)
+
+
+def test_without_normalisation_start_before_data_and_cut_end(gpu_lib):
+    """median_window 0 (no normalisation), rectangular band, no edge taper,
+    the series starting 1.5 s before the first SFT and ending inside the last
+    chunk."""
+    ss, X = _case([0, 1, 2, 3, 5, 6], 7, seed=3, median_window=0, band_taper=0.0, edge_taper_s=0.0,
+                  t_start=-1.5, n_out=90)
+    ref, gref = _oracle(ss, X)
+    got, gaps = _gpu(gpu_lib, ss, X)
+    assert np.array_equal(gaps, gref)
+    assert np.max(np.abs(got - ref)) <= 1e-4 * np.max(np.abs(ref))
+
+
+def test_single_sft_chunks_and_few_dirichlet_terms(gpu_lib):
+    ss, X = _case([0, 2, 4, 6], 7, seed=4, dk=2, median_window=31)
+    ref, gref = _oracle(ss, X)
+    got, gaps = _gpu(gpu_lib, ss, X)
+    assert np.array_equal(gaps, gref)
+    assert np.max(np.abs(got - ref)) <= 1e-4 * np.max(np.abs(ref))
+
+
+def test_ten_day_sft_set_sampled_against_oracle(gpu_lib):
+    """The full T = 10 d input: 432 SFTs of 1800 s (48 missing), 7318 bins
+    each, output 3,456,000 samples at 4 Hz.  The first chunk is recomputed by
+    the oracle from its own SFTs; over the whole series the gaps are the
+    missing SFTs, gap samples are zero, and chunk interiors carry unit power
+    times the band window's mean square."""
+    import torch
+    ss, X = synth.sft_set_c2()
+    plan = gpu_lib.SftPlan(ss)
+    got = plan.heterodyne(torch.from_numpy(X).cuda()).cpu().numpy()
+    gaps = plan.gaps
+    T = ss.t_sft_len
+    # gaps: runs of missing SFT slots
+    slots = np.rint(ss.t_sft / T).astype(np.int64)
+    present = np.zeros(480, dtype=bool)
+    present[slots] = True
+    exp_gaps = []
+    a = 0
+    while a < 480:
+        if not present[a]:
+            e = a
+            while e < 480 and not present[e]:
+                e += 1
+            exp_gaps.append((int(a * T * ss.band), int(e * T * ss.band)))
+            a = e
+        else:
+            a += 1
+    assert np.array_equal(gaps, np.array(exp_gaps, dtype=np.int64).reshape(-1, 2))
+    assert np.all(np.isfinite(got))
+    for a, b in gaps:
+        assert np.all(got[a:b] == 0)
+    # first chunk against the oracle
+    chunks = osft.chunks(ss.t_sft, T)
+    a0, M = chunks[0]
+    Xc = X[a0:a0 + M].astype(np.complex128)
+    Xh = osft.normalise(Xc, ss.median_window)
+    z, _ = osft.chunk_series(Xh, ss.k_lo, int(ss.band * T), int(round(ss.f_het * T)), ss.dk, ss.band_taper)
+    t_c = ss.t_sft[a0] - ss.t_start
+    z = z * np.exp(-2j * np.pi * ss.f_het * t_c) * osft.time_taper(len(z), int(round(ss.edge_taper_s * ss.band)))
+    j0 = int(round(t_c * ss.band))
+    seg = got[j0:j0 + len(z)]
+    err = np.max(np.abs(seg - z))
+    print(f"sft front end, 10 d, first chunk ({M} SFTs): max|d| / max|x| = {err / np.max(np.abs(z)):.2e}",
+          flush=True)
+    assert err <= 1e-4 * np.max(np.abs(z))
+    # unit power in chunk interiors (edge tapers excluded): the band window's
+    # mean square, less the Dirichlet tail beyond dk (about 1 / (pi^2 dk) of
+    # the power), plus the ~2 % upward bias of 1/median over 101 bins
+    w2 = np.mean(osft.tukey(int(ss.band * T) * 8, ss.band_taper) ** 2)
+    e = int(round(ss.edge_taper_s * ss.band)) + 64
+    vals = []
+    for a0, M in chunks:
+        j0 = int(round((ss.t_sft[a0] - ss.t_start) * ss.band))
+        n = int(ss.band * T) * M
+        vals.append(got[j0 + e:j0 + n - e])
+    p = np.mean(np.abs(np.concatenate(vals)) ** 2)
+    assert abs(p / w2 - 1.0) < 0.04
+    plan.close()
