@@ -151,7 +151,7 @@ struct Profiler {
     static constexpr int kKinds = 11;
     const char* names[kKinds] = {"rsf_resample_k", "rsf_antenna_reduce_k", "rsf_fft_pass_a_k", "rsf_fft_pass_b_k",
                                  "rsf_point_k",    "rsf_point_reduce_k",   "rsf_topk_k",       "rsf_sft_norm_k",
-                                 "rsf_sft_merge_k", "rsf_ifft_rows_k",     "rsf_ifft_cols_k"};
+                                 "rsf_sft_merge_k", "rsf_sft_rows_k",      "rsf_sft_cols_k"};
     int64_t launches[kKinds] = {};
     double ms[kKinds] = {};
 
@@ -175,7 +175,7 @@ struct Profiler {
 };
 enum {
     K_RESAMPLE = 0, K_REDUCE = 1, K_PASS_A = 2, K_PASS_B = 3, K_POINT = 4, K_POINT_REDUCE = 5, K_TOPK = 6,
-    K_SFT_NORM = 7, K_SFT_MERGE = 8, K_IFFT_ROWS = 9, K_IFFT_COLS = 10
+    K_SFT_NORM = 7, K_SFT_MERGE = 8, K_SFT_ROWS = 9, K_SFT_COLS = 10
 };
 }  // namespace
 
@@ -1088,10 +1088,15 @@ struct rsf_sft_plan {
     int64_t band_bins, f_het_bins;
     std::vector<SftXform> xf;
     std::vector<SftChunk> chunks;
-    std::vector<int64_t> gaps;  // [n][2]
-    int64_t n_max;              // longest transform
-    size_t spill_max;           // float4 elements of the largest spill
-    size_t lds_max;
+    std::vector<std::vector<int>> group;  // chunk ids per transform length (index of xf)
+    std::vector<int64_t> gaps;            // [n][2]
+    int64_t y_total;                      // band bins of all chunks
+    size_t spill_total;                   // float4 elements of all spills
+    int64_t merge_blocks;
+    size_t merge_lds, lds_max;
+    SftChunkDev* chunks_dev;              // device table
+    int* ids_dev;                         // chunk ids, grouped by length
+    std::vector<int64_t> ids_off;         // first id of each group in ids_dev
 };
 
 namespace {
@@ -1106,14 +1111,16 @@ SftWs sft_ws(const rsf_sft_plan* p) {
     L.xh = off;
     if (p->d.median_window > 0) off = align_up(off + (size_t)p->d.n_sft * p->d.n_bins * sizeof(float2));
     L.y = off;
-    off = align_up(off + (size_t)p->n_max * sizeof(float2));
+    off = align_up(off + (size_t)p->y_total * sizeof(float2));
     L.spill = off;
-    off = align_up(off + p->spill_max * sizeof(float4));
+    off = align_up(off + p->spill_total * sizeof(float4));
     L.total = off;
     return L;
 }
 
 void sft_free(rsf_sft_plan* p) {
+    (void)hipFree(p->chunks_dev);
+    (void)hipFree(p->ids_dev);
     for (auto& x : p->xf) {
         (void)hipFree(x.t1);
         (void)hipFree(x.t1_hi);
@@ -1164,9 +1171,13 @@ int rsf_sft_plan_create(rsf_sft_plan** out, const rsf_sft_desc* d, const double*
     p->prof = new Profiler();
     p->band_bins = (int64_t)std::nearbyint(bb);
     p->f_het_bins = (int64_t)std::nearbyint(fb);
-    p->n_max = 0;
-    p->spill_max = 0;
+    p->y_total = 0;
+    p->spill_total = 0;
+    p->merge_blocks = 0;
+    p->merge_lds = 0;
     p->lds_max = 0;
+    p->chunks_dev = nullptr;
+    p->ids_dev = nullptr;
     int dev = 0, lds_dev = 0;
     (void)hipGetDevice(&dev);
     if (hipDeviceGetAttribute(&lds_dev, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || lds_dev <= 0)
@@ -1219,11 +1230,12 @@ int rsf_sft_plan_create(rsf_sft_plan** out, const rsf_sft_desc* d, const double*
                 return rc;
             }
             xi = (int)p->xf.size() - 1;
+            p->group.emplace_back();
             p->lds_max = std::max({p->lds_max, fft_pass_a_lds(xr.L1), fft_pass_b_lds(xr.L2, 0)});
-            p->spill_max = std::max(p->spill_max, (size_t)xr.n_groups * kPassBCols * xr.L2);
-            p->n_max = std::max(p->n_max, n);
         }
         c.xf = xi;
+        p->group[(size_t)xi].push_back((int)p->chunks.size());
+        p->merge_lds = std::max(p->merge_lds, sft_merge_lds(c.Mp, c.M, d->dk));
         const double tc = t_sft[a0] - d->t_start;
         c.j0 = (int64_t)std::nearbyint(tc * d->band);
         c.n_keep = p->band_bins * c.M;
@@ -1253,7 +1265,45 @@ int rsf_sft_plan_create(rsf_sft_plan** out, const rsf_sft_desc* d, const double*
         p->gaps.push_back(j);
         p->gaps.push_back(d->n_out);
     }
-    if (p->lds_max > 65536) (void)fft_set_lds_limits(p->lds_max);
+    // device table of chunks: band bins, spills and merge workgroups laid end to end
+    std::vector<SftChunkDev> tab(p->chunks.size());
+    for (size_t i = 0; i < p->chunks.size(); ++i) {
+        const SftChunk& c = p->chunks[i];
+        const SftXform& x = p->xf[(size_t)c.xf];
+        SftChunkDev& t = tab[i];
+        t.a0 = c.a0;
+        t.M = c.M;
+        t.Mp = c.Mp;
+        t.n = (int)x.n;
+        t.b0 = p->f_het_bins * c.Mp;
+        t.y_off = p->y_total;
+        t.spill_off = (int64_t)p->spill_total;
+        t.j0 = c.j0;
+        t.n_keep = c.n_keep;
+        t.blk0 = p->merge_blocks;
+        t.scale = (float)(1.0 / std::sqrt((double)x.n * (double)c.M));
+        t.corr = c.corr;
+        p->y_total += x.n;
+        p->spill_total += (size_t)x.n_groups * kPassBCols * x.L2;
+        p->merge_blocks += sft_merge_blocks((int)x.n);
+    }
+    std::vector<int> ids;
+    for (const auto& g : p->group) {
+        p->ids_off.push_back((int64_t)ids.size());
+        ids.insert(ids.end(), g.begin(), g.end());
+    }
+    if (hipMalloc((void**)&p->chunks_dev, tab.size() * sizeof(SftChunkDev)) != hipSuccess ||
+        hipMemcpy(p->chunks_dev, tab.data(), tab.size() * sizeof(SftChunkDev), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMalloc((void**)&p->ids_dev, ids.size() * sizeof(int)) != hipSuccess ||
+        hipMemcpy(p->ids_dev, ids.data(), ids.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+        sft_free(p);
+        return fail(RSF_EHIP, "chunk table upload failed");
+    }
+    const size_t lds_need = std::max(p->lds_max, p->merge_lds);
+    if (lds_need > 65536 && sft_set_lds_limits(lds_need) != hipSuccess) {
+        sft_free(p);
+        return fail(RSF_EUNSUPPORTED, "chunk transforms need %zu bytes of LDS", lds_need);
+    }
     *out = p;
     return RSF_OK;
 }
@@ -1303,25 +1353,22 @@ int rsf_sft_heterodyne(const rsf_sft_plan* p, const float* sft, float* x_h, void
     }
     float2* y = reinterpret_cast<float2*>(w + L.y);
     float4* spill = reinterpret_cast<float4*>(w + L.spill);
-    for (const auto& c : p->chunks) {
-        const SftXform& x = p->xf[(size_t)c.xf];
-        SftMergeArgs m{};
-        m.xh = xh;
-        m.K = (int)d.n_bins;
-        m.k_lo = d.k_lo;
-        m.a0 = c.a0;
-        m.M = c.M;
-        m.Mp = c.Mp;
-        m.b0 = p->f_het_bins * c.Mp;
-        m.n = (int)x.n;
-        m.L1 = x.L1;
-        m.L2 = x.L2;
-        m.dk = d.dk;
-        m.taper = (float)d.band_taper;
-        m.scale = (float)(1.0 / std::sqrt((double)x.n * (double)c.M));
-        m.y = y;
-        RSF_HIP(timed_pr(p->prof, K_SFT_MERGE, s, [&] { return launch_sft_merge(m, s); }), "sft merge launch");
-        IfftRowsArgs r{};
+    SftMergeArgs m{};
+    m.xh = xh;
+    m.K = (int)d.n_bins;
+    m.k_lo = d.k_lo;
+    m.dk = d.dk;
+    m.taper = (float)d.band_taper;
+    m.chunks = p->chunks_dev;
+    m.n_chunks = (int)p->chunks.size();
+    m.y = y;
+    RSF_HIP(timed_pr(p->prof, K_SFT_MERGE, s, [&] { return launch_sft_merge(m, p->merge_blocks, p->merge_lds, s); }),
+            "sft merge launch");
+    for (size_t g = 0; g < p->group.size(); ++g) {
+        const SftXform& x = p->xf[g];
+        const int nc = (int)p->group[g].size();
+        const int* ids = p->ids_dev + p->ids_off[g];
+        SftRowsArgs r{};
         r.n = x.n;
         r.LA = x.L1;
         r.LB = x.L2;
@@ -1330,10 +1377,12 @@ int rsf_sft_heterodyne(const rsf_sft_plan* p, const float* sft, float* x_h, void
         r.tws_hi = x.t1_hi;
         r.tw_lo = x.tw_lo;
         r.tw_hi = x.tw_hi;
+        r.chunks = p->chunks_dev;
+        r.ids = ids;
         r.y = y;
         r.spill = spill;
-        RSF_HIP(timed_pr(p->prof, K_IFFT_ROWS, s, [&] { return launch_ifft_rows(r, s); }), "ifft rows launch");
-        IfftColsArgs k{};
+        RSF_HIP(timed_pr(p->prof, K_SFT_ROWS, s, [&] { return launch_sft_rows(r, nc, s); }), "sft rows launch");
+        SftColsArgs k{};
         k.n = x.n;
         k.LA = x.L1;
         k.LB = x.L2;
@@ -1341,14 +1390,13 @@ int rsf_sft_heterodyne(const rsf_sft_plan* p, const float* sft, float* x_h, void
         k.st = x.st2;
         k.tw_lo = x.t2;
         k.tw_hi = x.t2_hi;
+        k.chunks = p->chunks_dev;
+        k.ids = ids;
         k.spill = spill;
         k.x = reinterpret_cast<float2*>(x_h);
-        k.j0 = c.j0;
-        k.n_keep = c.n_keep;
         k.n_out = d.n_out;
         k.n_edge = (int)std::nearbyint(d.edge_taper_s * d.band);
-        k.corr = c.corr;
-        RSF_HIP(timed_pr(p->prof, K_IFFT_COLS, s, [&] { return launch_ifft_cols(k, s); }), "ifft cols launch");
+        RSF_HIP(timed_pr(p->prof, K_SFT_COLS, s, [&] { return launch_sft_cols(k, nc, s); }), "sft cols launch");
     }
     return RSF_OK;
 }

@@ -19,6 +19,7 @@
 
 #include "rsf_device.h"
 #include "rsf_launch.h"
+#include "rsf_spill.h"
 
 namespace rsf {
 
@@ -73,39 +74,6 @@ __device__ __forceinline__ void accumulate_integrand(cp& y, const Sample& p, dou
     y.z += p.wb * er;
     y.w += p.wb * ei;
 }
-
-// Spill layout: 4-column groups, float4 [template][k_a / 4][n_b][k_a % 4]:
-// the two groups of a second-pass block are adjacent, so the block is one
-// contiguous run and every cache line is fetched once.
-constexpr int kGroupCols = kPassBCols / 2;
-
-// Writer of the first pass's last stage: output k_a = j + r L1/R of the row
-// transform, times the inter-pass twiddle W_N^{n_b k_a}, goes straight from
-// registers to the spill.  The twiddle of butterfly j = tid + q NT is
-// W^{n_b tid} (W^{n_b NT})^q, advanced once per call (calls come in q order),
-// and steps by W^{n_b L1/R} along r.
-struct SpillSink {
-    char* out;  // this template's spill (< 4 GiB, so byte offsets fit 32 bits)
-    int LB, n_b, LR;
-    float2 wq, w_step, w_lr;
-    template <int R>
-    __device__ __forceinline__ void put(int, int j, int, cp (&v)[R]) {
-        // offsets and twiddles depend only on the thread and the plan; opaque
-        // copies of j and w keep the compiler from hoisting all of them out
-        // of the spindown loop (where they would be spilled)
-        int jv = j;
-        float2 w = wq;
-        asm volatile("" : "+v"(jv), "+v"(w.x), "+v"(w.y));
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const uint32_t k = (uint32_t)(jv + r * LR);
-            const uint32_t off = (((k >> 2) * (uint32_t)LB + (uint32_t)n_b) * kGroupCols + (k & 3u)) * 16u;
-            *reinterpret_cast<float4*>(out + off) = cp_rot(v[r], w);
-            if (r + 1 < R) w = c_mul(w, w_lr);
-        }
-        wq = c_mul(wq, w_step);
-    }
-};
 
 // Inputs of one row held per thread: n_a = tid + q * kNT, q < kInPer (P <= LA/2 <= 5120).
 constexpr int kInPer = (kFftMaxLen / 2 + kNT - 1) / kNT;
@@ -291,97 +259,6 @@ __global__ __launch_bounds__(kNTB) void rsf_fft_pass_b_k(PassBArgs B) {
     }
 }
 
-// ---------------------------------------------------------------------------
-// Inverse transform of an SFT chunk's band (paper Sec. III.B, "Downsampling
-// and low-pass filtering"), as a forward four-step transform of the
-// conjugated band: rows pass (one workgroup per row m2, the same spill as the
-// first F-statistic pass) and columns pass (8 columns per workgroup) whose
-// outputs are conjugated, moved to the common heterodyne reference (eq.
-// hetStartCorr), tapered at the chunk edges and written into the series.  The
-// second member of each complex pair is unused (zero).
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kNT) void rsf_ifft_rows_k(IfftRowsArgs A) {
-    extern __shared__ float4 lds[];
-    float2* twl = reinterpret_cast<float2*>(lds + A.LA);
-    const int n_hi = (A.LA + 31) >> kTwLoBits;
-    for (int i = threadIdx.x; i < 32 + n_hi; i += kNT) twl[i] = (i < 32) ? A.tws_lo[i] : A.tws_hi[i - 32];
-    const TwLds tws{twl, twl + 32};
-    const int n_b = blockIdx.x;
-    const int tid = threadIdx.x;
-    const float2* src = A.y + (int64_t)n_b * A.LA;
-    for (int n_a = tid; n_a < A.LA; n_a += kNT) {
-        const float2 v = src[n_a];
-        lds[n_a] = make_float4(v.x, v.y, 0.f, 0.f);
-    }
-    const int64_t mb = ((int64_t)n_b * tid) % A.n;
-    const int64_t ms = ((int64_t)n_b * kNT) % A.n;
-    const int msk = (1 << kTwSplitBits) - 1;
-    const float2 w_base = c_mul(A.tw_hi[mb >> kTwSplitBits], A.tw_lo[mb & msk]);
-    const float2 w_step = c_mul(A.tw_hi[ms >> kTwSplitBits], A.tw_lo[ms & msk]);
-    const int r_last = A.st.n_stages ? A.st.radix[A.st.n_stages - 1] : 1;
-    const int lr = A.LA / r_last;
-    const int64_t ml = ((int64_t)n_b * lr) % A.n;
-    const float2 w_lr = c_mul(A.tw_hi[ml >> kTwSplitBits], A.tw_lo[ml & msk]);
-    __syncthreads();
-    SpillSink sink{reinterpret_cast<char*>(A.spill), A.LB, n_b, lr, w_base, w_step, w_lr};
-    lds_fft_into<kNT, kEPT, 1, false>(lds, A.st, tws, Interleaved<1>{}, sink, NoMid{});
-}
-
-// Output j = k_a + LA k_b of the chunk's transform: x[j0 + j] for j < n_keep.
-struct SeriesSink {
-    float2* x;
-    int64_t j0, n_keep, n_out;
-    int LA, LR, ka0, n_edge;
-    float2 corr;
-    template <int R>
-    __device__ __forceinline__ void put(int, int j, int b, cp (&v)[R]) {
-        const int ka = ka0 + b;
-        if (ka >= LA) return;
-        const int e = (int)min((int64_t)n_edge, n_keep / 2);
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int64_t jj = (int64_t)ka + (int64_t)LA * (j + r * LR);
-            const int64_t o = j0 + jj;
-            if (jj < n_keep && o >= 0 && o < n_out) {
-                // conjugate (inverse transform), then the chunk's phase correction
-                const float re = v[r].x, im = -v[r].y;
-                float g = 1.0f;
-                if (jj < e) g = 0.5f * (1.0f - cospif(((float)jj + 0.5f) / (float)e));
-                else if (jj >= n_keep - e) g = 0.5f * (1.0f - cospif(((float)(n_keep - 1 - jj) + 0.5f) / (float)e));
-                x[o] = make_float2(g * (re * corr.x - im * corr.y), g * (re * corr.y + im * corr.x));
-            }
-        }
-    }
-};
-
-__global__ __launch_bounds__(kNTB) void rsf_ifft_cols_k(IfftColsArgs B) {
-    extern __shared__ float4 lds[];
-    const int blk = B.LB * kPassBCols;
-    const int buf_elems = ((blk + 63) / 64) * 64;
-    float2* twl = reinterpret_cast<float2*>(lds + buf_elems);
-    const int n_hi = (B.LB + 31) >> kTwLoBits;
-    const int tid = threadIdx.x;
-    for (int i = tid; i < 32 + n_hi; i += kNTB) twl[i] = (i < 32) ? B.tw_lo[i] : B.tw_hi[i - 32];
-    const TwLds tw{twl, twl + 32};
-    const int c = blockIdx.x;
-    const float4* src = B.spill + (int64_t)c * blk;  // both 4-column groups of the block
-    for (int e = tid; e < blk; e += kNTB) lds[e] = src[e];
-    __syncthreads();
-    const int r_last = B.st.n_stages ? B.st.radix[B.st.n_stages - 1] : 1;
-    SeriesSink sink{B.x, B.j0, B.n_keep, B.n_out, B.LA, B.LB / r_last, c * kPassBCols, B.n_edge, B.corr};
-    lds_fft_into<kNTB, kPassBEPT, kPassBCols, false>(lds, B.st, tw, Grouped4{B.LB * kGroupCols}, sink, NoMid{});
-}
-
-hipError_t launch_ifft_rows(const IfftRowsArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(rsf_ifft_rows_k, dim3((unsigned)a.LB), dim3(kNT), fft_pass_a_lds(a.LA), s, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_ifft_cols(const IfftColsArgs& b, hipStream_t s) {
-    hipLaunchKernelGGL(rsf_ifft_cols_k, dim3((unsigned)b.n_groups), dim3(kNTB), fft_pass_b_lds(b.LB, 0), s, b);
-    return hipGetLastError();
-}
-
 int fft_pass_max_elems() { return kFftMaxLen < kNT * kEPT ? kFftMaxLen : kNT * kEPT; }
 
 size_t fft_pass_a_lds(int LA) { return (size_t)LA * sizeof(float4) + (32 + (LA + 31) / 32) * sizeof(float2); }
@@ -411,8 +288,7 @@ hipError_t fft_set_lds_limits(size_t bytes) {
     // undo a larger one
     static size_t granted = 0;
     if (bytes <= granted) return hipSuccess;
-    const void* fns[] = {(const void*)rsf_fft_pass_a_k, (const void*)rsf_fft_pass_b_k, (const void*)rsf_ifft_rows_k,
-                         (const void*)rsf_ifft_cols_k};
+    const void* fns[] = {(const void*)rsf_fft_pass_a_k, (const void*)rsf_fft_pass_b_k};
     hipError_t out = hipSuccess;
     for (const void* f : fns) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);

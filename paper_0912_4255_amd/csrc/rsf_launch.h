@@ -25,9 +25,12 @@ int topk_merge_per_block();
 hipError_t launch_fill_u32(unsigned int* p, int n, unsigned int v, hipStream_t s);
 
 hipError_t launch_sft_norm(const SftNormArgs& a, int n_sft, hipStream_t s);
-hipError_t launch_sft_merge(const SftMergeArgs& a, hipStream_t s);
-hipError_t launch_ifft_rows(const IfftRowsArgs& a, hipStream_t s);
-hipError_t launch_ifft_cols(const IfftColsArgs& b, hipStream_t s);
+int64_t sft_merge_blocks(int n);  // merge workgroups of a chunk of n bins
+size_t sft_merge_lds(int Mp, int M, int dk);
+hipError_t launch_sft_merge(const SftMergeArgs& a, int64_t blocks, size_t lds, hipStream_t s);
+hipError_t launch_sft_rows(const SftRowsArgs& a, int n_chunks, hipStream_t s);
+hipError_t launch_sft_cols(const SftColsArgs& b, int n_chunks, hipStream_t s);
+hipError_t sft_set_lds_limits(size_t bytes);
 
 int point_blocks(int64_t P);
 hipError_t launch_point(const PointArgs& a, bool grad, hipStream_t s);

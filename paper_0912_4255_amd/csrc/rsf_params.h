@@ -239,26 +239,38 @@ struct SftNormArgs {
     int K, w;           // bins per SFT, window (odd, <= K)
 };
 
-// Long-baseline transform of one chunk (eqs. e9/e91, kernel of eq. e75),
-// relabelled band, Tukey window and scale, written conjugated (the inverse
-// transform runs as a forward one on conjugates) in the rows layout of the
-// chunk's four-step transform: element m = L2 m1 + m2 at m2 L1 + m1.
-struct SftMergeArgs {
-    const float2* xh;   // normalised SFT bands [n_sft][K]
-    int K;
-    int64_t k_lo;
-    int a0, M, Mp;      // first SFT of the chunk, its count, the 7-smooth grid M' >= M
-    int64_t b0;         // long-baseline bin of relabelled bin 0: f_h T_sft M'
-    int n;              // transform length B T_sft M'
-    int L1, L2;
-    int dk;
-    float taper;        // Tukey fraction over the band
-    float scale;        // 1 / sqrt(n M)
-    float2* y;          // [L2][L1]
+// One contiguous chunk of SFTs and its transform (device table).
+struct SftChunkDev {
+    int a0, M, Mp;        // first SFT, count, 7-smooth grid M' >= M
+    int n;                // transform length B T_sft M'
+    int64_t b0;           // long-baseline bin of relabelled bin 0: f_h T_sft M'
+    int64_t y_off;        // first element of the chunk's band bins in y
+    int64_t spill_off;    // first float4 of its spill
+    int64_t j0, n_keep;   // output offset and kept samples
+    int64_t blk0;         // first merge workgroup of the chunk
+    float scale;          // 1 / sqrt(n M)
+    float2 corr;          // exp(-2 pi i f_h (t_c - t_s))
 };
 
-// Rows pass of a chunk's transform (one workgroup per row m2).
-struct IfftRowsArgs {
+// Band bins of every chunk (one launch): bin m of chunk c is the
+// long-baseline transform (eqs. e9/e91, kernel of eq. e75) at
+// b = b0 + q (q = m below n/2, m - n above), times the Tukey window and the
+// scale, conjugated (the inverse transform runs as a forward one on
+// conjugates), at y[y_off + m].
+struct SftMergeArgs {
+    const float2* xh;     // normalised SFT bands [n_sft][K]
+    int K;
+    int64_t k_lo;
+    int dk;
+    float taper;          // Tukey fraction over the band
+    const SftChunkDev* chunks;
+    int n_chunks;
+    float2* y;
+};
+
+// Rows pass over the chunks of one transform length n = LA LB: workgroup
+// (n_b, i) transforms row n_b (elements m = LB n_a + n_b) of chunk ids[i].
+struct SftRowsArgs {
     int64_t n;
     int LA, LB;
     FftStages st;
@@ -266,23 +278,27 @@ struct IfftRowsArgs {
     const float2* tws_hi;
     const float2* tw_lo;    // W_n^m = tw_hi[m >> 12] * tw_lo[m & 4095]
     const float2* tw_hi;
-    const float2* y;        // [LB][LA]
-    float4* spill;          // [ceil(LA/8) * 2][LB][4]
+    const SftChunkDev* chunks;
+    const int* ids;
+    const float2* y;
+    float4* spill;
 };
 
-// Columns pass: output j = k_a + LA k_b; the first n_keep samples, conjugated,
-// times the chunk's phase correction and the edge taper, go to x[j0 + j].
-struct IfftColsArgs {
+// Columns pass: output j = k_a + LA k_b of chunk ids[blockIdx.y]; the first
+// n_keep samples, conjugated, times the chunk's phase correction and the
+// edge taper, go to x[j0 + j].
+struct SftColsArgs {
     int64_t n;
     int LA, LB, n_groups;
     FftStages st;
     const float2* tw_lo;    // W_LB^m = tw_lo[m % 32] * tw_hi[m / 32]
     const float2* tw_hi;
+    const SftChunkDev* chunks;
+    const int* ids;
     const float4* spill;
     float2* x;
-    int64_t j0, n_keep, n_out;
+    int64_t n_out;
     int n_edge;
-    float2 corr;            // exp(-2 pi i f_h (t_c - t_s))
 };
 
 }  // namespace rsf

@@ -1,0 +1,42 @@
+// The spill between the two passes of a four-step transform: layout and
+// the writer used by the last stage of a first pass.
+#pragma once
+
+#include "rsf_device.h"
+
+namespace rsf {
+
+// Spill layout: 4-column groups, float4 [template][k_a / 4][n_b][k_a % 4]:
+// the two groups of a second-pass block are adjacent, so the block is one
+// contiguous run and every cache line is fetched once.
+constexpr int kGroupCols = kPassBCols / 2;
+
+// Writer of the first pass's last stage: output k_a = j + r L1/R of the row
+// transform, times the inter-pass twiddle W_N^{n_b k_a}, goes straight from
+// registers to the spill.  The twiddle of butterfly j = tid + q NT is
+// W^{n_b tid} (W^{n_b NT})^q, advanced once per call (calls come in q order),
+// and steps by W^{n_b L1/R} along r.
+struct SpillSink {
+    char* out;  // this template's spill (< 4 GiB, so byte offsets fit 32 bits)
+    int LB, n_b, LR;
+    float2 wq, w_step, w_lr;
+    template <int R>
+    __device__ __forceinline__ void put(int, int j, int, cp (&v)[R]) {
+        // offsets and twiddles depend only on the thread and the plan; opaque
+        // copies of j and w keep the compiler from hoisting all of them out
+        // of the spindown loop (where they would be spilled)
+        int jv = j;
+        float2 w = wq;
+        asm volatile("" : "+v"(jv), "+v"(w.x), "+v"(w.y));
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t k = (uint32_t)(jv + r * LR);
+            const uint32_t off = (((k >> 2) * (uint32_t)LB + (uint32_t)n_b) * kGroupCols + (k & 3u)) * 16u;
+            *reinterpret_cast<float4*>(out + off) = cp_rot(v[r], w);
+            if (r + 1 < R) w = c_mul(w, w_lr);
+        }
+        wq = c_mul(wq, w_step);
+    }
+};
+
+}  // namespace rsf
