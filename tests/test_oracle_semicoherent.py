@@ -1,0 +1,80 @@
+"""Pins of the semi-coherent combination in the oracle.
+
+* one segment on its own grid, no spindown drift: the sum is the map;
+* a drift fdot (t_seg - t_ref) of 3.4 and 3.5 bins moves the track by 3 and 4
+  bins (nearest bin, halves up); a grid twice as coarse samples every other
+  bin; bins outside the band add nothing;
+* an injection seen by three segments: with the matching spindown, the sum
+  peaks at the injected f0 on the common grid, and the peak is the sum of the
+  three per-segment peaks."""
+import numpy as np
+
+from oracle import fstat as of
+from oracle import semicoherent as sc
+from paper_0912_4255_amd import synth
+from paper_0912_4255_amd.synth import Injection
+from tests.helpers import make_inputs
+
+
+def _maps(rng, n_sky, n_fdot, n_out):
+    return rng.random((n_sky, n_fdot, n_out)) * 10.0
+
+
+def test_single_segment_on_its_own_grid_is_the_map():
+    rng = np.random.default_rng(0)
+    maps = _maps(rng, 2, 3, 50)
+    df, f_het, s_lo = 0.01, 100.0, -20
+    S = np.zeros((2, 3, 50))
+    sc.accumulate_segment(S, maps, s_lo, 50, f_het, df, 1000.0, np.array([0.0, 0.0, 0.0]), 1000.0,
+                          f_het + s_lo * df, df)
+    assert np.array_equal(S, maps)
+
+
+def test_drift_shift_coarse_grid_and_band_edges():
+    rng = np.random.default_rng(1)
+    n_out = 40
+    maps = _maps(rng, 1, 3, n_out)
+    # binary fractions throughout, so that the half-bin drift is an exact tie
+    df, f_het, s_lo = 0.25, 100.0, 0
+    t_seg, t_ref = 4096.0, 0.0
+    # drifts of 3.375, 3.5 and -2 bins
+    fd = np.array([3.375, 3.5, -2.0]) * df / (t_seg - t_ref)
+    n_c = 20
+    S = np.zeros((1, 3, n_c))
+    sc.accumulate_segment(S, maps, s_lo, n_out, f_het, df, t_seg, fd, t_ref, f_het, 2 * df)
+    for f, shift in enumerate((3, 4, -2)):
+        for j in range(n_c):
+            i = 2 * j + shift
+            exp = maps[0, f, i] if 0 <= i < n_out else 0.0
+            assert S[0, f, j] == exp, (f, j)
+
+
+def test_injection_seen_by_three_segments_peaks_at_f0():
+    n, dt = 2400, 4.0
+    fdot = -3e-9
+    f0 = 100.0 + 37.0 / (2 * n * dt)
+    t_ref = 0.0
+    starts = [0.0, 60000.0, 120000.0]                  # drift fdot * 60000 s = 3.5 bins per step
+    S = None
+    peaks = []
+    fd_grid = np.array([fdot, 0.0])
+    for i, t0 in enumerate(starts):
+        w = synth.small_workload(n=n, dt=dt, t_start=t0)
+        fi = f0 + fdot * (t0 - t_ref)
+        inj = Injection(h0=4.0, cosi=0.3, psi=0.2, phi0=0.5 + i, f0=fi, fdot=fdot, alpha=1.0, delta=0.4)
+        xs, gaps = make_inputs(w, seed=30 + i, injections=[inj])
+        rs = [of.resample(xs[0], gaps[0], w.segment, 1.0, 0.4, w.eph, w.detectors[0], w.kernel, w.taps)]
+        n_fft = of.fft_length(n, of.NFFT_TWICE)
+        df = 1.0 / (n_fft * dt)
+        s_lo, n_out = -n_fft // 2, n_fft
+        maps = np.stack([of.fstat_band(rs, w.detectors, fd, n_fft, s_lo, n_out) for fd in fd_grid])[None]
+        peaks.append(maps[0, 0].max())
+        if S is None:
+            f_lo, df_c, n_c = 99.99, df / 2, 2400
+            S = np.zeros((1, 2, n_c))
+        sc.accumulate_segment(S, maps, s_lo, n_out, 100.0, df, t0, fd_grid, t_ref, f_lo, df_c)
+    j = int(np.argmax(S[0, 0]))
+    assert abs((f_lo + j * df_c) - f0) <= df_c
+    assert S[0, 0, j] > 0.9 * sum(peaks)
+    # without the spindown only the first segment's peak sits on f0's track
+    assert S[0, 1, j] < 0.6 * sum(peaks)
