@@ -161,8 +161,13 @@ def c3_leg(rsf, synth, torch, dev, n_seg, n_sky, n_fdot=16, k=10):
     dt = 0.5 s, 5 % gaps, 7-smooth FFT lengths), n_sky sky positions x 16
     spindowns each, per-segment top-10 (rsf_fstat_topk)."""
     total_t = 0.0
+    semi_t = 0.0
     templates = 0
     samples = 0
+    # semi-coherent sum over the same segments on a common grid of 1/(2 d) over [99, 101) Hz
+    f_lo, df_c = 99.0, 1.0 / (2 * 86400.0)
+    n_c = int(round(2.0 / df_c))
+    S = torch.zeros((n_sky * n_fdot, n_c), dtype=torch.float32, device=dev)
     for i in range(n_seg):
         w = synth.workload_c3_segment(i, n_sky=max(n_sky, 1))
         rng = np.random.default_rng([synth.SEED_BASE + 2, 1000 + i])
@@ -179,12 +184,23 @@ def c3_leg(rsf, synth, torch, dev, n_seg, n_sky, n_fdot=16, k=10):
         plan.topk(tx, tg, sky, fd, k=k, ws=ws)
         torch.cuda.synchronize()
         total_t += time.perf_counter() - t0
+        wss = plan.workspace(rsf.RSF_ENTRY_SEMICOHERENT, n_sky, n_fdot, device=dev)
+        if i == 0:
+            plan.semicoherent(tx, tg, sky, fd, torch.zeros_like(S), 0.0, f_lo, df_c, ws=wss)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.semicoherent(tx, tg, sky, fd, S, 0.0, f_lo, df_c, ws=wss)
+        torch.cuda.synchronize()
+        semi_t += time.perf_counter() - t0
         templates += n_sky * n_fdot
         samples += w.segment.n
         plan.close()
     return {"workload": f"first {n_seg} of 64 uneven segments (mean N={samples // n_seg}), "
                         f"{n_sky} sky x {n_fdot} fdot, top-{k} per segment",
-            "segment_templates": templates, "segment_templates_per_s": round(templates / total_t, 1)}
+            "segment_templates": templates, "segment_templates_per_s": round(templates / total_t, 1),
+            "semicoherent": {"grid": f"[99, 101) Hz at 1/(2 d), {n_c} bins, t_ref = 0",
+                             "segment_templates_per_s": round(templates / semi_t, 1),
+                             "peak_S": round(float(S.max()), 2), "mean_S": round(float(S.mean()), 3)}}
 
 
 def sft_leg(rsf, synth, torch, dev, reps=5):

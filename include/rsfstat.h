@@ -66,7 +66,10 @@ enum { RSF_KERNEL_LANCZOS = 0, RSF_KERNEL_DIRICHLET = 1 };
 enum { RSF_NFFT_TWICE = 0, RSF_NFFT_SMOOTH7 = 1 };
 enum { RSF_STORE_F32 = 0, RSF_STORE_F16 = 1 };
 enum { RSF_MODE_PLAIN = 0, RSF_MODE_BATCHED = 1 };
-enum { RSF_ENTRY_RESAMPLE = 0, RSF_ENTRY_FSTAT = 1, RSF_ENTRY_POINT = 2, RSF_ENTRY_BACKWARD = 3, RSF_ENTRY_TOPK = 4 };
+enum {
+    RSF_ENTRY_RESAMPLE = 0, RSF_ENTRY_FSTAT = 1, RSF_ENTRY_POINT = 2, RSF_ENTRY_BACKWARD = 3, RSF_ENTRY_TOPK = 4,
+    RSF_ENTRY_SEMICOHERENT = 5
+};
 enum { RSF_FLAG_DEGENERATE = 1, RSF_FLAG_WINDOW = 2 };
 
 /* Interferometer site: latitude, longitude (rad, east positive), azimuth of
@@ -198,6 +201,21 @@ int rsf_fstat(const rsf_plan* plan, const rsf_segment* seg, const double* sky, i
 int rsf_fstat_topk(const rsf_plan* plan, const rsf_segment* seg, const double* sky, int64_t n_sky,
                    const double* fdot, int64_t n_fdot, int k, rsf_topk_entry* topk,
                    void* ws, size_t ws_bytes, void* stream);
+
+/* Semi-coherent ("stack-slide") sum over segments, the hierarchical scheme
+ * named in the paper's introduction, as a plain sum of per-segment 2F along
+ * each template's frequency track.  Template (sky, f0, fdot) has f0 at the
+ * reference time t_ref (seconds, the clock of t_start); this segment, whose
+ * phase reference is its start t_start, sees f = f0 + fdot (t_start - t_ref)
+ * and adds its 2F at the nearest bin floor((f - f_het) / df + 1/2) (FP64),
+ * nothing when that bin is outside its reported band.  Common grid
+ * f0_j = f_lo + j df_c, j < n_c.  S: float [n_sky * n_fdot][n_c] (device,
+ * row sky * n_fdot + fdot), ACCUMULATED (+=): zero it before the first
+ * segment and call once per segment on one stream.  Workspace:
+ * rsf_workspace_size(plan, RSF_ENTRY_SEMICOHERENT, n_sky, n_fdot, ...). */
+int rsf_fstat_semicoherent(const rsf_plan* plan, const rsf_segment* seg, const double* sky, int64_t n_sky,
+                           const double* fdot, int64_t n_fdot, double t_ref, double f_lo, double df_c, int64_t n_c,
+                           float* S, void* ws, size_t ws_bytes, void* stream);
 
 /* 2F at continuous parameters: theta device float64[n][4] = (f Hz, fdot Hz/s,
  * alpha, delta rad); f_a(f) = sum_k y^a_k exp(-2 pi i (f - f_het) k dt) on the

@@ -4,7 +4,8 @@ The hot path (resampling, FFTs, F-statistic, gradients) runs in HIP kernels
 for gfx950 inside librsfstat.so, reached through the C ABI declared in
 include/rsfstat.h.  This package is the thin Python binding.
 """
-from ._lib import (RSF_ENTRY_BACKWARD, RSF_ENTRY_FSTAT, RSF_ENTRY_POINT, RSF_ENTRY_RESAMPLE, RSF_ENTRY_TOPK,
+from ._lib import (RSF_ENTRY_BACKWARD, RSF_ENTRY_FSTAT, RSF_ENTRY_POINT, RSF_ENTRY_RESAMPLE,
+                   RSF_ENTRY_SEMICOHERENT, RSF_ENTRY_TOPK,
                    RSF_FLAG_DEGENERATE, RSF_FLAG_WINDOW, RSF_MODE_BATCHED, RSF_MODE_PLAIN, RsfError,
                    load)
 

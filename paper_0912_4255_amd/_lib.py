@@ -13,12 +13,14 @@ RSF_MAX_DET = 4
 RSF_OK, RSF_EINVAL, RSF_EUNSUPPORTED, RSF_EWORKSPACE, RSF_EHIP = 0, -1, -2, -3, -4
 RSF_MODE_PLAIN, RSF_MODE_BATCHED = 0, 1
 RSF_ENTRY_RESAMPLE, RSF_ENTRY_FSTAT, RSF_ENTRY_POINT, RSF_ENTRY_BACKWARD, RSF_ENTRY_TOPK = 0, 1, 2, 3, 4
+RSF_ENTRY_SEMICOHERENT = 5
 RSF_FLAG_DEGENERATE, RSF_FLAG_WINDOW = 1, 2
 
 EXPORTS = [
     "rsf_plan_create", "rsf_plan_destroy", "rsf_plan_query", "rsf_plan_set_batching", "rsf_plan_batching", "rsf_fft_factor",
     "rsf_workspace_size",
-    "rsf_resample", "rsf_fstat", "rsf_fstat_topk", "rsf_fstat_point", "rsf_fstat_backward",
+    "rsf_resample", "rsf_fstat", "rsf_fstat_topk", "rsf_fstat_semicoherent", "rsf_fstat_point",
+    "rsf_fstat_backward",
     "rsf_get_flags", "rsf_last_error", "rsf_version", "rsf_profile_enable", "rsf_profile_read",
     "rsf_graph_create_fstat", "rsf_graph_create_topk", "rsf_graph_launch", "rsf_graph_destroy",
     "rsf_sft_plan_create", "rsf_sft_plan_destroy", "rsf_sft_plan_query", "rsf_sft_workspace_size",
@@ -93,6 +95,8 @@ def load(path=None):
     lib.rsf_resample.argtypes = [vp, C.POINTER(Segment), vp, i64, C.POINTER(Resampled), vp, sz, vp]
     lib.rsf_fstat.argtypes = [vp, C.POINTER(Segment), vp, i64, vp, i64, i32, vp, vp, sz, vp]
     lib.rsf_fstat_topk.argtypes = [vp, C.POINTER(Segment), vp, i64, vp, i64, i32, vp, vp, sz, vp]
+    lib.rsf_fstat_semicoherent.argtypes = [vp, C.POINTER(Segment), vp, i64, vp, i64, C.c_double, C.c_double,
+                                           C.c_double, i64, vp, vp, sz, vp]
     lib.rsf_fstat_point.argtypes = [vp, C.POINTER(Segment), vp, i64, vp, vp, sz, vp]
     lib.rsf_fstat_backward.argtypes = [vp, C.POINTER(Segment), vp, i64, vp, vp, vp, vp, sz, vp]
     lib.rsf_get_flags.argtypes = [vp, vp, C.POINTER(C.c_uint32), vp]

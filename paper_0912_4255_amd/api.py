@@ -174,6 +174,23 @@ class Plan:
                                         _ptr(out), _ptr(ws), ws.numel(), _stream()))
         return out[:, 0].view(torch.float32), out[:, 1:]
 
+    def semicoherent(self, xs, gaps, sky, fdot, S, t_ref, f_lo, df_c, ws=None):
+        """rsf_fstat_semicoherent: add this segment's 2F along every template's
+        track to S (float32 [n_sky * n_fdot][n_c], accumulated in place)."""
+        _need_cuda(sky, torch.float64, "sky")
+        _need_cuda(fdot, torch.float64, "fdot")
+        _need_cuda(S, torch.float32, "S")
+        n_sky, n_fdot = sky.shape[0], fdot.shape[0]
+        if S.dim() != 2 or S.shape[0] != n_sky * n_fdot:
+            raise ValueError("S must be [n_sky * n_fdot][n_c]")
+        seg, keep = self.segment(xs, gaps)
+        if ws is None:
+            ws = self.workspace(L.RSF_ENTRY_SEMICOHERENT, n_sky, n_fdot, device=xs[0].device)
+        L.check(self.lib.rsf_fstat_semicoherent(self._p, C.byref(seg), _ptr(sky), n_sky, _ptr(fdot), n_fdot,
+                                                float(t_ref), float(f_lo), float(df_c), S.shape[1], _ptr(S),
+                                                _ptr(ws), ws.numel(), _stream()))
+        return S
+
     def point(self, xs, gaps, theta, out=None, ws=None):
         """rsf_fstat_point: 2F [n] at continuous theta [n, 4] = (f, fdot, alpha, delta)."""
         _need_cuda(theta, torch.float64, "theta")

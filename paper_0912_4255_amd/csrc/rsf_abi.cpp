@@ -148,10 +148,10 @@ struct Profiler {
     };
     std::vector<Rec> pending;
     std::vector<hipEvent_t> pool;
-    static constexpr int kKinds = 11;
+    static constexpr int kKinds = 12;
     const char* names[kKinds] = {"rsf_resample_k", "rsf_antenna_reduce_k", "rsf_fft_pass_a_k", "rsf_fft_pass_b_k",
                                  "rsf_point_k",    "rsf_point_reduce_k",   "rsf_topk_k",       "rsf_sft_norm_k",
-                                 "rsf_sft_merge_k", "rsf_sft_rows_k",      "rsf_sft_cols_k"};
+                                 "rsf_sft_merge_k", "rsf_sft_rows_k",      "rsf_sft_cols_k",   "rsf_semico_k"};
     int64_t launches[kKinds] = {};
     double ms[kKinds] = {};
 
@@ -175,7 +175,7 @@ struct Profiler {
 };
 enum {
     K_RESAMPLE = 0, K_REDUCE = 1, K_PASS_A = 2, K_PASS_B = 3, K_POINT = 4, K_POINT_REDUCE = 5, K_TOPK = 6,
-    K_SFT_NORM = 7, K_SFT_MERGE = 8, K_SFT_ROWS = 9, K_SFT_COLS = 10
+    K_SFT_NORM = 7, K_SFT_MERGE = 8, K_SFT_ROWS = 9, K_SFT_COLS = 10, K_SEMICO = 11
 };
 }  // namespace
 
@@ -578,6 +578,7 @@ int rsf_workspace_size(const rsf_plan* p, int entry, int64_t n_sky, int64_t n_fd
             *bytes = fstat_layout(p, n_sky, n_fdot, mode, false).total;
             return RSF_OK;
         case RSF_ENTRY_TOPK:
+        case RSF_ENTRY_SEMICOHERENT:
             *bytes = fstat_layout(p, n_sky, n_fdot, RSF_MODE_BATCHED, true).total;
             return RSF_OK;
         case RSF_ENTRY_POINT:
@@ -643,19 +644,27 @@ int rsf_resample(const rsf_plan* p, const rsf_segment* seg, const double* sky, i
 namespace {
 // The full path over n_sky x n_fdot templates; writes the 2F map (twoF) or,
 // when topk is not null, only the k best entries.
+// Semi-coherent consumer of the per-launch maps (see rsf_fstat_semicoherent).
+struct SemicoOut {
+    double t_ref, f_lo, df_c;
+    int64_t n_c;
+    float* S;
+};
+
 int run_fstat(const rsf_plan* p, const rsf_segment* seg, const double* sky, int64_t n_sky, const double* fdot,
               int64_t n_fdot, int mode, float* twoF, int k, rsf_topk_entry* topk, void* ws, size_t ws_bytes,
-              void* stream) {
+              void* stream, const SemicoOut* semico = nullptr) {
     if (!p) return fail(RSF_EINVAL, "plan is NULL");
     int rc = check_segment(p, seg);
     if (rc) return rc;
     const bool want_topk = topk != nullptr;
-    if (!sky || !fdot || (!twoF && !want_topk)) return fail(RSF_EINVAL, "sky, fdot or output is NULL");
+    const bool want_map = want_topk || semico != nullptr;
+    if (!sky || !fdot || (!twoF && !want_map)) return fail(RSF_EINVAL, "sky, fdot or output is NULL");
     if (n_sky < 1 || n_fdot < 1) return fail(RSF_EINVAL, "n_sky and n_fdot must be positive");
     if (mode != RSF_MODE_PLAIN && mode != RSF_MODE_BATCHED) return fail(RSF_EINVAL, "unknown mode");
     if (want_topk && (k < 1 || k > kTopkMax)) return fail(RSF_EINVAL, "k must be in 1..%d", kTopkMax);
     if (!ws) return fail(RSF_EINVAL, "workspace is NULL");
-    const WsLayout L = fstat_layout(p, n_sky, n_fdot, mode, want_topk);
+    const WsLayout L = fstat_layout(p, n_sky, n_fdot, mode, want_map);
     if (ws_bytes < L.total) return fail(RSF_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, L.total);
     hipStream_t s = (hipStream_t)stream;
     char* w = (char*)ws;
@@ -759,8 +768,8 @@ int run_fstat(const rsf_plan* p, const rsf_segment* seg, const double* sky, int6
             B.n_sky_l = q.ns;
             B.s_lo = p->s_lo;
             B.n_out = p->n_out;
-            B.map_rows = want_topk ? 1 : 0;
-            B.twoF = want_topk ? (float*)(w + L.map) : twoF;
+            B.map_rows = want_map ? 1 : 0;
+            B.twoF = want_map ? (float*)(w + L.map) : twoF;
             B.sky0 = c0 + q.s;
             B.n_fdot = n_fdot;
             B.f0 = q.f0;
@@ -768,6 +777,27 @@ int run_fstat(const rsf_plan* p, const rsf_segment* seg, const double* sky, int6
             B.n_tmpl = q.ns * q.nf;
             RSF_HIP(timed(p, K_PASS_B, s, [&] { return launch_fft_pass_b(B, p->n_cu, s); }), "pass B launch");
 
+            if (semico) {
+                SemicoArgs sa{};
+                sa.map = (const float*)(w + L.map);
+                sa.n_out = p->n_out;
+                sa.s_lo = p->s_lo;
+                sa.f_het = p->d.f_het;
+                sa.df = p->df;
+                sa.t_seg = p->d.t_start;
+                sa.t_ref = semico->t_ref;
+                sa.f_lo = semico->f_lo;
+                sa.df_c = semico->df_c;
+                sa.n_c = semico->n_c;
+                sa.fdot = fdot;
+                sa.sky0 = B.sky0;
+                sa.n_fdot = n_fdot;
+                sa.f0 = q.f0;
+                sa.nf_l = q.nf;
+                sa.n_tmpl = B.n_tmpl;
+                sa.S = semico->S;
+                RSF_HIP(timed(p, K_SEMICO, s, [&] { return launch_semico(sa, s); }), "semi-coherent launch");
+            }
             if (want_topk) {
                 TopkScanArgs ta{};
                 ta.map = (const float*)(w + L.map);
@@ -832,6 +862,18 @@ int rsf_fstat(const rsf_plan* p, const rsf_segment* seg, const double* sky, int6
               int64_t n_fdot, int mode, float* twoF, void* ws, size_t ws_bytes, void* stream) {
     if (!twoF) return fail(RSF_EINVAL, "twoF is NULL");
     return run_fstat(p, seg, sky, n_sky, fdot, n_fdot, mode, twoF, 0, nullptr, ws, ws_bytes, stream);
+}
+
+int rsf_fstat_semicoherent(const rsf_plan* p, const rsf_segment* seg, const double* sky, int64_t n_sky,
+                           const double* fdot, int64_t n_fdot, double t_ref, double f_lo, double df_c, int64_t n_c,
+                           float* S, void* ws, size_t ws_bytes, void* stream) {
+    if (!S) return fail(RSF_EINVAL, "S is NULL");
+    if (!is_fin(t_ref) || !is_fin(f_lo) || !is_fin(df_c) || df_c <= 0)
+        return fail(RSF_EINVAL, "t_ref, f_lo and df_c must be finite and df_c positive");
+    if (n_c < 1 || n_c > INT32_MAX * 256LL) return fail(RSF_EINVAL, "n_c out of range");
+    const SemicoOut so{t_ref, f_lo, df_c, n_c, S};
+    return run_fstat(p, seg, sky, n_sky, fdot, n_fdot, RSF_MODE_BATCHED, nullptr, 0, nullptr, ws, ws_bytes, stream,
+                     &so);
 }
 
 int rsf_fstat_topk(const rsf_plan* p, const rsf_segment* seg, const double* sky, int64_t n_sky, const double* fdot,

@@ -1,0 +1,90 @@
+"""Semi-coherent sum on the GPU against the oracle.
+
+Bar: the nearest-bin decisions are FP64 on both sides (identical bins); each
+S value is a sum of per-segment FP32 2F values, so
+|S_gpu - S_oracle| <= 1e-4 (S_oracle + 4 n_seg).  The common grid is half the
+segment bin width with f_lo on a bin, so every other grid point is an exact
+half-bin tie."""
+import numpy as np
+import pytest
+
+from oracle import fstat as of
+from oracle import semicoherent as sc
+from paper_0912_4255_amd import synth
+from paper_0912_4255_amd.synth import Injection
+from tests.helpers import make_inputs, to_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def test_three_segments_against_oracle(gpu_lib):
+    import torch
+    n, dt = 2400, 4.0
+    fdots = np.array([-3e-9, 0.0, 2e-9])
+    sky = np.array([[1.0, 0.4], [2.5, -0.3]])
+    f0 = 100.0 + 37.0 / (2 * n * dt)
+    t_ref = 0.0
+    starts = [0.0, 60000.0, 120000.0]
+    df = 1.0 / (2 * n * dt)
+    f_lo, df_c, n_c = 100.0 - 500 * df, df / 2, 2000
+    S_ref = np.zeros((2, 3, n_c))
+    S = torch.zeros((6, n_c), dtype=torch.float32, device="cuda")
+    ts, tf = torch.from_numpy(sky).cuda(), torch.from_numpy(fdots).cuda()
+    for i, t0 in enumerate(starts):
+        w = synth.small_workload(n=n, dt=dt, t_start=t0)
+        inj = Injection(h0=4.0, cosi=0.3, psi=0.2, phi0=0.5 + i, f0=f0 + fdots[0] * (t0 - t_ref), fdot=fdots[0],
+                        alpha=1.0, delta=0.4)
+        xs, gaps = make_inputs(w, seed=40 + i, injections=[inj])
+        plan = gpu_lib.Plan(w)
+        assert plan.df == df
+        tx, tg = to_gpu(xs, gaps)
+        plan.semicoherent(tx, tg, ts, tf, S, t_ref, f_lo, df_c)
+        maps = np.zeros((2, 3, plan.n_out))
+        for si in range(2):
+            rs = [of.resample(xs[0], gaps[0], w.segment, *sky[si], w.eph, w.detectors[0], w.kernel, w.taps)]
+            for fi in range(3):
+                maps[si, fi] = of.fstat_band(rs, w.detectors, fdots[fi], plan.n_fft, plan.s_lo, plan.n_out)
+        sc.accumulate_segment(S_ref, maps, plan.s_lo, plan.n_out, w.segment.f_het, plan.df, t0, fdots, t_ref,
+                              f_lo, df_c)
+        plan.close()
+    got = S.cpu().numpy().reshape(2, 3, n_c)
+    err = np.abs(got - S_ref) / (S_ref + 4.0 * len(starts))
+    print(f"semi-coherent, 3 segments: max |dS| / (S + 12) = {err.max():.2e}; peak S = {S_ref.max():.1f}",
+          flush=True)
+    assert np.all(err <= 1e-4)
+    j = int(np.argmax(got[0, 0]))
+    assert abs(f_lo + j * df_c - f0) <= df_c
+
+
+def test_uneven_segments_full_length_match_the_maps(gpu_lib):
+    """The first four of the 64 uneven segments at full length (7-smooth
+    FFTs), 2 sky x 4 spindowns: S equals the sum of the segments' own 2F maps
+    (rsf_fstat) gathered at the FP64 nearest bins, to the FP32 rounding of
+    the additions."""
+    import torch
+    sky = synth.uniform_sky(np.random.default_rng(7), 2)
+    fdots = synth.fdot_grid(4)
+    t_ref = 0.0
+    f_lo, df_c = 99.0, 1.0 / (2 * 86400.0)
+    n_c = int(2.0 / df_c)
+    S = torch.zeros((8, n_c), dtype=torch.float32, device="cuda")
+    ref = np.zeros((8, n_c), dtype=np.float64)
+    ts, tf = torch.from_numpy(np.ascontiguousarray(sky)).cuda(), torch.from_numpy(fdots).cuda()
+    for i in range(4):
+        w = synth.workload_c3_segment(i, n_sky=2, n_fdot=4)
+        rng = np.random.default_rng([synth.SEED_BASE + 2, 1000 + i])
+        x = synth.zero_gaps(synth.gaussian_noise(rng, w.segment.n, 1.0), w.gaps[0])
+        plan = gpu_lib.Plan(w)
+        tx, tg = to_gpu([x], [w.gaps[0]])
+        plan.semicoherent(tx, tg, ts, tf, S, t_ref, f_lo, df_c)
+        maps = plan.fstat(tx, tg, ts, tf).cpu().numpy().astype(np.float64)
+        j = np.arange(n_c)
+        for r in range(8):
+            shift = fdots[r % 4] * (w.segment.t_start - t_ref)
+            s = np.floor(((f_lo + j * df_c) + shift - w.segment.f_het) / plan.df + 0.5).astype(np.int64)
+            k = s - plan.s_lo
+            ok = (k >= 0) & (k < plan.n_out)
+            ref[r, ok] += maps[r, k[ok]]
+        plan.close()
+    got = S.cpu().numpy()
+    assert np.max(np.abs(got - ref) / (ref + 16.0)) <= 1e-6
