@@ -22,8 +22,9 @@ design notes):
   z = x_h exp(-2 pi i f_h t_m) and bin s sits at f_h + s df.
 * Spindown phase sign: eqs. eq12/eq13/eq19/eq20 print exp(+i Phi_s), but
   eq. eq5 inserted into eqs. eq7/eq8 gives exp(-i Phi); exp(-i Phi_s) is used.
-* Spindown phase (s = 1, eq. eq4pt1): Phi_s = 2 pi fdot (T^2/2 + t_m T), at
-  T^k with t_m,k = t_b^k - T^k (eq. phi-s-explain).
+* Spindown phase (eq. eq4pt1): Phi_s = 2 pi sum_j f^(j) (T^{j+1}/(j+1)! + t_m T^j/j!)
+  at T^k with t_m,k = t_b^k - T^k (eq. phi-s-explain); s = 1 by default, up to 3
+  when a template carries (fdot, f^(2), f^(3)).
 * dt_b/dt is taken as 1 (the paper drops the ~1e-4 Doppler Jacobian, eqs.
   eq11b/eq11c).
 * Gaps: the input is zero-filled; A, B, C are sums over the SSB grid with the
@@ -110,8 +111,19 @@ def antenna_sums(rs_list, dets):
 
 
 def spindown_phase(T, tm, fdot):
-    """Phi_s,k = 2 pi fdot (T_k^2 / 2 + t_m,k T_k) (eq. eq4pt1, s = 1)."""
-    return 2.0 * np.pi * fdot * (T * T / 2.0 + tm * T)
+    """Phi_s,k of eq. eq4pt1 at T_k with t_m,k:
+    2 pi sum_{j=1..s} f^(j) (T^{j+1} / (j+1)! + t_m T^j / j!).
+    fdot is f^(1) (s = 1) or the sequence (f^(1), ..., f^(s))."""
+    spins = np.atleast_1d(np.asarray(fdot, dtype=np.float64))
+    cycles = 0.0
+    Tj = T                        # T^j
+    fact = 1.0                    # j!
+    for j, fj in enumerate(spins, start=1):
+        fact_next = fact * (j + 1)
+        cycles = cycles + fj * (Tj * T / fact_next + tm * Tj / fact)
+        Tj = Tj * T
+        fact = fact_next
+    return 2.0 * np.pi * cycles
 
 
 def integrands(rs_list, dets, fdot):

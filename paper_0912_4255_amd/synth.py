@@ -93,6 +93,8 @@ class Injection:
     fdot: float
     alpha: float
     delta: float
+    f2: float = 0.0     # second and third frequency derivatives (eq. eq4, s up to 3)
+    f3: float = 0.0
 
 
 @dataclass

@@ -240,3 +240,38 @@ def test_smooth7_length_is_least_even_smooth_and_full_band_fits():
         n_out = int(round(2.0 / df))
         assert n_out == m
         of.band_indices(m, s_lo, n_out)  # raises if outside the data band
+
+
+def test_higher_order_spindown_phase_is_first_order_expansion():
+    """Eq. eq4pt1 for s = 3 is the expansion of sum_j f^(j) (T + t_m)^{j+1}/(j+1)!
+    to first order in t_m: the difference is the binomial remainder (powers
+    t_m^m, m >= 2), computed here from math.comb."""
+    rng = np.random.default_rng(3)
+    T = rng.uniform(1e5, 2e6, 50)
+    tm = rng.uniform(-500.0, 500.0, 50)
+    spins = (-3e-10, 2e-17, -4e-24)
+    got = of.spindown_phase(T, tm, spins) / (2 * math.pi)
+    exact = np.zeros_like(T)
+    rem = np.zeros_like(T)
+    for j, fj in enumerate(spins, start=1):
+        n = j + 1
+        exact += fj * (T + tm) ** n / math.factorial(n)
+        rem += fj * sum(math.comb(n, m) * T ** (n - m) * tm ** m for m in range(2, n + 1)) / math.factorial(n)
+    assert np.allclose(got + rem, exact, rtol=1e-12, atol=0)
+    # order 1 given as a scalar or a one-element sequence is the same phase
+    assert np.array_equal(of.spindown_phase(T, tm, -3e-10), of.spindown_phase(T, tm, (-3e-10,)))
+
+
+def test_second_derivative_injection_needs_the_matching_template():
+    """An injection with f^(2) = 5e-13 Hz/s^2 (about 50 cycles of T^3/6 over the
+    day) is recovered with (fdot, f^(2)) and lost with fdot alone."""
+    s = 3000
+    inj = _inj(s_bin=s, fdot=-3e-10, f2=5e-13)
+    x = signal(SEG, inj, EPH, DET_H)
+    rs = of.resample(x, NOGAP, SEG, inj.alpha, inj.delta, EPH, DET_H, KERNEL_LANCZOS, 8)
+    A, B, C = of.antenna_sums([rs], [DET_H])
+    rho2 = rho2_matched(A, B, C, inj)
+    F2 = of.fstat_bins([rs], [DET_H], (inj.fdot, inj.f2), NFFT, [s])[0]
+    F1 = of.fstat_spectrum([rs], [DET_H], inj.fdot, NFFT)[0].max()
+    assert abs(F2 / rho2 - 1.0) < 0.02
+    assert F1 / rho2 < 0.2
