@@ -18,7 +18,7 @@
  * - The SSB grid is t_b^k = k dt, k = 0..n-1.  T^k is the detector time with
  *   T^k + t_m(T^k) = t_b^k (eq. eq21), t_m = n0 . r_d / c (eq. eq4pt2).
  * - Spindown phase Phi_s = 2 pi fdot (T^2/2 + t_m T) (eq. eq4pt1, s = 1),
- *   applied as exp(-i Phi_s).
+ *   applied as exp(-i Phi_s); orders 2 and 3 through rsf_plan_set_spin_order.
  * - Output bin s (signed) is the frequency f_het + s / (n_fft dt); bands are
  *   reported in ascending s.
  * - 2F = 2 (B'|f_a|^2 + A'|f_b|^2 - 2 C' Re(f_a f_b^*)) / D' with
@@ -142,6 +142,13 @@ typedef struct rsf_plan rsf_plan;
 int rsf_plan_create(rsf_plan** out, const rsf_plan_desc* desc);
 int rsf_plan_destroy(rsf_plan* plan);
 
+/* Spindown order of the plan's templates (eq. eq4pt1 with s = order, 1..3;
+ * default 1).  With order s, every `fdot` argument of rsf_fstat,
+ * rsf_fstat_topk and the graph builders is double [n_fdot][s]: row i holds
+ * (f^(1), ..., f^(s)) of template i, and
+ * Phi_s = 2 pi sum_j f^(j) (T^{j+1}/(j+1)! + t_m T^j/j!).  The point and gradient
+ * entries and the semi-coherent sum take order 1 only (RSF_EUNSUPPORTED). */
+int rsf_plan_set_spin_order(rsf_plan* plan, int order);
 /* Batching knobs of RSF_MODE_BATCHED (0 = keep the automatic value):
  * fb = spindowns sharing one read of the resampled series in the first FFT
  * pass (1..16); templates = templates per FFT launch (1..256). */

@@ -62,10 +62,29 @@ class Plan:
                                         C.byref(l1), C.byref(l2), C.byref(df)))
         self.n_fft, self.s_lo, self.n_out = n_fft.value, s_lo.value, n_out.value
         self.fft_l1, self.fft_l2, self.df = l1.value, l2.value, df.value
+        self.spin_order = 1
 
     def set_batching(self, fb=0, templates=0):
         """rsf_plan_set_batching: spindowns sharing a first-pass row, templates per launch."""
         L.check(self.lib.rsf_plan_set_batching(self._p, fb, templates))
+
+    def _n_fdot(self, fdot):
+        """Templates in a spindown tensor: [n_fdot] at order 1, [n_fdot, s] at order s."""
+        if self.spin_order == 1:
+            if fdot.dim() == 2 and fdot.shape[1] == 1:
+                return fdot.shape[0]
+            if fdot.dim() != 1:
+                raise ValueError("fdot must be [n_fdot] at spin order 1")
+            return fdot.shape[0]
+        if fdot.dim() != 2 or fdot.shape[1] != self.spin_order:
+            raise ValueError(f"fdot must be [n_fdot, {self.spin_order}] at spin order {self.spin_order}")
+        return fdot.shape[0]
+
+    def set_spin_order(self, order):
+        """rsf_plan_set_spin_order: templates carry (f^(1) .. f^(order)); fdot
+        tensors are then [n_fdot, order]."""
+        L.check(self.lib.rsf_plan_set_spin_order(self._p, int(order)))
+        self.spin_order = int(order)
 
     def batching(self, n_sky=1, n_fdot=1, mode=L.RSF_MODE_BATCHED):
         """rsf_plan_batching: effective (fb, templates per launch, skies per launch)."""
@@ -145,7 +164,7 @@ class Plan:
         """rsf_fstat: 2F [n_sky * n_fdot, n_out] (float32), ascending frequency."""
         _need_cuda(sky, torch.float64, "sky")
         _need_cuda(fdot, torch.float64, "fdot")
-        n_sky, n_fdot = sky.shape[0], fdot.shape[0]
+        n_sky, n_fdot = sky.shape[0], self._n_fdot(fdot)
         seg, keep = self.segment(xs, gaps)
         dev = xs[0].device
         if out is None:
@@ -164,7 +183,7 @@ class Plan:
         and bins; returns (values float32 [k], indices int32 [k, 3])."""
         _need_cuda(sky, torch.float64, "sky")
         _need_cuda(fdot, torch.float64, "fdot")
-        n_sky, n_fdot = sky.shape[0], fdot.shape[0]
+        n_sky, n_fdot = sky.shape[0], self._n_fdot(fdot)
         seg, keep = self.segment(xs, gaps)
         dev = xs[0].device
         out = torch.empty((k, 4), dtype=torch.int32, device=dev)
@@ -180,7 +199,7 @@ class Plan:
         _need_cuda(sky, torch.float64, "sky")
         _need_cuda(fdot, torch.float64, "fdot")
         _need_cuda(S, torch.float32, "S")
-        n_sky, n_fdot = sky.shape[0], fdot.shape[0]
+        n_sky, n_fdot = sky.shape[0], self._n_fdot(fdot)
         if S.dim() != 2 or S.shape[0] != n_sky * n_fdot:
             raise ValueError("S must be [n_sky * n_fdot][n_c]")
         seg, keep = self.segment(xs, gaps)
@@ -225,7 +244,7 @@ class Plan:
         (Graph, out).  Graph.launch() replays it on the current stream."""
         _need_cuda(sky, torch.float64, "sky")
         _need_cuda(fdot, torch.float64, "fdot")
-        n_sky, n_fdot = sky.shape[0], fdot.shape[0]
+        n_sky, n_fdot = sky.shape[0], self._n_fdot(fdot)
         seg, keep = self.segment(xs, gaps)
         dev = xs[0].device
         if out is None:
@@ -239,7 +258,7 @@ class Plan:
 
     def graph_topk(self, xs, gaps, sky, fdot, k=10, ws=None):
         """Capture a rsf_fstat_topk call into a HIP graph; returns (Graph, values, indices)."""
-        n_sky, n_fdot = sky.shape[0], fdot.shape[0]
+        n_sky, n_fdot = sky.shape[0], self._n_fdot(fdot)
         seg, keep = self.segment(xs, gaps)
         dev = xs[0].device
         res = torch.empty((k, 4), dtype=torch.int32, device=dev)

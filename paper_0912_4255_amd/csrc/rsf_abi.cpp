@@ -189,6 +189,7 @@ struct rsf_plan {
     int64_t P;           // rows of the transposed series: ceil(n / LB)
     int n_groups;        // ceil(LA / 8)
     int n_cu;            // compute units (persistent second-pass grid)
+    int spin_order;      // spindown derivatives per template (eq. eq4pt1), 1..3
     int fb_override;     // spindowns sharing a row in the first pass (0 = automatic)
     int g_override;      // templates per FFT launch (0 = automatic)
     FftStages stA, stB;
@@ -405,6 +406,7 @@ int rsf_plan_create(rsf_plan** out, const rsf_plan_desc* d) {
     rsf_plan* p = new rsf_plan();
     p->d = *d;
     p->prof = new Profiler();
+    p->spin_order = 1;
     p->n = d->n;
     // even, so that a band reaching f_het +- 1/(2 dt) has its edges on bins
     p->n_fft = (d->nfft_policy == RSF_NFFT_TWICE) ? 2 * d->n : 2 * next_7smooth(d->n);
@@ -518,6 +520,13 @@ int rsf_plan_destroy(rsf_plan* p) {
     (void)hipFree(p->tw_hi);
     delete p->prof;
     delete p;
+    return RSF_OK;
+}
+
+int rsf_plan_set_spin_order(rsf_plan* p, int order) {
+    if (!p) return fail(RSF_EINVAL, "plan is NULL");
+    if (order < 1 || order > 3) return fail(RSF_EINVAL, "spin order must be 1, 2 or 3");
+    p->spin_order = order;
     return RSF_OK;
 }
 
@@ -741,7 +750,8 @@ int run_fstat(const rsf_plan* p, const rsf_segment* seg, const double* sky, int6
             }
             A.rs_sky_stride = L.rs_stride;
             A.f16 = f16;
-            A.fdot = fdot + q.f0;
+            A.fdot = fdot + q.f0 * p->spin_order;
+            A.spin_order = p->spin_order;
             A.nf_l = q.nf;
             A.n_sky_l = q.ns;
             A.fb = fb;
@@ -868,6 +878,7 @@ int rsf_fstat_semicoherent(const rsf_plan* p, const rsf_segment* seg, const doub
                            const double* fdot, int64_t n_fdot, double t_ref, double f_lo, double df_c, int64_t n_c,
                            float* S, void* ws, size_t ws_bytes, void* stream) {
     if (!S) return fail(RSF_EINVAL, "S is NULL");
+    if (p && p->spin_order != 1) return fail(RSF_EUNSUPPORTED, "the semi-coherent sum takes spin order 1 only");
     if (!is_fin(t_ref) || !is_fin(f_lo) || !is_fin(df_c) || df_c <= 0)
         return fail(RSF_EINVAL, "t_ref, f_lo and df_c must be finite and df_c positive");
     if (n_c < 1 || n_c > INT32_MAX * 256LL) return fail(RSF_EINVAL, "n_c out of range");
@@ -888,6 +899,7 @@ int point_common(const rsf_plan* p, const rsf_segment* seg, const double* theta,
     if (!p) return fail(RSF_EINVAL, "plan is NULL");
     int rc = check_segment(p, seg);
     if (rc) return rc;
+    if (p->spin_order != 1) return fail(RSF_EUNSUPPORTED, "point evaluation and its gradient take spin order 1 only");
     if (!theta) return fail(RSF_EINVAL, "theta is NULL");
     if (n < 1 || n > 65535) return fail(RSF_EINVAL, "number of candidates must be in 1..65535");
     if (grad && (!g_twoF || !g_theta)) return fail(RSF_EINVAL, "g_twoF or g_theta is NULL");

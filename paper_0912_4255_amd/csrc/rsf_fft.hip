@@ -30,16 +30,19 @@ constexpr int kEPT = kFftEPT;
 }  // namespace
 
 // One resampled sample of one detector, unpacked for the integrand: z~,
-// the noise-weighted beam patterns w a, w b, and u = (t_b^2 - t_m^2) / 2 in
-// FP64, so that Phi_s = 2 pi fdot (T^2/2 + t_m T) = 2 pi fdot u with
-// T = t_b - t_m (eq. eq4pt1); u does not depend on the spindown.
+// the noise-weighted beam patterns w a, w b, and the spindown coefficients
+// u_j of eq. eq4pt1 in FP64, Phi_s = 2 pi sum_j f^(j) u_j with
+// u_j = T^{j+1}/(j+1)! + t_m T^j/j!, T = t_b - t_m; they do not depend on the
+// template.  u_1 = (t_b^2 - t_m^2) / 2.
+template <int ORDER>
 struct Sample {
     float zr, zi, wa, wb;
-    double u;
+    double u[ORDER];
 };
 
-__device__ __forceinline__ Sample unpack_sample(float4 m, float tmf, bool f16, double tb, float w) {
-    Sample r;
+template <int ORDER>
+__device__ __forceinline__ Sample<ORDER> unpack_sample(float4 m, float tmf, bool f16, double tb, float w) {
+    Sample<ORDER> r;
     if (f16) {
         const uint32_t bits = __float_as_uint(m.x);
         const __half2 h = *reinterpret_cast<const __half2*>(&bits);
@@ -56,13 +59,28 @@ __device__ __forceinline__ Sample unpack_sample(float4 m, float tmf, bool f16, d
         r.wb = w * m.w;
     }
     const double tm = (double)tmf;
-    r.u = 0.5 * (tb * tb - tm * tm);
+    r.u[0] = 0.5 * (tb * tb - tm * tm);
+    if constexpr (ORDER >= 2) {
+        const double T = tb - tm;
+        const double T2 = T * T;
+        r.u[1] = T2 * (T * (1.0 / 6.0) + 0.5 * tm);
+        if constexpr (ORDER >= 3) r.u[2] = T2 * T * (T * (1.0 / 24.0) + tm * (1.0 / 6.0));
+    }
     return r;
 }
 
+// Spindown parameters (f^(1) .. f^(ORDER)) of one template.
+template <int ORDER>
+struct Spin {
+    double f[ORDER];
+};
+
 // y += (w a, w b) z~ exp(-i Phi_s) for one detector (eqs. eq19, eq20).
-__device__ __forceinline__ void accumulate_integrand(cp& y, const Sample& p, double fd) {
-    const double cyc = fd * p.u;
+template <int ORDER>
+__device__ __forceinline__ void accumulate_integrand(cp& y, const Sample<ORDER>& p, const Spin<ORDER>& sp) {
+    double cyc = sp.f[0] * p.u[0];
+#pragma unroll
+    for (int j = 1; j < ORDER; ++j) cyc = fma(sp.f[j], p.u[j], cyc);
     // reduced to [-1/2, 1/2] cycle; v_sin_f32 / v_cos_f32 take revolutions
     const float ph = (float)(cyc - rint(cyc));
     const float s = __builtin_amdgcn_sinf(ph);
@@ -78,6 +96,7 @@ __device__ __forceinline__ void accumulate_integrand(cp& y, const Sample& p, dou
 // Inputs of one row held per thread: n_a = tid + q * kNT, q < kInPer (P <= LA/2 <= 5120).
 constexpr int kInPer = (kFftMaxLen / 2 + kNT - 1) / kNT;
 
+template <int ORDER>
 __global__ __launch_bounds__(kNT) void rsf_fft_pass_a_k(PassAArgs A) {
     extern __shared__ float4 lds[];
     // stage twiddles in LDS after the row: no global load inside the stages,
@@ -110,11 +129,11 @@ __global__ __launch_bounds__(kNT) void rsf_fft_pass_a_k(PassAArgs A) {
             tm0[q] = 0.f;
         }
     }
-    Sample p0[kInPer];
+    Sample<ORDER> p0[kInPer];
 #pragma unroll
     for (int q = 0; q < kInPer; ++q) {
         const int64_t k = (int64_t)A.LB * (tid + q * kNT) + n_b;
-        p0[q] = unpack_sample(m0[q], tm0[q], A.f16, (double)k * A.dt, (float)A.w[0]);
+        p0[q] = unpack_sample<ORDER>(m0[q], tm0[q], A.f16, (double)k * A.dt, (float)A.w[0]);
     }
     // the upper half of the row is zero padding when P <= LA/2: it is
     // neither written nor read (pruned first stage)
@@ -134,7 +153,9 @@ __global__ __launch_bounds__(kNT) void rsf_fft_pass_a_k(PassAArgs A) {
 
     for (int f = f_lo; f < f_hi; ++f) {
         const int t = s_l * A.nf_l + f;
-        const double fd = A.fdot[f];
+        Spin<ORDER> fd;
+#pragma unroll
+        for (int j = 0; j < ORDER; ++j) fd.f[j] = A.fdot[(int64_t)f * ORDER + j];
 #pragma unroll
         for (int q = 0; q < kInPer; ++q) {
             const int n_a = tid + q * kNT;
@@ -145,7 +166,8 @@ __global__ __launch_bounds__(kNT) void rsf_fft_pass_a_k(PassAArgs A) {
                     accumulate_integrand(y, p0[q], fd);
                     for (int X = 1; X < A.n_det; ++X)
                         accumulate_integrand(y,
-                                             unpack_sample(A.rs_main[X][row + n_a], A.f16 ? 0.f : A.rs_tm[X][row + n_a],
+                                             unpack_sample<ORDER>(A.rs_main[X][row + n_a],
+                                                                  A.f16 ? 0.f : A.rs_tm[X][row + n_a],
                                                            A.f16, (double)k * A.dt, (float)A.w[X]),
                                              fd);
                 }
@@ -266,7 +288,12 @@ size_t fft_pass_a_lds(int LA) { return (size_t)LA * sizeof(float4) + (32 + (LA +
 hipError_t launch_fft_pass_a(const PassAArgs& a, hipStream_t s) {
     const size_t lds = fft_pass_a_lds(a.LA);
     const unsigned gy = (unsigned)(a.n_sky_l * ((a.nf_l + a.fb - 1) / a.fb));
-    hipLaunchKernelGGL(rsf_fft_pass_a_k, dim3((unsigned)a.LB, gy), dim3(kNT), lds, s, a);
+    switch (a.spin_order) {
+        case 1: hipLaunchKernelGGL(rsf_fft_pass_a_k<1>, dim3((unsigned)a.LB, gy), dim3(kNT), lds, s, a); break;
+        case 2: hipLaunchKernelGGL(rsf_fft_pass_a_k<2>, dim3((unsigned)a.LB, gy), dim3(kNT), lds, s, a); break;
+        case 3: hipLaunchKernelGGL(rsf_fft_pass_a_k<3>, dim3((unsigned)a.LB, gy), dim3(kNT), lds, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -288,7 +315,8 @@ hipError_t fft_set_lds_limits(size_t bytes) {
     // undo a larger one
     static size_t granted = 0;
     if (bytes <= granted) return hipSuccess;
-    const void* fns[] = {(const void*)rsf_fft_pass_a_k, (const void*)rsf_fft_pass_b_k};
+    const void* fns[] = {(const void*)rsf_fft_pass_a_k<1>, (const void*)rsf_fft_pass_a_k<2>,
+                         (const void*)rsf_fft_pass_a_k<3>, (const void*)rsf_fft_pass_b_k};
     hipError_t out = hipSuccess;
     for (const void* f : fns) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);

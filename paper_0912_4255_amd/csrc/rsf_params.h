@@ -124,7 +124,8 @@ struct PassAArgs {
     const float* rs_tm[kMaxDet];
     int64_t rs_sky_stride;
     int f16;
-    const double* fdot;
+    const double* fdot;       // [nf_l][spin_order]: f^(1) .. f^(spin_order) per template
+    int spin_order;           // 1..3 (eq. eq4pt1)
     int nf_l;
     int n_sky_l;
     int fb;

@@ -1,0 +1,68 @@
+"""Spindown orders 2 and 3 (eq. eq4pt1 with s = 2, 3) on the GPU against the
+oracle: full-band 2F of templates (f^(1), f^(2)[, f^(3)]) within the FP32
+tolerance, recovery of an f^(2) injection, top-k at order 2, order 1 given
+as [n, 1] equal to [n], and the entries that take order 1 only."""
+import numpy as np
+import pytest
+
+from oracle import fstat as of
+from paper_0912_4255_amd import synth
+from paper_0912_4255_amd.synth import Injection
+from tests.helpers import make_inputs, to_gpu, twoF_tol
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(seed=3, injections=()):
+    w = synth.small_workload(n=21600, dt=4.0, kernel=synth.KERNEL_DIRICHLET, taps=16)
+    xs, gaps = make_inputs(w, seed=seed, injections=list(injections))
+    return w, xs, gaps
+
+
+@pytest.mark.parametrize("order", [2, 3])
+def test_higher_orders_match_oracle(gpu_lib, order):
+    import torch
+    df = 1.0 / (2 * 21600 * 4.0)
+    inj = Injection(h0=2.0, cosi=0.2, psi=0.1, phi0=0.3, f0=100.0 + 2500 * df, fdot=-2e-10, alpha=1.1, delta=0.5,
+                    f2=5e-13, f3=(-2e-19 if order == 3 else 0.0))
+    w, xs, gaps = _setup(injections=[inj])
+    spins = np.array([[-2e-10, 5e-13, -2e-19], [0.0, 0.0, 0.0], [1e-10, -3e-13, 1e-19]])[:, :order]
+    sky = np.array([[1.1, 0.5], [3.0, -0.8]])
+    plan = gpu_lib.Plan(w)
+    plan.set_spin_order(order)
+    tx, tg = to_gpu(xs, gaps)
+    ts, tf = torch.from_numpy(sky).cuda(), torch.from_numpy(np.ascontiguousarray(spins)).cuda()
+    got = plan.fstat(tx, tg, ts, tf).cpu().numpy()
+    for si in range(2):
+        rs = [of.resample(xs[0], gaps[0], w.segment, *sky[si], w.eph, w.detectors[0], w.kernel, w.taps)]
+        for fi in range(3):
+            ref = of.fstat_band(rs, w.detectors, tuple(spins[fi]), plan.n_fft, plan.s_lo, plan.n_out)
+            assert np.all(np.abs(got[si * 3 + fi] - ref) <= twoF_tol(ref)), (order, si, fi)
+    # the matching template finds the injection at its bin
+    assert int(np.argmax(got[0])) == 2500 - plan.s_lo
+    vals, ids = plan.topk(tx, tg, ts, tf, k=5)
+    assert tuple(ids.cpu().numpy()[0]) == (0, 0, 2500 - plan.s_lo)
+    plan.close()
+
+
+def test_order_one_as_column_and_order_one_only_entries(gpu_lib):
+    import torch
+    w, xs, gaps = _setup(seed=5)
+    plan = gpu_lib.Plan(w)
+    tx, tg = to_gpu(xs, gaps)
+    sky = torch.tensor([[0.7, 0.2]], dtype=torch.float64).cuda()
+    fd = torch.from_numpy(synth.fdot_grid(4)).cuda()
+    a = plan.fstat(tx, tg, sky, fd).cpu().numpy()
+    b = plan.fstat(tx, tg, sky, fd[:, None].contiguous()).cpu().numpy()
+    assert np.array_equal(a, b)
+    plan.set_spin_order(2)
+    theta = torch.tensor([[100.01, -1e-10, 0.7, 0.2]], dtype=torch.float64).cuda()
+    with pytest.raises(Exception, match="spin order 1 only"):
+        plan.point(tx, tg, theta)
+    S = torch.zeros((4, 100), dtype=torch.float32, device="cuda")
+    spins = torch.zeros((4, 2), dtype=torch.float64, device="cuda")
+    with pytest.raises(Exception, match="spin order 1 only"):
+        plan.semicoherent(tx, tg, sky, spins, S, 0.0, 99.9, 1e-4)
+    with pytest.raises(ValueError):
+        plan.fstat(tx, tg, sky, fd)        # [n] at order 2
+    plan.close()
