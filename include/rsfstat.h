@@ -350,6 +350,38 @@ int rsf_sft_heterodyne(const rsf_sft_plan* plan, const float* sft, float* x_h, v
 int rsf_sft_profile_enable(rsf_sft_plan* plan, int on);
 int rsf_sft_profile_read(rsf_sft_plan* plan, rsf_kernel_time* out, int max_kinds, int* n_kinds);
 
+/* ---------------------------------------------------------------------------
+ * Time-domain front end (paper Sec. III.A.1, eqs. eq14-eq16): from a real
+ * high-rate series x[m] (float32, m < n_raw, sample m at m dt_raw from the
+ * series start) to the heterodyned, downsampled series
+ *   x_h[j] = sum_i h[i] x[j D + c - i] exp(-2 pi i f_het (j D + c - i) dt_raw),
+ * j < n_out, with output sample j at j D dt_raw (band B = 1 / (D dt_raw)).
+ * h: L = 2 K D + 1 taps centred on c = K D, a sinc with cutoff B/2 (the new
+ * Nyquist frequency) times a Kaiser window of parameter beta, normalised to
+ * unit gain at DC.  Raw samples outside [0, n_raw) count as zero.  The taps
+ * (heterodyne folded in, FP64 then FP32) live in the plan.  Requirements:
+ * D >= 1, K >= 0, beta >= 0, the taps and a tile of raw samples fitting in
+ * LDS (about (63 D + 3 L) * 4 bytes <= 160 KiB). */
+typedef struct rsf_hetdec_desc {
+    int64_t n_raw;    /* raw samples */
+    double dt_raw;    /* raw sampling interval, s */
+    double f_het;     /* heterodyne frequency, Hz */
+    int32_t D;        /* downsampling factor */
+    int32_t K;        /* filter half-length in output samples */
+    double beta;      /* Kaiser window parameter */
+    int64_t n_out;    /* output samples */
+} rsf_hetdec_desc;
+
+typedef struct rsf_hetdec_plan rsf_hetdec_plan;
+
+int rsf_hetdec_plan_create(rsf_hetdec_plan** out, const rsf_hetdec_desc* desc);
+int rsf_hetdec_plan_destroy(rsf_hetdec_plan* plan);
+/* x: float32 [n_raw] (device); x_h: complex64 [n_out] (device, overwritten).
+ * No workspace.  Asynchronous on `stream`. */
+int rsf_hetdec(const rsf_hetdec_plan* plan, const float* x, float* x_h, void* stream);
+int rsf_hetdec_profile_enable(rsf_hetdec_plan* plan, int on);
+int rsf_hetdec_profile_read(rsf_hetdec_plan* plan, rsf_kernel_time* out, int max_kinds, int* n_kinds);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* rsf_last_error(void);
 

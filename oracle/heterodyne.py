@@ -49,3 +49,19 @@ def heterodyne_decimate(x, dt_r, f_het, D, K, beta, n_out):
         ok = (m >= 0) & (m < len(x))
         out[j] = np.sum(h[ok] * xh[m[ok]])
     return out
+
+
+def heterodyne_decimate_at(x, dt_r, f_het, D, K, beta, js):
+    """Steps 1-3 at the output samples js only (for sampled checks of long
+    series); the same arithmetic as heterodyne_decimate."""
+    x = np.asarray(x)
+    h = kaiser_lowpass(D, K, beta)
+    L = len(h)
+    c = K * D
+    out = np.zeros(len(js), dtype=np.complex128)
+    for o, j in enumerate(js):
+        m = j * D + c - np.arange(L)
+        ok = (m >= 0) & (m < len(x))
+        mm = m[ok]
+        out[o] = np.sum(h[ok] * x[mm].astype(np.float64) * np.exp(-2j * np.pi * f_het * (mm * dt_r)))
+    return out

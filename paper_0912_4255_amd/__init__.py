@@ -13,7 +13,7 @@ from ._lib import (RSF_ENTRY_BACKWARD, RSF_ENTRY_FSTAT, RSF_ENTRY_POINT, RSF_ENT
 def __getattr__(name):
     # torch is imported lazily so that the pure-Python parts (synth, build)
     # work without it
-    if name in ("Plan", "plan_desc_from_workload", "FStatFn", "fstat_point", "SftPlan", "sft_desc_from_set"):
+    if name in ("Plan", "plan_desc_from_workload", "FStatFn", "fstat_point", "SftPlan", "sft_desc_from_set", "HetdecPlan"):
         from . import api
         return getattr(api, name)
     raise AttributeError(name)

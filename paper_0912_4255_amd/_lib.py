@@ -26,6 +26,8 @@ EXPORTS = [
     "rsf_graph_create_fstat", "rsf_graph_create_topk", "rsf_graph_launch", "rsf_graph_destroy",
     "rsf_sft_plan_create", "rsf_sft_plan_destroy", "rsf_sft_plan_query", "rsf_sft_workspace_size",
     "rsf_sft_heterodyne", "rsf_sft_profile_enable", "rsf_sft_profile_read",
+    "rsf_hetdec_plan_create", "rsf_hetdec_plan_destroy", "rsf_hetdec", "rsf_hetdec_profile_enable",
+    "rsf_hetdec_profile_read",
 ]
 
 
@@ -65,6 +67,11 @@ class SftDesc(C.Structure):
                 ("n_bins", C.c_int64), ("t_start", C.c_double), ("f_het", C.c_double), ("band", C.c_double),
                 ("n_out", C.c_int64), ("dk", C.c_int32), ("median_window", C.c_int32),
                 ("band_taper", C.c_double), ("edge_taper_s", C.c_double)]
+
+
+class HetdecDesc(C.Structure):
+    _fields_ = [("n_raw", C.c_int64), ("dt_raw", C.c_double), ("f_het", C.c_double), ("D", C.c_int32),
+                ("K", C.c_int32), ("beta", C.c_double), ("n_out", C.c_int64)]
 
 
 class KernelTime(C.Structure):
@@ -117,6 +124,11 @@ def load(path=None):
     lib.rsf_sft_heterodyne.argtypes = [vp, vp, vp, vp, sz, vp]
     lib.rsf_sft_profile_enable.argtypes = [vp, i32]
     lib.rsf_sft_profile_read.argtypes = [vp, C.POINTER(KernelTime), i32, C.POINTER(C.c_int)]
+    lib.rsf_hetdec_plan_create.argtypes = [C.POINTER(vp), C.POINTER(HetdecDesc)]
+    lib.rsf_hetdec_plan_destroy.argtypes = [vp]
+    lib.rsf_hetdec.argtypes = [vp, vp, vp, vp]
+    lib.rsf_hetdec_profile_enable.argtypes = [vp, i32]
+    lib.rsf_hetdec_profile_read.argtypes = [vp, C.POINTER(KernelTime), i32, C.POINTER(C.c_int)]
     lib.rsf_last_error.restype = C.c_char_p
     lib.rsf_last_error.argtypes = []
     lib.rsf_version.argtypes = []

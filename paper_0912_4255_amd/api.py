@@ -410,3 +410,46 @@ class SftPlan:
             self.close()
         except Exception:
             pass
+
+
+class HetdecPlan:
+    """An rsf_hetdec_plan: the heterodyned low-pass taps of the time-domain
+    front end (paper Sec. III.A.1)."""
+
+    def __init__(self, n_raw, dt_raw, f_het, D, K, beta, n_out):
+        self.lib = L.load()
+        self.desc = L.HetdecDesc(int(n_raw), float(dt_raw), float(f_het), int(D), int(K), float(beta), int(n_out))
+        self._p = C.c_void_p()
+        L.check(self.lib.rsf_hetdec_plan_create(C.byref(self._p), C.byref(self.desc)))
+
+    def run(self, x, out=None):
+        """rsf_hetdec: float32 [n_raw] -> complex64 [n_out]."""
+        _need_cuda(x, torch.float32, "x")
+        if x.numel() != self.desc.n_raw:
+            raise ValueError("x must hold n_raw samples")
+        out = out if out is not None else torch.empty(self.desc.n_out, dtype=torch.complex64, device=x.device)
+        _need_cuda(out, torch.complex64, "out")
+        if out.numel() != self.desc.n_out:
+            raise ValueError("out must hold n_out samples")
+        L.check(self.lib.rsf_hetdec(self._p, _ptr(x), _ptr(out), _stream()))
+        return out
+
+    def profile(self, on=True):
+        L.check(self.lib.rsf_hetdec_profile_enable(self._p, 1 if on else 0))
+
+    def profile_read(self):
+        buf = (L.KernelTime * 4)()
+        n = C.c_int()
+        L.check(self.lib.rsf_hetdec_profile_read(self._p, buf, 4, C.byref(n)))
+        return {buf[i].name.decode(): (buf[i].launches, buf[i].total_ms) for i in range(min(n.value, 4))}
+
+    def close(self):
+        if self._p:
+            self.lib.rsf_hetdec_plan_destroy(self._p)
+            self._p = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

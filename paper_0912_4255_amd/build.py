@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librsfstat.so")
 
-SOURCES = ["rsf_abi.cpp", "rsf_resample.hip", "rsf_fft.hip", "rsf_point.hip", "rsf_topk.hip", "rsf_sft.hip", "rsf_semico.hip"]
+SOURCES = ["rsf_abi.cpp", "rsf_resample.hip", "rsf_fft.hip", "rsf_point.hip", "rsf_topk.hip", "rsf_sft.hip", "rsf_semico.hip", "rsf_hetdec.hip"]
 
 ARCH = os.environ.get("RSF_OFFLOAD_ARCH", "gfx950")
 FLAGS = [

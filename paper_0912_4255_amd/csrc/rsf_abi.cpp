@@ -148,10 +148,11 @@ struct Profiler {
     };
     std::vector<Rec> pending;
     std::vector<hipEvent_t> pool;
-    static constexpr int kKinds = 12;
+    static constexpr int kKinds = 13;
     const char* names[kKinds] = {"rsf_resample_k", "rsf_antenna_reduce_k", "rsf_fft_pass_a_k", "rsf_fft_pass_b_k",
                                  "rsf_point_k",    "rsf_point_reduce_k",   "rsf_topk_k",       "rsf_sft_norm_k",
-                                 "rsf_sft_merge_k", "rsf_sft_rows_k",      "rsf_sft_cols_k",   "rsf_semico_k"};
+                                 "rsf_sft_merge_k", "rsf_sft_rows_k",      "rsf_sft_cols_k",   "rsf_semico_k",
+                                 "rsf_hetdec_k"};
     int64_t launches[kKinds] = {};
     double ms[kKinds] = {};
 
@@ -175,7 +176,7 @@ struct Profiler {
 };
 enum {
     K_RESAMPLE = 0, K_REDUCE = 1, K_PASS_A = 2, K_PASS_B = 3, K_POINT = 4, K_POINT_REDUCE = 5, K_TOPK = 6,
-    K_SFT_NORM = 7, K_SFT_MERGE = 8, K_SFT_ROWS = 9, K_SFT_COLS = 10, K_SEMICO = 11
+    K_SFT_NORM = 7, K_SFT_MERGE = 8, K_SFT_ROWS = 9, K_SFT_COLS = 10, K_SEMICO = 11, K_HETDEC = 12
 };
 }  // namespace
 
@@ -1467,3 +1468,111 @@ int rsf_sft_profile_read(rsf_sft_plan* p, rsf_kernel_time* out, int max_kinds, i
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Time-domain front end (paper Sec. III.A.1)
+// ---------------------------------------------------------------------------
+struct rsf_hetdec_plan {
+    rsf_hetdec_desc d;
+    Profiler* prof;
+    int L, c;
+    float2* g;  // device taps
+};
+
+extern "C" {
+
+int rsf_hetdec_plan_create(rsf_hetdec_plan** out, const rsf_hetdec_desc* d) {
+    if (!out || !d) return fail(RSF_EINVAL, "out or desc is NULL");
+    *out = nullptr;
+    if (d->n_raw < 1 || d->n_out < 1 || d->D < 1 || d->K < 0)
+        return fail(RSF_EINVAL, "n_raw, n_out and D must be positive and K >= 0");
+    if (!is_fin(d->dt_raw) || d->dt_raw <= 0 || !is_fin(d->f_het) || !is_fin(d->beta) || d->beta < 0)
+        return fail(RSF_EINVAL, "dt_raw must be positive and f_het, beta finite (beta >= 0)");
+    const int64_t L = 2LL * d->K * d->D + 1;
+    if (L > (1 << 20) || d->n_out > (int64_t)INT32_MAX * 64) return fail(RSF_EINVAL, "filter or output too long");
+    const size_t lds = hetdec_lds((int)L, d->D);
+    if (lds > 163840) return fail(RSF_EUNSUPPORTED, "taps and raw tile need %zu bytes of LDS (> 160 KiB)", lds);
+    // Kaiser-windowed sinc, cutoff 1/(2D) cycles per raw sample, unit DC gain
+    const int64_t c = (int64_t)d->K * d->D;
+    std::vector<double> h((size_t)L);
+    double sum = 0.0;
+    const double i0b = std::cyl_bessel_i(0.0, d->beta);
+    for (int64_t i = 0; i < L; ++i) {
+        const double n = (double)(i - c);
+        const double x = n / (double)d->D;
+        const double sinc = (i == c) ? 1.0 : std::sin(M_PI * x) / (M_PI * x);
+        const double r = c > 0 ? n / (double)c : 0.0;
+        const double w = c > 0 ? std::cyl_bessel_i(0.0, d->beta * std::sqrt(std::max(0.0, 1.0 - r * r))) / i0b : 1.0;
+        h[(size_t)i] = sinc / (double)d->D * w;
+        sum += h[(size_t)i];
+    }
+    // heterodyne folded into the taps: exp(-2 pi i f_h (c - i) dt), angle reduced in cycles
+    std::vector<float2> g((size_t)L);
+    for (int64_t i = 0; i < L; ++i) {
+        const double cyc = d->f_het * ((double)(c - i) * d->dt_raw);
+        const double fr = cyc - std::nearbyint(cyc);
+        const double v = h[(size_t)i] / sum;
+        g[(size_t)i] = make_float2((float)(v * std::cos(2.0 * M_PI * fr)), (float)(-v * std::sin(2.0 * M_PI * fr)));
+    }
+    auto* p = new rsf_hetdec_plan();
+    p->d = *d;
+    p->prof = new Profiler();
+    p->L = (int)L;
+    p->c = (int)c;
+    p->g = nullptr;
+    if (hipMalloc((void**)&p->g, g.size() * sizeof(float2)) != hipSuccess ||
+        hipMemcpy(p->g, g.data(), g.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(p->g);
+        delete p->prof;
+        delete p;
+        return fail(RSF_EHIP, "tap upload failed");
+    }
+    if (lds > 65536 && hetdec_set_lds_limit(lds) != hipSuccess) {
+        (void)hipFree(p->g);
+        delete p->prof;
+        delete p;
+        return fail(RSF_EUNSUPPORTED, "cannot grant %zu bytes of LDS", lds);
+    }
+    *out = p;
+    return RSF_OK;
+}
+
+int rsf_hetdec_plan_destroy(rsf_hetdec_plan* p) {
+    if (p) {
+        (void)hipFree(p->g);
+        delete p->prof;
+        delete p;
+    }
+    return RSF_OK;
+}
+
+int rsf_hetdec(const rsf_hetdec_plan* p, const float* x, float* x_h, void* stream) {
+    if (!p || !x || !x_h) return fail(RSF_EINVAL, "plan, x or x_h is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    HetdecArgs a{};
+    a.x = x;
+    a.n_raw = p->d.n_raw;
+    a.g = p->g;
+    a.L = p->L;
+    a.c = p->c;
+    a.D = p->d.D;
+    a.cyc_per_out = p->d.f_het * ((double)p->d.D * p->d.dt_raw);
+    a.out = reinterpret_cast<float2*>(x_h);
+    a.n_out = p->d.n_out;
+    RSF_HIP(timed_pr(p->prof, K_HETDEC, s, [&] { return launch_hetdec(a, s); }), "hetdec launch");
+    return RSF_OK;
+}
+
+int rsf_hetdec_profile_enable(rsf_hetdec_plan* p, int on) {
+    if (!p) return fail(RSF_EINVAL, "plan is NULL");
+    p->prof->on = on != 0;
+    return RSF_OK;
+}
+
+int rsf_hetdec_profile_read(rsf_hetdec_plan* p, rsf_kernel_time* out, int max_kinds, int* n_kinds) {
+    if (!p || !n_kinds) return fail(RSF_EINVAL, "plan or n_kinds is NULL");
+    return profile_read(p->prof, out, max_kinds, n_kinds);
+}
+
+}  // extern "C"
+

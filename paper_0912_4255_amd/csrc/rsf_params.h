@@ -241,6 +241,18 @@ struct SemicoArgs {
     float* S;                 // [n_sky * n_fdot][n_c], accumulated
 };
 
+// Time-domain front end: x_h[j] = P_j sum_i g[i] x[j D + c - i], g the
+// heterodyned low-pass taps, P_j = exp(-2 pi i f_h j D dt_raw).
+struct HetdecArgs {
+    const float* x;           // real raw series [n_raw]
+    int64_t n_raw;
+    const float2* g;          // [L] complex taps
+    int L, c, D;
+    double cyc_per_out;       // f_h D dt_raw (cycles per output sample)
+    float2* out;              // [n_out]
+    int64_t n_out;
+};
+
 // ---------------------------------------------------------------------------
 // SFT front end (paper Sec. III.B)
 // ---------------------------------------------------------------------------

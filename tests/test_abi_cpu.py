@@ -47,6 +47,8 @@ def test_struct_sizes_match_header_layout():
     assert C.sizeof(L.TopkEntry) == 16
     # rsf_sft_desc: 5 int64 + 6 double + 2 int32
     assert C.sizeof(L.SftDesc) == 5 * 8 + 6 * 8 + 2 * 4
+    # rsf_hetdec_desc: int64, 2 double, 2 int32, double, int64
+    assert C.sizeof(L.HetdecDesc) == 8 + 2 * 8 + 2 * 4 + 8 + 8
 
 
 def test_null_arguments_rejected_without_gpu(lib):
@@ -122,4 +124,18 @@ def test_invalid_sft_descriptors_rejected_before_device_use(lib):
         t = np.ascontiguousarray(t, dtype=np.float64)
         rc = lib.rsf_sft_plan_create(C.byref(p), C.byref(desc), t.ctypes.data_as(C.POINTER(C.c_double)))
         assert rc == L.RSF_EINVAL, lib.rsf_last_error()
+        assert not p.value
+
+
+def test_invalid_hetdec_descriptors_rejected_before_device_use(lib):
+    good = dict(n_raw=1000, dt_raw=1.0 / 256.0, f_het=100.0, D=64, K=16, beta=8.0, n_out=10)
+    bad = [dict(D=0), dict(K=-1), dict(beta=-1.0), dict(dt_raw=0.0), dict(n_out=0), dict(f_het=float("inf")),
+           dict(D=512, K=16)]                       # taps and tile beyond 160 KiB of LDS
+    for b in bad:
+        d = dict(good)
+        d.update(b)
+        desc = L.HetdecDesc(d["n_raw"], d["dt_raw"], d["f_het"], d["D"], d["K"], d["beta"], d["n_out"])
+        p = C.c_void_p()
+        rc = lib.rsf_hetdec_plan_create(C.byref(p), C.byref(desc))
+        assert rc in (L.RSF_EINVAL, L.RSF_EUNSUPPORTED), (b, lib.rsf_last_error())
         assert not p.value

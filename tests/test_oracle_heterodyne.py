@@ -63,3 +63,11 @@ def test_worked_example_990_to_1000_hz():
     exp = 0.5 * (np.exp(2j * np.pi * (992.0 - fh) * tj) + np.exp(2j * np.pi * (998.0 - fh) * tj))
     core = slice(24, out_n - 24)
     assert np.max(np.abs(got[core] - exp[core])) < 2e-3
+
+
+def test_sampled_evaluation_equals_the_full_one():
+    rng = np.random.default_rng(9)
+    x = rng.standard_normal(4000)
+    full = oh.heterodyne_decimate(x, 1.0 / 128.0, 20.0, 16, 6, 7.0, 250)
+    js = [0, 1, 77, 248, 249]
+    assert np.allclose(oh.heterodyne_decimate_at(x, 1.0 / 128.0, 20.0, 16, 6, 7.0, js), full[js], rtol=0, atol=1e-12)
