@@ -74,21 +74,25 @@ def sample_mask(n, gaps):
     return m
 
 
-def heterodyne_correction(x_h, seg, alpha, delta, eph, det):
-    """Step 2: z(t^k) = x_h(t^k) exp(-2 pi i f_h t_m(t^k)) on the detector grid."""
+def heterodyne_correction(x_h, seg, alpha, delta, eph, det, binary=None):
+    """Step 2: z(t^k) = x_h(t^k) exp(-2 pi i f_h t_m(t^k)) on the detector grid
+    (t_m replaced by the total delay d with a binary orbit)."""
     t = np.arange(seg.n, dtype=np.float64) * seg.dt
     tm = roemer_delay(seg.t_start + t, alpha, delta, eph, det)
+    if binary is not None:
+        from .binary import binary_delay, emission_time
+        tm = tm - binary_delay(emission_time(seg.t_start + t + tm, binary), binary)
     return np.asarray(x_h, dtype=np.complex128) * np.exp(-2j * np.pi * seg.f_het * tm)
 
 
-def resample(x_h, gaps, seg, alpha, delta, eph, det, kernel, W):
+def resample(x_h, gaps, seg, alpha, delta, eph, det, kernel, W, binary=None):
     """Steps 2-5 for one detector and one sky position.
 
     Returns a dict with the detector times T^k, t_m,k, u_k = T^k/dt, the
     resampled series z~_k, the beam patterns a_k, b_k at T^k and the SSB
     mask m~_k."""
-    z = heterodyne_correction(x_h, seg, alpha, delta, eph, det)
-    T, tm = invert_ssb_times(seg, alpha, delta, eph, det)
+    z = heterodyne_correction(x_h, seg, alpha, delta, eph, det, binary)
+    T, tm = invert_ssb_times(seg, alpha, delta, eph, det, binary=binary)
     u = T / seg.dt
     zt = interpolate(z, u, kernel, W)
     a, b = beam_ab(seg.t_start + T, alpha, delta, eph, det)

@@ -11,7 +11,8 @@ heterodyne sign of Sec. III.A.1's worked example).
 Psi - Phi0 = 2 pi f0 (t + t_m) + Phi_s(t),
 Phi_s = 2 pi sum_j f^(j) (t^{j+1}/(j+1)! + t_m t^j/j!) for j = 1..3 (f^(1) = fdot,
 f^(2), f^(3) of the injection; zero unless set), with t measured from the
-segment start (Phi0 is the phase there).
+segment start (Phi0 is the phase there).  With a binary orbit (oracle.binary)
+t_m is replaced by the total delay d = t_m - R(tau_e).
 """
 import numpy as np
 
@@ -24,6 +25,9 @@ def signal(seg, inj, eph, det):
     t = np.arange(seg.n, dtype=np.float64) * seg.dt
     tau = seg.t_start + t
     tm = roemer_delay(tau, inj.alpha, inj.delta, eph, det)
+    if inj.binary is not None:                    # total delay d = t_m - R(tau_e)
+        from .binary import binary_delay, emission_time
+        tm = tm - binary_delay(emission_time(tau + tm, inj.binary), inj.binary)
     fp, fx = beam_fplus_fcross(tau, inj.alpha, inj.delta, inj.psi, eph, det)
     a_plus = inj.h0 * (1.0 + inj.cosi ** 2) / 2.0
     a_cross = inj.h0 * inj.cosi

@@ -23,13 +23,19 @@ def ssb_grid(seg):
     return np.arange(seg.n, dtype=np.float64) * seg.dt
 
 
-def invert_ssb_times(seg, alpha, delta, eph, det, tol=1e-12, max_iter=12):
+def invert_ssb_times(seg, alpha, delta, eph, det, tol=1e-12, max_iter=12, binary=None):
     """Return (T, t_m_at_T): detector times T^k with T^k + t_m(T^k) = k dt,
-    and t_m,k = t_b^k - T^k."""
+    and t_m,k = t_b^k - T^k.  With a binary orbit (oracle.binary) the grid is
+    regular in emission time and the target is k dt + R(t_s + k dt); the
+    second value is then the total delay d at T^k."""
     tb = ssb_grid(seg)
-    T = tb.copy()
+    target = tb
+    if binary is not None:
+        from .binary import binary_delay
+        target = tb + binary_delay(seg.t_start + tb, binary)
+    T = target.copy()
     for _ in range(max_iter):
-        T_new = tb - roemer_delay(seg.t_start + T, alpha, delta, eph, det)
+        T_new = target - roemer_delay(seg.t_start + T, alpha, delta, eph, det)
         step = np.max(np.abs(T_new - T)) if T.size else 0.0
         T = T_new
         if step <= tol:

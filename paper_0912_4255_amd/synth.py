@@ -84,6 +84,16 @@ STORE_F16 = 1
 
 
 @dataclass
+class Binary:
+    """Circular binary orbit of the source: projected semi-major axis a_p
+    (light-seconds), period p_orb (s), time of the ascending node t_asc (s,
+    on the ephemeris clock)."""
+    a_p: float
+    p_orb: float
+    t_asc: float
+
+
+@dataclass
 class Injection:
     h0: float
     cosi: float
@@ -95,6 +105,7 @@ class Injection:
     delta: float
     f2: float = 0.0     # second and third frequency derivatives (eq. eq4, s up to 3)
     f3: float = 0.0
+    binary: Optional[Binary] = None
 
 
 @dataclass
