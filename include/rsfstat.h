@@ -149,6 +149,19 @@ int rsf_plan_destroy(rsf_plan* plan);
  * Phi_s = 2 pi sum_j f^(j) (T^{j+1}/(j+1)! + t_m T^j/j!).  The point and gradient
  * entries and the semi-coherent sum take order 1 only (RSF_EUNSUPPORTED). */
 int rsf_plan_set_spin_order(rsf_plan* plan, int order);
+
+/* Sources in circular binary orbits (on != 0; default off).  Every `sky`
+ * argument becomes double [n_sky][5]: (alpha, delta, a_p, P_b, t_asc) with
+ * the projected semi-major axis a_p in light-seconds (>= 0), the period P_b
+ * in seconds (> 0, 2 pi a_p / P_b <= 1e-2) and the time of the ascending node
+ * t_asc on the clock of t_start.  A wavefront emitted at tau_e reaches the
+ * SSB at tau_e + R(tau_e), R = a_p sin(2 pi (tau_e - t_asc) / P_b).  The
+ * resampled grid is then regular in emission time: T^k solves
+ * T + t_m(T) = k dt + R(t_start + k dt), and the heterodyne correction and
+ * the spindown phase use the total delay d = t_m - R(tau_e) in place of t_m.
+ * The point and gradient entries take isolated sources only
+ * (RSF_EUNSUPPORTED). */
+int rsf_plan_set_binary(rsf_plan* plan, int on);
 /* Batching knobs of RSF_MODE_BATCHED (0 = keep the automatic value):
  * fb = spindowns sharing one read of the resampled series in the first FFT
  * pass (1..16); templates = templates per FFT launch (1..256). */

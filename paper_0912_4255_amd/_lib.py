@@ -18,7 +18,7 @@ RSF_FLAG_DEGENERATE, RSF_FLAG_WINDOW = 1, 2
 
 EXPORTS = [
     "rsf_plan_create", "rsf_plan_destroy", "rsf_plan_query", "rsf_plan_set_batching", "rsf_plan_batching", "rsf_fft_factor",
-    "rsf_plan_set_spin_order",
+    "rsf_plan_set_spin_order", "rsf_plan_set_binary",
     "rsf_workspace_size",
     "rsf_resample", "rsf_fstat", "rsf_fstat_topk", "rsf_fstat_semicoherent", "rsf_fstat_point",
     "rsf_fstat_backward",
@@ -98,6 +98,7 @@ def load(path=None):
                                    C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double)]
     lib.rsf_plan_set_batching.argtypes = [vp, i32, i32]
     lib.rsf_plan_set_spin_order.argtypes = [vp, i32]
+    lib.rsf_plan_set_binary.argtypes = [vp, i32]
     lib.rsf_fft_factor.argtypes = [i64, i32, i32, C.POINTER(i32), C.POINTER(i32)]
     lib.rsf_plan_batching.argtypes = [vp, i64, i64, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
     lib.rsf_workspace_size.argtypes = [vp, i32, i64, i64, i32, C.POINTER(sz)]

@@ -63,6 +63,7 @@ class Plan:
         self.n_fft, self.s_lo, self.n_out = n_fft.value, s_lo.value, n_out.value
         self.fft_l1, self.fft_l2, self.df = l1.value, l2.value, df.value
         self.spin_order = 1
+        self.binary = False
 
     def set_batching(self, fb=0, templates=0):
         """rsf_plan_set_batching: spindowns sharing a first-pass row, templates per launch."""
@@ -79,6 +80,17 @@ class Plan:
         if fdot.dim() != 2 or fdot.shape[1] != self.spin_order:
             raise ValueError(f"fdot must be [n_fdot, {self.spin_order}] at spin order {self.spin_order}")
         return fdot.shape[0]
+
+    def set_binary(self, on=True):
+        """rsf_plan_set_binary: sky rows become (alpha, delta, a_p, P_b, t_asc)."""
+        L.check(self.lib.rsf_plan_set_binary(self._p, 1 if on else 0))
+        self.binary = bool(on)
+
+    def _n_sky(self, sky):
+        width = 5 if self.binary else 2
+        if sky.dim() != 2 or sky.shape[1] != width:
+            raise ValueError(f"sky must be [n_sky, {width}]")
+        return sky.shape[0]
 
     def set_spin_order(self, order):
         """rsf_plan_set_spin_order: templates carry (f^(1) .. f^(order)); fdot
@@ -139,7 +151,7 @@ class Plan:
     def resample(self, xs, gaps, sky, ws=None):
         """rsf_resample: per detector dict(z, a, b, tm, mask, abc) of [n_sky, ...] tensors."""
         _need_cuda(sky, torch.float64, "sky")
-        n_sky = sky.shape[0]
+        n_sky = self._n_sky(sky)
         seg, keep = self.segment(xs, gaps)
         dev = xs[0].device
         f16 = self.desc.storage == 1
@@ -164,7 +176,7 @@ class Plan:
         """rsf_fstat: 2F [n_sky * n_fdot, n_out] (float32), ascending frequency."""
         _need_cuda(sky, torch.float64, "sky")
         _need_cuda(fdot, torch.float64, "fdot")
-        n_sky, n_fdot = sky.shape[0], self._n_fdot(fdot)
+        n_sky, n_fdot = self._n_sky(sky), self._n_fdot(fdot)
         seg, keep = self.segment(xs, gaps)
         dev = xs[0].device
         if out is None:
@@ -183,7 +195,7 @@ class Plan:
         and bins; returns (values float32 [k], indices int32 [k, 3])."""
         _need_cuda(sky, torch.float64, "sky")
         _need_cuda(fdot, torch.float64, "fdot")
-        n_sky, n_fdot = sky.shape[0], self._n_fdot(fdot)
+        n_sky, n_fdot = self._n_sky(sky), self._n_fdot(fdot)
         seg, keep = self.segment(xs, gaps)
         dev = xs[0].device
         out = torch.empty((k, 4), dtype=torch.int32, device=dev)
@@ -199,7 +211,7 @@ class Plan:
         _need_cuda(sky, torch.float64, "sky")
         _need_cuda(fdot, torch.float64, "fdot")
         _need_cuda(S, torch.float32, "S")
-        n_sky, n_fdot = sky.shape[0], self._n_fdot(fdot)
+        n_sky, n_fdot = self._n_sky(sky), self._n_fdot(fdot)
         if S.dim() != 2 or S.shape[0] != n_sky * n_fdot:
             raise ValueError("S must be [n_sky * n_fdot][n_c]")
         seg, keep = self.segment(xs, gaps)
@@ -244,7 +256,7 @@ class Plan:
         (Graph, out).  Graph.launch() replays it on the current stream."""
         _need_cuda(sky, torch.float64, "sky")
         _need_cuda(fdot, torch.float64, "fdot")
-        n_sky, n_fdot = sky.shape[0], self._n_fdot(fdot)
+        n_sky, n_fdot = self._n_sky(sky), self._n_fdot(fdot)
         seg, keep = self.segment(xs, gaps)
         dev = xs[0].device
         if out is None:
@@ -258,7 +270,7 @@ class Plan:
 
     def graph_topk(self, xs, gaps, sky, fdot, k=10, ws=None):
         """Capture a rsf_fstat_topk call into a HIP graph; returns (Graph, values, indices)."""
-        n_sky, n_fdot = sky.shape[0], self._n_fdot(fdot)
+        n_sky, n_fdot = self._n_sky(sky), self._n_fdot(fdot)
         seg, keep = self.segment(xs, gaps)
         dev = xs[0].device
         res = torch.empty((k, 4), dtype=torch.int32, device=dev)

@@ -191,6 +191,7 @@ struct rsf_plan {
     int n_groups;        // ceil(LA / 8)
     int n_cu;            // compute units (persistent second-pass grid)
     int spin_order;      // spindown derivatives per template (eq. eq4pt1), 1..3
+    int binary;          // sky rows carry a circular binary orbit (a_p, P_b, t_asc)
     int fb_override;     // spindowns sharing a row in the first pass (0 = automatic)
     int g_override;      // templates per FFT launch (0 = automatic)
     FftStages stA, stB;
@@ -408,6 +409,7 @@ int rsf_plan_create(rsf_plan** out, const rsf_plan_desc* d) {
     p->d = *d;
     p->prof = new Profiler();
     p->spin_order = 1;
+    p->binary = 0;
     p->n = d->n;
     // even, so that a band reaching f_het +- 1/(2 dt) has its edges on bins
     p->n_fft = (d->nfft_policy == RSF_NFFT_TWICE) ? 2 * d->n : 2 * next_7smooth(d->n);
@@ -524,6 +526,12 @@ int rsf_plan_destroy(rsf_plan* p) {
     return RSF_OK;
 }
 
+int rsf_plan_set_binary(rsf_plan* p, int on) {
+    if (!p) return fail(RSF_EINVAL, "plan is NULL");
+    p->binary = on ? 1 : 0;
+    return RSF_OK;
+}
+
 int rsf_plan_set_spin_order(rsf_plan* p, int order) {
     if (!p) return fail(RSF_EINVAL, "plan is NULL");
     if (order < 1 || order > 3) return fail(RSF_EINVAL, "spin order must be 1, 2 or 3");
@@ -617,6 +625,8 @@ int rsf_resample(const rsf_plan* p, const rsf_segment* seg, const double* sky, i
     for (int X = 0; X < p->d.n_det; ++X) {
         ResampleArgs a = base_resample_args(p, seg, X);
         a.sky = sky;
+        a.sky_stride = p->binary ? 5 : 2;
+        a.binary = p->binary;
         a.LB = 64;
         a.P = P;
         a.layout = 0;
@@ -696,7 +706,9 @@ int run_fstat(const rsf_plan* p, const rsf_segment* seg, const double* sky, int6
         const int sc = (int)std::min<int64_t>(L.S, n_sky - c0);
         for (int X = 0; X < p->d.n_det; ++X) {
             ResampleArgs a = base_resample_args(p, seg, X);
-            a.sky = sky + 2 * c0;
+            a.sky = sky + (p->binary ? 5 : 2) * c0;
+            a.sky_stride = p->binary ? 5 : 2;
+            a.binary = p->binary;
             a.LB = p->LB;
             a.P = p->P;
             a.layout = 1;
@@ -901,6 +913,7 @@ int point_common(const rsf_plan* p, const rsf_segment* seg, const double* theta,
     int rc = check_segment(p, seg);
     if (rc) return rc;
     if (p->spin_order != 1) return fail(RSF_EUNSUPPORTED, "point evaluation and its gradient take spin order 1 only");
+    if (p->binary) return fail(RSF_EUNSUPPORTED, "point evaluation and its gradient take isolated sources only");
     if (!theta) return fail(RSF_EINVAL, "theta is NULL");
     if (n < 1 || n > 65535) return fail(RSF_EINVAL, "number of candidates must be in 1..65535");
     if (grad && (!g_twoF || !g_theta)) return fail(RSF_EINVAL, "g_twoF or g_theta is NULL");

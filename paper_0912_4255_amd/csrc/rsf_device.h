@@ -553,6 +553,29 @@ __device__ __forceinline__ Inversion invert_ssb(double t_start, double tb, const
     return v;
 }
 
+// Circular binary orbit of the source: a wavefront emitted at tau_e reaches
+// the SSB at tau_e + R(tau_e), R = a_p sin(2 pi (tau_e - t_asc) / P_b).
+struct BinaryOrbit {
+    double a_p, p_orb, t_asc;
+};
+__device__ __forceinline__ double binary_delay(const BinaryOrbit& b, double tau_e) {
+    const double cyc = (tau_e - b.t_asc) / b.p_orb;
+    return b.a_p * sin(2.0 * kPi * (cyc - floor(cyc)));
+}
+// tau_e with tau_e + R(tau_e) = tau_ssb by the fixed point tau_e <- tau_ssb - R(tau_e):
+// contraction 2 pi a_p / P_b (<= 1e-2 is required), at most 8 steps, stopping
+// once a step changes nothing.
+__device__ __forceinline__ double emission_time(const BinaryOrbit& b, double tau_ssb) {
+    double te = tau_ssb;
+    for (int it = 0; it < 8; ++it) {
+        const double tn = tau_ssb - binary_delay(b, te);
+        const bool done = tn == te;
+        te = tn;
+        if (done) break;
+    }
+    return te;
+}
+
 // Lane l's double, read into scalar registers (l must be wave-uniform).
 __device__ __forceinline__ double readlane_d(double v, int l) {
     const long long b = __double_as_longlong(v);

@@ -72,7 +72,9 @@ struct ResampleArgs {
     const float2* x;
     const int64_t* gaps;
     int n_gaps;
-    const double* sky;        // [n_sky][2]
+    const double* sky;        // [n_sky][sky_stride]: alpha, delta (, a_p, P_b, t_asc with a binary orbit)
+    int sky_stride;           // 2, or 5 with a binary orbit
+    int binary;
     // tile geometry: k = LB * n_a + n_b, 0 <= n_b < LB, 0 <= n_a < P
     int LB;
     int64_t P;

@@ -49,6 +49,11 @@ __device__ __forceinline__ uint32_t pack_half2(float re, float im) {
 }
 }  // namespace
 
+// BIN: the source is in a circular binary orbit; the grid is regular in
+// emission time (target t_b + R(t_s + t_b) of the inversion) and the delay
+// used by the correction and stored for the spindown phase is the total
+// d = t_m - R(tau_e), tau_e from tau_e + R(tau_e) = tau + t_m(tau).
+template <bool BIN>
 __global__ __launch_bounds__(kThreads) void rsf_resample_k(ResampleArgs A) {
     __shared__ float2 win[4][kWinMax];
     __shared__ float4 tile_main[kTileA][kTileB + 1];
@@ -61,7 +66,10 @@ __global__ __launch_bounds__(kThreads) void rsf_resample_k(ResampleArgs A) {
     const int b0 = blockIdx.x * kTileB;
     const int64_t a0 = (int64_t)blockIdx.y * kTileA;
     const int sky = blockIdx.z;
-    const double alpha = A.sky[2 * sky], delta = A.sky[2 * sky + 1];
+    const double* srow = A.sky + (int64_t)A.sky_stride * sky;
+    const double alpha = srow[0], delta = srow[1];
+    BinaryOrbit bo{};
+    if constexpr (BIN) bo = BinaryOrbit{srow[2], srow[3], srow[4]};
     const double3 n0 = sky_unit(alpha, delta);
     const SkyFrame fr = sky_frame(alpha, delta);
     const int W = A.ip.taps;
@@ -84,7 +92,9 @@ __global__ __launch_bounds__(kThreads) void rsf_resample_k(ResampleArgs A) {
         Inversion inv{};
         if (valid) {
             const double tb = (double)k * A.dt;
-            inv = invert_ssb(A.t_start, tb, n0, A.eph, A.det);
+            double target = tb;
+            if constexpr (BIN) target = tb + binary_delay(bo, A.t_start + tb);
+            inv = invert_ssb(A.t_start, target, n0, A.eph, A.det);
             const double T = inv.T;
             tm = tb - T;
             const double u = T / A.dt;
@@ -119,7 +129,9 @@ __global__ __launch_bounds__(kThreads) void rsf_resample_k(ResampleArgs A) {
                 float2 z = make_float2(0.f, 0.f);
                 if (jj >= 0 && jj < A.n) {
                     const float2 xv = A.x[jj];
-                    const double tmj = tm_expand(rref, (double)jj * A.dt - t_ref);
+                    double tmj = tm_expand(rref, (double)jj * A.dt - t_ref);
+                    if constexpr (BIN)
+                        tmj -= binary_delay(bo, emission_time(bo, A.t_start + (double)jj * A.dt + tmj));
                     const double cyc = A.f_het * tmj;
                     const float ph = (float)(cyc - rint(cyc));
                     const float s = __builtin_amdgcn_sinf(ph), c = __builtin_amdgcn_cosf(ph);  // revolutions
@@ -327,7 +339,10 @@ __global__ __launch_bounds__(256) void rsf_antenna_reduce_k(ReduceArgs R) {
 hipError_t launch_resample(const ResampleArgs& a, int n_sky, hipStream_t s) {
     const unsigned gx = (unsigned)((a.LB + kTileB - 1) / kTileB);
     const unsigned gy = (unsigned)((a.P + kTileA - 1) / kTileA);
-    hipLaunchKernelGGL(rsf_resample_k, dim3(gx, gy, (unsigned)n_sky), dim3(kThreads), 0, s, a);
+    if (a.binary)
+        hipLaunchKernelGGL(rsf_resample_k<true>, dim3(gx, gy, (unsigned)n_sky), dim3(kThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL(rsf_resample_k<false>, dim3(gx, gy, (unsigned)n_sky), dim3(kThreads), 0, s, a);
     return hipGetLastError();
 }
 
