@@ -25,6 +25,8 @@ def _run(gpu_lib, x, dt, fh, D, K, beta, n_out):
     (1.0 / 64.0, 10.3, 1, 0, 5000, 5000),          # heterodyne only
     (1.0 / 1000.0, 995.0, 100, 12, 40000, 400),     # the worked example's rates
     (1.0 / 256.0, 100.0, 32, 12, 256 * 37 + 11, 300),  # ragged: 300 outputs, the last tile partial
+    (1.0 / 256.0, 101.0, 64, 8, 256 * 80 + 5, 320),     # polyphase form (D = 64), ragged chunks
+    (1.0 / 256.0, 101.0, 64, 16, 256 * 80, 300),        # polyphase, 33 taps per phase
 ])
 def test_matches_oracle(gpu_lib, dt, fh, D, K, n_raw, n_out):
     rng = np.random.default_rng(D + K)
