@@ -384,7 +384,7 @@ def main():
     if not a.no_cpu:
         cpu = cpu_baseline(w, x, w.gaps[0], a.cpu_templates, n_t)
 
-    rec = {"metric": "F-stat templates/s at T=10d, 2Hz band (batched; plain and %HBM alongside)",
+    rec = {"metric": "F-stat templates/s at T=10d, 2Hz band: plain vs batched+grad; %HBM roofline",
            "value": round(value, 2), "unit": "templates/s", "n_gpus": 1, "steps": a.steps,
            "warmup": a.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
