@@ -40,6 +40,10 @@
  * Nothing aborts or throws across this interface.  A template whose Gram
  * determinant D' is not positive (e.g. an all-gap segment) yields NaN outputs
  * and sets RSF_FLAG_DEGENERATE in the flags word readable with rsf_get_flags.
+ * A run of 64 consecutive resampled times whose interpolation windows span
+ * more detector samples than a wave stages (only for time compressions far
+ * beyond any physical Doppler factor) yields NaN samples there and sets
+ * RSF_FLAG_WINDOW.
  */
 #ifndef RSFSTAT_H
 #define RSFSTAT_H
