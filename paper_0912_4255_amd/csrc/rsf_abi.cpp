@@ -148,11 +148,11 @@ struct Profiler {
     };
     std::vector<Rec> pending;
     std::vector<hipEvent_t> pool;
-    static constexpr int kKinds = 13;
+    static constexpr int kKinds = 14;
     const char* names[kKinds] = {"rsf_resample_k", "rsf_antenna_reduce_k", "rsf_fft_pass_a_k", "rsf_fft_pass_b_k",
                                  "rsf_point_k",    "rsf_point_reduce_k",   "rsf_topk_k",       "rsf_sft_norm_k",
                                  "rsf_sft_merge_k", "rsf_sft_rows_k",      "rsf_sft_cols_k",   "rsf_semico_k",
-                                 "rsf_hetdec_k"};
+                                 "rsf_hetdec_k",   "rsf_sft_dft_k"};
     int64_t launches[kKinds] = {};
     double ms[kKinds] = {};
 
@@ -176,7 +176,7 @@ struct Profiler {
 };
 enum {
     K_RESAMPLE = 0, K_REDUCE = 1, K_PASS_A = 2, K_PASS_B = 3, K_POINT = 4, K_POINT_REDUCE = 5, K_TOPK = 6,
-    K_SFT_NORM = 7, K_SFT_MERGE = 8, K_SFT_ROWS = 9, K_SFT_COLS = 10, K_SEMICO = 11, K_HETDEC = 12
+    K_SFT_NORM = 7, K_SFT_MERGE = 8, K_SFT_ROWS = 9, K_SFT_COLS = 10, K_SEMICO = 11, K_HETDEC = 12, K_SFT_DFT = 13
 };
 }  // namespace
 
@@ -1160,17 +1160,24 @@ struct rsf_sft_plan {
     std::vector<int64_t> gaps;            // [n][2]
     int64_t y_total;                      // band bins of all chunks
     size_t spill_total;                   // float4 elements of all spills
-    int64_t merge_blocks;
-    size_t merge_lds, lds_max;
+    int64_t merge_blocks, dft_blocks;     // workgroups of the merge and DFT launches
+    int64_t dft_total;                    // elements of all chunks' DFT tables
+    size_t dft_lds, lds_max;
     SftChunkDev* chunks_dev;              // device table
     int* ids_dev;                         // chunk ids, grouped by length
     std::vector<int64_t> ids_off;         // first id of each group in ids_dev
+    SftLenDev* lens_dev;                  // device table of the transform lengths
+    int64_t rows_blocks, cols_blocks;     // workgroups of the single rows / columns launches
+    size_t rows_lds, cols_lds;
 };
 
 namespace {
 
+// Workspace: normalised bins | band bins y | spill.  The DFT tables live in
+// the spill's space: the merge has consumed them before the rows pass
+// writes the spill (stream order).
 struct SftWs {
-    size_t xh, y, spill, total;
+    size_t xh, y, spill, dft, total;
 };
 
 SftWs sft_ws(const rsf_sft_plan* p) {
@@ -1181,7 +1188,8 @@ SftWs sft_ws(const rsf_sft_plan* p) {
     L.y = off;
     off = align_up(off + (size_t)p->y_total * sizeof(float2));
     L.spill = off;
-    off = align_up(off + p->spill_total * sizeof(float4));
+    L.dft = off;
+    off = align_up(off + std::max(p->spill_total * sizeof(float4), (size_t)p->dft_total * sizeof(float2)));
     L.total = off;
     return L;
 }
@@ -1189,6 +1197,7 @@ SftWs sft_ws(const rsf_sft_plan* p) {
 void sft_free(rsf_sft_plan* p) {
     (void)hipFree(p->chunks_dev);
     (void)hipFree(p->ids_dev);
+    (void)hipFree(p->lens_dev);
     for (auto& x : p->xf) {
         (void)hipFree(x.t1);
         (void)hipFree(x.t1_hi);
@@ -1242,10 +1251,15 @@ int rsf_sft_plan_create(rsf_sft_plan** out, const rsf_sft_desc* d, const double*
     p->y_total = 0;
     p->spill_total = 0;
     p->merge_blocks = 0;
-    p->merge_lds = 0;
+    p->dft_blocks = 0;
+    p->dft_total = 0;
+    p->dft_lds = 0;
     p->lds_max = 0;
     p->chunks_dev = nullptr;
     p->ids_dev = nullptr;
+    p->lens_dev = nullptr;
+    p->rows_blocks = p->cols_blocks = 0;
+    p->rows_lds = p->cols_lds = 0;
     int dev = 0, lds_dev = 0;
     (void)hipGetDevice(&dev);
     if (hipDeviceGetAttribute(&lds_dev, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || lds_dev <= 0)
@@ -1303,7 +1317,7 @@ int rsf_sft_plan_create(rsf_sft_plan** out, const rsf_sft_desc* d, const double*
         }
         c.xf = xi;
         p->group[(size_t)xi].push_back((int)p->chunks.size());
-        p->merge_lds = std::max(p->merge_lds, sft_merge_lds(c.Mp, c.M, d->dk));
+        p->dft_lds = std::max(p->dft_lds, sft_dft_lds(c.Mp));
         const double tc = t_sft[a0] - d->t_start;
         c.j0 = (int64_t)std::nearbyint(tc * d->band);
         c.n_keep = p->band_bins * c.M;
@@ -1349,25 +1363,58 @@ int rsf_sft_plan_create(rsf_sft_plan** out, const rsf_sft_desc* d, const double*
         t.j0 = c.j0;
         t.n_keep = c.n_keep;
         t.blk0 = p->merge_blocks;
+        t.dft_off = p->dft_total;
+        t.dft_blk0 = p->dft_blocks;
         t.scale = (float)(1.0 / std::sqrt((double)x.n * (double)c.M));
         t.corr = c.corr;
         p->y_total += x.n;
         p->spill_total += (size_t)x.n_groups * kPassBCols * x.L2;
         p->merge_blocks += sft_merge_blocks((int)x.n);
+        p->dft_total += (int64_t)d->n_bins * c.Mp;
+        p->dft_blocks += sft_dft_blocks((int64_t)d->n_bins * c.Mp);
     }
     std::vector<int> ids;
     for (const auto& g : p->group) {
         p->ids_off.push_back((int64_t)ids.size());
         ids.insert(ids.end(), g.begin(), g.end());
     }
+    // table of the transform lengths: the workgroups of the single rows and
+    // columns launches, length after length
+    std::vector<SftLenDev> lens(p->xf.size());
+    for (size_t g = 0; g < p->xf.size(); ++g) {
+        const SftXform& x = p->xf[g];
+        SftLenDev& l = lens[g];
+        l.n = x.n;
+        l.LA = x.L1;
+        l.LB = x.L2;
+        l.n_groups = x.n_groups;
+        l.nc = (int)p->group[g].size();
+        l.id0 = (int)p->ids_off[g];
+        l.rows_blk0 = p->rows_blocks;
+        l.cols_blk0 = p->cols_blocks;
+        l.st1 = x.st1;
+        l.st2 = x.st2;
+        l.t1 = x.t1;
+        l.t1_hi = x.t1_hi;
+        l.t2 = x.t2;
+        l.t2_hi = x.t2_hi;
+        l.tw_lo = x.tw_lo;
+        l.tw_hi = x.tw_hi;
+        p->rows_blocks += (int64_t)x.L2 * l.nc;
+        p->cols_blocks += (int64_t)x.n_groups * l.nc;
+        p->rows_lds = std::max(p->rows_lds, fft_pass_a_lds(x.L1));
+        p->cols_lds = std::max(p->cols_lds, fft_pass_b_lds(x.L2, 0));
+    }
     if (hipMalloc((void**)&p->chunks_dev, tab.size() * sizeof(SftChunkDev)) != hipSuccess ||
         hipMemcpy(p->chunks_dev, tab.data(), tab.size() * sizeof(SftChunkDev), hipMemcpyHostToDevice) != hipSuccess ||
         hipMalloc((void**)&p->ids_dev, ids.size() * sizeof(int)) != hipSuccess ||
-        hipMemcpy(p->ids_dev, ids.data(), ids.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+        hipMemcpy(p->ids_dev, ids.data(), ids.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMalloc((void**)&p->lens_dev, lens.size() * sizeof(SftLenDev)) != hipSuccess ||
+        hipMemcpy(p->lens_dev, lens.data(), lens.size() * sizeof(SftLenDev), hipMemcpyHostToDevice) != hipSuccess) {
         sft_free(p);
         return fail(RSF_EHIP, "chunk table upload failed");
     }
-    const size_t lds_need = std::max(p->lds_max, p->merge_lds);
+    const size_t lds_need = std::max(p->lds_max, p->dft_lds);
     if (lds_need > 65536 && sft_set_lds_limits(lds_need) != hipSuccess) {
         sft_free(p);
         return fail(RSF_EUNSUPPORTED, "chunk transforms need %zu bytes of LDS", lds_need);
@@ -1421,8 +1468,17 @@ int rsf_sft_heterodyne(const rsf_sft_plan* p, const float* sft, float* x_h, void
     }
     float2* y = reinterpret_cast<float2*>(w + L.y);
     float4* spill = reinterpret_cast<float4*>(w + L.spill);
+    float2* Y = reinterpret_cast<float2*>(w + L.dft);
+    SftDftArgs f{};
+    f.xh = xh;
+    f.K = (int)d.n_bins;
+    f.chunks = p->chunks_dev;
+    f.n_chunks = (int)p->chunks.size();
+    f.Y = Y;
+    RSF_HIP(timed_pr(p->prof, K_SFT_DFT, s, [&] { return launch_sft_dft(f, p->dft_blocks, p->dft_lds, s); }),
+            "sft dft launch");
     SftMergeArgs m{};
-    m.xh = xh;
+    m.Y = Y;
     m.K = (int)d.n_bins;
     m.k_lo = d.k_lo;
     m.dk = d.dk;
@@ -1430,42 +1486,28 @@ int rsf_sft_heterodyne(const rsf_sft_plan* p, const float* sft, float* x_h, void
     m.chunks = p->chunks_dev;
     m.n_chunks = (int)p->chunks.size();
     m.y = y;
-    RSF_HIP(timed_pr(p->prof, K_SFT_MERGE, s, [&] { return launch_sft_merge(m, p->merge_blocks, p->merge_lds, s); }),
+    RSF_HIP(timed_pr(p->prof, K_SFT_MERGE, s, [&] { return launch_sft_merge(m, p->merge_blocks, s); }),
             "sft merge launch");
-    for (size_t g = 0; g < p->group.size(); ++g) {
-        const SftXform& x = p->xf[g];
-        const int nc = (int)p->group[g].size();
-        const int* ids = p->ids_dev + p->ids_off[g];
-        SftRowsArgs r{};
-        r.n = x.n;
-        r.LA = x.L1;
-        r.LB = x.L2;
-        r.st = x.st1;
-        r.tws_lo = x.t1;
-        r.tws_hi = x.t1_hi;
-        r.tw_lo = x.tw_lo;
-        r.tw_hi = x.tw_hi;
-        r.chunks = p->chunks_dev;
-        r.ids = ids;
-        r.y = y;
-        r.spill = spill;
-        RSF_HIP(timed_pr(p->prof, K_SFT_ROWS, s, [&] { return launch_sft_rows(r, nc, s); }), "sft rows launch");
-        SftColsArgs k{};
-        k.n = x.n;
-        k.LA = x.L1;
-        k.LB = x.L2;
-        k.n_groups = x.n_groups;
-        k.st = x.st2;
-        k.tw_lo = x.t2;
-        k.tw_hi = x.t2_hi;
-        k.chunks = p->chunks_dev;
-        k.ids = ids;
-        k.spill = spill;
-        k.x = reinterpret_cast<float2*>(x_h);
-        k.n_out = d.n_out;
-        k.n_edge = (int)std::nearbyint(d.edge_taper_s * d.band);
-        RSF_HIP(timed_pr(p->prof, K_SFT_COLS, s, [&] { return launch_sft_cols(k, nc, s); }), "sft cols launch");
-    }
+    SftRowsArgs r{};
+    r.lens = p->lens_dev;
+    r.n_lens = (int)p->xf.size();
+    r.chunks = p->chunks_dev;
+    r.ids = p->ids_dev;
+    r.y = y;
+    r.spill = spill;
+    RSF_HIP(timed_pr(p->prof, K_SFT_ROWS, s, [&] { return launch_sft_rows(r, p->rows_blocks, p->rows_lds, s); }),
+            "sft rows launch");
+    SftColsArgs k{};
+    k.lens = p->lens_dev;
+    k.n_lens = (int)p->xf.size();
+    k.chunks = p->chunks_dev;
+    k.ids = p->ids_dev;
+    k.spill = spill;
+    k.x = reinterpret_cast<float2*>(x_h);
+    k.n_out = d.n_out;
+    k.n_edge = (int)std::nearbyint(d.edge_taper_s * d.band);
+    RSF_HIP(timed_pr(p->prof, K_SFT_COLS, s, [&] { return launch_sft_cols(k, p->cols_blocks, p->cols_lds, s); }),
+            "sft cols launch");
     return RSF_OK;
 }
 

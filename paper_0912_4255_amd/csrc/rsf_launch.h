@@ -29,11 +29,13 @@ hipError_t launch_hetdec(const HetdecArgs& a, hipStream_t s);
 hipError_t hetdec_set_lds_limit(size_t bytes);
 
 hipError_t launch_sft_norm(const SftNormArgs& a, int n_sft, hipStream_t s);
+int64_t sft_dft_blocks(int64_t entries);  // DFT workgroups of a chunk of K M' entries
+size_t sft_dft_lds(int Mp);
+hipError_t launch_sft_dft(const SftDftArgs& a, int64_t blocks, size_t lds, hipStream_t s);
 int64_t sft_merge_blocks(int n);  // merge workgroups of a chunk of n bins
-size_t sft_merge_lds(int Mp, int M, int dk);
-hipError_t launch_sft_merge(const SftMergeArgs& a, int64_t blocks, size_t lds, hipStream_t s);
-hipError_t launch_sft_rows(const SftRowsArgs& a, int n_chunks, hipStream_t s);
-hipError_t launch_sft_cols(const SftColsArgs& b, int n_chunks, hipStream_t s);
+hipError_t launch_sft_merge(const SftMergeArgs& a, int64_t blocks, hipStream_t s);
+hipError_t launch_sft_rows(const SftRowsArgs& a, int64_t blocks, size_t lds, hipStream_t s);
+hipError_t launch_sft_cols(const SftColsArgs& b, int64_t blocks, size_t lds, hipStream_t s);
 hipError_t sft_set_lds_limits(size_t bytes);
 
 int point_blocks(int64_t P);

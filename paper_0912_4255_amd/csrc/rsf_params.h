@@ -278,17 +278,31 @@ struct SftChunkDev {
     int64_t spill_off;    // first float4 of its spill
     int64_t j0, n_keep;   // output offset and kept samples
     int64_t blk0;         // first merge workgroup of the chunk
+    int64_t dft_off;      // first element of its table Y[K][M'] in the DFT buffer
+    int64_t dft_blk0;     // first workgroup of the chunk in the DFT launch
     float scale;          // 1 / sqrt(n M)
     float2 corr;          // exp(-2 pi i f_h (t_c - t_s))
+};
+
+// Per chunk (one launch over all chunks), for every stored bin k and every
+// r < M': Y[k][r] = sum_{alpha < M} X^_{a0+alpha, k} W_{M'}^{r alpha}, the
+// M'-point DFT over the chunk's SFTs (missing ones zero) of each bin.
+struct SftDftArgs {
+    const float2* xh;     // normalised SFT bands [n_sft][K]
+    int K;
+    const SftChunkDev* chunks;
+    int n_chunks;
+    float2* Y;            // per chunk [K][M'] at dft_off
 };
 
 // Band bins of every chunk (one launch): bin m of chunk c is the
 // long-baseline transform (eqs. e9/e91, kernel of eq. e75) at
 // b = b0 + q (q = m below n/2, m - n above), times the Tukey window and the
 // scale, conjugated (the inverse transform runs as a forward one on
-// conjugates), at y[y_off + m].
+// conjugates), at y[y_off + m].  With b = k* M' + r, the sum over SFTs and
+// Dirichlet terms is taken as sum_d P_d(r) Y[k* + d][r].
 struct SftMergeArgs {
-    const float2* xh;     // normalised SFT bands [n_sft][K]
+    const float2* Y;      // the DFT tables of SftDftArgs
     int K;
     int64_t k_lo;
     int dk;
@@ -298,31 +312,41 @@ struct SftMergeArgs {
     float2* y;
 };
 
-// Rows pass over the chunks of one transform length n = LA LB: workgroup
-// (n_b, i) transforms row n_b (elements m = LB n_a + n_b) of chunk ids[i].
-struct SftRowsArgs {
+// One chunk transform length n = LA LB of the SFT front end.  Its chunks are
+// ids[id0 .. id0 + nc); in the single rows launch its workgroups are
+// rows_blk0 + i LB + n_b (row n_b of its i-th chunk), in the single columns
+// launch cols_blk0 + i n_groups + g (8-column group g of its i-th chunk).
+struct SftLenDev {
     int64_t n;
-    int LA, LB;
-    FftStages st;
-    const float2* tws_lo;   // W_LA^m = tws_lo[m % 32] * tws_hi[m / 32]
-    const float2* tws_hi;
+    int LA, LB, n_groups, nc, id0;
+    int64_t rows_blk0, cols_blk0;
+    FftStages st1, st2;
+    const float2* t1;       // W_LA^m = t1[m % 32] * t1_hi[m / 32]
+    const float2* t1_hi;
+    const float2* t2;       // W_LB^m = t2[m % 32] * t2_hi[m / 32]
+    const float2* t2_hi;
     const float2* tw_lo;    // W_n^m = tw_hi[m >> 12] * tw_lo[m & 4095]
     const float2* tw_hi;
+};
+
+// Rows pass over every chunk (one launch): workgroup -> (length, chunk, n_b)
+// through the length table; row n_b (elements m = LB n_a + n_b) is
+// transformed over n_a and spilled with the inter-pass twiddle.
+struct SftRowsArgs {
+    const SftLenDev* lens;
+    int n_lens;
     const SftChunkDev* chunks;
     const int* ids;
     const float2* y;
     float4* spill;
 };
 
-// Columns pass: output j = k_a + LA k_b of chunk ids[blockIdx.y]; the first
-// n_keep samples, conjugated, times the chunk's phase correction and the
-// edge taper, go to x[j0 + j].
+// Columns pass over every chunk (one launch): output j = k_a + LA k_b of a
+// chunk; the first n_keep samples, conjugated, times the chunk's phase
+// correction and the edge taper, go to x[j0 + j].
 struct SftColsArgs {
-    int64_t n;
-    int LA, LB, n_groups;
-    FftStages st;
-    const float2* tw_lo;    // W_LB^m = tw_lo[m % 32] * tw_hi[m / 32]
-    const float2* tw_hi;
+    const SftLenDev* lens;
+    int n_lens;
     const SftChunkDev* chunks;
     const int* ids;
     const float4* spill;

@@ -1,7 +1,9 @@
 // SFT front end (paper Sec. III.B): running-median normalisation of the
 // SFT bands (eq. dimlessSFTs1), and per contiguous chunk the long-baseline
 // transform by the truncated Dirichlet merge (eqs. dft3, e9, e91 with the
-// large-N kernel of eq. e75), relabelled so that f_h is DC, windowed over
+// large-N kernel of eq. e75; its double sum over SFTs and terms is taken as
+// a DFT over the SFTs per stored bin, then the terms), relabelled so that
+// f_h is DC, windowed over
 // the band and inverse transformed ("Downsampling and low-pass filtering"),
 // then moved to the common heterodyne reference (eq. hetStartCorr), tapered
 // at the chunk edges and written into the series ("Gaps in the data").
@@ -96,55 +98,71 @@ __global__ __launch_bounds__(kNormThreads) void rsf_sft_norm_k(SftNormArgs a) {
     }
 }
 
-// Merge: one workgroup per 256 consecutive relabelled bins u = q + n/2 of
-// one chunk (all chunks in one launch; the chunk comes from the workgroup
-// index).  The bins' long-baseline indices b = b0 - n/2 + u are contiguous,
-// so their k* span a short range; the SFT bins they need,
-// [k*_lo - dk, k*_hi + dk] of every SFT of the chunk, are staged in LDS in
-// tiles of SFTs and read from there by all the workgroup's bins.  For bin b,
-// k* = floor(b / M'), r = b - k* M'; the kernel of eq. e75 at
-// y = 2 pi (r/M' - d) for k = k* + d has sin y = sin(2 pi r/M') and
-// 1 - cos y = 2 sin^2(pi r/M') for every d, so P_d = (sin y - i (1 - cos y)) / y_d
-// (1 at y = 0; 0 for d != 0 when r = 0); the phase e^{-2 pi i b alpha / M'}
-// is e^{-2 pi i r alpha / M'}, read from the table of the M' roots.  Terms
-// outside the stored band are absent.  The bin, windowed, scaled and
-// conjugated, goes to y[y_off + m] with m = q mod n (natural order).
+// DFT over each chunk's SFTs: one thread per (k, r) of a chunk, consecutive
+// r on consecutive threads (they share X^_{alpha, k}); workgroups of one
+// chunk are contiguous from dft_blk0.  The phases W_{M'}^{r alpha} come from
+// a table of the M' roots in LDS, indexed by r alpha mod M'.
 namespace {
+constexpr int kDftThreads = 256;
 constexpr int kMergeThreads = 256;
-constexpr int kMergeStage = 32768;  // bytes of staged SFT bins per tile
-}  // namespace
 
-__global__ __launch_bounds__(kMergeThreads) void rsf_sft_merge_k(SftMergeArgs a) {
-    extern __shared__ float2 sm[];
-    // chunk of this workgroup: the last one whose first workgroup is <= ours
-    int lo = 0, hi = a.n_chunks - 1;
+// the chunk whose first workgroup (member BLK0) is the last one not after w
+template <int64_t SftChunkDev::*BLK0>
+__device__ __forceinline__ int sft_chunk_of(const SftChunkDev* chunks, int n_chunks, int64_t w) {
+    int lo = 0, hi = n_chunks - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (a.chunks[mid].blk0 <= (int64_t)blockIdx.x) lo = mid;
+        if (chunks[mid].*BLK0 <= w) lo = mid;
         else hi = mid - 1;
     }
-    const SftChunkDev c = a.chunks[lo];
-    const int n = c.n;
-    const int u0 = (int)((int64_t)blockIdx.x - c.blk0) * kMergeThreads;
-    const int nb = min(kMergeThreads, n - u0);
-    float2* roots = sm;                                        // M' entries
-    float2* st = sm + ((c.Mp + 1) & ~1);                       // staged bins
-    for (int i = threadIdx.x; i < c.Mp; i += kMergeThreads) {
+    return lo;
+}
+}  // namespace
+
+__global__ __launch_bounds__(kDftThreads) void rsf_sft_dft_k(SftDftArgs a) {
+    extern __shared__ float2 roots[];
+    const SftChunkDev c = a.chunks[sft_chunk_of<&SftChunkDev::dft_blk0>(a.chunks, a.n_chunks, blockIdx.x)];
+    for (int i = threadIdx.x; i < c.Mp; i += kDftThreads) {
         float s, co;
         sincospif(2.0f * (float)i / (float)c.Mp, &s, &co);
         roots[i] = make_float2(co, -s);
     }
-    const int64_t bfirst = c.b0 - n / 2 + u0;
-    const int64_t ks_lo = bfirst / c.Mp;
-    const int64_t ks_hi = (bfirst + nb - 1) / c.Mp;
-    const int64_t kl = max(ks_lo - a.dk, a.k_lo);
-    const int64_t kh = min(ks_hi + a.dk, a.k_lo + a.K - 1);
-    const int W = (int)max((int64_t)0, kh - kl + 1);           // staged bins per SFT
-    const int TA = W > 0 ? max(1, min(c.M, kMergeStage / (int)sizeof(float2) / W)) : c.M;
+    __syncthreads();
+    const int64_t e = ((int64_t)blockIdx.x - c.dft_blk0) * kDftThreads + threadIdx.x;
+    if (e >= (int64_t)a.K * c.Mp) return;
+    const int k = (int)(e / c.Mp);
+    const int r = (int)(e - (int64_t)k * c.Mp);
+    const float2* x = a.xh + (int64_t)c.a0 * a.K + k;
+    float2 acc = make_float2(0.f, 0.f);
+    int idx = 0;  // r alpha mod M'
+    for (int al = 0; al < c.M; ++al) {
+        const float2 v = x[(int64_t)al * a.K];
+        const float2 w = roots[idx];
+        acc.x += v.x * w.x - v.y * w.y;
+        acc.y += v.x * w.y + v.y * w.x;
+        idx += r;
+        if (idx >= c.Mp) idx -= c.Mp;
+    }
+    a.Y[c.dft_off + e] = acc;
+}
 
-    const int u = u0 + (int)threadIdx.x;
-    const bool act = (int)threadIdx.x < nb;
-    const int64_t b = bfirst + threadIdx.x;
+// Merge: one thread per relabelled bin u = q + n/2 of a chunk (all chunks in
+// one launch; the chunk comes from the workgroup index).  For bin
+// b = b0 - n/2 + u: k* = floor(b / M'), r = b - k* M'; the kernel of eq. e75
+// at y = 2 pi (r/M' - d) for k = k* + d has sin y = sin(2 pi r/M') and
+// 1 - cos y = 2 sin^2(pi r/M') for every d, so
+// P_d = (sin y - i (1 - cos y)) / y_d (1 at y = 0; 0 for d != 0 when r = 0).
+// The bin is sum_d P_d Y[k* + d][r], the sum over the chunk's SFTs of
+// X^_{alpha, k*+d} e^{-2 pi i b alpha / M'} (e^{-2 pi i b alpha / M'} =
+// W_{M'}^{r alpha}) taken once per (k, r) in the DFT tables.  Terms outside the
+// stored band are absent.  The bin, windowed, scaled and conjugated, goes to
+// y[y_off + m] with m = q mod n (natural order).
+__global__ __launch_bounds__(kMergeThreads) void rsf_sft_merge_k(SftMergeArgs a) {
+    const SftChunkDev c = a.chunks[sft_chunk_of<&SftChunkDev::blk0>(a.chunks, a.n_chunks, blockIdx.x)];
+    const int n = c.n;
+    const int u = (int)((int64_t)blockIdx.x - c.blk0) * kMergeThreads + (int)threadIdx.x;
+    if (u >= n) return;
+    const int64_t b = c.b0 - n / 2 + u;
     const int64_t ks = b / c.Mp;
     const int r = (int)(b - ks * c.Mp);
     float sy, cy, sh, ch;
@@ -152,55 +170,26 @@ __global__ __launch_bounds__(kMergeThreads) void rsf_sft_merge_k(SftMergeArgs a)
     sincospif((float)r / (float)c.Mp, &sh, &ch);
     const float omc = 2.0f * sh * sh;  // 1 - cos y
     const float fr = (float)r / (float)c.Mp;
-    const int d_lo = (int)max((int64_t)-a.dk, kl - ks);
-    const int d_hi = (int)min((int64_t)a.dk, kh - ks);
-    const int kb = (int)(ks - kl);                             // k* in the staged window
-    float2 P[kSftMaxTerms];
+    const int d_lo = (int)max((int64_t)-a.dk, a.k_lo - ks);
+    const int d_hi = (int)min((int64_t)a.dk, a.k_lo + a.K - 1 - ks);
+    const float2* Yr = a.Y + c.dft_off + r;  // Y[k - k_lo][r]
+    float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
     for (int t = 0; t < kSftMaxTerms; ++t) {
         const int d = t - a.dk;
-        P[t] = make_float2(0.f, 0.f);
         if (d >= d_lo && d <= d_hi) {
+            float2 P;
             if (r == 0) {
-                P[t].x = d == 0 ? 1.f : 0.f;
+                P = make_float2(d == 0 ? 1.f : 0.f, 0.f);
             } else {
                 const float inv = 1.0f / (6.28318530717958648f * (fr - (float)d));
-                P[t] = make_float2(sy * inv, -omc * inv);
+                P = make_float2(sy * inv, -omc * inv);
             }
+            const float2 v = Yr[(ks + d - a.k_lo) * c.Mp];
+            acc.x += v.x * P.x - v.y * P.y;
+            acc.y += v.x * P.y + v.y * P.x;
         }
     }
-    float2 acc = make_float2(0.f, 0.f);
-    int idx = 0;  // r alpha mod M'
-    for (int t0 = 0; t0 < c.M; t0 += TA) {
-        const int ta = min(TA, c.M - t0);
-        __syncthreads();  // previous tile consumed (and the roots written)
-        for (int i = threadIdx.x; i < ta * W; i += kMergeThreads) {
-            const int al = i / W, k = i - al * W;
-            st[i] = a.xh[(int64_t)(c.a0 + t0 + al) * a.K + (kl - a.k_lo) + k];
-        }
-        __syncthreads();
-        if (act) {
-            for (int al = 0; al < ta; ++al) {
-                const float2* row = st + al * W + kb;
-                float2 in = make_float2(0.f, 0.f);
-#pragma unroll
-                for (int t = 0; t < kSftMaxTerms; ++t) {
-                    const int d = t - a.dk;
-                    if (d >= d_lo && d <= d_hi) {
-                        const float2 x = row[d];
-                        in.x += x.x * P[t].x - x.y * P[t].y;
-                        in.y += x.x * P[t].y + x.y * P[t].x;
-                    }
-                }
-                const float2 e = roots[idx];
-                acc.x += in.x * e.x - in.y * e.y;
-                acc.y += in.x * e.y + in.y * e.x;
-                idx += r;
-                if (idx >= c.Mp) idx -= c.Mp;
-            }
-        }
-    }
-    if (!act) return;
     // Tukey window over the ascending band, x = (u + 1/2) / n
     float wgt = 1.0f;
     if (a.taper > 0.f) {
@@ -215,35 +204,54 @@ __global__ __launch_bounds__(kMergeThreads) void rsf_sft_merge_k(SftMergeArgs a)
     a.y[c.y_off + m] = make_float2(acc.x * g, -acc.y * g);
 }
 
-// Rows pass: workgroup (n_b, i) gathers row n_b of chunk ids[i]'s band bins
-// (elements m = LB n_a + n_b), transforms it over n_a and spills it with the
+// The length whose first workgroup (at member BLK0) is the last one not
+// after workgroup w.
+template <int64_t SftLenDev::*BLK0>
+__device__ __forceinline__ int sft_len_of(const SftLenDev* lens, int n_lens, int64_t w) {
+    int lo = 0, hi = n_lens - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (lens[mid].*BLK0 <= w) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Rows pass: workgroup w gathers row n_b of its chunk's band bins (elements
+// m = LB n_a + n_b), transforms it over n_a and spills it with the
 // inter-pass twiddle W_n^{n_b k_a}.
 __global__ __launch_bounds__(kNT) void rsf_sft_rows_k(SftRowsArgs A) {
     extern __shared__ float4 lds[];
-    float2* twl = reinterpret_cast<float2*>(lds + A.LA);
-    const int n_hi = (A.LA + 31) >> kTwLoBits;
-    for (int i = threadIdx.x; i < 32 + n_hi; i += kNT) twl[i] = (i < 32) ? A.tws_lo[i] : A.tws_hi[i - 32];
+    const SftLenDev& L = A.lens[sft_len_of<&SftLenDev::rows_blk0>(A.lens, A.n_lens, blockIdx.x)];
+    const int LA = L.LA, LB = L.LB;
+    const int64_t n = L.n;
+    const int64_t local = (int64_t)blockIdx.x - L.rows_blk0;
+    const int i = (int)(local / LB);
+    const int n_b = (int)(local - (int64_t)i * LB);
+    const FftStages st = L.st1;
+    float2* twl = reinterpret_cast<float2*>(lds + LA);
+    const int n_hi = (LA + 31) >> kTwLoBits;
+    for (int e = threadIdx.x; e < 32 + n_hi; e += kNT) twl[e] = (e < 32) ? L.t1[e] : L.t1_hi[e - 32];
     const TwLds tws{twl, twl + 32};
-    const SftChunkDev& c = A.chunks[A.ids[blockIdx.y]];
-    const int n_b = blockIdx.x;
+    const SftChunkDev& c = A.chunks[A.ids[L.id0 + i]];
     const int tid = threadIdx.x;
     const float2* src = A.y + c.y_off + n_b;
-    for (int n_a = tid; n_a < A.LA; n_a += kNT) {
-        const float2 v = src[(int64_t)A.LB * n_a];
+    for (int n_a = tid; n_a < LA; n_a += kNT) {
+        const float2 v = src[(int64_t)LB * n_a];
         lds[n_a] = make_float4(v.x, v.y, 0.f, 0.f);
     }
-    const int64_t mb = ((int64_t)n_b * tid) % A.n;
-    const int64_t ms = ((int64_t)n_b * kNT) % A.n;
+    const int64_t mb = ((int64_t)n_b * tid) % n;
+    const int64_t ms = ((int64_t)n_b * kNT) % n;
     const int msk = (1 << kTwSplitBits) - 1;
-    const float2 w_base = c_mul(A.tw_hi[mb >> kTwSplitBits], A.tw_lo[mb & msk]);
-    const float2 w_step = c_mul(A.tw_hi[ms >> kTwSplitBits], A.tw_lo[ms & msk]);
-    const int r_last = A.st.n_stages ? A.st.radix[A.st.n_stages - 1] : 1;
-    const int lr = A.LA / r_last;
-    const int64_t ml = ((int64_t)n_b * lr) % A.n;
-    const float2 w_lr = c_mul(A.tw_hi[ml >> kTwSplitBits], A.tw_lo[ml & msk]);
+    const float2 w_base = c_mul(L.tw_hi[mb >> kTwSplitBits], L.tw_lo[mb & msk]);
+    const float2 w_step = c_mul(L.tw_hi[ms >> kTwSplitBits], L.tw_lo[ms & msk]);
+    const int r_last = st.n_stages ? st.radix[st.n_stages - 1] : 1;
+    const int lr = LA / r_last;
+    const int64_t ml = ((int64_t)n_b * lr) % n;
+    const float2 w_lr = c_mul(L.tw_hi[ml >> kTwSplitBits], L.tw_lo[ml & msk]);
     __syncthreads();
-    SpillSink sink{reinterpret_cast<char*>(A.spill + c.spill_off), A.LB, n_b, lr, w_base, w_step, w_lr};
-    lds_fft_into<kNT, kFftEPT, 1, false>(lds, A.st, tws, Interleaved<1>{}, sink, NoMid{});
+    SpillSink sink{reinterpret_cast<char*>(A.spill + c.spill_off), LB, n_b, lr, w_base, w_step, w_lr};
+    lds_fft_into<kNT, kFftEPT, 1, false>(lds, st, tws, Interleaved<1>{}, sink, NoMid{});
 }
 
 // Output j = k_a + LA k_b of the chunk's transform: x[j0 + j] for j < n_keep.
@@ -273,25 +281,30 @@ struct SeriesSink {
     }
 };
 
-// Columns pass: workgroup (g, i) transforms the 8 columns of group pair g of
-// chunk ids[i] (both 4-column spill groups) over n_b and writes the series.
+// Columns pass: workgroup w transforms the 8 columns of group pair g of its
+// chunk (both 4-column spill groups) over n_b and writes the series.
 __global__ __launch_bounds__(kNTB) void rsf_sft_cols_k(SftColsArgs B) {
     extern __shared__ float4 lds[];
-    const int blk = B.LB * kPassBCols;
+    const SftLenDev& L = B.lens[sft_len_of<&SftLenDev::cols_blk0>(B.lens, B.n_lens, blockIdx.x)];
+    const int LA = L.LA, LB = L.LB;
+    const int64_t local = (int64_t)blockIdx.x - L.cols_blk0;
+    const int i = (int)(local / L.n_groups);
+    const int c = (int)(local - (int64_t)i * L.n_groups);
+    const FftStages st = L.st2;
+    const int blk = LB * kPassBCols;
     const int buf_elems = ((blk + 63) / 64) * 64;
     float2* twl = reinterpret_cast<float2*>(lds + buf_elems);
-    const int n_hi = (B.LB + 31) >> kTwLoBits;
+    const int n_hi = (LB + 31) >> kTwLoBits;
     const int tid = threadIdx.x;
-    for (int i = tid; i < 32 + n_hi; i += kNTB) twl[i] = (i < 32) ? B.tw_lo[i] : B.tw_hi[i - 32];
+    for (int e = tid; e < 32 + n_hi; e += kNTB) twl[e] = (e < 32) ? L.t2[e] : L.t2_hi[e - 32];
     const TwLds tw{twl, twl + 32};
-    const SftChunkDev& ch = B.chunks[B.ids[blockIdx.y]];
-    const int c = blockIdx.x;
+    const SftChunkDev& ch = B.chunks[B.ids[L.id0 + i]];
     const float4* src = B.spill + ch.spill_off + (int64_t)c * blk;
     for (int e = tid; e < blk; e += kNTB) lds[e] = src[e];
     __syncthreads();
-    const int r_last = B.st.n_stages ? B.st.radix[B.st.n_stages - 1] : 1;
-    SeriesSink sink{B.x, ch.j0, ch.n_keep, B.n_out, B.LA, B.LB / r_last, c * kPassBCols, B.n_edge, ch.corr};
-    lds_fft_into<kNTB, kPassBEPT, kPassBCols, false>(lds, B.st, tw, Grouped4{B.LB * kGroupCols}, sink, NoMid{});
+    const int r_last = st.n_stages ? st.radix[st.n_stages - 1] : 1;
+    SeriesSink sink{B.x, ch.j0, ch.n_keep, B.n_out, LA, LB / r_last, c * kPassBCols, B.n_edge, ch.corr};
+    lds_fft_into<kNTB, kPassBEPT, kPassBCols, false>(lds, st, tw, Grouped4{LB * kGroupCols}, sink, NoMid{});
 }
 
 hipError_t launch_sft_norm(const SftNormArgs& a, int n_sft, hipStream_t s) {
@@ -300,35 +313,36 @@ hipError_t launch_sft_norm(const SftNormArgs& a, int n_sft, hipStream_t s) {
     return hipGetLastError();
 }
 
+int64_t sft_dft_blocks(int64_t entries) { return (entries + kDftThreads - 1) / kDftThreads; }
+
+size_t sft_dft_lds(int Mp) { return (size_t)Mp * sizeof(float2); }
+
+hipError_t launch_sft_dft(const SftDftArgs& a, int64_t blocks, size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL(rsf_sft_dft_k, dim3((unsigned)blocks), dim3(kDftThreads), lds, s, a);
+    return hipGetLastError();
+}
+
 int64_t sft_merge_blocks(int n) { return (n + kMergeThreads - 1) / kMergeThreads; }
 
-size_t sft_merge_lds(int Mp, int M, int dk) {
-    (void)M;
-    (void)dk;
-    return (size_t)((Mp + 1) & ~1) * sizeof(float2) + kMergeStage;
-}
-
-hipError_t launch_sft_merge(const SftMergeArgs& a, int64_t blocks, size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL(rsf_sft_merge_k, dim3((unsigned)blocks), dim3(kMergeThreads), lds, s, a);
+hipError_t launch_sft_merge(const SftMergeArgs& a, int64_t blocks, hipStream_t s) {
+    hipLaunchKernelGGL(rsf_sft_merge_k, dim3((unsigned)blocks), dim3(kMergeThreads), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_sft_rows(const SftRowsArgs& a, int n_chunks, hipStream_t s) {
-    hipLaunchKernelGGL(rsf_sft_rows_k, dim3((unsigned)a.LB, (unsigned)n_chunks), dim3(kNT), fft_pass_a_lds(a.LA), s,
-                       a);
+hipError_t launch_sft_rows(const SftRowsArgs& a, int64_t blocks, size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL(rsf_sft_rows_k, dim3((unsigned)blocks), dim3(kNT), lds, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_sft_cols(const SftColsArgs& b, int n_chunks, hipStream_t s) {
-    hipLaunchKernelGGL(rsf_sft_cols_k, dim3((unsigned)b.n_groups, (unsigned)n_chunks), dim3(kNTB),
-                       fft_pass_b_lds(b.LB, 0), s, b);
+hipError_t launch_sft_cols(const SftColsArgs& b, int64_t blocks, size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL(rsf_sft_cols_k, dim3((unsigned)blocks), dim3(kNTB), lds, s, b);
     return hipGetLastError();
 }
 
 hipError_t sft_set_lds_limits(size_t bytes) {
     static size_t granted = 0;  // only grows
     if (bytes <= granted) return hipSuccess;
-    const void* fns[] = {(const void*)rsf_sft_merge_k, (const void*)rsf_sft_rows_k, (const void*)rsf_sft_cols_k};
+    const void* fns[] = {(const void*)rsf_sft_dft_k, (const void*)rsf_sft_rows_k, (const void*)rsf_sft_cols_k};
     hipError_t out = hipSuccess;
     for (const void* f : fns) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
