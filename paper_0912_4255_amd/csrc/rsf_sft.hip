@@ -98,6 +98,100 @@ __global__ __launch_bounds__(kNormThreads) void rsf_sft_norm_k(SftNormArgs a) {
     }
 }
 
+// Running median for windows of at most kNormRegMax bins: each thread slides
+// one window over kNormRun consecutive bins, holding it as a sorted array in
+// registers.  The array has kNormRegMax + 1 slots: the w values, (kNormRegMax - w) / 2
+// copies of -inf below and as many of +inf above, and one more +inf, so that
+// the median is always slot kNormRegMax / 2 (a constant index).  The first
+// window is sorted by a bitonic network; a step of the window removes the
+// outgoing value (every slot from its first copy on takes its upper
+// neighbour) and inserts the incoming one (slot i becomes
+// max(s[i-1], min(x, s[i])), i descending).  The powers of the workgroup's
+// bins are staged in LDS, and the gains go back through LDS so that the
+// scaled bins are written in order.
+namespace {
+constexpr int kNormRegMax = 127;              // odd; slots kNormRegMax + 1 = 128 = 2^7
+constexpr int kNormRun = 15;                  // bins per thread (odd: conflict-free LDS strides)
+constexpr int kNormTile = kNormThreads * kNormRun;
+
+__device__ __forceinline__ void cmp_swap(float& lo, float& hi) {
+    const float a = fminf(lo, hi), b = fmaxf(lo, hi);
+    lo = a;
+    hi = b;
+}
+
+// ascending bitonic sort of N = 2^LOG2N values in registers
+template <int LOG2N>
+__device__ __forceinline__ void sort_regs(float (&v)[1 << LOG2N]) {
+    constexpr int N = 1 << LOG2N;
+#pragma unroll
+    for (int ls = 1; ls <= LOG2N; ++ls)
+#pragma unroll
+        for (int lt = ls - 1; lt >= 0; --lt)
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const int l = i ^ (1 << lt);
+                if (l > i) {
+                    if ((i & (1 << ls)) == 0) cmp_swap(v[i], v[l]);
+                    else cmp_swap(v[l], v[i]);
+                }
+            }
+}
+}  // namespace
+
+__global__ __launch_bounds__(kNormThreads) __attribute__((amdgpu_waves_per_eu(2))) void rsf_sft_norm_reg_k(SftNormArgs a) {
+    constexpr int S = kNormRegMax + 1;
+    __shared__ float pw[kNormTile + kNormRegMax - 1];
+    __shared__ float gain[kNormTile];
+    const int alpha = blockIdx.y;
+    const int w = a.w, h = a.w / 2;
+    const int k0 = blockIdx.x * kNormTile;
+    const int kend = min(k0 + kNormTile, a.K);
+    auto lo_of = [&](int k) { return min(max(k - h, 0), a.K - w); };  // first bin of k's window
+    const int base = lo_of(k0);
+    const int top = lo_of(kend - 1) + w;
+    const float2* row = a.in + (int64_t)alpha * a.K;
+    for (int i = threadIdx.x; i < top - base; i += kNormThreads) {
+        const float2 x = row[base + i];
+        pw[i] = x.x * x.x + x.y * x.y;
+    }
+    __syncthreads();
+    const int kt = k0 + (int)threadIdx.x * kNormRun;
+    if (kt < kend) {
+        const int pad = (kNormRegMax - w) / 2;
+        int lo = lo_of(kt);
+        float v[S];
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+            const int j = i - pad;
+            v[i] = (j < 0) ? -__builtin_inff() : ((j < w) ? pw[lo - base + j] : __builtin_inff());
+        }
+        sort_regs<7>(v);
+#pragma unroll 1
+        for (int k = kt; k < min(kt + kNormRun, kend); ++k) {
+            const int lk = lo_of(k);
+            if (lk != lo) {  // lk = lo + 1
+                const float y = pw[lo - base];
+                const float x = pw[lo + w - base];
+#pragma unroll
+                for (int i = 0; i + 1 < S; ++i) v[i] = (v[i] < y) ? v[i] : v[i + 1];
+#pragma unroll
+                for (int i = S - 1; i > 0; --i) v[i] = fmaxf(v[i - 1], fminf(x, v[i]));
+                v[0] = fminf(x, v[0]);
+                lo = lk;
+            }
+            const float med = v[kNormRegMax / 2];
+            gain[k - k0] = med > 0.f ? sqrtf(0.69314718055994531f / med) : 0.f;
+        }
+    }
+    __syncthreads();
+    for (int k = k0 + (int)threadIdx.x; k < kend; k += kNormThreads) {
+        const float2 x = row[k];
+        const float g = gain[k - k0];
+        a.out[(int64_t)alpha * a.K + k] = make_float2(x.x * g, x.y * g);
+    }
+}
+
 // DFT over each chunk's SFTs: one thread per (k, r) of a chunk, consecutive
 // r on consecutive threads (they share X^_{alpha, k}); workgroups of one
 // chunk are contiguous from dft_blk0.  The phases W_{M'}^{r alpha} come from
@@ -308,8 +402,13 @@ __global__ __launch_bounds__(kNTB) void rsf_sft_cols_k(SftColsArgs B) {
 }
 
 hipError_t launch_sft_norm(const SftNormArgs& a, int n_sft, hipStream_t s) {
-    const unsigned gx = (unsigned)((a.K + kNormThreads - 1) / kNormThreads);
-    hipLaunchKernelGGL(rsf_sft_norm_k, dim3(gx, (unsigned)n_sft), dim3(kNormThreads), 0, s, a);
+    if (a.w <= kNormRegMax) {
+        const unsigned gx = (unsigned)((a.K + kNormTile - 1) / kNormTile);
+        hipLaunchKernelGGL(rsf_sft_norm_reg_k, dim3(gx, (unsigned)n_sft), dim3(kNormThreads), 0, s, a);
+    } else {
+        const unsigned gx = (unsigned)((a.K + kNormThreads - 1) / kNormThreads);
+        hipLaunchKernelGGL(rsf_sft_norm_k, dim3(gx, (unsigned)n_sft), dim3(kNormThreads), 0, s, a);
+    }
     return hipGetLastError();
 }
 

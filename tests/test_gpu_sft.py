@@ -91,6 +91,18 @@ def test_single_sft_chunks_and_few_dirichlet_terms(gpu_lib):
     assert np.max(np.abs(got - ref)) <= 1e-4 * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("median_window", [1, 127, 129, 131])
+def test_running_median_window_sizes(gpu_lib, median_window):
+    """Windows up to 127 bins take the register running median, longer ones
+    the sorted-tile one; 1 is the degenerate window (each bin its own
+    median)."""
+    ss, X = _case([0, 1, 2, 4, 5], 6, seed=5, median_window=median_window)
+    ref, gref = _oracle(ss, X)
+    got, gaps = _gpu(gpu_lib, ss, X)
+    assert np.array_equal(gaps, gref)
+    assert np.max(np.abs(got - ref)) <= 1e-4 * np.max(np.abs(ref)), median_window
+
+
 def test_ten_day_sft_set_sampled_against_oracle(gpu_lib):
     """The full T = 10 d input: 432 SFTs of 1800 s (48 missing), 7318 bins
     each, output 3,456,000 samples at 4 Hz.  The first chunk is recomputed by
