@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime_api.h>
 
+#include "rsf_front_params.h"
 #include "rsf_params.h"
 
 namespace rsf {

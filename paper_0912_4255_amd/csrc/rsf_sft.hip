@@ -28,8 +28,10 @@ constexpr int kNT = kFftThreads;
 constexpr int kNTB = kPassBThreads;
 }  // namespace
 
-// One workgroup per 256 bins of one SFT.  The powers |X|^2 of the bins that
-// any of its windows touch (the tile and its halo, windows clamped inside the
+// Running median for windows longer than kNormRegMax bins (the register
+// version, rsf_sft_norm_reg_k, takes the shorter ones).  One workgroup per
+// 256 bins of one SFT.  The powers |X|^2 of the bins that any of its windows
+// touch (the tile and its halo, windows clamped inside the
 // band) are sorted once in LDS with their positions; the median of bin k's
 // window is then the (w/2 + 1)-th smallest sorted value whose position lies in
 // the window, found by a pass over the sorted list that stops there.  The
