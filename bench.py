@@ -57,6 +57,7 @@ def parse():
 
 KERNEL_SOURCES = ("rsf_fft.hip", "rsf_spill.h", "rsf_device.h", "rsf_params.h", "rsf_resample.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_fft_T10d.md")
+PEAK_FP32_MFMA_TFLOPS = 157.3  # MI355X dense FP32 matrix
 
 
 def kernel_source_hash():
@@ -265,11 +266,17 @@ def hetdec_leg(rsf, torch, dev, reps=5):
     k_ms = prof["rsf_hetdec_k"][1] / reps
     alg = n_raw * 4 + n_out * 8
     taps = 2 * K * D + 1
+    # the filter as a real product on the FP32 matrix cores: 4 flops (re and im
+    # multiply-add) per tap and output
+    tflops = 4.0 * taps * n_out / (k_ms * 1e-3) / 1e12
     return {"workload": f"T=10d real series at 256 Hz ({n_raw} samples) -> {n_out} samples at 4 Hz, "
                         f"{taps}-tap Kaiser low-pass, f_h = {fh:g} Hz",
             "ms_per_segment": round(t * 1e3, 3), "kernel_ms": round(k_ms, 3),
             "algorithmic_bytes": alg, "algorithmic_GBps": round(alg / (k_ms * 1e-3) / 1e9, 1),
-            "GMAC_per_s": round(n_out * taps / (k_ms * 1e-3) / 1e9, 1)}
+            "GMAC_per_s": round(n_out * taps / (k_ms * 1e-3) / 1e9, 1),
+            "roofline": {"bound": "mfma", "achieved": round(tflops, 2), "peak": PEAK_FP32_MFMA_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(tflops / PEAK_FP32_MFMA_TFLOPS, 4),
+                         "flops": 4 * taps * n_out}}
 
 
 def main():

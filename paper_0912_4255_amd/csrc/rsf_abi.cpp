@@ -1531,6 +1531,7 @@ struct rsf_hetdec_plan {
     rsf_hetdec_desc d;
     Profiler* prof;
     int L, c;
+    int n_cu;   // compute units (persistent grid of the matrix-core form)
     float2* g;  // device taps
 };
 
@@ -1575,6 +1576,10 @@ int rsf_hetdec_plan_create(rsf_hetdec_plan** out, const rsf_hetdec_desc* d) {
     p->L = (int)L;
     p->c = (int)c;
     p->g = nullptr;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || p->n_cu <= 0)
+        p->n_cu = 256;
     if (hipMalloc((void**)&p->g, g.size() * sizeof(float2)) != hipSuccess ||
         hipMemcpy(p->g, g.data(), g.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess) {
         (void)hipFree(p->g);
@@ -1614,7 +1619,7 @@ int rsf_hetdec(const rsf_hetdec_plan* p, const float* x, float* x_h, void* strea
     a.cyc_per_out = p->d.f_het * ((double)p->d.D * p->d.dt_raw);
     a.out = reinterpret_cast<float2*>(x_h);
     a.n_out = p->d.n_out;
-    RSF_HIP(timed_pr(p->prof, K_HETDEC, s, [&] { return launch_hetdec(a, s); }), "hetdec launch");
+    RSF_HIP(timed_pr(p->prof, K_HETDEC, s, [&] { return launch_hetdec(a, p->n_cu, s); }), "hetdec launch");
     return RSF_OK;
 }
 

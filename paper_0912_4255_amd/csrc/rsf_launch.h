@@ -26,7 +26,7 @@ int topk_merge_per_block();
 hipError_t launch_fill_u32(unsigned int* p, int n, unsigned int v, hipStream_t s);
 hipError_t launch_semico(const SemicoArgs& a, hipStream_t s);
 size_t hetdec_lds(int L, int D);
-hipError_t launch_hetdec(const HetdecArgs& a, hipStream_t s);
+hipError_t launch_hetdec(const HetdecArgs& a, int n_cu, hipStream_t s);  // n_cu: persistent grid of the D = 64 form
 hipError_t hetdec_set_lds_limit(size_t bytes);
 
 hipError_t launch_sft_norm(const SftNormArgs& a, int n_sft, hipStream_t s);

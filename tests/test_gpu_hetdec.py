@@ -2,7 +2,8 @@
 
 Bar: |x_gpu - x_oracle| <= 1e-4 max|x_oracle| (FP32 sums over L taps of an
 FP64-built filter; heterodyne phases in FP64).  Cases: no filter (D = 1,
-K = 0), the 995 Hz worked example (D = 100), a ragged last tile, and the
+K = 0), the 995 Hz worked example (D = 100), a ragged last tile, the
+matrix-core form (D = 64, K = 8, 12, 16) over several workgroups, and the
 full T = 10 d series at 256 Hz (221,184,000 raw samples, D = 64, 2049 taps)
 sampled at 256 outputs."""
 import numpy as np
@@ -25,8 +26,9 @@ def _run(gpu_lib, x, dt, fh, D, K, beta, n_out):
     (1.0 / 64.0, 10.3, 1, 0, 5000, 5000),          # heterodyne only
     (1.0 / 1000.0, 995.0, 100, 12, 40000, 400),     # the worked example's rates
     (1.0 / 256.0, 100.0, 32, 12, 256 * 37 + 11, 300),  # ragged: 300 outputs, the last tile partial
-    (1.0 / 256.0, 101.0, 64, 8, 256 * 80 + 5, 320),     # polyphase form (D = 64), ragged chunks
-    (1.0 / 256.0, 101.0, 64, 16, 256 * 80, 300),        # polyphase, 33 taps per phase
+    (1.0 / 256.0, 101.0, 64, 8, 256 * 80 + 5, 320),     # matrix-core form (D = 64): 2 workgroups, ragged
+    (1.0 / 256.0, 101.0, 64, 12, 64 * 700 + 3, 650),    # matrix-core form, K = 12: 3 workgroups
+    (1.0 / 256.0, 101.0, 64, 16, 256 * 80, 300),        # matrix-core form, 2049 taps
 ])
 def test_matches_oracle(gpu_lib, dt, fh, D, K, n_raw, n_out):
     rng = np.random.default_rng(D + K)
