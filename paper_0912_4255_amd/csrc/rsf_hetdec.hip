@@ -93,12 +93,12 @@ __global__ __launch_bounds__(kHdThreads) void rsf_hetdec_k(HetdecArgs a) {
 // J = 256 - 2K outputs and a halo of K rows on each side.  Persistent
 // workgroups (one per CU) walk the blocks with two row buffers: the next
 // block's rows arrive by DMA (global -> LDS) while the current block's Z is
-// computed in place of its rows (each wave owns whole 16-row tiles), then one
+// computed in place of its rows (each wave owns one 16-row tile), then one
 // thread per output adds the 2K diagonal terms and applies the output phase.
 namespace {
 constexpr int kMmRows = 256;     // raw rows per block, halo included
-constexpr int kMmStride = 68;    // LDS row stride in floats (conflict-free A reads and Z writes)
-constexpr int kMmThreads = 512;
+constexpr int kMmStride = 66;    // LDS row stride in floats: A reads, Z writes and diagonal reads at most 2-way
+constexpr int kMmThreads = 1024;  // 4 waves per SIMD
 constexpr int kMmBuf = kMmRows * kMmStride;
 typedef float mm_v4f __attribute__((ext_vector_type(4)));
 }  // namespace
