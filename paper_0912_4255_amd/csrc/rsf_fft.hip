@@ -203,8 +203,9 @@ __device__ __forceinline__ void passb_dma(const PassBArgs& B, int unit, float4* 
     for (int e0 = wave * 64; e0 < blk; e0 += kNTB) {
         const int e = e0 + lane;
         if (e < blk) {
+            // the spill is read once: non-temporal (cache policy nt)
             __builtin_amdgcn_global_load_lds((const void*)(base + e), (__attribute__((address_space(3))) void*)(dst + e0),
-                                             16, 0, 0);
+                                             16, 0, 2);
         }
     }
 }

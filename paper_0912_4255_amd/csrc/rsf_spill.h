@@ -11,11 +11,15 @@ namespace rsf {
 // contiguous run and every cache line is fetched once.
 constexpr int kGroupCols = kPassBCols / 2;
 
+typedef float spill_v4 __attribute__((ext_vector_type(4)));
+
 // Writer of the first pass's last stage: output k_a = j + r L1/R of the row
 // transform, times the inter-pass twiddle W_N^{n_b k_a}, goes straight from
 // registers to the spill.  The twiddle of butterfly j = tid + q NT is
 // W^{n_b tid} (W^{n_b NT})^q, advanced once per call (calls come in q order),
-// and steps by W^{n_b L1/R} along r.
+// and steps by W^{n_b L1/R} along r.  The spill is written once and read once
+// by the second pass, long after: the stores are non-temporal, so they do not
+// displace cached lines.
 struct SpillSink {
     char* out;  // this template's spill (< 4 GiB, so byte offsets fit 32 bits)
     int LB, n_b, LR;
@@ -32,7 +36,8 @@ struct SpillSink {
         for (int r = 0; r < R; ++r) {
             const uint32_t k = (uint32_t)(jv + r * LR);
             const uint32_t off = (((k >> 2) * (uint32_t)LB + (uint32_t)n_b) * kGroupCols + (k & 3u)) * 16u;
-            *reinterpret_cast<float4*>(out + off) = cp_rot(v[r], w);
+            const cp u = cp_rot(v[r], w);
+            __builtin_nontemporal_store(spill_v4{u.x, u.y, u.z, u.w}, reinterpret_cast<spill_v4*>(out + off));
             if (r + 1 < R) w = c_mul(w, w_lr);
         }
         wq = c_mul(wq, w_step);
