@@ -42,6 +42,7 @@ int hip_fail(hipError_t e, const char* what) {
     } while (0)
 
 constexpr size_t kAlign = 256;
+constexpr size_t kLastLevelCacheBytes = (size_t)256 << 20;  // MI355X Infinity Cache
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 bool is_7smooth(int64_t n) {
@@ -775,6 +776,8 @@ int run_fstat(const rsf_plan* p, const rsf_segment* seg, const double* sky, int6
             A.tw_hi = p->tw_hi;
             A.spill = spill;
             A.spill_tmpl_stride = spill_stride;
+            // a spill larger than the last-level cache goes out (and comes back) non-temporally
+            A.nt_spill = (size_t)q.ns * q.nf * (size_t)spill_stride * sizeof(float4) > kLastLevelCacheBytes ? 1 : 0;
             RSF_HIP(timed(p, K_PASS_A, s, [&] { return launch_fft_pass_a(A, s); }), "pass A launch");
 
             PassBArgs B{};
@@ -787,6 +790,7 @@ int run_fstat(const rsf_plan* p, const rsf_segment* seg, const double* sky, int6
             B.tw_hi = p->twB_hi;
             B.spill = spill;
             B.spill_tmpl_stride = spill_stride;
+            B.nt_spill = A.nt_spill;
             B.coef = (const float*)(w + L.coef) + 4 * q.s;
             B.n_sky_l = q.ns;
             B.s_lo = p->s_lo;

@@ -96,7 +96,8 @@ __device__ __forceinline__ void accumulate_integrand(cp& y, const Sample<ORDER>&
 // Inputs of one row held per thread: n_a = tid + q * kNT, q < kInPer (P <= LA/2 <= 5120).
 constexpr int kInPer = (kFftMaxLen / 2 + kNT - 1) / kNT;
 
-template <int ORDER>
+// NT: the launch's spill is larger than the last-level cache (non-temporal stores)
+template <int ORDER, bool NT>
 __global__ __launch_bounds__(kNT) void rsf_fft_pass_a_k(PassAArgs A) {
     extern __shared__ float4 lds[];
     // stage twiddles in LDS after the row: no global load inside the stages,
@@ -176,8 +177,8 @@ __global__ __launch_bounds__(kNT) void rsf_fft_pass_a_k(PassAArgs A) {
         }
         for (int n_a = tid + kInPer * kNT; n_a < zlim; n_a += kNT) lds[n_a] = make_float4(0.f, 0.f, 0.f, 0.f);
         __syncthreads();
-        SpillSink sink{reinterpret_cast<char*>(A.spill + (int64_t)t * A.spill_tmpl_stride), A.LB, n_b, lr, w_base,
-                       w_step, w_lr};
+        SpillSink<NT> sink{reinterpret_cast<char*>(A.spill + (int64_t)t * A.spill_tmpl_stride), A.LB, n_b, lr,
+                           w_base, w_step, w_lr};
         lds_fft_into<kNT, kEPT, 1, false>(lds, A.st, tws, Interleaved<1>{}, sink, NoMid{}, prune);
         __syncthreads();
     }
@@ -194,6 +195,7 @@ __global__ __launch_bounds__(kNT) void rsf_fft_pass_a_k(PassAArgs A) {
 // is in flight.  Eight consecutive lanes hold the eight columns of one row,
 // so each store covers 32 contiguous bytes of the output.
 
+template <bool NT>
 __device__ __forceinline__ void passb_dma(const PassBArgs& B, int unit, float4* dst) {
     const int t = unit / B.n_groups;
     const int c = unit - t * B.n_groups;
@@ -203,9 +205,10 @@ __device__ __forceinline__ void passb_dma(const PassBArgs& B, int unit, float4* 
     for (int e0 = wave * 64; e0 < blk; e0 += kNTB) {
         const int e = e0 + lane;
         if (e < blk) {
-            // the spill is read once: non-temporal (cache policy nt)
+            // the spill is read once: non-temporal (cache policy nt) when it
+            // was written so, else from the cache
             __builtin_amdgcn_global_load_lds((const void*)(base + e), (__attribute__((address_space(3))) void*)(dst + e0),
-                                             16, 0, 2);
+                                             16, 0, NT ? 2 : 0);
         }
     }
 }
@@ -236,16 +239,18 @@ struct TwoFSink {
     }
 };
 
+template <bool NT>
 struct PassBMid {
     const PassBArgs* B;
     int next;
     float4* buf;
     __device__ __forceinline__ void operator()() const {
         __syncthreads();  // every thread holds its last-stage inputs: the buffer is free
-        if (next >= 0) passb_dma(*B, next, buf);
+        if (next >= 0) passb_dma<NT>(*B, next, buf);
     }
 };
 
+template <bool NT>
 __global__ __launch_bounds__(kNTB) void rsf_fft_pass_b_k(PassBArgs B) {
     extern __shared__ float4 lds[];
     const int blk = B.LB * kPassBCols;
@@ -262,7 +267,7 @@ __global__ __launch_bounds__(kNTB) void rsf_fft_pass_b_k(PassBArgs B) {
     const int r_last = B.st.n_stages ? B.st.radix[B.st.n_stages - 1] : 1;
 
     int unit = blockIdx.x;
-    if (unit < n_units) passb_dma(B, unit, lds);
+    if (unit < n_units) passb_dma<NT>(B, unit, lds);
     while (unit < n_units) {
         // this thread's DMA loads (and last block's stores) are complete;
         // after the barrier, everyone's
@@ -276,7 +281,7 @@ __global__ __launch_bounds__(kNTB) void rsf_fft_pass_b_k(PassBArgs B) {
         const int64_t out_row = B.map_rows ? (int64_t)t : (B.sky0 + s_l) * B.n_fdot + B.f0 + f;
         TwoFSink sink{B.twoF + out_row * B.n_out, B.LA, B.LB / r_last, c * kPassBCols, (int)B.n_fft, (int)B.s_lo,
                       (int)B.n_out, cfl[4 * s_l], cfl[4 * s_l + 1], cfl[4 * s_l + 2]};
-        const PassBMid mid{&B, nunit < n_units ? nunit : -1, lds};
+        const PassBMid<NT> mid{&B, nunit < n_units ? nunit : -1, lds};
         lds_fft_into<kNTB, kPassBEPT, kPassBCols, true>(lds, B.st, tw, lay, sink, mid);
         unit = nunit;
     }
@@ -289,12 +294,19 @@ size_t fft_pass_a_lds(int LA) { return (size_t)LA * sizeof(float4) + (32 + (LA +
 hipError_t launch_fft_pass_a(const PassAArgs& a, hipStream_t s) {
     const size_t lds = fft_pass_a_lds(a.LA);
     const unsigned gy = (unsigned)(a.n_sky_l * ((a.nf_l + a.fb - 1) / a.fb));
+    const dim3 grid((unsigned)a.LB, gy);
+#define RSF_PASS_A(ORD)                                                              \
+    if (a.nt_spill)                                                                  \
+        hipLaunchKernelGGL((rsf_fft_pass_a_k<ORD, true>), grid, dim3(kNT), lds, s, a); \
+    else                                                                             \
+        hipLaunchKernelGGL((rsf_fft_pass_a_k<ORD, false>), grid, dim3(kNT), lds, s, a)
     switch (a.spin_order) {
-        case 1: hipLaunchKernelGGL(rsf_fft_pass_a_k<1>, dim3((unsigned)a.LB, gy), dim3(kNT), lds, s, a); break;
-        case 2: hipLaunchKernelGGL(rsf_fft_pass_a_k<2>, dim3((unsigned)a.LB, gy), dim3(kNT), lds, s, a); break;
-        case 3: hipLaunchKernelGGL(rsf_fft_pass_a_k<3>, dim3((unsigned)a.LB, gy), dim3(kNT), lds, s, a); break;
+        case 1: RSF_PASS_A(1); break;
+        case 2: RSF_PASS_A(2); break;
+        case 3: RSF_PASS_A(3); break;
         default: return hipErrorInvalidValue;
     }
+#undef RSF_PASS_A
     return hipGetLastError();
 }
 
@@ -307,7 +319,10 @@ hipError_t launch_fft_pass_b(const PassBArgs& b, int n_cu, hipStream_t s) {
     const size_t lds = fft_pass_b_lds(b.LB, b.n_sky_l);
     const int n_items = b.n_tmpl * b.n_groups;
     const unsigned grid = (unsigned)std::max(1, std::min(n_items, n_cu));
-    hipLaunchKernelGGL(rsf_fft_pass_b_k, dim3(grid), dim3(kNTB), lds, s, b);
+    if (b.nt_spill)
+        hipLaunchKernelGGL(rsf_fft_pass_b_k<true>, dim3(grid), dim3(kNTB), lds, s, b);
+    else
+        hipLaunchKernelGGL(rsf_fft_pass_b_k<false>, dim3(grid), dim3(kNTB), lds, s, b);
     return hipGetLastError();
 }
 
@@ -316,8 +331,10 @@ hipError_t fft_set_lds_limits(size_t bytes) {
     // undo a larger one
     static size_t granted = 0;
     if (bytes <= granted) return hipSuccess;
-    const void* fns[] = {(const void*)rsf_fft_pass_a_k<1>, (const void*)rsf_fft_pass_a_k<2>,
-                         (const void*)rsf_fft_pass_a_k<3>, (const void*)rsf_fft_pass_b_k};
+    const void* fns[] = {(const void*)rsf_fft_pass_a_k<1, false>, (const void*)rsf_fft_pass_a_k<2, false>,
+                         (const void*)rsf_fft_pass_a_k<3, false>, (const void*)rsf_fft_pass_a_k<1, true>,
+                         (const void*)rsf_fft_pass_a_k<2, true>,  (const void*)rsf_fft_pass_a_k<3, true>,
+                         (const void*)rsf_fft_pass_b_k<false>,    (const void*)rsf_fft_pass_b_k<true>};
     hipError_t out = hipSuccess;
     for (const void* f : fns) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);

@@ -138,6 +138,7 @@ struct PassAArgs {
     const float2* tw_hi;
     float4* spill;            // [n_sky_l * nf_l][2 * ceil(LA/8)][LB][4]: 4-column groups
     int64_t spill_tmpl_stride;
+    int nt_spill;             // spill larger than the last-level cache: non-temporal stores
 };
 
 // Second FFT pass and F-statistic for the launch's n_sky_l * nf_l templates;
@@ -152,6 +153,7 @@ struct PassBArgs {
     const float2* tw_hi;      // W_LB^{32 m} for m < ceil(LB / 32)
     const float4* spill;
     int64_t spill_tmpl_stride;
+    int nt_spill;             // the spill was written non-temporally: read it the same way
     const float* coef;        // per sky of the launch {2B/D, 2A/D, -4C/D, flag}
     int n_sky_l;
     int64_t s_lo, n_out;

@@ -13,8 +13,8 @@
 // LDS Stockham stages of the F-statistic passes: a rows pass that spills like
 // the first F-statistic pass, and a columns pass that conjugates and writes
 // the series.  The second member of each complex pair is unused.  Every
-// launch covers all chunks (merge) or all chunks of one transform length
-// (rows, columns), read from a device table of chunks.
+// launch covers all chunks, read from device tables of the chunks and of the
+// transform lengths.
 #include "rsf_device.h"
 #include "rsf_launch.h"
 #include "rsf_spill.h"
@@ -141,7 +141,8 @@ __device__ __forceinline__ void sort_regs(float (&v)[1 << LOG2N]) {
 }
 }  // namespace
 
-__global__ __launch_bounds__(kNormThreads) __attribute__((amdgpu_waves_per_eu(2))) void rsf_sft_norm_reg_k(SftNormArgs a) {
+__global__ __launch_bounds__(kNormThreads) __attribute__((amdgpu_waves_per_eu(2)))
+void rsf_sft_norm_reg_k(SftNormArgs a) {
     constexpr int S = kNormRegMax + 1;
     __shared__ float pw[kNormTile + kNormRegMax - 1];
     __shared__ float gain[kNormTile];
@@ -346,7 +347,7 @@ __global__ __launch_bounds__(kNT) void rsf_sft_rows_k(SftRowsArgs A) {
     const int64_t ml = ((int64_t)n_b * lr) % n;
     const float2 w_lr = c_mul(L.tw_hi[ml >> kTwSplitBits], L.tw_lo[ml & msk]);
     __syncthreads();
-    SpillSink sink{reinterpret_cast<char*>(A.spill + c.spill_off), LB, n_b, lr, w_base, w_step, w_lr};
+    SpillSink<false> sink{reinterpret_cast<char*>(A.spill + c.spill_off), LB, n_b, lr, w_base, w_step, w_lr};
     lds_fft_into<kNT, kFftEPT, 1, false>(lds, st, tws, Interleaved<1>{}, sink, NoMid{});
 }
 

@@ -18,8 +18,11 @@ typedef float spill_v4 __attribute__((ext_vector_type(4)));
 // registers to the spill.  The twiddle of butterfly j = tid + q NT is
 // W^{n_b tid} (W^{n_b NT})^q, advanced once per call (calls come in q order),
 // and steps by W^{n_b L1/R} along r.  The spill is written once and read once
-// by the second pass, long after: the stores are non-temporal, so they do not
-// displace cached lines.
+// by the second pass.  When a launch's spill is larger than the last-level
+// cache it cannot stay there until then, and the stores are non-temporal
+// (NT), so that they do not displace cached lines; a smaller spill is stored
+// normally and read back from the cache.
+template <bool NT>
 struct SpillSink {
     char* out;  // this template's spill (< 4 GiB, so byte offsets fit 32 bits)
     int LB, n_b, LR;
@@ -37,7 +40,10 @@ struct SpillSink {
             const uint32_t k = (uint32_t)(jv + r * LR);
             const uint32_t off = (((k >> 2) * (uint32_t)LB + (uint32_t)n_b) * kGroupCols + (k & 3u)) * 16u;
             const cp u = cp_rot(v[r], w);
-            __builtin_nontemporal_store(spill_v4{u.x, u.y, u.z, u.w}, reinterpret_cast<spill_v4*>(out + off));
+            if constexpr (NT)
+                __builtin_nontemporal_store(spill_v4{u.x, u.y, u.z, u.w}, reinterpret_cast<spill_v4*>(out + off));
+            else
+                *reinterpret_cast<float4*>(out + off) = u;
             if (r + 1 < R) w = c_mul(w, w_lr);
         }
         wq = c_mul(wq, w_step);
