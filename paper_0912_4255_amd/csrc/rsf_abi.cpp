@@ -1171,6 +1171,7 @@ struct rsf_sft_plan {
     int* ids_dev;                         // chunk ids, grouped by length
     std::vector<int64_t> ids_off;         // first id of each group in ids_dev
     SftLenDev* lens_dev;                  // device table of the transform lengths
+    int rows_R, cols_C;                   // rows per rows workgroup, columns per columns workgroup
     int64_t rows_blocks, cols_blocks;     // workgroups of the single rows / columns launches
     size_t rows_lds, cols_lds;
 };
@@ -1262,6 +1263,8 @@ int rsf_sft_plan_create(rsf_sft_plan** out, const rsf_sft_desc* d, const double*
     p->chunks_dev = nullptr;
     p->ids_dev = nullptr;
     p->lens_dev = nullptr;
+    p->rows_R = 1;
+    p->cols_C = kPassBCols;
     p->rows_blocks = p->cols_blocks = 0;
     p->rows_lds = p->cols_lds = 0;
     int dev = 0, lds_dev = 0;
@@ -1332,6 +1335,39 @@ int rsf_sft_plan_create(rsf_sft_plan** out, const rsf_sft_desc* d, const double*
         p->chunks.push_back(c);
         a0 = a;
     }
+    // rows and columns per workgroup: the most that every transform length of
+    // the plan fits (stage capacity and LDS), so that the many short rows and
+    // columns of these transforms come several to a workgroup
+    {
+        auto rows_fit = [&](int R) {
+            for (const auto& x : p->xf) {
+                FftStages st;
+                if (!radix_plan(x.L1, R, kFftThreads, kFftEPT, &st) || sft_rows_lds(x.L1, R) > (size_t)lds_cap)
+                    return false;
+            }
+            return true;
+        };
+        auto cols_fit = [&](int C) {
+            for (const auto& x : p->xf) {
+                FftStages st;
+                if (!radix_plan(x.L2, C, kPassBThreads, kPassBEPT, &st) || sft_cols_lds(x.L2, C) > (size_t)lds_cap)
+                    return false;
+            }
+            return true;
+        };
+        int R = 8, C = 32;
+        while (R > 1 && !rows_fit(R)) R /= 2;
+        while (C > kPassBCols && !cols_fit(C)) C /= 2;
+        p->rows_R = R;
+        p->cols_C = C;
+        p->lds_max = 0;
+        for (auto& x : p->xf) {
+            radix_plan(x.L1, R, kFftThreads, kFftEPT, &x.st1);
+            radix_plan(x.L2, C, kPassBThreads, kPassBEPT, &x.st2);
+            x.n_groups = (x.L1 + C - 1) / C;
+            p->lds_max = std::max({p->lds_max, sft_rows_lds(x.L1, R), sft_cols_lds(x.L2, C)});
+        }
+    }
     // gaps: output samples outside every chunk
     std::vector<std::pair<int64_t, int64_t>> cov;
     for (const auto& c : p->chunks) {
@@ -1372,7 +1408,7 @@ int rsf_sft_plan_create(rsf_sft_plan** out, const rsf_sft_desc* d, const double*
         t.scale = (float)(1.0 / std::sqrt((double)x.n * (double)c.M));
         t.corr = c.corr;
         p->y_total += x.n;
-        p->spill_total += (size_t)x.n_groups * kPassBCols * x.L2;
+        p->spill_total += (size_t)x.n_groups * p->cols_C * x.L2;
         p->merge_blocks += sft_merge_blocks((int)x.n);
         p->dft_total += (int64_t)d->n_bins * c.Mp;
         p->dft_blocks += sft_dft_blocks((int64_t)d->n_bins * c.Mp);
@@ -1404,10 +1440,10 @@ int rsf_sft_plan_create(rsf_sft_plan** out, const rsf_sft_desc* d, const double*
         l.t2_hi = x.t2_hi;
         l.tw_lo = x.tw_lo;
         l.tw_hi = x.tw_hi;
-        p->rows_blocks += (int64_t)x.L2 * l.nc;
+        p->rows_blocks += (int64_t)((x.L2 + p->rows_R - 1) / p->rows_R) * l.nc;
         p->cols_blocks += (int64_t)x.n_groups * l.nc;
-        p->rows_lds = std::max(p->rows_lds, fft_pass_a_lds(x.L1));
-        p->cols_lds = std::max(p->cols_lds, fft_pass_b_lds(x.L2, 0));
+        p->rows_lds = std::max(p->rows_lds, sft_rows_lds(x.L1, p->rows_R));
+        p->cols_lds = std::max(p->cols_lds, sft_cols_lds(x.L2, p->cols_C));
     }
     if (hipMalloc((void**)&p->chunks_dev, tab.size() * sizeof(SftChunkDev)) != hipSuccess ||
         hipMemcpy(p->chunks_dev, tab.data(), tab.size() * sizeof(SftChunkDev), hipMemcpyHostToDevice) != hipSuccess ||
@@ -1499,7 +1535,7 @@ int rsf_sft_heterodyne(const rsf_sft_plan* p, const float* sft, float* x_h, void
     r.ids = p->ids_dev;
     r.y = y;
     r.spill = spill;
-    RSF_HIP(timed_pr(p->prof, K_SFT_ROWS, s, [&] { return launch_sft_rows(r, p->rows_blocks, p->rows_lds, s); }),
+    RSF_HIP(timed_pr(p->prof, K_SFT_ROWS, s, [&] { return launch_sft_rows(r, p->rows_blocks, p->rows_lds, p->rows_R, s); }),
             "sft rows launch");
     SftColsArgs k{};
     k.lens = p->lens_dev;
@@ -1510,7 +1546,7 @@ int rsf_sft_heterodyne(const rsf_sft_plan* p, const float* sft, float* x_h, void
     k.x = reinterpret_cast<float2*>(x_h);
     k.n_out = d.n_out;
     k.n_edge = (int)std::nearbyint(d.edge_taper_s * d.band);
-    RSF_HIP(timed_pr(p->prof, K_SFT_COLS, s, [&] { return launch_sft_cols(k, p->cols_blocks, p->cols_lds, s); }),
+    RSF_HIP(timed_pr(p->prof, K_SFT_COLS, s, [&] { return launch_sft_cols(k, p->cols_blocks, p->cols_lds, p->cols_C, s); }),
             "sft cols launch");
     return RSF_OK;
 }

@@ -77,9 +77,12 @@ struct SftMergeArgs {
 };
 
 // One chunk transform length n = LA LB of the SFT front end.  Its chunks are
-// ids[id0 .. id0 + nc); in the single rows launch its workgroups are
-// rows_blk0 + i LB + n_b (row n_b of its i-th chunk), in the single columns
-// launch cols_blk0 + i n_groups + g (8-column group g of its i-th chunk).
+// ids[id0 .. id0 + nc).  With R rows and C columns per workgroup (the same for
+// every length of a plan), its workgroups in the single rows launch are
+// rows_blk0 + i ceil(LB / R) + g (rows g R .. g R + R - 1 of its i-th chunk),
+// in the single columns launch cols_blk0 + i n_groups + g (columns
+// g C .. g C + C - 1, n_groups = ceil(LA / C)); st1 and st2 are planned for R
+// and C interleaved transforms.
 struct SftLenDev {
     int64_t n;
     int LA, LB, n_groups, nc, id0;

@@ -35,8 +35,10 @@ size_t sft_dft_lds(int Mp);
 hipError_t launch_sft_dft(const SftDftArgs& a, int64_t blocks, size_t lds, hipStream_t s);
 int64_t sft_merge_blocks(int n);  // merge workgroups of a chunk of n bins
 hipError_t launch_sft_merge(const SftMergeArgs& a, int64_t blocks, hipStream_t s);
-hipError_t launch_sft_rows(const SftRowsArgs& a, int64_t blocks, size_t lds, hipStream_t s);
-hipError_t launch_sft_cols(const SftColsArgs& b, int64_t blocks, size_t lds, hipStream_t s);
+size_t sft_rows_lds(int LA, int R);  // R rows of LA points per workgroup
+size_t sft_cols_lds(int LB, int C);  // C columns of LB points per workgroup
+hipError_t launch_sft_rows(const SftRowsArgs& a, int64_t blocks, size_t lds, int R, hipStream_t s);  // R in {1, 2, 4, 8}
+hipError_t launch_sft_cols(const SftColsArgs& b, int64_t blocks, size_t lds, int C, hipStream_t s);  // C in {8, 16, 32}
 hipError_t sft_set_lds_limits(size_t bytes);
 
 int point_blocks(int64_t P);

@@ -314,31 +314,62 @@ __device__ __forceinline__ int sft_len_of(const SftLenDev* lens, int n_lens, int
     return lo;
 }
 
-// Rows pass: workgroup w gathers row n_b of its chunk's band bins (elements
-// m = LB n_a + n_b), transforms it over n_a and spills it with the
-// inter-pass twiddle W_n^{n_b k_a}.
+// Spill writer of the rows pass, as the first F-statistic pass's: output
+// k_a = j + r LA/R_last of row n_b, times W_n^{n_b k_a}, goes to the spill in
+// 4-column groups; the twiddle of butterfly j = j0 + q s is
+// W^{n_b j0} (W^{n_b s})^q and steps by W^{n_b LA/R_last} along r.  A row past
+// the transform (ok false, in a workgroup's last group of rows) writes nothing.
+struct SftSpillSink {
+    char* out;
+    int LB, n_b, LR;
+    float2 wq, w_step, w_lr;
+    bool ok;
+    template <int R>
+    __device__ __forceinline__ void put(int, int j, int, cp (&v)[R]) {
+        if (!ok) return;
+        float2 w = wq;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t k = (uint32_t)(j + r * LR);
+            const uint32_t off = (((k >> 2) * (uint32_t)LB + (uint32_t)n_b) * kGroupCols + (k & 3u)) * 16u;
+            *reinterpret_cast<float4*>(out + off) = cp_rot(v[r], w);
+            if (r + 1 < R) w = c_mul(w, w_lr);
+        }
+        wq = c_mul(wq, w_step);
+    }
+};
+
+// Rows pass: workgroup w gathers RB consecutive rows n_b of its chunk's band
+// bins (elements m = LB n_a + n_b, the RB rows adjacent in memory), transforms
+// them over n_a as RB interleaved columns and spills them with the inter-pass
+// twiddle W_n^{n_b k_a}.  Thread tid always holds row tid mod RB (kNT is a
+// multiple of RB), so its twiddle recurrences run for one n_b.
+template <int RB>
 __global__ __launch_bounds__(kNT) void rsf_sft_rows_k(SftRowsArgs A) {
     extern __shared__ float4 lds[];
     const SftLenDev& L = A.lens[sft_len_of<&SftLenDev::rows_blk0>(A.lens, A.n_lens, blockIdx.x)];
     const int LA = L.LA, LB = L.LB;
     const int64_t n = L.n;
+    const int ng = (LB + RB - 1) / RB;  // row groups per chunk
     const int64_t local = (int64_t)blockIdx.x - L.rows_blk0;
-    const int i = (int)(local / LB);
-    const int n_b = (int)(local - (int64_t)i * LB);
+    const int i = (int)(local / ng);
+    const int nb0 = (int)(local - (int64_t)i * ng) * RB;
     const FftStages st = L.st1;
-    float2* twl = reinterpret_cast<float2*>(lds + LA);
+    float2* twl = reinterpret_cast<float2*>(lds + LA * RB);
     const int n_hi = (LA + 31) >> kTwLoBits;
     for (int e = threadIdx.x; e < 32 + n_hi; e += kNT) twl[e] = (e < 32) ? L.t1[e] : L.t1_hi[e - 32];
     const TwLds tws{twl, twl + 32};
     const SftChunkDev& c = A.chunks[A.ids[L.id0 + i]];
     const int tid = threadIdx.x;
-    const float2* src = A.y + c.y_off + n_b;
-    for (int n_a = tid; n_a < LA; n_a += kNT) {
-        const float2 v = src[(int64_t)LB * n_a];
-        lds[n_a] = make_float4(v.x, v.y, 0.f, 0.f);
+    const float2* src = A.y + c.y_off;
+    for (int e = tid; e < LA * RB; e += kNT) {
+        const int n_a = e / RB, b = e - n_a * RB;
+        const float2 v = (nb0 + b < LB) ? src[(int64_t)LB * n_a + nb0 + b] : make_float2(0.f, 0.f);
+        lds[e] = make_float4(v.x, v.y, 0.f, 0.f);
     }
-    const int64_t mb = ((int64_t)n_b * tid) % n;
-    const int64_t ms = ((int64_t)n_b * kNT) % n;
+    const int n_b = nb0 + tid % RB;
+    const int64_t mb = ((int64_t)n_b * (tid / RB)) % n;
+    const int64_t ms = ((int64_t)n_b * (kNT / RB)) % n;
     const int msk = (1 << kTwSplitBits) - 1;
     const float2 w_base = c_mul(L.tw_hi[mb >> kTwSplitBits], L.tw_lo[mb & msk]);
     const float2 w_step = c_mul(L.tw_hi[ms >> kTwSplitBits], L.tw_lo[ms & msk]);
@@ -347,8 +378,8 @@ __global__ __launch_bounds__(kNT) void rsf_sft_rows_k(SftRowsArgs A) {
     const int64_t ml = ((int64_t)n_b * lr) % n;
     const float2 w_lr = c_mul(L.tw_hi[ml >> kTwSplitBits], L.tw_lo[ml & msk]);
     __syncthreads();
-    SpillSink<false> sink{reinterpret_cast<char*>(A.spill + c.spill_off), LB, n_b, lr, w_base, w_step, w_lr};
-    lds_fft_into<kNT, kFftEPT, 1, false>(lds, st, tws, Interleaved<1>{}, sink, NoMid{});
+    SftSpillSink sink{reinterpret_cast<char*>(A.spill + c.spill_off), LB, n_b, lr, w_base, w_step, w_lr, n_b < LB};
+    lds_fft_into<kNT, kFftEPT, RB, false>(lds, st, tws, Interleaved<RB>{}, sink, NoMid{});
 }
 
 // Output j = k_a + LA k_b of the chunk's transform: x[j0 + j] for j < n_keep.
@@ -378,8 +409,11 @@ struct SeriesSink {
     }
 };
 
-// Columns pass: workgroup w transforms the 8 columns of group pair g of its
-// chunk (both 4-column spill groups) over n_b and writes the series.
+// Columns pass: workgroup w transforms the CB columns g CB .. g CB + CB - 1 of
+// its chunk (CB / 4 consecutive 4-column spill groups, one contiguous run)
+// over n_b and writes the series.  Columns at or past LA (padding of the last
+// group) are transformed but not written.
+template <int CB>
 __global__ __launch_bounds__(kNTB) void rsf_sft_cols_k(SftColsArgs B) {
     extern __shared__ float4 lds[];
     const SftLenDev& L = B.lens[sft_len_of<&SftLenDev::cols_blk0>(B.lens, B.n_lens, blockIdx.x)];
@@ -388,7 +422,7 @@ __global__ __launch_bounds__(kNTB) void rsf_sft_cols_k(SftColsArgs B) {
     const int i = (int)(local / L.n_groups);
     const int c = (int)(local - (int64_t)i * L.n_groups);
     const FftStages st = L.st2;
-    const int blk = LB * kPassBCols;
+    const int blk = LB * CB;
     const int buf_elems = ((blk + 63) / 64) * 64;
     float2* twl = reinterpret_cast<float2*>(lds + buf_elems);
     const int n_hi = (LB + 31) >> kTwLoBits;
@@ -400,8 +434,8 @@ __global__ __launch_bounds__(kNTB) void rsf_sft_cols_k(SftColsArgs B) {
     for (int e = tid; e < blk; e += kNTB) lds[e] = src[e];
     __syncthreads();
     const int r_last = st.n_stages ? st.radix[st.n_stages - 1] : 1;
-    SeriesSink sink{B.x, ch.j0, ch.n_keep, B.n_out, LA, LB / r_last, c * kPassBCols, B.n_edge, ch.corr};
-    lds_fft_into<kNTB, kPassBEPT, kPassBCols, false>(lds, st, tw, Grouped4{LB * kGroupCols}, sink, NoMid{});
+    SeriesSink sink{B.x, ch.j0, ch.n_keep, B.n_out, LA, LB / r_last, c * CB, B.n_edge, ch.corr};
+    lds_fft_into<kNTB, kPassBEPT, CB, false>(lds, st, tw, Grouped4{LB * kGroupCols}, sink, NoMid{});
 }
 
 hipError_t launch_sft_norm(const SftNormArgs& a, int n_sft, hipStream_t s) {
@@ -431,20 +465,43 @@ hipError_t launch_sft_merge(const SftMergeArgs& a, int64_t blocks, hipStream_t s
     return hipGetLastError();
 }
 
-hipError_t launch_sft_rows(const SftRowsArgs& a, int64_t blocks, size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL(rsf_sft_rows_k, dim3((unsigned)blocks), dim3(kNT), lds, s, a);
+size_t sft_rows_lds(int LA, int R) {
+    return (size_t)LA * R * sizeof(float4) + (32 + (LA + 31) / 32) * sizeof(float2);
+}
+
+size_t sft_cols_lds(int LB, int C) {
+    return (size_t)((LB * C + 63) / 64) * 64 * sizeof(float4) + (32 + (LB + 31) / 32) * sizeof(float2);
+}
+
+hipError_t launch_sft_rows(const SftRowsArgs& a, int64_t blocks, size_t lds, int R, hipStream_t s) {
+    const dim3 g((unsigned)blocks), b(kNT);
+    switch (R) {
+        case 1: hipLaunchKernelGGL(rsf_sft_rows_k<1>, g, b, lds, s, a); break;
+        case 2: hipLaunchKernelGGL(rsf_sft_rows_k<2>, g, b, lds, s, a); break;
+        case 4: hipLaunchKernelGGL(rsf_sft_rows_k<4>, g, b, lds, s, a); break;
+        case 8: hipLaunchKernelGGL(rsf_sft_rows_k<8>, g, b, lds, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_sft_cols(const SftColsArgs& b, int64_t blocks, size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL(rsf_sft_cols_k, dim3((unsigned)blocks), dim3(kNTB), lds, s, b);
+hipError_t launch_sft_cols(const SftColsArgs& k, int64_t blocks, size_t lds, int C, hipStream_t s) {
+    const dim3 g((unsigned)blocks), b(kNTB);
+    switch (C) {
+        case 8: hipLaunchKernelGGL(rsf_sft_cols_k<8>, g, b, lds, s, k); break;
+        case 16: hipLaunchKernelGGL(rsf_sft_cols_k<16>, g, b, lds, s, k); break;
+        case 32: hipLaunchKernelGGL(rsf_sft_cols_k<32>, g, b, lds, s, k); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
 hipError_t sft_set_lds_limits(size_t bytes) {
     static size_t granted = 0;  // only grows
     if (bytes <= granted) return hipSuccess;
-    const void* fns[] = {(const void*)rsf_sft_dft_k, (const void*)rsf_sft_rows_k, (const void*)rsf_sft_cols_k};
+    const void* fns[] = {(const void*)rsf_sft_dft_k,      (const void*)rsf_sft_rows_k<1>,  (const void*)rsf_sft_rows_k<2>,
+                         (const void*)rsf_sft_rows_k<4>,  (const void*)rsf_sft_rows_k<8>,  (const void*)rsf_sft_cols_k<8>,
+                         (const void*)rsf_sft_cols_k<16>, (const void*)rsf_sft_cols_k<32>};
     hipError_t out = hipSuccess;
     for (const void* f : fns) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
