@@ -16,7 +16,11 @@ gives:
   spindowns.
 Tolerance: |delta 2F| <= 1e-4 max(2F_oracle, 4).  Each injection is also
 recovered: in its own template the largest 2F within 8 bins of f0 sits on
-one of the two bins next to f0."""
+one of the two bins next to f0.
+
+A second test checks at the same size that the spill's cache policy (non-
+temporal when one launch's spill exceeds the last-level cache) changes no
+result bit."""
 import numpy as np
 import pytest
 
@@ -85,3 +89,27 @@ def test_c2_full_size_in_the_benchmark_launch_configuration(gpu_lib):
         peak = lo + int(np.argmax(rows[t][lo:lo + 18]))
         assert peak + s_lo in (int(np.floor(b)), int(np.floor(b)) + 1), (t, b, peak + s_lo)
         assert rows[t][peak] > 100.0
+
+
+def test_spill_cache_policy_leaves_results_bitwise_equal(gpu_lib):
+    """At T = 10 d a launch of 64 templates spills 7 GB, more than the
+    last-level cache, and takes the non-temporal stores and loads; a launch
+    of 2 templates (221 MB) is stored and read normally.  Cache hints change
+    no arithmetic: 128 templates give bitwise the same 2F both ways."""
+    import torch
+    w = synth.workload_c2(n_fdot=128)
+    print("\ncase: C2 noise, 128 spindowns, batching (16, 64) against (2, 2)", flush=True)
+    rng = np.random.default_rng(3)
+    x = synth.zero_gaps(synth.gaussian_noise(rng, w.segment.n, 1.0), w.gaps[0])
+    tx = [torch.from_numpy(x).cuda()]
+    tg = [torch.from_numpy(w.gaps[0]).cuda()]
+    sky = torch.from_numpy(np.ascontiguousarray(w.skies)).cuda()
+    fd = torch.from_numpy(np.ascontiguousarray(w.fdots)).cuda()
+    plan = gpu_lib.Plan(w)
+    outs = []
+    for fb, g in ((16, 64), (2, 2)):
+        plan.set_batching(fb, g)
+        outs.append(plan.fstat(tx, tg, sky, fd, mode=gpu_lib.RSF_MODE_BATCHED).cpu())
+        torch.cuda.empty_cache()
+    assert torch.equal(outs[0], outs[1])
+    assert torch.isfinite(outs[0]).all()
