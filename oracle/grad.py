@@ -1,14 +1,15 @@
 """Finite-difference gradient of 2F at a continuous frequency (oracle, FP64).
 
 A project addition (the paper has no gradients).  2F(theta), theta =
-(f, fdot, alpha, delta), is the resampling-chain statistic of ``oracle.fstat``
-evaluated at the continuous frequency f (``fstat_point``), with the series
-re-resampled for every sky offset.  Derivatives are central differences with
+(f, f^(1), ..., f^(s), alpha, delta) with spindown order s = len(theta) - 3
+(eq. eq4pt1 for general s), is the resampling-chain statistic of
+``oracle.fstat`` evaluated at the continuous frequency f (``fstat_point``),
+with the series re-resampled for every sky offset.  Derivatives are central differences with
 Richardson extrapolation, D = (4 g(h/2) - g(h)) / 3, g(h) = (F(x+h) - F(x-h)) / (2h), with 2h taken as the
 difference of the two rounded arguments.
 
-Default steps: h_f = 1e-3 / T0 Hz, h_fdot = 1e-3 / T0^2 Hz/s,
-h_alpha = h_delta = 1e-7 rad.
+Default steps: h_f = 1e-3 / T0 Hz, h_(j) = 1e-3 / T0^(j+1) Hz/s^j for
+f^(j), h_alpha = h_delta = 1e-7 rad.
 """
 import numpy as np
 
@@ -39,13 +40,14 @@ class PointProblem:
         return self._cache[key]
 
     def twoF(self, theta):
-        f, fdot, alpha, delta = (float(v) for v in theta)
-        return fstat_point(self.resampled(alpha, delta), self.dets, self.seg, f, fdot)
+        th = np.asarray(theta, dtype=np.float64)
+        f, spins, alpha, delta = float(th[0]), th[1:-2], float(th[-2]), float(th[-1])
+        return fstat_point(self.resampled(alpha, delta), self.dets, self.seg, f, spins)
 
 
-def default_steps(seg):
+def default_steps(seg, order=1):
     T0 = seg.n * seg.dt
-    return np.array([1e-3 / T0, 1e-3 / T0 ** 2, 1e-7, 1e-7])
+    return np.array([1e-3 / T0] + [1e-3 / T0 ** (j + 1) for j in range(1, order + 1)] + [1e-7, 1e-7])
 
 
 def central(fun, theta, i, h):
@@ -60,10 +62,12 @@ def central(fun, theta, i, h):
 
 
 def gradient(problem, theta, steps=None):
-    """Richardson-extrapolated central differences of 2F w.r.t. theta."""
-    steps = default_steps(problem.seg) if steps is None else np.asarray(steps)
-    g = np.empty(4)
-    for i in range(4):
+    """Richardson-extrapolated central differences of 2F w.r.t. every
+    component of theta."""
+    theta = np.asarray(theta, dtype=np.float64)
+    steps = default_steps(problem.seg, len(theta) - 3) if steps is None else np.asarray(steps)
+    g = np.empty(len(theta))
+    for i in range(len(theta)):
         g1 = central(problem.twoF, theta, i, steps[i])
         g2 = central(problem.twoF, theta, i, steps[i] / 2.0)
         g[i] = (4.0 * g2 - g1) / 3.0

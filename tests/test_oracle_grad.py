@@ -1,14 +1,16 @@
 """Pins for the oracle's finite-difference gradient of 2F.
 
-* in f and fdot the resampled series is fixed, so the derivative has a
-  closed form (the single-bin sum differentiated under the sum), derived
-  here independently of the finite differences;
+* in f and the spindowns f^(1..s) the resampled series is fixed, so the
+  derivative has a closed form (the single-bin sum differentiated under the
+  sum: d Phi_s / d f^(j) = 2 pi (T^(j+1)/(j+1)! + t_m T^j/j!)), derived here
+  independently of the finite differences, at spindown orders 1, 2 and 3;
 * in alpha and delta the series is re-resampled; the Richardson value must
   agree with plain central differences at two step sizes;
 * at the noise-free peak of an on-bin matched injection of a stationary
   detector, d2F/df vanishes by symmetry.
 """
 import numpy as np
+import pytest
 
 from oracle import fstat as of
 from oracle import grad as og
@@ -29,18 +31,20 @@ def _problem(seed=1, h0=0.5, eph=EPH):
     return og.PointProblem([x], [NOGAP], SEG, [DET_H], eph, KERNEL_LANCZOS, 8), inj
 
 
-def _analytic_f_fdot(problem, theta):
-    f, fdot, alpha, delta = theta
+def _analytic_f_spins(problem, theta):
+    f, spins, alpha, delta = theta[0], theta[1:-2], theta[-2], theta[-1]
     rs = problem.resampled(alpha, delta)
     A, B, C = of.antenna_sums(rs, problem.dets)
     D = A * B - C * C
-    ya, yb = of.integrands(rs, problem.dets, fdot)
+    ya, yb = of.integrands(rs, problem.dets, spins)
     t = np.arange(SEG.n) * SEG.dt
     e = np.exp(-2j * np.pi * (f - SEG.f_het) * t)
-    u = rs[0]["T"] ** 2 / 2 + rs[0]["tm"] * rs[0]["T"]
+    T, tm = rs[0]["T"], rs[0]["tm"]
+    # d/d f^(j) of the spindown phase, written out per order
+    u = [T ** 2 / 2 + tm * T, T ** 3 / 6 + tm * T ** 2 / 2, T ** 4 / 24 + tm * T ** 3 / 6][:len(spins)]
     fa, fb = np.sum(ya * e), np.sum(yb * e)
     out = []
-    for w in (-2j * np.pi * t, -2j * np.pi * u):
+    for w in [-2j * np.pi * t] + [-2j * np.pi * uj for uj in u]:
         dfa, dfb = np.sum(w * ya * e), np.sum(w * yb * e)
         d = 2.0 * (2 * B * np.real(np.conj(fa) * dfa) + 2 * A * np.real(np.conj(fb) * dfb)
                    - 2 * C * np.real(dfa * np.conj(fb) + fa * np.conj(dfb))) / D
@@ -48,20 +52,23 @@ def _analytic_f_fdot(problem, theta):
     return np.array(out)
 
 
-def test_fd_matches_closed_form_in_f_and_fdot():
+@pytest.mark.parametrize("spins", [[3e-12], [3e-12, -2e-17], [3e-12, -2e-17, 5e-23]])
+def test_fd_matches_closed_form_in_f_and_spindowns(spins):
     prob, inj = _problem()
-    theta = np.array([inj.f0 + 0.2 * DF, inj.fdot + 3e-12, inj.alpha, inj.delta])
+    theta = np.array([inj.f0 + 0.2 * DF] + [inj.fdot + spins[0]] + spins[1:] + [inj.alpha, inj.delta])
     g = og.gradient(prob, theta)
-    ref = _analytic_f_fdot(prob, theta)
-    assert np.max(np.abs(g[:2] - ref) / np.abs(ref)) < 1e-6
+    assert g.shape == theta.shape
+    ref = _analytic_f_spins(prob, theta)
+    assert np.max(np.abs(g[:1 + len(spins)] - ref) / np.abs(ref)) < 1e-6
 
 
-def test_richardson_consistent_in_sky():
+@pytest.mark.parametrize("extra", [[], [4e-17]])
+def test_richardson_consistent_in_sky(extra):
     prob, inj = _problem(seed=2)
-    theta = np.array([inj.f0, inj.fdot, inj.alpha + 2e-4, inj.delta - 1e-4])
-    h = og.default_steps(SEG)
+    theta = np.array([inj.f0, inj.fdot] + extra + [inj.alpha + 2e-4, inj.delta - 1e-4])
+    h = og.default_steps(SEG, 1 + len(extra))
     g = og.gradient(prob, theta)
-    for i in (2, 3):
+    for i in (len(theta) - 2, len(theta) - 1):
         c1 = og.central(prob.twoF, theta, i, h[i])
         c2 = og.central(prob.twoF, theta, i, h[i] / 4)
         assert abs(c1 - g[i]) < 1e-4 * abs(g[i]) + 1e-3
