@@ -150,8 +150,10 @@ int rsf_plan_destroy(rsf_plan* plan);
  * default 1).  With order s, every `fdot` argument of rsf_fstat,
  * rsf_fstat_topk and the graph builders is double [n_fdot][s]: row i holds
  * (f^(1), ..., f^(s)) of template i, and
- * Phi_s = 2 pi sum_j f^(j) (T^{j+1}/(j+1)! + t_m T^j/j!).  The point and gradient
- * entries and the semi-coherent sum take order 1 only (RSF_EUNSUPPORTED). */
+ * Phi_s = 2 pi sum_j f^(j) (T^{j+1}/(j+1)! + t_m T^j/j!), and every `theta`
+ * of rsf_fstat_point / rsf_fstat_backward is double [n][3 + s]:
+ * (f, f^(1), ..., f^(s), alpha, delta).  The semi-coherent sum takes order 1
+ * only (RSF_EUNSUPPORTED). */
 int rsf_plan_set_spin_order(rsf_plan* plan, int order);
 
 /* Sources in circular binary orbits (on != 0; default off).  Every `sky`
@@ -241,20 +243,23 @@ int rsf_fstat_semicoherent(const rsf_plan* plan, const rsf_segment* seg, const d
                            const double* fdot, int64_t n_fdot, double t_ref, double f_lo, double df_c, int64_t n_c,
                            float* S, void* ws, size_t ws_bytes, void* stream);
 
-/* 2F at continuous parameters: theta device float64[n][4] = (f Hz, fdot Hz/s,
- * alpha, delta rad); f_a(f) = sum_k y^a_k exp(-2 pi i (f - f_het) k dt) on the
+/* 2F at continuous parameters: theta device float64[n][3 + s] = (f Hz,
+ * f^(1) Hz/s, ..., f^(s) Hz/s^s, alpha, delta rad) at the plan's spindown
+ * order s (1 by default: (f, fdot, alpha, delta));
+ * f_a(f) = sum_k y^a_k exp(-2 pi i (f - f_het) k dt) on the
  * resampled series of each candidate's own sky (equal to FFT bin s when
  * f = f_het + s df).  twoF: device float32[n]. */
 int rsf_fstat_point(const rsf_plan* plan, const rsf_segment* seg, const double* theta, int64_t n,
                     float* twoF, void* ws, size_t ws_bytes, void* stream);
 
 /* Vector-Jacobian product of rsf_fstat_point: g_theta[i][:] = g_twoF[i] *
- * d2F/d(f, fdot, alpha, delta) at theta[i], through the F-statistic, the
- * Fourier sum, the spindown phase, the interpolation, the heterodyne
+ * d2F/d(f, f^(1), ..., f^(s), alpha, delta) at theta[i], through the
+ * F-statistic, the Fourier sum, the spindown phase (including its
+ * dependence on the sky through T and t_m), the interpolation, the heterodyne
  * correction, the beam patterns and the timing inversion (dT/dtheta =
  * -(dt_m/dtheta)/(1 + dt_m/dt)).  The resampled series is recomputed, never
  * stored.  g_twoF: device float32[n]; twoF: device float32[n] or NULL;
- * g_theta: device float64[n][4]. */
+ * g_theta: device float64[n][3 + s]. */
 int rsf_fstat_backward(const rsf_plan* plan, const rsf_segment* seg, const double* theta, int64_t n,
                        const float* g_twoF, float* twoF, double* g_theta,
                        void* ws, size_t ws_bytes, void* stream);

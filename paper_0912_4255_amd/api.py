@@ -81,6 +81,13 @@ class Plan:
             raise ValueError(f"fdot must be [n_fdot, {self.spin_order}] at spin order {self.spin_order}")
         return fdot.shape[0]
 
+    def _n_theta(self, theta):
+        """Candidates in a theta tensor [n, 3 + s] = (f, f^(1) .. f^(s), alpha, delta)."""
+        width = 3 + self.spin_order
+        if theta.dim() != 2 or theta.shape[1] != width:
+            raise ValueError(f"theta must be [n, {width}] at spin order {self.spin_order}")
+        return theta.shape[0]
+
     def set_binary(self, on=True):
         """rsf_plan_set_binary: sky rows become (alpha, delta, a_p, P_b, t_asc)."""
         L.check(self.lib.rsf_plan_set_binary(self._p, 1 if on else 0))
@@ -223,9 +230,10 @@ class Plan:
         return S
 
     def point(self, xs, gaps, theta, out=None, ws=None):
-        """rsf_fstat_point: 2F [n] at continuous theta [n, 4] = (f, fdot, alpha, delta)."""
+        """rsf_fstat_point: 2F [n] at continuous theta [n, 3 + s] =
+        (f, f^(1) .. f^(s), alpha, delta), s the spin order (1: (f, fdot, alpha, delta))."""
         _need_cuda(theta, torch.float64, "theta")
-        n = theta.shape[0]
+        n = self._n_theta(theta)
         seg, keep = self.segment(xs, gaps)
         dev = xs[0].device
         if out is None:
@@ -237,14 +245,14 @@ class Plan:
         return out
 
     def backward(self, xs, gaps, theta, g_twoF, ws=None):
-        """rsf_fstat_backward: (2F [n], g_twoF * d2F/dtheta [n, 4])."""
+        """rsf_fstat_backward: (2F [n], g_twoF * d2F/dtheta [n, 3 + s])."""
         _need_cuda(theta, torch.float64, "theta")
         _need_cuda(g_twoF, torch.float32, "g_twoF")
-        n = theta.shape[0]
+        n = self._n_theta(theta)
         seg, keep = self.segment(xs, gaps)
         dev = xs[0].device
         twoF = torch.empty(n, dtype=torch.float32, device=dev)
-        g_theta = torch.empty((n, 4), dtype=torch.float64, device=dev)
+        g_theta = torch.empty((n, theta.shape[1]), dtype=torch.float64, device=dev)
         if ws is None:
             ws = self.workspace(L.RSF_ENTRY_BACKWARD, 1, n, device=dev)
         L.check(self.lib.rsf_fstat_backward(self._p, C.byref(seg), _ptr(theta), n, _ptr(g_twoF), _ptr(twoF),
@@ -321,9 +329,10 @@ class Graph:
 
 
 class FStatFn(torch.autograd.Function):
-    """2F(theta) at continuous (f, fdot, alpha, delta) with a hand-written
-    adjoint: forward calls rsf_fstat_point, backward rsf_fstat_backward (which
-    recomputes the resampled series).  theta: float64 [n, 4] on the GPU."""
+    """2F(theta) at continuous (f, f^(1) .. f^(s), alpha, delta) with a
+    hand-written adjoint: forward calls rsf_fstat_point, backward
+    rsf_fstat_backward (which recomputes the resampled series).  theta:
+    float64 [n, 3 + s] on the GPU, s the plan's spin order."""
 
     @staticmethod
     def forward(ctx, theta, plan, xs, gaps):

@@ -916,7 +916,6 @@ int point_common(const rsf_plan* p, const rsf_segment* seg, const double* theta,
     if (!p) return fail(RSF_EINVAL, "plan is NULL");
     int rc = check_segment(p, seg);
     if (rc) return rc;
-    if (p->spin_order != 1) return fail(RSF_EUNSUPPORTED, "point evaluation and its gradient take spin order 1 only");
     if (p->binary) return fail(RSF_EUNSUPPORTED, "point evaluation and its gradient take isolated sources only");
     if (!theta) return fail(RSF_EINVAL, "theta is NULL");
     if (n < 1 || n > 65535) return fail(RSF_EINVAL, "number of candidates must be in 1..65535");
@@ -952,6 +951,7 @@ int point_common(const rsf_plan* p, const rsf_segment* seg, const double* theta,
     }
     a.ip = p->ip;
     a.theta = theta;
+    a.order = p->spin_order;
     a.n_cand = (int)n;
     a.P = (p->n + 63) / 64;
     a.n_blocks = L.n_blocks;
@@ -962,6 +962,7 @@ int point_common(const rsf_plan* p, const rsf_segment* seg, const double* theta,
     r.partials = a.partials;
     r.n_blocks = L.n_blocks;
     r.n_cand = (int)n;
+    r.order = p->spin_order;
     r.grad = grad ? 1 : 0;
     r.g_twoF = g_twoF;
     r.twoF = twoF;

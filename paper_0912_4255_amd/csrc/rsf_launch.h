@@ -5,6 +5,7 @@
 
 #include "rsf_front_params.h"
 #include "rsf_params.h"
+#include "rsf_point_params.h"
 
 namespace rsf {
 

@@ -195,41 +195,6 @@ struct TopkMergeArgs {
     void* entries;            // rsf_topk_entry[k] written if not null
 };
 
-// Continuous-parameter 2F and its gradient (one detector set, a batch of
-// candidates theta = (f, fdot, alpha, delta)).
-constexpr int kPointSums = 32;      // FP64 partial sums per (block, candidate)
-constexpr int kPointTiles = 8;      // 1024-sample tiles per block
-
-struct PointArgs {
-    int64_t n;
-    double dt, t_start, f_het;
-    EphDev eph;
-    int n_det;
-    DetDev det[kMaxDet];
-    InterpDev ip;
-    const float2* x[kMaxDet];
-    const int64_t* gaps[kMaxDet];
-    int n_gaps[kMaxDet];
-    const double* theta;      // [n_cand][4]
-    int n_cand;
-    int64_t P;                // 64-sample rows: ceil(n / 64)
-    int n_blocks;             // blocks per candidate
-    double* partials;         // [n_cand][n_blocks][kPointSums]
-    unsigned int* flags;
-};
-
-struct PointReduceArgs {
-    const double* partials;
-    int n_blocks;
-    int n_cand;
-    int grad;
-    const float* g_twoF;      // [n_cand] (grad)
-    float* twoF;              // [n_cand] (may be null)
-    double* g_theta;          // [n_cand][4] (grad)
-    unsigned int* flags;
-};
-
-
 // Semi-coherent sum: template t = s nf_l + f of a launch adds its 2F at the
 // bin nearest f_lo + j df_c + fdot (t_seg - t_ref) to S[row][j].
 struct SemicoArgs {

@@ -1,20 +1,23 @@
 // 2F at continuous parameters and its gradient (project addition on top of
-// paper Sec. III.A.2): for every candidate theta = (f, fdot, alpha, delta)
-// the resampled series of the candidate's own sky is recomputed on the fly
+// paper Sec. III.A.2): for every candidate theta = (f, f^(1), ..., f^(s),
+// alpha, delta) at spindown order s = 1..3 the resampled series of the
+// candidate's own sky is recomputed on the fly
 // (never stored) and reduced to
 //   F_a = sum_k y^a_k exp(-2 pi i (f - f_het) t_b^k),   F_b likewise,
 //   A', B', C'  (masked antenna sums),
 // plus, for the gradient, the derivatives of all five with respect to
 // theta, following every dependence of the resampling chain:
 //   * f:     d/df exp(-2 pi i (f - f_het) t_b) = -2 pi i t_b (...);
-//   * fdot:  Phi_s = pi fdot (t_b^2 - t_m^2)  (eq. eq4pt1 with T = t_b - t_m);
+//   * f^(j): Phi_s = 2 pi sum_j f^(j) (T^(j+1)/(j+1)! + t_m T^j/j!)  (eq. eq4pt1),
+//            which at s = 1 is pi fdot (t_b^2 - t_m^2) with T = t_b - t_m;
 //   * sky:   t_m(tau) = n0 . r_d(tau) (eq. eq4pt2); the inversion of eq. eq21
 //            gives dT/dtheta = -(dt_m/dtheta)/(1 + dt_m/dt); the
 //            interpolated series changes through the kernel derivative
 //            w'(u - p) dT/dtheta / dt and through the heterodyne correction
 //            dz_p/dtheta = -2 pi i f_het (dt_m/dtheta)(t_p) z_p (eq. absorb);
 //            the beam patterns change through p, q(alpha, delta) and T; the
-//            spindown phase through t_m.
+//            spindown phase through T at fixed t_b:
+//            dPhi_s/dT = 2 pi t_m sum_j f^(j) T^(j-1)/(j-1)!.
 // Each block accumulates FP64 partial sums over 8 tiles of 1024 samples;
 // rsf_point_reduce_k sums the blocks of a candidate in a fixed order and
 // forms 2F (eq. eq6) and the vector-Jacobian product g * d2F/dtheta.
@@ -32,16 +35,22 @@ constexpr int kThreads = 256;
 constexpr int kWinMax = kTileB + kMaxTaps + 8;
 constexpr float kPiF = 3.14159265358979323846f;
 
-// partial-sum slots
-enum {
-    S_FA = 0, S_FB = 2, S_A = 4, S_B = 5, S_C = 6,
-    S_DFA = 7,   // 4 parameters x (re, im)
-    S_DFB = 15,
-    S_DA = 23,   // (alpha, delta)
-    S_DB = 25,
-    S_DC = 27,
-    S_USED = 29
+// partial-sum slots at spindown order ORDER (3 + ORDER parameters)
+template <int ORDER>
+struct Slots {
+    static constexpr int NP = 3 + ORDER;
+    static constexpr int FA = 0, FB = 2, A = 4, B = 5, C = 6;
+    static constexpr int DFA = 7;             // NP parameters x (re, im)
+    static constexpr int DFB = DFA + 2 * NP;
+    static constexpr int DA = DFB + 2 * NP;   // (alpha, delta)
+    static constexpr int DB = DA + 2;
+    static constexpr int DC = DB + 2;
+    static constexpr int USED = DC + 2;
 };
+static_assert(Slots<3>::USED <= kPointSums, "partial-sum stride too small");
+
+// 1/j! for the spindown terms
+__device__ constexpr double kInvFact[5] = {1.0, 1.0, 0.5, 1.0 / 6.0, 1.0 / 24.0};
 
 struct Orbit {
     double3 r;       // r_d / c (s)
@@ -215,16 +224,26 @@ __device__ __forceinline__ void kernel_w(const InterpDev& ip, float x, float sx,
 
 }  // namespace
 
-template <bool GRAD>
+template <bool GRAD, int ORDER>
 __global__ __launch_bounds__(kThreads, 2) void rsf_point_k(PointArgs A) {
+    using SL = Slots<ORDER>;
+    constexpr int NP = SL::NP;
+    constexpr int S_FA = SL::FA, S_FB = SL::FB, S_A = SL::A, S_B = SL::B, S_C = SL::C;
+    constexpr int S_DFA = SL::DFA, S_DFB = SL::DFB, S_DA = SL::DA, S_DB = SL::DB, S_DC = SL::DC;
+    constexpr int S_USED = SL::USED;
+    constexpr int S_SKY = 2 * (1 + ORDER);  // offset of (alpha, delta) within S_DFA / S_DFB
     __shared__ float4 win[4][kWinMax];  // z (re, im), 2 pi f_het dt_m/dalpha, 2 pi f_het dt_m/ddelta
     __shared__ double red[4][kPointSums];
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int cand = blockIdx.y;
-    const double f = A.theta[4 * cand + 0], fd = A.theta[4 * cand + 1];
-    const double al = A.theta[4 * cand + 2], de = A.theta[4 * cand + 3];
+    const double* th = A.theta + (int64_t)NP * cand;
+    const double f = th[0], al = th[NP - 2], de = th[NP - 1];
+    double fs[ORDER];  // f^(1) .. f^(ORDER)
+#pragma unroll
+    for (int i = 0; i < ORDER; ++i) fs[i] = th[1 + i];
+    const double fd = fs[0];
     double sa, ca, sd, cd;
     sincos(al, &sa, &ca);
     sincos(de, &sd, &cd);
@@ -434,8 +453,22 @@ __global__ __launch_bounds__(kThreads, 2) void rsf_point_k(PointArgs A) {
                             szd.y += w * zz.w * zz.y;
                         }
                     }
-                    // total phase: spindown Phi_s and the Fourier kernel at f
-                    const double cyc = fd * 0.5 * (tb * tb - tm * tm) + (f - A.f_het) * tb;
+                    // total phase: spindown Phi_s and the Fourier kernel at f;
+                    // us[j] = T^(j+2)/(j+2)! + t_m T^(j+1)/(j+1)! (cycles per unit f^(j+1))
+                    double us[ORDER];
+                    double cyc;
+                    if constexpr (ORDER == 1) {
+                        cyc = fd * 0.5 * (tb * tb - tm * tm) + (f - A.f_het) * tb;
+                    } else {
+                        double Tj = T;  // T^(j+1)
+                        cyc = (f - A.f_het) * tb;
+#pragma unroll
+                        for (int i = 0; i < ORDER; ++i) {
+                            us[i] = Tj * T * kInvFact[i + 2] + tm * Tj * kInvFact[i + 1];
+                            cyc += fs[i] * us[i];
+                            Tj *= T;
+                        }
+                    }
                     const float ph = (float)(cyc - rint(cyc));
                     const float s = __builtin_amdgcn_sinf(ph), c = __builtin_amdgcn_cosf(ph);  // revolutions
                     // ze = z~ exp(-2 pi i cyc)
@@ -451,22 +484,41 @@ __global__ __launch_bounds__(kThreads, 2) void rsf_point_k(PointArgs A) {
                         acc[S_C] += w * av * bv;
                     }
                     if (GRAD) {
-                        // d/df: -2 pi i t_b ; d/dfdot: -i pi (t_b^2 - t_m^2)
+                        // d/df: -2 pi i t_b ; d/df^(j): -2 pi i us[j-1]
+                        // (at order 1: -i pi (t_b^2 - t_m^2))
                         const double cf_ = 2.0 * kPi * tb;
-                        const double cfd = kPi * (tb * tb - tm * tm);
                         // (-i c) (x + i y) = c y - i c x
                         acc[S_DFA + 0] += w * av * cf_ * zei;
                         acc[S_DFA + 1] -= w * av * cf_ * zer;
                         acc[S_DFB + 0] += w * bv * cf_ * zei;
                         acc[S_DFB + 1] -= w * bv * cf_ * zer;
-                        acc[S_DFA + 2] += w * av * cfd * zei;
-                        acc[S_DFA + 3] -= w * av * cfd * zer;
-                        acc[S_DFB + 2] += w * bv * cfd * zei;
-                        acc[S_DFB + 3] -= w * bv * cfd * zer;
-                        // sky: dz~/dth = s1 dT/dth / dt - i sz_th ; dPhi/dth = 2 pi fdot t_m dT/dth
+                        // dPhi_s/dT / (2 pi t_m) = sum_j f^(j) T^(j-1)/(j-1)!
+                        double rate;
+                        if constexpr (ORDER == 1) {
+                            const double cfd = kPi * (tb * tb - tm * tm);
+                            acc[S_DFA + 2] += w * av * cfd * zei;
+                            acc[S_DFA + 3] -= w * av * cfd * zer;
+                            acc[S_DFB + 2] += w * bv * cfd * zei;
+                            acc[S_DFB + 3] -= w * bv * cfd * zer;
+                            rate = fd;
+                        } else {
+                            double Tj = 1.0;
+                            rate = 0.0;
+#pragma unroll
+                            for (int i = 0; i < ORDER; ++i) {
+                                const double cu = 2.0 * kPi * us[i];
+                                acc[S_DFA + 2 + 2 * i] += w * av * cu * zei;
+                                acc[S_DFA + 3 + 2 * i] -= w * av * cu * zer;
+                                acc[S_DFB + 2 + 2 * i] += w * bv * cu * zei;
+                                acc[S_DFB + 3 + 2 * i] -= w * bv * cu * zer;
+                                rate += fs[i] * Tj * kInvFact[i];
+                                Tj *= T;
+                            }
+                        }
+                        // sky: dz~/dth = s1 dT/dth / dt - i sz_th ; dPhi/dth = dPhi_s/dT dT/dth
                         const float dTa_u = (float)(dTa / A.dt), dTd_u = (float)(dTd / A.dt);
-                        const float dpa = (float)(2.0 * kPi * fd * tm * dTa);
-                        const float dpd = (float)(2.0 * kPi * fd * tm * dTd);
+                        const float dpa = (float)(2.0 * kPi * rate * tm * dTa);
+                        const float dpd = (float)(2.0 * kPi * rate * tm * dTd);
                         // dz~_alpha = (s1.x dTa_u + sza.y, s1.y dTa_u - sza.x)
                         const float dza_r = s1.x * dTa_u + sza.y, dza_i = s1.y * dTa_u - sza.x;
                         const float dzd_r = s1.x * dTd_u + szd.y, dzd_i = s1.y * dTd_u - szd.x;
@@ -474,14 +526,14 @@ __global__ __launch_bounds__(kThreads, 2) void rsf_point_k(PointArgs A) {
                         const float ea_r = dza_r * c + dza_i * s, ea_i = dza_i * c - dza_r * s;
                         const float ed_r = dzd_r * c + dzd_i * s, ed_i = dzd_i * c - dzd_r * s;
                         // d(a ze)/dth = da ze + a (dz~ e) + a ze (-i dPhi)
-                        acc[S_DFA + 4] += w * (daa * zer + av * ea_r + av * dpa * zei);
-                        acc[S_DFA + 5] += w * (daa * zei + av * ea_i - av * dpa * zer);
-                        acc[S_DFA + 6] += w * (dad * zer + av * ed_r + av * dpd * zei);
-                        acc[S_DFA + 7] += w * (dad * zei + av * ed_i - av * dpd * zer);
-                        acc[S_DFB + 4] += w * (dba * zer + bv * ea_r + bv * dpa * zei);
-                        acc[S_DFB + 5] += w * (dba * zei + bv * ea_i - bv * dpa * zer);
-                        acc[S_DFB + 6] += w * (dbd * zer + bv * ed_r + bv * dpd * zei);
-                        acc[S_DFB + 7] += w * (dbd * zei + bv * ed_i - bv * dpd * zer);
+                        acc[S_DFA + S_SKY + 0] += w * (daa * zer + av * ea_r + av * dpa * zei);
+                        acc[S_DFA + S_SKY + 1] += w * (daa * zei + av * ea_i - av * dpa * zer);
+                        acc[S_DFA + S_SKY + 2] += w * (dad * zer + av * ed_r + av * dpd * zei);
+                        acc[S_DFA + S_SKY + 3] += w * (dad * zei + av * ed_i - av * dpd * zer);
+                        acc[S_DFB + S_SKY + 0] += w * (dba * zer + bv * ea_r + bv * dpa * zei);
+                        acc[S_DFB + S_SKY + 1] += w * (dba * zei + bv * ea_i - bv * dpa * zer);
+                        acc[S_DFB + S_SKY + 2] += w * (dbd * zer + bv * ed_r + bv * dpd * zei);
+                        acc[S_DFB + S_SKY + 3] += w * (dbd * zei + bv * ed_i - bv * dpd * zer);
                         if (mk) {
                             acc[S_DA + 0] += w * 2.0 * av * daa;
                             acc[S_DA + 1] += w * 2.0 * av * dad;
@@ -521,11 +573,16 @@ __global__ __launch_bounds__(kThreads, 2) void rsf_point_k(PointArgs A) {
 // One workgroup per candidate: fixed-order sum of the block partials, then
 // 2F = 2Q/D with Q = B|Fa|^2 + A|Fb|^2 - 2C Re(Fa Fb^*), D = AB - C^2, and
 // d2F = 2 (dQ D - Q dD) / D^2.
+template <int ORDER>
 __global__ __launch_bounds__(256) void rsf_point_reduce_k(PointReduceArgs R) {
+    using SL = Slots<ORDER>;
+    constexpr int NP = SL::NP;
+    constexpr int S_FA = SL::FA, S_FB = SL::FB, S_A = SL::A, S_B = SL::B, S_C = SL::C;
+    constexpr int S_DFA = SL::DFA, S_DFB = SL::DFB, S_DA = SL::DA, S_DB = SL::DB, S_DC = SL::DC;
     __shared__ double red[256];
     __shared__ double tot[kPointSums];
     const int cand = blockIdx.x;
-    const int nsum = R.grad ? S_USED : S_DFA;
+    const int nsum = R.grad ? SL::USED : S_DFA;
     const double* p = R.partials + (int64_t)cand * R.n_blocks * kPointSums;
     for (int i = 0; i < nsum; ++i) {
         double s = 0.0;
@@ -552,18 +609,20 @@ __global__ __launch_bounds__(256) void rsf_point_reduce_k(PointReduceArgs R) {
     if (R.twoF) R.twoF[cand] = (float)F2;
     if (!R.grad) return;
     const double g = (double)R.g_twoF[cand];
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < NP; ++i) {
         const double dar = tot[S_DFA + 2 * i], dai = tot[S_DFA + 2 * i + 1];
         const double dbr = tot[S_DFB + 2 * i], dbi = tot[S_DFB + 2 * i + 1];
-        const double dA = (i >= 2) ? tot[S_DA + i - 2] : 0.0;
-        const double dB = (i >= 2) ? tot[S_DB + i - 2] : 0.0;
-        const double dC = (i >= 2) ? tot[S_DC + i - 2] : 0.0;
+        // the antenna sums depend on the sky only (the last two parameters)
+        const int k = i - (NP - 2);
+        const double dA = (k >= 0) ? tot[S_DA + k] : 0.0;
+        const double dB = (k >= 0) ? tot[S_DB + k] : 0.0;
+        const double dC = (k >= 0) ? tot[S_DC + k] : 0.0;
         const double dQ = dB * fa2 + 2.0 * Bb * (Far * dar + Fai * dai) + dA * fb2 +
                           2.0 * Aa * (Fbr * dbr + Fbi * dbi) - 2.0 * dC * reab -
                           2.0 * Cc * (dar * Fbr + dai * Fbi + Far * dbr + Fai * dbi);
         const double dD = dA * Bb + Aa * dB - 2.0 * Cc * dC;
         const double d2F = degenerate ? F2 : 2.0 * (dQ * D - Q * dD) / (D * D);
-        R.g_theta[4 * cand + i] = g * d2F;
+        R.g_theta[(int64_t)NP * cand + i] = g * d2F;
     }
 }
 
@@ -571,15 +630,28 @@ int point_blocks(int64_t P) { return (int)((P + kTileA * kPointTiles - 1) / (kTi
 
 hipError_t launch_point(const PointArgs& a, bool grad, hipStream_t s) {
     const dim3 grid((unsigned)a.n_blocks, (unsigned)a.n_cand);
-    if (grad)
-        hipLaunchKernelGGL(rsf_point_k<true>, grid, dim3(kThreads), 0, s, a);
-    else
-        hipLaunchKernelGGL(rsf_point_k<false>, grid, dim3(kThreads), 0, s, a);
+#define RSF_POINT(G, O) hipLaunchKernelGGL((rsf_point_k<G, O>), grid, dim3(kThreads), 0, s, a)
+    switch (a.order * 2 + (grad ? 1 : 0)) {
+        case 2: RSF_POINT(false, 1); break;
+        case 3: RSF_POINT(true, 1); break;
+        case 4: RSF_POINT(false, 2); break;
+        case 5: RSF_POINT(true, 2); break;
+        case 6: RSF_POINT(false, 3); break;
+        case 7: RSF_POINT(true, 3); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef RSF_POINT
     return hipGetLastError();
 }
 
 hipError_t launch_point_reduce(const PointReduceArgs& r, hipStream_t s) {
-    hipLaunchKernelGGL(rsf_point_reduce_k, dim3((unsigned)r.n_cand), dim3(256), 0, s, r);
+    const dim3 grid((unsigned)r.n_cand);
+    switch (r.order) {
+        case 1: hipLaunchKernelGGL(rsf_point_reduce_k<1>, grid, dim3(256), 0, s, r); break;
+        case 2: hipLaunchKernelGGL(rsf_point_reduce_k<2>, grid, dim3(256), 0, s, r); break;
+        case 3: hipLaunchKernelGGL(rsf_point_reduce_k<3>, grid, dim3(256), 0, s, r); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -1,4 +1,5 @@
-"""GPU point evaluation and hand-written adjoint against the FP64 oracle.
+"""GPU point evaluation and hand-written adjoint against the FP64 oracle, at
+spindown orders 1, 2 and 3.
 
 2F at continuous theta: |delta| <= 1e-4 max(2F_oracle, 4).
 Gradient: scaled components g~ = g (1/T0, 1/T0^2, 1e-5, 1e-5) must satisfy
@@ -136,4 +137,67 @@ def test_point_long_sampling_interval_and_range_check(gpu_lib):
     tx, tg = to_gpu(xs, gaps)
     with pytest.raises(Exception, match="point search needs"):
         plan.point(tx, tg, torch.from_numpy(th[:1]).cuda())
+    plan.close()
+
+
+@pytest.mark.parametrize("order", [2, 3])
+def test_higher_order_point_and_adjoint_match_oracle(gpu_lib, order):
+    """Spindown orders 2 and 3, theta = (f, f^(1) .. f^(s), alpha, delta):
+    2F within 1e-4 max(2F, 4) of the oracle, and the adjoint within the
+    scaled 1e-3 bar above, f^(j) scaled by 1/T0^(j+1).  With f^(2) = f^(3) = 0
+    the order-s values equal the order-1 ones, and the autograd function
+    returns a gradient of the same width as theta."""
+    import torch
+    w = synth.small_workload(n=21600, dt=4.0, kernel=synth.KERNEL_DIRICHLET, taps=16)
+    rng = np.random.default_rng(3)
+    w.gaps = [synth.random_gaps(rng, w.segment.n, 500, 3)]
+    df = 1.0 / (2 * w.segment.n * w.segment.dt)
+    inj = Injection(h0=1.5, cosi=0.2, psi=-0.3, phi0=2.0, f0=w.segment.f_het + 2200.3 * df, fdot=-4e-10,
+                    alpha=2.1, delta=-0.4, f2=1e-14, f3=(4e-19 if order == 3 else 0.0))
+    xs, gaps = make_inputs(w, seed=7, injections=[inj])
+    print(f"\ncase: point and adjoint at spin order {order}", flush=True)
+    spins = np.array([[inj.fdot, inj.f2, inj.f3],
+                      [inj.fdot + 2e-12, inj.f2 - 2e-15, inj.f3 + 5e-20],
+                      [inj.fdot - 1e-11, inj.f2 + 4e-15, inj.f3 - 1e-19]])[:, :order]
+    th = np.column_stack([[inj.f0, inj.f0 + 0.3 * df, inj.f0 - 0.45 * df], spins,
+                          [inj.alpha, inj.alpha + 3e-4, inj.alpha - 1e-3],
+                          [inj.delta, inj.delta - 2e-4, inj.delta + 1e-3]])
+    plan = gpu_lib.Plan(w)
+    plan.set_spin_order(order)
+    tx, tg = to_gpu(xs, gaps)
+    g_in = torch.tensor([1.0, -0.5, 2.0], dtype=torch.float32).cuda()
+    twoF, gth = plan.backward(tx, tg, torch.from_numpy(th).cuda(), g_in)
+    pt = plan.point(tx, tg, torch.from_numpy(th).cuda()).cpu().numpy()
+    twoF, gth = twoF.cpu().numpy(), gth.cpu().numpy()
+    assert gth.shape == th.shape
+    prob = og.PointProblem(xs, gaps, w.segment, list(w.detectors), w.eph, w.kernel, w.taps)
+    ref = np.array([prob.twoF(t) for t in th])
+    assert np.all(np.abs(pt - ref) <= 1e-4 * np.maximum(ref, 4.0)), (pt, ref)
+    assert np.all(np.abs(twoF - ref) <= 1e-4 * np.maximum(ref, 4.0)), (twoF, ref)
+    assert ref[0] > 100.0                                  # the matched template sees the injection
+    T0 = w.segment.n * w.segment.dt
+    scale = np.array([1 / T0 ** (j + 1) for j in range(1 + order)] + [1e-5, 1e-5])
+    for i, t in enumerate(th):
+        rg = og.gradient(prob, t) * float(g_in[i])
+        gs, rs = gth[i] * scale, rg * scale
+        tol = 1e-3 * max(np.max(np.abs(rs)), 1.0)
+        assert np.all(np.abs(gs - rs) <= tol), (i, gs, rs)
+
+    # zero higher spindowns: the same values as order 1
+    th0 = th.copy()
+    th0[:, 2:1 + order] = 0.0
+    tt = torch.from_numpy(th0).cuda().requires_grad_(True)
+    F_s = gpu_lib.fstat_point(plan, tx, tg, tt)
+    F_s.sum().backward()
+    g_s = tt.grad.cpu().numpy()
+    assert g_s.shape == th.shape
+    plan.set_spin_order(1)
+    th1 = np.ascontiguousarray(th0[:, [0, 1, 1 + order, 2 + order]])
+    F_1, g_1 = plan.backward(tx, tg, torch.from_numpy(th1).cuda(), torch.ones(3, dtype=torch.float32).cuda())
+    F_s, F_1, g_1 = F_s.detach().cpu().numpy(), F_1.cpu().numpy(), g_1.cpu().numpy()
+    assert np.all(np.abs(F_s - F_1) <= 1e-5 * np.maximum(F_1, 4.0)), (F_s, F_1)
+    sc1 = scale[[0, 1, 1 + order, 2 + order]]
+    for i in range(3):
+        a, b = g_s[i, [0, 1, 1 + order, 2 + order]] * sc1, g_1[i] * sc1
+        assert np.all(np.abs(a - b) <= 1e-4 * max(np.max(np.abs(b)), 1.0)), (i, a, b)
     plan.close()

@@ -1,7 +1,8 @@
 """Spindown orders 2 and 3 (eq. eq4pt1 with s = 2, 3) on the GPU against the
 oracle: full-band 2F of templates (f^(1), f^(2)[, f^(3)]) within the FP32
 tolerance, recovery of an f^(2) injection, top-k at order 2, order 1 given
-as [n, 1] equal to [n], and the entries that take order 1 only."""
+as [n, 1] equal to [n], tensor widths checked against the order, and the
+semi-coherent sum, which takes order 1 only."""
 import numpy as np
 import pytest
 
@@ -57,8 +58,8 @@ def test_order_one_as_column_and_order_one_only_entries(gpu_lib):
     assert np.array_equal(a, b)
     plan.set_spin_order(2)
     theta = torch.tensor([[100.01, -1e-10, 0.7, 0.2]], dtype=torch.float64).cuda()
-    with pytest.raises(Exception, match="spin order 1 only"):
-        plan.point(tx, tg, theta)
+    with pytest.raises(ValueError, match=r"theta must be \[n, 5\]"):
+        plan.point(tx, tg, theta)                 # [n, 4] at order 2
     S = torch.zeros((4, 100), dtype=torch.float32, device="cuda")
     spins = torch.zeros((4, 2), dtype=torch.float64, device="cuda")
     with pytest.raises(Exception, match="spin order 1 only"):
