@@ -58,12 +58,17 @@ def parse():
 KERNEL_SOURCES = ("rsf_fft.hip", "rsf_spill.h", "rsf_device.h", "rsf_params.h", "rsf_resample.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_fft_T10d.md")
 PEAK_FP32_MFMA_TFLOPS = 157.3  # MI355X dense FP32 matrix
+# Vector-instruction issue: 256 CUs x 4 SIMDs, one wave64 VALU instruction per
+# SIMD every 4 cycles at 2.4 GHz (FP64 and unpacked FP32 alike).
+PEAK_VALU_ISSUE_G = 256 * 4 * 2.4 / 4  # 614.4 G wave instructions/s
+POINT_SOURCES = ("rsf_point.hip", "rsf_point_params.h", "rsf_device.h", "rsf_params.h")
+POINT_COUNTS_FILE = os.path.join(ROOT, "profiles", "pmc_point_grad_T10d.md")
 
 
-def kernel_source_hash():
+def kernel_source_hash(names=KERNEL_SOURCES):
     import hashlib
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
+    for name in names:
         with open(os.path.join(ROOT, "paper_0912_4255_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -83,6 +88,24 @@ def committed_traffic(kernel, config):
         f = ln.strip().strip("`").split()
         # traffic <kernel> <bytes per launch> src=<hash> cfg=<L1>x<L2>,fb<fb>,g<G>
         if len(f) == 5 and f[0] == "traffic" and f[1] == kernel and f[3] == "src=" + src and f[4] == "cfg=" + config:
+            return float(f[2])
+    return None
+
+
+def committed_point_valu(config):
+    """VALU wave instructions per candidate of the gradient point kernel from
+    the committed counter summary (SQ_INSTS_VALU), or None when it is missing,
+    was taken on another configuration, or the point kernel's sources have
+    changed since."""
+    try:
+        lines = open(POINT_COUNTS_FILE).read().splitlines()
+    except OSError:
+        return None
+    src = kernel_source_hash(POINT_SOURCES)
+    for ln in lines:
+        f = ln.strip().strip("`").split()
+        # valu_per_candidate rsf_point_k <instructions> src=<hash> cfg=<config>
+        if len(f) == 5 and f[0] == "valu_per_candidate" and f[3] == "src=" + src and f[4] == "cfg=" + config:
             return float(f[2])
     return None
 
@@ -152,10 +175,30 @@ def grad_leg(rsf, synth, torch, dev, n_cand, steps=20):
         th = th + step * gs / gs.abs().amax(dim=1, keepdim=True).clamp_min(1e-30)
     torch.cuda.synchronize()
     t_steps = time.perf_counter() - t0
+    # the point kernel's own duration (HIP events on the launch stream), and
+    # its vector-issue rate from the committed instruction count
+    plan.profile(True)
+    plan.profile_read()
+    plan.backward(tx, [None], theta, g1, ws=ws)
+    prof = plan.profile_read()
+    plan.profile(False)
+    n_c = int(theta.shape[0])
+    launches, ms = prof["rsf_point_k"]
+    k_s = ms * 1e-3 / launches
+    cfg = f"N{w.segment.n},grad,order1"
+    per_cand = committed_point_valu(cfg)
+    roof = {"bound": "alu", "kernel": "rsf_point_k", "avg_launch_us": round(k_s * 1e6, 1),
+            "unit": "G VALU wave-instructions/s", "peak": PEAK_VALU_ISSUE_G, "config": cfg,
+            "kernel_src": kernel_source_hash(POINT_SOURCES), "achieved": None, "frac": None}
+    if per_cand is not None:
+        rate = per_cand * n_c / k_s / 1e9
+        roof.update(achieved=round(rate, 1), frac=round(rate / PEAK_VALU_ISSUE_G, 4),
+                    valu_per_launch=per_cand * n_c)
     return {"workload": "T=10d dt=0.5s N=1728000, Dirichlet-16, synthetic noise",
-            "candidates": int(theta.shape[0]),
-            "candidates_per_s": round(theta.shape[0] / t_one, 1),
-            "refine_steps": steps, "refine_s": round(t_steps, 4)}
+            "candidates": n_c,
+            "candidates_per_s": round(n_c / t_one, 1),
+            "refine_steps": steps, "refine_s": round(t_steps, 4),
+            "roofline": roof}
 
 
 def c3_leg(rsf, synth, torch, dev, n_seg, n_sky, n_fdot=16, k=10):
