@@ -206,8 +206,8 @@ def fstat_point(rs_list, dets, seg, f, fdot):
     return twoF_from(np.sum(ya * e), np.sum(yb * e), A, B, C)
 
 
-def resample_all(xs, gaps_list, seg, alpha, delta, eph, dets, kernel, W):
-    return [resample(x, g, seg, alpha, delta, eph, d, kernel, W)
+def resample_all(xs, gaps_list, seg, alpha, delta, eph, dets, kernel, W, binary=None):
+    return [resample(x, g, seg, alpha, delta, eph, d, kernel, W, binary=binary)
             for x, g, d in zip(xs, gaps_list, dets)]
 
 

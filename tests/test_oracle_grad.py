@@ -86,3 +86,28 @@ def test_peak_has_zero_frequency_derivative():
     F = prob.twoF(theta)
     T0 = SEG.n * SEG.dt
     assert abs(g[0]) * (1.0 / T0) < 1e-6 * F
+
+
+def test_binary_gradient_zero_orbit_and_consistency():
+    """Binary theta (f, fdot, alpha, delta, a_p, P_b, t_asc): with a_p = 0 the
+    orbit drops out, so 2F and the first four derivatives equal the isolated
+    source's and the P_b, t_asc derivatives vanish exactly; on a real orbit
+    each orbital derivative agrees with plain central differences at two
+    step sizes."""
+    x_prob, inj = _problem(seed=4)
+    prob = og.PointProblem(x_prob.xs, x_prob.gaps, SEG, [DET_H], EPH, KERNEL_LANCZOS, 8, binary=True)
+    th4 = np.array([inj.f0 + 0.1 * DF, inj.fdot, inj.alpha + 1e-4, inj.delta])
+    g4 = og.gradient(x_prob, th4)
+    th7 = np.concatenate([th4, [0.0, 40000.0, 9.0e3]])
+    g7 = og.gradient(prob, th7)
+    assert prob.twoF(th7) == x_prob.twoF(th4)
+    assert np.allclose(g7[:4], g4, rtol=1e-9, atol=0)
+    assert g7[5] == 0.0 and g7[6] == 0.0 and g7[4] != 0.0
+    th = np.concatenate([th4, [0.8, 40000.0, 9.0e3]])
+    h = og.default_steps(SEG, 1, binary=True)
+    g = og.gradient(prob, th)
+    for i in (4, 5, 6):
+        c1 = og.central(prob.twoF, th, i, h[i])
+        c2 = og.central(prob.twoF, th, i, h[i] / 4)
+        assert abs(c1 - g[i]) < 1e-4 * abs(g[i]) + 1e-6, (i, c1, g[i])
+        assert abs(c2 - g[i]) < 1e-4 * abs(g[i]) + 1e-6, (i, c2, g[i])
