@@ -165,8 +165,10 @@ int rsf_plan_set_spin_order(rsf_plan* plan, int order);
  * resampled grid is then regular in emission time: T^k solves
  * T + t_m(T) = k dt + R(t_start + k dt), and the heterodyne correction and
  * the spindown phase use the total delay d = t_m - R(tau_e) in place of t_m.
- * The point and gradient entries take isolated sources only
- * (RSF_EUNSUPPORTED). */
+ * Every `theta` of rsf_fstat_point / rsf_fstat_backward then ends with the
+ * candidate's orbit, double [n][6 + s]: (f, f^(1), ..., f^(s), alpha, delta,
+ * a_p, P_b, t_asc), with a_p <= 100 light-s, and the gradient includes
+ * d2F/d(a_p, P_b, t_asc). */
 int rsf_plan_set_binary(rsf_plan* plan, int on);
 /* Batching knobs of RSF_MODE_BATCHED (0 = keep the automatic value):
  * fb = spindowns sharing one read of the resampled series in the first FFT
@@ -245,7 +247,8 @@ int rsf_fstat_semicoherent(const rsf_plan* plan, const rsf_segment* seg, const d
 
 /* 2F at continuous parameters: theta device float64[n][3 + s] = (f Hz,
  * f^(1) Hz/s, ..., f^(s) Hz/s^s, alpha, delta rad) at the plan's spindown
- * order s (1 by default: (f, fdot, alpha, delta));
+ * order s (1 by default: (f, fdot, alpha, delta)), followed by the orbit
+ * (a_p, P_b, t_asc) when the plan's sources are binary;
  * f_a(f) = sum_k y^a_k exp(-2 pi i (f - f_het) k dt) on the
  * resampled series of each candidate's own sky (equal to FFT bin s when
  * f = f_het + s df).  twoF: device float32[n]. */
@@ -253,13 +256,13 @@ int rsf_fstat_point(const rsf_plan* plan, const rsf_segment* seg, const double* 
                     float* twoF, void* ws, size_t ws_bytes, void* stream);
 
 /* Vector-Jacobian product of rsf_fstat_point: g_theta[i][:] = g_twoF[i] *
- * d2F/d(f, f^(1), ..., f^(s), alpha, delta) at theta[i], through the
+ * d2F/d(f, f^(1), ..., f^(s), alpha, delta[, a_p, P_b, t_asc]) at theta[i], through the
  * F-statistic, the Fourier sum, the spindown phase (including its
  * dependence on the sky through T and t_m), the interpolation, the heterodyne
  * correction, the beam patterns and the timing inversion (dT/dtheta =
  * -(dt_m/dtheta)/(1 + dt_m/dt)).  The resampled series is recomputed, never
  * stored.  g_twoF: device float32[n]; twoF: device float32[n] or NULL;
- * g_theta: device float64[n][3 + s]. */
+ * g_theta: device float64, the shape of theta. */
 int rsf_fstat_backward(const rsf_plan* plan, const rsf_segment* seg, const double* theta, int64_t n,
                        const float* g_twoF, float* twoF, double* g_theta,
                        void* ws, size_t ws_bytes, void* stream);

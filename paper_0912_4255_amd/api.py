@@ -82,10 +82,12 @@ class Plan:
         return fdot.shape[0]
 
     def _n_theta(self, theta):
-        """Candidates in a theta tensor [n, 3 + s] = (f, f^(1) .. f^(s), alpha, delta)."""
-        width = 3 + self.spin_order
+        """Candidates in a theta tensor [n, 3 + s] = (f, f^(1) .. f^(s), alpha,
+        delta), followed by (a_p, P_b, t_asc) when the plan's sources are binary."""
+        width = 3 + self.spin_order + (3 if self.binary else 0)
         if theta.dim() != 2 or theta.shape[1] != width:
-            raise ValueError(f"theta must be [n, {width}] at spin order {self.spin_order}")
+            raise ValueError(f"theta must be [n, {width}] at spin order {self.spin_order}"
+                             + (" with a binary orbit" if self.binary else ""))
         return theta.shape[0]
 
     def set_binary(self, on=True):
@@ -231,7 +233,8 @@ class Plan:
 
     def point(self, xs, gaps, theta, out=None, ws=None):
         """rsf_fstat_point: 2F [n] at continuous theta [n, 3 + s] =
-        (f, f^(1) .. f^(s), alpha, delta), s the spin order (1: (f, fdot, alpha, delta))."""
+        (f, f^(1) .. f^(s), alpha, delta), s the spin order (1: (f, fdot, alpha,
+        delta)); binary sources append (a_p, P_b, t_asc)."""
         _need_cuda(theta, torch.float64, "theta")
         n = self._n_theta(theta)
         seg, keep = self.segment(xs, gaps)
@@ -245,7 +248,7 @@ class Plan:
         return out
 
     def backward(self, xs, gaps, theta, g_twoF, ws=None):
-        """rsf_fstat_backward: (2F [n], g_twoF * d2F/dtheta [n, 3 + s])."""
+        """rsf_fstat_backward: (2F [n], g_twoF * d2F/dtheta, the width of theta)."""
         _need_cuda(theta, torch.float64, "theta")
         _need_cuda(g_twoF, torch.float32, "g_twoF")
         n = self._n_theta(theta)

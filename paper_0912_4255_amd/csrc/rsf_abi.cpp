@@ -916,7 +916,6 @@ int point_common(const rsf_plan* p, const rsf_segment* seg, const double* theta,
     if (!p) return fail(RSF_EINVAL, "plan is NULL");
     int rc = check_segment(p, seg);
     if (rc) return rc;
-    if (p->binary) return fail(RSF_EUNSUPPORTED, "point evaluation and its gradient take isolated sources only");
     if (!theta) return fail(RSF_EINVAL, "theta is NULL");
     if (n < 1 || n > 65535) return fail(RSF_EINVAL, "number of candidates must be in 1..65535");
     if (grad && (!g_twoF || !g_theta)) return fail(RSF_EINVAL, "g_twoF or g_theta is NULL");
@@ -924,11 +923,12 @@ int point_common(const rsf_plan* p, const rsf_segment* seg, const double* theta,
     if (!ws) return fail(RSF_EINVAL, "workspace is NULL");
     {
         // the point kernel turns the run's orbital and sidereal angles by
-        // w |delta| with |delta| <= 63 dt + max|t_m|; its series needs <= 0.3
-        const double span = 63.0 * p->d.dt + p->eph.au_c + p->eph.re_c;
+        // w |delta| with |delta| <= 63 dt + max|t_m| (+ a_p <= 100 s for a
+        // binary source); its series needs <= 0.3
+        const double span = 63.0 * p->d.dt + p->eph.au_c + p->eph.re_c + (p->binary ? 100.0 : 0.0);
         const double w_max = 2.0 * M_PI * std::max(std::fabs(p->eph.inv_p_sid), std::fabs(p->eph.inv_p_orb));
         if (!(w_max * span <= 0.3))
-            return fail(RSF_EINVAL, "point search needs (63 dt + max|t_m|) w_sid <= 0.3 (dt up to about 55 s)");
+            return fail(RSF_EINVAL, "point search needs (63 dt + max|t_m| + 100 s if binary) w_sid <= 0.3 (dt up to about 55 s)");
     }
     const PointLayout L = point_layout(p, n);
     if (ws_bytes < L.total) return fail(RSF_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, L.total);
@@ -952,6 +952,7 @@ int point_common(const rsf_plan* p, const rsf_segment* seg, const double* theta,
     a.ip = p->ip;
     a.theta = theta;
     a.order = p->spin_order;
+    a.binary = p->binary ? 1 : 0;
     a.n_cand = (int)n;
     a.P = (p->n + 63) / 64;
     a.n_blocks = L.n_blocks;
@@ -963,6 +964,7 @@ int point_common(const rsf_plan* p, const rsf_segment* seg, const double* theta,
     r.n_blocks = L.n_blocks;
     r.n_cand = (int)n;
     r.order = p->spin_order;
+    r.binary = p->binary ? 1 : 0;
     r.grad = grad ? 1 : 0;
     r.g_twoF = g_twoF;
     r.twoF = twoF;

@@ -1,6 +1,7 @@
 // 2F at continuous parameters and its gradient (project addition on top of
 // paper Sec. III.A.2): for every candidate theta = (f, f^(1), ..., f^(s),
-// alpha, delta) at spindown order s = 1..3 the resampled series of the
+// alpha, delta) at spindown order s = 1..3 (followed by the orbit (a_p, P_b,
+// t_asc) for a source in a circular binary orbit) the resampled series of the
 // candidate's own sky is recomputed on the fly
 // (never stored) and reduced to
 //   F_a = sum_k y^a_k exp(-2 pi i (f - f_het) t_b^k),   F_b likewise,
@@ -17,7 +18,14 @@
 //            dz_p/dtheta = -2 pi i f_het (dt_m/dtheta)(t_p) z_p (eq. absorb);
 //            the beam patterns change through p, q(alpha, delta) and T; the
 //            spindown phase through T at fixed t_b:
-//            dPhi_s/dT = 2 pi t_m sum_j f^(j) T^(j-1)/(j-1)!.
+//            dPhi_s/dT = 2 pi t_m sum_j f^(j) T^(j-1)/(j-1)!;
+//   * orbit: the inversion targets t_b + R(tau_e) (tau_e = t_start + t_b on
+//            the emission grid), so dT/dtheta_o = (dR/dtheta_o)/(1 + dt_m/dt);
+//            t_m is replaced by the total delay d = t_m - R(tau_e) (equal to
+//            t_b - T), and at a detector sample p the correction's delay
+//            d_p = t_m(t_p) - R(tau_e,p) with tau_e,p + R(tau_e,p) = tau_p +
+//            t_m(t_p) changes by -(dR/dtheta_o)/(1 + R') for the orbit and by
+//            (dt_m/dtheta)/(1 + R') for the sky, R' = dR/dtau at tau_e,p.
 // Each block accumulates FP64 partial sums over 8 tiles of 1024 samples;
 // rsf_point_reduce_k sums the blocks of a candidate in a fixed order and
 // forms 2F (eq. eq6) and the vector-Jacobian product g * d2F/dtheta.
@@ -35,19 +43,38 @@ constexpr int kThreads = 256;
 constexpr int kWinMax = kTileB + kMaxTaps + 8;
 constexpr float kPiF = 3.14159265358979323846f;
 
-// partial-sum slots at spindown order ORDER (3 + ORDER parameters)
-template <int ORDER>
+// partial-sum slots at spindown order ORDER: NP = 1 + ORDER + NS parameters,
+// the last NS of which (alpha, delta, and a_p, P_b, t_asc for a binary
+// source) move the resampled times and hence also A', B', C'
+template <int ORDER, bool BIN>
 struct Slots {
-    static constexpr int NP = 3 + ORDER;
+    static constexpr int NS = BIN ? 5 : 2;
+    static constexpr int NP = 1 + ORDER + NS;
     static constexpr int FA = 0, FB = 2, A = 4, B = 5, C = 6;
     static constexpr int DFA = 7;             // NP parameters x (re, im)
     static constexpr int DFB = DFA + 2 * NP;
-    static constexpr int DA = DFB + 2 * NP;   // (alpha, delta)
-    static constexpr int DB = DA + 2;
-    static constexpr int DC = DB + 2;
-    static constexpr int USED = DC + 2;
+    static constexpr int DA = DFB + 2 * NP;   // NS parameters each
+    static constexpr int DB = DA + NS;
+    static constexpr int DC = DB + NS;
+    static constexpr int USED = DC + NS;
 };
-static_assert(Slots<3>::USED <= kPointSums, "partial-sum stride too small");
+static_assert(Slots<3, true>::USED <= kPointSums, "partial-sum stride too small");
+
+// R(tau_e) of a circular orbit, with cos of its angle for the derivatives
+__device__ __forceinline__ double orbit_delay(const BinaryOrbit& b, double tau_e, double& s_phi, double& c_phi) {
+    const double cyc = (tau_e - b.t_asc) / b.p_orb;
+    sincos(2.0 * kPi * (cyc - floor(cyc)), &s_phi, &c_phi);
+    return b.a_p * s_phi;
+}
+
+// dR/d(a_p, P_b, t_asc) at tau_e from the angle's sin and cos
+__device__ __forceinline__ void orbit_partials(const BinaryOrbit& b, double tau_e, double s_phi, double c_phi,
+                                               double* dR) {
+    const double w = 2.0 * kPi / b.p_orb;
+    dR[0] = s_phi;
+    dR[1] = -b.a_p * c_phi * w * (tau_e - b.t_asc) / b.p_orb;
+    dR[2] = -b.a_p * c_phi * w;
+}
 
 // 1/j! for the spindown terms
 __device__ constexpr double kInvFact[5] = {1.0, 1.0, 0.5, 1.0 / 6.0, 1.0 / 24.0};
@@ -224,26 +251,29 @@ __device__ __forceinline__ void kernel_w(const InterpDev& ip, float x, float sx,
 
 }  // namespace
 
-template <bool GRAD, int ORDER>
+template <bool GRAD, int ORDER, bool BIN>
 __global__ __launch_bounds__(kThreads, 2) void rsf_point_k(PointArgs A) {
-    using SL = Slots<ORDER>;
+    using SL = Slots<ORDER, BIN>;
     constexpr int NP = SL::NP;
     constexpr int S_FA = SL::FA, S_FB = SL::FB, S_A = SL::A, S_B = SL::B, S_C = SL::C;
     constexpr int S_DFA = SL::DFA, S_DFB = SL::DFB, S_DA = SL::DA, S_DB = SL::DB, S_DC = SL::DC;
     constexpr int S_USED = SL::USED;
     constexpr int S_SKY = 2 * (1 + ORDER);  // offset of (alpha, delta) within S_DFA / S_DFB
-    __shared__ float4 win[4][kWinMax];  // z (re, im), 2 pi f_het dt_m/dalpha, 2 pi f_het dt_m/ddelta
+    __shared__ float4 win[4][kWinMax];  // z (re, im), 2 pi f_het dd_p/dalpha, 2 pi f_het dd_p/ddelta
+    __shared__ float4 wino[4][(BIN && GRAD) ? kWinMax : 1];  // 2 pi f_het dd_p/d(a_p, P_b, t_asc)
     __shared__ double red[4][kPointSums];
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int cand = blockIdx.y;
     const double* th = A.theta + (int64_t)NP * cand;
-    const double f = th[0], al = th[NP - 2], de = th[NP - 1];
+    const double f = th[0], al = th[1 + ORDER], de = th[2 + ORDER];
     double fs[ORDER];  // f^(1) .. f^(ORDER)
 #pragma unroll
     for (int i = 0; i < ORDER; ++i) fs[i] = th[1 + i];
     const double fd = fs[0];
+    BinaryOrbit bo{};
+    if constexpr (BIN) bo = BinaryOrbit{th[3 + ORDER], th[4 + ORDER], th[5 + ORDER]};
     double sa, ca, sd, cd;
     sincos(al, &sa, &ca);
     sincos(de, &sd, &cd);
@@ -294,14 +324,24 @@ __global__ __launch_bounds__(kThreads, 2) void rsf_point_k(PointArgs A) {
                 float frac = 0.f;
                 double T = tb, tm = 0.0, dTa = 0.0, dTd = 0.0;
                 double av = 0.0, bv = 0.0, daa = 0.0, dad = 0.0, dba = 0.0, dbd = 0.0;
+                double dTo[3] = {0.0, 0.0, 0.0}, dao[3] = {0.0, 0.0, 0.0}, dbo[3] = {0.0, 0.0, 0.0};
                 bool mk = false;
                 double T1 = 0.0;
                 RoemerD x0{}, xa{}, xd{};  // expansions of n0.r, n0_alpha.r, n0_delta.r about T1
                 if (valid) {
                     // eq. eq21: one fixed-point step and one Newton step (residual below 1e-12 s)
-                    const double dl = (double)lane * A.dt;  // offset from the run's first sample
+                    // a binary source's grid is regular in emission time: the
+                    // target is t_b + R(t_start + t_b)
+                    double tgt = tb, dRk[3] = {0.0, 0.0, 0.0};
+                    if constexpr (BIN) {
+                        double sp, cp;
+                        const double te = A.t_start + tb;
+                        tgt = tb + orbit_delay(bo, te, sp, cp);
+                        if (GRAD) orbit_partials(bo, te, sp, cp, dRk);
+                    }
+                    const double dl = (double)lane * A.dt + (BIN ? tgt - tb : 0.0);  // offset from the run's first sample
                     const double tm0 = dot3(n0, orbit_from(ra, dl, A.eph, D, wo, w_sid).r);
-                    T1 = tb - tm0;
+                    T1 = tgt - tm0;
                     const Orbit o1 = orbit_from(ra, dl - tm0, A.eph, D, wo, w_sid);
                     {
                         const double wo2 = 4.0 * kPi * kPi * A.eph.inv_p_orb * A.eph.inv_p_orb;
@@ -313,7 +353,7 @@ __global__ __launch_bounds__(kThreads, 2) void rsf_point_k(PointArgs A) {
                             xd = project(o1, n0d, A.eph, wo2, ws2, rez);
                         }
                     }
-                    const double dT = -(T1 + dot3(n0, o1.r) - tb) / (1.0 + dot3(n0, o1.v));
+                    const double dT = -(T1 + dot3(n0, o1.r) - tgt) / (1.0 + dot3(n0, o1.v));
                     T = T1 + dT;
                     // the orbit at T: positions moved by v dT, the sidereal angle turned by w_sid dT
                     Orbit o = o1;
@@ -361,6 +401,14 @@ __global__ __launch_bounds__(kThreads, 2) void rsf_point_k(PointArgs A) {
                         dba = upa * uq + up * uqa - vpa * vq - vp * vqa + bdT * dTa;
                         dad = -uq * uqd + vq * vqd + adT * dTd;
                         dbd = up * uqd - vp * vqd + bdT * dTd;
+                        if constexpr (BIN) {
+#pragma unroll
+                            for (int i = 0; i < 3; ++i) {
+                                dTo[i] = dRk[i] / (1.0 + tmdot);
+                                dao[i] = adT * dTo[i];
+                                dbo[i] = bdT * dTo[i];
+                            }
+                        }
                     }
                 }
                 // expansion point of t_m (and of its sky derivatives) for the
@@ -390,21 +438,37 @@ __global__ __launch_bounds__(kThreads, 2) void rsf_point_k(PointArgs A) {
                     for (int p = lane; p < wlen; p += 64) {
                         const int64_t jj = (int64_t)w0 + p;
                         float4 e = make_float4(0.f, 0.f, 0.f, 0.f);
+                        float4 eo = make_float4(0.f, 0.f, 0.f, 0.f);
                         if (jj >= 0 && jj < A.n) {
                             const float2 xv = A.x[X][jj];
                             const double dl = (double)jj * A.dt - t_ref;
-                            const double tmj = tm_expand(q0, dl);
+                            double tmj = tm_expand(q0, dl);
+                            double inv1r = 1.0;  // 1 / (1 + R') at this sample's emission time
+                            if constexpr (BIN) {
+                                // total delay d_p = t_m - R(tau_e), tau_e + R(tau_e) = tau_p + t_m
+                                const double te = emission_time(bo, A.t_start + (double)jj * A.dt + tmj);
+                                double sp, cp;
+                                tmj -= orbit_delay(bo, te, sp, cp);
+                                if (GRAD) {
+                                    inv1r = 1.0 / (1.0 + bo.a_p * cp * (2.0 * kPi / bo.p_orb));
+                                    double dR[3];
+                                    orbit_partials(bo, te, sp, cp, dR);
+                                    const double k = -2.0 * kPi * A.f_het * inv1r;
+                                    eo = make_float4((float)(k * dR[0]), (float)(k * dR[1]), (float)(k * dR[2]), 0.f);
+                                }
+                            }
                             const double cyc = A.f_het * tmj;
                             const float ph = (float)(cyc - rint(cyc));
                             const float s = __builtin_amdgcn_sinf(ph), c = __builtin_amdgcn_cosf(ph);  // revolutions
                             e.x = xv.x * c + xv.y * s;
                             e.y = xv.y * c - xv.x * s;
                             if (GRAD) {
-                                e.z = (float)(2.0 * kPi * A.f_het * tm_expand(qa, dl));
-                                e.w = (float)(2.0 * kPi * A.f_het * tm_expand(qd, dl));
+                                e.z = (float)(2.0 * kPi * A.f_het * tm_expand(qa, dl) * inv1r);
+                                e.w = (float)(2.0 * kPi * A.f_het * tm_expand(qd, dl) * inv1r);
                             }
                         }
                         win[wave][p] = e;
+                        if constexpr (BIN && GRAD) wino[wave][p] = eo;
                     }
                 }
                 if (any && !ok) overflow = true;
@@ -415,6 +479,7 @@ __global__ __launch_bounds__(kThreads, 2) void rsf_point_k(PointArgs A) {
                     // interpolation (and derivative pieces)
                     const float sf = __builtin_amdgcn_sinf(0.5f * frac), cf = __builtin_amdgcn_cosf(0.5f * frac);
                     float2 zt = make_float2(0.f, 0.f), s1 = zt, sza = zt, szd = zt;
+                    float2 szo[3] = {zt, zt, zt};
                     const int base = j - hw + 1 - w0;
                     for (int i = 1; i <= W; ++i) {
                         const float x = frac + (float)(hw - i);
@@ -451,6 +516,15 @@ __global__ __launch_bounds__(kThreads, 2) void rsf_point_k(PointArgs A) {
                             sza.y += w * zz.z * zz.y;
                             szd.x += w * zz.w * zz.x;
                             szd.y += w * zz.w * zz.y;
+                            if constexpr (BIN) {
+                                const float4 oo = wino[wave][base + i - 1];
+                                szo[0].x += w * oo.x * zz.x;
+                                szo[0].y += w * oo.x * zz.y;
+                                szo[1].x += w * oo.y * zz.x;
+                                szo[1].y += w * oo.y * zz.y;
+                                szo[2].x += w * oo.z * zz.x;
+                                szo[2].y += w * oo.z * zz.y;
+                            }
                         }
                     }
                     // total phase: spindown Phi_s and the Fourier kernel at f;
@@ -542,6 +616,25 @@ __global__ __launch_bounds__(kThreads, 2) void rsf_point_k(PointArgs A) {
                             acc[S_DC + 0] += w * (daa * bv + av * dba);
                             acc[S_DC + 1] += w * (dad * bv + av * dbd);
                         }
+                        if constexpr (BIN) {
+                            // the orbit moves T like the sky does, through dT/dtheta_o
+#pragma unroll
+                            for (int i = 0; i < 3; ++i) {
+                                const float dTo_u = (float)(dTo[i] / A.dt);
+                                const float dpo = (float)(2.0 * kPi * rate * tm * dTo[i]);
+                                const float dz_r = s1.x * dTo_u + szo[i].y, dz_i = s1.y * dTo_u - szo[i].x;
+                                const float eo_r = dz_r * c + dz_i * s, eo_i = dz_i * c - dz_r * s;
+                                acc[S_DFA + S_SKY + 4 + 2 * i] += w * (dao[i] * zer + av * eo_r + av * dpo * zei);
+                                acc[S_DFA + S_SKY + 5 + 2 * i] += w * (dao[i] * zei + av * eo_i - av * dpo * zer);
+                                acc[S_DFB + S_SKY + 4 + 2 * i] += w * (dbo[i] * zer + bv * eo_r + bv * dpo * zei);
+                                acc[S_DFB + S_SKY + 5 + 2 * i] += w * (dbo[i] * zei + bv * eo_i - bv * dpo * zer);
+                                if (mk) {
+                                    acc[S_DA + 2 + i] += w * 2.0 * av * dao[i];
+                                    acc[S_DB + 2 + i] += w * 2.0 * bv * dbo[i];
+                                    acc[S_DC + 2 + i] += w * (dao[i] * bv + av * dbo[i]);
+                                }
+                            }
+                        }
                     }
                 } else if (valid && !ok) {
                     acc[S_FA] = __longlong_as_double(0x7ff8000000000000LL);
@@ -573,9 +666,9 @@ __global__ __launch_bounds__(kThreads, 2) void rsf_point_k(PointArgs A) {
 // One workgroup per candidate: fixed-order sum of the block partials, then
 // 2F = 2Q/D with Q = B|Fa|^2 + A|Fb|^2 - 2C Re(Fa Fb^*), D = AB - C^2, and
 // d2F = 2 (dQ D - Q dD) / D^2.
-template <int ORDER>
+template <int ORDER, bool BIN>
 __global__ __launch_bounds__(256) void rsf_point_reduce_k(PointReduceArgs R) {
-    using SL = Slots<ORDER>;
+    using SL = Slots<ORDER, BIN>;
     constexpr int NP = SL::NP;
     constexpr int S_FA = SL::FA, S_FB = SL::FB, S_A = SL::A, S_B = SL::B, S_C = SL::C;
     constexpr int S_DFA = SL::DFA, S_DFB = SL::DFB, S_DA = SL::DA, S_DB = SL::DB, S_DC = SL::DC;
@@ -612,8 +705,8 @@ __global__ __launch_bounds__(256) void rsf_point_reduce_k(PointReduceArgs R) {
     for (int i = 0; i < NP; ++i) {
         const double dar = tot[S_DFA + 2 * i], dai = tot[S_DFA + 2 * i + 1];
         const double dbr = tot[S_DFB + 2 * i], dbi = tot[S_DFB + 2 * i + 1];
-        // the antenna sums depend on the sky only (the last two parameters)
-        const int k = i - (NP - 2);
+        // the antenna sums depend only on the parameters that move T (the last NS)
+        const int k = i - (NP - SL::NS);
         const double dA = (k >= 0) ? tot[S_DA + k] : 0.0;
         const double dB = (k >= 0) ? tot[S_DB + k] : 0.0;
         const double dC = (k >= 0) ? tot[S_DC + k] : 0.0;
@@ -630,14 +723,20 @@ int point_blocks(int64_t P) { return (int)((P + kTileA * kPointTiles - 1) / (kTi
 
 hipError_t launch_point(const PointArgs& a, bool grad, hipStream_t s) {
     const dim3 grid((unsigned)a.n_blocks, (unsigned)a.n_cand);
-#define RSF_POINT(G, O) hipLaunchKernelGGL((rsf_point_k<G, O>), grid, dim3(kThreads), 0, s, a)
-    switch (a.order * 2 + (grad ? 1 : 0)) {
-        case 2: RSF_POINT(false, 1); break;
-        case 3: RSF_POINT(true, 1); break;
-        case 4: RSF_POINT(false, 2); break;
-        case 5: RSF_POINT(true, 2); break;
-        case 6: RSF_POINT(false, 3); break;
-        case 7: RSF_POINT(true, 3); break;
+#define RSF_POINT(G, O, B) hipLaunchKernelGGL((rsf_point_k<G, O, B>), grid, dim3(kThreads), 0, s, a)
+    switch (a.order * 4 + (a.binary ? 2 : 0) + (grad ? 1 : 0)) {
+        case 4: RSF_POINT(false, 1, false); break;
+        case 5: RSF_POINT(true, 1, false); break;
+        case 6: RSF_POINT(false, 1, true); break;
+        case 7: RSF_POINT(true, 1, true); break;
+        case 8: RSF_POINT(false, 2, false); break;
+        case 9: RSF_POINT(true, 2, false); break;
+        case 10: RSF_POINT(false, 2, true); break;
+        case 11: RSF_POINT(true, 2, true); break;
+        case 12: RSF_POINT(false, 3, false); break;
+        case 13: RSF_POINT(true, 3, false); break;
+        case 14: RSF_POINT(false, 3, true); break;
+        case 15: RSF_POINT(true, 3, true); break;
         default: return hipErrorInvalidValue;
     }
 #undef RSF_POINT
@@ -646,12 +745,17 @@ hipError_t launch_point(const PointArgs& a, bool grad, hipStream_t s) {
 
 hipError_t launch_point_reduce(const PointReduceArgs& r, hipStream_t s) {
     const dim3 grid((unsigned)r.n_cand);
-    switch (r.order) {
-        case 1: hipLaunchKernelGGL(rsf_point_reduce_k<1>, grid, dim3(256), 0, s, r); break;
-        case 2: hipLaunchKernelGGL(rsf_point_reduce_k<2>, grid, dim3(256), 0, s, r); break;
-        case 3: hipLaunchKernelGGL(rsf_point_reduce_k<3>, grid, dim3(256), 0, s, r); break;
+#define RSF_POINT_REDUCE(O, B) hipLaunchKernelGGL((rsf_point_reduce_k<O, B>), grid, dim3(256), 0, s, r)
+    switch (r.order * 2 + (r.binary ? 1 : 0)) {
+        case 2: RSF_POINT_REDUCE(1, false); break;
+        case 3: RSF_POINT_REDUCE(1, true); break;
+        case 4: RSF_POINT_REDUCE(2, false); break;
+        case 5: RSF_POINT_REDUCE(2, true); break;
+        case 6: RSF_POINT_REDUCE(3, false); break;
+        case 7: RSF_POINT_REDUCE(3, true); break;
         default: return hipErrorInvalidValue;
     }
+#undef RSF_POINT_REDUCE
     return hipGetLastError();
 }
 

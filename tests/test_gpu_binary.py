@@ -1,4 +1,5 @@
-"""Sources in circular binary orbits on the GPU against the oracle.
+"""Sources in circular binary orbits on the GPU against the oracle: the
+resampling, the full-band search, and the point 2F with its adjoint.
 
 Bars as for isolated sources: the total delay d (stored t_m) within 1e-9 s,
 a, b within 1e-6, z~ within 2e-5 of the series rms, the SSB mask exact, A',
@@ -83,8 +84,81 @@ def test_fstat_parity_and_recovery_binary(gpu_lib):
     vals, ids = plan.topk(tx, tg, ts, tf, k=3)
     assert tuple(ids.cpu().numpy()[0]) == (0, 0, 2800 - plan.s_lo)
     theta = torch.tensor([[inj.f0, inj.fdot, 1.2, 0.3]], dtype=torch.float64).cuda()
-    with pytest.raises(Exception, match="isolated sources only"):
-        plan.point(tx, tg, theta)
+    with pytest.raises(ValueError, match=r"theta must be \[n, 7\]"):
+        plan.point(tx, tg, theta)                 # a binary plan's theta carries the orbit
     with pytest.raises(ValueError):
         plan.fstat(tx, tg, ts[:, :2].contiguous(), tf)
+    plan.close()
+
+
+def test_point_and_adjoint_binary(gpu_lib):
+    """Point 2F and its adjoint for a binary source, theta = (f, fdot, alpha,
+    delta, a_p, P_b, t_asc): 2F within 1e-4 max(2F, 4) of the oracle; the
+    gradient against the oracle's finite differences, the first four
+    components scaled by (1/T0, 1/T0^2, 1e-5, 1e-5) within 1e-3 of their
+    largest, the orbital ones scaled by (1e-3, 1, 10) within 2e-3 of theirs.
+    A zero orbit reproduces the isolated source, with vanishing P_b and t_asc
+    derivatives.  At spin order 2 the point 2F also matches."""
+    import torch
+    from oracle import grad as og
+    w = synth.small_workload(n=21600, dt=4.0, kernel=synth.KERNEL_DIRICHLET, taps=16, t_start=1.0e5)
+    rng = np.random.default_rng(3)
+    w.gaps = [synth.random_gaps(rng, w.segment.n, 500, 3)]
+    df = 1.0 / (2 * w.segment.n * w.segment.dt)
+    orb = ORBITS[0]
+    inj = Injection(h0=1.5, cosi=0.2, psi=-0.3, phi0=2.0, f0=w.segment.f_het + 2200.3 * df, fdot=-4e-10,
+                    alpha=2.1, delta=-0.4, binary=orb)
+    xs, gaps = make_inputs(w, seed=7, injections=[inj])
+    print("\ncase: binary point and adjoint, order 1", flush=True)
+    th = np.array([[inj.f0, inj.fdot, inj.alpha, inj.delta, orb.a_p, orb.p_orb, orb.t_asc],
+                   [inj.f0 + 0.3 * df, inj.fdot + 2e-12, inj.alpha + 3e-4, inj.delta - 2e-4,
+                    orb.a_p + 2e-4, orb.p_orb - 3.0, orb.t_asc + 5.0],
+                   [inj.f0 - 0.45 * df, inj.fdot - 1e-11, inj.alpha - 1e-3, inj.delta + 1e-3,
+                    orb.a_p - 5e-4, orb.p_orb + 8.0, orb.t_asc - 12.0]])
+    plan = gpu_lib.Plan(w)
+    plan.set_binary(True)
+    tx, tg = to_gpu(xs, gaps)
+    g_in = torch.tensor([1.0, -0.5, 2.0], dtype=torch.float32).cuda()
+    pt = plan.point(tx, tg, torch.from_numpy(th).cuda()).cpu().numpy()
+    twoF, gth = plan.backward(tx, tg, torch.from_numpy(th).cuda(), g_in)
+    twoF, gth = twoF.cpu().numpy(), gth.cpu().numpy()
+    assert gth.shape == th.shape
+    prob = og.PointProblem(xs, gaps, w.segment, list(w.detectors), w.eph, w.kernel, w.taps, binary=True)
+    ref = np.array([prob.twoF(t) for t in th])
+    assert np.all(np.abs(pt - ref) <= 1e-4 * np.maximum(ref, 4.0)), (pt, ref)
+    assert np.all(np.abs(twoF - ref) <= 1e-4 * np.maximum(ref, 4.0)), (twoF, ref)
+    assert ref[0] > 100.0
+    T0 = w.segment.n * w.segment.dt
+    sc_main = np.array([1 / T0, 1 / T0 ** 2, 1e-5, 1e-5])
+    sc_orb = np.array([1e-3, 1.0, 10.0])
+    for i, t in enumerate(th):
+        rg = og.gradient(prob, t) * float(g_in[i])
+        gm, rm = gth[i, :4] * sc_main, rg[:4] * sc_main
+        assert np.all(np.abs(gm - rm) <= 1e-3 * max(np.max(np.abs(rm)), 1.0)), (i, gm, rm)
+        go, ro = gth[i, 4:] * sc_orb, rg[4:] * sc_orb
+        assert np.all(np.abs(go - ro) <= 2e-3 * max(np.max(np.abs(ro)), 1.0)), (i, go, ro)
+        print(f"candidate {i}: 2F {pt[i]:.3f}, orbital gradient {go} vs {ro}", flush=True)
+
+    # zero orbit: the isolated source's values
+    th0 = th.copy()
+    th0[:, 4] = 0.0
+    F_b, g_b = plan.backward(tx, tg, torch.from_numpy(th0).cuda(), torch.ones(3, dtype=torch.float32).cuda())
+    plan.set_binary(False)
+    F_i, g_i = plan.backward(tx, tg, torch.from_numpy(np.ascontiguousarray(th0[:, :4])).cuda(),
+                             torch.ones(3, dtype=torch.float32).cuda())
+    F_b, g_b, F_i, g_i = F_b.cpu().numpy(), g_b.cpu().numpy(), F_i.cpu().numpy(), g_i.cpu().numpy()
+    assert np.all(np.abs(F_b - F_i) <= 1e-5 * np.maximum(F_i, 4.0)), (F_b, F_i)
+    for i in range(3):
+        a, b = g_b[i, :4] * sc_main, g_i[i] * sc_main
+        assert np.all(np.abs(a - b) <= 1e-4 * max(np.max(np.abs(b)), 1.0)), (i, a, b)
+    assert np.all(g_b[:, 5:] == 0.0)
+
+    # spin order 2 with the orbit
+    print("case: binary point, order 2", flush=True)
+    plan.set_binary(True)
+    plan.set_spin_order(2)
+    th2 = np.column_stack([th[:, :2], [3e-15, -2e-15, 0.0], th[:, 2:]])
+    pt2 = plan.point(tx, tg, torch.from_numpy(th2).cuda()).cpu().numpy()
+    ref2 = np.array([prob.twoF(t) for t in th2])
+    assert np.all(np.abs(pt2 - ref2) <= 1e-4 * np.maximum(ref2, 4.0)), (pt2, ref2)
     plan.close()
