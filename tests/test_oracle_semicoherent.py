@@ -78,3 +78,65 @@ def test_injection_seen_by_three_segments_peaks_at_f0():
     assert S[0, 0, j] > 0.9 * sum(peaks)
     # without the spindown only the first segment's peak sits on f0's track
     assert S[0, 1, j] < 0.6 * sum(peaks)
+
+
+def test_spindown_translation_is_the_taylor_identity():
+    """Moving (f0, f^(1..3)) from 0 to D reproduces the phase polynomial
+    phi(t) = f0 t + sum_k f^(k) t^(k+1)/(k+1)! about D: phi(D + tau) =
+    phi(D) + f(D) tau + sum_j f^(j)(D) tau^(j+1)/(j+1)!, written out here
+    term by term."""
+    f0, spins = 100.25, np.array([-3e-9, 4e-15, -2e-21])
+    D = 2.5e5
+    tr = sc.translate_spindowns(spins, D)
+    fD = f0 + sc.frequency_shift(spins, D)
+
+    def phi(t):
+        return f0 * t + spins[0] * t ** 2 / 2 + spins[1] * t ** 3 / 6 + spins[2] * t ** 4 / 24
+
+    for tau in (-3.1e4, 1.7e3, 8.6e4):
+        moved = phi(D) + fD * tau + tr[0] * tau ** 2 / 2 + tr[1] * tau ** 3 / 6 + tr[2] * tau ** 4 / 24
+        assert abs(moved - phi(D + tau)) <= 1e-12 * abs(phi(D + tau))
+    assert tr[2] == spins[2]
+    # order 1: the translation is the identity and the shift fdot D
+    assert sc.translate_spindowns([-3e-9], D)[0] == -3e-9
+    assert sc.frequency_shift(-3e-9, D) == -3e-9 * D
+
+
+def test_second_order_injection_seen_by_three_segments_peaks_at_f0():
+    """An f^(2) source (f^(2) D^2 / 2 is 0.7 and 2.8 bins at the second and
+    third segment starts) summed over three segments with order-2 templates, each segment
+    demodulated with the spindowns moved to its start: the track with the
+    true (fdot, f^(2)) peaks at f0 with nearly all of the segments' power;
+    without f^(2), f0's track collects much less and no track collects as
+    much."""
+    n, dt = 2400, 4.0
+    fdot, f2 = -3e-9, 2e-14
+    f0 = 100.0 + 37.0 / (2 * n * dt)
+    t_ref = 0.0
+    starts = [0.0, 60000.0, 120000.0]
+    grid = np.array([[fdot, f2], [fdot, 0.0]])
+    S, peaks = None, []
+    for i, t0 in enumerate(starts):
+        w = synth.small_workload(n=n, dt=dt, t_start=t0)
+        moved = sc.translate_spindowns([fdot, f2], t0 - t_ref)
+        inj = Injection(h0=4.0, cosi=0.3, psi=0.2, phi0=0.5 + i, f0=f0 + sc.frequency_shift([fdot, f2], t0 - t_ref),
+                        fdot=moved[0], f2=moved[1], alpha=1.0, delta=0.4)
+        xs, gaps = make_inputs(w, seed=50 + i, injections=[inj])
+        rs = [of.resample(xs[0], gaps[0], w.segment, 1.0, 0.4, w.eph, w.detectors[0], w.kernel, w.taps)]
+        n_fft = of.fft_length(n, of.NFFT_TWICE)
+        df = 1.0 / (n_fft * dt)
+        s_lo, n_out = -n_fft // 2, n_fft
+        maps = np.stack([of.fstat_band(rs, w.detectors, tuple(sc.translate_spindowns(g, t0 - t_ref)),
+                                       n_fft, s_lo, n_out) for g in grid])[None]
+        peaks.append(maps[0, 0].max())
+        if S is None:
+            f_lo, df_c, n_c = 99.99, df / 2, 2400
+            S = np.zeros((1, 2, n_c))
+        sc.accumulate_segment(S, maps, s_lo, n_out, 100.0, df, t0, grid, t_ref, f_lo, df_c)
+    j = int(np.argmax(S[0, 0]))
+    assert abs((f_lo + j * df_c) - f0) <= df_c
+    assert S[0, 0, j] > 0.9 * sum(peaks)
+    # without f^(2) the segments' peaks leave f0's track, and no other
+    # frequency gathers as much as the true track
+    assert S[0, 1, j] < 0.7 * S[0, 0, j]
+    assert S[0, 1].max() < S[0, 0, j]
