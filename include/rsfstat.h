@@ -152,8 +152,9 @@ int rsf_plan_destroy(rsf_plan* plan);
  * (f^(1), ..., f^(s)) of template i, and
  * Phi_s = 2 pi sum_j f^(j) (T^{j+1}/(j+1)! + t_m T^j/j!), and every `theta`
  * of rsf_fstat_point / rsf_fstat_backward is double [n][3 + s]:
- * (f, f^(1), ..., f^(s), alpha, delta).  The semi-coherent sum takes order 1
- * only (RSF_EUNSUPPORTED). */
+ * (f, f^(1), ..., f^(s), alpha, delta).  The semi-coherent sum takes its
+ * templates' spindowns at t_ref and moves them to each segment's start
+ * (see rsf_fstat_semicoherent). */
 int rsf_plan_set_spin_order(rsf_plan* plan, int order);
 
 /* Sources in circular binary orbits (on != 0; default off).  Every `sky`
@@ -235,6 +236,10 @@ int rsf_fstat_topk(const rsf_plan* plan, const rsf_segment* seg, const double* s
  * each template's frequency track.  Template (sky, f0, fdot) has f0 at the
  * reference time t_ref (seconds, the clock of t_start); this segment, whose
  * phase reference is its start t_start, sees f = f0 + fdot (t_start - t_ref)
+ * (at spin order s: f = f0 + sum_k f^(k) D^k / k!, D = t_start - t_ref, the
+ * terms formed and added in order of k in FP64 without fused multiply-adds,
+ * and the segment demodulates with f^(j)(t_start) = sum_{k >= j} f^(k)
+ * D^(k-j) / (k-j)!, computed into the workspace)
  * and adds its 2F at the nearest bin floor((f - f_het) / df + 1/2) (FP64),
  * nothing when that bin is outside its reported band.  Common grid
  * f0_j = f_lo + j df_c, j < n_c.  S: float [n_sky * n_fdot][n_c] (device,

@@ -211,7 +211,7 @@ namespace {
 
 struct WsLayout {
     size_t flags, rs_main[RSF_MAX_DET], rs_tm[RSF_MAX_DET], partials, coef, abc_w, spill, map, cand, run, mtmp[2],
-        total;
+        spins, total;
     int n_blocks;
     int64_t G;        // templates per FFT launch
     int64_t S;        // sky positions per resampling chunk
@@ -245,7 +245,9 @@ hipError_t topk_merge_levels(const rsf_plan* p, hipStream_t s, const TopkItem* c
                              const TopkItem* run_in, TopkItem* run_out, int k, int64_t n_fdot, void* entries,
                              TopkItem* const tmp[2]);
 
-WsLayout fstat_layout(const rsf_plan* p, int64_t n_sky, int64_t n_fdot, int mode, bool topk) {
+// spins: room for the call's spindowns moved to the segment start (the
+// semi-coherent sum at spin order > 1)
+WsLayout fstat_layout(const rsf_plan* p, int64_t n_sky, int64_t n_fdot, int mode, bool topk, bool spins = false) {
     WsLayout L{};
     size_t off = 0;
     L.flags = off;
@@ -285,6 +287,10 @@ WsLayout fstat_layout(const rsf_plan* p, int64_t n_sky, int64_t n_fdot, int mode
             L.mtmp[i] = off;
             off = align_up(off + (size_t)b1 * kTopkMax * sizeof(TopkItem));
         }
+    }
+    if (spins) {
+        L.spins = off;
+        off = align_up(off + (size_t)n_fdot * p->spin_order * sizeof(double));
     }
     L.total = off;
     return L;
@@ -597,8 +603,10 @@ int rsf_workspace_size(const rsf_plan* p, int entry, int64_t n_sky, int64_t n_fd
             *bytes = fstat_layout(p, n_sky, n_fdot, mode, false).total;
             return RSF_OK;
         case RSF_ENTRY_TOPK:
-        case RSF_ENTRY_SEMICOHERENT:
             *bytes = fstat_layout(p, n_sky, n_fdot, RSF_MODE_BATCHED, true).total;
+            return RSF_OK;
+        case RSF_ENTRY_SEMICOHERENT:
+            *bytes = fstat_layout(p, n_sky, n_fdot, RSF_MODE_BATCHED, true, p->spin_order > 1).total;
             return RSF_OK;
         case RSF_ENTRY_POINT:
         case RSF_ENTRY_BACKWARD:
@@ -685,12 +693,22 @@ int run_fstat(const rsf_plan* p, const rsf_segment* seg, const double* sky, int6
     if (mode != RSF_MODE_PLAIN && mode != RSF_MODE_BATCHED) return fail(RSF_EINVAL, "unknown mode");
     if (want_topk && (k < 1 || k > kTopkMax)) return fail(RSF_EINVAL, "k must be in 1..%d", kTopkMax);
     if (!ws) return fail(RSF_EINVAL, "workspace is NULL");
-    const WsLayout L = fstat_layout(p, n_sky, n_fdot, mode, want_map);
+    const bool translate = semico != nullptr && p->spin_order > 1;
+    const WsLayout L = fstat_layout(p, n_sky, n_fdot, mode, want_map, translate);
     if (ws_bytes < L.total) return fail(RSF_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, L.total);
     hipStream_t s = (hipStream_t)stream;
     char* w = (char*)ws;
     unsigned int* flags = (unsigned int*)(w + L.flags);
     RSF_HIP(launch_fill_u32(flags, 16, 0u, s), "flags clear");
+    // the segment demodulates with the templates' spindowns moved from t_ref
+    // to its start; the semi-coherent track reads the originals
+    const double* fdot_demod = fdot;
+    if (translate) {
+        double* moved = (double*)(w + L.spins);
+        RSF_HIP(launch_spin_translate(fdot, moved, n_fdot, p->spin_order, p->d.t_start - semico->t_ref, s),
+                "spindown translation launch");
+        fdot_demod = moved;
+    }
     const int fb = first_pass_share(p, mode);
     float4* spill = (float4*)(w + L.spill);
     const int64_t spill_stride = (int64_t)p->n_groups * p->LB * kPassBCols;
@@ -764,7 +782,7 @@ int run_fstat(const rsf_plan* p, const rsf_segment* seg, const double* sky, int6
             }
             A.rs_sky_stride = L.rs_stride;
             A.f16 = f16;
-            A.fdot = fdot + q.f0 * p->spin_order;
+            A.fdot = fdot_demod + q.f0 * p->spin_order;
             A.spin_order = p->spin_order;
             A.nf_l = q.nf;
             A.n_sky_l = q.ns;
@@ -817,6 +835,7 @@ int run_fstat(const rsf_plan* p, const rsf_segment* seg, const double* sky, int6
                 sa.df_c = semico->df_c;
                 sa.n_c = semico->n_c;
                 sa.fdot = fdot;
+                sa.order = p->spin_order;
                 sa.sky0 = B.sky0;
                 sa.n_fdot = n_fdot;
                 sa.f0 = q.f0;
@@ -895,7 +914,6 @@ int rsf_fstat_semicoherent(const rsf_plan* p, const rsf_segment* seg, const doub
                            const double* fdot, int64_t n_fdot, double t_ref, double f_lo, double df_c, int64_t n_c,
                            float* S, void* ws, size_t ws_bytes, void* stream) {
     if (!S) return fail(RSF_EINVAL, "S is NULL");
-    if (p && p->spin_order != 1) return fail(RSF_EUNSUPPORTED, "the semi-coherent sum takes spin order 1 only");
     if (!is_fin(t_ref) || !is_fin(f_lo) || !is_fin(df_c) || df_c <= 0)
         return fail(RSF_EINVAL, "t_ref, f_lo and df_c must be finite and df_c positive");
     if (n_c < 1 || n_c > INT32_MAX * 256LL) return fail(RSF_EINVAL, "n_c out of range");

@@ -6,6 +6,7 @@
 #include "rsf_front_params.h"
 #include "rsf_params.h"
 #include "rsf_point_params.h"
+#include "rsf_semico_params.h"
 
 namespace rsf {
 
@@ -26,6 +27,8 @@ hipError_t launch_topk_merge(const TopkMergeArgs& a, hipStream_t s);
 int topk_merge_per_block();
 hipError_t launch_fill_u32(unsigned int* p, int n, unsigned int v, hipStream_t s);
 hipError_t launch_semico(const SemicoArgs& a, hipStream_t s);
+// spindowns [n][order] moved by D seconds along their Taylor series
+hipError_t launch_spin_translate(const double* in, double* out, int64_t n, int order, double D, hipStream_t s);
 size_t hetdec_lds(int L, int D);
 hipError_t launch_hetdec(const HetdecArgs& a, int n_cu, hipStream_t s);  // n_cu: persistent grid of the D = 64 form
 hipError_t hetdec_set_lds_limit(size_t bytes);

@@ -195,19 +195,4 @@ struct TopkMergeArgs {
     void* entries;            // rsf_topk_entry[k] written if not null
 };
 
-// Semi-coherent sum: template t = s nf_l + f of a launch adds its 2F at the
-// bin nearest f_lo + j df_c + fdot (t_seg - t_ref) to S[row][j].
-struct SemicoArgs {
-    const float* map;         // [n_tmpl][n_out] rows of the launch
-    int64_t n_out, s_lo;
-    double f_het, df;         // segment grid: bin s at f_het + s df
-    double t_seg, t_ref;
-    double f_lo, df_c;        // common grid
-    int64_t n_c;
-    const double* fdot;       // the call's spindowns
-    int64_t sky0, n_fdot, f0;
-    int nf_l, n_tmpl;
-    float* S;                 // [n_sky * n_fdot][n_c], accumulated
-};
-
 }  // namespace rsf

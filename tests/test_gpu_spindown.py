@@ -1,8 +1,7 @@
 """Spindown orders 2 and 3 (eq. eq4pt1 with s = 2, 3) on the GPU against the
 oracle: full-band 2F of templates (f^(1), f^(2)[, f^(3)]) within the FP32
 tolerance, recovery of an f^(2) injection, top-k at order 2, order 1 given
-as [n, 1] equal to [n], tensor widths checked against the order, and the
-semi-coherent sum, which takes order 1 only."""
+as [n, 1] equal to [n], and tensor widths checked against the order."""
 import numpy as np
 import pytest
 
@@ -61,9 +60,8 @@ def test_order_one_as_column_and_order_one_only_entries(gpu_lib):
     with pytest.raises(ValueError, match=r"theta must be \[n, 5\]"):
         plan.point(tx, tg, theta)                 # [n, 4] at order 2
     S = torch.zeros((4, 100), dtype=torch.float32, device="cuda")
-    spins = torch.zeros((4, 2), dtype=torch.float64, device="cuda")
-    with pytest.raises(Exception, match="spin order 1 only"):
-        plan.semicoherent(tx, tg, sky, spins, S, 0.0, 99.9, 1e-4)
+    with pytest.raises(ValueError):
+        plan.semicoherent(tx, tg, sky, fd, S, 0.0, 99.9, 1e-4)  # [n] at order 2
     with pytest.raises(ValueError):
         plan.fstat(tx, tg, sky, fd)        # [n] at order 2
     plan.close()
