@@ -251,8 +251,11 @@ __device__ __forceinline__ void kernel_w(const InterpDev& ip, float x, float sx,
 
 }  // namespace
 
+// The binary gradient's 50 to 58 FP64 partial sums do not fit beside the rest
+// at two waves per SIMD; at one wave per SIMD its spills go to the
+// accumulation registers instead of scratch memory.
 template <bool GRAD, int ORDER, bool BIN>
-__global__ __launch_bounds__(kThreads, 2) void rsf_point_k(PointArgs A) {
+__global__ __launch_bounds__(kThreads, (BIN && GRAD) ? 1 : 2) void rsf_point_k(PointArgs A) {
     using SL = Slots<ORDER, BIN>;
     constexpr int NP = SL::NP;
     constexpr int S_FA = SL::FA, S_FB = SL::FB, S_A = SL::A, S_B = SL::B, S_C = SL::C;
@@ -648,7 +651,9 @@ __global__ __launch_bounds__(kThreads, 2) void rsf_point_k(PointArgs A) {
     if (overflow && lane == 0) atomicOr(A.flags, 2u);
 
     // block reduction in a fixed order
-    const int nsum = GRAD ? S_USED : S_DFA;
+    // unrolled: a loop-indexed acc would live in scratch memory
+    constexpr int nsum = GRAD ? S_USED : S_DFA;
+#pragma unroll
     for (int i = 0; i < nsum; ++i) {
         double v = acc[i];
 #pragma unroll
