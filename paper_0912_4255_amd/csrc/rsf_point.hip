@@ -67,6 +67,25 @@ __device__ __forceinline__ double orbit_delay(const BinaryOrbit& b, double tau_e
     return b.a_p * s_phi;
 }
 
+// tau_e with tau_e + R(tau_e) = tau by two Newton steps from tau - R(tau):
+// the start is off by at most max R' times max R (at most 1e-2 a_p), and each
+// step squares the error times (2 pi / P_b)^2 a_p / 2, so two steps reach
+// rounding for every admitted orbit.  The angle's sin and cos at the result
+// come from those of the last evaluation turned by the last step (first order).
+__device__ __forceinline__ double emission_newton(const BinaryOrbit& b, double tau, double& s_phi, double& c_phi) {
+    const double w = 2.0 * kPi / b.p_orb;
+    double te = tau - orbit_delay(b, tau, s_phi, c_phi);
+    double r = orbit_delay(b, te, s_phi, c_phi);
+    te -= (te + r - tau) / (1.0 + b.a_p * w * c_phi);
+    r = orbit_delay(b, te, s_phi, c_phi);
+    const double d = (te + r - tau) / (1.0 + b.a_p * w * c_phi);
+    te -= d;
+    const double s = s_phi - c_phi * (w * d), c = c_phi + s_phi * (w * d);
+    s_phi = s;
+    c_phi = c;
+    return te;
+}
+
 // dR/d(a_p, P_b, t_asc) at tau_e from the angle's sin and cos
 __device__ __forceinline__ void orbit_partials(const BinaryOrbit& b, double tau_e, double s_phi, double c_phi,
                                                double* dR) {
@@ -449,9 +468,9 @@ __global__ __launch_bounds__(kThreads, (BIN && GRAD) ? 1 : 2) void rsf_point_k(P
                             double inv1r = 1.0;  // 1 / (1 + R') at this sample's emission time
                             if constexpr (BIN) {
                                 // total delay d_p = t_m - R(tau_e), tau_e + R(tau_e) = tau_p + t_m
-                                const double te = emission_time(bo, A.t_start + (double)jj * A.dt + tmj);
                                 double sp, cp;
-                                tmj -= orbit_delay(bo, te, sp, cp);
+                                const double te = emission_newton(bo, A.t_start + (double)jj * A.dt + tmj, sp, cp);
+                                tmj -= bo.a_p * sp;
                                 if (GRAD) {
                                     inv1r = 1.0 / (1.0 + bo.a_p * cp * (2.0 * kPi / bo.p_orb));
                                     double dR[3];
