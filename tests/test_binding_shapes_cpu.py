@@ -1,0 +1,42 @@
+"""Host-side tensor-shape checks of the Python binding (no device needed):
+the width of theta and of the spindown rows follows the plan's spindown
+order and whether its sources are binary, and the sky rows follow the orbit
+setting.  The checks are called on a stand-in carrying only the plan's two
+settings."""
+from types import SimpleNamespace
+
+import pytest
+import torch
+
+from paper_0912_4255_amd.api import Plan
+
+
+def _plan(order, binary):
+    return SimpleNamespace(spin_order=order, binary=binary)
+
+
+@pytest.mark.parametrize("order,binary,width", [(1, False, 4), (2, False, 5), (3, False, 6),
+                                                (1, True, 7), (2, True, 8), (3, True, 9)])
+def test_theta_width_follows_order_and_orbit(order, binary, width):
+    p = _plan(order, binary)
+    assert Plan._n_theta(p, torch.zeros((3, width), dtype=torch.float64)) == 3
+    for bad in (width - 1, width + 1):
+        with pytest.raises(ValueError, match=rf"theta must be \[n, {width}\]"):
+            Plan._n_theta(p, torch.zeros((3, bad), dtype=torch.float64))
+    with pytest.raises(ValueError):
+        Plan._n_theta(p, torch.zeros(width, dtype=torch.float64))
+
+
+def test_spindown_rows_and_sky_rows():
+    p1, p3 = _plan(1, False), _plan(3, True)
+    assert Plan._n_fdot(p1, torch.zeros(7, dtype=torch.float64)) == 7
+    assert Plan._n_fdot(p1, torch.zeros((7, 1), dtype=torch.float64)) == 7
+    assert Plan._n_fdot(p3, torch.zeros((7, 3), dtype=torch.float64)) == 7
+    with pytest.raises(ValueError):
+        Plan._n_fdot(p3, torch.zeros(7, dtype=torch.float64))
+    with pytest.raises(ValueError):
+        Plan._n_fdot(p3, torch.zeros((7, 2), dtype=torch.float64))
+    assert Plan._n_sky(p1, torch.zeros((2, 2), dtype=torch.float64)) == 2
+    assert Plan._n_sky(p3, torch.zeros((2, 5), dtype=torch.float64)) == 2
+    with pytest.raises(ValueError):
+        Plan._n_sky(p3, torch.zeros((2, 2), dtype=torch.float64))
