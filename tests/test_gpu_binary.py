@@ -98,7 +98,8 @@ def test_point_and_adjoint_binary(gpu_lib):
     components scaled by (1/T0, 1/T0^2, 1e-5, 1e-5) within 1e-3 of their
     largest, the orbital ones scaled by (1e-3, 1, 10) within 2e-3 of theirs.
     A zero orbit reproduces the isolated source, with vanishing P_b and t_asc
-    derivatives.  At spin order 2 the point 2F also matches."""
+    derivatives.  At spin order 2 the point 2F also matches, and at order 3
+    2F and the whole gradient of one candidate."""
     import torch
     from oracle import grad as og
     w = synth.small_workload(n=21600, dt=4.0, kernel=synth.KERNEL_DIRICHLET, taps=16, t_start=1.0e5)
@@ -161,4 +162,19 @@ def test_point_and_adjoint_binary(gpu_lib):
     pt2 = plan.point(tx, tg, torch.from_numpy(th2).cuda()).cpu().numpy()
     ref2 = np.array([prob.twoF(t) for t in th2])
     assert np.all(np.abs(pt2 - ref2) <= 1e-4 * np.maximum(ref2, 4.0)), (pt2, ref2)
+
+    # spin order 3 with the orbit: 2F and the whole gradient of one candidate
+    print("case: binary point and adjoint, order 3", flush=True)
+    plan.set_spin_order(3)
+    th3 = np.column_stack([th[1:2, :2], [[3e-15, 1e-21]], th[1:2, 2:]])
+    F3, g3 = plan.backward(tx, tg, torch.from_numpy(th3).cuda(), torch.ones(1, dtype=torch.float32).cuda())
+    F3, g3 = float(F3.cpu()[0]), g3.cpu().numpy()[0]
+    ref3 = prob.twoF(th3[0])
+    assert abs(F3 - ref3) <= 1e-4 * max(ref3, 4.0), (F3, ref3)
+    rg3 = og.gradient(prob, th3[0])
+    sc3 = np.array([1 / T0, 1 / T0 ** 2, 1 / T0 ** 3, 1 / T0 ** 4, 1e-5, 1e-5])
+    a, b = g3[:6] * sc3, rg3[:6] * sc3
+    assert np.all(np.abs(a - b) <= 1e-3 * max(np.max(np.abs(b)), 1.0)), (a, b)
+    a, b = g3[6:] * sc_orb, rg3[6:] * sc_orb
+    assert np.all(np.abs(a - b) <= 2e-3 * max(np.max(np.abs(b)), 1.0)), (a, b)
     plan.close()
