@@ -281,6 +281,8 @@ class Plan:
 
     def graph_topk(self, xs, gaps, sky, fdot, k=10, ws=None):
         """Capture a rsf_fstat_topk call into a HIP graph; returns (Graph, values, indices)."""
+        _need_cuda(sky, torch.float64, "sky")
+        _need_cuda(fdot, torch.float64, "fdot")
         n_sky, n_fdot = self._n_sky(sky), self._n_fdot(fdot)
         seg, keep = self.segment(xs, gaps)
         dev = xs[0].device

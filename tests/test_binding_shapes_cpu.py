@@ -40,3 +40,24 @@ def test_spindown_rows_and_sky_rows():
     assert Plan._n_sky(p3, torch.zeros((2, 5), dtype=torch.float64)) == 2
     with pytest.raises(ValueError):
         Plan._n_sky(p3, torch.zeros((2, 2), dtype=torch.float64))
+
+
+class _NoLib:
+    """A library stand-in whose every attribute fails the test: the checks
+    must raise before any entry point is reached."""
+
+    def __getattr__(self, name):
+        raise AssertionError(f"library entry {name} reached")
+
+
+def test_graph_builders_refuse_host_tensors():
+    """A host sky tensor's address would be captured into the graph and read
+    by a kernel: both graph builders refuse it (and a float32 one) first."""
+    p = SimpleNamespace(spin_order=1, binary=False, lib=_NoLib())
+    sky = torch.zeros((1, 2), dtype=torch.float64)
+    fdot = torch.zeros(4, dtype=torch.float64)
+    for fn in (Plan.graph_topk, Plan.graph_fstat):
+        with pytest.raises(TypeError, match="sky"):
+            fn(p, [torch.zeros(8, dtype=torch.complex64)], None, sky, fdot)
+        with pytest.raises(TypeError, match="sky"):
+            fn(p, [], None, sky.float(), fdot)
