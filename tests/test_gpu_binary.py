@@ -2,7 +2,7 @@
 resampling, the full-band search, and the point 2F with its adjoint.
 
 Bars as for isolated sources: the total delay d (stored t_m) within 1e-9 s,
-a, b within 1e-6, z~ within 2e-5 of the series rms, the SSB mask exact, A',
+a, b within 1e-6, z~ within 3e-6 of the series rms, the SSB mask exact, A',
 B', C' to 1e-10; full-band 2F within 1e-4 max(2F, 4).  Orbit: a_p = 1.44
 light-s, P_b = 68,023.7 s (2 pi a_p / P_b = 1.3e-4), segment starting at
 1e5 s; an orbit of a_p = 0 must equal the isolated source."""
@@ -49,7 +49,7 @@ def test_resample_parity_binary(gpu_lib):
         rms = np.sqrt(np.mean(np.abs(ref["z"]) ** 2))
         err = np.max(np.abs(o["z"] - ref["z"])) / rms
         print(f"binary resample sky {s}: max|dz|/rms = {err:.2e}", flush=True)
-        assert err < 2e-5
+        assert err < 3e-6
         bits = np.unpackbits(o["mask"].view(np.uint8), bitorder="little")[: w.segment.n]
         assert np.array_equal(bits.astype(bool), ref["mask"] > 0)
         A, B, C = (np.sum(ref["mask"] * ref["a"] ** 2), np.sum(ref["mask"] * ref["b"] ** 2),

@@ -2,7 +2,8 @@
 same seeded inputs.
 
 Tolerances (FP32 bulk, FP64 timing/phase/antenna sums):
-  t_m,k: 1e-9 s;  a, b: 1e-6 absolute;  z~: 2e-6 relative to the series rms;
+  t_m,k: 1e-9 s;  a, b: 1e-6 absolute;  z~: 3e-6 of the series rms (measured
+  at most 1.0e-6 for Lanczos-8 and Dirichlet-16);
   A', B', C': 1e-10 relative;  mask: exact;
   2F: |delta| <= 1e-4 max(2F_oracle, 4) in every bin.
 """
@@ -56,7 +57,9 @@ def test_resample_parity(gpu_lib, kernel, taps):
         assert np.max(np.abs(o["a"] - ref["a"])) < 1e-6
         assert np.max(np.abs(o["b"] - ref["b"])) < 1e-6
         rms = np.sqrt(np.mean(np.abs(ref["z"]) ** 2))
-        assert np.max(np.abs(o["z"] - ref["z"])) < 2e-6 * rms * 10
+        zerr = np.max(np.abs(o["z"] - ref["z"])) / rms
+        print(f"resample kernel {kernel} W={taps} sky {s}: max|dz|/rms = {zerr:.2e}", flush=True)
+        assert zerr < 3e-6
         bits = np.unpackbits(o["mask"].view(np.uint8), bitorder="little")[: w.segment.n]
         assert np.array_equal(bits.astype(bool), ref["mask"] > 0)
         A, B, Cc = (np.sum(ref["mask"] * ref["a"] ** 2), np.sum(ref["mask"] * ref["b"] ** 2),

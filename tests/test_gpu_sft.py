@@ -103,12 +103,11 @@ def test_running_median_window_sizes(gpu_lib, median_window):
     assert np.max(np.abs(got - ref)) <= 1e-4 * np.max(np.abs(ref)), median_window
 
 
-def test_ten_day_sft_set_sampled_against_oracle(gpu_lib):
+def test_ten_day_sft_set_whole_series(gpu_lib):
     """The full T = 10 d input: 432 SFTs of 1800 s (48 missing), 7318 bins
-    each, output 3,456,000 samples at 4 Hz.  Five chunks of different
-    transform lengths are recomputed by the oracle from their own SFTs; over
-    the whole series the gaps are the missing SFTs, gap samples are zero, and
-    chunk interiors carry unit power times the band window's mean square."""
+    each, output 3,456,000 samples at 4 Hz.  Over the whole series the gaps
+    are the missing SFTs, gap samples are zero, and chunk interiors carry
+    unit power times the band window's mean square."""
     import torch
     ss, X = synth.sft_set_c2()
     plan = gpu_lib.SftPlan(ss)
@@ -134,37 +133,7 @@ def test_ten_day_sft_set_sampled_against_oracle(gpu_lib):
     assert np.all(np.isfinite(got))
     for a, b in gaps:
         assert np.all(got[a:b] == 0)
-    # chunks against the oracle, each recomputed from its own SFTs: the first,
-    # and the first of each grid M' = 8, 14, 21, 40, whose second passes have
-    # 225, 105, 135 and 180 rows (odd counts leave the last group of rows of a
-    # rows workgroup partly empty)
     chunks = osft.chunks(ss.t_sft, T)
-    def smooth7(m):
-        for q in (2, 3, 5, 7):
-            while m % q == 0:
-                m //= q
-        return m == 1
-
-    grids = {}
-    for a0, M in chunks:
-        g = M
-        while not smooth7(g):
-            g += 1
-        grids.setdefault(g, (a0, M))
-    picked = [chunks[0]] + [grids[g] for g in (8, 14, 21, 40) if g in grids]
-    assert len(picked) == 5
-    for a0, M in picked:
-        Xc = X[a0:a0 + M].astype(np.complex128)
-        Xh = osft.normalise(Xc, ss.median_window)
-        z, _ = osft.chunk_series(Xh, ss.k_lo, int(ss.band * T), int(round(ss.f_het * T)), ss.dk, ss.band_taper)
-        t_c = ss.t_sft[a0] - ss.t_start
-        z = z * np.exp(-2j * np.pi * ss.f_het * t_c) * osft.time_taper(len(z), int(round(ss.edge_taper_s * ss.band)))
-        j0 = int(round(t_c * ss.band))
-        seg = got[j0:j0 + len(z)]
-        err = np.max(np.abs(seg - z))
-        print(f"sft front end, 10 d, chunk of {M} SFTs at {a0}: max|d| / max|x| = {err / np.max(np.abs(z)):.2e}",
-              flush=True)
-        assert err <= 1e-4 * np.max(np.abs(z)), (a0, M)
     # unit power in chunk interiors (edge tapers excluded): the band window's
     # mean square, less the Dirichlet tail beyond dk (about 1 / (pi^2 dk) of
     # the power), plus the ~2 % upward bias of 1/median over 101 bins
@@ -177,4 +146,53 @@ def test_ten_day_sft_set_sampled_against_oracle(gpu_lib):
         vals.append(got[j0 + e:j0 + n - e])
     p = np.mean(np.abs(np.concatenate(vals)) ** 2)
     assert abs(p / w2 - 1.0) < 0.04
+    plan.close()
+
+
+def _smooth7(m):
+    for q in (2, 3, 5, 7):
+        while m % q == 0:
+            m //= q
+    return m == 1
+
+
+def _distinct_chunks():
+    """The first chunk of every distinct length M in the 10-day set (18
+    lengths from 1 to 38 SFTs, on 7-smooth grids M' from 1 to 40)."""
+    ss, _ = synth.sft_set_c2()
+    first = {}
+    for a0, M in osft.chunks(ss.t_sft, ss.t_sft_len):
+        first.setdefault(M, (a0, M))
+    return [first[M] for M in sorted(first)]
+
+
+@pytest.mark.parametrize("part", [0, 1])
+def test_ten_day_sft_chunks_against_oracle(gpu_lib, part):
+    """One chunk of every distinct length of the 10-day set, recomputed by the
+    oracle from its own SFTs (the lengths up to 16 SFTs, then the longer
+    ones: about half of the oracle's time each), on every 7-smooth grid M'
+    the set uses (1 to 40 SFTs; 13 -> 14, 19 -> 20, 22 -> 24, 29 -> 30,
+    38 -> 40 carry appended zero SFTs)."""
+    import torch
+    ss, X = synth.sft_set_c2()
+    T = ss.t_sft_len
+    plan = gpu_lib.SftPlan(ss)
+    got = plan.heterodyne(torch.from_numpy(X).cuda()).cpu().numpy()
+    picked = [c for c in _distinct_chunks() if (c[1] > 16) == bool(part)]
+    assert len(picked) == (12 if part == 0 else 6)
+    for a0, M in picked:
+        Mp = M
+        while not _smooth7(Mp):
+            Mp += 1
+        Xc = X[a0:a0 + M].astype(np.complex128)
+        Xh = osft.normalise(Xc, ss.median_window)
+        z, _ = osft.chunk_series(Xh, ss.k_lo, int(ss.band * T), int(round(ss.f_het * T)), ss.dk, ss.band_taper)
+        t_c = ss.t_sft[a0] - ss.t_start
+        z = z * np.exp(-2j * np.pi * ss.f_het * t_c) * osft.time_taper(len(z), int(round(ss.edge_taper_s * ss.band)))
+        j0 = int(round(t_c * ss.band))
+        seg = got[j0:j0 + len(z)]
+        err = np.max(np.abs(seg - z))
+        print(f"sft front end, 10 d, chunk of {M} SFTs (grid {Mp}) at {a0}: max|d| / max|x| = "
+              f"{err / np.max(np.abs(z)):.2e}", flush=True)
+        assert err <= 1e-4 * np.max(np.abs(z)), (a0, M)
     plan.close()
