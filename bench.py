@@ -9,14 +9,23 @@ signals do not change the work and are left out.
 
 A step is the whole hot path over that batch: resampling for the sky
 position, the antenna sums, and for every spindown the demodulation, both
-zero-padded FFTs and the 2F reduction of every bin (batched mode).  Inputs
-are resident in HBM before the timed region; the timed region is exactly
-`--steps` steps between two device synchronisations.
+zero-padded FFTs and the 2F reduction of every bin (batched mode), captured
+once into a HIP graph and replayed.  Inputs are resident in HBM before the
+timed region; the timed region is exactly `--steps` replays between two
+device synchronisations, with no per-kernel instrumentation inside it.
+After it, replays continue until at least 5 of them and 10 s have been
+timed one by one (hipEvents around each replay) and their median is
+reported; then a separate instrumented pass of the same launches gives the
+per-kernel durations (hipEvents on the launch stream) for the roofline.
+
+The CPU oracle runs first, before anything touches the GPU, on bounded
+samples of the same workload: one thread, all host cores (one process per
+core, forked), and the oracle's finite-difference gradient of one candidate
+of the gradient workload.
 
 Printed: one JSON line with templates/s (whole job), the per-template plain
-rate, the roofline of the dominant kernel (kernel durations measured with
-hipEvents on the launch stream during the timed region) and the CPU oracle
-on a bounded sample of the same workload.
+rate, the roofline of the dominant kernel and of the whole path, a measured
+device-to-device copy bandwidth, and the CPU baselines.
 """
 import argparse
 import json
@@ -41,9 +50,9 @@ def parse():
     ap.add_argument("--n-fdot", type=int, default=1000)
     ap.add_argument("--plain-templates", type=int, default=32)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-templates", type=int, default=3)
+    ap.add_argument("--cpu-templates", type=int, default=2)
     ap.add_argument("--copy-check", action="store_true",
-                    help="also run one 1 GiB device-to-device copy (counter calibration under a profiler)")
+                    help="accepted for older profiling commands; the 1 GiB copy now always runs")
     ap.add_argument("--no-autotune", action="store_true", help="use the planner's default configuration")
     ap.add_argument("--no-grad", action="store_true", help="skip the gradient workload")
     ap.add_argument("--grad-candidates", type=int, default=1024)
@@ -110,20 +119,71 @@ def committed_point_valu(config):
     return None
 
 
-def cpu_baseline(w, x, gaps, n_templates, n_step):
-    """The FP64 oracle, as it stands, on a bounded sample: resampling for the
-    sky position, then n_templates full-band templates, single thread.  The
-    rate is scaled to a step of n_step templates: one resampling plus n_step
-    templates at the measured per-template time."""
+def host_info():
+    """Host cores available to this process and the CPU model name."""
+    model = ""
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        avail = os.cpu_count() or 1
+    return {"nproc": avail, "cpu_count": os.cpu_count(), "model": model}
+
+
+# state shared with forked oracle workers (set before the pool starts)
+_CPU = {}
+
+
+def _one_thread():
     try:
         from threadpoolctl import threadpool_limits
+        return threadpool_limits(limits=1)
     except ImportError:  # pragma: no cover
-        threadpool_limits = None
+        import contextlib
+        return contextlib.nullcontext()
+
+
+def _cpu_template(i):
     from oracle import fstat as of
-    ctx = threadpool_limits(limits=1) if threadpool_limits else None
-    try:
-        if ctx:
-            ctx.__enter__()
+    c = _CPU
+    with _one_thread():
+        t0 = time.perf_counter()
+        of.fstat_band(c["rss"], c["dets"], float(c["fdots"][i]), c["n_fft"], c["s_lo"], c["n_out"])
+        return time.perf_counter() - t0
+
+
+def _cpu_grad_component(i):
+    from oracle import grad as og
+    c = _CPU
+    with _one_thread():
+        t0 = time.perf_counter()
+        prob = og.PointProblem(c["gx"], c["ggaps"], c["gseg"], c["gdets"], c["geph"], c["gkernel"], c["gtaps"])
+        g1 = og.central(prob.twoF, c["gtheta"], i, c["gsteps"][i])
+        g2 = og.central(prob.twoF, c["gtheta"], i, c["gsteps"][i] / 2.0)
+        return (4.0 * g2 - g1) / 3.0, time.perf_counter() - t0
+
+
+def cpu_baseline(w, x, gaps, n_templates, n_step, synth):
+    """The FP64 oracle, as it stands, on bounded samples, before the GPU is
+    touched: (1) one thread: resampling for the sky position, then
+    n_templates full-band templates; (2) one forked process per host core
+    (at most 16), each one full-band template from the same resampled
+    series; (3) the oracle's Richardson finite-difference gradient of one
+    candidate of the gradient workload, its four components in four
+    processes.  Rates are scaled to a step of n_step templates: one
+    resampling plus n_step templates at the measured per-template time."""
+    import multiprocessing as mp
+
+    from oracle import fstat as of
+    from oracle import grad as og
+    host = host_info()
+    with _one_thread():
         t0 = time.perf_counter()
         alpha, delta = w.skies[0]
         rss = of.resample_all([x], [gaps], w.segment, alpha, delta, w.eph, w.detectors, w.kernel, w.taps)
@@ -136,13 +196,42 @@ def cpu_baseline(w, x, gaps, n_templates, n_step):
         for i in range(n_templates):
             of.fstat_band(rss, w.detectors, float(w.fdots[i]), n_fft, s_lo, n_out)
         t_tp = (time.perf_counter() - t1) / n_templates
-    finally:
-        if ctx:
-            ctx.__exit__(None, None, None)
-    return {"value": n_step / (t_rs + n_step * t_tp), "unit": "templates/s", "cores": 1, "kind": "oracle",
-            "sample": f"T=10d workload, numpy FP64, 1 thread: resampling of 1 sky position ({t_rs:.1f} s) + "
-                      f"{n_templates} full-band template(s) ({t_tp:.1f} s each); rate for a step of "
-                      f"{n_step} templates = {n_step} / (resampling + {n_step} x template)"}
+    single = {"templates_per_s": n_step / (t_rs + n_step * t_tp), "resample_s": round(t_rs, 2),
+              "template_s": round(t_tp, 2), "templates": n_templates, "cores": 1}
+
+    # all cores: one template per forked worker (workers only run numpy)
+    P = max(1, min(16, host["nproc"]))
+    _CPU.update(rss=rss, dets=w.detectors, fdots=w.fdots, n_fft=n_fft, s_lo=s_lo, n_out=n_out)
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(P) as pool:
+        per = pool.map(_cpu_template, range(P))
+    wall = time.perf_counter() - t0
+    multi = {"templates_per_s": n_step / (t_rs + n_step * wall / P), "cores": P, "templates": P,
+             "wall_s": round(wall, 2), "mean_template_s": round(float(np.mean(per)), 2)}
+
+    # gradient workload: one candidate, the oracle's FD gradient over 4 processes
+    gw = synth.workload_c5()
+    gx = synth.gaussian_noise(synth.streams(4)[5], gw.segment.n, 1.0)
+    gdf = 1.0 / (2 * gw.segment.n * gw.segment.dt)
+    _CPU.update(gx=[gx], ggaps=[np.zeros((0, 2), np.int64)], gseg=gw.segment, gdets=list(gw.detectors),
+                geph=gw.eph, gkernel=gw.kernel, gtaps=gw.taps, gtheta=synth.c5_candidates(gw, gdf)[0],
+                gsteps=og.default_steps(gw.segment))
+    t0 = time.perf_counter()
+    with ctx.Pool(4) as pool:
+        res = pool.map(_cpu_grad_component, range(4))
+    gwall = time.perf_counter() - t0
+    gcpu = float(sum(t for _, t in res))
+    grad = {"candidates_per_s": round(1.0 / gcpu, 5), "s_per_candidate_one_core": round(gcpu, 2),
+            "wall_s_4_cores": round(gwall, 2),
+            "sample": "T=10d dt=0.5s N=1728000 workload, one candidate, Richardson central differences "
+                      "(8 evaluations of 2F per component, the series re-resampled for each sky offset)"}
+    _CPU.clear()
+    return {"value": multi["templates_per_s"], "unit": "templates/s", "cores": P, "kind": "oracle",
+            "sample": f"T=10d workload, numpy FP64: resampling of 1 sky position ({t_rs:.1f} s, one thread), "
+                      f"then {P} full-band templates in {P} forked single-thread processes ({wall:.1f} s wall); "
+                      f"rate for a step of {n_step} templates = {n_step} / (resampling + {n_step} x wall / {P})",
+            "host": host, "single_thread": single, "all_cores": multi, "gradient": grad}
 
 
 def grad_leg(rsf, synth, torch, dev, n_cand, steps=20):
@@ -201,48 +290,60 @@ def grad_leg(rsf, synth, torch, dev, n_cand, steps=20):
             "roofline": roof}
 
 
-def c3_leg(rsf, synth, torch, dev, n_seg, n_sky, n_fdot=16, k=10):
+def c3_leg(rsf, synth, torch, dev, n_seg, n_sky, n_fdot=16, k=10, reps=3):
     """Uneven segments: the first n_seg of the 64 segments (T_i ~ U[1, 30] d,
     dt = 0.5 s, 5 % gaps, 7-smooth FFT lengths), n_sky sky positions x 16
-    spindowns each, per-segment top-10 (rsf_fstat_topk)."""
-    total_t = 0.0
-    semi_t = 0.0
-    templates = 0
-    samples = 0
+    spindowns each, per-segment top-10, every segment with its own tuned
+    taps, factorisation and batching, all segments in one HIP graph of the
+    multi-segment entry (rsf_fstat_topk_segments), replayed."""
+    from paper_0912_4255_amd import autotune
+    wls = [synth.workload_c3_segment(i, n_sky=max(n_sky, 1)) for i in range(n_seg)]
+    plans, n_tuned = autotune.segment_plans(wls)
+    inputs = []
+    samples = points = 0
+    for i, w in enumerate(wls):
+        rng = np.random.default_rng([synth.SEED_BASE + 2, 1000 + i])
+        x = synth.zero_gaps(synth.gaussian_noise(rng, w.segment.n, 1.0), w.gaps[0])
+        inputs.append(([torch.from_numpy(x).to(dev)], [torch.from_numpy(w.gaps[0]).to(dev)]))
+        samples += w.segment.n
+        points += plans[i].n_fft
+    sky = torch.from_numpy(np.ascontiguousarray(wls[0].skies[:n_sky])).to(dev)
+    fd = torch.from_numpy(np.ascontiguousarray(wls[0].fdots[:n_fdot])).to(dev)
+    g, vals, ids = rsf.graph_topk_segments(plans, inputs, sky, fd, k=k)
+    g.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g.launch()
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / reps
+    g.close()
+    templates = n_seg * n_sky * n_fdot
+    full = 64 * 4096 * n_fdot
+    taps = sorted({p.desc.taps for p in plans})
+
     # semi-coherent sum over the same segments on a common grid of 1/(2 d) over [99, 101) Hz
     f_lo, df_c = 99.0, 1.0 / (2 * 86400.0)
     n_c = int(round(2.0 / df_c))
     S = torch.zeros((n_sky * n_fdot, n_c), dtype=torch.float32, device=dev)
-    for i in range(n_seg):
-        w = synth.workload_c3_segment(i, n_sky=max(n_sky, 1))
-        rng = np.random.default_rng([synth.SEED_BASE + 2, 1000 + i])
-        x = synth.zero_gaps(synth.gaussian_noise(rng, w.segment.n, 1.0), w.gaps[0])
-        plan = rsf.Plan(w)
-        tx = [torch.from_numpy(x).to(dev)]
-        tg = [torch.from_numpy(w.gaps[0]).to(dev)]
-        sky = torch.from_numpy(np.ascontiguousarray(w.skies[:n_sky])).to(dev)
-        fd = torch.from_numpy(np.ascontiguousarray(w.fdots[:n_fdot])).to(dev)
-        ws = plan.workspace(rsf.RSF_ENTRY_TOPK, n_sky, n_fdot, device=dev)
-        plan.topk(tx, tg, sky, fd, k=k, ws=ws)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        plan.topk(tx, tg, sky, fd, k=k, ws=ws)
-        torch.cuda.synchronize()
-        total_t += time.perf_counter() - t0
-        wss = plan.workspace(rsf.RSF_ENTRY_SEMICOHERENT, n_sky, n_fdot, device=dev)
-        if i == 0:
-            plan.semicoherent(tx, tg, sky, fd, torch.zeros_like(S), 0.0, f_lo, df_c, ws=wss)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        plan.semicoherent(tx, tg, sky, fd, S, 0.0, f_lo, df_c, ws=wss)
-        torch.cuda.synchronize()
-        semi_t += time.perf_counter() - t0
-        templates += n_sky * n_fdot
-        samples += w.segment.n
-        plan.close()
+    big = max(p.workspace_bytes(rsf.RSF_ENTRY_SEMICOHERENT, n_sky, n_fdot) for p in plans)
+    wss = torch.empty(big, dtype=torch.uint8, device=dev)
+    plans[0].semicoherent(*inputs[0], sky, fd, torch.zeros_like(S), 0.0, f_lo, df_c, ws=wss)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for p, (tx, tg) in zip(plans, inputs):
+        p.semicoherent(tx, tg, sky, fd, S, 0.0, f_lo, df_c, ws=wss)
+    torch.cuda.synchronize()
+    semi_t = time.perf_counter() - t1
+    for p in plans:
+        p.close()
     return {"workload": f"first {n_seg} of 64 uneven segments (mean N={samples // n_seg}), "
-                        f"{n_sky} sky x {n_fdot} fdot, top-{k} per segment",
-            "segment_templates": templates, "segment_templates_per_s": round(templates / total_t, 1),
+                        f"{n_sky} sky x {n_fdot} fdot, top-{k} per segment, one HIP graph over all segments",
+            "segment_templates": templates, "segment_templates_per_s": round(templates / t, 1),
+            "ms_per_replay": round(t * 1e3, 2), "tuned_segments": n_tuned, "taps": taps,
+            "fft_points_per_s": round(n_sky * n_fdot * points / t, 1),
+            "extrapolated_full_s": round(full / (templates / t), 1),
+            "extrapolation": f"64 segments x 4096 sky x {n_fdot} fdot = {full} segment-templates at the measured rate",
             "semicoherent": {"grid": f"[99, 101) Hz at 1/(2 d), {n_c} bins, t_ref = 0",
                              "segment_templates_per_s": round(templates / semi_t, 1),
                              "peak_S": round(float(S.max()), 2), "mean_S": round(float(S.mean()), 3)}}
@@ -322,6 +423,32 @@ def hetdec_leg(rsf, torch, dev, reps=5):
                          "flops": 4 * taps * n_out}}
 
 
+# Compulsory bytes per template of the method at this shape: the inputs once
+# (complex64 series 8 B, the resampled series with a, b and t_m 16 B per
+# sample), one spill of both spectra (2 x 8 B per FFT point, written and read
+# back) and the 2F outputs (4 B per bin): 24 N + 32 N_fft + 4 N_out.
+def b_alg(N, Nf, No):
+    return 24 * N + 32 * Nf + 4 * No
+
+
+def copy_bandwidth(torch, dev, nbytes=1 << 30, reps=5):
+    """Device-to-device copy of nbytes, timed with hipEvents: GB/s counting
+    the bytes read plus the bytes written."""
+    src = torch.empty(nbytes, dtype=torch.uint8, device=dev).fill_(1)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(reps):
+        dst.copy_(src)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / reps
+    del src, dst
+    return {"bytes": 2 * nbytes, "ms": round(ms, 4), "GBps": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -329,16 +456,24 @@ def main():
               "and needs no collective: run one process per GPU on disjoint template ranges.",
               file=sys.stderr)
         sys.exit(2)
-    import torch
-
-    import paper_0912_4255_amd as rsf
     from paper_0912_4255_amd import synth
 
-    rsf.load()
-    dev = torch.device("cuda:0")
     w = synth.workload_c2(n_fdot=a.n_fdot)
     rng = synth.streams(1)[0]
     x = synth.zero_gaps(synth.gaussian_noise(rng, w.segment.n, 1.0), w.gaps[0])
+    n_t = a.n_fdot
+
+    # the CPU oracle first: its worker processes are forked before the GPU is touched
+    cpu = None
+    if not a.no_cpu:
+        cpu = cpu_baseline(w, x, w.gaps[0], a.cpu_templates, n_t, synth)
+
+    import torch
+
+    import paper_0912_4255_amd as rsf
+
+    rsf.load()
+    dev = torch.device("cuda:0")
     tuned = None
     if a.no_autotune:
         plan = rsf.Plan(w)
@@ -349,34 +484,50 @@ def main():
     tg = [torch.from_numpy(w.gaps[0]).to(dev)]
     sky = torch.from_numpy(np.ascontiguousarray(w.skies)).to(dev)
     fd = torch.from_numpy(np.ascontiguousarray(w.fdots)).to(dev)
-    n_t = a.n_fdot
     out = torch.empty((n_t, plan.n_out), dtype=torch.float32, device=dev)
     ws = plan.workspace(rsf.RSF_ENTRY_FSTAT, 1, n_t, rsf.RSF_MODE_BATCHED, device=dev)
 
-    if a.copy_check:
-        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev).fill_(1)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-
-    def step():
-        plan.fstat(tx, tg, sky, fd, mode=rsf.RSF_MODE_BATCHED, out=out, ws=ws)
-
+    # the step, captured once into a HIP graph
+    graph, _ = plan.graph_fstat(tx, tg, sky, fd, out=out, ws=ws)
     for _ in range(a.warmup):
-        step()
-    torch.cuda.synchronize()
-    plan.profile(True)
+        graph.launch()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(a.steps):
-        step()
+        graph.launch()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof = plan.profile_read()
-    plan.profile(False)
     ms_step = (t1 - t0) * 1e3 / a.steps
     value = n_t * a.steps / (t1 - t0)
+
+    # replays timed one by one until >= 5 replays and >= 10 s: the median
+    ev = []
+    t_start = time.perf_counter()
+    while len(ev) < 5 or time.perf_counter() - t_start < 10.0:
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        graph.launch()
+        e1.record()
+        ev.append((e0, e1))
+        if len(ev) % 16 == 0:
+            torch.cuda.synchronize()
+    torch.cuda.synchronize()
+    rep_ms = np.array([e0.elapsed_time(e1) for e0, e1 in ev])
+    replays = {"n": int(len(rep_ms)), "total_s": round(float(rep_ms.sum()) / 1e3, 2),
+               "median_ms": round(float(np.median(rep_ms)), 3), "min_ms": round(float(rep_ms.min()), 3),
+               "max_ms": round(float(rep_ms.max()), 3),
+               "median_templates_per_s": round(n_t / (float(np.median(rep_ms)) * 1e-3), 2)}
+    graph.close()
+
+    # per-kernel durations: a separate instrumented pass of the same launches
+    # (hipEvents recorded by the library on the launch stream)
+    prof_steps = max(1, min(a.steps, 5))
+    plan.profile(True)
+    plan.profile_read()
+    for _ in range(prof_steps):
+        plan.fstat(tx, tg, sky, fd, mode=rsf.RSF_MODE_BATCHED, out=out, ws=ws)
+    prof = plan.profile_read()
+    plan.profile(False)
 
     # plain per-template path on a subset of the spindowns (0 skips it)
     n_p = min(a.plain_templates, n_t)
@@ -393,9 +544,8 @@ def main():
         plain_rate = round(n_p / (time.perf_counter() - tp0), 2)
         del out_p, ws_p
 
-    # roofline of the dominant kernel: algorithmic bytes over the timed region
-    # (per-launch bytes summed over its launches) / summed launch durations,
-    # i.e. mean bytes per launch / mean launch duration
+    # roofline of the dominant kernel: algorithmic bytes per launch (per-launch
+    # bytes summed over the instrumented pass's launches) / mean launch duration
     N, Nf, No = w.segment.n, plan.n_fft, plan.n_out
     fb, G, _ = plan.batching(1, n_t)
     sizes = [min(G, n_t - f0) for f0 in range(0, n_t, G)]
@@ -412,7 +562,7 @@ def main():
     dom = max(kern, key=lambda k: kern[k][1])
     launches, total_ms = kern[dom]
     avg_s = total_ms / launches / 1e3
-    bytes_per_launch = total_bytes[dom] * a.steps / launches
+    bytes_per_launch = total_bytes[dom] * prof_steps / launches
     achieved = bytes_per_launch / avg_s / 1e9
     cfg = f"{plan.fft_l1}x{plan.fft_l2},fb{fb},g{G}"
     traffic = committed_traffic(dom, cfg)
@@ -424,15 +574,19 @@ def main():
                 "kernels": {k: {"launches": v[0], "avg_us": round(v[1] / v[0] * 1e3, 2),
                                 "share": round(v[1] / sum(t for _, t in prof.values()), 4)}
                             for k, v in prof.items()}}
+    copy = copy_bandwidth(torch, dev)
+    B = b_alg(N, Nf, No)
+    path = {"bytes_per_template": B, "formula": "24 N + 32 N_fft + 4 N_out",
+            "achieved_GBps": round(value * B / 1e9, 1), "frac": round(value * B / 1e9 / HBM_PEAK_GBS, 4),
+            "frac_of_copy": round(value * B / 1e9 / copy["GBps"], 4)}
 
     grad = None if a.no_grad else grad_leg(rsf, synth, torch, dev, a.grad_candidates)
     sft_fe = None if a.no_sft else sft_leg(rsf, synth, torch, dev)
     hetdec = None if a.no_hetdec else hetdec_leg(rsf, torch, dev)
     c3 = None if a.no_c3 else c3_leg(rsf, synth, torch, dev, a.c3_segments, a.c3_sky)
-
-    cpu = None
-    if not a.no_cpu:
-        cpu = cpu_baseline(w, x, w.gaps[0], a.cpu_templates, n_t)
+    if c3 is not None:
+        # FFT points per second against the headline's (same kernels, other shapes)
+        c3["fft_points_per_s_vs_headline"] = round(c3["fft_points_per_s"] / (value * Nf), 4)
 
     rec = {"metric": "F-stat templates/s at T=10d, 2Hz band: plain vs batched+grad; %HBM roofline",
            "value": round(value, 2), "unit": "templates/s", "n_gpus": 1, "steps": a.steps,
@@ -441,10 +595,10 @@ def main():
            "config": {"workload": f"T=10d dt=0.25s N=3456000 10pct gaps, 1 sky x {n_t} fdot, "
                                   "Dirichlet-16, N_fft=6912000, band [100,102) Hz",
                       "templates_per_step": n_t, "n_fft": Nf, "n_out": No,
-                      "fft_factors": [plan.fft_l1, plan.fft_l2]},
-           "plain_templates_per_s": plain_rate,
+                      "fft_factors": [plan.fft_l1, plan.fft_l2], "timing": "HIP graph replays"},
+           "replays": replays, "plain_templates_per_s": plain_rate,
            "autotune": tuned, "grad": grad, "c3": c3, "sft_front_end": sft_fe, "time_domain_front_end": hetdec,
-           "roofline": roofline, "cpu_baseline": cpu}
+           "roofline": roofline, "path_roofline": path, "copy": copy, "cpu_baseline": cpu}
     print(json.dumps(rec))
 
 

@@ -231,6 +231,29 @@ int rsf_fstat_topk(const rsf_plan* plan, const rsf_segment* seg, const double* s
                    const double* fdot, int64_t n_fdot, int k, rsf_topk_entry* topk,
                    void* ws, size_t ws_bytes, void* stream);
 
+/* Several data segments of uneven length in one call: the template loop of
+ * Sec. IV.A (over the sky positions and spindowns, the same templates for
+ * every segment) run over n_seg segments, each reduced to its own k best.
+ * plans: HOST array of n_seg plan pointers, plans[i] describing segment i
+ * (its n, dt, t_start, f_het, band, interpolation kernel and taps, FFT
+ * factorisation and batching knobs, so each segment may carry its own tuned
+ * settings); every plan must have the same n_det, spindown order and orbit
+ * setting, else RSF_EINVAL.  segs: HOST array of n_seg segment descriptors
+ * (device series and gap lists, as for rsf_fstat).  sky, fdot: as for
+ * rsf_fstat_topk, shared by all segments; each segment's spindowns refer to
+ * its own start (phase reference t = 0 at its t_start).  topk: device
+ * rsf_topk_entry [n_seg][k], 1 <= k <= 64: row i holds segment i's k largest
+ * 2F over its templates and the bins of its band (bin = index into segment
+ * i's ascending band), ordered and tie-broken as rsf_fstat_topk.  The
+ * segments run one after another on `stream` without any host
+ * synchronisation, sharing one workspace of at least
+ * rsf_segments_workspace_size bytes (the largest any segment needs). */
+int rsf_segments_workspace_size(const rsf_plan* const* plans, int64_t n_seg, int64_t n_sky, int64_t n_fdot,
+                                size_t* bytes);
+int rsf_fstat_topk_segments(const rsf_plan* const* plans, const rsf_segment* segs, int64_t n_seg, const double* sky,
+                            int64_t n_sky, const double* fdot, int64_t n_fdot, int k, rsf_topk_entry* topk, void* ws,
+                            size_t ws_bytes, void* stream);
+
 /* Semi-coherent ("stack-slide") sum over segments, the hierarchical scheme
  * named in the paper's introduction, as a plain sum of per-segment 2F along
  * each template's frequency track.  Template (sky, f0, fdot) has f0 at the
@@ -288,6 +311,12 @@ int rsf_graph_create_fstat(rsf_graph** out, const rsf_plan* plan, const rsf_segm
 int rsf_graph_create_topk(rsf_graph** out, const rsf_plan* plan, const rsf_segment* seg, const double* sky,
                           int64_t n_sky, const double* fdot, int64_t n_fdot, int k, rsf_topk_entry* topk,
                           void* ws, size_t ws_bytes);
+/* rsf_fstat_topk_segments over all n_seg segments captured into one graph
+ * (plans and segs are read at capture; the device buffers they and the other
+ * arguments point to must stay valid while the graph exists). */
+int rsf_graph_create_topk_segments(rsf_graph** out, const rsf_plan* const* plans, const rsf_segment* segs,
+                                   int64_t n_seg, const double* sky, int64_t n_sky, const double* fdot, int64_t n_fdot,
+                                   int k, rsf_topk_entry* topk, void* ws, size_t ws_bytes);
 int rsf_graph_launch(rsf_graph* graph, void* stream);
 int rsf_graph_destroy(rsf_graph* graph);
 

@@ -13,7 +13,8 @@ from ._lib import (RSF_ENTRY_BACKWARD, RSF_ENTRY_FSTAT, RSF_ENTRY_POINT, RSF_ENT
 def __getattr__(name):
     # torch is imported lazily so that the pure-Python parts (synth, build)
     # work without it
-    if name in ("Plan", "plan_desc_from_workload", "FStatFn", "fstat_point", "SftPlan", "sft_desc_from_set", "HetdecPlan"):
+    if name in ("Plan", "plan_desc_from_workload", "FStatFn", "fstat_point", "SftPlan", "sft_desc_from_set", "HetdecPlan",
+                "fstat_topk_segments", "graph_topk_segments", "segments_workspace"):
         from . import api
         return getattr(api, name)
     raise AttributeError(name)

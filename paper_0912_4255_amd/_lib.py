@@ -24,6 +24,7 @@ EXPORTS = [
     "rsf_fstat_backward",
     "rsf_get_flags", "rsf_last_error", "rsf_version", "rsf_profile_enable", "rsf_profile_read",
     "rsf_graph_create_fstat", "rsf_graph_create_topk", "rsf_graph_launch", "rsf_graph_destroy",
+    "rsf_segments_workspace_size", "rsf_fstat_topk_segments", "rsf_graph_create_topk_segments",
     "rsf_sft_plan_create", "rsf_sft_plan_destroy", "rsf_sft_plan_query", "rsf_sft_workspace_size",
     "rsf_sft_heterodyne", "rsf_sft_profile_enable", "rsf_sft_profile_read",
     "rsf_hetdec_plan_create", "rsf_hetdec_plan_destroy", "rsf_hetdec", "rsf_hetdec_profile_enable",
@@ -113,6 +114,11 @@ def load(path=None):
     lib.rsf_graph_create_fstat.argtypes = [C.POINTER(vp), vp, C.POINTER(Segment), vp, i64, vp, i64, vp, vp, sz]
     lib.rsf_graph_create_topk.argtypes = [C.POINTER(vp), vp, C.POINTER(Segment), vp, i64, vp, i64, i32, vp, vp,
                                           sz]
+    lib.rsf_segments_workspace_size.argtypes = [C.POINTER(vp), i64, i64, i64, C.POINTER(sz)]
+    lib.rsf_fstat_topk_segments.argtypes = [C.POINTER(vp), C.POINTER(Segment), i64, vp, i64, vp, i64, i32, vp, vp,
+                                            sz, vp]
+    lib.rsf_graph_create_topk_segments.argtypes = [C.POINTER(vp), C.POINTER(vp), C.POINTER(Segment), i64, vp, i64,
+                                                   vp, i64, i32, vp, vp, sz]
     lib.rsf_graph_launch.argtypes = [vp, vp]
     lib.rsf_graph_destroy.argtypes = [vp]
     lib.rsf_profile_enable.argtypes = [vp, i32]

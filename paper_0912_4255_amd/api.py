@@ -333,6 +333,68 @@ class Graph:
             pass
 
 
+def _segments_args(plans, inputs):
+    """Host arrays of plan pointers and segment descriptors for a
+    multi-segment call; inputs[i] = (xs, gaps) of segment i."""
+    if len(plans) < 1 or len(plans) != len(inputs):
+        raise ValueError("one (xs, gaps) pair per plan is required")
+    n_seg = len(plans)
+    parr = (C.c_void_p * n_seg)(*[p._p.value for p in plans])
+    sarr = (L.Segment * n_seg)()
+    keep = []
+    for i, (p, (xs, gaps)) in enumerate(zip(plans, inputs)):
+        seg, k = p.segment(xs, gaps)
+        sarr[i] = seg
+        keep.append(k)
+    return parr, sarr, keep
+
+
+def segments_workspace(plans, n_sky, n_fdot, device="cuda"):
+    """rsf_segments_workspace_size, as a uint8 device tensor."""
+    lib = L.load()
+    parr = (C.c_void_p * len(plans))(*[p._p.value for p in plans])
+    b = C.c_size_t()
+    L.check(lib.rsf_segments_workspace_size(parr, len(plans), n_sky, n_fdot, C.byref(b)))
+    return torch.empty(max(1, b.value), dtype=torch.uint8, device=device)
+
+
+def _check_templates(plans, sky, fdot):
+    _need_cuda(sky, torch.float64, "sky")
+    _need_cuda(fdot, torch.float64, "fdot")
+    return plans[0]._n_sky(sky), plans[0]._n_fdot(fdot)
+
+
+def fstat_topk_segments(plans, inputs, sky, fdot, k=10, ws=None):
+    """rsf_fstat_topk_segments: the k best (2F, sky, fdot, bin) of every
+    segment; plans[i] and inputs[i] = (xs, gaps) describe segment i.  Returns
+    (values float32 [n_seg, k], indices int32 [n_seg, k, 3])."""
+    n_sky, n_fdot = _check_templates(plans, sky, fdot)
+    parr, sarr, keep = _segments_args(plans, inputs)
+    dev = sky.device
+    res = torch.empty((len(plans), k, 4), dtype=torch.int32, device=dev)
+    if ws is None:
+        ws = segments_workspace(plans, n_sky, n_fdot, device=dev)
+    L.check(plans[0].lib.rsf_fstat_topk_segments(parr, sarr, len(plans), _ptr(sky), n_sky, _ptr(fdot), n_fdot, k,
+                                                 _ptr(res), _ptr(ws), ws.numel(), _stream()))
+    return res[..., 0].view(torch.float32), res[..., 1:]
+
+
+def graph_topk_segments(plans, inputs, sky, fdot, k=10, ws=None):
+    """The multi-segment top-k captured into one HIP graph; returns (Graph,
+    values [n_seg, k], indices [n_seg, k, 3]), refreshed by every replay."""
+    n_sky, n_fdot = _check_templates(plans, sky, fdot)
+    parr, sarr, keep = _segments_args(plans, inputs)
+    dev = sky.device
+    res = torch.empty((len(plans), k, 4), dtype=torch.int32, device=dev)
+    if ws is None:
+        ws = segments_workspace(plans, n_sky, n_fdot, device=dev)
+    h = C.c_void_p()
+    L.check(plans[0].lib.rsf_graph_create_topk_segments(C.byref(h), parr, sarr, len(plans), _ptr(sky), n_sky,
+                                                        _ptr(fdot), n_fdot, k, _ptr(res), _ptr(ws), ws.numel()))
+    g = Graph(plans[0].lib, h, (list(plans), inputs, keep, sky, fdot, res, ws))
+    return g, res[..., 0].view(torch.float32), res[..., 1:]
+
+
 class FStatFn(torch.autograd.Function):
     """2F(theta) at continuous (f, f^(1) .. f^(s), alpha, delta) with a
     hand-written adjoint: forward calls rsf_fstat_point, backward

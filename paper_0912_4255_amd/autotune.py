@@ -165,6 +165,73 @@ def choose_taps(workload, candidates=(8, 12, 16, 24), bound=1e-2, ref_taps=32, n
     return (ok[0] if ok else max(candidates)), dev
 
 
+def _time_topk(plan, xs, gaps, sky, fdot, reps=2, k=10):
+    ws = plan.workspace(L.RSF_ENTRY_TOPK, sky.shape[0], fdot.shape[0])
+    plan.topk(xs, gaps, sky, fdot, k=k, ws=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.topk(xs, gaps, sky, fdot, k=k, ws=ws)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps / (sky.shape[0] * fdot.shape[0])
+
+
+def tune_segment(workload, n_sky=8, n_fdot=16, fbs=(8, 16), templates=(32, 64, 128), l1_limit=3, taps=None,
+                 verbose=False):
+    """Tuning of one uneven segment for its own template loop (n_sky sky
+    positions x n_fdot spindowns, per-segment top-k): the interpolation taps
+    from choose_taps (unless given), then the FFT factorisation and batching
+    timed on that loop.  Returns {taps, fft_l1, fft_l2, fb, templates,
+    s_per_template}."""
+    if taps is None:
+        taps, _ = choose_taps(workload)
+    desc = plan_desc_from_workload(workload)
+    desc.taps = taps
+    base = Plan(desc=desc)
+    rng = np.random.default_rng(1)
+    xs = [torch.from_numpy(synth.gaussian_noise(rng, base.n, d.sigma2)).cuda() for d in workload.detectors]
+    gaps = [None] * len(xs)
+    sky = torch.from_numpy(np.ascontiguousarray(synth.uniform_sky(rng, n_sky))).cuda()
+    fdot = torch.from_numpy(synth.fdot_grid(n_fdot)).cuda()
+    best = None
+    for p in candidate_l1(base, limit=l1_limit):
+        for fb in fbs:
+            for g in templates:
+                p.set_batching(fb, g)
+                t = _time_topk(p, xs, gaps, sky, fdot)
+                if verbose:
+                    print(f"n={base.n} L1={p.fft_l1} fb={fb} G={g}: {t * 1e6:.1f} us/template", flush=True)
+                if best is None or t < best["s_per_template"]:
+                    best = {"taps": taps, "fft_l1": p.fft_l1, "fft_l2": p.fft_l2, "fb": fb, "templates": g,
+                            "s_per_template": t}
+        p.close()
+    base.close()
+    return best
+
+
+SEGMENTS_KEY = "segments:c3"
+
+
+def segment_plans(workloads):
+    """Plans for uneven segments with the shipped per-segment tuning (taps,
+    factorisation, batching), keyed by segment length; segments without an
+    entry keep their workload's taps and the planner's choices."""
+    table = _read(SHIPPED).get(SEGMENTS_KEY, {})
+    plans, used = [], 0
+    for w in workloads:
+        e = table.get(str(w.segment.n))
+        desc = plan_desc_from_workload(w)
+        if e:
+            desc.taps = e["taps"]
+            desc.fft_l1 = e["fft_l1"]
+        p = Plan(desc=desc)
+        if e:
+            p.set_batching(e["fb"], e["templates"])
+            used += 1
+        plans.append(p)
+    return plans, used
+
+
 def _standard_workloads():
     return {"T=10d dt=0.25s (N=3456000)": synth.workload_c2(n_fdot=32),
             "T=10d dt=0.5s (N=1728000)": synth.workload_c5(),
@@ -175,26 +242,38 @@ def _standard_workloads():
 def main(argv=None):
     """Tune the standard workload shapes on the current GPU and write the
     entries (merged into an existing file) to --out (default: the shipped
-    table beside this module)."""
+    table beside this module).  --segments N also tunes the first N uneven
+    segments (taps, factorisation and batching each)."""
     import argparse
     ap = argparse.ArgumentParser(description=main.__doc__)
     ap.add_argument("--out", default=SHIPPED)
     ap.add_argument("--fbs", default="2,4,8,16")
     ap.add_argument("--templates", default="16,32,64")
     ap.add_argument("--n-fdot", type=int, default=64)
+    ap.add_argument("--segments", type=int, default=0)
+    ap.add_argument("--no-standard", action="store_true")
     a = ap.parse_args(argv)
     fbs = tuple(int(v) for v in a.fbs.split(","))
     gs = tuple(int(v) for v in a.templates.split(","))
     db = _read(a.out)
-    for name, w in _standard_workloads().items():
-        base = Plan(w)
-        key = _key(base.desc, base.n_fft)
-        base.close()
-        best = tune(w, n_fdot=a.n_fdot, reps=2, use_cache=False, fbs=fbs, templates=gs, verbose=True)
-        best["workload"] = name
-        db[key] = best
-        print(name, key, best, flush=True)
-        torch.cuda.empty_cache()
+    if not a.no_standard:
+        for name, w in _standard_workloads().items():
+            base = Plan(w)
+            key = _key(base.desc, base.n_fft)
+            base.close()
+            best = tune(w, n_fdot=a.n_fdot, reps=2, use_cache=False, fbs=fbs, templates=gs, verbose=True)
+            best["workload"] = name
+            db[key] = best
+            print(name, key, best, flush=True)
+            torch.cuda.empty_cache()
+    if a.segments:
+        table = db.setdefault(SEGMENTS_KEY, {})
+        for i in range(a.segments):
+            w = synth.workload_c3_segment(i, n_sky=8)
+            best = tune_segment(w)
+            table[str(w.segment.n)] = best
+            print(f"segment {i}: n={w.segment.n}", best, flush=True)
+            torch.cuda.empty_cache()
     with open(a.out, "w") as f:
         json.dump(db, f, indent=1, sort_keys=True)
         f.write("\n")

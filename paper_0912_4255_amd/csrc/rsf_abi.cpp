@@ -928,6 +928,70 @@ int rsf_fstat_topk(const rsf_plan* p, const rsf_segment* seg, const double* sky,
     return run_fstat(p, seg, sky, n_sky, fdot, n_fdot, RSF_MODE_BATCHED, nullptr, k, topk, ws, ws_bytes, stream);
 }
 
+}  // extern "C"
+
+namespace {
+// Plans of a multi-segment call: non-null, one detector set, spindown order
+// and orbit setting for all of them.
+int check_plans(const rsf_plan* const* plans, int64_t n_seg) {
+    if (!plans) return fail(RSF_EINVAL, "plans is NULL");
+    if (n_seg < 1) return fail(RSF_EINVAL, "n_seg must be positive");
+    for (int64_t i = 0; i < n_seg; ++i) {
+        if (!plans[i]) return fail(RSF_EINVAL, "plans[%lld] is NULL", (long long)i);
+        if (plans[i]->d.n_det != plans[0]->d.n_det || plans[i]->spin_order != plans[0]->spin_order ||
+            plans[i]->binary != plans[0]->binary)
+            return fail(RSF_EINVAL, "plans[%lld] differs from plans[0] in detectors, spindown order or orbit setting",
+                        (long long)i);
+    }
+    return RSF_OK;
+}
+
+size_t segments_ws(const rsf_plan* const* plans, int64_t n_seg, int64_t n_sky, int64_t n_fdot) {
+    size_t m = 0;
+    for (int64_t i = 0; i < n_seg; ++i)
+        m = std::max(m, fstat_layout(plans[i], n_sky, n_fdot, RSF_MODE_BATCHED, true).total);
+    return m;
+}
+
+// Segment after segment on one stream, sharing the workspace; segment i's
+// top-k goes to topk[i k .. i k + k).
+int run_segments(const rsf_plan* const* plans, const rsf_segment* segs, int64_t n_seg, const double* sky,
+                 int64_t n_sky, const double* fdot, int64_t n_fdot, int k, rsf_topk_entry* topk, void* ws,
+                 size_t ws_bytes, void* stream) {
+    int rc = check_plans(plans, n_seg);
+    if (rc) return rc;
+    if (!segs) return fail(RSF_EINVAL, "segs is NULL");
+    if (!topk) return fail(RSF_EINVAL, "topk is NULL");
+    if (n_sky < 1 || n_fdot < 1) return fail(RSF_EINVAL, "n_sky and n_fdot must be positive");
+    const size_t need = segments_ws(plans, n_seg, n_sky, n_fdot);
+    if (ws_bytes < need) return fail(RSF_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+    for (int64_t i = 0; i < n_seg; ++i) {
+        rc = run_fstat(plans[i], &segs[i], sky, n_sky, fdot, n_fdot, RSF_MODE_BATCHED, nullptr, k, topk + i * k, ws,
+                       ws_bytes, stream);
+        if (rc) return rc;
+    }
+    return RSF_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int rsf_segments_workspace_size(const rsf_plan* const* plans, int64_t n_seg, int64_t n_sky, int64_t n_fdot,
+                                size_t* bytes) {
+    int rc = check_plans(plans, n_seg);
+    if (rc) return rc;
+    if (!bytes) return fail(RSF_EINVAL, "bytes is NULL");
+    if (n_sky < 1 || n_fdot < 1) return fail(RSF_EINVAL, "n_sky and n_fdot must be positive");
+    *bytes = segments_ws(plans, n_seg, n_sky, n_fdot);
+    return RSF_OK;
+}
+
+int rsf_fstat_topk_segments(const rsf_plan* const* plans, const rsf_segment* segs, int64_t n_seg, const double* sky,
+                            int64_t n_sky, const double* fdot, int64_t n_fdot, int k, rsf_topk_entry* topk, void* ws,
+                            size_t ws_bytes, void* stream) {
+    return run_segments(plans, segs, n_seg, sky, n_sky, fdot, n_fdot, k, topk, ws, ws_bytes, stream);
+}
+
 namespace {
 int point_common(const rsf_plan* p, const rsf_segment* seg, const double* theta, int64_t n, const float* g_twoF,
                  float* twoF, double* g_theta, void* ws, size_t ws_bytes, void* stream, bool grad) {
@@ -1013,24 +1077,33 @@ struct rsf_graph {
 
 namespace {
 template <typename Fn>
-int capture_graph(rsf_graph** out, const rsf_plan* p, Fn body) {
+int capture_graph_plans(rsf_graph** out, const rsf_plan* const* plans, int64_t n_plans, Fn body) {
     if (!out) return fail(RSF_EINVAL, "out is NULL");
     *out = nullptr;
-    if (!p) return fail(RSF_EINVAL, "plan is NULL");
+    if (!plans || n_plans < 1) return fail(RSF_EINVAL, "plan is NULL");
+    for (int64_t i = 0; i < n_plans; ++i)
+        if (!plans[i]) return fail(RSF_EINVAL, "plan is NULL");
     hipStream_t cs = nullptr;
     RSF_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "hipStreamCreate");
-    const bool prof_on = p->prof->on;
-    p->prof->on = false;
+    // no instrumentation events inside a graph
+    std::vector<char> prof_on((size_t)n_plans);
+    for (int64_t i = 0; i < n_plans; ++i) {
+        prof_on[i] = plans[i]->prof->on;
+        plans[i]->prof->on = false;
+    }
+    auto restore = [&] {
+        for (int64_t i = 0; i < n_plans; ++i) plans[i]->prof->on = prof_on[i] != 0;
+    };
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) {
-        p->prof->on = prof_on;
+        restore();
         (void)hipStreamDestroy(cs);
         return hip_fail(e, "hipStreamBeginCapture");
     }
     const int rc = body(cs);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(cs, &g);
-    p->prof->on = prof_on;
+    restore();
     (void)hipStreamDestroy(cs);
     if (rc != RSF_OK) {
         if (g) (void)hipGraphDestroy(g);
@@ -1045,6 +1118,11 @@ int capture_graph(rsf_graph** out, const rsf_plan* p, Fn body) {
     }
     *out = new rsf_graph{g, x};
     return RSF_OK;
+}
+
+template <typename Fn>
+int capture_graph(rsf_graph** out, const rsf_plan* p, Fn body) {
+    return capture_graph_plans(out, &p, 1, body);
 }
 }  // namespace
 
@@ -1065,6 +1143,16 @@ int rsf_graph_create_topk(rsf_graph** out, const rsf_plan* p, const rsf_segment*
     if (!topk) return fail(RSF_EINVAL, "topk is NULL");
     return capture_graph(out, p, [&](hipStream_t cs) {
         return run_fstat(p, seg, sky, n_sky, fdot, n_fdot, RSF_MODE_BATCHED, nullptr, k, topk, ws, ws_bytes, cs);
+    });
+}
+
+int rsf_graph_create_topk_segments(rsf_graph** out, const rsf_plan* const* plans, const rsf_segment* segs,
+                                   int64_t n_seg, const double* sky, int64_t n_sky, const double* fdot, int64_t n_fdot,
+                                   int k, rsf_topk_entry* topk, void* ws, size_t ws_bytes) {
+    int rc = check_plans(plans, n_seg);
+    if (rc) return rc;
+    return capture_graph_plans(out, plans, n_seg, [&](hipStream_t cs) {
+        return run_segments(plans, segs, n_seg, sky, n_sky, fdot, n_fdot, k, topk, ws, ws_bytes, cs);
     });
 }
 

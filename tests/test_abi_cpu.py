@@ -61,6 +61,20 @@ def test_null_arguments_rejected_without_gpu(lib):
     assert lib.rsf_plan_batching(None, 1, 1, 0, None, None, None) == L.RSF_EINVAL
 
 
+def test_multi_segment_arguments_rejected_without_gpu(lib):
+    b = C.c_size_t()
+    assert lib.rsf_segments_workspace_size(None, 1, 1, 1, C.byref(b)) == L.RSF_EINVAL
+    plans = (C.c_void_p * 2)(None, None)
+    assert lib.rsf_segments_workspace_size(plans, 2, 1, 1, C.byref(b)) == L.RSF_EINVAL
+    assert b"plans[0]" in lib.rsf_last_error()
+    assert lib.rsf_segments_workspace_size(plans, 0, 1, 1, C.byref(b)) == L.RSF_EINVAL
+    assert lib.rsf_fstat_topk_segments(None, None, 1, None, 1, None, 1, 10, None, None, 0, None) == L.RSF_EINVAL
+    g = C.c_void_p()
+    assert lib.rsf_graph_create_topk_segments(C.byref(g), plans, None, 2, None, 1, None, 1, 10, None, None, 0) == \
+        L.RSF_EINVAL
+    assert not g.value
+
+
 def test_invalid_descriptors_rejected_before_device_use(lib):
     from paper_0912_4255_amd import synth
     from paper_0912_4255_amd.api import plan_desc_from_workload
