@@ -295,6 +295,23 @@ int rsf_fstat_backward(const rsf_plan* plan, const rsf_segment* seg, const doubl
                        const float* g_twoF, float* twoF, double* g_theta,
                        void* ws, size_t ws_bytes, void* stream);
 
+/* rsf_fstat_backward for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and results, with the scratch (per-candidate partial sums and the
+ * flags word) in a static device array of the library, 64 MiB per GPU, held
+ * from the first plan created on that GPU until the process ends.  No
+ * workspace argument; nothing is allocated and no instrumentation event is
+ * recorded.  The caller passes theta, g_twoF, twoF (may be NULL) and g_theta
+ * as for rsf_fstat_backward.  Returns RSF_EWORKSPACE (message: the largest n
+ * that fits) when n candidates need more scratch than the array holds (about
+ * 110 KB per candidate at n = 1,728,000 samples, i.e. up to about 600
+ * candidates), RSF_EHIP if the array's device address could not be
+ * resolved.  All calls on one GPU share the array: calls that overlap in
+ * time on one GPU (several streams or threads) race and must be serialised
+ * by the caller.  Flags are cleared at the start of each call. */
+int rsf_fstat_backward_static(const rsf_plan* plan, const rsf_segment* seg, const double* theta, int64_t n,
+                              const float* g_twoF, float* twoF, double* g_theta, void* stream);
+
 /* A batched search captured once into a HIP graph and replayed with one
  * launch (the template loop of Sec. IV.A as a single launchable unit).
  * rsf_graph_create_fstat / _topk record exactly the work of rsf_fstat

@@ -21,7 +21,7 @@ EXPORTS = [
     "rsf_plan_set_spin_order", "rsf_plan_set_binary",
     "rsf_workspace_size",
     "rsf_resample", "rsf_fstat", "rsf_fstat_topk", "rsf_fstat_semicoherent", "rsf_fstat_point",
-    "rsf_fstat_backward",
+    "rsf_fstat_backward", "rsf_fstat_backward_static",
     "rsf_get_flags", "rsf_last_error", "rsf_version", "rsf_profile_enable", "rsf_profile_read",
     "rsf_graph_create_fstat", "rsf_graph_create_topk", "rsf_graph_launch", "rsf_graph_destroy",
     "rsf_segments_workspace_size", "rsf_fstat_topk_segments", "rsf_graph_create_topk_segments",
@@ -110,6 +110,7 @@ def load(path=None):
                                            C.c_double, i64, vp, vp, sz, vp]
     lib.rsf_fstat_point.argtypes = [vp, C.POINTER(Segment), vp, i64, vp, vp, sz, vp]
     lib.rsf_fstat_backward.argtypes = [vp, C.POINTER(Segment), vp, i64, vp, vp, vp, vp, sz, vp]
+    lib.rsf_fstat_backward_static.argtypes = [vp, C.POINTER(Segment), vp, i64, vp, vp, vp, vp]
     lib.rsf_get_flags.argtypes = [vp, vp, C.POINTER(C.c_uint32), vp]
     lib.rsf_graph_create_fstat.argtypes = [C.POINTER(vp), vp, C.POINTER(Segment), vp, i64, vp, i64, vp, vp, sz]
     lib.rsf_graph_create_topk.argtypes = [C.POINTER(vp), vp, C.POINTER(Segment), vp, i64, vp, i64, i32, vp, vp,

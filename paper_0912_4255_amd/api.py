@@ -262,6 +262,23 @@ class Plan:
                                             _ptr(g_theta), _ptr(ws), ws.numel(), _stream()))
         return twoF, g_theta
 
+    def backward_static(self, xs, gaps, theta, g_twoF, twoF=None, g_theta=None):
+        """rsf_fstat_backward_static: as backward, with the library's static
+        device scratch instead of a workspace (outputs may be passed in)."""
+        _need_cuda(theta, torch.float64, "theta")
+        _need_cuda(g_twoF, torch.float32, "g_twoF")
+        n = self._n_theta(theta)
+        seg, keep = self.segment(xs, gaps)
+        dev = xs[0].device
+        twoF = twoF if twoF is not None else torch.empty(n, dtype=torch.float32, device=dev)
+        g_theta = g_theta if g_theta is not None else torch.empty((n, theta.shape[1]), dtype=torch.float64,
+                                                                  device=dev)
+        _need_cuda(twoF, torch.float32, "twoF")
+        _need_cuda(g_theta, torch.float64, "g_theta")
+        L.check(self.lib.rsf_fstat_backward_static(self._p, C.byref(seg), _ptr(theta), n, _ptr(g_twoF), _ptr(twoF),
+                                                   _ptr(g_theta), _stream()))
+        return twoF, g_theta
+
     def graph_fstat(self, xs, gaps, sky, fdot, out=None, ws=None):
         """Capture a batched rsf_fstat call into a HIP graph; returns
         (Graph, out).  Graph.launch() replays it on the current stream."""

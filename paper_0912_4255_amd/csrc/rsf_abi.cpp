@@ -1,6 +1,6 @@
 // C ABI of librsfstat: plans, argument validation, workspace layout and the
 // launch sequences of the resampling F-statistic (declared in rsfstat.h).
-#include <hip/hip_runtime_api.h>
+#include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -16,6 +17,14 @@
 #include "rsf_params.h"
 
 using namespace rsf;
+
+// Device scratch of rsf_fstat_backward_static (the entry for callers that
+// cannot allocate): one array per GPU the library runs on, held until the
+// process ends.  In host code `scratch` is only a stand-in for the symbol;
+// its device address on each GPU comes from hipGetSymbolAddress, resolved
+// once per device (scratch_setup) when the first plan is created there.
+static constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
 
 namespace {
 
@@ -43,6 +52,26 @@ int hip_fail(hipError_t e, const char* what) {
 
 constexpr size_t kAlign = 256;
 constexpr size_t kLastLevelCacheBytes = (size_t)256 << 20;  // MI355X Infinity Cache
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+hipError_t g_scratch_err[kMaxDevices];
+
+// With `device` current: resolve (once) and return its scratch address.
+hipError_t scratch_setup(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device] && g_scratch_err[device] == hipSuccess) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            g_scratch_err[device] = e != hipSuccess ? e : hipErrorInvalidSymbol;
+        else
+            g_scratch_ptr[device] = ptr;
+    }
+    return g_scratch_err[device];
+}
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 bool is_7smooth(int64_t n) {
@@ -434,6 +463,9 @@ int rsf_plan_create(rsf_plan** out, const rsf_plan_desc* d) {
 
     // device limits
     RSF_HIP(hipGetDevice(&p->device), "hipGetDevice");
+    // the static scratch of this device; a failure only disables
+    // rsf_fstat_backward_static, which reports it
+    (void)scratch_setup(p->device);
     int lds_max = 0;
     if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device) != hipSuccess ||
         lds_max <= 0)
@@ -994,7 +1026,8 @@ int rsf_fstat_topk_segments(const rsf_plan* const* plans, const rsf_segment* seg
 
 namespace {
 int point_common(const rsf_plan* p, const rsf_segment* seg, const double* theta, int64_t n, const float* g_twoF,
-                 float* twoF, double* g_theta, void* ws, size_t ws_bytes, void* stream, bool grad) {
+                 float* twoF, double* g_theta, void* ws, size_t ws_bytes, void* stream, bool grad,
+                 bool instrument = true) {
     if (!p) return fail(RSF_EINVAL, "plan is NULL");
     int rc = check_segment(p, seg);
     if (rc) return rc;
@@ -1040,7 +1073,10 @@ int point_common(const rsf_plan* p, const rsf_segment* seg, const double* theta,
     a.n_blocks = L.n_blocks;
     a.partials = (double*)(w + L.partials);
     a.flags = flags;
-    RSF_HIP(timed(p, K_POINT, s, [&] { return launch_point(a, grad, s); }), "point launch");
+    // the static-scratch entry records no instrumentation events
+    const rsf_plan* tp = instrument ? p : nullptr;
+    auto run = [&](int kind, auto fn) { return tp ? timed(tp, kind, s, fn) : fn(); };
+    RSF_HIP(run(K_POINT, [&] { return launch_point(a, grad, s); }), "point launch");
     PointReduceArgs r{};
     r.partials = a.partials;
     r.n_blocks = L.n_blocks;
@@ -1052,7 +1088,7 @@ int point_common(const rsf_plan* p, const rsf_segment* seg, const double* theta,
     r.twoF = twoF;
     r.g_theta = g_theta;
     r.flags = flags;
-    RSF_HIP(timed(p, K_POINT_REDUCE, s, [&] { return launch_point_reduce(r, s); }), "point reduce launch");
+    RSF_HIP(run(K_POINT_REDUCE, [&] { return launch_point_reduce(r, s); }), "point reduce launch");
     return RSF_OK;
 }
 }  // namespace
@@ -1066,6 +1102,25 @@ int rsf_fstat_backward(const rsf_plan* p, const rsf_segment* seg, const double* 
                        const float* g_twoF, float* twoF, double* g_theta, void* ws, size_t ws_bytes,
                        void* stream) {
     return point_common(p, seg, theta, n, g_twoF, twoF, g_theta, ws, ws_bytes, stream, true);
+}
+
+int rsf_fstat_backward_static(const rsf_plan* p, const rsf_segment* seg, const double* theta, int64_t n,
+                              const float* g_twoF, float* twoF, double* g_theta, void* stream) {
+    if (!p) return fail(RSF_EINVAL, "plan is NULL");
+    if (n < 1 || n > 65535) return fail(RSF_EINVAL, "number of candidates must be in 1..65535");
+    const hipError_t e = scratch_setup(p->device);
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    const size_t need = point_layout(p, n).total;
+    if (need > kStaticScratchBytes) {
+        const size_t per = point_layout(p, 2).total - point_layout(p, 1).total;
+        return fail(RSF_EWORKSPACE,
+                    "%lld candidates need %zu bytes of device scratch, above the static %zu bytes (at most %lld "
+                    "candidates at this plan's length)",
+                    (long long)n, need, kStaticScratchBytes,
+                    (long long)((kStaticScratchBytes - point_layout(p, 1).total) / per + 1));
+    }
+    return point_common(p, seg, theta, n, g_twoF, twoF, g_theta, g_scratch_ptr[p->device], kStaticScratchBytes,
+                        stream, true, false);
 }
 
 }  // extern "C"
