@@ -61,6 +61,9 @@ def parse():
     ap.add_argument("--no-hetdec", action="store_true", help="skip the time-domain front end")
     ap.add_argument("--c3-segments", type=int, default=64)
     ap.add_argument("--c3-sky", type=int, default=8)
+    ap.add_argument("--replay-seconds", type=float, default=10.0,
+                    help="time replays one by one for at least this long (0: only --replay-min replays)")
+    ap.add_argument("--replay-min", type=int, default=5)
     return ap.parse_args()
 
 
@@ -500,10 +503,10 @@ def main():
     ms_step = (t1 - t0) * 1e3 / a.steps
     value = n_t * a.steps / (t1 - t0)
 
-    # replays timed one by one until >= 5 replays and >= 10 s: the median
+    # replays timed one by one until >= 5 replays and >= 10 s (defaults): the median
     ev = []
     t_start = time.perf_counter()
-    while len(ev) < 5 or time.perf_counter() - t_start < 10.0:
+    while len(ev) < a.replay_min or time.perf_counter() - t_start < a.replay_seconds:
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         graph.launch()

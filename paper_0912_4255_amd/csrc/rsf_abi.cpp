@@ -852,6 +852,7 @@ int run_fstat(const rsf_plan* p, const rsf_segment* seg, const double* sky, int6
             B.f0 = q.f0;
             B.nf_l = q.nf;
             B.n_tmpl = q.ns * q.nf;
+            B.wave = fft_pass_b_wave_e(p->LB) != 0 ? 1 : 0;
             RSF_HIP(timed(p, K_PASS_B, s, [&] { return launch_fft_pass_b(B, p->n_cu, s); }), "pass B launch");
 
             if (semico) {

@@ -12,8 +12,9 @@
 // W_N^{n_b k_a} and spills in groups of 4 consecutive k_a (64-B rows).
 // Pass B: persistent workgroups over blocks of 8 consecutive k_a (two
 // adjacent spill groups, one contiguous run).  Each block is transformed
-// over n_b in LDS and every bin reduced to
-// 2F = cA |f_a|^2 + cB |f_b|^2 + cC Re(f_a f_b^*), written in ascending
+// over n_b, one column per wave in registers when LB = 64 E (E = 4, 8, 12),
+// otherwise as 8 columns through LDS Stockham stages, and every bin reduced
+// to 2F = cA |f_a|^2 + cB |f_b|^2 + cC Re(f_a f_b^*), written in ascending
 // frequency over the reported band.
 #include <algorithm>
 
@@ -287,6 +288,256 @@ __global__ __launch_bounds__(kNTB) void rsf_fft_pass_b_k(PassBArgs B) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Second pass, one column per wave (columns of LB = 64 E points, E = 4, 8,
+// 12).  Persistent workgroups of 8 waves take the same 8-column blocks as
+// rsf_fft_pass_b_k; wave b transforms column b of the block in its own
+// registers:
+//   n = l + 64 m (lane l < 64, m < E), k = k1 + E k2:
+//   X[k1 + E k2] = sum_l W_64^{l k2} W_LB^{l k1} sum_m x[l + 64 m] W_E^{m k1}.
+// The radix-E DFT over m runs in each lane's registers; the 64-point DFT over
+// the lanes is three radix-4 steps (l = 16 l1 + 4 a1 + a0 against
+// k2 = k2a + 4 b0 + 16 b1), each after a 4 x 4 exchange of value blocks
+// among four lanes: the lanes at stride 16 (the wave's four rows) by row
+// swaps in registers, the lanes at stride 4 and 1 through a 4 KB LDS region
+// of the wave, so no workgroup barrier is needed inside the transform.
+// Every twiddle a lane applies (W_LB^{l k1}, W_64^{l0 k2a}, W_16^{a0 b0})
+// is fixed for the kernel and computed once.
+// The block arrives by DMA (HBM -> LDS, 1 KB of contiguous spill per wave
+// instruction, stored column-major per 1 KB so that a column is read back
+// without bank conflicts); the next block's DMA runs while the current one
+// is transformed.  2F goes through an LDS stage so that each output row of
+// eight bins is written as 32 contiguous bytes.  Stores and loads share one
+// counter on this hardware, and once stores are outstanding a wait for a
+// load waits for every outstanding operation, so the stores of a block are
+// issued just before the DMA of the block after next, and each block's
+// single wait covers operations issued a whole transform earlier.
+// ---------------------------------------------------------------------------
+constexpr int kWaveColsThreads = 64 * kPassBCols;
+
+// DMA of block `unit` (two spill groups of 4 columns x LB rows, one
+// contiguous run) into dst: chunk i of 64 float4 (16 rows x 4 columns of one
+// group) goes to dst + 64 i with row r, column c at slot 16 c + r.
+template <bool NT>
+__device__ __forceinline__ void wave_dma(const PassBArgs& B, int unit, float4* dst, int wave, int lane) {
+    const int t = unit / B.n_groups;
+    const int g = unit - t * B.n_groups;
+    const float4* base = B.spill + (int64_t)t * B.spill_tmpl_stride + (int64_t)g * B.LB * kPassBCols;
+    const int n_chunks = B.LB * kPassBCols / 64;
+    const int src = 4 * (lane & 15) + (lane >> 4);  // lane 16 c + r takes float4 4 r + c of the chunk
+    for (int i = wave; i < n_chunks; i += kPassBCols)
+        __builtin_amdgcn_global_load_lds((const void*)(base + 64 * i + src),
+                                         (__attribute__((address_space(3))) void*)(dst + 64 * i), 16, 0, NT ? 2 : 0);
+}
+
+// Column b of the block in LDS, rows l + 64 m of lane l.
+template <int E>
+__device__ __forceinline__ void wave_col_read(const float4* blk, int b, int lane, cp (&v)[E]) {
+    constexpr int LB = 64 * E;
+    const float4* col = blk + (b >> 2) * (LB / 16) * 64 + 64 * (lane >> 4) + 16 * (b & 3) + (lane & 15);
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = col[256 * m];
+}
+
+// Exchange among the lanes {src0 + i s : i < 4} as a 4 x 4 transpose of
+// value blocks (K = 2: stride 4, K = 3: stride 1): the lane at position c of
+// its group receives, for each value group e < E/4, the register c Q + e of
+// the lane at position i as its register i Q + e.  One value group at a
+// time through the wave's region of 4 x 64 slots; slot (row c', lane l) at
+// c' * 64 + (l ^ X(c')), X = 4 c' (K = 2) or c' (K = 3), so that the 16
+// lanes an LDS cycle serves read 16 different bank groups.
+template <int E, int K>
+__device__ __forceinline__ void wave_exchange(cp* __restrict__ x, int lane, int c, int src0, int s, cp (&v)[E]) {
+    constexpr int Q = E / 4;
+#pragma unroll
+    for (int e = 0; e < Q; ++e) {
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) x[cc * 64 + (lane ^ (K == 2 ? 4 * cc : cc))] = v[cc * Q + e];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int xr = K == 2 ? 4 * c : c;
+        const cp* row = x + c * 64;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[i * Q + e] = row[(src0 + i * s) ^ xr];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+// The exchange among the lanes at stride 16 (the four 16-lane rows of the
+// wave) as a register transpose: row p receives from row i its registers
+// [p Q, p Q + Q) as registers [i Q, i Q + Q).  For each dword of a value
+// group the 4 x 4 (register block, row) transpose is two steps of row
+// swaps: v_permlane32_swap exchanges the upper 32 lanes of one register with
+// the lower 32 of another (blocks 0/2 and 1/3), then v_permlane16_swap the
+// odd rows of one with the even rows of another (blocks 0/1 and 2/3).
+__device__ __forceinline__ void row_transpose4(float& x0, float& x1, float& x2, float& x3) {
+    const auto a = __builtin_amdgcn_permlane32_swap(__float_as_uint(x0), __float_as_uint(x2), false, false);
+    const auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(x1), __float_as_uint(x3), false, false);
+    const auto c = __builtin_amdgcn_permlane16_swap(a[0], b[0], false, false);
+    const auto d = __builtin_amdgcn_permlane16_swap(a[1], b[1], false, false);
+    x0 = __uint_as_float(c[0]);
+    x1 = __uint_as_float(c[1]);
+    x2 = __uint_as_float(d[0]);
+    x3 = __uint_as_float(d[1]);
+}
+
+template <int E>
+__device__ __forceinline__ void wave_exchange_rows(cp (&v)[E]) {
+    constexpr int Q = E / 4;
+#pragma unroll
+    for (int e = 0; e < Q; ++e) {
+        row_transpose4(v[e].x, v[Q + e].x, v[2 * Q + e].x, v[3 * Q + e].x);
+        row_transpose4(v[e].y, v[Q + e].y, v[2 * Q + e].y, v[3 * Q + e].y);
+        row_transpose4(v[e].z, v[Q + e].z, v[2 * Q + e].z, v[3 * Q + e].z);
+        row_transpose4(v[e].w, v[Q + e].w, v[2 * Q + e].w, v[3 * Q + e].w);
+    }
+}
+
+// Radix-4 DFT over the exchanged index i for each of the Q value groups.
+template <int E>
+__device__ __forceinline__ void wave_dft4(cp (&v)[E]) {
+    constexpr int Q = E / 4;
+#pragma unroll
+    for (int e = 0; e < Q; ++e) {
+        cp t[4] = {v[e], v[Q + e], v[2 * Q + e], v[3 * Q + e]};
+        Dft<4>::run(t);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[i * Q + e] = t[i];
+    }
+}
+
+// The lane's fixed twiddles.
+template <int E>
+struct WaveTw {
+    float2 w1[E];  // W_LB^{l k1}, k1 < E (w1[0] unused)
+    float2 wa[4];  // W_64^{l0 k2a}
+    float2 wb[4];  // W_16^{a0 b0}
+};
+
+// The column transform of one lane: registers (b1, e) come out holding bin
+// k_b = Q p + e + E (q + 4 r + 16 b1), lane = 16 p + 4 q + r.
+template <int E>
+__device__ __forceinline__ void wave_transform(const WaveTw<E>& tw, cp* x, int lane, cp (&v)[E]) {
+    constexpr int Q = E / 4;
+    const int p = lane >> 4, q = (lane >> 2) & 3, r = lane & 3;
+    Dft<E>::run(v);                                     // over m -> k1
+#pragma unroll
+    for (int k = 1; k < E; ++k) v[k] = cp_rot(v[k], tw.w1[k]);
+    wave_exchange_rows<E>(v);                           // k1 block p gathers its four l1 values
+    wave_dft4<E>(v);                                    // over l1 -> k2a
+#pragma unroll
+    for (int k = 1; k < 4; ++k)
+#pragma unroll
+        for (int e = 0; e < Q; ++e) v[k * Q + e] = cp_rot(v[k * Q + e], tw.wa[k]);
+    wave_exchange<E, 2>(x, lane, q, 16 * p + r, 4, v);  // lane q takes k2a = q
+    wave_dft4<E>(v);                                    // over a1 -> b0
+#pragma unroll
+    for (int k = 1; k < 4; ++k)
+#pragma unroll
+        for (int e = 0; e < Q; ++e) v[k * Q + e] = cp_rot(v[k * Q + e], tw.wb[k]);
+    wave_exchange<E, 3>(x, lane, r, 16 * p + 4 * q, 1, v);  // lane r takes b0 = r
+    wave_dft4<E>(v);                                    // over a0 -> b1
+}
+
+// The 2F rows of block `unit` from the stage ([k_b][8] floats, columns
+// XOR-swizzled by bits 3..5 of k_b against bank conflicts): rows of eight
+// bins, 32 contiguous bytes each; every stage value is read before any
+// store is issued.
+template <int E>
+__device__ __forceinline__ void wave_output(const PassBArgs& B, int unit, const float* st, int tid, int hnf, int nf) {
+    const int t = unit / B.n_groups;
+    const int g = unit - t * B.n_groups;
+    const int s_l = t / B.nf_l;
+    const int f = t - s_l * B.nf_l;
+    const int64_t out_row = B.map_rows ? (int64_t)t : (B.sky0 + s_l) * B.n_fdot + B.f0 + f;
+    float* out = B.twoF + out_row * B.n_out;
+    const int col = tid & 7;
+    const int kac = g * kPassBCols + col;
+    float v[E];
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+        const int kb = (tid >> 3) + 64 * j;
+        v[j] = st[kb * kPassBCols + (col ^ ((kb >> 3) & 7))];
+    }
+    if (kac < B.LA) {
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            const int kb = (tid >> 3) + 64 * j;
+            const int k = kac + B.LA * kb;
+            const int o = ((k < hnf) ? k : k - nf) - (int)B.s_lo;
+            if ((unsigned)o < (unsigned)B.n_out) out[(unsigned)o] = v[j];
+        }
+    }
+}
+
+template <int E, bool NT>
+__global__ __launch_bounds__(kWaveColsThreads) void rsf_fft_pass_b_wave_k(PassBArgs B) {
+    constexpr int Q = E / 4;
+    constexpr int LBW = 64 * E;
+    extern __shared__ float4 lds[];
+    float4* blk = lds;                                              // the block, 8 columns x LB
+    cp* xch = lds + kPassBCols * LBW;                               // 8 waves x 4 x 64 slots
+    float* st = reinterpret_cast<float*>(xch + kPassBCols * 4 * 64);  // 2F stage [LB][8]
+    float* cfl = st + LBW * kPassBCols;                             // 4 per sky of the launch
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int p = lane >> 4, q = (lane >> 2) & 3, r = lane & 3;
+    for (int i = tid; i < 4 * B.n_sky_l; i += kWaveColsThreads) cfl[i] = B.coef[i];
+    // the lane's fixed twiddles from W_LB^m = hi[m >> 5] lo[m & 31]
+    WaveTw<E> tw;
+    auto w_lb = [&](int m) { return c_mul(B.tw_hi[m >> kTwLoBits], B.tw_lo[m & 31]); };
+#pragma unroll
+    for (int k = 1; k < E; ++k) tw.w1[k] = w_lb(lane * k);
+#pragma unroll
+    for (int k = 1; k < 4; ++k) {
+        tw.wa[k] = w_lb(E * (lane & 15) * k);
+        tw.wb[k] = w_lb(4 * E * (lane & 3) * k);
+    }
+    cp* x = xch + wave * 4 * 64;
+    const int hnf = (int)((B.n_fft + 1) >> 1);
+    const int nf = (int)B.n_fft;
+    const int n_units = B.n_tmpl * B.n_groups;
+    const int G = (int)gridDim.x;
+    int unit = blockIdx.x;
+    if (unit < n_units) wave_dma<NT>(B, unit, blk, wave, lane);
+    int prev = -1;
+    for (; unit < n_units; unit += G) {
+        // this block's DMA (and the previous block's stores) are complete in
+        // every wave; the previous block's stage is complete
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        const int t = unit / B.n_groups;
+        const int ka = (unit - t * B.n_groups) * kPassBCols + wave;
+        const bool live = ka < B.LA;
+        cp v[E];
+        if (live) wave_col_read<E>(blk, wave, lane, v);
+        if (prev >= 0) wave_output<E>(B, prev, st, tid, hnf, nf);
+        __syncthreads();  // the block buffer and the stage are free
+        if (unit + G < n_units) wave_dma<NT>(B, unit + G, blk, wave, lane);
+        if (live) {
+            wave_transform<E>(tw, x, lane, v);
+            const int s_l = t / B.nf_l;
+            const float cA = cfl[4 * s_l], cB = cfl[4 * s_l + 1], cC = cfl[4 * s_l + 2];
+#pragma unroll
+            for (int b1 = 0; b1 < 4; ++b1)
+#pragma unroll
+                for (int e = 0; e < Q; ++e) {
+                    const cp u = v[b1 * Q + e];
+                    const int kb = Q * p + e + E * (q + 4 * r + 16 * b1);
+                    st[kb * kPassBCols + (wave ^ ((kb >> 3) & 7))] =
+                        cA * (u.x * u.x + u.y * u.y) + cB * (u.z * u.z + u.w * u.w) + cC * (u.x * u.z + u.y * u.w);
+                }
+        }
+        prev = unit;
+    }
+    if (prev >= 0) {
+        __syncthreads();
+        wave_output<E>(B, prev, st, tid, hnf, nf);
+    }
+}
+
 int fft_pass_max_elems() { return kFftMaxLen < kNT * kEPT ? kFftMaxLen : kNT * kEPT; }
 
 size_t fft_pass_a_lds(int LA) { return (size_t)LA * sizeof(float4) + (32 + (LA + 31) / 32) * sizeof(float2); }
@@ -310,7 +561,16 @@ hipError_t launch_fft_pass_a(const PassAArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Columns of 64 E points, E = 4, 8, 12: the one-column-per-wave second pass.
+int fft_pass_b_wave_e(int LB) {
+    const int E = LB / 64;
+    return (LB % 64 == 0 && (E == 4 || E == 8 || E == 12)) ? E : 0;
+}
+
 size_t fft_pass_b_lds(int LB, int n_sky_l) {
+    if (fft_pass_b_wave_e(LB))
+        return (size_t)kPassBCols * LB * sizeof(float4) + (size_t)kPassBCols * 4 * 64 * sizeof(float4) +
+               (size_t)LB * kPassBCols * sizeof(float) + (size_t)4 * std::max(n_sky_l, 64) * sizeof(float);
     const size_t buf = (size_t)((LB * kPassBCols + 63) / 64) * 64;
     return buf * sizeof(float4) + (32 + (LB + 31) / 32) * sizeof(float2) + (size_t)4 * n_sky_l * sizeof(float);
 }
@@ -319,6 +579,20 @@ hipError_t launch_fft_pass_b(const PassBArgs& b, int n_cu, hipStream_t s) {
     const size_t lds = fft_pass_b_lds(b.LB, b.n_sky_l);
     const int n_items = b.n_tmpl * b.n_groups;
     const unsigned grid = (unsigned)std::max(1, std::min(n_items, n_cu));
+#define RSF_PASS_B_WAVE(EE)                                                                                     \
+    case EE:                                                                                                    \
+        if (b.nt_spill)                                                                                         \
+            hipLaunchKernelGGL((rsf_fft_pass_b_wave_k<EE, true>), dim3(grid), dim3(kWaveColsThreads), lds, s, b);  \
+        else                                                                                                    \
+            hipLaunchKernelGGL((rsf_fft_pass_b_wave_k<EE, false>), dim3(grid), dim3(kWaveColsThreads), lds, s, b); \
+        return hipGetLastError();
+    switch (b.wave ? fft_pass_b_wave_e(b.LB) : 0) {
+        RSF_PASS_B_WAVE(4)
+        RSF_PASS_B_WAVE(8)
+        RSF_PASS_B_WAVE(12)
+        default: break;
+    }
+#undef RSF_PASS_B_WAVE
     if (b.nt_spill)
         hipLaunchKernelGGL(rsf_fft_pass_b_k<true>, dim3(grid), dim3(kNTB), lds, s, b);
     else
@@ -331,10 +605,13 @@ hipError_t fft_set_lds_limits(size_t bytes) {
     // undo a larger one
     static size_t granted = 0;
     if (bytes <= granted) return hipSuccess;
-    const void* fns[] = {(const void*)rsf_fft_pass_a_k<1, false>, (const void*)rsf_fft_pass_a_k<2, false>,
-                         (const void*)rsf_fft_pass_a_k<3, false>, (const void*)rsf_fft_pass_a_k<1, true>,
-                         (const void*)rsf_fft_pass_a_k<2, true>,  (const void*)rsf_fft_pass_a_k<3, true>,
-                         (const void*)rsf_fft_pass_b_k<false>,    (const void*)rsf_fft_pass_b_k<true>};
+    const void* fns[] = {(const void*)rsf_fft_pass_a_k<1, false>,     (const void*)rsf_fft_pass_a_k<2, false>,
+                         (const void*)rsf_fft_pass_a_k<3, false>,     (const void*)rsf_fft_pass_a_k<1, true>,
+                         (const void*)rsf_fft_pass_a_k<2, true>,      (const void*)rsf_fft_pass_a_k<3, true>,
+                         (const void*)rsf_fft_pass_b_k<false>,        (const void*)rsf_fft_pass_b_k<true>,
+                         (const void*)rsf_fft_pass_b_wave_k<4, false>, (const void*)rsf_fft_pass_b_wave_k<4, true>,
+                         (const void*)rsf_fft_pass_b_wave_k<8, false>, (const void*)rsf_fft_pass_b_wave_k<8, true>,
+                         (const void*)rsf_fft_pass_b_wave_k<12, false>, (const void*)rsf_fft_pass_b_wave_k<12, true>};
     hipError_t out = hipSuccess;
     for (const void* f : fns) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);

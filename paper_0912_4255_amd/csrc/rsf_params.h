@@ -162,6 +162,7 @@ struct PassBArgs {
     int64_t sky0, n_fdot, f0;
     int nf_l;
     int n_tmpl;
+    int wave;                 // one column per wave when LB = 64 E, E = 4, 8, 12 (else the LDS-stage kernel)
 };
 
 // Top-k over a scratch map of 2F rows (template t = s nf_l + f of a launch):
