@@ -43,7 +43,11 @@
  * A run of 64 consecutive resampled times whose interpolation windows span
  * more detector samples than a wave stages (only for time compressions far
  * beyond any physical Doppler factor) yields NaN samples there and sets
- * RSF_FLAG_WINDOW.
+ * RSF_FLAG_WINDOW.  A binary orbit outside the admitted range (see
+ * rsf_plan_set_binary) makes the kernels that read it set RSF_FLAG_ORBIT and
+ * give NaN: every resampled sample of that sky row, hence every 2F of its
+ * templates (which top-k selection then skips), or that candidate's 2F and
+ * gradient in rsf_fstat_point / rsf_fstat_backward.
  */
 #ifndef RSFSTAT_H
 #define RSFSTAT_H
@@ -74,7 +78,7 @@ enum {
     RSF_ENTRY_RESAMPLE = 0, RSF_ENTRY_FSTAT = 1, RSF_ENTRY_POINT = 2, RSF_ENTRY_BACKWARD = 3, RSF_ENTRY_TOPK = 4,
     RSF_ENTRY_SEMICOHERENT = 5
 };
-enum { RSF_FLAG_DEGENERATE = 1, RSF_FLAG_WINDOW = 2 };
+enum { RSF_FLAG_DEGENERATE = 1, RSF_FLAG_WINDOW = 2, RSF_FLAG_ORBIT = 4 };
 
 /* Interferometer site: latitude, longitude (rad, east positive), azimuth of
  * the arm bisector counter-clockwise from local East (rad; arms at +-45 deg),
@@ -159,9 +163,10 @@ int rsf_plan_set_spin_order(rsf_plan* plan, int order);
 
 /* Sources in circular binary orbits (on != 0; default off).  Every `sky`
  * argument becomes double [n_sky][5]: (alpha, delta, a_p, P_b, t_asc) with
- * the projected semi-major axis a_p in light-seconds (>= 0), the period P_b
- * in seconds (> 0, 2 pi a_p / P_b <= 1e-2) and the time of the ascending node
- * t_asc on the clock of t_start.  A wavefront emitted at tau_e reaches the
+ * the projected semi-major axis a_p in light-seconds (0 <= a_p <= 100), the
+ * period P_b in seconds (finite, > 0, 2 pi a_p / P_b <= 1e-2) and the time of
+ * the ascending node t_asc (finite) on the clock of t_start; rows outside
+ * this range give NaN and RSF_FLAG_ORBIT.  A wavefront emitted at tau_e reaches the
  * SSB at tau_e + R(tau_e), R = a_p sin(2 pi (tau_e - t_asc) / P_b).  The
  * resampled grid is then regular in emission time: T^k solves
  * T + t_m(T) = k dt + R(t_start + k dt), and the heterodyne correction and

@@ -6,7 +6,7 @@ include/rsfstat.h.  This package is the thin Python binding.
 """
 from ._lib import (RSF_ENTRY_BACKWARD, RSF_ENTRY_FSTAT, RSF_ENTRY_POINT, RSF_ENTRY_RESAMPLE,
                    RSF_ENTRY_SEMICOHERENT, RSF_ENTRY_TOPK,
-                   RSF_FLAG_DEGENERATE, RSF_FLAG_WINDOW, RSF_MODE_BATCHED, RSF_MODE_PLAIN, RsfError,
+                   RSF_FLAG_DEGENERATE, RSF_FLAG_ORBIT, RSF_FLAG_WINDOW, RSF_MODE_BATCHED, RSF_MODE_PLAIN, RsfError,
                    load)
 
 

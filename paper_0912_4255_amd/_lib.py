@@ -14,7 +14,7 @@ RSF_OK, RSF_EINVAL, RSF_EUNSUPPORTED, RSF_EWORKSPACE, RSF_EHIP = 0, -1, -2, -3, 
 RSF_MODE_PLAIN, RSF_MODE_BATCHED = 0, 1
 RSF_ENTRY_RESAMPLE, RSF_ENTRY_FSTAT, RSF_ENTRY_POINT, RSF_ENTRY_BACKWARD, RSF_ENTRY_TOPK = 0, 1, 2, 3, 4
 RSF_ENTRY_SEMICOHERENT = 5
-RSF_FLAG_DEGENERATE, RSF_FLAG_WINDOW = 1, 2
+RSF_FLAG_DEGENERATE, RSF_FLAG_WINDOW, RSF_FLAG_ORBIT = 1, 2, 4
 
 EXPORTS = [
     "rsf_plan_create", "rsf_plan_destroy", "rsf_plan_query", "rsf_plan_set_batching", "rsf_plan_batching", "rsf_fft_factor",

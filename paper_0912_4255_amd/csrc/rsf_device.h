@@ -210,13 +210,52 @@ struct DftCT {
     }
 };
 
-template <> struct Dft<6> : DftCT<2, 3> {};
+// x with x a = 1 (mod m), for a coprime to m
+constexpr int inv_mod(int a, int m) {
+    for (int x = 1; x < m; ++x)
+        if ((a * x) % m == 1) return x;
+    return 1;
+}
+
+// Composite radix R = P * Q with P, Q coprime (prime-factor algorithm), in
+// place: with input index n = (Q n1 + P n2) mod R and output index
+// k = (eP k1 + eQ k2) mod R, where eP = 1 (mod P), 0 (mod Q) and eQ = 0
+// (mod P), 1 (mod Q), the kernel factors as W_R^{nk} = W_P^{n1 k1} W_Q^{n2 k2}:
+// P-point DFTs over n1, then Q-point DFTs over n2, and no twiddle factors
+// between them.  Both index maps are register permutations.
+template <int P, int Q>
+struct DftPFA {
+    __device__ __forceinline__ static void run(cp* x) {
+        constexpr int R = P * Q;
+        constexpr int eP = Q * inv_mod(Q % P, P);
+        constexpr int eQ = P * inv_mod(P % Q, Q);
+        static_assert(eP % P == 1 % P && eP % Q == 0 && eQ % P == 0 && eQ % Q == 1 % Q, "P, Q not coprime");
+        cp u[P][Q];
+#pragma unroll
+        for (int n2 = 0; n2 < Q; ++n2) {
+            cp t[P];
+#pragma unroll
+            for (int n1 = 0; n1 < P; ++n1) t[n1] = x[(Q * n1 + P * n2) % R];
+            Dft<P>::run(t);
+#pragma unroll
+            for (int k1 = 0; k1 < P; ++k1) u[k1][n2] = t[k1];
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < P; ++k1) {
+            Dft<Q>::run(u[k1]);
+#pragma unroll
+            for (int k2 = 0; k2 < Q; ++k2) x[(eP * k1 + eQ * k2) % R] = u[k1][k2];
+        }
+    }
+};
+
+template <> struct Dft<6> : DftPFA<2, 3> {};
 template <> struct Dft<8> : DftCT<2, 4> {};
 template <> struct Dft<9> : DftCT<3, 3> {};
-template <> struct Dft<10> : DftCT<2, 5> {};
-template <> struct Dft<12> : DftCT<3, 4> {};
-template <> struct Dft<14> : DftCT<2, 7> {};
-template <> struct Dft<15> : DftCT<3, 5> {};
+template <> struct Dft<10> : DftPFA<2, 5> {};
+template <> struct Dft<12> : DftPFA<3, 4> {};
+template <> struct Dft<14> : DftPFA<2, 7> {};
+template <> struct Dft<15> : DftPFA<3, 5> {};
 template <> struct Dft<16> : DftCT<4, 4> {};
 
 // ---------------------------------------------------------------------------
@@ -558,6 +597,18 @@ __device__ __forceinline__ Inversion invert_ssb(double t_start, double tb, const
 struct BinaryOrbit {
     double a_p, p_orb, t_asc;
 };
+// Orbits the timing code is built for: 0 <= a_p <= 100 light-s, finite
+// P_b > 0 with 2 pi a_p / P_b <= 1e-2 (the contraction of the emission-time
+// iteration), finite t_asc.  NaN fails every comparison and is refused.
+__device__ __forceinline__ bool orbit_admitted(const BinaryOrbit& b) {
+    return b.a_p >= 0.0 && b.a_p <= 100.0 && b.p_orb > 0.0 && b.p_orb < 1e300 &&
+           2.0 * kPi * b.a_p <= 1e-2 * b.p_orb && fabs(b.t_asc) < 1e300;
+}
+// A refused orbit is replaced by this one (no delay) so that every loop and
+// index stays well defined; the caller then writes NaN outputs.
+__device__ __forceinline__ BinaryOrbit orbit_or_none(const BinaryOrbit& b) {
+    return orbit_admitted(b) ? b : BinaryOrbit{0.0, 1.0, 0.0};
+}
 __device__ __forceinline__ double binary_delay(const BinaryOrbit& b, double tau_e) {
     const double cyc = (tau_e - b.t_asc) / b.p_orb;
     return b.a_p * sin(2.0 * kPi * (cyc - floor(cyc)));

@@ -97,8 +97,105 @@ __device__ __forceinline__ void accumulate_integrand(cp& y, const Sample<ORDER>&
 // Inputs of one row held per thread: n_a = tid + q * kNT, q < kInPer (P <= LA/2 <= 5120).
 constexpr int kInPer = (kFftMaxLen / 2 + kNT - 1) / kNT;
 
+// ---------------------------------------------------------------------------
+// First-pass rows with the radix sequence fixed at compile time (the row
+// length of the 10-day and 30-day workloads, 9000 = 10 10 10 9, with its
+// upper half zero).  Stage sizes are constants, so the butterfly index
+// arithmetic folds, and the twiddles of the two middle stages come from
+// per-stage tables in LDS, W_{Ns R}^{k r} at [r - 1][k], instead of being
+// formed by complex multiplications in every butterfly.
+// ---------------------------------------------------------------------------
+constexpr int kRow9000 = 1;
+constexpr int kRow9000Tab = 9 * 10 + 9 * 100;  // table entries of stages Ns = 10 and Ns = 100
+
+// One middle (or first) stage of length L after Ns points, radix R; table
+// tab = W_{Ns R}^{k r} at [r - 1][k] (unused when Ns = 1).  HZ: the upper
+// half of the input is zero.
+template <int L, int Ns, int R, bool HZ>
+__device__ __forceinline__ void row_stage(cp* __restrict__ s, const float2* __restrict__ tab) {
+    constexpr int LR = L / R;
+    constexpr int MAXB = (LR + kNT - 1) / kNT;
+    cp v[MAXB][R];
+    const int tid = opaque_tid();
+#pragma unroll
+    for (int q = 0; q < MAXB; ++q) {
+        const int j = tid + q * kNT;
+        if (q + 1 < MAXB || j < LR) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[q][r] = (HZ && 2 * r >= R) ? make_float4(0.f, 0.f, 0.f, 0.f) : s[j + r * LR];
+            if constexpr (Ns > 1) {
+                const int k = j % Ns;
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[q][r] = cp_rot(v[q][r], tab[(r - 1) * Ns + k]);
+            }
+            Dft<R>::run(v[q]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < MAXB; ++q) {
+        const int j = tid + q * kNT;
+        if (q + 1 < MAXB || j < LR) {
+            const int jq = j / Ns, k = j - jq * Ns;
+            cp* p = s + (jq * Ns * R + k);
+#pragma unroll
+            for (int r = 0; r < R; ++r) p[r * Ns] = v[q][r];
+        }
+    }
+    __syncthreads();
+}
+
+// The last stage (Ns R = L): butterfly j reads x[j + r Ns], rotates input r
+// by W_L^{j r} and hands its R outputs to the sink, in q order.
+template <int L, int R, typename Sink>
+__device__ __forceinline__ void row_last(const cp* __restrict__ s, const TwLds& tw, Sink& sink) {
+    constexpr int LR = L / R;
+    constexpr int MAXB = (LR + kNT - 1) / kNT;
+    const int tid = opaque_tid();
+#pragma unroll
+    for (int q = 0; q < MAXB; ++q) {
+        const int j = tid + q * kNT;
+        if (q + 1 < MAXB || j < LR) {
+            cp v[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[r] = s[j + r * LR];
+            bfly_dft<R, TwLds>(j, LR, 1, tw, v);
+            sink.template put<R>(q, j, 0, v);
+        }
+    }
+}
+
+// Fill the stage tables of the 9000-point row from the two-level table.
+__device__ __forceinline__ void row9000_tables(float2* tab, const TwLds& tw) {
+    for (int i = threadIdx.x; i < kRow9000Tab; i += kNT) {
+        const bool s2 = i < 90;
+        const int Ns = s2 ? 10 : 100;
+        const int e = s2 ? i : i - 90;
+        const int r = e / Ns + 1, k = e - (r - 1) * Ns;
+        tab[i] = tw(k * r * (9000 / (Ns * 10)));
+    }
+}
+
+template <typename Sink>
+__device__ __forceinline__ void row9000_fft(cp* __restrict__ s, const float2* __restrict__ tab, const TwLds& tw,
+                                            Sink& sink) {
+    row_stage<9000, 1, 10, true>(s, nullptr);
+    row_stage<9000, 10, 10, false>(s, tab);
+    row_stage<9000, 100, 10, false>(s, tab + 90);
+    row_last<9000, 9>(s, tw, sink);
+}
+
+// The fixed plan a first-pass launch can take (0: the general stages).
+__host__ __device__ inline int fixed_row_plan(const FftStages& st, bool prune) {
+    return (prune && st.len == 9000 && st.n_stages == 4 && st.radix[0] == 10 && st.radix[1] == 10 &&
+            st.radix[2] == 10 && st.radix[3] == 9)
+               ? kRow9000
+               : 0;
+}
+
 // NT: the launch's spill is larger than the last-level cache (non-temporal stores)
-template <int ORDER, bool NT>
+// PLAN: a fixed row plan (kRow9000), or 0 for the planned stages of A.st.
+template <int ORDER, bool NT, int PLAN>
 __global__ __launch_bounds__(kNT) void rsf_fft_pass_a_k(PassAArgs A) {
     extern __shared__ float4 lds[];
     // stage twiddles in LDS after the row: no global load inside the stages,
@@ -107,6 +204,11 @@ __global__ __launch_bounds__(kNT) void rsf_fft_pass_a_k(PassAArgs A) {
     const int n_hi = (A.LA + 31) >> kTwLoBits;
     for (int i = threadIdx.x; i < 32 + n_hi; i += kNT) twl[i] = (i < 32) ? A.tws_lo[i] : A.tws_hi[i - 32];
     const TwLds tws{twl, twl + 32};
+    float2* tab = twl + 32 + n_hi;
+    if constexpr (PLAN == kRow9000) {
+        __syncthreads();  // the two-level table is complete
+        row9000_tables(tab, tws);
+    }
     const int n_b = blockIdx.x;
     const int gpf = (A.nf_l + A.fb - 1) / A.fb;       // spindown groups per sky
     const int s_l = blockIdx.y / gpf;
@@ -180,7 +282,10 @@ __global__ __launch_bounds__(kNT) void rsf_fft_pass_a_k(PassAArgs A) {
         __syncthreads();
         SpillSink<NT> sink{reinterpret_cast<char*>(A.spill + (int64_t)t * A.spill_tmpl_stride), A.LB, n_b, lr,
                            w_base, w_step, w_lr};
-        lds_fft_into<kNT, kEPT, 1, false>(lds, A.st, tws, Interleaved<1>{}, sink, NoMid{}, prune);
+        if constexpr (PLAN == kRow9000)
+            row9000_fft(lds, tab, tws, sink);
+        else
+            lds_fft_into<kNT, kEPT, 1, false>(lds, A.st, tws, Interleaved<1>{}, sink, NoMid{}, prune);
         __syncthreads();
     }
 }
@@ -540,21 +645,32 @@ __global__ __launch_bounds__(kWaveColsThreads) void rsf_fft_pass_b_wave_k(PassBA
 
 int fft_pass_max_elems() { return kFftMaxLen < kNT * kEPT ? kFftMaxLen : kNT * kEPT; }
 
-size_t fft_pass_a_lds(int LA) { return (size_t)LA * sizeof(float4) + (32 + (LA + 31) / 32) * sizeof(float2); }
+// Bytes of LDS of a first-pass launch: the row, the two-level stage table
+// and, for a row length with a fixed plan, its stage tables.
+size_t fft_pass_a_lds(int LA) {
+    return (size_t)LA * sizeof(float4) + (32 + (LA + 31) / 32) * sizeof(float2) +
+           (LA == 9000 ? (size_t)kRow9000Tab * sizeof(float2) : 0);
+}
 
 hipError_t launch_fft_pass_a(const PassAArgs& a, hipStream_t s) {
     const size_t lds = fft_pass_a_lds(a.LA);
     const unsigned gy = (unsigned)(a.n_sky_l * ((a.nf_l + a.fb - 1) / a.fb));
     const dim3 grid((unsigned)a.LB, gy);
-#define RSF_PASS_A(ORD)                                                              \
-    if (a.nt_spill)                                                                  \
-        hipLaunchKernelGGL((rsf_fft_pass_a_k<ORD, true>), grid, dim3(kNT), lds, s, a); \
-    else                                                                             \
-        hipLaunchKernelGGL((rsf_fft_pass_a_k<ORD, false>), grid, dim3(kNT), lds, s, a)
-    switch (a.spin_order) {
-        case 1: RSF_PASS_A(1); break;
-        case 2: RSF_PASS_A(2); break;
-        case 3: RSF_PASS_A(3); break;
+    // the same pruning rule as the kernel's
+    const bool prune = 2 * a.P <= a.LA && a.st.n_stages > 1 && (a.st.radix[0] & 1) == 0;
+    const int plan = fixed_row_plan(a.st, prune);
+#define RSF_PASS_A(ORD, PL)                                                              \
+    if (a.nt_spill)                                                                      \
+        hipLaunchKernelGGL((rsf_fft_pass_a_k<ORD, true, PL>), grid, dim3(kNT), lds, s, a); \
+    else                                                                                 \
+        hipLaunchKernelGGL((rsf_fft_pass_a_k<ORD, false, PL>), grid, dim3(kNT), lds, s, a)
+    switch (a.spin_order * 2 + (plan == kRow9000 ? 1 : 0)) {
+        case 2: RSF_PASS_A(1, 0); break;
+        case 3: RSF_PASS_A(1, kRow9000); break;
+        case 4: RSF_PASS_A(2, 0); break;
+        case 5: RSF_PASS_A(2, kRow9000); break;
+        case 6: RSF_PASS_A(3, 0); break;
+        case 7: RSF_PASS_A(3, kRow9000); break;
         default: return hipErrorInvalidValue;
     }
 #undef RSF_PASS_A
@@ -605,9 +721,12 @@ hipError_t fft_set_lds_limits(size_t bytes) {
     // undo a larger one
     static size_t granted = 0;
     if (bytes <= granted) return hipSuccess;
-    const void* fns[] = {(const void*)rsf_fft_pass_a_k<1, false>,     (const void*)rsf_fft_pass_a_k<2, false>,
-                         (const void*)rsf_fft_pass_a_k<3, false>,     (const void*)rsf_fft_pass_a_k<1, true>,
-                         (const void*)rsf_fft_pass_a_k<2, true>,      (const void*)rsf_fft_pass_a_k<3, true>,
+    const void* fns[] = {(const void*)rsf_fft_pass_a_k<1, false, 0>,  (const void*)rsf_fft_pass_a_k<2, false, 0>,
+                         (const void*)rsf_fft_pass_a_k<3, false, 0>,  (const void*)rsf_fft_pass_a_k<1, true, 0>,
+                         (const void*)rsf_fft_pass_a_k<2, true, 0>,   (const void*)rsf_fft_pass_a_k<3, true, 0>,
+                         (const void*)rsf_fft_pass_a_k<1, false, kRow9000>, (const void*)rsf_fft_pass_a_k<2, false, kRow9000>,
+                         (const void*)rsf_fft_pass_a_k<3, false, kRow9000>, (const void*)rsf_fft_pass_a_k<1, true, kRow9000>,
+                         (const void*)rsf_fft_pass_a_k<2, true, kRow9000>,  (const void*)rsf_fft_pass_a_k<3, true, kRow9000>,
                          (const void*)rsf_fft_pass_b_k<false>,        (const void*)rsf_fft_pass_b_k<true>,
                          (const void*)rsf_fft_pass_b_wave_k<4, false>, (const void*)rsf_fft_pass_b_wave_k<4, true>,
                          (const void*)rsf_fft_pass_b_wave_k<8, false>, (const void*)rsf_fft_pass_b_wave_k<8, true>,

@@ -295,7 +295,12 @@ __global__ __launch_bounds__(kThreads, (BIN && GRAD) ? 1 : 2) void rsf_point_k(P
     for (int i = 0; i < ORDER; ++i) fs[i] = th[1 + i];
     const double fd = fs[0];
     BinaryOrbit bo{};
-    if constexpr (BIN) bo = BinaryOrbit{th[3 + ORDER], th[4 + ORDER], th[5 + ORDER]};
+    bool orbit_ok = true;
+    if constexpr (BIN) {
+        const BinaryOrbit given{th[3 + ORDER], th[4 + ORDER], th[5 + ORDER]};
+        orbit_ok = orbit_admitted(given);
+        bo = orbit_or_none(given);
+    }
     double sa, ca, sd, cd;
     sincos(al, &sa, &ca);
     sincos(de, &sd, &cd);
@@ -668,6 +673,11 @@ __global__ __launch_bounds__(kThreads, (BIN && GRAD) ? 1 : 2) void rsf_point_k(P
         }
     }
     if (overflow && lane == 0) atomicOr(A.flags, 2u);
+    if (!orbit_ok) {
+        // a refused orbit: NaN 2F and gradient for this candidate
+        acc[S_FA] = __longlong_as_double(0x7ff8000000000000LL);
+        if (threadIdx.x == 0) atomicOr(A.flags, 4u);
+    }
 
     // block reduction in a fixed order
     // unrolled: a loop-indexed acc would live in scratch memory

@@ -69,7 +69,12 @@ __global__ __launch_bounds__(kThreads) void rsf_resample_k(ResampleArgs A) {
     const double* srow = A.sky + (int64_t)A.sky_stride * sky;
     const double alpha = srow[0], delta = srow[1];
     BinaryOrbit bo{};
-    if constexpr (BIN) bo = BinaryOrbit{srow[2], srow[3], srow[4]};
+    bool orbit_ok = true;
+    if constexpr (BIN) {
+        const BinaryOrbit given{srow[2], srow[3], srow[4]};
+        orbit_ok = orbit_admitted(given);
+        bo = orbit_or_none(given);
+    }
     const double3 n0 = sky_unit(alpha, delta);
     const SkyFrame fr = sky_frame(alpha, delta);
     const int W = A.ip.taps;
@@ -185,6 +190,7 @@ __global__ __launch_bounds__(kThreads) void rsf_resample_k(ResampleArgs A) {
             } else {
                 zt = make_float2(__int_as_float(0x7fc00000), __int_as_float(0x7fc00000));
             }
+            if (!orbit_ok) zt = make_float2(__int_as_float(0x7fc00000), __int_as_float(0x7fc00000));
             if (mk) {
                 sA += av * av;
                 sB += bv * bv;
@@ -210,6 +216,7 @@ __global__ __launch_bounds__(kThreads) void rsf_resample_k(ResampleArgs A) {
     __syncthreads();  // the tile rows of all waves are complete
 
     if (window_overflow && lane == 0) atomicOr(A.flags, 2u);
+    if (!orbit_ok && threadIdx.x == 0) atomicOr(A.flags, 4u);
 
     // write the tile
     if (A.layout == 1) {

@@ -178,3 +178,49 @@ def test_point_and_adjoint_binary(gpu_lib):
     a, b = g3[6:] * sc_orb, rg3[6:] * sc_orb
     assert np.all(np.abs(a - b) <= 2e-3 * max(np.max(np.abs(b)), 1.0)), (a, b)
     plan.close()
+
+
+def test_out_of_range_orbit_is_flagged(gpu_lib):
+    """Orbits outside the admitted range (a_p > 100 light-s; 2 pi a_p / P_b >
+    1e-2; P_b <= 0; NaN) give NaN for their own sky rows or candidates only
+    and set the orbit flag; admitted rows in the same call equal a call
+    without the refused ones, and top-k never selects a refused row."""
+    import torch
+    w, xs, gaps = _setup(4)
+    good = [ORBITS[0], ORBITS[1]]
+    bad = [Binary(150.0, 1.0e7, 0.0), Binary(10.0, 1000.0, 0.0), Binary(1.0, -5.0e4, 0.0),
+           Binary(float("nan"), 5.0e4, 0.0)]
+    sky = [(1.2, 0.3), (4.1, -0.8)]
+    rows_mix = _sky_rows([sky[0], sky[0], sky[1], sky[1], sky[0], sky[1]],
+                         [good[0], bad[0], good[1], bad[1], bad[2], bad[3]])
+    rows_good = _sky_rows(sky, good)
+    fdots = torch.tensor([-2e-10, 0.0], dtype=torch.float64).cuda()
+    plan = gpu_lib.Plan(w)
+    plan.set_binary(True)
+    tx, tg = to_gpu(xs, gaps)
+    print("\ncase: out-of-range orbits, full band", flush=True)
+    ws = plan.workspace(gpu_lib.RSF_ENTRY_FSTAT, 6, 2)
+    mix = plan.fstat(tx, tg, torch.from_numpy(rows_mix).cuda(), fdots, ws=ws).cpu().numpy().reshape(6, 2, -1)
+    assert plan.flags(ws) & gpu_lib.RSF_FLAG_ORBIT
+    ws2 = plan.workspace(gpu_lib.RSF_ENTRY_FSTAT, 2, 2)
+    ref = plan.fstat(tx, tg, torch.from_numpy(rows_good).cuda(), fdots, ws=ws2).cpu().numpy().reshape(2, 2, -1)
+    assert plan.flags(ws2) == 0
+    assert np.isnan(mix[[1, 3, 4, 5]]).all()
+    assert np.allclose(mix[[0, 2]], ref, rtol=1e-6, atol=1e-6)
+    print("case: out-of-range orbits, top-k", flush=True)
+    _, ids = plan.topk(tx, tg, torch.from_numpy(rows_mix).cuda(), fdots, k=20)
+    assert set(ids.cpu().numpy()[:, 0].tolist()) <= {0, 2}
+
+    print("case: out-of-range orbits, point and adjoint", flush=True)
+    f0 = w.segment.f_het + 0.01
+    th_mix = np.array([[f0, -2e-10, 1.2, 0.3, o.a_p, o.p_orb, o.t_asc] for o in [good[0], bad[0], good[1], bad[1]]])
+    th_good = th_mix[[0, 2]]
+    wsp = plan.workspace(gpu_lib.RSF_ENTRY_BACKWARD, 1, 4)
+    F, g = plan.backward(tx, tg, torch.from_numpy(th_mix).cuda(), torch.ones(4, dtype=torch.float32).cuda(), ws=wsp)
+    assert plan.flags(wsp) & gpu_lib.RSF_FLAG_ORBIT
+    F, g = F.cpu().numpy(), g.cpu().numpy()
+    F0, g0 = plan.backward(tx, tg, torch.from_numpy(th_good).cuda(), torch.ones(2, dtype=torch.float32).cuda())
+    F0, g0 = F0.cpu().numpy(), g0.cpu().numpy()
+    assert np.isnan(F[[1, 3]]).all() and np.isnan(g[[1, 3]]).all()
+    assert np.array_equal(F[[0, 2]], F0) and np.array_equal(g[[0, 2]], g0)
+    plan.close()
