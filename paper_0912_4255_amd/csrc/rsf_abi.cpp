@@ -239,8 +239,9 @@ struct rsf_plan {
 namespace {
 
 struct WsLayout {
-    size_t flags, rs_main[RSF_MAX_DET], rs_tm[RSF_MAX_DET], partials, coef, abc_w, spill, map, cand, run, mtmp[2],
+    size_t flags, rs_main[RSF_MAX_DET], rs_tm[RSF_MAX_DET], partials, coef, abc_w, spill, map, gate, cand, run, mtmp[2],
         spins, total;
+    int64_t cap;      // top-k candidate capacity per FFT launch
     int n_blocks;
     int64_t G;        // templates per FFT launch
     int64_t S;        // sky positions per resampling chunk
@@ -272,11 +273,19 @@ int64_t batch_skies(int64_t n_sky, int64_t n_fdot, int64_t G, int mode) {
 // reductions through tmp[0], tmp[1] until one block remains.
 hipError_t topk_merge_levels(const rsf_plan* p, hipStream_t s, const TopkItem* cand, int64_t n_cand,
                              const TopkItem* run_in, TopkItem* run_out, int k, int64_t n_fdot, void* entries,
-                             TopkItem* const tmp[2]);
+                             TopkItem* const tmp[2], TopkGate* gate = nullptr, int64_t part_cap = 0);
 
+// The second pass selects the top-k itself (no 2F map) when it runs one
+// column per wave.
+bool fused_topk(const rsf_plan* p) { return fft_pass_b_wave_e(p->LB) != 0; }
+
+// map: room for a launch's 2F map (the semi-coherent sum, or a top-k whose
+// second pass cannot select in place); topk: the candidate gate, buffer and
+// merge levels.
 // spins: room for the call's spindowns moved to the segment start (the
 // semi-coherent sum at spin order > 1)
-WsLayout fstat_layout(const rsf_plan* p, int64_t n_sky, int64_t n_fdot, int mode, bool topk, bool spins = false) {
+WsLayout fstat_layout(const rsf_plan* p, int64_t n_sky, int64_t n_fdot, int mode, bool map, bool topk,
+                      bool spins = false) {
     WsLayout L{};
     size_t off = 0;
     L.flags = off;
@@ -302,15 +311,26 @@ WsLayout fstat_layout(const rsf_plan* p, int64_t n_sky, int64_t n_fdot, int mode
     off = align_up(off + (size_t)L.S * 3 * sizeof(double));
     L.spill = off;
     off = align_up(off + (size_t)L.G * p->n_groups * p->LB * kPassBCols * sizeof(float4));
-    if (topk) {
+    if (map) {
         L.map = off;
         off = align_up(off + (size_t)L.G * p->n_out * sizeof(float));
+    }
+    if (topk) {
+        // every producer unit of a launch (second-pass block, or scan wave
+        // over the map) appends at most kGateItemsPerUnit candidates to its
+        // workgroup's partition; partitions are sized for the workgroup with
+        // the most units, so the total is below (units + units per workgroup
+        // x partitions) items
+        const int64_t units = map ? topk_scan_chunks(L.G * p->n_out) + 4 : L.G * p->n_groups;
+        L.cap = (units + (int64_t)(map ? 4 : 1) * kGateParts) * kGateItemsPerUnit;
+        L.gate = off;
+        off = align_up(off + sizeof(TopkGate));
         L.cand = off;
-        off = align_up(off + (size_t)topk_scan_chunks(L.G * p->n_out) * kTopkMax * sizeof(TopkItem));
+        off = align_up(off + (size_t)L.cap * sizeof(TopkItem));
         L.run = off;
         off = align_up(off + 2 * kTopkMax * sizeof(TopkItem));
         // outputs of the first merge level (and of any further level)
-        const int64_t n1 = topk_scan_chunks(L.G * p->n_out) * kTopkMax + kTopkMax;
+        const int64_t n1 = L.cap + kTopkMax;
         const int64_t b1 = (n1 + topk_merge_per_block() - 1) / topk_merge_per_block();
         for (int i = 0; i < 2; ++i) {
             L.mtmp[i] = off;
@@ -632,13 +652,13 @@ int rsf_workspace_size(const rsf_plan* p, int entry, int64_t n_sky, int64_t n_fd
             return RSF_OK;
         case RSF_ENTRY_FSTAT:
             if (mode != RSF_MODE_PLAIN && mode != RSF_MODE_BATCHED) return fail(RSF_EINVAL, "unknown mode");
-            *bytes = fstat_layout(p, n_sky, n_fdot, mode, false).total;
+            *bytes = fstat_layout(p, n_sky, n_fdot, mode, false, false).total;
             return RSF_OK;
         case RSF_ENTRY_TOPK:
-            *bytes = fstat_layout(p, n_sky, n_fdot, RSF_MODE_BATCHED, true).total;
+            *bytes = fstat_layout(p, n_sky, n_fdot, RSF_MODE_BATCHED, !fused_topk(p), true).total;
             return RSF_OK;
         case RSF_ENTRY_SEMICOHERENT:
-            *bytes = fstat_layout(p, n_sky, n_fdot, RSF_MODE_BATCHED, true, p->spin_order > 1).total;
+            *bytes = fstat_layout(p, n_sky, n_fdot, RSF_MODE_BATCHED, true, false, p->spin_order > 1).total;
             return RSF_OK;
         case RSF_ENTRY_POINT:
         case RSF_ENTRY_BACKWARD:
@@ -719,14 +739,15 @@ int run_fstat(const rsf_plan* p, const rsf_segment* seg, const double* sky, int6
     int rc = check_segment(p, seg);
     if (rc) return rc;
     const bool want_topk = topk != nullptr;
-    const bool want_map = want_topk || semico != nullptr;
-    if (!sky || !fdot || (!twoF && !want_map)) return fail(RSF_EINVAL, "sky, fdot or output is NULL");
+    const bool in_pass = want_topk && semico == nullptr && fused_topk(p);  // top-k inside the second pass
+    const bool want_map = semico != nullptr || (want_topk && !in_pass);
+    if (!sky || !fdot || (!twoF && !want_map && !want_topk)) return fail(RSF_EINVAL, "sky, fdot or output is NULL");
     if (n_sky < 1 || n_fdot < 1) return fail(RSF_EINVAL, "n_sky and n_fdot must be positive");
     if (mode != RSF_MODE_PLAIN && mode != RSF_MODE_BATCHED) return fail(RSF_EINVAL, "unknown mode");
     if (want_topk && (k < 1 || k > kTopkMax)) return fail(RSF_EINVAL, "k must be in 1..%d", kTopkMax);
     if (!ws) return fail(RSF_EINVAL, "workspace is NULL");
     const bool translate = semico != nullptr && p->spin_order > 1;
-    const WsLayout L = fstat_layout(p, n_sky, n_fdot, mode, want_map, translate);
+    const WsLayout L = fstat_layout(p, n_sky, n_fdot, mode, want_map, want_topk, translate);
     if (ws_bytes < L.total) return fail(RSF_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, L.total);
     hipStream_t s = (hipStream_t)stream;
     char* w = (char*)ws;
@@ -748,9 +769,14 @@ int run_fstat(const rsf_plan* p, const rsf_segment* seg, const double* sky, int6
     TopkItem* run[2] = {nullptr, nullptr};
     int cur = 0;
     bool have_run = false;
+    TopkGate* gate = nullptr;
     if (want_topk) {
         run[0] = (TopkItem*)(w + L.run);
         run[1] = run[0] + kTopkMax;
+        // threshold -inf, no candidates
+        gate = (TopkGate*)(w + L.gate);
+        RSF_HIP(launch_fill_u32(&gate->thr, 1, 0xff800000u, s), "top-k gate threshold");
+        RSF_HIP(launch_fill_u32(gate->count, kGateParts * kGateStride, 0u, s), "top-k gate counts");
     }
 
     for (int64_t c0 = 0; c0 < n_sky; c0 += L.S) {
@@ -853,6 +879,18 @@ int run_fstat(const rsf_plan* p, const rsf_segment* seg, const double* sky, int6
             B.nf_l = q.nf;
             B.n_tmpl = q.ns * q.nf;
             B.wave = fft_pass_b_wave_e(p->LB) != 0 ? 1 : 0;
+            int64_t n_cand = 0, part_cap = 0;  // this launch's gate partitions x capacity, capacity
+            if (in_pass) {
+                B.topk = 1;
+                B.k = k;
+                B.gate = gate;
+                B.cand = (TopkItem*)(w + L.cand);
+                const int parts = fft_pass_b_grid(B, p->n_cu);
+                const int64_t n_units = (int64_t)B.n_tmpl * B.n_groups;
+                B.part_cap = (n_units + parts - 1) / parts * kGateItemsPerUnit;
+                part_cap = B.part_cap;
+                n_cand = parts * part_cap;
+            }
             RSF_HIP(timed(p, K_PASS_B, s, [&] { return launch_fft_pass_b(B, p->n_cu, s); }), "pass B launch");
 
             if (semico) {
@@ -878,20 +916,30 @@ int run_fstat(const rsf_plan* p, const rsf_segment* seg, const double* sky, int6
                 RSF_HIP(timed(p, K_SEMICO, s, [&] { return launch_semico(sa, s); }), "semi-coherent launch");
             }
             if (want_topk) {
-                TopkScanArgs ta{};
-                ta.map = (const float*)(w + L.map);
-                ta.n_vals = (int64_t)B.n_tmpl * p->n_out;
-                ta.n_out = p->n_out;
-                ta.sky0 = B.sky0;
-                ta.n_fdot = n_fdot;
-                ta.f0 = q.f0;
-                ta.nf_l = q.nf;
-                ta.k = k;
-                ta.cand = (TopkItem*)(w + L.cand);
-                RSF_HIP(timed(p, K_TOPK, s, [&] { return launch_topk_scan(ta, s); }), "topk scan launch");
+                if (!in_pass) {
+                    TopkScanArgs ta{};
+                    ta.map = (const float*)(w + L.map);
+                    ta.n_vals = (int64_t)B.n_tmpl * p->n_out;
+                    ta.n_out = p->n_out;
+                    ta.sky0 = B.sky0;
+                    ta.n_fdot = n_fdot;
+                    ta.f0 = q.f0;
+                    ta.nf_l = q.nf;
+                    ta.k = k;
+                    ta.cand = (TopkItem*)(w + L.cand);
+                    ta.n_part = topk_scan_parts(ta.n_vals, &ta.part_cap);
+                    ta.gate = gate;
+                    part_cap = ta.part_cap;
+                    n_cand = ta.n_part * part_cap;
+                    RSF_HIP(timed(p, K_TOPK, s, [&] { return launch_topk_scan(ta, s); }), "topk scan launch");
+                }
+                if (n_cand > L.cap) return fail(RSF_EHIP, "internal: top-k candidates exceed the workspace");
+                // this launch's candidates into the running k best; the gate's
+                // threshold becomes their k-th
                 TopkItem* const tmp[2] = {(TopkItem*)(w + L.mtmp[0]), (TopkItem*)(w + L.mtmp[1])};
-                RSF_HIP(topk_merge_levels(p, s, ta.cand, topk_scan_chunks(ta.n_vals) * k,
-                                          have_run ? run[cur] : nullptr, run[cur ^ 1], k, n_fdot, nullptr, tmp),
+                RSF_HIP(topk_merge_levels(p, s, (const TopkItem*)(w + L.cand), n_cand,
+                                          have_run ? run[cur] : nullptr, run[cur ^ 1], k, n_fdot, nullptr, tmp, gate,
+                                          part_cap),
                         "topk merge launch");
                 cur ^= 1;
                 have_run = true;
@@ -908,13 +956,19 @@ int run_fstat(const rsf_plan* p, const rsf_segment* seg, const double* sky, int6
 
 hipError_t topk_merge_levels(const rsf_plan* p, hipStream_t s, const TopkItem* cand, int64_t n_cand,
                              const TopkItem* run_in, TopkItem* run_out, int k, int64_t n_fdot, void* entries,
-                             TopkItem* const tmp[2]) {
+                             TopkItem* const tmp[2], TopkGate* gate, int64_t part_cap) {
     const int64_t per = topk_merge_per_block();
     int b = 0;
+    bool first = true;
     for (;;) {
         TopkMergeArgs ma{};
         ma.cand = cand;
         ma.n_cand = n_cand;
+        // the first level reads the gate's candidates; the last one updates the gate
+        ma.gate = gate;
+        ma.n_gate = (gate && first) ? 1 : 0;
+        ma.part_cap = part_cap;
+        first = false;
         ma.run_in = run_in;
         ma.k = k;
         ma.n_fdot = n_fdot;
@@ -982,7 +1036,7 @@ int check_plans(const rsf_plan* const* plans, int64_t n_seg) {
 size_t segments_ws(const rsf_plan* const* plans, int64_t n_seg, int64_t n_sky, int64_t n_fdot) {
     size_t m = 0;
     for (int64_t i = 0; i < n_seg; ++i)
-        m = std::max(m, fstat_layout(plans[i], n_sky, n_fdot, RSF_MODE_BATCHED, true).total);
+        m = std::max(m, fstat_layout(plans[i], n_sky, n_fdot, RSF_MODE_BATCHED, !fused_topk(plans[i]), true).total);
     return m;
 }
 

@@ -21,6 +21,7 @@
 #include "rsf_device.h"
 #include "rsf_launch.h"
 #include "rsf_spill.h"
+#include "rsf_topk_gate.h"
 
 namespace rsf {
 
@@ -578,7 +579,103 @@ __device__ __forceinline__ void wave_output(const PassBArgs& B, int unit, const 
     }
 }
 
-template <int E, bool NT>
+// LDS of the in-kernel top-k.
+struct WaveTopkLds {
+    int cnt[kPassBCols];
+    float sv[kPassBCols];
+    unsigned long long sk[kPassBCols];
+};
+
+// The same 2F values as wave_output, passed through the top-k gate instead
+// of being stored: with at most kGateFast values of the block at or above
+// the gate's threshold every wave appends its own; with more, the block
+// selects its k best (k rounds of a block-wide argmax), appends them and
+// raises the threshold to the k-th.  Called by every thread of the block.
+template <int E>
+__device__ __forceinline__ void wave_topk(const PassBArgs& B, int unit, const float* st, int tid, int hnf, int nf,
+                                          WaveTopkLds* tl) {
+    const int lane = tid & 63, wave = tid >> 6;
+    const int t = unit / B.n_groups;
+    const int g = unit - t * B.n_groups;
+    const int s_l = t / B.nf_l;
+    const int f = t - s_l * B.nf_l;
+    const unsigned long long row_key =
+        (unsigned long long)((B.sky0 + s_l) * B.n_fdot + B.f0 + f) * (unsigned long long)B.n_out;
+    const int col = tid & 7;
+    const int kac = g * kPassBCols + col;
+    const float thr = gate_threshold(B.gate);
+    float v[E];
+    int o[E];
+    unsigned mask = 0u;
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+        const int kb = (tid >> 3) + 64 * j;
+        v[j] = st[kb * kPassBCols + (col ^ ((kb >> 3) & 7))];
+        const int k = kac + B.LA * kb;
+        o[j] = ((k < hnf) ? k : k - nf) - (int)B.s_lo;
+        if (kac < B.LA && (unsigned)o[j] < (unsigned)B.n_out && gate_pass(v[j], thr)) mask |= 1u << j;
+    }
+    int wsum;
+    const int pre = wave_prefix(__popc(mask), lane, wsum);
+    if (lane == 0) tl->cnt[wave] = wsum;
+    __syncthreads();
+    int total = 0;
+#pragma unroll
+    for (int i = 0; i < kPassBCols; ++i) total += tl->cnt[i];
+    if (total == 0) return;
+    // this workgroup's partition of the candidate buffer
+    TopkItem* pc = B.cand + (int64_t)blockIdx.x * B.part_cap;
+    if (total <= kGateFast) {
+        if (wsum > 0) {
+            unsigned slot = gate_reserve(B.gate, (int)blockIdx.x, wsum, lane) + (unsigned)pre;
+#pragma unroll
+            for (int j = 0; j < E; ++j)
+                if ((mask >> j) & 1u) {
+                    if ((int64_t)slot < B.part_cap) {
+                        TopkItem it;
+                        it.v = v[j];
+                        it.pad = 0;
+                        it.key = row_key + (unsigned long long)o[j];
+                        pc[slot] = it;
+                    }
+                    ++slot;
+                }
+        }
+        return;
+    }
+    unsigned first_slot = 0u;
+    if (tid == 0) first_slot = atomicAdd(&B.gate->count[blockIdx.x * kGateStride], (unsigned)B.k);
+    float pv = INFINITY;
+    unsigned long long pk = 0ull;
+    for (int r = 0; r < B.k; ++r) {
+        float bv = -INFINITY;
+        unsigned long long bk = ~0ull;
+#pragma unroll
+        for (int j = 0; j < E; ++j)
+            if ((mask >> j) & 1u) {
+                const unsigned long long key = row_key + (unsigned long long)o[j];
+                if ((r == 0 || topk_better(pv, pk, v[j], key)) && topk_better(v[j], key, bv, bk)) {
+                    bv = v[j];
+                    bk = key;
+                }
+            }
+        block_best<kWaveColsThreads>(bv, bk, tl->sv, tl->sk);
+        if (tid == 0 && (int64_t)(first_slot + r) < B.part_cap) {
+            TopkItem it = topk_empty();
+            if (bv != -INFINITY) {
+                it.v = bv;
+                it.key = bk;
+            }
+            pc[first_slot + r] = it;
+        }
+        pv = bv;
+        pk = bk;
+    }
+    if (tid == 0) gate_raise(B.gate, pv);  // -inf (no raise) when fewer than k values passed
+}
+
+// TOPK: the block's 2F values go through the top-k gate (wave_topk), not to memory.
+template <int E, bool NT, bool TOPK>
 __global__ __launch_bounds__(kWaveColsThreads) void rsf_fft_pass_b_wave_k(PassBArgs B) {
     constexpr int Q = E / 4;
     constexpr int LBW = 64 * E;
@@ -587,6 +684,7 @@ __global__ __launch_bounds__(kWaveColsThreads) void rsf_fft_pass_b_wave_k(PassBA
     cp* xch = lds + kPassBCols * LBW;                               // 8 waves x 4 x 64 slots
     float* st = reinterpret_cast<float*>(xch + kPassBCols * 4 * 64);  // 2F stage [LB][8]
     float* cfl = st + LBW * kPassBCols;                             // 4 per sky of the launch
+    WaveTopkLds* tkl = reinterpret_cast<WaveTopkLds*>(cfl + 4 * (B.n_sky_l > 64 ? B.n_sky_l : 64));
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int p = lane >> 4, q = (lane >> 2) & 3, r = lane & 3;
     for (int i = tid; i < 4 * B.n_sky_l; i += kWaveColsThreads) cfl[i] = B.coef[i];
@@ -618,7 +716,12 @@ __global__ __launch_bounds__(kWaveColsThreads) void rsf_fft_pass_b_wave_k(PassBA
         const bool live = ka < B.LA;
         cp v[E];
         if (live) wave_col_read<E>(blk, wave, lane, v);
-        if (prev >= 0) wave_output<E>(B, prev, st, tid, hnf, nf);
+        if (prev >= 0) {
+            if constexpr (TOPK)
+                wave_topk<E>(B, prev, st, tid, hnf, nf, tkl);
+            else
+                wave_output<E>(B, prev, st, tid, hnf, nf);
+        }
         __syncthreads();  // the block buffer and the stage are free
         if (unit + G < n_units) wave_dma<NT>(B, unit + G, blk, wave, lane);
         if (live) {
@@ -639,7 +742,10 @@ __global__ __launch_bounds__(kWaveColsThreads) void rsf_fft_pass_b_wave_k(PassBA
     }
     if (prev >= 0) {
         __syncthreads();
-        wave_output<E>(B, prev, st, tid, hnf, nf);
+        if constexpr (TOPK)
+            wave_topk<E>(B, prev, st, tid, hnf, nf, tkl);
+        else
+            wave_output<E>(B, prev, st, tid, hnf, nf);
     }
 }
 
@@ -686,21 +792,37 @@ int fft_pass_b_wave_e(int LB) {
 size_t fft_pass_b_lds(int LB, int n_sky_l) {
     if (fft_pass_b_wave_e(LB))
         return (size_t)kPassBCols * LB * sizeof(float4) + (size_t)kPassBCols * 4 * 64 * sizeof(float4) +
-               (size_t)LB * kPassBCols * sizeof(float) + (size_t)4 * std::max(n_sky_l, 64) * sizeof(float);
+               (size_t)LB * kPassBCols * sizeof(float) + (size_t)4 * std::max(n_sky_l, 64) * sizeof(float) +
+               sizeof(WaveTopkLds);
     const size_t buf = (size_t)((LB * kPassBCols + 63) / 64) * 64;
     return buf * sizeof(float4) + (32 + (LB + 31) / 32) * sizeof(float2) + (size_t)4 * n_sky_l * sizeof(float);
 }
 
+// Persistent grid of the second pass: one workgroup per CU, and with the
+// in-kernel top-k at most one per gate partition.
+int fft_pass_b_grid(const PassBArgs& b, int n_cu) {
+    const int n_items = b.n_tmpl * b.n_groups;
+    return std::max(1, std::min({n_items, n_cu, b.topk ? kGateParts : n_cu}));
+}
+
 hipError_t launch_fft_pass_b(const PassBArgs& b, int n_cu, hipStream_t s) {
     const size_t lds = fft_pass_b_lds(b.LB, b.n_sky_l);
-    const int n_items = b.n_tmpl * b.n_groups;
-    const unsigned grid = (unsigned)std::max(1, std::min(n_items, n_cu));
-#define RSF_PASS_B_WAVE(EE)                                                                                     \
-    case EE:                                                                                                    \
-        if (b.nt_spill)                                                                                         \
-            hipLaunchKernelGGL((rsf_fft_pass_b_wave_k<EE, true>), dim3(grid), dim3(kWaveColsThreads), lds, s, b);  \
-        else                                                                                                    \
-            hipLaunchKernelGGL((rsf_fft_pass_b_wave_k<EE, false>), dim3(grid), dim3(kWaveColsThreads), lds, s, b); \
+    const unsigned grid = (unsigned)fft_pass_b_grid(b, n_cu);
+#define RSF_PASS_B_WAVE1(EE, NTT, TK) \
+    hipLaunchKernelGGL((rsf_fft_pass_b_wave_k<EE, NTT, TK>), dim3(grid), dim3(kWaveColsThreads), lds, s, b)
+#define RSF_PASS_B_WAVE(EE)                  \
+    case EE:                                 \
+        if (b.nt_spill) {                    \
+            if (b.topk)                      \
+                RSF_PASS_B_WAVE1(EE, true, true);  \
+            else                             \
+                RSF_PASS_B_WAVE1(EE, true, false); \
+        } else {                             \
+            if (b.topk)                      \
+                RSF_PASS_B_WAVE1(EE, false, true); \
+            else                             \
+                RSF_PASS_B_WAVE1(EE, false, false); \
+        }                                    \
         return hipGetLastError();
     switch (b.wave ? fft_pass_b_wave_e(b.LB) : 0) {
         RSF_PASS_B_WAVE(4)
@@ -709,6 +831,7 @@ hipError_t launch_fft_pass_b(const PassBArgs& b, int n_cu, hipStream_t s) {
         default: break;
     }
 #undef RSF_PASS_B_WAVE
+#undef RSF_PASS_B_WAVE1
     if (b.nt_spill)
         hipLaunchKernelGGL(rsf_fft_pass_b_k<true>, dim3(grid), dim3(kNTB), lds, s, b);
     else
@@ -728,9 +851,12 @@ hipError_t fft_set_lds_limits(size_t bytes) {
                          (const void*)rsf_fft_pass_a_k<3, false, kRow9000>, (const void*)rsf_fft_pass_a_k<1, true, kRow9000>,
                          (const void*)rsf_fft_pass_a_k<2, true, kRow9000>,  (const void*)rsf_fft_pass_a_k<3, true, kRow9000>,
                          (const void*)rsf_fft_pass_b_k<false>,        (const void*)rsf_fft_pass_b_k<true>,
-                         (const void*)rsf_fft_pass_b_wave_k<4, false>, (const void*)rsf_fft_pass_b_wave_k<4, true>,
-                         (const void*)rsf_fft_pass_b_wave_k<8, false>, (const void*)rsf_fft_pass_b_wave_k<8, true>,
-                         (const void*)rsf_fft_pass_b_wave_k<12, false>, (const void*)rsf_fft_pass_b_wave_k<12, true>};
+                         (const void*)rsf_fft_pass_b_wave_k<4, false, false>, (const void*)rsf_fft_pass_b_wave_k<4, true, false>,
+                         (const void*)rsf_fft_pass_b_wave_k<8, false, false>, (const void*)rsf_fft_pass_b_wave_k<8, true, false>,
+                         (const void*)rsf_fft_pass_b_wave_k<12, false, false>, (const void*)rsf_fft_pass_b_wave_k<12, true, false>,
+                         (const void*)rsf_fft_pass_b_wave_k<4, false, true>, (const void*)rsf_fft_pass_b_wave_k<4, true, true>,
+                         (const void*)rsf_fft_pass_b_wave_k<8, false, true>, (const void*)rsf_fft_pass_b_wave_k<8, true, true>,
+                         (const void*)rsf_fft_pass_b_wave_k<12, false, true>, (const void*)rsf_fft_pass_b_wave_k<12, true, true>};
     hipError_t out = hipSuccess;
     for (const void* f : fns) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);

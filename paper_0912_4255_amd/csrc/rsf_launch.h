@@ -24,6 +24,8 @@ int fft_pass_max_elems();
 
 int64_t topk_scan_chunks(int64_t n_vals);  // candidate groups (k each) of a scan
 hipError_t launch_topk_scan(const TopkScanArgs& a, hipStream_t s);
+int topk_scan_parts(int64_t n_vals, int64_t* part_cap);  // gate partitions of a scan and their capacity
+int fft_pass_b_grid(const PassBArgs& b, int n_cu);       // workgroups of a second-pass launch
 hipError_t launch_topk_merge(const TopkMergeArgs& a, hipStream_t s);
 int topk_merge_per_block();
 hipError_t launch_fill_u32(unsigned int* p, int n, unsigned int v, hipStream_t s);

@@ -141,6 +141,22 @@ struct PassAArgs {
     int nt_spill;             // spill larger than the last-level cache: non-temporal stores
 };
 
+// Candidate gate of a top-k search (device memory, one per call): thr holds
+// the bits of a float t such that at least k values of the call are known to
+// be >= t (so a value below t is never among the k best; -inf at the start).
+// Candidates go to kGateParts partitions of part_cap slots each, one per
+// producer workgroup (index mod kGateParts), so that no counter is shared
+// across the chip; count[p kGateStride] is partition p's fill since the last
+// merge (counters 128 bytes apart).
+constexpr int kGateParts = 256;
+constexpr int kGateStride = 32;
+struct TopkItem;
+struct TopkGate {
+    unsigned thr;
+    unsigned pad_[kGateStride - 1];
+    unsigned count[kGateParts * kGateStride];
+};
+
 // Second FFT pass and F-statistic for the launch's n_sky_l * nf_l templates;
 // template t = s nf_l + f goes to output row (sky0 + s) * n_fdot + f0 + f, or
 // to row t of a scratch map (map_rows = 1).
@@ -163,7 +179,14 @@ struct PassBArgs {
     int nf_l;
     int n_tmpl;
     int wave;                 // one column per wave when LB = 64 E, E = 4, 8, 12 (else the LDS-stage kernel)
+    // top-k selection inside the one-column-per-wave kernel (topk != 0): no
+    // 2F map is written; each block appends its candidates through the gate
+    int topk, k;
+    TopkGate* gate;
+    TopkItem* cand;           // partition p = blockIdx.x at [p part_cap, (p + 1) part_cap)
+    int64_t part_cap;
 };
+
 
 // Top-k over a scratch map of 2F rows (template t = s nf_l + f of a launch):
 // order by 2F descending, ties by the lower key (sky, fdot, bin) packed as
@@ -175,6 +198,12 @@ struct TopkItem {
     unsigned long long key;
 };
 
+// Top-k gate: a producer unit with at most kGateFast values at or above the
+// threshold appends them all, else its k best; so a unit appends at most
+// kGateItemsPerUnit candidates.
+constexpr int kGateFast = 32;
+constexpr int kGateItemsPerUnit = kGateFast > kTopkMax ? kGateFast : kTopkMax;
+
 struct TopkScanArgs {
     const float* map;
     int64_t n_vals;           // rows * n_out
@@ -182,12 +211,18 @@ struct TopkScanArgs {
     int64_t sky0, n_fdot, f0;
     int nf_l;
     int k;
-    TopkItem* cand;           // [gridDim.x][k]
+    TopkItem* cand;           // partition p = blockIdx.x mod n_part at [p part_cap, (p + 1) part_cap)
+    int64_t part_cap;
+    int n_part;
+    TopkGate* gate;
 };
 
 struct TopkMergeArgs {
-    const TopkItem* cand;     // n_cand items
+    const TopkItem* cand;     // n_cand items (n_gate: partitions of part_cap items, filled per gate->count)
     int64_t n_cand;
+    TopkGate* gate;           // the one-block level sets gate->thr from its k-th result and clears the counts
+    int n_gate;
+    int64_t part_cap;
     const TopkItem* run_in;   // k items (may be null: start empty)
     TopkItem* run_out;        // k items (one-block grid)
     TopkItem* out_blocks;     // [gridDim.x][k] items (grids of several blocks)

@@ -1,0 +1,117 @@
+"""Per-segment top-k through the candidate gate (order: 2F descending, ties by
+the lower (sky, fdot, bin); NaN never enters), against the selection over the
+full 2F map computed by the same plan:
+
+* second passes of LB = 256, 512, 768 points select inside the kernel (no
+  map); other lengths scan a map; both over several FFT launches, so the
+  threshold carried from launch to launch is exercised;
+* a series of zeros makes every 2F exactly 0: every value ties, every block
+  takes its slow path and the result is the k lowest keys;
+* an all-gap segment has NaN everywhere: no entry;
+* graph replays reproduce the eager result."""
+import numpy as np
+import pytest
+
+from paper_0912_4255_amd import synth
+from tests.helpers import make_inputs, to_gpu
+from tests.test_gpu_batch import numpy_topk
+
+pytestmark = pytest.mark.gpu
+
+N, DT = 38400, 4.0      # N_fft = 76800 = 300 x 256 = 150 x 512 = 100 x 768
+N_FDOT = 9
+
+
+def _plan(gpu_lib, w, l1):
+    from paper_0912_4255_amd.api import plan_desc_from_workload
+    d = plan_desc_from_workload(w)
+    d.fft_l1 = l1
+    plan = gpu_lib.Plan(desc=d)
+    assert plan.fft_l1 == l1
+    plan.set_batching(4, 8)    # 8 templates per FFT launch: several launches per call
+    return plan
+
+
+def _expected(maps, k, n_out):
+    flat = numpy_topk(maps, k)
+    ids = np.stack([flat // (n_out * N_FDOT), (flat // n_out) % N_FDOT, flat % n_out], axis=1)
+    return maps.reshape(-1)[flat], ids
+
+
+@pytest.mark.parametrize("l1", [300, 150, 100, 160])
+@pytest.mark.parametrize("k", [1, 10, 64])
+def test_topk_matches_map_selection(gpu_lib, l1, k):
+    import torch
+    w = synth.small_workload(n=N, dt=DT, kernel=synth.KERNEL_DIRICHLET, taps=16)
+    rng = np.random.default_rng(31)
+    w.gaps = [synth.random_gaps(rng, N, 600, 3)]
+    xs, gaps = make_inputs(w, seed=32)
+    plan = _plan(gpu_lib, w, l1)
+    print(f"\ncase: top-{k}, L1 x L2 = {plan.fft_l1} x {plan.fft_l2}", flush=True)
+    tx, tg = to_gpu(xs, gaps)
+    sky = torch.from_numpy(synth.uniform_sky(np.random.default_rng(33), 3)).cuda()
+    fd = torch.from_numpy(synth.fdot_grid(N_FDOT)).cuda()
+    maps = plan.fstat(tx, tg, sky, fd).cpu().numpy()
+    vals, ids = plan.topk(tx, tg, sky, fd, k=k)
+    ev, ei = _expected(maps, k, plan.n_out)
+    assert np.array_equal(ids.cpu().numpy(), ei)
+    assert np.array_equal(vals.cpu().numpy(), ev)
+    plan.close()
+
+
+@pytest.mark.parametrize("l1", [150, 160])
+def test_all_ties_give_lowest_keys(gpu_lib, l1):
+    import torch
+    w = synth.small_workload(n=N, dt=DT, kernel=synth.KERNEL_DIRICHLET, taps=16)
+    xs = [np.zeros(N, np.complex64)]
+    gaps = [np.zeros((0, 2), np.int64)]
+    plan = _plan(gpu_lib, w, l1)
+    print(f"\ncase: all 2F = 0, L1 = {l1}", flush=True)
+    tx, tg = to_gpu(xs, gaps)
+    sky = torch.from_numpy(synth.uniform_sky(np.random.default_rng(34), 2)).cuda()
+    fd = torch.from_numpy(synth.fdot_grid(N_FDOT)).cuda()
+    vals, ids = plan.topk(tx, tg, sky, fd, k=64)
+    assert np.all(vals.cpu().numpy() == 0.0)
+    exp = np.stack([np.zeros(64, int), np.zeros(64, int), np.arange(64)], axis=1)
+    assert np.array_equal(ids.cpu().numpy(), exp)
+    plan.close()
+
+
+@pytest.mark.parametrize("l1", [150, 160])
+def test_all_nan_gives_no_entry(gpu_lib, l1):
+    import torch
+    w = synth.small_workload(n=N, dt=DT, kernel=synth.KERNEL_DIRICHLET, taps=16)
+    xs = [np.zeros(N, np.complex64)]
+    gaps = [np.array([[0, N]], dtype=np.int64)]
+    plan = _plan(gpu_lib, w, l1)
+    print(f"\ncase: all 2F NaN, L1 = {l1}", flush=True)
+    tx, tg = to_gpu(xs, gaps)
+    sky = torch.tensor([[1.0, 0.2]], dtype=torch.float64).cuda()
+    fd = torch.from_numpy(synth.fdot_grid(N_FDOT)).cuda()
+    vals, ids = plan.topk(tx, tg, sky, fd, k=10)
+    assert np.all(np.isneginf(vals.cpu().numpy()))
+    assert np.all(ids.cpu().numpy() == -1)
+    plan.close()
+
+
+def test_graph_replays_in_pass_topk(gpu_lib):
+    import torch
+    w = synth.small_workload(n=N, dt=DT, kernel=synth.KERNEL_DIRICHLET, taps=16)
+    xs, gaps = make_inputs(w, seed=35)
+    plan = _plan(gpu_lib, w, 100)
+    print("\ncase: graph replays of the in-pass top-k", flush=True)
+    tx, tg = to_gpu(xs, gaps)
+    sky = torch.from_numpy(synth.uniform_sky(np.random.default_rng(36), 2)).cuda()
+    fd = torch.from_numpy(synth.fdot_grid(N_FDOT)).cuda()
+    ev, ei = plan.topk(tx, tg, sky, fd, k=20)
+    ev, ei = ev.cpu().numpy(), ei.cpu().numpy()
+    g, kv, ki = plan.graph_topk(tx, tg, sky, fd, k=20)
+    for rep in range(3):
+        kv.fill_(-1.0)
+        g.launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(kv.cpu().numpy(), ev) and np.array_equal(ki.cpu().numpy(), ei), rep
+        plan.fstat(tx, tg, sky, fd)  # eager work between replays
+        torch.cuda.synchronize()
+    g.close()
+    plan.close()
