@@ -71,7 +71,7 @@ typedef enum rsf_status {
 } rsf_status;
 
 enum { RSF_KERNEL_LANCZOS = 0, RSF_KERNEL_DIRICHLET = 1 };
-enum { RSF_NFFT_TWICE = 0, RSF_NFFT_SMOOTH7 = 1 };
+enum { RSF_NFFT_TWICE = 0, RSF_NFFT_SMOOTH7 = 1, RSF_NFFT_SMOOTH7_256 = 2 };
 enum { RSF_STORE_F32 = 0, RSF_STORE_F16 = 1 };
 enum { RSF_MODE_PLAIN = 0, RSF_MODE_BATCHED = 1 };
 enum {
@@ -97,7 +97,9 @@ typedef struct rsf_ephemeris {
 
 typedef struct rsf_plan_desc {
     int32_t n_det;                   /* 1..RSF_MAX_DET */
-    int32_t nfft_policy;             /* RSF_NFFT_TWICE: 2n; RSF_NFFT_SMOOTH7: smallest even 2^a3^b5^c7^d >= 2n */
+    int32_t nfft_policy;             /* RSF_NFFT_TWICE: 2n; RSF_NFFT_SMOOTH7: smallest even 2^a3^b5^c7^d >= 2n;
+                                        RSF_NFFT_SMOOTH7_256: smallest 256 2^a3^b5^c7^d >= 2n (a length the
+                                        one-column-per-wave second pass can take, LB = 256, 512 or 768) */
     int32_t kernel;                  /* RSF_KERNEL_LANCZOS or RSF_KERNEL_DIRICHLET */
     int32_t taps;                    /* even, 2..RSF_MAX_TAPS */
     int32_t storage;                 /* RSF_STORE_F32 or RSF_STORE_F16 (resampled series kept as half2) */

@@ -52,17 +52,22 @@ from .timing import invert_ssb_times
 
 NFFT_TWICE = 0
 NFFT_SMOOTH7 = 1
+NFFT_SMOOTH7_256 = 2
 
 
 def fft_length(n, policy):
-    """Zero-padded length of step 5 (Sec. III.A.2): twice the series, or the
-    smallest even 7-smooth length >= 2n.  Even, so that a band reaching the
-    Nyquist edges f_het +- 1/(2 dt) starts and ends on bins; an even
-    7-smooth m >= 2n is 2j with j 7-smooth and j >= n."""
+    """Zero-padded length of step 5 (Sec. III.A.2): twice the series, the
+    smallest even 7-smooth length >= 2n, or the smallest 7-smooth multiple
+    of 256 that is >= 2n.  Even, so that a band reaching the Nyquist edges
+    f_het +- 1/(2 dt) starts and ends on bins; an even 7-smooth m >= 2n is
+    2j with j 7-smooth and j >= n, and a 7-smooth multiple of 256 is 256j
+    with j 7-smooth and 256j >= 2n."""
     if policy == NFFT_TWICE:
         return 2 * n
     if policy == NFFT_SMOOTH7:
         return 2 * next_7smooth(n)
+    if policy == NFFT_SMOOTH7_256:
+        return 256 * next_7smooth(-(-2 * n // 256))
     raise ValueError("unknown FFT length policy")
 
 

@@ -153,7 +153,12 @@ bool choose_factors(int64_t n_fft, int lds_max, int fft_l1, int* out_la, int* ou
             fft_pass_b_lds((int)lb, 64) > (size_t)lds_max)
             continue;
         const double lds_a = (double)la * 16, lds_b = (double)lb * 128;
-        const double score = (sa.n_stages + sb.n_stages) * 1e9 + ((la % 8) ? 1e8 : 0.0) + std::max(lds_a, lds_b);
+        // a second pass of one column per wave (LB = 256, 512, 768) first,
+        // the longest such; then the fewest stages, L1 a multiple of 8 and
+        // the most balanced LDS footprints
+        const bool wave = fft_pass_b_wave_e((int)lb) != 0;
+        const double score = (wave ? -1e12 - 1e9 * (double)lb : 0.0) + (sa.n_stages + sb.n_stages) * 1e9 +
+                             ((la % 8) ? 1e8 : 0.0) + std::max(lds_a, lds_b);
         if (score < best_score) {
             best_score = score;
             best_la = (int)la;
@@ -449,7 +454,8 @@ int rsf_plan_create(rsf_plan** out, const rsf_plan_desc* d) {
         return fail(RSF_EUNSUPPORTED, "taps must be even and in 2..%d", RSF_MAX_TAPS);
     if (d->storage != RSF_STORE_F32 && d->storage != RSF_STORE_F16) return fail(RSF_EINVAL, "unknown storage");
     if (d->fft_l1 < 0) return fail(RSF_EINVAL, "fft_l1 must be 0 (automatic) or positive");
-    if (d->nfft_policy != RSF_NFFT_TWICE && d->nfft_policy != RSF_NFFT_SMOOTH7)
+    if (d->nfft_policy != RSF_NFFT_TWICE && d->nfft_policy != RSF_NFFT_SMOOTH7 &&
+        d->nfft_policy != RSF_NFFT_SMOOTH7_256)
         return fail(RSF_EINVAL, "unknown FFT length policy");
     const rsf_ephemeris& E = d->eph;
     if (!is_fin(E.au_c) || !is_fin(E.re_c) || !is_fin(E.eps) || !is_fin(E.lambda0) || !is_fin(E.theta0) ||
@@ -468,7 +474,12 @@ int rsf_plan_create(rsf_plan** out, const rsf_plan_desc* d) {
     p->binary = 0;
     p->n = d->n;
     // even, so that a band reaching f_het +- 1/(2 dt) has its edges on bins
-    p->n_fft = (d->nfft_policy == RSF_NFFT_TWICE) ? 2 * d->n : 2 * next_7smooth(d->n);
+    if (d->nfft_policy == RSF_NFFT_TWICE)
+        p->n_fft = 2 * d->n;
+    else if (d->nfft_policy == RSF_NFFT_SMOOTH7)
+        p->n_fft = 2 * next_7smooth(d->n);
+    else
+        p->n_fft = 256 * next_7smooth((2 * d->n + 255) / 256);
     if (!is_7smooth(p->n_fft)) {
         delete p;
         return fail(RSF_EUNSUPPORTED, "FFT length %lld has a prime factor above 7", (long long)(2 * d->n));

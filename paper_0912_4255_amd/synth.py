@@ -79,6 +79,7 @@ KERNEL_LANCZOS = 0
 KERNEL_DIRICHLET = 1
 NFFT_TWICE = 0        # N_fft = 2 N
 NFFT_SMOOTH7 = 1      # smallest 2^a 3^b 5^c 7^d >= 2 N
+NFFT_SMOOTH7_256 = 2  # smallest 256 x 2^a 3^b 5^c 7^d >= 2 N
 STORE_F32 = 0
 STORE_F16 = 1
 
@@ -266,7 +267,7 @@ def workload_c3_segment(i: int, n_sky: int = 4096, n_fdot: int = 16) -> Workload
     n_gaps = int(round(0.05 * seg.n / 3600))
     gaps = random_gaps(rg, seg.n, gap_len=3600, n_gaps=n_gaps)
     return Workload(name=f"C3[{i}]", detectors=(DET_H,), segment=seg, f_lo=99.0, f_hi=101.0,
-                    kernel=KERNEL_DIRICHLET, taps=16, nfft_policy=NFFT_SMOOTH7,
+                    kernel=KERNEL_DIRICHLET, taps=16, nfft_policy=NFFT_SMOOTH7_256,
                     skies=skies, fdots=fdot_grid(n_fdot), gaps=[gaps], seed=SEED_BASE + 2)
 
 

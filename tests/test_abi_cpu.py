@@ -98,16 +98,30 @@ def test_invalid_descriptors_rejected_before_device_use(lib):
 
 def test_fft_factorisation_covers_every_workload_length(lib):
     """Every FFT length of the standard workloads, and of all 64 uneven
-    segments (even 7-smooth lengths), has a two-pass factorisation that fits
-    160 KiB of LDS; non-7-smooth lengths are refused."""
-    from oracle.fstat import NFFT_SMOOTH7, fft_length
+    segments (even 7-smooth lengths, and 7-smooth multiples of 256), has a
+    two-pass factorisation that fits 160 KiB of LDS, with a one-column-per-
+    wave second pass wherever one fits; non-7-smooth lengths are refused."""
+    from oracle.fstat import NFFT_SMOOTH7, NFFT_SMOOTH7_256, fft_length
     from paper_0912_4255_amd.synth import c3_segment_lengths
     lengths = [345600, 6912000, 10368000, 3456000]
     lengths += [fft_length(n, NFFT_SMOOTH7) for n in c3_segment_lengths()]
+    lengths += [fft_length(n, NFFT_SMOOTH7_256) for n in c3_segment_lengths()]
     for m in lengths:
         l1, l2 = C.c_int32(), C.c_int32()
         assert lib.rsf_fft_factor(m, 163840, 0, C.byref(l1), C.byref(l2)) == L.RSF_OK, (m, lib.rsf_last_error())
         assert l1.value * l2.value == m and l1.value <= 10240
+    # the one-column-per-wave second pass (L2 = 256, 512, 768) is preferred where it fits
+    l1, l2 = C.c_int32(), C.c_int32()
+    assert lib.rsf_fft_factor(6912000, 163840, 0, C.byref(l1), C.byref(l2)) == L.RSF_OK
+    assert (l1.value, l2.value) == (9000, 768)
+    wave = 0
+    for n in c3_segment_lengths():
+        m = fft_length(n, NFFT_SMOOTH7_256)
+        assert lib.rsf_fft_factor(m, 163840, 0, C.byref(l1), C.byref(l2)) == L.RSF_OK
+        wave += l2.value in (256, 512, 768)
+        if any(m % lb == 0 and m // lb <= 10000 for lb in (256, 512, 768)):
+            assert l2.value in (256, 512, 768), (m, l1.value, l2.value)
+    assert wave >= 45
     assert lib.rsf_fft_factor(2 * 11 * 1000, 163840, 0, None, None) == L.RSF_EUNSUPPORTED
     assert lib.rsf_fft_factor(6912000, 163840, 7200, C.byref(l1), None) == L.RSF_OK and l1.value == 7200
 

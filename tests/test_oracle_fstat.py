@@ -233,8 +233,14 @@ def test_smooth7_length_is_least_even_smooth_and_full_band_fits():
         m = of.fft_length(n, of.NFFT_SMOOTH7)
         want = next(k for k in range(2 * n, 4 * n + 16) if k % 2 == 0 and smooth(k))
         assert m == want, n
+    # the multiple-of-256 policy, by brute force
+    for n in list(range(1, 700, 7)) + [10007, 86413, 1126800]:
+        m = of.fft_length(n, of.NFFT_SMOOTH7_256)
+        want = next(k for k in range(256, 8 * n + 1024, 256) if k >= 2 * n and smooth(k))
+        assert m == want, n
     for n in c3_segment_lengths():
-        m = of.fft_length(n, of.NFFT_SMOOTH7)
+        m = of.fft_length(n, of.NFFT_SMOOTH7_256)
+        assert m % 256 == 0 and m >= 2 * n and m <= 2.04 * n
         df = 1.0 / (m * 0.5)
         s_lo = int(round(-1.0 / df))
         n_out = int(round(2.0 / df))
