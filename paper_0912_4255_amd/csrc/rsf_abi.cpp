@@ -1134,6 +1134,9 @@ int point_common(const rsf_plan* p, const rsf_segment* seg, const double* theta,
     a.theta = theta;
     a.order = p->spin_order;
     a.binary = p->binary ? 1 : 0;
+    // runs of 64 samples short against a sidereal day: the chain is
+    // interpolated along each run (remainder below 2e-11 s in t_m)
+    a.fast = (!p->binary && p->d.n_det == 1 && 63.0 * p->d.dt * 2.0 * M_PI * std::fabs(p->eph.inv_p_sid) <= 4e-3) ? 1 : 0;
     a.n_cand = (int)n;
     a.P = (p->n + 63) / 64;
     a.n_blocks = L.n_blocks;

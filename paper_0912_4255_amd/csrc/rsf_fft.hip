@@ -102,16 +102,17 @@ constexpr int kInPer = (kFftMaxLen / 2 + kNT - 1) / kNT;
 // First-pass rows with the radix sequence fixed at compile time (the row
 // length of the 10-day and 30-day workloads, 9000 = 10 10 10 9, with its
 // upper half zero).  Stage sizes are constants, so the butterfly index
-// arithmetic folds, and the twiddles of the two middle stages come from
-// per-stage tables in LDS, W_{Ns R}^{k r} at [r - 1][k], instead of being
-// formed by complex multiplications in every butterfly.
+// arithmetic and the LDS offsets fold into the instructions, and only the
+// radices of this plan are compiled in.  The base twiddle W_{Ns R}^k of a
+// middle-stage butterfly comes from a small per-stage table in LDS, its
+// powers from complex products.
 // ---------------------------------------------------------------------------
 constexpr int kRow9000 = 1;
-constexpr int kRow9000Tab = 9 * 10 + 9 * 100;  // table entries of stages Ns = 10 and Ns = 100
+constexpr int kRow9000Tab = 10 + 100;  // base twiddles of the stages Ns = 10 and Ns = 100
 
 // One middle (or first) stage of length L after Ns points, radix R; table
-// tab = W_{Ns R}^{k r} at [r - 1][k] (unused when Ns = 1).  HZ: the upper
-// half of the input is zero.
+// tab = W_{Ns R}^k for k < Ns (unused when Ns = 1).  HZ: the upper half of
+// the input is zero.
 template <int L, int Ns, int R, bool HZ>
 __device__ __forceinline__ void row_stage(cp* __restrict__ s, const float2* __restrict__ tab) {
     constexpr int LR = L / R;
@@ -125,9 +126,13 @@ __device__ __forceinline__ void row_stage(cp* __restrict__ s, const float2* __re
 #pragma unroll
             for (int r = 0; r < R; ++r) v[q][r] = (HZ && 2 * r >= R) ? make_float4(0.f, 0.f, 0.f, 0.f) : s[j + r * LR];
             if constexpr (Ns > 1) {
-                const int k = j % Ns;
+                const float2 w1 = tab[j % Ns];
+                float2 w = w1;
 #pragma unroll
-                for (int r = 1; r < R; ++r) v[q][r] = cp_rot(v[q][r], tab[(r - 1) * Ns + k]);
+                for (int r = 1; r < R; ++r) {
+                    v[q][r] = cp_rot(v[q][r], w);
+                    if (r + 1 < R) w = c_mul(w, w1);
+                }
             }
             Dft<R>::run(v[q]);
         }
@@ -166,15 +171,10 @@ __device__ __forceinline__ void row_last(const cp* __restrict__ s, const TwLds& 
     }
 }
 
-// Fill the stage tables of the 9000-point row from the two-level table.
+// Fill the stage tables of the 9000-point row from the two-level table:
+// W_100^k (k < 10), then W_1000^k (k < 100).
 __device__ __forceinline__ void row9000_tables(float2* tab, const TwLds& tw) {
-    for (int i = threadIdx.x; i < kRow9000Tab; i += kNT) {
-        const bool s2 = i < 90;
-        const int Ns = s2 ? 10 : 100;
-        const int e = s2 ? i : i - 90;
-        const int r = e / Ns + 1, k = e - (r - 1) * Ns;
-        tab[i] = tw(k * r * (9000 / (Ns * 10)));
-    }
+    for (int i = threadIdx.x; i < kRow9000Tab; i += kNT) tab[i] = (i < 10) ? tw(90 * i) : tw(9 * (i - 10));
 }
 
 template <typename Sink>
@@ -182,7 +182,7 @@ __device__ __forceinline__ void row9000_fft(cp* __restrict__ s, const float2* __
                                             Sink& sink) {
     row_stage<9000, 1, 10, true>(s, nullptr);
     row_stage<9000, 10, 10, false>(s, tab);
-    row_stage<9000, 100, 10, false>(s, tab + 90);
+    row_stage<9000, 100, 10, false>(s, tab + 10);
     row_last<9000, 9>(s, tw, sink);
 }
 

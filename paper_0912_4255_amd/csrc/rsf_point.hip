@@ -268,12 +268,132 @@ __device__ __forceinline__ void kernel_w(const InterpDev& ip, float x, float sx,
     }
 }
 
+// The sky's unit vector n0, its derivatives, and the polarisation basis
+// (p, q) with the derivatives the gradient needs.
+struct SkyGeom {
+    double3 n0, n0a, n0d, pp, qq, pa, qa, qd;
+};
+
+// The timing chain of one resampled sample (eqs. eq4pt2, eq21 and the beam
+// patterns of eq2, eq3), and for the gradient its sky (and orbit)
+// derivatives.
+struct ChainOut {
+    double T1;                   // fixed-point iterate of T, the window's expansion point
+    RoemerD x0, xa, xd;          // n0.r, n0_alpha.r, n0_delta.r and their time derivatives at T1
+    double T, av, bv, dTa, dTd, daa, dad, dba, dbd;
+    double dTo[3], dao[3], dbo[3];
+};
+
+// The chain at t_b = tb, a sample dl0 seconds after the first sample of its
+// run (whose orbital and sidereal angles are ra): one fixed-point step and one
+// Newton step of the inversion (residual below 1e-12 s), then the beam
+// patterns at T.
+template <bool GRAD, bool BIN>
+__device__ __forceinline__ ChainOut chain_at(const PointArgs& A, const DetDev& D, const RunAngles& ra, double dl0,
+                                             double tb, const SkyGeom& g, const BinaryOrbit& bo, double wo,
+                                             double w_sid) {
+    const double3 n0 = g.n0, n0a = g.n0a, n0d = g.n0d, pp = g.pp, qq = g.qq, pa = g.pa, qa = g.qa, qd = g.qd;
+    ChainOut c{};
+    // eq. eq21: one fixed-point step and one Newton step (residual below 1e-12 s)
+    // a binary source's grid is regular in emission time: the
+    // target is t_b + R(t_start + t_b)
+    double tgt = tb, dRk[3] = {0.0, 0.0, 0.0};
+    if constexpr (BIN) {
+        double sp, cp;
+        const double te = A.t_start + tb;
+        tgt = tb + orbit_delay(bo, te, sp, cp);
+        if (GRAD) orbit_partials(bo, te, sp, cp, dRk);
+    }
+    const double dl = dl0 + (BIN ? tgt - tb : 0.0);  // offset from the run's first sample
+    const double tm0 = dot3(n0, orbit_from(ra, dl, A.eph, D, wo, w_sid).r);
+    c.T1 = tgt - tm0;
+    const Orbit o1 = orbit_from(ra, dl - tm0, A.eph, D, wo, w_sid);
+    {
+        const double wo2 = 4.0 * kPi * kPi * A.eph.inv_p_orb * A.eph.inv_p_orb;
+        const double ws2 = w_sid * w_sid;
+        const double rez = A.eph.re_c * D.slat;
+        c.x0 = project(o1, n0, A.eph, wo2, ws2, rez);
+        if (GRAD) {
+            c.xa = project(o1, n0a, A.eph, wo2, ws2, rez);
+            c.xd = project(o1, n0d, A.eph, wo2, ws2, rez);
+        }
+    }
+    const double dT = -(c.T1 + dot3(n0, o1.r) - tgt) / (1.0 + dot3(n0, o1.v));
+    c.T = c.T1 + dT;
+    // the orbit at T: positions moved by v dT, the sidereal angle turned by w_sid dT
+    Orbit o = o1;
+    o.r = make_double3(o1.r.x + o1.v.x * dT, o1.r.y + o1.v.y * dT, o1.r.z + o1.v.z * dT);
+    {
+        const double a = w_sid * dT;
+        const double sa = a * (1.0 - a * a / 6.0), ca = 1.0 - 0.5 * a * a;
+        o.sth = o1.sth * ca + o1.cth * sa;
+        o.cth = o1.cth * ca - o1.sth * sa;
+    }
+    // arms at the local sidereal angle, and their rate of change
+    const double3 eE = make_double3(-o.sth, o.cth, 0.0);
+    const double3 eN = make_double3(-D.slat * o.cth, -D.slat * o.sth, D.clat);
+    const double3 eEt = make_double3(-o.cth, -o.sth, 0.0);
+    const double3 eNt = make_double3(D.slat * o.sth, -D.slat * o.cth, 0.0);
+    const double3 uu = make_double3(D.cgu * eE.x + D.sgu * eN.x, D.cgu * eE.y + D.sgu * eN.y,
+                                    D.cgu * eE.z + D.sgu * eN.z);
+    const double3 vv = make_double3(D.cgv * eE.x + D.sgv * eN.x, D.cgv * eE.y + D.sgv * eN.y,
+                                    D.cgv * eE.z + D.sgv * eN.z);
+    const double up = dot3(uu, pp), uq = dot3(uu, qq), vp = dot3(vv, pp), vq = dot3(vv, qq);
+    c.av = 0.5 * (up * up - uq * uq - vp * vp + vq * vq);
+    c.bv = up * uq - vp * vq;
+    if (GRAD) {
+        const double tmdot = dot3(n0, o.v);
+        c.dTa = -dot3(n0a, o.r) / (1.0 + tmdot);
+        c.dTd = -dot3(n0d, o.r) / (1.0 + tmdot);
+        const double3 ut = make_double3(D.cgu * eEt.x + D.sgu * eNt.x, D.cgu * eEt.y + D.sgu * eNt.y, 0.0);
+        const double3 vt = make_double3(D.cgv * eEt.x + D.sgv * eNt.x, D.cgv * eEt.y + D.sgv * eNt.y, 0.0);
+        // d/dT through the sidereal rotation (per second)
+        const double upt = dot3(ut, pp) * w_sid, uqt = dot3(ut, qq) * w_sid;
+        const double vpt = dot3(vt, pp) * w_sid, vqt = dot3(vt, qq) * w_sid;
+        const double adT = up * upt - uq * uqt - vp * vpt + vq * vqt;
+        const double bdT = upt * uq + up * uqt - vpt * vq - vp * vqt;
+        // d/dalpha, d/ddelta at fixed T through p and q
+        const double upa = dot3(uu, pa), uqa = dot3(uu, qa), vpa = dot3(vv, pa), vqa = dot3(vv, qa);
+        const double uqd = dot3(uu, qd), vqd = dot3(vv, qd);
+        c.daa = up * upa - uq * uqa - vp * vpa + vq * vqa + adT * c.dTa;
+        c.dba = upa * uq + up * uqa - vpa * vq - vp * vqa + bdT * c.dTa;
+        c.dad = -uq * uqd + vq * vqd + adT * c.dTd;
+        c.dbd = up * uqd - vp * vqd + bdT * c.dTd;
+        if constexpr (BIN) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                c.dTo[i] = dRk[i] / (1.0 + tmdot);
+                c.dao[i] = adT * c.dTo[i];
+                c.dbo[i] = bdT * c.dTo[i];
+            }
+        }
+    }
+    return c;
+}
+
+// Per-run interpolation of the chain (used when the run is short against a
+// sidereal day): the quantities that vary along a run of 64 samples (t_m,
+// a, b and, for the gradient, dT/dalpha, dT/ddelta and the sky derivatives of
+// a and b) are evaluated exactly at lanes 0, 32 and 63 and every lane takes
+// the quadratic through them, q(l) = q_0 + l d_1 + l (l - 32) d_2.  Each
+// quantity is a sum of circular motions with rate w <= 2 w_sid (the orbital
+// rate is 366 times smaller), so the remainder is at most 0.008 times the
+// third derivative's bound times (63 dt)^3, i.e. 0.008 A (2 w_sid 63 dt)^3
+// with A the amplitude: for 63 dt w_sid <= 4e-3 that is below 2e-11 s for
+// t_m (A = R_E / c) and below 5e-9 for a, b and their derivatives.
+constexpr int kChainQ = 9;                         // interpolated quantities
+constexpr int kChainRef = 13;                      // T1 and the three expansions of lane 0
+constexpr int kRunVals = 3 * kChainQ + kChainRef;  // per run: q_0, d_1, d_2, then the reference
+constexpr int kWaveRuns = kPointTiles * (kTileA / 4);
+
 }  // namespace
 
 // The binary gradient's 50 to 58 FP64 partial sums do not fit beside the rest
 // at two waves per SIMD; at one wave per SIMD its spills go to the
 // accumulation registers instead of scratch memory.
-template <bool GRAD, int ORDER, bool BIN>
+// FAST: one detector, no orbit, runs short against a sidereal day: the
+// chain of each run is interpolated from three exact nodes.
+template <bool GRAD, int ORDER, bool BIN, bool FAST>
 __global__ __launch_bounds__(kThreads, (BIN && GRAD) ? 1 : 2) void rsf_point_k(PointArgs A) {
     using SL = Slots<ORDER, BIN>;
     constexpr int NP = SL::NP;
@@ -284,6 +404,8 @@ __global__ __launch_bounds__(kThreads, (BIN && GRAD) ? 1 : 2) void rsf_point_k(P
     __shared__ float4 win[4][kWinMax];  // z (re, im), 2 pi f_het dd_p/dalpha, 2 pi f_het dd_p/ddelta
     __shared__ float4 wino[4][(BIN && GRAD) ? kWinMax : 1];  // 2 pi f_het dd_p/d(a_p, P_b, t_asc)
     __shared__ double red[4][kPointSums];
+    __shared__ double runs[4][FAST ? kWaveRuns : 1][FAST ? kRunVals : 1];
+    static_assert(!(FAST && BIN), "the interpolated chain is for isolated sources");
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -312,12 +434,16 @@ __global__ __launch_bounds__(kThreads, (BIN && GRAD) ? 1 : 2) void rsf_point_k(P
     const double3 pa = make_double3(-ca, -sa, 0.0);          // dp/dalpha (dp/ddelta = 0)
     const double3 qa = make_double3(sd * sa, -sd * ca, 0.0);  // dq/dalpha
     const double3 qd = make_double3(-cd * ca, -cd * sa, -sd); // dq/ddelta
+    const SkyGeom geo{n0, n0a, n0d, pp, qq, pa, qa, qd};
     const double w_sid = 2.0 * kPi * A.eph.inv_p_sid;
     const int W = A.ip.taps;
     const int hw = W / 2;
     // Dirichlet weights by their small-argument series when pi x / n < 0.01 on every tap
     const float pin = kPiF / (float)A.ip.n;
     const bool dir_series = A.ip.kernel == 1 && pin * (float)(hw + 1) < 0.01f;
+    // ... and when pi x / n < 2.9e-4 on every tap, g = 1 and g' pi / n = 0 to
+    // FP32 precision: the weights are sinc(x) and its derivative
+    const bool dir_flat = A.ip.kernel == 1 && pin * (float)(hw + 1) < 2.9e-4f;
 
     double acc[S_USED];
 #pragma unroll
@@ -338,6 +464,62 @@ __global__ __launch_bounds__(kThreads, (BIN && GRAD) ? 1 : 2) void rsf_point_k(P
         sincos(w_sid * dtau, &s_dg, &c_dg);
     }
 
+    if constexpr (FAST) {
+        // nodes: lanes 0, 32, 63 of each of this wave's runs (run rr is row
+        // wave + 4 (rr % 4) of tile rr / 4), the chain evaluated exactly
+        const DetDev& D = A.det[0];
+        for (int nd = lane; nd < 3 * kWaveRuns; nd += 64) {
+            const int rr = nd / 3, m = nd - 3 * (nd / 3);
+            const int off = m == 0 ? 0 : (m == 1 ? 32 : 63);
+            const int64_t row = ((int64_t)blockIdx.x * kPointTiles + rr / 4) * kTileA + wave + 4 * (rr % 4);
+            const double tau_run = A.t_start + (double)(row * kTileB) * A.dt;
+            RunAngles rn;
+            sincos(A.eph.lambda0 + 2.0 * kPi * frac_rev(tau_run * A.eph.inv_p_orb), &rn.sl, &rn.cl);
+            sincos(A.eph.theta0 + 2.0 * kPi * frac_rev(tau_run * A.eph.inv_p_sid), &rn.sg, &rn.cg);
+            const double tb = (double)(row * kTileB + off) * A.dt;
+            const ChainOut c = chain_at<GRAD, false>(A, D, rn, (double)off * A.dt, tb, geo, bo, wo, w_sid);
+            double* v = runs[wave][rr] + m * kChainQ;
+            v[0] = tb - c.T;
+            v[1] = c.av;
+            v[2] = c.bv;
+            v[3] = c.dTa;
+            v[4] = c.dTd;
+            v[5] = c.daa;
+            v[6] = c.dad;
+            v[7] = c.dba;
+            v[8] = c.dbd;
+            if (m == 0) {
+                double* rf = runs[wave][rr] + 3 * kChainQ;
+                rf[0] = c.T1;
+                rf[1] = c.x0.tm;
+                rf[2] = c.x0.d1;
+                rf[3] = c.x0.d2;
+                rf[4] = c.x0.d3;
+                rf[5] = c.xa.tm;
+                rf[6] = c.xa.d1;
+                rf[7] = c.xa.d2;
+                rf[8] = c.xa.d3;
+                rf[9] = c.xd.tm;
+                rf[10] = c.xd.d1;
+                rf[11] = c.xd.d2;
+                rf[12] = c.xd.d3;
+            }
+        }
+        __syncthreads();
+        // node values (q_0, q_32, q_63) to Newton coefficients (q_0, d_1, d_2)
+        if (lane < kWaveRuns) {
+            double* v = runs[wave][lane];
+#pragma unroll
+            for (int i = 0; i < kChainQ; ++i) {
+                const double q0 = v[i], q32 = v[kChainQ + i], q63 = v[2 * kChainQ + i];
+                const double d1 = (q32 - q0) * (1.0 / 32.0);
+                v[kChainQ + i] = d1;
+                v[2 * kChainQ + i] = ((q63 - q32) * (1.0 / 31.0) - d1) * (1.0 / 63.0);
+            }
+        }
+        __syncthreads();
+    }
+
     for (int tile = 0; tile < kPointTiles; ++tile) {
         const int64_t a0 = ((int64_t)blockIdx.x * kPointTiles + tile) * kTileA;
         for (int r = 0; r < kTileA / 4; ++r) {
@@ -349,106 +531,65 @@ __global__ __launch_bounds__(kThreads, (BIN && GRAD) ? 1 : 2) void rsf_point_k(P
                 const DetDev& D = A.det[X];
                 int j = 0;
                 float frac = 0.f;
-                double T = tb, tm = 0.0, dTa = 0.0, dTd = 0.0;
-                double av = 0.0, bv = 0.0, daa = 0.0, dad = 0.0, dba = 0.0, dbd = 0.0;
-                double dTo[3] = {0.0, 0.0, 0.0}, dao[3] = {0.0, 0.0, 0.0}, dbo[3] = {0.0, 0.0, 0.0};
+                double T = tb, tm = 0.0;
                 bool mk = false;
-                double T1 = 0.0;
-                RoemerD x0{}, xa{}, xd{};  // expansions of n0.r, n0_alpha.r, n0_delta.r about T1
+                ChainOut c{};
+                double t_ref;
+                RoemerD q0, qa{}, qd{};
+                if constexpr (FAST) {
+                    // the run's quadratic through its nodes at lanes 0, 32, 63
+                    const double* nd = runs[wave][tile * (kTileA / 4) + r];
+                    const double l = (double)lane, b = l * (l - 32.0);
+                    auto at = [&](int i) { return nd[i] + l * nd[kChainQ + i] + b * nd[2 * kChainQ + i]; };
+                    tm = at(0);
+                    c.av = at(1);
+                    c.bv = at(2);
+                    if (GRAD) {
+                        c.dTa = at(3);
+                        c.dTd = at(4);
+                        c.daa = at(5);
+                        c.dad = at(6);
+                        c.dba = at(7);
+                        c.dbd = at(8);
+                    }
+                    const double* rf = nd + 3 * kChainQ;
+                    t_ref = rf[0];
+                    q0 = RoemerD{rf[1], rf[2], rf[3], rf[4]};
+                    if (GRAD) {
+                        qa = RoemerD{rf[5], rf[6], rf[7], rf[8]};
+                        qd = RoemerD{rf[9], rf[10], rf[11], rf[12]};
+                    }
+                    T = tb - tm;
+                } else {
+                    if (valid) {
+                        c = chain_at<GRAD, BIN>(A, D, ra, (double)lane * A.dt, tb, geo, bo, wo, w_sid);
+                        T = c.T;
+                        tm = tb - T;
+                    }
+                    // expansion point of t_m (and of its sky derivatives) for the
+                    // window: the first valid lane's fixed-point iterate
+                    const uint64_t vmask = __ballot(valid);
+                    const int src = vmask ? __ffsll((long long)vmask) - 1 : 0;
+                    t_ref = readlane_d(c.T1, src);
+                    q0 = readlane_rd(c.x0, src);
+                    if (GRAD) {
+                        qa = readlane_rd(c.xa, src);
+                        qd = readlane_rd(c.xd, src);
+                    }
+                }
                 if (valid) {
-                    // eq. eq21: one fixed-point step and one Newton step (residual below 1e-12 s)
-                    // a binary source's grid is regular in emission time: the
-                    // target is t_b + R(t_start + t_b)
-                    double tgt = tb, dRk[3] = {0.0, 0.0, 0.0};
-                    if constexpr (BIN) {
-                        double sp, cp;
-                        const double te = A.t_start + tb;
-                        tgt = tb + orbit_delay(bo, te, sp, cp);
-                        if (GRAD) orbit_partials(bo, te, sp, cp, dRk);
-                    }
-                    const double dl = (double)lane * A.dt + (BIN ? tgt - tb : 0.0);  // offset from the run's first sample
-                    const double tm0 = dot3(n0, orbit_from(ra, dl, A.eph, D, wo, w_sid).r);
-                    T1 = tgt - tm0;
-                    const Orbit o1 = orbit_from(ra, dl - tm0, A.eph, D, wo, w_sid);
-                    {
-                        const double wo2 = 4.0 * kPi * kPi * A.eph.inv_p_orb * A.eph.inv_p_orb;
-                        const double ws2 = w_sid * w_sid;
-                        const double rez = A.eph.re_c * D.slat;
-                        x0 = project(o1, n0, A.eph, wo2, ws2, rez);
-                        if (GRAD) {
-                            xa = project(o1, n0a, A.eph, wo2, ws2, rez);
-                            xd = project(o1, n0d, A.eph, wo2, ws2, rez);
-                        }
-                    }
-                    const double dT = -(T1 + dot3(n0, o1.r) - tgt) / (1.0 + dot3(n0, o1.v));
-                    T = T1 + dT;
-                    // the orbit at T: positions moved by v dT, the sidereal angle turned by w_sid dT
-                    Orbit o = o1;
-                    o.r = make_double3(o1.r.x + o1.v.x * dT, o1.r.y + o1.v.y * dT, o1.r.z + o1.v.z * dT);
-                    {
-                        const double a = w_sid * dT;
-                        const double sa = a * (1.0 - a * a / 6.0), ca = 1.0 - 0.5 * a * a;
-                        o.sth = o1.sth * ca + o1.cth * sa;
-                        o.cth = o1.cth * ca - o1.sth * sa;
-                    }
-                    tm = tb - T;
                     const double u = T / A.dt;
                     const double fl = floor(u);
                     j = (int)fl;
                     frac = (float)(u - fl);
                     const int64_t jn = (int64_t)floor(u + 0.5);
                     mk = (jn >= 0) && (jn < A.n) && !in_gap(A.gaps[X], A.n_gaps[X], jn);
-                    // arms at the local sidereal angle, and their rate of change
-                    const double3 eE = make_double3(-o.sth, o.cth, 0.0);
-                    const double3 eN = make_double3(-D.slat * o.cth, -D.slat * o.sth, D.clat);
-                    const double3 eEt = make_double3(-o.cth, -o.sth, 0.0);
-                    const double3 eNt = make_double3(D.slat * o.sth, -D.slat * o.cth, 0.0);
-                    const double3 uu = make_double3(D.cgu * eE.x + D.sgu * eN.x, D.cgu * eE.y + D.sgu * eN.y,
-                                                    D.cgu * eE.z + D.sgu * eN.z);
-                    const double3 vv = make_double3(D.cgv * eE.x + D.sgv * eN.x, D.cgv * eE.y + D.sgv * eN.y,
-                                                    D.cgv * eE.z + D.sgv * eN.z);
-                    const double up = dot3(uu, pp), uq = dot3(uu, qq), vp = dot3(vv, pp), vq = dot3(vv, qq);
-                    av = 0.5 * (up * up - uq * uq - vp * vp + vq * vq);
-                    bv = up * uq - vp * vq;
-                    if (GRAD) {
-                        const double tmdot = dot3(n0, o.v);
-                        dTa = -dot3(n0a, o.r) / (1.0 + tmdot);
-                        dTd = -dot3(n0d, o.r) / (1.0 + tmdot);
-                        const double3 ut = make_double3(D.cgu * eEt.x + D.sgu * eNt.x, D.cgu * eEt.y + D.sgu * eNt.y, 0.0);
-                        const double3 vt = make_double3(D.cgv * eEt.x + D.sgv * eNt.x, D.cgv * eEt.y + D.sgv * eNt.y, 0.0);
-                        // d/dT through the sidereal rotation (per second)
-                        const double upt = dot3(ut, pp) * w_sid, uqt = dot3(ut, qq) * w_sid;
-                        const double vpt = dot3(vt, pp) * w_sid, vqt = dot3(vt, qq) * w_sid;
-                        const double adT = up * upt - uq * uqt - vp * vpt + vq * vqt;
-                        const double bdT = upt * uq + up * uqt - vpt * vq - vp * vqt;
-                        // d/dalpha, d/ddelta at fixed T through p and q
-                        const double upa = dot3(uu, pa), uqa = dot3(uu, qa), vpa = dot3(vv, pa), vqa = dot3(vv, qa);
-                        const double uqd = dot3(uu, qd), vqd = dot3(vv, qd);
-                        daa = up * upa - uq * uqa - vp * vpa + vq * vqa + adT * dTa;
-                        dba = upa * uq + up * uqa - vpa * vq - vp * vqa + bdT * dTa;
-                        dad = -uq * uqd + vq * vqd + adT * dTd;
-                        dbd = up * uqd - vp * vqd + bdT * dTd;
-                        if constexpr (BIN) {
-#pragma unroll
-                            for (int i = 0; i < 3; ++i) {
-                                dTo[i] = dRk[i] / (1.0 + tmdot);
-                                dao[i] = adT * dTo[i];
-                                dbo[i] = bdT * dTo[i];
-                            }
-                        }
-                    }
                 }
-                // expansion point of t_m (and of its sky derivatives) for the
-                // window: the first valid lane's fixed-point iterate
-                const uint64_t vmask = __ballot(valid);
-                const int src = vmask ? __ffsll((long long)vmask) - 1 : 0;
-                const double t_ref = readlane_d(T1, src);
-                const RoemerD q0 = readlane_rd(x0, src);
-                RoemerD qa{}, qd{};
-                if (GRAD) {
-                    qa = readlane_rd(xa, src);
-                    qd = readlane_rd(xd, src);
-                }
+                const double av = c.av, bv = c.bv, dTa = c.dTa, dTd = c.dTd;
+                const double daa = c.daa, dad = c.dad, dba = c.dba, dbd = c.dbd;
+                const double* dTo = c.dTo;
+                const double* dao = c.dao;
+                const double* dbo = c.dbo;
                 // detector-grid window of this run, heterodyne-corrected
                 int jmin = valid ? j : INT_MAX;
                 int jmax = valid ? j : INT_MIN;
@@ -516,6 +657,8 @@ __global__ __launch_bounds__(kThreads, (BIN && GRAD) ? 1 : 2) void rsf_point_k(P
                         if (x == 0.f) {
                             w = 1.f;
                             dw = 0.f;
+                        } else if (dir_flat) {
+                            sinc_d(x, sx, cx, w, dw);
                         } else if (dir_series) {
                             // Dirichlet kernel of a long series: sinc(x) g(y), y = pi x / n
                             // small, g = y / tan(y) (n even) or y / sin(y) (n odd) as a series
@@ -757,20 +900,27 @@ int point_blocks(int64_t P) { return (int)((P + kTileA * kPointTiles - 1) / (kTi
 
 hipError_t launch_point(const PointArgs& a, bool grad, hipStream_t s) {
     const dim3 grid((unsigned)a.n_blocks, (unsigned)a.n_cand);
-#define RSF_POINT(G, O, B) hipLaunchKernelGGL((rsf_point_k<G, O, B>), grid, dim3(kThreads), 0, s, a)
-    switch (a.order * 4 + (a.binary ? 2 : 0) + (grad ? 1 : 0)) {
-        case 4: RSF_POINT(false, 1, false); break;
-        case 5: RSF_POINT(true, 1, false); break;
-        case 6: RSF_POINT(false, 1, true); break;
-        case 7: RSF_POINT(true, 1, true); break;
-        case 8: RSF_POINT(false, 2, false); break;
-        case 9: RSF_POINT(true, 2, false); break;
-        case 10: RSF_POINT(false, 2, true); break;
-        case 11: RSF_POINT(true, 2, true); break;
-        case 12: RSF_POINT(false, 3, false); break;
-        case 13: RSF_POINT(true, 3, false); break;
-        case 14: RSF_POINT(false, 3, true); break;
-        case 15: RSF_POINT(true, 3, true); break;
+#define RSF_POINT(G, O, B, F) hipLaunchKernelGGL((rsf_point_k<G, O, B, F>), grid, dim3(kThreads), 0, s, a)
+    const bool fast = a.fast && !a.binary && a.n_det == 1;
+    switch (a.order * 8 + (a.binary ? 4 : 0) + (fast ? 2 : 0) + (grad ? 1 : 0)) {
+        case 8: RSF_POINT(false, 1, false, false); break;
+        case 9: RSF_POINT(true, 1, false, false); break;
+        case 10: RSF_POINT(false, 1, false, true); break;
+        case 11: RSF_POINT(true, 1, false, true); break;
+        case 12: RSF_POINT(false, 1, true, false); break;
+        case 13: RSF_POINT(true, 1, true, false); break;
+        case 16: RSF_POINT(false, 2, false, false); break;
+        case 17: RSF_POINT(true, 2, false, false); break;
+        case 18: RSF_POINT(false, 2, false, true); break;
+        case 19: RSF_POINT(true, 2, false, true); break;
+        case 20: RSF_POINT(false, 2, true, false); break;
+        case 21: RSF_POINT(true, 2, true, false); break;
+        case 24: RSF_POINT(false, 3, false, false); break;
+        case 25: RSF_POINT(true, 3, false, false); break;
+        case 26: RSF_POINT(false, 3, false, true); break;
+        case 27: RSF_POINT(true, 3, false, true); break;
+        case 28: RSF_POINT(false, 3, true, false); break;
+        case 29: RSF_POINT(true, 3, true, false); break;
         default: return hipErrorInvalidValue;
     }
 #undef RSF_POINT

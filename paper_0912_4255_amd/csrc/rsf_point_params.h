@@ -24,6 +24,7 @@ struct PointArgs {
     const double* theta;      // [n_cand][3 + order (+ 3 when binary)]
     int order;                // spindown order s, 1..3
     int binary;               // theta ends with a circular orbit (a_p, P_b, t_asc)
+    int fast;                 // one detector, no orbit, 63 dt w_sid <= 4e-3: per-run interpolated chain
     int n_cand;
     int64_t P;                // 64-sample rows: ceil(n / 64)
     int n_blocks;             // blocks per candidate

@@ -80,6 +80,10 @@ __global__ __launch_bounds__(kThreads) void rsf_resample_k(ResampleArgs A) {
     const int W = A.ip.taps;
     const int hw = W / 2;
     const float pin = kPiF / (float)A.ip.n;  // pi / n of the Dirichlet kernel
+    // Dirichlet kernel of a long series: |y| = pi |x| / n < pi (hw + 1) / n
+    // keeps y / tan(y) (or y / sin(y)) within 1 + 3e-8, so in FP32 every
+    // weight is sin(pi x) / (pi x) = (-1)^m sin(pi frac) / (pi x), m = hw - i
+    const bool flat = A.ip.kernel == 1 && pin * (float)(hw + 1) < 2.9e-4f;
     double sA = 0.0, sB = 0.0, sC = 0.0;
     bool window_overflow = false;
 
@@ -152,7 +156,25 @@ __global__ __launch_bounds__(kThreads) void rsf_resample_k(ResampleArgs A) {
 
         float2 zt = make_float2(0.f, 0.f);
         if (valid) {
-            if (ok) {
+            if (ok && flat) {
+                const int base = j - hw + 1 - w0;
+                if (frac == 0.f) {
+                    zt = win[wave][base + hw - 1];  // x = 0 at the centre tap, sin(pi x) = 0 elsewhere
+                } else {
+                    // sum of (-1)^m z / x, then the common factor sin(pi frac) / pi
+                    float ax = 0.f, ay = 0.f;
+                    for (int i = 1; i <= W; ++i) {
+                        const float x = frac + (float)(hw - i);
+                        float r = __builtin_amdgcn_rcpf(x);
+                        if ((hw - i) & 1) r = -r;
+                        const float2 zz = win[wave][base + i - 1];
+                        ax += r * zz.x;
+                        ay += r * zz.y;
+                    }
+                    const float sc = sinpif(frac) * (1.0f / kPiF);
+                    zt = make_float2(ax * sc, ay * sc);
+                }
+            } else if (ok) {
                 const float sf = sinpif(frac);
                 const int base = j - hw + 1 - w0;
                 for (int i = 1; i <= W; ++i) {

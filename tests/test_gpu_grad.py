@@ -201,3 +201,41 @@ def test_higher_order_point_and_adjoint_match_oracle(gpu_lib, order):
         a, b = g_s[i, [0, 1, 1 + order, 2 + order]] * sc1, g_1[i] * sc1
         assert np.all(np.abs(a - b) <= 1e-4 * max(np.max(np.abs(b)), 1.0)), (i, a, b)
     plan.close()
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_interpolated_chain_against_oracle(gpu_lib, order):
+    """dt = 0.5 s (63 dt w_sid = 2.3e-3): the timing chain is evaluated at
+    three lanes of each 64-sample run and interpolated quadratically for the
+    others.  One day, three candidates near an injection: 2F within
+    1e-4 max(2F, 4) of the oracle, each gradient component (scaled by 1/T0,
+    1/T0^2 [, 1/T0^3], 1e-5, 1e-5) within 1e-3 of the largest scaled one."""
+    import torch
+    w = synth.small_workload(n=172800, dt=0.5, kernel=synth.KERNEL_DIRICHLET, taps=16)
+    rng = np.random.default_rng(9)
+    w.gaps = [synth.random_gaps(rng, w.segment.n, 3600, 3)]
+    df = 1.0 / (2 * w.segment.n * w.segment.dt)
+    inj = Injection(h0=1.0, cosi=0.2, psi=-0.3, phi0=2.0, f0=w.segment.f_het + 2200.3 * df,
+                    fdot=-4e-10, alpha=2.1, delta=-0.4)
+    xs, gaps = make_inputs(w, seed=8, injections=[inj])
+    plan = gpu_lib.Plan(w)
+    plan.set_spin_order(order)
+    tx, tg = to_gpu(xs, gaps)
+    th = _cands(inj, df)[:3]
+    if order == 2:
+        th = np.column_stack([th[:, :2], [1e-17, -2e-17, 0.0], th[:, 2:]])
+    print(f"\ncase: interpolated chain, order {order}", flush=True)
+    g_in = torch.ones(3, dtype=torch.float32).cuda()
+    twoF, gth = plan.backward(tx, tg, torch.from_numpy(th).cuda(), g_in)
+    twoF, gth = twoF.cpu().numpy(), gth.cpu().numpy()
+    prob = og.PointProblem(xs, gaps, w.segment, list(w.detectors), w.eph, w.kernel, w.taps)
+    T0 = w.segment.n * w.segment.dt
+    scale = np.array([1 / T0 ** (i + 1) for i in range(1 + order)] + [1e-5, 1e-5])
+    for i, t in enumerate(th):
+        ref2f = prob.twoF(t)
+        assert abs(twoF[i] - ref2f) <= 1e-4 * max(ref2f, 4.0), (i, twoF[i], ref2f)
+        rg = og.gradient(prob, t)
+        gs, rs = gth[i] * scale, rg * scale
+        print(f"candidate {i}: 2F {twoF[i]:.3f} vs {ref2f:.3f}, max scaled gradient error "
+              f"{np.max(np.abs(gs - rs)) / max(np.max(np.abs(rs)), 1.0):.2e}", flush=True)
+        assert np.all(np.abs(gs - rs) <= 1e-3 * max(np.max(np.abs(rs)), 1.0)), (i, gs, rs)

@@ -40,10 +40,15 @@ def _inj(w, f_off_bins=3000.5, fdot=-3e-10, alpha=1.2, delta=0.3, h0=2.0):
                      fdot=fdot, alpha=alpha, delta=delta)
 
 
-@pytest.mark.parametrize("kernel,taps", [(synth.KERNEL_LANCZOS, 8), (synth.KERNEL_DIRICHLET, 16)])
-def test_resample_parity(gpu_lib, kernel, taps):
+@pytest.mark.parametrize("kernel,taps,n,dt", [(synth.KERNEL_LANCZOS, 8, 21600, 4.0),
+                                               (synth.KERNEL_DIRICHLET, 16, 21600, 4.0),
+                                               (synth.KERNEL_DIRICHLET, 16, 172800, 0.5),
+                                               (synth.KERNEL_DIRICHLET, 24, 172800, 0.5)])
+def test_resample_parity(gpu_lib, kernel, taps, n, dt):
+    """Short series, and series long enough (n > 10500 (W/2 + 1)) for the
+    Dirichlet weights to reduce to sin(pi x) / (pi x) in FP32."""
     import torch
-    w = _small(kernel, taps)
+    w = _small(kernel, taps, n=n, dt=dt)
     xs, gaps = make_inputs(w, seed=1, injections=[_inj(w)])
     sky = np.array([[1.2, 0.3], [4.1, -0.8], [0.3, 1.4]])
     plan = gpu_lib.Plan(w)
@@ -58,7 +63,7 @@ def test_resample_parity(gpu_lib, kernel, taps):
         assert np.max(np.abs(o["b"] - ref["b"])) < 1e-6
         rms = np.sqrt(np.mean(np.abs(ref["z"]) ** 2))
         zerr = np.max(np.abs(o["z"] - ref["z"])) / rms
-        print(f"resample kernel {kernel} W={taps} sky {s}: max|dz|/rms = {zerr:.2e}", flush=True)
+        print(f"resample kernel {kernel} W={taps} n={n} sky {s}: max|dz|/rms = {zerr:.2e}", flush=True)
         assert zerr < 3e-6
         bits = np.unpackbits(o["mask"].view(np.uint8), bitorder="little")[: w.segment.n]
         assert np.array_equal(bits.astype(bool), ref["mask"] > 0)
