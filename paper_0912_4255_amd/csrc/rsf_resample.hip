@@ -158,8 +158,10 @@ __global__ __launch_bounds__(kThreads) void rsf_resample_k(ResampleArgs A) {
         if (valid) {
             if (ok && flat) {
                 const int base = j - hw + 1 - w0;
-                if (frac == 0.f) {
-                    zt = win[wave][base + hw - 1];  // x = 0 at the centre tap, sin(pi x) = 0 elsewhere
+                if (frac == 0.f || frac == 1.f) {
+                    // x = 0 at one tap (the centre, or the next one when the
+                    // fraction rounded up to 1 in FP32), sin(pi x) = 0 at the others
+                    zt = win[wave][base + hw - 1 + (frac == 1.f ? 1 : 0)];
                 } else {
                     // sum of (-1)^m z / x, then the common factor sin(pi frac) / pi
                     float ax = 0.f, ay = 0.f;

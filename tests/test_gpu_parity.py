@@ -215,3 +215,26 @@ def test_c1_noise_free_peak(gpu_lib):
     rss = _oracle_rs(w, xs, gaps, inj.alpha, inj.delta)
     ref = of.fstat_bins(rss, w.detectors, inj.fdot, plan.n_fft, [43200])[0]
     assert abs(got[43200 - plan.s_lo] - ref) <= 1e-4 * max(ref, 4.0)
+
+
+def test_resample_fraction_rounding_to_one(gpu_lib):
+    """A Roemer delay of at most 1e-9 s (an ephemeris with R_E / c = 1e-9 s
+    and no orbit) puts most resampled times a hair below a detector sample:
+    the fraction u - floor(u) then rounds to 1.0 in FP32, and the
+    interpolation must return the next sample (no NaN), as the oracle does.
+    Long series, so the sinc form of the Dirichlet weights is the one used."""
+    import torch
+    w = _small(synth.KERNEL_DIRICHLET, 24, n=172800, dt=0.5, gaps=False)
+    w = dataclasses.replace(w, eph=synth.Ephemeris(au_c=0.0, re_c=1e-9))
+    xs, gaps = make_inputs(w, seed=3)
+    sky = np.array([[1.2, 0.3], [4.1, -0.8]])
+    plan = gpu_lib.Plan(w)
+    tx, tg = to_gpu(xs, gaps)
+    print("\ncase: resampled fractions rounding to 1 in FP32", flush=True)
+    out = plan.resample(tx, tg, torch.from_numpy(sky).cuda())[0]
+    for s_, (al, de) in enumerate(sky):
+        ref = _oracle_rs(w, xs, gaps, al, de)[0]
+        z = out["z"][s_].cpu().numpy()
+        assert not np.isnan(z).any()
+        rms = np.sqrt(np.mean(np.abs(ref["z"]) ** 2))
+        assert np.max(np.abs(z - ref["z"])) / rms < 3e-6
