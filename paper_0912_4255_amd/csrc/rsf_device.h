@@ -315,11 +315,11 @@ struct Interleaved {
     __device__ __forceinline__ int col(int b) const { return b; }
     __device__ __forceinline__ int operator()(int row, int b) const { return row * B + b; }
 };
-struct Grouped4 {
+struct Grouped8 {
     int gs;
-    __device__ __forceinline__ static constexpr int rowstride() { return 4; }
-    __device__ __forceinline__ int col(int b) const { return (b >> 2) * gs + (b & 3); }
-    __device__ __forceinline__ int operator()(int row, int b) const { return row * 4 + col(b); }
+    __device__ __forceinline__ static constexpr int rowstride() { return 8; }
+    __device__ __forceinline__ int col(int b) const { return (b >> 3) * gs + (b & 7); }
+    __device__ __forceinline__ int operator()(int row, int b) const { return row * 8 + col(b); }
 };
 
 // One butterfly of a Stockham stage: x[j + r L/R] of column b, r < R ...

@@ -9,9 +9,9 @@
 //   y^a = sum_X w_X a z~ exp(-i Phi_s),  y^b likewise  (eq. eq4pt1, FP64 phase)
 // from the resampled series (stored transposed, so the row is contiguous),
 // transforms the row in LDS (both spectra in one float4 per element), applies
-// W_N^{n_b k_a} and spills in groups of 4 consecutive k_a (64-B rows).
-// Pass B: persistent workgroups over blocks of 8 consecutive k_a (two
-// adjacent spill groups, one contiguous run).  Each block is transformed
+// W_N^{n_b k_a} and spills in groups of 8 consecutive k_a (128-B rows).
+// Pass B: persistent workgroups over blocks of 8 consecutive k_a (one spill
+// group, one contiguous run).  Each block is transformed
 // over n_b, one column per wave in registers when LB = 64 E (E = 4, 8, 12),
 // otherwise as 8 columns through LDS Stockham stages, and every bin reduced
 // to 2F = cA |f_a|^2 + cB |f_b|^2 + cC Re(f_a f_b^*), written in ascending
@@ -292,9 +292,9 @@ __global__ __launch_bounds__(kNT) void rsf_fft_pass_a_k(PassAArgs A) {
 }
 
 // Second pass, persistent.  Workgroup g handles the spill blocks g, g +
-// grid, ... (block = template * n_groups + group of 8 columns k_a): the two
-// 4-column groups of a block come into one LDS buffer by DMA loads (global
-// -> LDS, no registers), kept as two contiguous [LB][4] groups; the block is
+// grid, ... (block = template * n_groups + group of 8 columns k_a): the
+// block's 8-column spill group comes into one LDS buffer by DMA loads (global
+// -> LDS, no registers), kept as one contiguous [LB][8] group; the block is
 // transformed over n_b as 8 columns.  In the last stage every thread reads
 // its inputs, the workgroup synchronises, the DMA of the next block is
 // issued into the same buffer, and the last butterflies, the 2F reduction
@@ -306,7 +306,7 @@ template <bool NT>
 __device__ __forceinline__ void passb_dma(const PassBArgs& B, int unit, float4* dst) {
     const int t = unit / B.n_groups;
     const int c = unit - t * B.n_groups;
-    const int blk = B.LB * kPassBCols;  // both groups of the block, contiguous in the spill
+    const int blk = B.LB * kPassBCols;  // the block's spill group, one contiguous run
     const float4* base = B.spill + (int64_t)t * B.spill_tmpl_stride + (int64_t)c * blk;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int e0 = wave * 64; e0 < blk; e0 += kNTB) {
@@ -369,7 +369,7 @@ __global__ __launch_bounds__(kNTB) void rsf_fft_pass_b_k(PassBArgs B) {
     for (int i = tid; i < 32 + n_hi; i += kNTB) twl[i] = (i < 32) ? B.tw_lo[i] : B.tw_hi[i - 32];
     for (int i = tid; i < 4 * B.n_sky_l; i += kNTB) cfl[i] = B.coef[i];
     const TwLds tw{twl, twl + 32};
-    const Grouped4 lay{B.LB * kGroupCols};
+    const Grouped8 lay{B.LB * kGroupCols};
     const int n_units = B.n_tmpl * B.n_groups;
     const int r_last = B.st.n_stages ? B.st.radix[B.st.n_stages - 1] : 1;
 
@@ -421,28 +421,32 @@ __global__ __launch_bounds__(kNTB) void rsf_fft_pass_b_k(PassBArgs B) {
 // ---------------------------------------------------------------------------
 constexpr int kWaveColsThreads = 64 * kPassBCols;
 
-// DMA of block `unit` (two spill groups of 4 columns x LB rows, one
-// contiguous run) into dst: chunk i of 64 float4 (16 rows x 4 columns of one
-// group) goes to dst + 64 i with row r, column c at slot 16 c + r.
+// DMA of block `unit` (one spill group of 8 columns x LB rows, one
+// contiguous run) into dst: chunk i of 64 float4 (8 rows x 8 columns) goes to
+// dst + 64 i with row r, column c at slot 8 (c ^ (i & 1)) + r: column-major,
+// and odd chunks with their column pairs swapped, so that the two 8-lane
+// halves of a 16-lane LDS cycle of a column read fall in different banks.
 template <bool NT>
 __device__ __forceinline__ void wave_dma(const PassBArgs& B, int unit, float4* dst, int wave, int lane) {
     const int t = unit / B.n_groups;
     const int g = unit - t * B.n_groups;
     const float4* base = B.spill + (int64_t)t * B.spill_tmpl_stride + (int64_t)g * B.LB * kPassBCols;
     const int n_chunks = B.LB * kPassBCols / 64;
-    const int src = 4 * (lane & 15) + (lane >> 4);  // lane 16 c + r takes float4 4 r + c of the chunk
-    for (int i = wave; i < n_chunks; i += kPassBCols)
+    for (int i = wave; i < n_chunks; i += kPassBCols) {
+        // lane 8 c' + r takes row r, column c' ^ (i & 1) of the chunk (float4 8 r + c)
+        const int src = 8 * (lane & 7) + ((lane >> 3) ^ (i & 1));
         __builtin_amdgcn_global_load_lds((const void*)(base + 64 * i + src),
                                          (__attribute__((address_space(3))) void*)(dst + 64 * i), 16, 0, NT ? 2 : 0);
+    }
 }
 
-// Column b of the block in LDS, rows l + 64 m of lane l.
+// Column b of the block in LDS, rows l + 64 m of lane l (row l + 64 m is in
+// chunk (l >> 3) + 8 m, whose parity is that of l >> 3).
 template <int E>
 __device__ __forceinline__ void wave_col_read(const float4* blk, int b, int lane, cp (&v)[E]) {
-    constexpr int LB = 64 * E;
-    const float4* col = blk + (b >> 2) * (LB / 16) * 64 + 64 * (lane >> 4) + 16 * (b & 3) + (lane & 15);
+    const float4* col = blk + 64 * (lane >> 3) + 8 * (b ^ ((lane >> 3) & 1)) + (lane & 7);
 #pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = col[256 * m];
+    for (int m = 0; m < E; ++m) v[m] = col[512 * m];
 }
 
 // Exchange among the lanes {src0 + i s : i < 4} as a 4 x 4 transpose of

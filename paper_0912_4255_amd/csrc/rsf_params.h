@@ -14,7 +14,7 @@ namespace rsf {
 constexpr int kMaxStages = 12;
 constexpr int kMaxTaps = 32;
 constexpr int kMaxDet = 4;
-constexpr int kPassBCols = 8;       // columns of a second-pass block (two 4-column spill groups)
+constexpr int kPassBCols = 8;       // columns of a second-pass block (one 8-column spill group)
 constexpr int kTwSplitBits = 12;    // inter-pass twiddle W_N^m = hi[m >> 12] * lo[m & 4095]
 constexpr int kFftThreads = 512;    // threads of a first-pass workgroup
 constexpr int kPassBThreads = 768;  // threads of a second-pass workgroup (3 waves per SIMD)
@@ -136,7 +136,7 @@ struct PassAArgs {
     const float2* tws_hi;
     const float2* tw_lo;      // inter-pass twiddle W_N^m = tw_hi[m >> 12] * tw_lo[m & 4095]
     const float2* tw_hi;
-    float4* spill;            // [n_sky_l * nf_l][2 * ceil(LA/8)][LB][4]: 4-column groups
+    float4* spill;            // [n_sky_l * nf_l][ceil(LA/8)][LB][8]: 8-column groups
     int64_t spill_tmpl_stride;
     int nt_spill;             // spill larger than the last-level cache: non-temporal stores
 };

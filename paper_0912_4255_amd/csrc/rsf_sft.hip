@@ -316,7 +316,7 @@ __device__ __forceinline__ int sft_len_of(const SftLenDev* lens, int n_lens, int
 
 // Spill writer of the rows pass, as the first F-statistic pass's: output
 // k_a = j + r LA/R_last of row n_b, times W_n^{n_b k_a}, goes to the spill in
-// 4-column groups; the twiddle of butterfly j = j0 + q s is
+// 8-column groups; the twiddle of butterfly j = j0 + q s is
 // W^{n_b j0} (W^{n_b s})^q and steps by W^{n_b LA/R_last} along r.  A row past
 // the transform (ok false, in a workgroup's last group of rows) writes nothing.
 struct SftSpillSink {
@@ -331,7 +331,7 @@ struct SftSpillSink {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const uint32_t k = (uint32_t)(j + r * LR);
-            const uint32_t off = (((k >> 2) * (uint32_t)LB + (uint32_t)n_b) * kGroupCols + (k & 3u)) * 16u;
+            const uint32_t off = (((k >> 3) * (uint32_t)LB + (uint32_t)n_b) * kGroupCols + (k & 7u)) * 16u;
             *reinterpret_cast<float4*>(out + off) = cp_rot(v[r], w);
             if (r + 1 < R) w = c_mul(w, w_lr);
         }
@@ -410,7 +410,7 @@ struct SeriesSink {
 };
 
 // Columns pass: workgroup w transforms the CB columns g CB .. g CB + CB - 1 of
-// its chunk (CB / 4 consecutive 4-column spill groups, one contiguous run)
+// its chunk (CB / 8 consecutive 8-column spill groups, one contiguous run)
 // over n_b and writes the series.  Columns at or past LA (padding of the last
 // group) are transformed but not written.
 template <int CB>
@@ -435,7 +435,7 @@ __global__ __launch_bounds__(kNTB) void rsf_sft_cols_k(SftColsArgs B) {
     __syncthreads();
     const int r_last = st.n_stages ? st.radix[st.n_stages - 1] : 1;
     SeriesSink sink{B.x, ch.j0, ch.n_keep, B.n_out, LA, LB / r_last, c * CB, B.n_edge, ch.corr};
-    lds_fft_into<kNTB, kPassBEPT, CB, false>(lds, st, tw, Grouped4{LB * kGroupCols}, sink, NoMid{});
+    lds_fft_into<kNTB, kPassBEPT, CB, false>(lds, st, tw, Grouped8{LB * kGroupCols}, sink, NoMid{});
 }
 
 hipError_t launch_sft_norm(const SftNormArgs& a, int n_sft, hipStream_t s) {

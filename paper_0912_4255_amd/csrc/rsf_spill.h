@@ -6,10 +6,12 @@
 
 namespace rsf {
 
-// Spill layout: 4-column groups, float4 [template][k_a / 4][n_b][k_a % 4]:
-// the two groups of a second-pass block are adjacent, so the block is one
-// contiguous run and every cache line is fetched once.
-constexpr int kGroupCols = kPassBCols / 2;
+// Spill layout: 8-column groups, float4 [template][k_a / 8][n_b][k_a % 8]:
+// a group is one second-pass block, one contiguous run, and the eight
+// consecutive k_a of a first-pass row fill one whole 128-byte line, which
+// that row's workgroup writes alone.
+constexpr int kGroupCols = kPassBCols;
+static_assert(kGroupCols == 8, "the offsets below assume 8-column groups");
 
 typedef float spill_v4 __attribute__((ext_vector_type(4)));
 
@@ -38,7 +40,7 @@ struct SpillSink {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const uint32_t k = (uint32_t)(jv + r * LR);
-            const uint32_t off = (((k >> 2) * (uint32_t)LB + (uint32_t)n_b) * kGroupCols + (k & 3u)) * 16u;
+            const uint32_t off = (((k >> 3) * (uint32_t)LB + (uint32_t)n_b) * kGroupCols + (k & 7u)) * 16u;
             const cp u = cp_rot(v[r], w);
             if constexpr (NT)
                 __builtin_nontemporal_store(spill_v4{u.x, u.y, u.z, u.w}, reinterpret_cast<spill_v4*>(out + off));
