@@ -136,7 +136,9 @@ bool radix_plan(int len, int B, int NT, int EPT, FftStages* st) {
 // Factorisation n_fft = LA * LB for the two FFT passes on a device with
 // lds_max bytes of LDS per workgroup: fewest total stages, LA a multiple of
 // 8, then the most balanced LDS footprints.  fft_l1 > 0 forces LA.
-bool choose_factors(int64_t n_fft, int lds_max, int fft_l1, int* out_la, int* out_lb) {
+// wave: prefer a second pass of one column per wave (the F-statistic's; the
+// SFT front end's columns pass is the LDS-stage kind for every length).
+bool choose_factors(int64_t n_fft, int lds_max, int fft_l1, int* out_la, int* out_lb, bool wave = true) {
     const int max_elems = fft_pass_max_elems();
     const int64_t la_max = std::min<int64_t>(max_elems, lds_max / (int)sizeof(float4));
     const int64_t lb_max = std::min<int64_t>(max_elems / kPassBCols, lds_max / (kPassBCols * (int)sizeof(float4)));
@@ -156,8 +158,8 @@ bool choose_factors(int64_t n_fft, int lds_max, int fft_l1, int* out_la, int* ou
         // a second pass of one column per wave (LB = 256, 512, 768) first,
         // the longest such; then the fewest stages, L1 a multiple of 8 and
         // the most balanced LDS footprints
-        const bool wave = fft_pass_b_wave_e((int)lb) != 0;
-        const double score = (wave ? -1e12 - 1e9 * (double)lb : 0.0) + (sa.n_stages + sb.n_stages) * 1e9 +
+        const bool wave_lb = wave && fft_pass_b_wave_e((int)lb) != 0;
+        const double score = (wave_lb ? -1e12 - 1e9 * (double)lb : 0.0) + (sa.n_stages + sb.n_stages) * 1e9 +
                              ((la % 8) ? 1e8 : 0.0) + std::max(lds_a, lds_b);
         if (score < best_score) {
             best_score = score;
@@ -1525,7 +1527,7 @@ int rsf_sft_plan_create(rsf_sft_plan** out, const rsf_sft_desc* d, const double*
         if (xi < 0) {
             SftXform x{};
             x.n = n;
-            if (!choose_factors(n, lds_cap, 0, &x.L1, &x.L2)) {
+            if (!choose_factors(n, lds_cap, 0, &x.L1, &x.L2, false)) {
                 sft_free(p);
                 return fail(RSF_EUNSUPPORTED, "chunk transform of %lld points has no factorisation", (long long)n);
             }
