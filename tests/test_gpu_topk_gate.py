@@ -8,7 +8,9 @@ full 2F map computed by the same plan:
 * a series of zeros makes every 2F exactly 0: every value ties, every block
   takes its slow path and the result is the k lowest keys;
 * an all-gap segment has NaN everywhere: no entry;
-* graph replays reproduce the eager result."""
+* graph replays reproduce the eager result;
+* at the T = 10 d shape (two launches of the benchmark's configuration) the
+  in-pass top-10 equals the selection over the full map."""
 import numpy as np
 import pytest
 
@@ -114,4 +116,35 @@ def test_graph_replays_in_pass_topk(gpu_lib):
         plan.fstat(tx, tg, sky, fd)  # eager work between replays
         torch.cuda.synchronize()
     g.close()
+    plan.close()
+
+
+def test_topk_at_the_ten_day_shape(gpu_lib):
+    """The T = 10 d search (N = 3,456,000, N_fft = 6,912,000, one column per
+    wave in the second pass), one sky and 96 spindowns in launches of 64
+    templates: the in-pass top-10 equals the selection over the full map."""
+    import torch
+    from paper_0912_4255_amd import autotune
+    w = synth.workload_c2()
+    xs, gaps = make_inputs(w, seed=5)
+    plan, _ = autotune.tuned_plan(w)
+    assert plan.fft_l2 in (256, 512, 768)
+    print(f"\ncase: top-10 at N = {w.segment.n}, plan {plan.fft_l1} x {plan.fft_l2}", flush=True)
+    tx, tg = to_gpu(xs, gaps)
+    sky = torch.from_numpy(np.ascontiguousarray(w.skies[:1])).cuda()
+    fd = torch.from_numpy(synth.fdot_grid(96)).cuda()
+    k = 10
+    vals, ids = plan.topk(tx, tg, sky, fd, k=k)
+    vals, ids = vals.cpu().numpy(), ids.cpu().numpy()
+    maps = plan.fstat(tx, tg, sky, fd)
+    flat = maps.reshape(-1)
+    kth = torch.topk(flat, k).values[-1]          # the k-th largest value
+    cand = torch.nonzero(flat >= kth).flatten().cpu().numpy()
+    v = flat[torch.from_numpy(cand).cuda()].cpu().numpy()
+    order = np.lexsort((cand, -v.astype(np.float64)))[:k]
+    sel = cand[order]
+    n_out = plan.n_out
+    exp_ids = np.stack([sel // (n_out * 96), (sel // n_out) % 96, sel % n_out], axis=1)
+    assert np.array_equal(ids, exp_ids), (ids, exp_ids)
+    assert np.array_equal(vals, v[order])
     plan.close()
