@@ -22,7 +22,12 @@ from the paper's formulas and not from the oracle's code:
   x_(k-m) with the Lanczos derivative at integers w'(m) = (-1)^m / m
   sinc(2m/W); the spindown phase 2 pi fdot (T^2/2 + d T) is stationary at
   d = 0; the beam patterns move by their time derivative (sidereal rotation
-  of the site frame) times S_k.
+  of the site frame) times S_k.  At a_p = 0 the derivatives in P_b and
+  t_asc vanish exactly.
+
+* The same orbit at a small a_p = e: the delay e S_k moves with P_b and
+  t_asc through dS_k/dP_b and dS_k/dt_asc, so those derivatives are e times
+  the zero-orbit derivative along these directions, up to O(e^2).
 
 A swapped (alpha, delta), a dropped chain term or a wrong sign in any of
 these fails the comparison.
@@ -150,17 +155,14 @@ def _lanczos_slope_at_integers(W):
     return m, out
 
 
-def test_orbit_amplitude_derivative_matches_closed_form_at_zero_orbit():
-    x, inj = _data(21)
-    p_b, t_asc = 40000.0, 9.0e3
-    prob = og.PointProblem([x], [NOGAP], SEG, [DET_H], EPH0, KERNEL_LANCZOS, W, binary=True)
-    theta = np.array([inj.f0 + 0.2 * DF, inj.fdot, inj.alpha, inj.delta, 0.0, p_b, t_asc])
-    g = og.gradient(prob, theta)
-
+def _delay_derivative(x, theta, v):
+    """2F at zero orbit and its derivative when the total delay of sample k
+    moves by -v_k (the emission-grid target T^k by +v_k), per the chain
+    terms listed above; also the derivative with the heterodyne term left
+    out."""
     n = SEG.n
     k = np.arange(n)
     tau = SEG.t_start + k * SEG.dt
-    S = np.sin(2.0 * np.pi * (tau - t_asc) / p_b)
     a, b, _, _, a_t, b_t = _beams(tau, theta[2], theta[3], DET_H, EPH0)
     xc = np.asarray(x, np.complex128)
     # interpolation slope: sum_m w'(m) x_(k-m), taps outside the segment zero
@@ -172,20 +174,66 @@ def test_orbit_amplitude_derivative_matches_closed_form_at_zero_orbit():
         j = k - m
         ok = (j >= 0) & (j < n)
         slope[ok] += wm * xc[j[ok]]
-    dz = S / SEG.dt * slope + 2j * np.pi * SEG.f_het * S * xc
     ph = _phase_kernel(theta[0], theta[1])
     fa, fb = np.sum(a * xc * ph), np.sum(b * xc * ph)
-    da, db = a_t * S, b_t * S
-    dfa = np.sum((da * xc + a * dz) * ph)
-    dfb = np.sum((db * xc + b * dz) * ph)
+    da, db = a_t * v, b_t * v
     A, B, C = np.sum(a * a), np.sum(b * b), np.sum(a * b)
-    F, dF = _twoF_and_grad(fa, fb, A, B, C, dfa, dfb, 2 * np.sum(a * da), 2 * np.sum(b * db),
-                           np.sum(da * b + a * db))
+    out = []
+    for het in (1.0, 0.0):
+        dz = v / SEG.dt * slope + het * 2j * np.pi * SEG.f_het * v * xc
+        dfa = np.sum((da * xc + a * dz) * ph)
+        dfb = np.sum((db * xc + b * dz) * ph)
+        out.append(_twoF_and_grad(fa, fb, A, B, C, dfa, dfb, 2 * np.sum(a * da), 2 * np.sum(b * db),
+                                  np.sum(da * b + a * db)))
+    (F, dF), (_, dF0) = out
+    return F, dF, dF0
+
+
+P_B, T_ASC = 40000.0, 9.0e3
+
+
+def _orbit_phase():
+    tau = SEG.t_start + np.arange(SEG.n) * SEG.dt
+    return tau, 2.0 * np.pi * (tau - T_ASC) / P_B
+
+
+def test_orbit_amplitude_derivative_matches_closed_form_at_zero_orbit():
+    x, inj = _data(21)
+    prob = og.PointProblem([x], [NOGAP], SEG, [DET_H], EPH0, KERNEL_LANCZOS, W, binary=True)
+    theta = np.array([inj.f0 + 0.2 * DF, inj.fdot, inj.alpha, inj.delta, 0.0, P_B, T_ASC])
+    g = og.gradient(prob, theta)
+    _, psi = _orbit_phase()
+    F, dF, dF0 = _delay_derivative(x, theta, np.sin(psi))
     assert abs(prob.twoF(theta) - F) < 1e-9 * F
     assert abs(g[4] - dF) <= 1e-6 * abs(dF) + 1e-8 * F, (g[4], dF)
     # the heterodyne term dominates: dropping it changes the derivative grossly
-    dfa0 = np.sum((da * xc + a * (S / SEG.dt * slope)) * ph)
-    dfb0 = np.sum((db * xc + b * (S / SEG.dt * slope)) * ph)
-    _, dF0 = _twoF_and_grad(fa, fb, A, B, C, dfa0, dfb0, 2 * np.sum(a * da), 2 * np.sum(b * db),
-                            np.sum(da * b + a * db))
     assert abs(dF0 - dF) > 1e-2 * abs(dF)
+    # with a_p = 0 the delay a_p S does not depend on P_b or t_asc at all
+    assert g[5] == 0.0 and g[6] == 0.0
+
+
+@pytest.mark.parametrize("seed", [22, 24])
+def test_orbit_period_and_epoch_derivatives_at_small_amplitude(seed):
+    """At a_p = e the delay is e S_k, so d2F/dP_b and d2F/dt_asc are e times
+    the zero-orbit derivative along dS/dP_b = -cos(psi) 2 pi (tau - t_asc) /
+    P_b^2 and dS/dt_asc = -cos(psi) 2 pi / P_b, plus O(e^2).  Richardson in e,
+    2 g(e)/e - g(2e)/(2e), removes the e^2 term; steps of 1 s in P_b and
+    t_asc keep the difference quotients above the FP64 rounding of t ~ 3e5 s
+    (the default steps are sized for a_p near a light-second)."""
+    x, inj = _data(seed)
+    prob = og.PointProblem([x], [NOGAP], SEG, [DET_H], EPH0, KERNEL_LANCZOS, W, binary=True)
+    steps = og.default_steps(SEG, 1, binary=True)
+    steps[5] = steps[6] = 1.0
+    e = 1e-5
+    gs = []
+    for ap in (e, 2 * e):
+        theta = np.array([inj.f0 + 0.2 * DF, inj.fdot, inj.alpha, inj.delta, ap, P_B, T_ASC])
+        gs.append(og.gradient(prob, theta, steps) / ap)
+    lin = 2.0 * gs[0] - gs[1]
+    tau, psi = _orbit_phase()
+    _, dP, _ = _delay_derivative(x, theta, -np.cos(psi) * 2.0 * np.pi * (tau - T_ASC) / P_B ** 2)
+    _, dT, _ = _delay_derivative(x, theta, -np.cos(psi) * 2.0 * np.pi / P_B)
+    assert abs(lin[5] - dP) <= 2e-3 * abs(dP), (lin[5], dP)
+    assert abs(lin[6] - dT) <= 2e-3 * abs(dT), (lin[6], dT)
+    # P_b and t_asc derivatives differ, so a swap of the two would fail
+    assert abs(dP - dT) > 0.5 * max(abs(dP), abs(dT))
