@@ -67,10 +67,10 @@ def _divisors(n, lo, hi):
 
 def candidate_l1(plan, limit=8):
     """First-pass lengths that the planner accepts: those that leave a
-    one-column-per-wave second pass (L2 = 768, 512, 256) first, then the
-    others nearest the automatic choice."""
+    one-column-per-wave second pass (L2 = 768, 512, 256, then 1024, the
+    top-k's) first, then the others nearest the automatic choice."""
     n_fft = plan.n_fft
-    wave = [n_fft // lb for lb in (768, 512, 256) if n_fft % lb == 0 and n_fft // lb <= 10240]
+    wave = [n_fft // lb for lb in (768, 512, 256, 1024) if n_fft % lb == 0 and n_fft // lb <= 10240]
     cands = _divisors(n_fft, max(8, plan.fft_l1 // 4), min(10240, plan.fft_l1 * 4))
     cands.sort(key=lambda d: abs(np.log(d / plan.fft_l1)))
     cands = wave + [d for d in cands if d not in wave]
@@ -255,6 +255,7 @@ def main(argv=None):
     ap.add_argument("--templates", default="16,32,64")
     ap.add_argument("--n-fdot", type=int, default=64)
     ap.add_argument("--segments", type=int, default=0)
+    ap.add_argument("--segment-ids", default="", help="comma-separated segment indices to tune instead")
     ap.add_argument("--no-standard", action="store_true")
     ap.add_argument("--keep-taps", action="store_true", help="segments keep the taps of the existing table")
     a = ap.parse_args(argv)
@@ -271,9 +272,10 @@ def main(argv=None):
             db[key] = best
             print(name, key, best, flush=True)
             torch.cuda.empty_cache()
-    if a.segments:
+    ids = [int(v) for v in a.segment_ids.split(",") if v] or list(range(a.segments))
+    if ids:
         table = db.setdefault(SEGMENTS_KEY, {})
-        for i in range(a.segments):
+        for i in ids:
             w = synth.workload_c3_segment(i, n_sky=8)
             old = table.get(str(w.segment.n))
             best = tune_segment(w, taps=old["taps"] if (a.keep_taps and old) else None)

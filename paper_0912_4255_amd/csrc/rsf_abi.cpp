@@ -133,6 +133,17 @@ bool radix_plan(int len, int B, int NT, int EPT, FftStages* st) {
     return true;
 }
 
+// Stage capacity (complex pairs per thread) of a first-pass row of length
+// la: kFftEPTWide when its LDS leaves room for one workgroup per CU only
+// and the wider stages need fewer of them, else kFftEPT.
+int pass_a_ept(int la) {
+    if (fft_pass_a_lds(la) <= kLdsPerGroupMax / 2) return kFftEPT;
+    FftStages narrow, wide;
+    if (!radix_plan(la, 1, kFftThreads, kFftEPTWide, &wide)) return kFftEPT;
+    if (!radix_plan(la, 1, kFftThreads, kFftEPT, &narrow)) return kFftEPTWide;
+    return wide.n_stages < narrow.n_stages ? kFftEPTWide : kFftEPT;
+}
+
 // Factorisation n_fft = LA * LB for the two FFT passes on a device with
 // lds_max bytes of LDS per workgroup: fewest total stages, LA a multiple of
 // 8, then the most balanced LDS footprints.  fft_l1 > 0 forces LA.
@@ -150,17 +161,19 @@ bool choose_factors(int64_t n_fft, int lds_max, int fft_l1, int* out_la, int* ou
         if (la > la_max || fft_pass_a_lds((int)la) > (size_t)lds_max) continue;
         if (fft_l1 > 0 && la != fft_l1) continue;
         FftStages sa, sb;
-        if (!radix_plan((int)la, 1, kFftThreads, kFftEPT, &sa) ||
+        if (!radix_plan((int)la, 1, kFftThreads, pass_a_ept((int)la), &sa) ||
             !radix_plan((int)lb, kPassBCols, kPassBThreads, kPassBEPT, &sb) ||
-            fft_pass_b_lds((int)lb, 64) > (size_t)lds_max)
+            fft_pass_b_lds((int)lb, 64, false) > (size_t)lds_max)
             continue;
         const double lds_a = (double)la * 16, lds_b = (double)lb * 128;
-        // a second pass of one column per wave (LB = 256, 512, 768) first,
-        // the longest such; then the fewest stages, L1 a multiple of 8 and
-        // the most balanced LDS footprints
-        const bool wave_lb = wave && fft_pass_b_wave_e((int)lb) != 0;
-        const double score = (wave_lb ? -1e12 - 1e9 * (double)lb : 0.0) + (sa.n_stages + sb.n_stages) * 1e9 +
-                             ((la % 8) ? 1e8 : 0.0) + std::max(lds_a, lds_b);
+        // a second pass of one column per wave first: LB = 256, 512, 768
+        // (the longest such), then LB = 1024 (one column per wave for the
+        // top-k only); then the fewest stages, L1 a multiple of 8 and the
+        // most balanced LDS footprints
+        const int we = wave && fft_pass_b_lds((int)lb, 64, true) <= (size_t)lds_max ? fft_pass_b_wave_e((int)lb, true) : 0;
+        const double wave_bonus = we == 0 ? 0.0 : we == 16 ? -5e11 : -1e12 - 1e9 * (double)lb;
+        const double score = wave_bonus + (sa.n_stages + sb.n_stages) * 1e9 + ((la % 8) ? 1e8 : 0.0) +
+                             std::max(lds_a, lds_b);
         if (score < best_score) {
             best_score = score;
             best_la = (int)la;
@@ -284,7 +297,9 @@ hipError_t topk_merge_levels(const rsf_plan* p, hipStream_t s, const TopkItem* c
 
 // The second pass selects the top-k itself (no 2F map) when it runs one
 // column per wave.
-bool fused_topk(const rsf_plan* p) { return fft_pass_b_wave_e(p->LB) != 0; }
+bool fused_topk(const rsf_plan* p) {
+    return fft_pass_b_wave_e(p->LB, true) != 0 && fft_pass_b_lds(p->LB, 64, true) <= kLdsPerGroupMax;
+}
 
 // map: room for a launch's 2F map (the semi-coherent sum, or a top-k whose
 // second pass cannot select in place); topk: the candidate gate, buffer and
@@ -511,7 +526,7 @@ int rsf_plan_create(rsf_plan** out, const rsf_plan_desc* d) {
     }
     p->LA = best_la;
     p->LB = best_lb;
-    radix_plan(p->LA, 1, kFftThreads, kFftEPT, &p->stA);
+    radix_plan(p->LA, 1, kFftThreads, pass_a_ept(p->LA), &p->stA);
     radix_plan(p->LB, kPassBCols, kPassBThreads, kPassBEPT, &p->stB);
     p->P = (p->n + p->LB - 1) / p->LB;
     p->n_groups = (p->LA + kPassBCols - 1) / kPassBCols;
@@ -519,7 +534,8 @@ int rsf_plan_create(rsf_plan** out, const rsf_plan_desc* d) {
         delete p;
         return fail(RSF_EUNSUPPORTED, "internal: rows exceed first-pass length");
     }
-    const size_t lds_need = std::max<size_t>(fft_pass_a_lds(p->LA), fft_pass_b_lds(p->LB, 64));
+    const size_t lds_need = std::max({fft_pass_a_lds(p->LA), fft_pass_b_lds(p->LB, 64, false),
+                                      fused_topk(p) ? fft_pass_b_lds(p->LB, 64, true) : (size_t)0});
     if (hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess ||
         p->n_cu <= 0)
         p->n_cu = 256;
@@ -859,6 +875,7 @@ int run_fstat(const rsf_plan* p, const rsf_segment* seg, const double* sky, int6
             A.n_sky_l = q.ns;
             A.fb = fb;
             A.st = p->stA;
+            A.ept = pass_a_ept(p->LA);
             A.tws_lo = p->twA;
             A.tws_hi = p->twA_hi;
             A.tw_lo = p->tw_lo;
@@ -891,7 +908,7 @@ int run_fstat(const rsf_plan* p, const rsf_segment* seg, const double* sky, int6
             B.f0 = q.f0;
             B.nf_l = q.nf;
             B.n_tmpl = q.ns * q.nf;
-            B.wave = fft_pass_b_wave_e(p->LB) != 0 ? 1 : 0;
+            B.wave = fft_pass_b_wave_e(p->LB, in_pass) != 0 ? 1 : 0;
             int64_t n_cand = 0, part_cap = 0;  // this launch's gate partitions x capacity, capacity
             if (in_pass) {
                 B.topk = 1;
@@ -1555,7 +1572,7 @@ int rsf_sft_plan_create(rsf_sft_plan** out, const rsf_sft_desc* d, const double*
             }
             xi = (int)p->xf.size() - 1;
             p->group.emplace_back();
-            p->lds_max = std::max({p->lds_max, fft_pass_a_lds(xr.L1), fft_pass_b_lds(xr.L2, 0)});
+            p->lds_max = std::max({p->lds_max, fft_pass_a_lds(xr.L1), fft_pass_b_lds(xr.L2, 0, false)});
         }
         c.xf = xi;
         p->group[(size_t)xi].push_back((int)p->chunks.size());

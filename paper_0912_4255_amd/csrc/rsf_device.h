@@ -464,12 +464,16 @@ struct NoMid {
     __device__ __forceinline__ void operator()() const {}
 };
 
-#define RSF_EVEN_RADIX_CASES(M) M(2) M(4) M(6) M(8) M(10) M(12) M(14) M(16)
+// Rows of the input a pruned first stage of radix R reads: x[j + r L/R] for
+// r < ceil(R/2) (the rest lie in the zero upper half).
+__host__ __device__ inline int pruned_first_reach(int L, int R) { return (L / R) * ((R + 1) / 2); }
 
 // Run all stages but the last of a planned transform in LDS, then the last
-// one through sink (see stockham_last).  first_half_zero: the upper half of
-// the input is zero and is neither written nor read (pruned first stage,
-// used when the first radix is even and there is more than one stage).
+// one through sink (see stockham_last).  first_half_zero: every input at or
+// above L/2 is zero; inputs at or above pruned_first_reach(L, radix[0]) are
+// neither written nor read (pruned first stage, when there is more than one
+// stage: input r of a radix-R butterfly, j + r L/R, lies at or above L/2
+// for 2 r >= R).
 template <int NT, int EPT, int B, bool SPLIT, typename TW, typename LAY, typename Sink, typename Mid>
 __device__ __forceinline__ void lds_fft_into(cp* __restrict__ s, const FftStages& st, const TW& tw, const LAY& lay,
                                              Sink& sink, const Mid& mid, bool first_half_zero = false) {
@@ -479,11 +483,11 @@ __device__ __forceinline__ void lds_fft_into(cp* __restrict__ s, const FftStages
     }
     int Ns = 1;
     int i0 = 0;
-    if (first_half_zero && st.n_stages > 1 && (st.radix[0] & 1) == 0) {
+    if (first_half_zero && st.n_stages > 1) {
         switch (st.radix[0]) {
 #define RSF_STAGE_HZ_CASE(RR) \
     case RR: stockham_stage<RR, NT, EPT, B, TW, LAY, true>(s, st.len, 1, tw, lay); break;
-            RSF_EVEN_RADIX_CASES(RSF_STAGE_HZ_CASE)
+            RSF_RADIX_CASES(RSF_STAGE_HZ_CASE)
 #undef RSF_STAGE_HZ_CASE
             default: break;
         }

@@ -186,6 +186,9 @@ __device__ __forceinline__ void row9000_fft(cp* __restrict__ s, const float2* __
     row_last<9000, 9>(s, tw, sink);
 }
 
+// The general stages planned for kFftEPTWide complex pairs per thread.
+constexpr int kPlanWide = 2;
+
 // The fixed plan a first-pass launch can take (0: the general stages).
 __host__ __device__ inline int fixed_row_plan(const FftStages& st, bool prune) {
     return (prune && st.len == 9000 && st.n_stages == 4 && st.radix[0] == 10 && st.radix[1] == 10 &&
@@ -195,9 +198,11 @@ __host__ __device__ inline int fixed_row_plan(const FftStages& st, bool prune) {
 }
 
 // NT: the launch's spill is larger than the last-level cache (non-temporal stores)
-// PLAN: a fixed row plan (kRow9000), or 0 for the planned stages of A.st.
+// PLAN: a fixed row plan (kRow9000), or the planned stages of A.st with
+// kFftEPT (0) or kFftEPTWide (kPlanWide) complex pairs per thread.
 template <int ORDER, bool NT, int PLAN>
 __global__ __launch_bounds__(kNT) void rsf_fft_pass_a_k(PassAArgs A) {
+    constexpr int EPT = PLAN == kPlanWide ? kFftEPTWide : kEPT;
     extern __shared__ float4 lds[];
     // stage twiddles in LDS after the row: no global load inside the stages,
     // so the spill stores of one spindown stay in flight during the next FFT
@@ -240,10 +245,11 @@ __global__ __launch_bounds__(kNT) void rsf_fft_pass_a_k(PassAArgs A) {
         const int64_t k = (int64_t)A.LB * (tid + q * kNT) + n_b;
         p0[q] = unpack_sample<ORDER>(m0[q], tm0[q], A.f16, (double)k * A.dt, (float)A.w[0]);
     }
-    // the upper half of the row is zero padding when P <= LA/2: it is
-    // neither written nor read (pruned first stage)
-    const bool prune = 2 * A.P <= A.LA && A.st.n_stages > 1 && (A.st.radix[0] & 1) == 0;
-    const int zlim = prune ? A.LA / 2 : A.LA;
+    // the upper half of the row is zero padding when P <= LA/2: the pruned
+    // first stage reads only the rows below pruned_first_reach (LA/2 for an
+    // even first radix), and only those are written
+    const bool prune = 2 * A.P <= A.LA && A.st.n_stages > 1;
+    const int zlim = prune ? pruned_first_reach(A.LA, A.st.radix[0]) : A.LA;
 
     // inter-pass twiddle W_N^{n_b k_a} for k_a = tid + q kNT: base W^{n_b tid}, step W^{n_b kNT}
     const int64_t mb = ((int64_t)n_b * tid) % A.n_fft;
@@ -286,7 +292,7 @@ __global__ __launch_bounds__(kNT) void rsf_fft_pass_a_k(PassAArgs A) {
         if constexpr (PLAN == kRow9000)
             row9000_fft(lds, tab, tws, sink);
         else
-            lds_fft_into<kNT, kEPT, 1, false>(lds, A.st, tws, Interleaved<1>{}, sink, NoMid{}, prune);
+            lds_fft_into<kNT, EPT, 1, false>(lds, A.st, tws, Interleaved<1>{}, sink, NoMid{}, prune);
         __syncthreads();
     }
 }
@@ -455,24 +461,52 @@ __device__ __forceinline__ void wave_col_read(const float4* blk, int b, int lane
 // the lane at position i as its register i Q + e.  One value group at a
 // time through the wave's region of 4 x 64 slots; slot (row c', lane l) at
 // c' * 64 + (l ^ X(c')), X = 4 c' (K = 2) or c' (K = 3), so that the 16
-// lanes an LDS cycle serves read 16 different bank groups.
-template <int E, int K>
+// lanes an LDS cycle serves read 16 different bank groups.  HALF: slots of
+// one complex value (float2, a 2 KB region), the two spectra in turn.
+template <int E, int K, bool HALF = false>
 __device__ __forceinline__ void wave_exchange(cp* __restrict__ x, int lane, int c, int src0, int s, cp (&v)[E]) {
     constexpr int Q = E / 4;
+    const int xr = K == 2 ? 4 * c : c;
+    auto sync = [] {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
 #pragma unroll
     for (int e = 0; e < Q; ++e) {
+        if constexpr (HALF) {
+            float2* xh = reinterpret_cast<float2*>(x);
+            const float2* row = xh + c * 64;
 #pragma unroll
-        for (int cc = 0; cc < 4; ++cc) x[cc * 64 + (lane ^ (K == 2 ? 4 * cc : cc))] = v[cc * Q + e];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const int xr = K == 2 ? 4 * c : c;
-        const cp* row = x + c * 64;
+            for (int h = 0; h < 2; ++h) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) v[i * Q + e] = row[(src0 + i * s) ^ xr];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                for (int cc = 0; cc < 4; ++cc) {
+                    const cp u = v[cc * Q + e];
+                    xh[cc * 64 + (lane ^ (K == 2 ? 4 * cc : cc))] = h ? make_float2(u.z, u.w) : make_float2(u.x, u.y);
+                }
+                sync();
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float2 u = row[(src0 + i * s) ^ xr];
+                    if (h) {
+                        v[i * Q + e].z = u.x;
+                        v[i * Q + e].w = u.y;
+                    } else {
+                        v[i * Q + e].x = u.x;
+                        v[i * Q + e].y = u.y;
+                    }
+                }
+                sync();
+            }
+        } else {
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc) x[cc * 64 + (lane ^ (K == 2 ? 4 * cc : cc))] = v[cc * Q + e];
+            sync();
+            const cp* row = x + c * 64;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) v[i * Q + e] = row[(src0 + i * s) ^ xr];
+            sync();
+        }
     }
 }
 
@@ -529,7 +563,7 @@ struct WaveTw {
 
 // The column transform of one lane: registers (b1, e) come out holding bin
 // k_b = Q p + e + E (q + 4 r + 16 b1), lane = 16 p + 4 q + r.
-template <int E>
+template <int E, bool HALF = false>
 __device__ __forceinline__ void wave_transform(const WaveTw<E>& tw, cp* x, int lane, cp (&v)[E]) {
     constexpr int Q = E / 4;
     const int p = lane >> 4, q = (lane >> 2) & 3, r = lane & 3;
@@ -542,13 +576,13 @@ __device__ __forceinline__ void wave_transform(const WaveTw<E>& tw, cp* x, int l
     for (int k = 1; k < 4; ++k)
 #pragma unroll
         for (int e = 0; e < Q; ++e) v[k * Q + e] = cp_rot(v[k * Q + e], tw.wa[k]);
-    wave_exchange<E, 2>(x, lane, q, 16 * p + r, 4, v);  // lane q takes k2a = q
+    wave_exchange<E, 2, HALF>(x, lane, q, 16 * p + r, 4, v);  // lane q takes k2a = q
     wave_dft4<E>(v);                                    // over a1 -> b0
 #pragma unroll
     for (int k = 1; k < 4; ++k)
 #pragma unroll
         for (int e = 0; e < Q; ++e) v[k * Q + e] = cp_rot(v[k * Q + e], tw.wb[k]);
-    wave_exchange<E, 3>(x, lane, r, 16 * p + 4 * q, 1, v);  // lane r takes b0 = r
+    wave_exchange<E, 3, HALF>(x, lane, r, 16 * p + 4 * q, 1, v);  // lane r takes b0 = r
     wave_dft4<E>(v);                                    // over a0 -> b1
 }
 
@@ -587,38 +621,19 @@ __device__ __forceinline__ void wave_output(const PassBArgs& B, int unit, const 
 struct WaveTopkLds {
     int cnt[kPassBCols];
     float sv[kPassBCols];
-    unsigned long long sk[kPassBCols];
+    unsigned so[kPassBCols];
 };
 
-// The same 2F values as wave_output, passed through the top-k gate instead
-// of being stored: with at most kGateFast values of the block at or above
-// the gate's threshold every wave appends its own; with more, the block
-// selects its k best (k rounds of a block-wide argmax), appends them and
-// raises the threshold to the k-th.  Called by every thread of the block.
+// Top-k gate of a block's 2F values, E per thread: v[j] at band offset o[j]
+// (key row_key + o[j]), bit j of mask set when v[j] lies in the band and
+// passes the gate's threshold.  With at most kGateFast values of the block
+// passing, every wave appends its own; with more, the block selects its k
+// best (k rounds of a block-wide argmax), appends them and raises the
+// threshold to the k-th.  Called by every thread of the block.
 template <int E>
-__device__ __forceinline__ void wave_topk(const PassBArgs& B, int unit, const float* st, int tid, int hnf, int nf,
-                                          WaveTopkLds* tl) {
+__device__ __forceinline__ void block_gate(const PassBArgs& B, unsigned long long row_key, const float (&v)[E],
+                                           const int (&o)[E], unsigned mask, int tid, WaveTopkLds* tl) {
     const int lane = tid & 63, wave = tid >> 6;
-    const int t = unit / B.n_groups;
-    const int g = unit - t * B.n_groups;
-    const int s_l = t / B.nf_l;
-    const int f = t - s_l * B.nf_l;
-    const unsigned long long row_key =
-        (unsigned long long)((B.sky0 + s_l) * B.n_fdot + B.f0 + f) * (unsigned long long)B.n_out;
-    const int col = tid & 7;
-    const int kac = g * kPassBCols + col;
-    const float thr = gate_threshold(B.gate);
-    float v[E];
-    int o[E];
-    unsigned mask = 0u;
-#pragma unroll
-    for (int j = 0; j < E; ++j) {
-        const int kb = (tid >> 3) + 64 * j;
-        v[j] = st[kb * kPassBCols + (col ^ ((kb >> 3) & 7))];
-        const int k = kac + B.LA * kb;
-        o[j] = ((k < hnf) ? k : k - nf) - (int)B.s_lo;
-        if (kac < B.LA && (unsigned)o[j] < (unsigned)B.n_out && gate_pass(v[j], thr)) mask |= 1u << j;
-    }
     int wsum;
     const int pre = wave_prefix(__popc(mask), lane, wsum);
     if (lane == 0) tl->cnt[wave] = wsum;
@@ -649,45 +664,116 @@ __device__ __forceinline__ void wave_topk(const PassBArgs& B, int unit, const fl
     }
     unsigned first_slot = 0u;
     if (tid == 0) first_slot = atomicAdd(&B.gate->count[blockIdx.x * kGateStride], (unsigned)B.k);
+    // every value of the block is in one template row: the order of the keys
+    // is that of the band offsets
     float pv = INFINITY;
-    unsigned long long pk = 0ull;
+    unsigned po = 0u;
     for (int r = 0; r < B.k; ++r) {
         float bv = -INFINITY;
-        unsigned long long bk = ~0ull;
+        unsigned bo = ~0u;
 #pragma unroll
         for (int j = 0; j < E; ++j)
             if ((mask >> j) & 1u) {
-                const unsigned long long key = row_key + (unsigned long long)o[j];
-                if ((r == 0 || topk_better(pv, pk, v[j], key)) && topk_better(v[j], key, bv, bk)) {
+                const unsigned oj = (unsigned)o[j];
+                if ((r == 0 || topk_better(pv, po, v[j], oj)) && topk_better(v[j], oj, bv, bo)) {
                     bv = v[j];
-                    bk = key;
+                    bo = oj;
                 }
             }
-        block_best<kWaveColsThreads>(bv, bk, tl->sv, tl->sk);
+        block_best<kWaveColsThreads>(bv, bo, tl->sv, tl->so);
         if (tid == 0 && (int64_t)(first_slot + r) < B.part_cap) {
             TopkItem it = topk_empty();
             if (bv != -INFINITY) {
                 it.v = bv;
-                it.key = bk;
+                it.key = row_key + (unsigned long long)bo;
             }
             pc[first_slot + r] = it;
         }
         pv = bv;
-        pk = bk;
+        po = bo;
     }
     if (tid == 0) gate_raise(B.gate, pv);  // -inf (no raise) when fewer than k values passed
 }
 
-// TOPK: the block's 2F values go through the top-k gate (wave_topk), not to memory.
+// Key of the first bin of block `unit`'s template row.
+__device__ __forceinline__ unsigned long long wave_row_key(const PassBArgs& B, int unit) {
+    const int t = unit / B.n_groups;
+    const int s_l = t / B.nf_l;
+    const int f = t - s_l * B.nf_l;
+    return (unsigned long long)((B.sky0 + s_l) * B.n_fdot + B.f0 + f) * (unsigned long long)B.n_out;
+}
+
+// The same 2F values as wave_output, from the stage, through the gate.
+template <int E>
+__device__ __forceinline__ void wave_topk(const PassBArgs& B, int unit, const float* st, int tid, int hnf, int nf,
+                                          WaveTopkLds* tl) {
+    const int t = unit / B.n_groups;
+    const int g = unit - t * B.n_groups;
+    const int col = tid & 7;
+    const int kac = g * kPassBCols + col;
+    const float thr = gate_threshold(B.gate);
+    float v[E];
+    int o[E];
+    unsigned mask = 0u;
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+        const int kb = (tid >> 3) + 64 * j;
+        v[j] = st[kb * kPassBCols + (col ^ ((kb >> 3) & 7))];
+        const int k = kac + B.LA * kb;
+        o[j] = ((k < hnf) ? k : k - nf) - (int)B.s_lo;
+        if (kac < B.LA && (unsigned)o[j] < (unsigned)B.n_out && gate_pass(v[j], thr)) mask |= 1u << j;
+    }
+    block_gate<E>(B, wave_row_key(B, unit), v, o, mask, tid, tl);
+}
+
+// The 2F values straight from the column transform's registers, through
+// the gate: lane 16 p + 4 q + r of wave w holds bin k_b = Q p + e + E (q +
+// 4 r + 16 b1) of column k_a = 8 g + w in tf[b1 Q + e]; live: k_a < LA.
+template <int E>
+__device__ __forceinline__ void wave_topk_regs(const PassBArgs& B, int unit, const float (&tf)[E], bool live, int tid,
+                                               int hnf, int nf, WaveTopkLds* tl) {
+    constexpr int Q = E / 4;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int p = lane >> 4, q = (lane >> 2) & 3, r = lane & 3;
+    const int t = unit / B.n_groups;
+    const int ka = (unit - t * B.n_groups) * kPassBCols + wave;
+    const float thr = gate_threshold(B.gate);
+    int o[E];
+    unsigned mask = 0u;
+#pragma unroll
+    for (int b1 = 0; b1 < 4; ++b1)
+#pragma unroll
+        for (int e = 0; e < Q; ++e) {
+            const int j = b1 * Q + e;
+            const int kb = Q * p + e + E * (q + 4 * r + 16 * b1);
+            const int k = ka + B.LA * kb;
+            o[j] = ((k < hnf) ? k : k - nf) - (int)B.s_lo;
+            if (live && (unsigned)o[j] < (unsigned)B.n_out && gate_pass(tf[j], thr)) mask |= 1u << j;
+        }
+    block_gate<E>(B, wave_row_key(B, unit), tf, o, mask, tid, tl);
+}
+
+// 2F of one transformed column value (eq. eq6 with the noise-weighted A', B', C').
+__device__ __forceinline__ float two_f(const cp& u, float cA, float cB, float cC) {
+    return cA * (u.x * u.x + u.y * u.y) + cB * (u.z * u.z + u.w * u.w) + cC * (u.x * u.z + u.y * u.w);
+}
+
+// TOPK: the block's 2F values go through the top-k gate (wave_topk), not to
+// memory.  E = 16 (1024-point columns, top-k only): the 128 KB block leaves
+// no room for the 2F stage, so the gate reads the transform's registers
+// (wave_topk_regs), and the lane exchanges go through 2 KB per wave, one
+// spectrum at a time.
 template <int E, bool NT, bool TOPK>
 __global__ __launch_bounds__(kWaveColsThreads) void rsf_fft_pass_b_wave_k(PassBArgs B) {
     constexpr int Q = E / 4;
     constexpr int LBW = 64 * E;
+    constexpr bool kDirect = E == 16;
+    static_assert(!kDirect || TOPK, "1024-point columns feed the top-k gate only");
     extern __shared__ float4 lds[];
     float4* blk = lds;                                              // the block, 8 columns x LB
     cp* xch = lds + kPassBCols * LBW;                               // 8 waves x 4 x 64 slots
-    float* st = reinterpret_cast<float*>(xch + kPassBCols * 4 * 64);  // 2F stage [LB][8]
-    float* cfl = st + LBW * kPassBCols;                             // 4 per sky of the launch
+    float* st = reinterpret_cast<float*>(xch + kPassBCols * (kDirect ? 2 : 4) * 64);  // 2F stage [LB][8]
+    float* cfl = kDirect ? st : st + LBW * kPassBCols;              // 4 per sky of the launch
     WaveTopkLds* tkl = reinterpret_cast<WaveTopkLds*>(cfl + 4 * (B.n_sky_l > 64 ? B.n_sky_l : 64));
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int p = lane >> 4, q = (lane >> 2) & 3, r = lane & 3;
@@ -702,13 +788,37 @@ __global__ __launch_bounds__(kWaveColsThreads) void rsf_fft_pass_b_wave_k(PassBA
         tw.wa[k] = w_lb(E * (lane & 15) * k);
         tw.wb[k] = w_lb(4 * E * (lane & 3) * k);
     }
-    cp* x = xch + wave * 4 * 64;
+    cp* x = xch + wave * (kDirect ? 2 : 4) * 64;
     const int hnf = (int)((B.n_fft + 1) >> 1);
     const int nf = (int)B.n_fft;
     const int n_units = B.n_tmpl * B.n_groups;
     const int G = (int)gridDim.x;
     int unit = blockIdx.x;
     if (unit < n_units) wave_dma<NT>(B, unit, blk, wave, lane);
+    if constexpr (kDirect) {
+        for (; unit < n_units; unit += G) {
+            // this block's DMA (and the previous block's candidate stores) are
+            // complete in every wave; every wave has left the previous gate
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            const int t = unit / B.n_groups;
+            const bool live = (unit - t * B.n_groups) * kPassBCols + wave < B.LA;
+            cp v[E];
+            if (live) wave_col_read<E>(blk, wave, lane, v);
+            __syncthreads();  // the block buffer is free
+            if (unit + G < n_units) wave_dma<NT>(B, unit + G, blk, wave, lane);
+            float tf[E];
+            if (live) {
+                wave_transform<E, true>(tw, x, lane, v);
+                const int s_l = t / B.nf_l;
+                const float cA = cfl[4 * s_l], cB = cfl[4 * s_l + 1], cC = cfl[4 * s_l + 2];
+#pragma unroll
+                for (int j = 0; j < E; ++j) tf[j] = two_f(v[j], cA, cB, cC);
+            }
+            wave_topk_regs<E>(B, unit, tf, live, tid, hnf, nf, tkl);
+        }
+        return;
+    }
     int prev = -1;
     for (; unit < n_units; unit += G) {
         // this block's DMA (and the previous block's stores) are complete in
@@ -736,10 +846,8 @@ __global__ __launch_bounds__(kWaveColsThreads) void rsf_fft_pass_b_wave_k(PassBA
             for (int b1 = 0; b1 < 4; ++b1)
 #pragma unroll
                 for (int e = 0; e < Q; ++e) {
-                    const cp u = v[b1 * Q + e];
                     const int kb = Q * p + e + E * (q + 4 * r + 16 * b1);
-                    st[kb * kPassBCols + (wave ^ ((kb >> 3) & 7))] =
-                        cA * (u.x * u.x + u.y * u.y) + cB * (u.z * u.z + u.w * u.w) + cC * (u.x * u.z + u.y * u.w);
+                    st[kb * kPassBCols + (wave ^ ((kb >> 3) & 7))] = two_f(v[b1 * Q + e], cA, cB, cC);
                 }
         }
         prev = unit;
@@ -767,34 +875,44 @@ hipError_t launch_fft_pass_a(const PassAArgs& a, hipStream_t s) {
     const unsigned gy = (unsigned)(a.n_sky_l * ((a.nf_l + a.fb - 1) / a.fb));
     const dim3 grid((unsigned)a.LB, gy);
     // the same pruning rule as the kernel's
-    const bool prune = 2 * a.P <= a.LA && a.st.n_stages > 1 && (a.st.radix[0] & 1) == 0;
-    const int plan = fixed_row_plan(a.st, prune);
+    const bool prune = 2 * a.P <= a.LA && a.st.n_stages > 1;
+    int plan = fixed_row_plan(a.st, prune);
+    if (plan == 0 && a.ept == kFftEPTWide) plan = kPlanWide;
+    else if (plan == 0 && a.ept != kFftEPT) return hipErrorInvalidValue;
 #define RSF_PASS_A(ORD, PL)                                                              \
     if (a.nt_spill)                                                                      \
         hipLaunchKernelGGL((rsf_fft_pass_a_k<ORD, true, PL>), grid, dim3(kNT), lds, s, a); \
     else                                                                                 \
         hipLaunchKernelGGL((rsf_fft_pass_a_k<ORD, false, PL>), grid, dim3(kNT), lds, s, a)
-    switch (a.spin_order * 2 + (plan == kRow9000 ? 1 : 0)) {
-        case 2: RSF_PASS_A(1, 0); break;
-        case 3: RSF_PASS_A(1, kRow9000); break;
-        case 4: RSF_PASS_A(2, 0); break;
-        case 5: RSF_PASS_A(2, kRow9000); break;
-        case 6: RSF_PASS_A(3, 0); break;
-        case 7: RSF_PASS_A(3, kRow9000); break;
+    switch (a.spin_order * 3 + plan) {
+        case 3: RSF_PASS_A(1, 0); break;
+        case 4: RSF_PASS_A(1, kRow9000); break;
+        case 5: RSF_PASS_A(1, kPlanWide); break;
+        case 6: RSF_PASS_A(2, 0); break;
+        case 7: RSF_PASS_A(2, kRow9000); break;
+        case 8: RSF_PASS_A(2, kPlanWide); break;
+        case 9: RSF_PASS_A(3, 0); break;
+        case 10: RSF_PASS_A(3, kRow9000); break;
+        case 11: RSF_PASS_A(3, kPlanWide); break;
         default: return hipErrorInvalidValue;
     }
 #undef RSF_PASS_A
     return hipGetLastError();
 }
 
-// Columns of 64 E points, E = 4, 8, 12: the one-column-per-wave second pass.
-int fft_pass_b_wave_e(int LB) {
+// Columns of 64 E points, E = 4, 8, 12, and E = 16 when the pass feeds the
+// top-k gate: the one-column-per-wave second pass.
+int fft_pass_b_wave_e(int LB, bool topk) {
     const int E = LB / 64;
-    return (LB % 64 == 0 && (E == 4 || E == 8 || E == 12)) ? E : 0;
+    return (LB % 64 == 0 && (E == 4 || E == 8 || E == 12 || (topk && E == 16))) ? E : 0;
 }
 
-size_t fft_pass_b_lds(int LB, int n_sky_l) {
-    if (fft_pass_b_wave_e(LB))
+size_t fft_pass_b_lds(int LB, int n_sky_l, bool topk) {
+    const int E = fft_pass_b_wave_e(LB, topk);
+    if (E == 16)
+        return (size_t)kPassBCols * LB * sizeof(float4) + (size_t)kPassBCols * 2 * 64 * sizeof(float4) +
+               (size_t)4 * std::max(n_sky_l, 64) * sizeof(float) + sizeof(WaveTopkLds);
+    if (E)
         return (size_t)kPassBCols * LB * sizeof(float4) + (size_t)kPassBCols * 4 * 64 * sizeof(float4) +
                (size_t)LB * kPassBCols * sizeof(float) + (size_t)4 * std::max(n_sky_l, 64) * sizeof(float) +
                sizeof(WaveTopkLds);
@@ -810,7 +928,7 @@ int fft_pass_b_grid(const PassBArgs& b, int n_cu) {
 }
 
 hipError_t launch_fft_pass_b(const PassBArgs& b, int n_cu, hipStream_t s) {
-    const size_t lds = fft_pass_b_lds(b.LB, b.n_sky_l);
+    const size_t lds = fft_pass_b_lds(b.LB, b.n_sky_l, b.topk != 0);
     const unsigned grid = (unsigned)fft_pass_b_grid(b, n_cu);
 #define RSF_PASS_B_WAVE1(EE, NTT, TK) \
     hipLaunchKernelGGL((rsf_fft_pass_b_wave_k<EE, NTT, TK>), dim3(grid), dim3(kWaveColsThreads), lds, s, b)
@@ -828,10 +946,16 @@ hipError_t launch_fft_pass_b(const PassBArgs& b, int n_cu, hipStream_t s) {
                 RSF_PASS_B_WAVE1(EE, false, false); \
         }                                    \
         return hipGetLastError();
-    switch (b.wave ? fft_pass_b_wave_e(b.LB) : 0) {
+    switch (b.wave ? fft_pass_b_wave_e(b.LB, b.topk) : 0) {
         RSF_PASS_B_WAVE(4)
         RSF_PASS_B_WAVE(8)
         RSF_PASS_B_WAVE(12)
+        case 16:
+            if (b.nt_spill)
+                RSF_PASS_B_WAVE1(16, true, true);
+            else
+                RSF_PASS_B_WAVE1(16, false, true);
+            return hipGetLastError();
         default: break;
     }
 #undef RSF_PASS_B_WAVE
@@ -854,13 +978,17 @@ hipError_t fft_set_lds_limits(size_t bytes) {
                          (const void*)rsf_fft_pass_a_k<1, false, kRow9000>, (const void*)rsf_fft_pass_a_k<2, false, kRow9000>,
                          (const void*)rsf_fft_pass_a_k<3, false, kRow9000>, (const void*)rsf_fft_pass_a_k<1, true, kRow9000>,
                          (const void*)rsf_fft_pass_a_k<2, true, kRow9000>,  (const void*)rsf_fft_pass_a_k<3, true, kRow9000>,
+                         (const void*)rsf_fft_pass_a_k<1, false, kPlanWide>, (const void*)rsf_fft_pass_a_k<2, false, kPlanWide>,
+                         (const void*)rsf_fft_pass_a_k<3, false, kPlanWide>, (const void*)rsf_fft_pass_a_k<1, true, kPlanWide>,
+                         (const void*)rsf_fft_pass_a_k<2, true, kPlanWide>,  (const void*)rsf_fft_pass_a_k<3, true, kPlanWide>,
                          (const void*)rsf_fft_pass_b_k<false>,        (const void*)rsf_fft_pass_b_k<true>,
                          (const void*)rsf_fft_pass_b_wave_k<4, false, false>, (const void*)rsf_fft_pass_b_wave_k<4, true, false>,
                          (const void*)rsf_fft_pass_b_wave_k<8, false, false>, (const void*)rsf_fft_pass_b_wave_k<8, true, false>,
                          (const void*)rsf_fft_pass_b_wave_k<12, false, false>, (const void*)rsf_fft_pass_b_wave_k<12, true, false>,
                          (const void*)rsf_fft_pass_b_wave_k<4, false, true>, (const void*)rsf_fft_pass_b_wave_k<4, true, true>,
                          (const void*)rsf_fft_pass_b_wave_k<8, false, true>, (const void*)rsf_fft_pass_b_wave_k<8, true, true>,
-                         (const void*)rsf_fft_pass_b_wave_k<12, false, true>, (const void*)rsf_fft_pass_b_wave_k<12, true, true>};
+                         (const void*)rsf_fft_pass_b_wave_k<12, false, true>, (const void*)rsf_fft_pass_b_wave_k<12, true, true>,
+                         (const void*)rsf_fft_pass_b_wave_k<16, false, true>, (const void*)rsf_fft_pass_b_wave_k<16, true, true>};
     hipError_t out = hipSuccess;
     for (const void* f : fns) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);

@@ -17,8 +17,10 @@ hipError_t launch_antenna_reduce(const ReduceArgs& r, hipStream_t s);
 hipError_t launch_fft_pass_a(const PassAArgs& a, hipStream_t s);
 size_t fft_pass_a_lds(int LA);
 hipError_t launch_fft_pass_b(const PassBArgs& b, int n_cu, hipStream_t s);
-size_t fft_pass_b_lds(int LB, int n_sky_l);
-int fft_pass_b_wave_e(int LB);  // E when the second pass runs one column of 64 E points per wave, else 0
+size_t fft_pass_b_lds(int LB, int n_sky_l, bool topk);
+// E when the second pass runs one column of 64 E points per wave (E = 16 only
+// when it feeds the top-k gate), else 0
+int fft_pass_b_wave_e(int LB, bool topk);
 hipError_t fft_set_lds_limits(size_t bytes);
 int fft_pass_max_elems();
 

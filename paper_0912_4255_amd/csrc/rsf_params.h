@@ -23,6 +23,13 @@ constexpr int kPassBThreads = 768;  // threads of a second-pass workgroup (3 wav
 // 10752); radices 2, 4, 5, 6, 8 ... 16 hold the same number as at 20
 constexpr int kFftEPT = 21;
 constexpr int kFftMaxLen = 10240;   // longest first-pass transform (10240 x 16 B = 160 KiB of LDS)
+constexpr size_t kLdsPerGroupMax = 163840;  // LDS one workgroup can hold (160 KiB)
+// First-pass rows too long for two workgroups per CU (over half the LDS) run
+// one workgroup of 8 waves per CU, 2 waves per SIMD, which leaves up to 256
+// VGPRs per lane: their stages hold up to kFftEPTWide complex pairs per
+// thread, so that radices 9 to 16 stay usable up to 10240 points (fewer
+// stages; 9720 = 10 x 12 x 9 x 9 instead of 10 x 4 x 3^5).
+constexpr int kFftEPTWide = 32;
 
 // Butterflies of radix R one thread holds in a stage: never more than EPT
 // elements, so a stage of radix R covers at most fft_radix_cap(R) butterflies
@@ -139,6 +146,7 @@ struct PassAArgs {
     float4* spill;            // [n_sky_l * nf_l][ceil(LA/8)][LB][8]: 8-column groups
     int64_t spill_tmpl_stride;
     int nt_spill;             // spill larger than the last-level cache: non-temporal stores
+    int ept;                  // stage capacity st was planned for: kFftEPT or kFftEPTWide
 };
 
 // Candidate gate of a top-k search (device memory, one per call): thr holds

@@ -21,6 +21,10 @@ namespace rsf {
 __device__ __forceinline__ bool topk_better(float va, unsigned long long ka, float vb, unsigned long long kb) {
     return va > vb || (va == vb && ka < kb);
 }
+// The same order on keys that share their upper part (one template row).
+__device__ __forceinline__ bool topk_better(float va, unsigned ka, float vb, unsigned kb) {
+    return va > vb || (va == vb && ka < kb);
+}
 
 __device__ __forceinline__ TopkItem topk_empty() {
     TopkItem e;

@@ -110,18 +110,26 @@ def test_fft_factorisation_covers_every_workload_length(lib):
         l1, l2 = C.c_int32(), C.c_int32()
         assert lib.rsf_fft_factor(m, 163840, 0, C.byref(l1), C.byref(l2)) == L.RSF_OK, (m, lib.rsf_last_error())
         assert l1.value * l2.value == m and l1.value <= 10240
-    # the one-column-per-wave second pass (L2 = 256, 512, 768) is preferred where it fits
+    # the one-column-per-wave second pass (L2 = 256, 512, 768) is preferred
+    # where it fits, then L2 = 1024 (one column per wave for the top-k)
     l1, l2 = C.c_int32(), C.c_int32()
     assert lib.rsf_fft_factor(6912000, 163840, 0, C.byref(l1), C.byref(l2)) == L.RSF_OK
     assert (l1.value, l2.value) == (9000, 768)
-    wave = 0
+
+    def first_pass_fits(la):   # the row and its two-level twiddle table in 160 KiB
+        return la <= 10240 and la * 16 + (32 + (la + 31) // 32) * 8 <= 163840
+
+    wave = wave16 = 0
     for n in c3_segment_lengths():
         m = fft_length(n, NFFT_SMOOTH7_256)
         assert lib.rsf_fft_factor(m, 163840, 0, C.byref(l1), C.byref(l2)) == L.RSF_OK
         wave += l2.value in (256, 512, 768)
+        wave16 += l2.value == 1024
         if any(m % lb == 0 and m // lb <= 10000 for lb in (256, 512, 768)):
             assert l2.value in (256, 512, 768), (m, l1.value, l2.value)
-    assert wave >= 45
+        elif m % 1024 == 0 and first_pass_fits(m // 1024):
+            assert l2.value == 1024, (m, l1.value, l2.value)
+    assert wave >= 45 and wave + wave16 >= 56
     assert lib.rsf_fft_factor(2 * 11 * 1000, 163840, 0, None, None) == L.RSF_EUNSUPPORTED
     assert lib.rsf_fft_factor(6912000, 163840, 7200, C.byref(l1), None) == L.RSF_OK and l1.value == 7200
 

@@ -2,15 +2,21 @@
 the lower (sky, fdot, bin); NaN never enters), against the selection over the
 full 2F map computed by the same plan:
 
-* second passes of LB = 256, 512, 768 points select inside the kernel (no
-  map); other lengths scan a map; both over several FFT launches, so the
-  threshold carried from launch to launch is exercised;
+* second passes of LB = 256, 512, 768 points select inside the kernel from
+  a 2F stage in LDS, LB = 1024 straight from the transform's registers (no
+  map either way); other lengths scan a map; all over several FFT
+  launches, so the threshold carried from launch to launch is exercised;
 * a series of zeros makes every 2F exactly 0: every value ties, every block
   takes its slow path and the result is the k lowest keys;
 * an all-gap segment has NaN everywhere: no entry;
 * graph replays reproduce the eager result;
 * at the T = 10 d shape (two launches of the benchmark's configuration) the
-  in-pass top-10 equals the selection over the full map."""
+  in-pass top-10 equals the selection over the full map, and at a 26.6-day
+  uneven segment (N_fft = 9000 x 1024) it agrees with it to FP32 rounding.
+
+With 1024-point columns the map comes from the LDS-stage second pass and
+the top-k from the one-column-per-wave pass, so the two agree to FP32
+rounding rather than bit for bit."""
 import numpy as np
 import pytest
 
@@ -20,7 +26,7 @@ from tests.test_gpu_batch import numpy_topk
 
 pytestmark = pytest.mark.gpu
 
-N, DT = 38400, 4.0      # N_fft = 76800 = 300 x 256 = 150 x 512 = 100 x 768
+N, DT = 38400, 4.0      # N_fft = 76800 = 300 x 256 = 150 x 512 = 100 x 768 = 75 x 1024
 N_FDOT = 9
 
 
@@ -40,7 +46,33 @@ def _expected(maps, k, n_out):
     return maps.reshape(-1)[flat], ids
 
 
-@pytest.mark.parametrize("l1", [300, 150, 100, 160])
+def _check_selection(vals, ids, maps, k, exact):
+    """The top-k (vals, ids) against the selection over the 2F map `maps`
+    [n_sky][n_fdot][n_out].  exact: the map came from the same second-pass
+    kernel, so values and keys are identical.  Otherwise (1024-point
+    columns: the map pass is the LDS-stage kind, the top-k pass the
+    one-column-per-wave kind) the two agree to FP32 rounding: every value
+    matches the map at its key, the values descend, and no map value clearly
+    above the k-th is missing."""
+    n_out = maps.shape[-1]
+    if exact:
+        ev, ei = _expected(maps, k, n_out)
+        assert np.array_equal(ids, ei)
+        assert np.array_equal(vals, ev)
+        return
+    tol = lambda v: 1e-5 * np.maximum(np.abs(v), 4.0)
+    at = maps[ids[:, 0], ids[:, 1], ids[:, 2]]
+    assert np.all(np.abs(vals - at) <= tol(at)), np.max(np.abs(vals - at))
+    assert np.all(np.diff(vals) <= 0)
+    assert len({tuple(i) for i in ids}) == k
+    ev, _ = _expected(maps, k, n_out)
+    assert abs(vals[-1] - ev[-1]) <= tol(ev[-1])
+    chosen = np.zeros(maps.shape, bool)
+    chosen[ids[:, 0], ids[:, 1], ids[:, 2]] = True
+    assert not np.any((maps > vals[-1] + 2 * tol(vals[-1])) & ~chosen)
+
+
+@pytest.mark.parametrize("l1", [300, 150, 100, 75, 160])
 @pytest.mark.parametrize("k", [1, 10, 64])
 def test_topk_matches_map_selection(gpu_lib, l1, k):
     import torch
@@ -53,15 +85,13 @@ def test_topk_matches_map_selection(gpu_lib, l1, k):
     tx, tg = to_gpu(xs, gaps)
     sky = torch.from_numpy(synth.uniform_sky(np.random.default_rng(33), 3)).cuda()
     fd = torch.from_numpy(synth.fdot_grid(N_FDOT)).cuda()
-    maps = plan.fstat(tx, tg, sky, fd).cpu().numpy()
+    maps = plan.fstat(tx, tg, sky, fd).cpu().numpy().reshape(3, N_FDOT, plan.n_out)
     vals, ids = plan.topk(tx, tg, sky, fd, k=k)
-    ev, ei = _expected(maps, k, plan.n_out)
-    assert np.array_equal(ids.cpu().numpy(), ei)
-    assert np.array_equal(vals.cpu().numpy(), ev)
+    _check_selection(vals.cpu().numpy(), ids.cpu().numpy(), maps, k, exact=plan.fft_l2 != 1024)
     plan.close()
 
 
-@pytest.mark.parametrize("l1", [150, 160])
+@pytest.mark.parametrize("l1", [150, 75, 160])
 def test_all_ties_give_lowest_keys(gpu_lib, l1):
     import torch
     w = synth.small_workload(n=N, dt=DT, kernel=synth.KERNEL_DIRICHLET, taps=16)
@@ -79,7 +109,7 @@ def test_all_ties_give_lowest_keys(gpu_lib, l1):
     plan.close()
 
 
-@pytest.mark.parametrize("l1", [150, 160])
+@pytest.mark.parametrize("l1", [150, 75, 160])
 def test_all_nan_gives_no_entry(gpu_lib, l1):
     import torch
     w = synth.small_workload(n=N, dt=DT, kernel=synth.KERNEL_DIRICHLET, taps=16)
@@ -96,12 +126,13 @@ def test_all_nan_gives_no_entry(gpu_lib, l1):
     plan.close()
 
 
-def test_graph_replays_in_pass_topk(gpu_lib):
+@pytest.mark.parametrize("l1", [100, 75])
+def test_graph_replays_in_pass_topk(gpu_lib, l1):
     import torch
     w = synth.small_workload(n=N, dt=DT, kernel=synth.KERNEL_DIRICHLET, taps=16)
     xs, gaps = make_inputs(w, seed=35)
-    plan = _plan(gpu_lib, w, 100)
-    print("\ncase: graph replays of the in-pass top-k", flush=True)
+    plan = _plan(gpu_lib, w, l1)
+    print(f"\ncase: graph replays of the in-pass top-k, L1 = {l1}", flush=True)
     tx, tg = to_gpu(xs, gaps)
     sky = torch.from_numpy(synth.uniform_sky(np.random.default_rng(36), 2)).cuda()
     fd = torch.from_numpy(synth.fdot_grid(N_FDOT)).cuda()
@@ -119,6 +150,55 @@ def test_graph_replays_in_pass_topk(gpu_lib):
     plan.close()
 
 
+def _map_selection(torch, maps, k, n_out, n_fdot):
+    """The k best of a 2F map on the GPU: the values at or above the k-th
+    largest, ordered by value, then by key."""
+    flat = maps.reshape(-1)
+    kth = torch.topk(flat, k).values[-1]
+    cand = torch.nonzero(flat >= kth).flatten().cpu().numpy()
+    v = flat[torch.from_numpy(cand).cuda()].cpu().numpy()
+    order = np.lexsort((cand, -v.astype(np.float64)))[:k]
+    sel = cand[order]
+    return v[order], np.stack([sel // (n_out * n_fdot), (sel // n_out) % n_fdot, sel % n_out], axis=1)
+
+
+def test_topk_at_a_long_uneven_segment(gpu_lib):
+    """A 26.6-day segment of the uneven set (N = 4,593,600, dt = 0.5 s,
+    N_fft = 9,216,000 = 9000 x 1024: 1024-point columns, one per wave), one
+    sky and 64 spindowns in launches of 32 templates: the in-pass top-10
+    agrees with the selection over the full map to FP32 rounding (the map
+    comes from the LDS-stage second pass)."""
+    import torch
+    lengths = synth.c3_segment_lengths()
+    i = lengths.index(4593600)
+    w = synth.workload_c3_segment(i, n_sky=1)
+    from paper_0912_4255_amd.api import plan_desc_from_workload
+    d = plan_desc_from_workload(w)
+    d.fft_l1 = 9000
+    plan = gpu_lib.Plan(desc=d)
+    assert (plan.fft_l1, plan.fft_l2) == (9000, 1024)
+    plan.set_batching(16, 32)
+    rng = np.random.default_rng(41)
+    x = synth.zero_gaps(synth.gaussian_noise(rng, w.segment.n, 1.0), w.gaps[0])
+    print(f"\ncase: top-10 at N = {w.segment.n}, plan {plan.fft_l1} x {plan.fft_l2}", flush=True)
+    tx, tg = to_gpu([x], [w.gaps[0]])
+    sky = torch.from_numpy(np.ascontiguousarray(w.skies[:1])).cuda()
+    fd = torch.from_numpy(synth.fdot_grid(64)).cuda()
+    vals, ids = plan.topk(tx, tg, sky, fd, k=10)
+    vals, ids = vals.cpu().numpy(), ids.cpu().numpy()
+    maps = plan.fstat(tx, tg, sky, fd).reshape(1, 64, plan.n_out)
+    # the selection over the map (the LDS-stage second pass) agrees to FP32 rounding
+    ev, ei = _map_selection(torch, maps, 10, plan.n_out, 64)
+    tol = 1e-5 * np.maximum(np.abs(ev), 4.0)
+    at = maps[0, torch.from_numpy(ids[:, 1]).cuda(), torch.from_numpy(ids[:, 2]).cuda()].cpu().numpy()
+    assert np.all(ids[:, 0] == 0) and np.all(np.abs(vals - at) <= tol)
+    assert np.all(np.abs(vals - ev) <= tol) and np.all(np.diff(vals) <= 0)
+    clear = (ev - ev[-1]) > 2 * tol[-1]          # entries clearly above the 10th must be there
+    got = {tuple(i) for i in ids}
+    assert all(tuple(e) in got for e in ei[clear]), (ids, ei)
+    plan.close()
+
+
 def test_topk_at_the_ten_day_shape(gpu_lib):
     """The T = 10 d search (N = 3,456,000, N_fft = 6,912,000, one column per
     wave in the second pass), one sky and 96 spindowns in launches of 64
@@ -133,18 +213,8 @@ def test_topk_at_the_ten_day_shape(gpu_lib):
     tx, tg = to_gpu(xs, gaps)
     sky = torch.from_numpy(np.ascontiguousarray(w.skies[:1])).cuda()
     fd = torch.from_numpy(synth.fdot_grid(96)).cuda()
-    k = 10
-    vals, ids = plan.topk(tx, tg, sky, fd, k=k)
-    vals, ids = vals.cpu().numpy(), ids.cpu().numpy()
-    maps = plan.fstat(tx, tg, sky, fd)
-    flat = maps.reshape(-1)
-    kth = torch.topk(flat, k).values[-1]          # the k-th largest value
-    cand = torch.nonzero(flat >= kth).flatten().cpu().numpy()
-    v = flat[torch.from_numpy(cand).cuda()].cpu().numpy()
-    order = np.lexsort((cand, -v.astype(np.float64)))[:k]
-    sel = cand[order]
-    n_out = plan.n_out
-    exp_ids = np.stack([sel // (n_out * 96), (sel // n_out) % 96, sel % n_out], axis=1)
-    assert np.array_equal(ids, exp_ids), (ids, exp_ids)
-    assert np.array_equal(vals, v[order])
+    vals, ids = plan.topk(tx, tg, sky, fd, k=10)
+    ev, ei = _map_selection(torch, plan.fstat(tx, tg, sky, fd), 10, plan.n_out, 96)
+    assert np.array_equal(ids.cpu().numpy(), ei), (ids, ei)
+    assert np.array_equal(vals.cpu().numpy(), ev)
     plan.close()

@@ -106,3 +106,80 @@ def test_pruned_first_stage_for_each_even_radix(gpu_lib, n, l1):
     rss = [of.resample(xs[0], gaps[0], w.segment, 2.2, 0.4, w.eph, w.detectors[0], w.kernel, w.taps)]
     ref = of.fstat_band(rss, w.detectors, -2e-10, plan.n_fft, plan.s_lo, plan.n_out)
     assert np.all(np.abs(got - ref) <= twoF_tol(ref)), l1
+
+
+@pytest.mark.parametrize("n,l1", [(9262, 125), (8401, 135), (8401, 189), (8193, 343)])
+def test_pruned_first_stage_for_each_odd_radix(gpu_lib, n, l1):
+    """First-pass lengths 125 = 5^3, 135 = 15 x 9, 189 = 9 x 7 x 3 and
+    343 = 7^3 (odd first radix 5, 15, 9, 7) on 7-smooth FFT lengths with
+    padding beyond 2N, so that the nonzero rows end below L1/2: the pruned
+    first stage reads inputs r < (R + 1)/2 of each radix-R butterfly only,
+    and no row at or above ((R + 1)/2) L1/R is written."""
+    import torch
+    from paper_0912_4255_amd.api import plan_desc_from_workload
+    w = synth.small_workload(n=n, dt=4.0, kernel=synth.KERNEL_DIRICHLET, taps=16, nfft_policy=synth.NFFT_SMOOTH7)
+    xs, gaps = make_inputs(w, seed=14)
+    d = plan_desc_from_workload(w)
+    d.fft_l1 = l1
+    plan = gpu_lib.Plan(desc=d)
+    assert plan.fft_l1 == l1 and 2 * -(-n // plan.fft_l2) <= l1   # rows P <= L1 / 2
+    print(f"\ncase: odd first radix, L1 x L2 = {plan.fft_l1} x {plan.fft_l2}", flush=True)
+    tx, tg = to_gpu(xs, gaps)
+    sky = torch.tensor([[0.4, -1.1]], dtype=torch.float64).cuda()
+    fd = torch.tensor([3e-10], dtype=torch.float64).cuda()
+    got = plan.fstat(tx, tg, sky, fd).cpu().numpy()[0]
+    rss = [of.resample(xs[0], gaps[0], w.segment, 0.4, -1.1, w.eph, w.detectors[0], w.kernel, w.taps)]
+    ref = of.fstat_band(rss, w.detectors, 3e-10, plan.n_fft, plan.s_lo, plan.n_out)
+    assert np.all(np.abs(got - ref) <= twoF_tol(ref)), l1
+
+
+def test_odd_first_pass_at_an_uneven_segment(gpu_lib):
+    """A 22.6-day uneven segment (N = 1,951,200, N_fft = 3,919,104): the
+    planner's L1 = 5103 = 9 x 9 x 9 x 7 (pruned first stage of radix 9)
+    against L1 = 6804 (first radix 12) on the same input, one sky and four
+    spindowns: the two full-band 2F maps agree within the parity bar."""
+    import torch
+    from paper_0912_4255_amd.api import plan_desc_from_workload
+    lengths = synth.c3_segment_lengths()
+    w = synth.workload_c3_segment(lengths.index(1951200), n_sky=1)
+    rng = np.random.default_rng(43)
+    x = synth.zero_gaps(synth.gaussian_noise(rng, w.segment.n, 1.0), w.gaps[0])
+    tx, tg = to_gpu([x], [w.gaps[0]])
+    sky = torch.from_numpy(np.ascontiguousarray(w.skies[:1])).cuda()
+    fd = torch.from_numpy(synth.fdot_grid(4)).cuda()
+    maps = []
+    for l1 in (5103, 6804):
+        d = plan_desc_from_workload(w)
+        d.fft_l1 = l1
+        plan = gpu_lib.Plan(desc=d)
+        assert plan.fft_l1 == l1 and plan.n_fft == 3919104
+        print(f"\ncase: uneven segment, L1 x L2 = {plan.fft_l1} x {plan.fft_l2}", flush=True)
+        maps.append(plan.fstat(tx, tg, sky, fd).cpu().numpy())
+        plan.close()
+    assert np.all(np.abs(maps[0] - maps[1]) <= twoF_tol(maps[1]))
+
+
+@pytest.mark.parametrize("n,l1", [(38880, 9720), (36864, 9216), (37632, 9408), (37044, 9261)])
+def test_wide_first_pass_stages(gpu_lib, n, l1):
+    """First-pass rows of one workgroup per CU whose stages hold up to 32
+    complex pairs per thread: 9720 = 12 x 10 x 9 x 9, 9216 = 16 x 9 x 8 x 8,
+    9408 = 16 x 12 x 7 x 7 (four stages each, against seven, six and six at
+    21 pairs per thread) and 9261 = 9 x 7 x 7 x 7 x 3 (odd, not pruned),
+    with 8-point columns in the second pass, full band against the oracle."""
+    import torch
+    from paper_0912_4255_amd.api import plan_desc_from_workload
+    w = synth.small_workload(n=n, dt=4.0, kernel=synth.KERNEL_DIRICHLET, taps=16)
+    xs, gaps = make_inputs(w, seed=15)
+    d = plan_desc_from_workload(w)
+    d.fft_l1 = l1
+    plan = gpu_lib.Plan(desc=d)
+    assert (plan.fft_l1, plan.fft_l2) == (l1, 2 * n // l1)
+    print(f"\ncase: wide first pass, L1 x L2 = {plan.fft_l1} x {plan.fft_l2}", flush=True)
+    tx, tg = to_gpu(xs, gaps)
+    sky = torch.tensor([[5.1, 0.9]], dtype=torch.float64).cuda()
+    fd = torch.tensor([-1e-9, 2e-10], dtype=torch.float64).cuda()
+    got = plan.fstat(tx, tg, sky, fd).cpu().numpy()
+    rss = [of.resample(xs[0], gaps[0], w.segment, 5.1, 0.9, w.eph, w.detectors[0], w.kernel, w.taps)]
+    for i, f in enumerate((-1e-9, 2e-10)):
+        ref = of.fstat_band(rss, w.detectors, f, plan.n_fft, plan.s_lo, plan.n_out)
+        assert np.all(np.abs(got[i] - ref) <= twoF_tol(ref)), (l1, i)
