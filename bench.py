@@ -67,7 +67,8 @@ def parse():
     return ap.parse_args()
 
 
-KERNEL_SOURCES = ("rsf_fft.hip", "rsf_spill.h", "rsf_device.h", "rsf_params.h", "rsf_resample.hip")
+KERNEL_SOURCES = ("rsf_fft.hip", "rsf_pass_a.h", "rsf_spill.h", "rsf_topk_gate.h", "rsf_device.h", "rsf_params.h",
+                  "rsf_resample.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_fft_T10d.md")
 PEAK_FP32_MFMA_TFLOPS = 157.3  # MI355X dense FP32 matrix
 # Vector-instruction issue: 256 CUs x 4 SIMDs, one wave64 VALU instruction per

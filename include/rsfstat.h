@@ -202,6 +202,26 @@ int rsf_plan_batching(const rsf_plan* plan, int64_t n_sky, int64_t n_fdot, int m
 int rsf_plan_query(const rsf_plan* plan, int64_t* n_fft, int64_t* bin_lo, int64_t* n_out,
                    int32_t* l1, int32_t* l2, double* df);
 
+/* First-pass kernel kinds (rsf_plan_first_pass).  The first FFT pass
+ * (Sec. III.A.2, step 6: rows of length L1 in LDS) runs either the planned
+ * radix stages of a general kernel or a kernel whose radix sequence is fixed
+ * at compile time (constant stage sizes, per-stage twiddle tables): one
+ * compiled into the library, or one compiled at plan creation with hipRTC
+ * from the library's own headers (found beside the library, checked against
+ * the hash recorded when it was built; cached on disk under
+ * $RSF_KERNEL_CACHE, else $XDG_CACHE_HOME/rsfstat or ~/.cache/rsfstat).
+ * Run-time kernels are made for transforms of 2^19 points or more
+ * (RSF_RTC=all: any size; RSF_RTC=0: never) whose rows end below L1/2 (the
+ * pruned first stage); when that is not possible the general kernel runs.
+ * Every kind computes the same transform to FP32 rounding. */
+enum { RSF_ROWS_GENERAL = 0, RSF_ROWS_GENERAL_WIDE = 1, RSF_ROWS_FIXED = 2, RSF_ROWS_RUNTIME = 3 };
+
+/* Host output: the kind of first-pass kernel the plan's transforms run on
+ * (RSF_ROWS_GENERAL: planned stages, up to 21 complex pairs per thread;
+ * RSF_ROWS_GENERAL_WIDE: up to 32, for rows that run one workgroup per CU;
+ * RSF_ROWS_FIXED, RSF_ROWS_RUNTIME: see above). */
+int rsf_plan_first_pass(const rsf_plan* plan, int32_t* kind);
+
 /* Workspace bytes for an entry point (RSF_ENTRY_*) with the given numbers of
  * sky positions, spindowns (or candidates for POINT/BACKWARD) and mode. */
 int rsf_workspace_size(const rsf_plan* plan, int entry, int64_t n_sky, int64_t n_fdot, int mode,

@@ -15,9 +15,10 @@ RSF_MODE_PLAIN, RSF_MODE_BATCHED = 0, 1
 RSF_ENTRY_RESAMPLE, RSF_ENTRY_FSTAT, RSF_ENTRY_POINT, RSF_ENTRY_BACKWARD, RSF_ENTRY_TOPK = 0, 1, 2, 3, 4
 RSF_ENTRY_SEMICOHERENT = 5
 RSF_FLAG_DEGENERATE, RSF_FLAG_WINDOW, RSF_FLAG_ORBIT = 1, 2, 4
+RSF_ROWS_GENERAL, RSF_ROWS_GENERAL_WIDE, RSF_ROWS_FIXED, RSF_ROWS_RUNTIME = 0, 1, 2, 3
 
 EXPORTS = [
-    "rsf_plan_create", "rsf_plan_destroy", "rsf_plan_query", "rsf_plan_set_batching", "rsf_plan_batching", "rsf_fft_factor",
+    "rsf_plan_create", "rsf_plan_destroy", "rsf_plan_query", "rsf_plan_first_pass", "rsf_plan_set_batching", "rsf_plan_batching", "rsf_fft_factor",
     "rsf_plan_set_spin_order", "rsf_plan_set_binary",
     "rsf_workspace_size",
     "rsf_resample", "rsf_fstat", "rsf_fstat_topk", "rsf_fstat_semicoherent", "rsf_fstat_point",
@@ -97,6 +98,7 @@ def load(path=None):
     lib.rsf_plan_destroy.argtypes = [vp]
     lib.rsf_plan_query.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64),
                                    C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double)]
+    lib.rsf_plan_first_pass.argtypes = [vp, C.POINTER(C.c_int32)]
     lib.rsf_plan_set_batching.argtypes = [vp, i32, i32]
     lib.rsf_plan_set_spin_order.argtypes = [vp, i32]
     lib.rsf_plan_set_binary.argtypes = [vp, i32]

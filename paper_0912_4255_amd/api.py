@@ -65,6 +65,13 @@ class Plan:
         self.spin_order = 1
         self.binary = False
 
+    @property
+    def first_pass(self):
+        """rsf_plan_first_pass: RSF_ROWS_GENERAL, _GENERAL_WIDE, _FIXED or _RUNTIME."""
+        k = C.c_int32()
+        L.check(self.lib.rsf_plan_first_pass(self._p, C.byref(k)))
+        return k.value
+
     def set_batching(self, fb=0, templates=0):
         """rsf_plan_set_batching: spindowns sharing a first-pass row, templates per launch."""
         L.check(self.lib.rsf_plan_set_batching(self._p, fb, templates))

@@ -20,7 +20,11 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librsfstat.so")
 
-SOURCES = ["rsf_abi.cpp", "rsf_resample.hip", "rsf_fft.hip", "rsf_point.hip", "rsf_topk.hip", "rsf_sft.hip", "rsf_semico.hip", "rsf_hetdec.hip"]
+SOURCES = ["rsf_abi.cpp", "rsf_rtc.cpp", "rsf_resample.hip", "rsf_fft.hip", "rsf_point.hip", "rsf_topk.hip", "rsf_sft.hip",
+           "rsf_semico.hip", "rsf_hetdec.hip"]
+# the headers a first-pass row plan compiled at run time is built from (their
+# hash is recorded in the library, which compiles only from matching ones)
+ROW_HEADERS = ["rsf_pass_a.h", "rsf_device.h", "rsf_spill.h", "rsf_params.h"]
 
 ARCH = os.environ.get("RSF_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
@@ -30,6 +34,16 @@ FLAGS = [
     "-Wno-unused-command-line-argument",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
+
+
+def row_src_hash():
+    """FNV-1a (64 bit) over the run-time row-plan headers, in ROW_HEADERS order."""
+    h = 1469598103934665603
+    for name in ROW_HEADERS:
+        with open(os.path.join(CSRC, name), "rb") as f:
+            for b in f.read():
+                h = ((h ^ b) * 1099511628211) & 0xFFFFFFFFFFFFFFFF
+    return h
 
 
 def hipcc():
@@ -62,7 +76,8 @@ def san_runtime():
 def _compile(src, sanitize=False):
     out = SAN_BUILD if sanitize else BUILD
     obj = os.path.join(out, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc(), *FLAGS, *(SAN_FLAGS if sanitize else []), "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+    defs = [f"-DRSF_ROW_SRC_HASH={row_src_hash():#x}ull", f'-DRSF_OFFLOAD_ARCH="{ARCH}"']
+    cmd = [hipcc(), *FLAGS, *defs, *(SAN_FLAGS if sanitize else []), "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {src}\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
@@ -81,7 +96,7 @@ def build(jobs=None, verbose=False, sanitize=False):
     # the sanitized library leaves the runtime's symbols to the preloaded ASan runtime
     link_san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
                 "-shared-libsan"] if sanitize else []
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *link_san, *objs, "-o", tmp]
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *link_san, *objs, "-lhiprtc", "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

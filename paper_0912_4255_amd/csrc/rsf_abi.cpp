@@ -245,6 +245,7 @@ struct rsf_plan {
     int fb_override;     // spindowns sharing a row in the first pass (0 = automatic)
     int g_override;      // templates per FFT launch (0 = automatic)
     FftStages stA, stB;
+    void* rowA_fn[2];    // run-time compiled RowPlan kernels of stA for spin_order (or null)
     float2* twA;
     float2* twA_hi;
     float2* twB;
@@ -294,6 +295,23 @@ int64_t batch_skies(int64_t n_sky, int64_t n_fdot, int64_t G, int mode) {
 hipError_t topk_merge_levels(const rsf_plan* p, hipStream_t s, const TopkItem* cand, int64_t n_cand,
                              const TopkItem* run_in, TopkItem* run_out, int k, int64_t n_fdot, void* entries,
                              TopkItem* const tmp[2], TopkGate* gate = nullptr, int64_t part_cap = 0);
+
+// The first pass of a large transform (2^19 points or more, RSF_RTC=all: any)
+// whose row plan is not compiled in runs a RowPlan kernel compiled at run
+// time for its radices, when that is available (it prunes the first stage,
+// so the rows must end below LA/2); else the general stages.
+void prepare_row_kernels(rsf_plan* p) {
+    p->rowA_fn[0] = p->rowA_fn[1] = nullptr;
+    if (2 * p->P > p->LA || p->stA.n_stages < 2 || fft_pass_a_fixed(p->stA, p->P)) return;
+    if (fft_pass_a_lds(p->LA) + (size_t)row_plan_tab_entries(p->stA) * sizeof(float2) > kLdsPerGroupMax) return;
+    const char* env = getenv("RSF_RTC");
+    if (p->n_fft < (int64_t(1) << 19) && !(env && strcmp(env, "all") == 0)) return;
+    void* fn[2];
+    if (row_plan_kernels(p->spin_order, p->stA, fn)) {
+        p->rowA_fn[0] = fn[0];
+        p->rowA_fn[1] = fn[1];
+    }
+}
 
 // The second pass selects the top-k itself (no 2F map) when it runs one
 // column per wave.
@@ -534,12 +552,13 @@ int rsf_plan_create(rsf_plan** out, const rsf_plan_desc* d) {
         delete p;
         return fail(RSF_EUNSUPPORTED, "internal: rows exceed first-pass length");
     }
-    const size_t lds_need = std::max({fft_pass_a_lds(p->LA), fft_pass_b_lds(p->LB, 64, false),
+    const size_t lds_need = std::max({fft_pass_a_plan_lds(p->stA, p->P), fft_pass_b_lds(p->LB, 64, false),
                                       fused_topk(p) ? fft_pass_b_lds(p->LB, 64, true) : (size_t)0});
     if (hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess ||
         p->n_cu <= 0)
         p->n_cu = 256;
     if (lds_need > 65536) (void)fft_set_lds_limits(lds_need);
+    prepare_row_kernels(p);
 
     // twiddle tables, built in FP64 and stored as FP32
     auto table = [](int64_t len, int64_t count, int64_t step) {
@@ -623,7 +642,10 @@ int rsf_plan_set_binary(rsf_plan* p, int on) {
 int rsf_plan_set_spin_order(rsf_plan* p, int order) {
     if (!p) return fail(RSF_EINVAL, "plan is NULL");
     if (order < 1 || order > 3) return fail(RSF_EINVAL, "spin order must be 1, 2 or 3");
-    p->spin_order = order;
+    if (p->spin_order != order) {
+        p->spin_order = order;
+        prepare_row_kernels(p);
+    }
     return RSF_OK;
 }
 
@@ -669,6 +691,15 @@ int rsf_plan_query(const rsf_plan* p, int64_t* n_fft, int64_t* bin_lo, int64_t* 
     if (l1) *l1 = p->LA;
     if (l2) *l2 = p->LB;
     if (df) *df = p->df;
+    return RSF_OK;
+}
+
+int rsf_plan_first_pass(const rsf_plan* p, int32_t* kind) {
+    if (!p || !kind) return fail(RSF_EINVAL, "plan or kind is NULL");
+    *kind = fft_pass_a_fixed(p->stA, p->P) ? RSF_ROWS_FIXED
+            : p->rowA_fn[0]                ? RSF_ROWS_RUNTIME
+            : pass_a_ept(p->LA) == kFftEPTWide ? RSF_ROWS_GENERAL_WIDE
+                                           : RSF_ROWS_GENERAL;
     return RSF_OK;
 }
 
@@ -884,7 +915,7 @@ int run_fstat(const rsf_plan* p, const rsf_segment* seg, const double* sky, int6
             A.spill_tmpl_stride = spill_stride;
             // a spill larger than the last-level cache goes out (and comes back) non-temporally
             A.nt_spill = (size_t)q.ns * q.nf * (size_t)spill_stride * sizeof(float4) > kLastLevelCacheBytes ? 1 : 0;
-            RSF_HIP(timed(p, K_PASS_A, s, [&] { return launch_fft_pass_a(A, s); }), "pass A launch");
+            RSF_HIP(timed(p, K_PASS_A, s, [&] { return launch_fft_pass_a(A, s, p->rowA_fn); }), "pass A launch");
 
             PassBArgs B{};
             B.n_fft = p->n_fft;

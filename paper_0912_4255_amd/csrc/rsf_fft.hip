@@ -20,6 +20,7 @@
 
 #include "rsf_device.h"
 #include "rsf_launch.h"
+#include "rsf_pass_a.h"
 #include "rsf_spill.h"
 #include "rsf_topk_gate.h"
 
@@ -30,272 +31,6 @@ constexpr int kNT = kFftThreads;
 constexpr int kNTB = kPassBThreads;
 constexpr int kEPT = kFftEPT;
 }  // namespace
-
-// One resampled sample of one detector, unpacked for the integrand: z~,
-// the noise-weighted beam patterns w a, w b, and the spindown coefficients
-// u_j of eq. eq4pt1 in FP64, Phi_s = 2 pi sum_j f^(j) u_j with
-// u_j = T^{j+1}/(j+1)! + t_m T^j/j!, T = t_b - t_m; they do not depend on the
-// template.  u_1 = (t_b^2 - t_m^2) / 2.
-template <int ORDER>
-struct Sample {
-    float zr, zi, wa, wb;
-    double u[ORDER];
-};
-
-template <int ORDER>
-__device__ __forceinline__ Sample<ORDER> unpack_sample(float4 m, float tmf, bool f16, double tb, float w) {
-    Sample<ORDER> r;
-    if (f16) {
-        const uint32_t bits = __float_as_uint(m.x);
-        const __half2 h = *reinterpret_cast<const __half2*>(&bits);
-        const float2 z = __half22float2(h);
-        r.zr = z.x;
-        r.zi = z.y;
-        r.wa = w * m.y;
-        r.wb = w * m.z;
-        tmf = m.w;
-    } else {
-        r.zr = m.x;
-        r.zi = m.y;
-        r.wa = w * m.z;
-        r.wb = w * m.w;
-    }
-    const double tm = (double)tmf;
-    r.u[0] = 0.5 * (tb * tb - tm * tm);
-    if constexpr (ORDER >= 2) {
-        const double T = tb - tm;
-        const double T2 = T * T;
-        r.u[1] = T2 * (T * (1.0 / 6.0) + 0.5 * tm);
-        if constexpr (ORDER >= 3) r.u[2] = T2 * T * (T * (1.0 / 24.0) + tm * (1.0 / 6.0));
-    }
-    return r;
-}
-
-// Spindown parameters (f^(1) .. f^(ORDER)) of one template.
-template <int ORDER>
-struct Spin {
-    double f[ORDER];
-};
-
-// y += (w a, w b) z~ exp(-i Phi_s) for one detector (eqs. eq19, eq20).
-template <int ORDER>
-__device__ __forceinline__ void accumulate_integrand(cp& y, const Sample<ORDER>& p, const Spin<ORDER>& sp) {
-    double cyc = sp.f[0] * p.u[0];
-#pragma unroll
-    for (int j = 1; j < ORDER; ++j) cyc = fma(sp.f[j], p.u[j], cyc);
-    // reduced to [-1/2, 1/2] cycle; v_sin_f32 / v_cos_f32 take revolutions
-    const float ph = (float)(cyc - rint(cyc));
-    const float s = __builtin_amdgcn_sinf(ph);
-    const float c = __builtin_amdgcn_cosf(ph);
-    const float er = p.zr * c + p.zi * s;  // z exp(-i Phi_s)
-    const float ei = p.zi * c - p.zr * s;
-    y.x += p.wa * er;
-    y.y += p.wa * ei;
-    y.z += p.wb * er;
-    y.w += p.wb * ei;
-}
-
-// Inputs of one row held per thread: n_a = tid + q * kNT, q < kInPer (P <= LA/2 <= 5120).
-constexpr int kInPer = (kFftMaxLen / 2 + kNT - 1) / kNT;
-
-// ---------------------------------------------------------------------------
-// First-pass rows with the radix sequence fixed at compile time (the row
-// length of the 10-day and 30-day workloads, 9000 = 10 10 10 9, with its
-// upper half zero).  Stage sizes are constants, so the butterfly index
-// arithmetic and the LDS offsets fold into the instructions, and only the
-// radices of this plan are compiled in.  The base twiddle W_{Ns R}^k of a
-// middle-stage butterfly comes from a small per-stage table in LDS, its
-// powers from complex products.
-// ---------------------------------------------------------------------------
-constexpr int kRow9000 = 1;
-constexpr int kRow9000Tab = 10 + 100;  // base twiddles of the stages Ns = 10 and Ns = 100
-
-// One middle (or first) stage of length L after Ns points, radix R; table
-// tab = W_{Ns R}^k for k < Ns (unused when Ns = 1).  HZ: the upper half of
-// the input is zero.
-template <int L, int Ns, int R, bool HZ>
-__device__ __forceinline__ void row_stage(cp* __restrict__ s, const float2* __restrict__ tab) {
-    constexpr int LR = L / R;
-    constexpr int MAXB = (LR + kNT - 1) / kNT;
-    cp v[MAXB][R];
-    const int tid = opaque_tid();
-#pragma unroll
-    for (int q = 0; q < MAXB; ++q) {
-        const int j = tid + q * kNT;
-        if (q + 1 < MAXB || j < LR) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) v[q][r] = (HZ && 2 * r >= R) ? make_float4(0.f, 0.f, 0.f, 0.f) : s[j + r * LR];
-            if constexpr (Ns > 1) {
-                const float2 w1 = tab[j % Ns];
-                float2 w = w1;
-#pragma unroll
-                for (int r = 1; r < R; ++r) {
-                    v[q][r] = cp_rot(v[q][r], w);
-                    if (r + 1 < R) w = c_mul(w, w1);
-                }
-            }
-            Dft<R>::run(v[q]);
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < MAXB; ++q) {
-        const int j = tid + q * kNT;
-        if (q + 1 < MAXB || j < LR) {
-            const int jq = j / Ns, k = j - jq * Ns;
-            cp* p = s + (jq * Ns * R + k);
-#pragma unroll
-            for (int r = 0; r < R; ++r) p[r * Ns] = v[q][r];
-        }
-    }
-    __syncthreads();
-}
-
-// The last stage (Ns R = L): butterfly j reads x[j + r Ns], rotates input r
-// by W_L^{j r} and hands its R outputs to the sink, in q order.
-template <int L, int R, typename Sink>
-__device__ __forceinline__ void row_last(const cp* __restrict__ s, const TwLds& tw, Sink& sink) {
-    constexpr int LR = L / R;
-    constexpr int MAXB = (LR + kNT - 1) / kNT;
-    const int tid = opaque_tid();
-#pragma unroll
-    for (int q = 0; q < MAXB; ++q) {
-        const int j = tid + q * kNT;
-        if (q + 1 < MAXB || j < LR) {
-            cp v[R];
-#pragma unroll
-            for (int r = 0; r < R; ++r) v[r] = s[j + r * LR];
-            bfly_dft<R, TwLds>(j, LR, 1, tw, v);
-            sink.template put<R>(q, j, 0, v);
-        }
-    }
-}
-
-// Fill the stage tables of the 9000-point row from the two-level table:
-// W_100^k (k < 10), then W_1000^k (k < 100).
-__device__ __forceinline__ void row9000_tables(float2* tab, const TwLds& tw) {
-    for (int i = threadIdx.x; i < kRow9000Tab; i += kNT) tab[i] = (i < 10) ? tw(90 * i) : tw(9 * (i - 10));
-}
-
-template <typename Sink>
-__device__ __forceinline__ void row9000_fft(cp* __restrict__ s, const float2* __restrict__ tab, const TwLds& tw,
-                                            Sink& sink) {
-    row_stage<9000, 1, 10, true>(s, nullptr);
-    row_stage<9000, 10, 10, false>(s, tab);
-    row_stage<9000, 100, 10, false>(s, tab + 10);
-    row_last<9000, 9>(s, tw, sink);
-}
-
-// The general stages planned for kFftEPTWide complex pairs per thread.
-constexpr int kPlanWide = 2;
-
-// The fixed plan a first-pass launch can take (0: the general stages).
-__host__ __device__ inline int fixed_row_plan(const FftStages& st, bool prune) {
-    return (prune && st.len == 9000 && st.n_stages == 4 && st.radix[0] == 10 && st.radix[1] == 10 &&
-            st.radix[2] == 10 && st.radix[3] == 9)
-               ? kRow9000
-               : 0;
-}
-
-// NT: the launch's spill is larger than the last-level cache (non-temporal stores)
-// PLAN: a fixed row plan (kRow9000), or the planned stages of A.st with
-// kFftEPT (0) or kFftEPTWide (kPlanWide) complex pairs per thread.
-template <int ORDER, bool NT, int PLAN>
-__global__ __launch_bounds__(kNT) void rsf_fft_pass_a_k(PassAArgs A) {
-    constexpr int EPT = PLAN == kPlanWide ? kFftEPTWide : kEPT;
-    extern __shared__ float4 lds[];
-    // stage twiddles in LDS after the row: no global load inside the stages,
-    // so the spill stores of one spindown stay in flight during the next FFT
-    float2* twl = reinterpret_cast<float2*>(lds + A.LA);
-    const int n_hi = (A.LA + 31) >> kTwLoBits;
-    for (int i = threadIdx.x; i < 32 + n_hi; i += kNT) twl[i] = (i < 32) ? A.tws_lo[i] : A.tws_hi[i - 32];
-    const TwLds tws{twl, twl + 32};
-    float2* tab = twl + 32 + n_hi;
-    if constexpr (PLAN == kRow9000) {
-        __syncthreads();  // the two-level table is complete
-        row9000_tables(tab, tws);
-    }
-    const int n_b = blockIdx.x;
-    const int gpf = (A.nf_l + A.fb - 1) / A.fb;       // spindown groups per sky
-    const int s_l = blockIdx.y / gpf;
-    const int f_lo = (blockIdx.y - s_l * gpf) * A.fb;
-    const int f_hi = min(f_lo + A.fb, A.nf_l);
-    const int tid = threadIdx.x;
-    const int64_t row = (int64_t)s_l * A.rs_sky_stride + (int64_t)n_b * A.P;
-
-    // first detector's row: all loads issued before any is used, kept
-    // (unpacked, with u) for every spindown
-    float4 m0[kInPer];
-    float tm0[kInPer];
-#pragma unroll
-    for (int q = 0; q < kInPer; ++q) {
-        const int n_a = tid + q * kNT;
-        const int64_t k = (int64_t)A.LB * n_a + n_b;
-        if (n_a < A.P && k < A.n) {
-            m0[q] = A.rs_main[0][row + n_a];
-            tm0[q] = A.f16 ? 0.f : A.rs_tm[0][row + n_a];
-        } else {
-            m0[q] = make_float4(0.f, 0.f, 0.f, 0.f);
-            tm0[q] = 0.f;
-        }
-    }
-    Sample<ORDER> p0[kInPer];
-#pragma unroll
-    for (int q = 0; q < kInPer; ++q) {
-        const int64_t k = (int64_t)A.LB * (tid + q * kNT) + n_b;
-        p0[q] = unpack_sample<ORDER>(m0[q], tm0[q], A.f16, (double)k * A.dt, (float)A.w[0]);
-    }
-    // the upper half of the row is zero padding when P <= LA/2: the pruned
-    // first stage reads only the rows below pruned_first_reach (LA/2 for an
-    // even first radix), and only those are written
-    const bool prune = 2 * A.P <= A.LA && A.st.n_stages > 1;
-    const int zlim = prune ? pruned_first_reach(A.LA, A.st.radix[0]) : A.LA;
-
-    // inter-pass twiddle W_N^{n_b k_a} for k_a = tid + q kNT: base W^{n_b tid}, step W^{n_b kNT}
-    const int64_t mb = ((int64_t)n_b * tid) % A.n_fft;
-    const int64_t ms = ((int64_t)n_b * kNT) % A.n_fft;
-    const int msk = (1 << kTwSplitBits) - 1;
-    const float2 w_base = c_mul(A.tw_hi[mb >> kTwSplitBits], A.tw_lo[mb & msk]);
-    const float2 w_step = c_mul(A.tw_hi[ms >> kTwSplitBits], A.tw_lo[ms & msk]);
-    const int r_last = A.st.n_stages ? A.st.radix[A.st.n_stages - 1] : 1;
-    const int lr = A.LA / r_last;
-    const int64_t ml = ((int64_t)n_b * lr) % A.n_fft;
-    const float2 w_lr = c_mul(A.tw_hi[ml >> kTwSplitBits], A.tw_lo[ml & msk]);
-
-    for (int f = f_lo; f < f_hi; ++f) {
-        const int t = s_l * A.nf_l + f;
-        Spin<ORDER> fd;
-#pragma unroll
-        for (int j = 0; j < ORDER; ++j) fd.f[j] = A.fdot[(int64_t)f * ORDER + j];
-#pragma unroll
-        for (int q = 0; q < kInPer; ++q) {
-            const int n_a = tid + q * kNT;
-            if (n_a < zlim) {
-                cp y = make_float4(0.f, 0.f, 0.f, 0.f);
-                const int64_t k = (int64_t)A.LB * n_a + n_b;
-                if (n_a < A.P && k < A.n) {
-                    accumulate_integrand(y, p0[q], fd);
-                    for (int X = 1; X < A.n_det; ++X)
-                        accumulate_integrand(y,
-                                             unpack_sample<ORDER>(A.rs_main[X][row + n_a],
-                                                                  A.f16 ? 0.f : A.rs_tm[X][row + n_a],
-                                                           A.f16, (double)k * A.dt, (float)A.w[X]),
-                                             fd);
-                }
-                lds[n_a] = y;
-            }
-        }
-        for (int n_a = tid + kInPer * kNT; n_a < zlim; n_a += kNT) lds[n_a] = make_float4(0.f, 0.f, 0.f, 0.f);
-        __syncthreads();
-        SpillSink<NT> sink{reinterpret_cast<char*>(A.spill + (int64_t)t * A.spill_tmpl_stride), A.LB, n_b, lr,
-                           w_base, w_step, w_lr};
-        if constexpr (PLAN == kRow9000)
-            row9000_fft(lds, tab, tws, sink);
-        else
-            lds_fft_into<kNT, EPT, 1, false>(lds, A.st, tws, Interleaved<1>{}, sink, NoMid{}, prune);
-        __syncthreads();
-    }
-}
 
 // Second pass, persistent.  Workgroup g handles the spill blocks g, g +
 // grid, ... (block = template * n_groups + group of 8 columns k_a): the
@@ -863,41 +598,96 @@ __global__ __launch_bounds__(kWaveColsThreads) void rsf_fft_pass_b_wave_k(PassBA
 
 int fft_pass_max_elems() { return kFftMaxLen < kNT * kEPT ? kFftMaxLen : kNT * kEPT; }
 
-// Bytes of LDS of a first-pass launch: the row, the two-level stage table
-// and, for a row length with a fixed plan, its stage tables.
-size_t fft_pass_a_lds(int LA) {
-    return (size_t)LA * sizeof(float4) + (32 + (LA + 31) / 32) * sizeof(float2) +
-           (LA == 9000 ? (size_t)kRow9000Tab * sizeof(float2) : 0);
+// The first-pass row plans compiled in, with their kernels
+// [spindown order - 1][non-temporal spill].
+struct FixedRow {
+    int n_stages;
+    int radix[kMaxStages];
+    int tab;  // base-twiddle table entries
+    const void* fn[3][2];
+};
+#define RSF_ROW_FN(ORD, ...)                                                 \
+    {(const void*)rsf_fft_pass_a_k<ORD, false, RowPlan<__VA_ARGS__>>,        \
+     (const void*)rsf_fft_pass_a_k<ORD, true, RowPlan<__VA_ARGS__>>}
+#define RSF_ROW(...)                                                                               \
+    {RowPlan<__VA_ARGS__>::kStages, {__VA_ARGS__}, RowPlan<__VA_ARGS__>::tab_entries(),            \
+     {RSF_ROW_FN(1, __VA_ARGS__), RSF_ROW_FN(2, __VA_ARGS__), RSF_ROW_FN(3, __VA_ARGS__)}}
+const FixedRow kFixedRows[] = {
+    RSF_ROW(10, 10, 10, 9),  // 9000: the rows of the 10-day and 30-day workloads
+#ifdef RSF_EXTRA_ROW_PLANS
+    RSF_EXTRA_ROW_PLANS
+#endif
+};
+#undef RSF_ROW
+#undef RSF_ROW_FN
+constexpr int kNumFixedRows = (int)(sizeof(kFixedRows) / sizeof(kFixedRows[0]));
+
+// The general-stage kernels [stage capacity: kFftEPT, kFftEPTWide][spindown order - 1][non-temporal spill].
+const void* const kGeneralRows[2][3][2] = {
+    {{(const void*)rsf_fft_pass_a_k<1, false, GeneralStages<kFftEPT>>, (const void*)rsf_fft_pass_a_k<1, true, GeneralStages<kFftEPT>>},
+     {(const void*)rsf_fft_pass_a_k<2, false, GeneralStages<kFftEPT>>, (const void*)rsf_fft_pass_a_k<2, true, GeneralStages<kFftEPT>>},
+     {(const void*)rsf_fft_pass_a_k<3, false, GeneralStages<kFftEPT>>, (const void*)rsf_fft_pass_a_k<3, true, GeneralStages<kFftEPT>>}},
+    {{(const void*)rsf_fft_pass_a_k<1, false, GeneralStages<kFftEPTWide>>, (const void*)rsf_fft_pass_a_k<1, true, GeneralStages<kFftEPTWide>>},
+     {(const void*)rsf_fft_pass_a_k<2, false, GeneralStages<kFftEPTWide>>, (const void*)rsf_fft_pass_a_k<2, true, GeneralStages<kFftEPTWide>>},
+     {(const void*)rsf_fft_pass_a_k<3, false, GeneralStages<kFftEPTWide>>, (const void*)rsf_fft_pass_a_k<3, true, GeneralStages<kFftEPTWide>>}}};
+
+// Bytes of LDS of a first-pass row of length LA on the general stages: the
+// row and the two-level stage table.
+size_t fft_pass_a_lds(int LA) { return (size_t)LA * sizeof(float4) + (32 + (LA + 31) / 32) * sizeof(float2); }
+
+namespace {
+// The compiled-in plan of a first-pass launch (-1: the general stages): the
+// planned radices, a pruned first stage (P <= LA/2) and the tables in LDS.
+int fixed_row_index(const FftStages& st, int64_t P) {
+    if (2 * P > st.len || st.n_stages < 2) return -1;
+    for (int i = 0; i < kNumFixedRows; ++i) {
+        const FixedRow& f = kFixedRows[i];
+        if (f.n_stages != st.n_stages) continue;
+        bool same = true;
+        for (int j = 0; j < f.n_stages; ++j) same = same && f.radix[j] == st.radix[j];
+        if (same && fft_pass_a_lds(st.len) + (size_t)f.tab * sizeof(float2) <= kLdsPerGroupMax) return i;
+    }
+    return -1;
+}
+}  // namespace
+
+bool fft_pass_a_fixed(const FftStages& st, int64_t P) { return fixed_row_index(st, P) >= 0; }
+
+int row_plan_tab_entries(const FftStages& st) {
+    int ns = st.n_stages ? st.radix[0] : 1, t = 0;
+    for (int i = 1; i + 1 < st.n_stages; ++i) {
+        t += ns;
+        ns *= st.radix[i];
+    }
+    return t;
 }
 
-hipError_t launch_fft_pass_a(const PassAArgs& a, hipStream_t s) {
-    const size_t lds = fft_pass_a_lds(a.LA);
+size_t fft_pass_a_plan_lds(const FftStages& st, int64_t P) {
+    const int i = fixed_row_index(st, P);
+    return fft_pass_a_lds(st.len) + (i >= 0 ? (size_t)kFixedRows[i].tab * sizeof(float2) : 0);
+}
+
+hipError_t launch_fft_pass_a(const PassAArgs& a, hipStream_t s, void* const* row_fn) {
+    if (a.spin_order < 1 || a.spin_order > 3 || a.st.len != a.LA) return hipErrorInvalidValue;
+    const int fi = fixed_row_index(a.st, a.P);
+    const size_t lds = fft_pass_a_plan_lds(a.st, a.P);
     const unsigned gy = (unsigned)(a.n_sky_l * ((a.nf_l + a.fb - 1) / a.fb));
     const dim3 grid((unsigned)a.LB, gy);
-    // the same pruning rule as the kernel's
-    const bool prune = 2 * a.P <= a.LA && a.st.n_stages > 1;
-    int plan = fixed_row_plan(a.st, prune);
-    if (plan == 0 && a.ept == kFftEPTWide) plan = kPlanWide;
-    else if (plan == 0 && a.ept != kFftEPT) return hipErrorInvalidValue;
-#define RSF_PASS_A(ORD, PL)                                                              \
-    if (a.nt_spill)                                                                      \
-        hipLaunchKernelGGL((rsf_fft_pass_a_k<ORD, true, PL>), grid, dim3(kNT), lds, s, a); \
-    else                                                                                 \
-        hipLaunchKernelGGL((rsf_fft_pass_a_k<ORD, false, PL>), grid, dim3(kNT), lds, s, a)
-    switch (a.spin_order * 3 + plan) {
-        case 3: RSF_PASS_A(1, 0); break;
-        case 4: RSF_PASS_A(1, kRow9000); break;
-        case 5: RSF_PASS_A(1, kPlanWide); break;
-        case 6: RSF_PASS_A(2, 0); break;
-        case 7: RSF_PASS_A(2, kRow9000); break;
-        case 8: RSF_PASS_A(2, kPlanWide); break;
-        case 9: RSF_PASS_A(3, 0); break;
-        case 10: RSF_PASS_A(3, kRow9000); break;
-        case 11: RSF_PASS_A(3, kPlanWide); break;
-        default: return hipErrorInvalidValue;
-    }
-#undef RSF_PASS_A
-    return hipGetLastError();
+    const int nt = a.nt_spill ? 1 : 0;
+    void* args[] = {const_cast<PassAArgs*>(&a)};
+    // a run-time compiled RowPlan (it prunes the first stage, like the compiled-in ones)
+    const size_t lds_row = fft_pass_a_lds(a.LA) + (size_t)row_plan_tab_entries(a.st) * sizeof(float2);
+    if (fi < 0 && row_fn && row_fn[nt] && 2 * a.P <= a.LA && a.st.n_stages > 1 && lds_row <= kLdsPerGroupMax)
+        return hipModuleLaunchKernel((hipFunction_t)row_fn[nt], grid.x, grid.y, 1, kNT, 1, 1, (unsigned)lds_row, s,
+                                     args, nullptr);
+    const void* fn;
+    if (fi >= 0)
+        fn = kFixedRows[fi].fn[a.spin_order - 1][nt];
+    else if (a.ept == kFftEPT || a.ept == kFftEPTWide)
+        fn = kGeneralRows[a.ept == kFftEPTWide ? 1 : 0][a.spin_order - 1][nt];
+    else
+        return hipErrorInvalidValue;
+    return hipLaunchKernel(fn, grid, dim3(kNT), args, lds, s);
 }
 
 // Columns of 64 E points, E = 4, 8, 12, and E = 16 when the pass feeds the
@@ -972,15 +762,7 @@ hipError_t fft_set_lds_limits(size_t bytes) {
     // undo a larger one
     static size_t granted = 0;
     if (bytes <= granted) return hipSuccess;
-    const void* fns[] = {(const void*)rsf_fft_pass_a_k<1, false, 0>,  (const void*)rsf_fft_pass_a_k<2, false, 0>,
-                         (const void*)rsf_fft_pass_a_k<3, false, 0>,  (const void*)rsf_fft_pass_a_k<1, true, 0>,
-                         (const void*)rsf_fft_pass_a_k<2, true, 0>,   (const void*)rsf_fft_pass_a_k<3, true, 0>,
-                         (const void*)rsf_fft_pass_a_k<1, false, kRow9000>, (const void*)rsf_fft_pass_a_k<2, false, kRow9000>,
-                         (const void*)rsf_fft_pass_a_k<3, false, kRow9000>, (const void*)rsf_fft_pass_a_k<1, true, kRow9000>,
-                         (const void*)rsf_fft_pass_a_k<2, true, kRow9000>,  (const void*)rsf_fft_pass_a_k<3, true, kRow9000>,
-                         (const void*)rsf_fft_pass_a_k<1, false, kPlanWide>, (const void*)rsf_fft_pass_a_k<2, false, kPlanWide>,
-                         (const void*)rsf_fft_pass_a_k<3, false, kPlanWide>, (const void*)rsf_fft_pass_a_k<1, true, kPlanWide>,
-                         (const void*)rsf_fft_pass_a_k<2, true, kPlanWide>,  (const void*)rsf_fft_pass_a_k<3, true, kPlanWide>,
+    const void* fns[] = {
                          (const void*)rsf_fft_pass_b_k<false>,        (const void*)rsf_fft_pass_b_k<true>,
                          (const void*)rsf_fft_pass_b_wave_k<4, false, false>, (const void*)rsf_fft_pass_b_wave_k<4, true, false>,
                          (const void*)rsf_fft_pass_b_wave_k<8, false, false>, (const void*)rsf_fft_pass_b_wave_k<8, true, false>,
@@ -990,10 +772,17 @@ hipError_t fft_set_lds_limits(size_t bytes) {
                          (const void*)rsf_fft_pass_b_wave_k<12, false, true>, (const void*)rsf_fft_pass_b_wave_k<12, true, true>,
                          (const void*)rsf_fft_pass_b_wave_k<16, false, true>, (const void*)rsf_fft_pass_b_wave_k<16, true, true>};
     hipError_t out = hipSuccess;
-    for (const void* f : fns) {
+    auto set = [&](const void* f) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         if (out == hipSuccess) out = e;
-    }
+    };
+    for (const void* f : fns) set(f);
+    for (const auto& c : kGeneralRows)
+        for (const auto& o : c)
+            for (const void* f : o) set(f);
+    for (const FixedRow& r : kFixedRows)
+        for (const auto& o : r.fn)
+            for (const void* f : o) set(f);
     if (out == hipSuccess) granted = bytes;
     return out;
 }

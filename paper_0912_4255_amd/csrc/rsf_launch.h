@@ -14,8 +14,17 @@ hipError_t launch_resample(const ResampleArgs& a, int n_sky, hipStream_t s);
 int resample_blocks(int LB, int64_t P);
 hipError_t launch_antenna_reduce(const ReduceArgs& r, hipStream_t s);
 
-hipError_t launch_fft_pass_a(const PassAArgs& a, hipStream_t s);
-size_t fft_pass_a_lds(int LA);
+// row_fn: a run-time compiled RowPlan kernel of a.st per non-temporal flag
+// (row_plan_kernels), used when no compiled-in plan serves the launch.
+hipError_t launch_fft_pass_a(const PassAArgs& a, hipStream_t s, void* const* row_fn = nullptr);
+bool fft_pass_a_fixed(const FftStages& st, int64_t P);  // a compiled-in row plan serves this launch
+int row_plan_tab_entries(const FftStages& st);           // base-twiddle entries of RowPlan<st.radix...>
+// The first-pass kernels RowPlan<plan.radix...> for spindown order `order`
+// (fn[0]: cached spill stores, fn[1]: non-temporal) compiled at run time and
+// loaded on the current device; false (fn null) when that is not available.
+bool row_plan_kernels(int order, const FftStages& plan, void* fn[2]);
+size_t fft_pass_a_lds(int LA);  // general stages
+size_t fft_pass_a_plan_lds(const FftStages& st, int64_t P);  // the kernel a launch of plan st with P rows takes
 hipError_t launch_fft_pass_b(const PassBArgs& b, int n_cu, hipStream_t s);
 size_t fft_pass_b_lds(int LB, int n_sky_l, bool topk);
 // E when the second pass runs one column of 64 E points per wave (E = 16 only

@@ -183,3 +183,64 @@ def test_wide_first_pass_stages(gpu_lib, n, l1):
     for i, f in enumerate((-1e-9, 2e-10)):
         ref = of.fstat_band(rss, w.detectors, f, plan.n_fft, plan.s_lo, plan.n_out)
         assert np.all(np.abs(got[i] - ref) <= twoF_tol(ref)), (l1, i)
+
+
+@pytest.mark.parametrize("n,l1,policy", [(21600, 96, synth.NFFT_TWICE), (25088, 98, synth.NFFT_TWICE),
+                                         (9262, 125, synth.NFFT_SMOOTH7), (31360, 7840, synth.NFFT_TWICE),
+                                         (38880, 9720, synth.NFFT_TWICE), (37632, 9408, synth.NFFT_TWICE)])
+def test_runtime_row_plans_against_oracle(gpu_lib, monkeypatch, n, l1, policy):
+    """Row plans compiled at plan creation (RSF_RTC=all makes them for any
+    size): 96 = 12 x 8, 98 = 14 x 7, 125 = 5^3 (odd first radix), 7840 =
+    16 x 10 x 7 x 7, 9720 = 12 x 10 x 9 x 9, 9408 = 16 x 12 x 7 x 7; at
+    spindown order 1 and, for the last two, order 2 (a second kernel made on
+    set_spin_order); full band against the oracle."""
+    import torch
+    from paper_0912_4255_amd import _lib as L
+    from paper_0912_4255_amd.api import plan_desc_from_workload
+    monkeypatch.setenv("RSF_RTC", "all")
+    w = synth.small_workload(n=n, dt=4.0, kernel=synth.KERNEL_DIRICHLET, taps=16, nfft_policy=policy)
+    xs, gaps = make_inputs(w, seed=16)
+    d = plan_desc_from_workload(w)
+    d.fft_l1 = l1
+    plan = gpu_lib.Plan(desc=d)
+    assert plan.fft_l1 == l1
+    assert plan.first_pass == L.RSF_ROWS_RUNTIME
+    print(f"\ncase: run-time row plan, L1 x L2 = {plan.fft_l1} x {plan.fft_l2}", flush=True)
+    tx, tg = to_gpu(xs, gaps)
+    sky = torch.tensor([[3.3, -0.2]], dtype=torch.float64).cuda()
+    rss = [of.resample(xs[0], gaps[0], w.segment, 3.3, -0.2, w.eph, w.detectors[0], w.kernel, w.taps)]
+    fd = torch.tensor([-6e-10], dtype=torch.float64).cuda()
+    got = plan.fstat(tx, tg, sky, fd).cpu().numpy()[0]
+    ref = of.fstat_band(rss, w.detectors, -6e-10, plan.n_fft, plan.s_lo, plan.n_out)
+    assert np.all(np.abs(got - ref) <= twoF_tol(ref)), l1
+    if l1 >= 9000:
+        plan.set_spin_order(2)
+        assert plan.first_pass == L.RSF_ROWS_RUNTIME
+        spins = np.array([[-6e-10, 3e-17]])
+        got = plan.fstat(tx, tg, sky, torch.from_numpy(spins).cuda()).cpu().numpy()[0]
+        ref = of.fstat_band(rss, w.detectors, tuple(spins[0]), plan.n_fft, plan.s_lo, plan.n_out)
+        assert np.all(np.abs(got - ref) <= twoF_tol(ref)), (l1, "order 2")
+    plan.close()
+
+
+def test_first_pass_kinds(gpu_lib, monkeypatch):
+    """The 10-day row (9000 = 10 x 10 x 10 x 9) runs the compiled-in plan; a
+    long uneven segment's row (5103 = 9^3 x 7, N_fft = 3,919,104) a plan
+    compiled at plan creation; a short transform the general stages."""
+    from paper_0912_4255_amd import _lib as L
+    monkeypatch.delenv("RSF_RTC", raising=False)
+    from paper_0912_4255_amd import autotune
+    plan, _ = autotune.tuned_plan(synth.workload_c2())
+    assert plan.fft_l1 == 9000 and plan.first_pass == L.RSF_ROWS_FIXED
+    plan.close()
+    lengths = synth.c3_segment_lengths()
+    w = synth.workload_c3_segment(lengths.index(1951200), n_sky=1)
+    from paper_0912_4255_amd.api import plan_desc_from_workload
+    d = plan_desc_from_workload(w)
+    d.fft_l1 = 5103
+    plan = gpu_lib.Plan(desc=d)
+    assert plan.first_pass == L.RSF_ROWS_RUNTIME
+    plan.close()
+    plan = gpu_lib.Plan(synth.small_workload(n=21600, dt=4.0))
+    assert plan.first_pass in (L.RSF_ROWS_GENERAL, L.RSF_ROWS_GENERAL_WIDE)
+    plan.close()
