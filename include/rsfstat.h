@@ -126,7 +126,9 @@ typedef struct rsf_segment {
  * z: complex64[n] resampled series z~(t_b^k) (eq. eq19's z(t_b^k));
  * a, b: float32[n] beam patterns at T^k; tm: float64[n] t_m,k = t_b^k - T^k;
  * mask: uint32[ceil(n/32)] bit k = nearest-sample mask m~_k;
- * abc: float64[3] unweighted A' = sum m~ a^2, B' = sum m~ b^2, C' = sum m~ a b.
+ * abc: float64[3] unweighted A' = sum m~ a^2, B' = sum m~ b^2, C' = sum m~ a b;
+ * u: float64[n] u_k = T^k / dt, the detector-grid position the series is
+ *    interpolated at (eq. eq21's inversion divided by the sampling interval).
  * Any pointer may be NULL to skip that output. */
 typedef struct rsf_resampled {
     void* z;
@@ -135,6 +137,7 @@ typedef struct rsf_resampled {
     double* tm;
     uint32_t* mask;
     double* abc;
+    double* u;
 } rsf_resampled;
 
 typedef struct rsf_topk_entry {

@@ -57,7 +57,7 @@ class Segment(C.Structure):
 
 class Resampled(C.Structure):
     _fields_ = [("z", C.c_void_p), ("a", C.c_void_p), ("b", C.c_void_p), ("tm", C.c_void_p),
-                ("mask", C.c_void_p), ("abc", C.c_void_p)]
+                ("mask", C.c_void_p), ("abc", C.c_void_p), ("u", C.c_void_p)]
 
 
 class TopkEntry(C.Structure):

@@ -165,7 +165,7 @@ class Plan:
 
     # -- entry points ----------------------------------------------------
     def resample(self, xs, gaps, sky, ws=None):
-        """rsf_resample: per detector dict(z, a, b, tm, mask, abc) of [n_sky, ...] tensors."""
+        """rsf_resample: per detector dict(z, a, b, tm, mask, abc, u) of [n_sky, ...] tensors."""
         _need_cuda(sky, torch.float64, "sky")
         n_sky = self._n_sky(sky)
         seg, keep = self.segment(xs, gaps)
@@ -178,9 +178,11 @@ class Plan:
                      b=torch.empty((n_sky, self.n), dtype=torch.float32, device=dev),
                      tm=torch.empty((n_sky, self.n), dtype=torch.float64, device=dev),
                      mask=torch.empty((n_sky, (self.n + 31) // 32), dtype=torch.int32, device=dev),
-                     abc=torch.empty((n_sky, 3), dtype=torch.float64, device=dev))
+                     abc=torch.empty((n_sky, 3), dtype=torch.float64, device=dev),
+                     u=torch.empty((n_sky, self.n), dtype=torch.float64, device=dev))
             descs[i] = L.Resampled(o["z"].data_ptr(), o["a"].data_ptr(), o["b"].data_ptr(),
-                                   o["tm"].data_ptr(), o["mask"].data_ptr(), o["abc"].data_ptr())
+                                   o["tm"].data_ptr(), o["mask"].data_ptr(), o["abc"].data_ptr(),
+                                   o["u"].data_ptr())
             outs.append(o)
         if ws is None:
             ws = self.workspace(L.RSF_ENTRY_RESAMPLE, n_sky, 1, device=dev)

@@ -760,6 +760,7 @@ int rsf_resample(const rsf_plan* p, const rsf_segment* seg, const double* sky, i
         a.out_a = out[X].a;
         a.out_b = out[X].b;
         a.out_tm = out[X].tm;
+        a.out_u = out[X].u;
         a.out_mask = out[X].mask;
         a.n_words = (p->n + 31) / 32;
         a.partials = (double*)(w + L.partials) + (size_t)X * n_sky * L.n_blocks * 3;

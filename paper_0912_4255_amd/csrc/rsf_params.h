@@ -92,6 +92,7 @@ struct ResampleArgs {
     float* out_a;
     float* out_b;
     double* out_tm;
+    double* out_u;            // T^k / dt
     uint32_t* out_mask;
     int64_t n_words;
     // FFT-layout outputs: main = {z.re, z.im, a, b} (F32) or {z as half2, a, b, tm} (F16)

@@ -270,6 +270,7 @@ __global__ __launch_bounds__(kThreads) void rsf_resample_k(ResampleArgs A) {
                 if (A.out_a) A.out_a[sky_off + k] = A.f16 ? m.y : m.z;
                 if (A.out_b) A.out_b[sky_off + k] = A.f16 ? m.z : m.w;
                 if (A.out_tm) A.out_tm[sky_off + k] = tile_tm[ia][lane];
+                if (A.out_u) A.out_u[sky_off + k] = ((double)k * A.dt - tile_tm[ia][lane]) / A.dt;
             }
         }
         if (A.out_mask && threadIdx.x < kTileA && A.LB == 64) {

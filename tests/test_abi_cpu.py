@@ -43,7 +43,7 @@ def test_struct_sizes_match_header_layout():
     # rsf_plan_desc: 6 int32 + int64 + 5 double + ephemeris (7 double) + 4 detectors (4 double)
     assert C.sizeof(L.PlanDesc) == 6 * 4 + 8 + 5 * 8 + 7 * 8 + 4 * 4 * 8
     assert C.sizeof(L.Segment) == 4 * 8 + 4 * 8 + 4 * 4
-    assert C.sizeof(L.Resampled) == 6 * 8
+    assert C.sizeof(L.Resampled) == 7 * 8
     assert C.sizeof(L.TopkEntry) == 16
     # rsf_sft_desc: 5 int64 + 6 double + 2 int32
     assert C.sizeof(L.SftDesc) == 5 * 8 + 6 * 8 + 2 * 4

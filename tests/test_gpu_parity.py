@@ -59,6 +59,7 @@ def test_resample_parity(gpu_lib, kernel, taps, n, dt):
         ref = _oracle_rs(w, xs, gaps, al, de)[0]
         o = {k: v[s].cpu().numpy() for k, v in out[0].items()}
         assert np.max(np.abs(o["tm"] - ref["tm"])) < 1e-9
+        assert np.max(np.abs(o["u"] - ref["u"])) < 1e-9 / w.segment.dt
         assert np.max(np.abs(o["a"] - ref["a"])) < 1e-6
         assert np.max(np.abs(o["b"] - ref["b"])) < 1e-6
         rms = np.sqrt(np.mean(np.abs(ref["z"]) ** 2))
