@@ -436,6 +436,8 @@ ResampleArgs base_resample_args(const rsf_plan* p, const rsf_segment* seg, int X
     a.x = (const float2*)seg->x[X];
     a.gaps = seg->gaps[X];
     a.n_gaps = seg->n_gaps[X];
+    // the same criterion as the point kernel's interpolated chain
+    a.fast_chain = (!p->binary && 63.0 * p->d.dt * 2.0 * M_PI * std::fabs(p->eph.inv_p_sid) <= 4e-3) ? 1 : 0;
     return a;
 }
 

@@ -82,6 +82,9 @@ struct ResampleArgs {
     const double* sky;        // [n_sky][sky_stride]: alpha, delta (, a_p, P_b, t_asc with a binary orbit)
     int sky_stride;           // 2, or 5 with a binary orbit
     int binary;
+    // the timing chain (inversion, beam patterns) exact at lanes 0, 32, 63 of each run
+    // of 64 outputs and quadratic between them (no orbit, 63 dt w_sid <= 4e-3)
+    int fast_chain;
     // tile geometry: k = LB * n_a + n_b, 0 <= n_b < LB, 0 <= n_a < P
     int LB;
     int64_t P;

@@ -4,7 +4,13 @@
 // k = LB * n_a + n_b (n_a = tile row, n_b = lane).  Each wave handles four
 // runs of 64 consecutive k:
 //   1. every lane inverts eq. eq21 for its k in FP64 (one fixed-point step
-//      and one Newton step, residual below 1e-12 s);
+//      and one Newton step, residual below 1e-12 s).  For sampling intervals
+//      short against a sidereal day (63 dt w_sid <= 4e-3, no orbit) the wave
+//      instead inverts only lanes 0, 32 and 63 of its four runs, all twelve
+//      at once, and every lane takes t_m, a and b from the quadratic through
+//      its run's three: t_m, a and b are sums of circular motions with rates
+//      up to 2 w_sid, so the remainder is at most 0.008 A (2 w_sid 63 dt)^3,
+//      below 2e-11 s for t_m and 1e-9 for a and b;
 //   2. the wave loads the detector-grid window its 64 outputs need into LDS,
 //      applying the heterodyne correction z = x_h exp(-2 pi i f_h t_m) on the
 //      way (eqs. absorb/Fa3; t_m at the detector samples from a third-order
@@ -60,6 +66,12 @@ __global__ __launch_bounds__(kThreads) void rsf_resample_k(ResampleArgs A) {
     __shared__ double tile_tm[kTileA][kTileB + 1];
     __shared__ uint32_t tile_mask[kTileA][2];
     __shared__ double red[4][3];
+    // interpolated timing chain: per wave and run, t_m, a, b at lanes 0, 32, 63,
+    // and lane 0's expansion point of t_m (the window's heterodyne correction)
+    constexpr int kRuns = kTileA / 4;
+    __shared__ double node_v[4][3][3 * kRuns];
+    __shared__ RoemerD node_r1[4][kRuns];
+    __shared__ double node_t1[4][kRuns];
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -86,6 +98,35 @@ __global__ __launch_bounds__(kThreads) void rsf_resample_k(ResampleArgs A) {
     const bool flat = A.ip.kernel == 1 && pin * (float)(hw + 1) < 2.9e-4f;
     double sA = 0.0, sB = 0.0, sC = 0.0;
     bool window_overflow = false;
+    const bool fast = !BIN && A.fast_chain;
+    if (fast) {
+        // node m of run m / 3 sits at lane 0, 32 or 63 of that run
+        if (lane < 3 * kRuns) {
+            const int rr = lane / 3, which = lane - 3 * rr;
+            const int64_t k = (int64_t)A.LB * (a0 + wave + 4 * rr) + b0 + (which == 0 ? 0 : which == 1 ? 32 : 63);
+            const double tb = (double)k * A.dt;
+            const Inversion inv = invert_ssb(A.t_start, tb, n0, A.eph, A.det);
+            double av = 0.0, bv = 0.0;
+            beam_ab(inv.ang, A.det, fr, &av, &bv);
+            node_v[wave][0][lane] = tb - inv.T;
+            node_v[wave][1][lane] = av;
+            node_v[wave][2][lane] = bv;
+            if (which == 0) {
+                node_r1[wave][rr] = inv.r1;
+                node_t1[wave][rr] = inv.T1;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    // value at lane l of the quadratic through (0, f0), (32, f32), (63, f63)
+    auto quad = [lane](const double* f) {
+        const double d1 = (f[1] - f[0]) * (1.0 / 32.0);
+        const double d2 = ((f[2] - f[1]) * (1.0 / 31.0) - d1) * (1.0 / 63.0);
+        const double l = (double)lane;
+        return f[0] + l * d1 + l * (l - 32.0) * d2;
+    };
 
     for (int r = 0; r < kTileA / 4; ++r) {
         const int ia = wave + 4 * r;
@@ -101,24 +142,33 @@ __global__ __launch_bounds__(kThreads) void rsf_resample_k(ResampleArgs A) {
         Inversion inv{};
         if (valid) {
             const double tb = (double)k * A.dt;
-            double target = tb;
-            if constexpr (BIN) target = tb + binary_delay(bo, A.t_start + tb);
-            inv = invert_ssb(A.t_start, target, n0, A.eph, A.det);
-            const double T = inv.T;
-            tm = tb - T;
+            double T;
+            if (fast) {
+                tm = quad(&node_v[wave][0][3 * r]);
+                av = quad(&node_v[wave][1][3 * r]);
+                bv = quad(&node_v[wave][2][3 * r]);
+                T = tb - tm;
+            } else {
+                double target = tb;
+                if constexpr (BIN) target = tb + binary_delay(bo, A.t_start + tb);
+                inv = invert_ssb(A.t_start, target, n0, A.eph, A.det);
+                T = inv.T;
+                tm = tb - T;
+                beam_ab(inv.ang, A.det, fr, &av, &bv);
+            }
             const double u = T / A.dt;
             const double fl = floor(u);
             j = (int)fl;
             frac = (float)(u - fl);
-            beam_ab(inv.ang, A.det, fr, &av, &bv);
             const int64_t jn = (int64_t)floor(u + 0.5);
             mk = (jn >= 0) && (jn < A.n) && !in_gap(A.gaps, A.n_gaps, jn);
         }
         // expansion point of t_m for this run's window: the first valid lane
+        // (lane 0 whenever any lane is valid: it has the run's smallest k)
         const uint64_t vmask = __ballot(valid);
         const int src = vmask ? __ffsll((long long)vmask) - 1 : 0;
-        const RoemerD rref = readlane_rd(inv.r1, src);
-        const double t_ref = readlane_d(inv.T1, src);
+        const RoemerD rref = fast ? node_r1[wave][r] : readlane_rd(inv.r1, src);
+        const double t_ref = fast ? node_t1[wave][r] : readlane_d(inv.T1, src);
 
         // window of detector samples needed by this run
         int jmin = valid ? j : INT_MAX;
