@@ -215,7 +215,9 @@ int rsf_plan_query(const rsf_plan* plan, int64_t* n_fft, int64_t* bin_lo, int64_
  * $RSF_KERNEL_CACHE, else $XDG_CACHE_HOME/rsfstat or ~/.cache/rsfstat).
  * Run-time kernels are made for transforms of 2^19 points or more
  * (RSF_RTC=all: any size; RSF_RTC=0: never) whose rows end below L1/2 (the
- * pruned first stage); when that is not possible the general kernel runs.
+ * pruned first stage); when that is not possible the general kernel runs
+ * (RSF_RTC_VERBOSE=1 prints the compiler's log of a failed compile).  A
+ * cached code object that does not load is compiled again.
  * Every kind computes the same transform to FP32 rounding. */
 enum { RSF_ROWS_GENERAL = 0, RSF_ROWS_GENERAL_WIDE = 1, RSF_ROWS_FIXED = 2, RSF_ROWS_RUNTIME = 3 };
 

@@ -150,6 +150,14 @@ bool compile(const RtcState& st, const std::string exprs[2], std::string names[2
                           // no packed FP32 instructions, as in the library's own device code
                           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
     ok = ok && hiprtcCompileProgram(prog, (int)(sizeof(opts) / sizeof(opts[0])), opts) == HIPRTC_SUCCESS;
+    if (!ok && getenv("RSF_RTC_VERBOSE")) {
+        size_t log_n = 0;
+        if (hiprtcGetProgramLogSize(prog, &log_n) == HIPRTC_SUCCESS && log_n > 1) {
+            std::string log(log_n, '\0');
+            if (hiprtcGetProgramLog(prog, &log[0]) == HIPRTC_SUCCESS)
+                fprintf(stderr, "rsfstat: row plan %s not compiled:\n%s\n", exprs[0].c_str(), log.c_str());
+        }
+    }
     size_t n = 0;
     ok = ok && hiprtcGetCodeSize(prog, &n) == HIPRTC_SUCCESS && n > 0;
     if (ok) {
@@ -196,22 +204,29 @@ bool row_plan_kernels(int order, const FftStages& plan, void* fn[2]) {
         snprintf(hex, sizeof hex, "%016llx",
                  (unsigned long long)fnv1a(exprs[0] + "|" + RSF_OFFLOAD_ARCH, st.src_hash));
         const std::string path = st.cache + "/row_" + hex + ".co";
+        // a cached code object first; one that does not load (truncated,
+        // another toolchain's) is replaced by a fresh compile
+        auto load = [&](const std::string names[2], const std::string& code) {
+            hipModule_t mod = nullptr;
+            hipFunction_t f0 = nullptr, f1 = nullptr;
+            if (hipModuleLoadData(&mod, code.data()) != hipSuccess) return false;
+            if (hipModuleGetFunction(&f0, mod, names[0].c_str()) != hipSuccess ||
+                hipModuleGetFunction(&f1, mod, names[1].c_str()) != hipSuccess) {
+                (void)hipModuleUnload(mod);
+                return false;
+            }
+            e.mod = mod;
+            e.fn[0] = f0;
+            e.fn[1] = f1;
+            return true;
+        };
         std::string names[2], code;
-        if (!cache_read(path, names, &code)) {
-            if (!compile(st, exprs, names, &code)) return false;
+        const bool cached = cache_read(path, names, &code);
+        if (!cached || !load(names, code)) {
+            if (cached) (void)unlink(path.c_str());
+            if (!compile(st, exprs, names, &code) || !load(names, code)) return false;
             cache_write(st.cache, path, names, code);
         }
-        hipModule_t mod = nullptr;
-        hipFunction_t f0 = nullptr, f1 = nullptr;
-        if (hipModuleLoadData(&mod, code.data()) != hipSuccess) return false;
-        if (hipModuleGetFunction(&f0, mod, names[0].c_str()) != hipSuccess ||
-            hipModuleGetFunction(&f1, mod, names[1].c_str()) != hipSuccess) {
-            (void)hipModuleUnload(mod);
-            return false;
-        }
-        e.mod = mod;
-        e.fn[0] = f0;
-        e.fn[1] = f1;
     }
     if (!e.mod) return false;
     fn[0] = (void*)e.fn[0];
