@@ -16,7 +16,7 @@ def pytest_configure(config):
 @pytest.fixture(scope="session")
 def gpu_lib():
     """The HIP library through its Python binding; the test is an error, not a
-    skip, when the library is missing on a GPU machine."""
+    skip, when the library is missing on a machine with a GPU."""
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
