@@ -451,7 +451,11 @@ int rsf_sft_plan_query(const rsf_sft_plan* plan, int64_t* n_chunks, int64_t* gap
                        int64_t* n_gaps);
 int rsf_sft_workspace_size(const rsf_sft_plan* plan, size_t* bytes);
 /* sft: complex64 [n_sft][n_bins] (device, read only); x_h: complex64 [n_out]
- * (device, overwritten, gaps zero).  Asynchronous on `stream`. */
+ * (device, overwritten, gaps zero).  Asynchronous on `stream`.  The DFT over
+ * a chunk's SFTs and the Dirichlet merge run as one kernel with the DFT rows
+ * in LDS when every chunk fits 64 KiB of it (chunks up to several hundred
+ * SFTs), else as two with the DFT tables in the workspace; RSF_SFT_FUSED=0
+ * forces the second form. */
 int rsf_sft_heterodyne(const rsf_sft_plan* plan, const float* sft, float* x_h, void* ws, size_t ws_bytes,
                        void* stream);
 /* Kernel timing of the plan's launches, as rsf_profile_enable/read. */

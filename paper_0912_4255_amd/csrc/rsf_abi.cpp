@@ -198,11 +198,11 @@ struct Profiler {
     };
     std::vector<Rec> pending;
     std::vector<hipEvent_t> pool;
-    static constexpr int kKinds = 14;
+    static constexpr int kKinds = 15;
     const char* names[kKinds] = {"rsf_resample_k", "rsf_antenna_reduce_k", "rsf_fft_pass_a_k", "rsf_fft_pass_b_k",
                                  "rsf_point_k",    "rsf_point_reduce_k",   "rsf_topk_k",       "rsf_sft_norm_k",
                                  "rsf_sft_merge_k", "rsf_sft_rows_k",      "rsf_sft_cols_k",   "rsf_semico_k",
-                                 "rsf_hetdec_k",   "rsf_sft_dft_k"};
+                                 "rsf_hetdec_k",   "rsf_sft_dft_k",        "rsf_sft_dftmerge_k"};
     int64_t launches[kKinds] = {};
     double ms[kKinds] = {};
 
@@ -226,7 +226,8 @@ struct Profiler {
 };
 enum {
     K_RESAMPLE = 0, K_REDUCE = 1, K_PASS_A = 2, K_PASS_B = 3, K_POINT = 4, K_POINT_REDUCE = 5, K_TOPK = 6,
-    K_SFT_NORM = 7, K_SFT_MERGE = 8, K_SFT_ROWS = 9, K_SFT_COLS = 10, K_SEMICO = 11, K_HETDEC = 12, K_SFT_DFT = 13
+    K_SFT_NORM = 7, K_SFT_MERGE = 8, K_SFT_ROWS = 9, K_SFT_COLS = 10, K_SEMICO = 11, K_HETDEC = 12, K_SFT_DFT = 13,
+    K_SFT_DFTMERGE = 14
 };
 }  // namespace
 
@@ -1451,6 +1452,8 @@ struct rsf_sft_plan {
     int64_t y_total;                      // band bins of all chunks
     size_t spill_total;                   // float4 elements of all spills
     int64_t merge_blocks, dft_blocks;     // workgroups of the merge and DFT launches
+    int64_t fused_blocks;                 // workgroups of the fused DFT and merge launch
+    size_t fused_lds;                     // its LDS; 0: the DFT tables go through HBM instead
     int64_t dft_total;                    // elements of all chunks' DFT tables
     size_t dft_lds, lds_max;
     SftChunkDev* chunks_dev;              // device table
@@ -1543,6 +1546,8 @@ int rsf_sft_plan_create(rsf_sft_plan** out, const rsf_sft_desc* d, const double*
     p->spill_total = 0;
     p->merge_blocks = 0;
     p->dft_blocks = 0;
+    p->fused_blocks = 0;
+    p->fused_lds = 0;
     p->dft_total = 0;
     p->dft_lds = 0;
     p->lds_max = 0;
@@ -1691,6 +1696,7 @@ int rsf_sft_plan_create(rsf_sft_plan** out, const rsf_sft_desc* d, const double*
         t.blk0 = p->merge_blocks;
         t.dft_off = p->dft_total;
         t.dft_blk0 = p->dft_blocks;
+        t.fblk0 = p->fused_blocks;
         t.scale = (float)(1.0 / std::sqrt((double)x.n * (double)c.M));
         t.corr = c.corr;
         p->y_total += x.n;
@@ -1698,6 +1704,8 @@ int rsf_sft_plan_create(rsf_sft_plan** out, const rsf_sft_desc* d, const double*
         p->merge_blocks += sft_merge_blocks((int)x.n);
         p->dft_total += (int64_t)d->n_bins * c.Mp;
         p->dft_blocks += sft_dft_blocks((int64_t)d->n_bins * c.Mp);
+        p->fused_blocks += sft_fused_blocks((int)x.n);
+        p->fused_lds = std::max(p->fused_lds, sft_fused_lds(c.M, c.Mp, d->dk));
     }
     std::vector<int> ids;
     for (const auto& g : p->group) {
@@ -1726,8 +1734,9 @@ int rsf_sft_plan_create(rsf_sft_plan** out, const rsf_sft_desc* d, const double*
         l.t2_hi = x.t2_hi;
         l.tw_lo = x.tw_lo;
         l.tw_hi = x.tw_hi;
-        p->rows_blocks += (int64_t)((x.L2 + p->rows_R - 1) / p->rows_R) * l.nc;
-        p->cols_blocks += (int64_t)x.n_groups * l.nc;
+        // chunks of one length go through both passes in pairs
+        p->rows_blocks += (int64_t)((x.L2 + p->rows_R - 1) / p->rows_R) * ((l.nc + 1) / 2);
+        p->cols_blocks += (int64_t)x.n_groups * ((l.nc + 1) / 2);
         p->rows_lds = std::max(p->rows_lds, sft_rows_lds(x.L1, p->rows_R));
         p->cols_lds = std::max(p->cols_lds, sft_cols_lds(x.L2, p->cols_C));
     }
@@ -1795,15 +1804,8 @@ int rsf_sft_heterodyne(const rsf_sft_plan* p, const float* sft, float* x_h, void
     float2* y = reinterpret_cast<float2*>(w + L.y);
     float4* spill = reinterpret_cast<float4*>(w + L.spill);
     float2* Y = reinterpret_cast<float2*>(w + L.dft);
-    SftDftArgs f{};
-    f.xh = xh;
-    f.K = (int)d.n_bins;
-    f.chunks = p->chunks_dev;
-    f.n_chunks = (int)p->chunks.size();
-    f.Y = Y;
-    RSF_HIP(timed_pr(p->prof, K_SFT_DFT, s, [&] { return launch_sft_dft(f, p->dft_blocks, p->dft_lds, s); }),
-            "sft dft launch");
     SftMergeArgs m{};
+    m.xh = xh;
     m.Y = Y;
     m.K = (int)d.n_bins;
     m.k_lo = d.k_lo;
@@ -1812,8 +1814,24 @@ int rsf_sft_heterodyne(const rsf_sft_plan* p, const float* sft, float* x_h, void
     m.chunks = p->chunks_dev;
     m.n_chunks = (int)p->chunks.size();
     m.y = y;
-    RSF_HIP(timed_pr(p->prof, K_SFT_MERGE, s, [&] { return launch_sft_merge(m, p->merge_blocks, s); }),
-            "sft merge launch");
+    const char* fused_env = getenv("RSF_SFT_FUSED");
+    if (p->fused_lds > 0 && p->fused_lds <= 65536 && !(fused_env && fused_env[0] == '0')) {
+        // the DFT rows each workgroup's bins reach are formed in its LDS
+        RSF_HIP(timed_pr(p->prof, K_SFT_DFTMERGE, s,
+                         [&] { return launch_sft_dftmerge(m, p->fused_blocks, p->fused_lds, s); }),
+                "sft dft and merge launch");
+    } else {
+        SftDftArgs f{};
+        f.xh = xh;
+        f.K = (int)d.n_bins;
+        f.chunks = p->chunks_dev;
+        f.n_chunks = (int)p->chunks.size();
+        f.Y = Y;
+        RSF_HIP(timed_pr(p->prof, K_SFT_DFT, s, [&] { return launch_sft_dft(f, p->dft_blocks, p->dft_lds, s); }),
+                "sft dft launch");
+        RSF_HIP(timed_pr(p->prof, K_SFT_MERGE, s, [&] { return launch_sft_merge(m, p->merge_blocks, s); }),
+                "sft merge launch");
+    }
     SftRowsArgs r{};
     r.lens = p->lens_dev;
     r.n_lens = (int)p->xf.size();

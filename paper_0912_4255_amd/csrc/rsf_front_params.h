@@ -44,6 +44,7 @@ struct SftChunkDev {
     int64_t blk0;         // first merge workgroup of the chunk
     int64_t dft_off;      // first element of its table Y[K][M'] in the DFT buffer
     int64_t dft_blk0;     // first workgroup of the chunk in the DFT launch
+    int64_t fblk0;        // first workgroup of the chunk in the fused DFT and merge launch
     float scale;          // 1 / sqrt(n M)
     float2 corr;          // exp(-2 pi i f_h (t_c - t_s))
 };
@@ -66,7 +67,8 @@ struct SftDftArgs {
 // conjugates), at y[y_off + m].  With b = k* M' + r, the sum over SFTs and
 // Dirichlet terms is taken as sum_d P_d(r) Y[k* + d][r].
 struct SftMergeArgs {
-    const float2* Y;      // the DFT tables of SftDftArgs
+    const float2* xh;     // normalised SFT bands [n_sft][K] (the fused DFT and merge)
+    const float2* Y;      // the DFT tables of SftDftArgs (the separate merge)
     int K;
     int64_t k_lo;
     int dk;
@@ -77,12 +79,13 @@ struct SftMergeArgs {
 };
 
 // One chunk transform length n = LA LB of the SFT front end.  Its chunks are
-// ids[id0 .. id0 + nc).  With R rows and C columns per workgroup (the same for
-// every length of a plan), its workgroups in the single rows launch are
-// rows_blk0 + i ceil(LB / R) + g (rows g R .. g R + R - 1 of its i-th chunk),
-// in the single columns launch cols_blk0 + i n_groups + g (columns
-// g C .. g C + C - 1, n_groups = ceil(LA / C)); st1 and st2 are planned for R
-// and C interleaved transforms.
+// ids[id0 .. id0 + nc), transformed in pairs (chunks 2i and 2i + 1 as the two
+// complex halves of each float4; the last alone when nc is odd).  With R rows
+// and C columns per workgroup (the same for every length of a plan), its
+// workgroups in the single rows launch are rows_blk0 + i ceil(LB / R) + g
+// (rows g R .. g R + R - 1 of its i-th pair), in the single columns launch
+// cols_blk0 + i n_groups + g (columns g C .. g C + C - 1, n_groups =
+// ceil(LA / C)); st1 and st2 are planned for R and C interleaved transforms.
 struct SftLenDev {
     int64_t n;
     int LA, LB, n_groups, nc, id0;

@@ -53,6 +53,9 @@ size_t sft_dft_lds(int Mp);
 hipError_t launch_sft_dft(const SftDftArgs& a, int64_t blocks, size_t lds, hipStream_t s);
 int64_t sft_merge_blocks(int n);  // merge workgroups of a chunk of n bins
 hipError_t launch_sft_merge(const SftMergeArgs& a, int64_t blocks, hipStream_t s);
+int64_t sft_fused_blocks(int n);         // fused DFT and merge workgroups of a chunk of n bins
+size_t sft_fused_lds(int M, int Mp, int dk);  // their LDS for a chunk of M SFTs on a grid of M', dk terms per side
+hipError_t launch_sft_dftmerge(const SftMergeArgs& a, int64_t blocks, size_t lds, hipStream_t s);
 size_t sft_rows_lds(int LA, int R);  // R rows of LA points per workgroup
 size_t sft_cols_lds(int LB, int C);  // C columns of LB points per workgroup
 hipError_t launch_sft_rows(const SftRowsArgs& a, int64_t blocks, size_t lds, int R, hipStream_t s);  // R in {1, 2, 4, 8}

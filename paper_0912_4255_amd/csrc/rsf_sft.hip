@@ -301,6 +301,104 @@ __global__ __launch_bounds__(kMergeThreads) void rsf_sft_merge_k(SftMergeArgs a)
     a.y[c.y_off + m] = make_float2(acc.x * g, -acc.y * g);
 }
 
+// The DFT over the SFTs and the merge in one pass, without the tables in
+// HBM: workgroup g of a chunk takes its band bins u in [1024 g, 1024 g +
+// 1024).  The stored bins k those bins reach (k* of the first and last bin,
+// +- dk) come into LDS for every SFT of the chunk in one coalesced load; the
+// rows Y[k][.] are formed there and merged as in rsf_sft_merge_k.  The
+// phases W^{r alpha} are running products of W^r, the terms' sines come from
+// the hardware sine (argument in revolutions) and their reciprocals from
+// v_rcp_f32 (each within a few 1e-7 relative).  Chosen when every chunk fits
+// the LDS (sft_fused_lds).
+namespace {
+constexpr int kFuseBins = 1024;
+}
+
+__global__ __launch_bounds__(kMergeThreads) void rsf_sft_dftmerge_k(SftMergeArgs a) {
+    extern __shared__ float2 sh[];
+    const SftChunkDev c = a.chunks[sft_chunk_of<&SftChunkDev::fblk0>(a.chunks, a.n_chunks, blockIdx.x)];
+    const int n = c.n, Mp = c.Mp, M = c.M;
+    const int u0 = (int)((int64_t)blockIdx.x - c.fblk0) * kFuseBins;
+    const int u1 = min(u0 + kFuseBins, n);
+    const int64_t ks_first = (c.b0 - n / 2 + u0) / Mp;
+    const int64_t ks_last = (c.b0 - n / 2 + u1 - 1) / Mp;
+    const int64_t k_min = max(ks_first - a.dk, a.k_lo);
+    const int64_t k_max = min(ks_last + a.dk, a.k_lo + a.K - 1);
+    const int rows = k_max >= k_min ? (int)(k_max - k_min + 1) : 0;
+    float2* roots = sh;                // M'
+    float2* Xt = roots + Mp;           // [M][rows]: X^_{a0 + alpha, k_min + kr}
+    float2* Yt = Xt + M * rows;        // [rows][M']
+    for (int i = threadIdx.x; i < Mp; i += kMergeThreads) {
+        float s, co;
+        sincospif(2.0f * (float)i / (float)Mp, &s, &co);
+        roots[i] = make_float2(co, -s);
+    }
+    const float2* xk = a.xh + (int64_t)c.a0 * a.K + (k_min - a.k_lo);
+    for (int i = threadIdx.x; i < M * rows; i += kMergeThreads) {
+        const int al = i / rows;
+        Xt[i] = xk[(int64_t)al * a.K + (i - al * rows)];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < rows * Mp; e += kMergeThreads) {
+        const int kr = e / Mp;
+        const int r = e - kr * Mp;
+        // W_{M'}^{r alpha} by repeated products of W_{M'}^r (M <= M' factors,
+        // a few ulp each): the threads of one k read the same X^ (one LDS
+        // broadcast) and no table
+        const float2 step = roots[r];
+        float2 w = make_float2(1.f, 0.f);
+        float2 acc = make_float2(0.f, 0.f);
+        for (int al = 0; al < M; ++al) {
+            const float2 v = Xt[al * rows + kr];
+            acc.x += v.x * w.x - v.y * w.y;
+            acc.y += v.x * w.y + v.y * w.x;
+            w = make_float2(w.x * step.x - w.y * step.y, w.x * step.y + w.y * step.x);
+        }
+        Yt[e] = acc;
+    }
+    __syncthreads();
+    const float inv_mp = 1.0f / (float)Mp;
+    for (int u = u0 + (int)threadIdx.x; u < u1; u += kMergeThreads) {
+        const int64_t b = c.b0 - n / 2 + u;
+        const int64_t ks = b / Mp;
+        const int r = (int)(b - ks * Mp);
+        const float fr = (float)r * inv_mp;                // r / M' in [0, 1)
+        const float sy = __builtin_amdgcn_sinf(fr);        // sin(2 pi r / M')
+        const float sh2 = __builtin_amdgcn_sinf(0.5f * fr);  // sin(pi r / M')
+        const float omc = 2.0f * sh2 * sh2;                // 1 - cos y
+        const int d_lo = (int)max((int64_t)-a.dk, a.k_lo - ks);
+        const int d_hi = (int)min((int64_t)a.dk, a.k_lo + a.K - 1 - ks);
+        float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int t = 0; t < kSftMaxTerms; ++t) {
+            const int d = t - a.dk;
+            if (d >= d_lo && d <= d_hi) {
+                float2 P;
+                if (r == 0) {
+                    P = make_float2(d == 0 ? 1.f : 0.f, 0.f);
+                } else {
+                    const float inv = __builtin_amdgcn_rcpf(6.28318530717958648f * (fr - (float)d));
+                    P = make_float2(sy * inv, -omc * inv);
+                }
+                const float2 v = Yt[(ks + d - k_min) * Mp + r];
+                acc.x += v.x * P.x - v.y * P.y;
+                acc.y += v.x * P.y + v.y * P.x;
+            }
+        }
+        float wgt = 1.0f;
+        if (a.taper > 0.f) {
+            const float x = ((float)u + 0.5f) / (float)n;
+            const float e = 0.5f * a.taper;
+            if (x < e) wgt = 0.5f * (1.0f - cospif(x / e));
+            else if (x > 1.0f - e) wgt = 0.5f * (1.0f - cospif((1.0f - x) / e));
+        }
+        const float g = wgt * c.scale;
+        const int q = u - n / 2;
+        const int m = q < 0 ? q + n : q;
+        a.y[c.y_off + m] = make_float2(acc.x * g, -acc.y * g);
+    }
+}
+
 // The length whose first workgroup (at member BLK0) is the last one not
 // after workgroup w.
 template <int64_t SftLenDev::*BLK0>
@@ -339,11 +437,13 @@ struct SftSpillSink {
     }
 };
 
-// Rows pass: workgroup w gathers RB consecutive rows n_b of its chunk's band
-// bins (elements m = LB n_a + n_b, the RB rows adjacent in memory), transforms
-// them over n_a as RB interleaved columns and spills them with the inter-pass
-// twiddle W_n^{n_b k_a}.  Thread tid always holds row tid mod RB (kNT is a
-// multiple of RB), so its twiddle recurrences run for one n_b.
+// Rows pass: workgroup w gathers RB consecutive rows n_b of its chunk pair's
+// band bins (elements m = LB n_a + n_b, the RB rows adjacent in memory; the
+// first chunk's in the low complex half of each float4, the second's in the
+// high half), transforms them over n_a as RB interleaved columns and spills
+// them with the inter-pass twiddle W_n^{n_b k_a} into the first chunk's
+// spill.  Thread tid always holds row tid mod RB (kNT is a multiple of RB), so
+// its twiddle recurrences run for one n_b.
 template <int RB>
 __global__ __launch_bounds__(kNT) void rsf_sft_rows_k(SftRowsArgs A) {
     extern __shared__ float4 lds[];
@@ -359,13 +459,18 @@ __global__ __launch_bounds__(kNT) void rsf_sft_rows_k(SftRowsArgs A) {
     const int n_hi = (LA + 31) >> kTwLoBits;
     for (int e = threadIdx.x; e < 32 + n_hi; e += kNT) twl[e] = (e < 32) ? L.t1[e] : L.t1_hi[e - 32];
     const TwLds tws{twl, twl + 32};
-    const SftChunkDev& c = A.chunks[A.ids[L.id0 + i]];
-    const int tid = threadIdx.x;
+    const SftChunkDev& c = A.chunks[A.ids[L.id0 + 2 * i]];
+    const bool pair = 2 * i + 1 < L.nc;
     const float2* src = A.y + c.y_off;
+    const float2* src2 = A.y + (pair ? A.chunks[A.ids[L.id0 + 2 * i + 1]].y_off : c.y_off);
+    const int tid = threadIdx.x;
     for (int e = tid; e < LA * RB; e += kNT) {
         const int n_a = e / RB, b = e - n_a * RB;
-        const float2 v = (nb0 + b < LB) ? src[(int64_t)LB * n_a + nb0 + b] : make_float2(0.f, 0.f);
-        lds[e] = make_float4(v.x, v.y, 0.f, 0.f);
+        const bool in = nb0 + b < LB;
+        const int64_t m = (int64_t)LB * n_a + nb0 + b;
+        const float2 v = in ? src[m] : make_float2(0.f, 0.f);
+        const float2 v2 = in && pair ? src2[m] : make_float2(0.f, 0.f);
+        lds[e] = make_float4(v.x, v.y, v2.x, v2.y);
     }
     const int n_b = nb0 + tid % RB;
     const int64_t mb = ((int64_t)n_b * (tid / RB)) % n;
@@ -382,37 +487,51 @@ __global__ __launch_bounds__(kNT) void rsf_sft_rows_k(SftRowsArgs A) {
     lds_fft_into<kNT, kFftEPT, RB, false>(lds, st, tws, Interleaved<RB>{}, sink, NoMid{});
 }
 
-// Output j = k_a + LA k_b of the chunk's transform: x[j0 + j] for j < n_keep.
+// One chunk's output: transform value (re, im) at j = k_a + LA k_b goes to
+// x[j0 + j] for j < n_keep, conjugated, tapered at the edges and phase
+// corrected.
+struct SeriesOut {
+    int64_t j0, n_keep;
+    float2 corr;
+    __device__ __forceinline__ void put(float2* x, int64_t n_out, int n_edge, int64_t jj, float re, float im) const {
+        const int64_t o = j0 + jj;
+        if (jj >= n_keep || o < 0 || o >= n_out) return;
+        const int e = (int)min((int64_t)n_edge, n_keep / 2);
+        // conjugate (inverse transform), then the chunk's phase correction
+        im = -im;
+        float g = 1.0f;
+        if (jj < e) g = 0.5f * (1.0f - cospif(((float)jj + 0.5f) / (float)e));
+        else if (jj >= n_keep - e) g = 0.5f * (1.0f - cospif(((float)(n_keep - 1 - jj) + 0.5f) / (float)e));
+        x[o] = make_float2(g * (re * corr.x - im * corr.y), g * (re * corr.y + im * corr.x));
+    }
+};
+
+// Output j = k_a + LA k_b of a chunk pair's transforms: the low halves to the
+// first chunk's series, the high halves to the second's (when there is one).
 struct SeriesSink {
     float2* x;
-    int64_t j0, n_keep, n_out;
+    int64_t n_out;
     int LA, LR, ka0, n_edge;
-    float2 corr;
+    SeriesOut c1, c2;
+    bool pair;
     template <int R>
     __device__ __forceinline__ void put(int, int j, int b, cp (&v)[R]) {
         const int ka = ka0 + b;
         if (ka >= LA) return;
-        const int e = (int)min((int64_t)n_edge, n_keep / 2);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int64_t jj = (int64_t)ka + (int64_t)LA * (j + r * LR);
-            const int64_t o = j0 + jj;
-            if (jj < n_keep && o >= 0 && o < n_out) {
-                // conjugate (inverse transform), then the chunk's phase correction
-                const float re = v[r].x, im = -v[r].y;
-                float g = 1.0f;
-                if (jj < e) g = 0.5f * (1.0f - cospif(((float)jj + 0.5f) / (float)e));
-                else if (jj >= n_keep - e) g = 0.5f * (1.0f - cospif(((float)(n_keep - 1 - jj) + 0.5f) / (float)e));
-                x[o] = make_float2(g * (re * corr.x - im * corr.y), g * (re * corr.y + im * corr.x));
-            }
+            c1.put(x, n_out, n_edge, jj, v[r].x, v[r].y);
+            if (pair) c2.put(x, n_out, n_edge, jj, v[r].z, v[r].w);
         }
     }
 };
 
 // Columns pass: workgroup w transforms the CB columns g CB .. g CB + CB - 1 of
-// its chunk (CB / 8 consecutive 8-column spill groups, one contiguous run)
-// over n_b and writes the series.  Columns at or past LA (padding of the last
-// group) are transformed but not written.
+// its chunk pair (CB / 8 consecutive 8-column spill groups of the first
+// chunk's spill, one contiguous run) over n_b and writes both series.
+// Columns at or past LA (padding of the last group) are transformed but not
+// written.
 template <int CB>
 __global__ __launch_bounds__(kNTB) void rsf_sft_cols_k(SftColsArgs B) {
     extern __shared__ float4 lds[];
@@ -429,12 +548,15 @@ __global__ __launch_bounds__(kNTB) void rsf_sft_cols_k(SftColsArgs B) {
     const int tid = threadIdx.x;
     for (int e = tid; e < 32 + n_hi; e += kNTB) twl[e] = (e < 32) ? L.t2[e] : L.t2_hi[e - 32];
     const TwLds tw{twl, twl + 32};
-    const SftChunkDev& ch = B.chunks[B.ids[L.id0 + i]];
+    const SftChunkDev& ch = B.chunks[B.ids[L.id0 + 2 * i]];
+    const bool pair = 2 * i + 1 < L.nc;
+    const SftChunkDev& ch2 = B.chunks[B.ids[L.id0 + (pair ? 2 * i + 1 : 2 * i)]];
     const float4* src = B.spill + ch.spill_off + (int64_t)c * blk;
     for (int e = tid; e < blk; e += kNTB) lds[e] = src[e];
     __syncthreads();
     const int r_last = st.n_stages ? st.radix[st.n_stages - 1] : 1;
-    SeriesSink sink{B.x, ch.j0, ch.n_keep, B.n_out, LA, LB / r_last, c * CB, B.n_edge, ch.corr};
+    SeriesSink sink{B.x, B.n_out, LA, LB / r_last, c * CB, B.n_edge, SeriesOut{ch.j0, ch.n_keep, ch.corr},
+                    SeriesOut{ch2.j0, ch2.n_keep, ch2.corr}, pair};
     lds_fft_into<kNTB, kPassBEPT, CB, false>(lds, st, tw, Grouped8{LB * kGroupCols}, sink, NoMid{});
 }
 
@@ -459,6 +581,20 @@ hipError_t launch_sft_dft(const SftDftArgs& a, int64_t blocks, size_t lds, hipSt
 }
 
 int64_t sft_merge_blocks(int n) { return (n + kMergeThreads - 1) / kMergeThreads; }
+
+int64_t sft_fused_blocks(int n) { return (n + kFuseBins - 1) / kFuseBins; }
+
+// the roots, and the SFT bins and DFT rows of the most stored bins a
+// workgroup's bins reach: ceil(1024 / M') + 1 + 2 dk
+size_t sft_fused_lds(int M, int Mp, int dk) {
+    const size_t rows = (size_t)((kFuseBins + Mp - 1) / Mp + 1 + 2 * dk);
+    return sizeof(float2) * ((size_t)Mp + rows * (size_t)(M + Mp));
+}
+
+hipError_t launch_sft_dftmerge(const SftMergeArgs& a, int64_t blocks, size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL(rsf_sft_dftmerge_k, dim3((unsigned)blocks), dim3(kMergeThreads), lds, s, a);
+    return hipGetLastError();
+}
 
 hipError_t launch_sft_merge(const SftMergeArgs& a, int64_t blocks, hipStream_t s) {
     hipLaunchKernelGGL(rsf_sft_merge_k, dim3((unsigned)blocks), dim3(kMergeThreads), 0, s, a);

@@ -71,6 +71,21 @@ def test_front_end_matches_oracle(gpu_lib, slots, n_slots):
         assert np.all(got[a:b] == 0)
 
 
+@pytest.mark.parametrize("fused", ["1", "0"])
+def test_fused_and_separate_dft_merge(gpu_lib, monkeypatch, fused):
+    """The DFT over the SFTs and the merge in one kernel (rows in LDS, the
+    default) and in two (the DFT tables through the workspace, taken when a
+    chunk is too long for the LDS; RSF_SFT_FUSED=0 forces it): both against
+    the oracle on chunks of 3, 5 (grid 6), 1 and 11 (grid 12) SFTs."""
+    monkeypatch.setenv("RSF_SFT_FUSED", fused)
+    for slots, n_slots in (([0, 1, 2, 4, 5, 6, 7, 8, 10], 11), ([1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11], 12)):
+        ss, X = _case(slots, n_slots, seed=20 + len(slots))
+        ref, gref = _oracle(ss, X)
+        got, gaps = _gpu(gpu_lib, ss, X)
+        assert np.array_equal(gaps, gref)
+        assert np.max(np.abs(got - ref)) <= 1e-4 * np.max(np.abs(ref)), (fused, len(slots))
+
+
 def test_without_normalisation_start_before_data_and_cut_end(gpu_lib):
     """median_window 0 (no normalisation), rectangular band, no edge taper,
     the series starting 1.5 s before the first SFT and ending inside the last
