@@ -245,11 +245,12 @@ int rsf_resample(const rsf_plan* plan, const rsf_segment* seg, const double* sky
  * 2F over the reported band for every (sky, fdot).
  * fdot: device float64[n_fdot] (Hz/s).  twoF: device float32
  * [n_sky * n_fdot][n_out], row = sky * n_fdot + fdot, ascending frequency.
- * mode RSF_MODE_PLAIN launches the two FFT passes once per template;
+ * mode RSF_MODE_PLAIN is the paper's chain per template: it resamples the
+ * series and launches the two FFT passes once per template;
  * RSF_MODE_BATCHED resamples several sky positions per launch, shares each
- * resampled series between 16 spindowns in the first FFT pass and runs 64
- * templates per launch (defaults; see rsf_plan_set_batching).  Both modes
- * give identical results. */
+ * resampled series between all spindowns of its sky and 16 of them in the
+ * first FFT pass, and runs 64 templates per launch (defaults; see
+ * rsf_plan_set_batching).  Both modes give identical results. */
 int rsf_fstat(const rsf_plan* plan, const rsf_segment* seg, const double* sky, int64_t n_sky,
               const double* fdot, int64_t n_fdot, int mode, float* twoF,
               void* ws, size_t ws_bytes, void* stream);

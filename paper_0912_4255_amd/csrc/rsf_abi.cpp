@@ -845,33 +845,41 @@ int run_fstat(const rsf_plan* p, const rsf_segment* seg, const double* sky, int6
 
     for (int64_t c0 = 0; c0 < n_sky; c0 += L.S) {
         const int sc = (int)std::min<int64_t>(L.S, n_sky - c0);
-        for (int X = 0; X < p->d.n_det; ++X) {
-            ResampleArgs a = base_resample_args(p, seg, X);
-            a.sky = sky + (p->binary ? 5 : 2) * c0;
-            a.sky_stride = p->binary ? 5 : 2;
-            a.binary = p->binary;
-            a.LB = p->LB;
-            a.P = p->P;
-            a.layout = 1;
-            a.f16 = f16;
-            a.rs_main = (float4*)(w + L.rs_main[X]);
-            a.rs_tm = f16 ? nullptr : (float*)(w + L.rs_tm[X]);
-            a.rs_sky_stride = L.rs_stride;
-            a.partials = (double*)(w + L.partials) + (size_t)X * sc * L.n_blocks * 3;
-            a.n_blocks = L.n_blocks;
-            a.flags = flags;
-            RSF_HIP(timed(p, K_RESAMPLE, s, [&] { return launch_resample(a, sc, s); }), "resample launch");
-        }
-        ReduceArgs r{};
-        r.partials = (const double*)(w + L.partials);
-        r.n_blocks = L.n_blocks;
-        r.n_det = p->d.n_det;
-        r.n_sky = sc;
-        for (int X = 0; X < p->d.n_det; ++X) r.w[X] = p->det[X].w;
-        r.abc_w = (double*)(w + L.abc_w);
-        r.coef = (float*)(w + L.coef);
-        r.flags = flags;
-        RSF_HIP(timed(p, K_REDUCE, s, [&] { return launch_antenna_reduce(r, s); }), "antenna reduce launch");
+        // steps 1-5 for the chunk's skies: the resampled series, A', B', C'
+        auto resample_chunk = [&]() -> int {
+            for (int X = 0; X < p->d.n_det; ++X) {
+                ResampleArgs a = base_resample_args(p, seg, X);
+                a.sky = sky + (p->binary ? 5 : 2) * c0;
+                a.sky_stride = p->binary ? 5 : 2;
+                a.binary = p->binary;
+                a.LB = p->LB;
+                a.P = p->P;
+                a.layout = 1;
+                a.f16 = f16;
+                a.rs_main = (float4*)(w + L.rs_main[X]);
+                a.rs_tm = f16 ? nullptr : (float*)(w + L.rs_tm[X]);
+                a.rs_sky_stride = L.rs_stride;
+                a.partials = (double*)(w + L.partials) + (size_t)X * sc * L.n_blocks * 3;
+                a.n_blocks = L.n_blocks;
+                a.flags = flags;
+                RSF_HIP(timed(p, K_RESAMPLE, s, [&] { return launch_resample(a, sc, s); }), "resample launch");
+            }
+            ReduceArgs r{};
+            r.partials = (const double*)(w + L.partials);
+            r.n_blocks = L.n_blocks;
+            r.n_det = p->d.n_det;
+            r.n_sky = sc;
+            for (int X = 0; X < p->d.n_det; ++X) r.w[X] = p->det[X].w;
+            r.abc_w = (double*)(w + L.abc_w);
+            r.coef = (float*)(w + L.coef);
+            r.flags = flags;
+            RSF_HIP(timed(p, K_REDUCE, s, [&] { return launch_antenna_reduce(r, s); }), "antenna reduce launch");
+            return RSF_OK;
+        };
+        // the plain path is the paper's chain per template: it resamples again
+        // before every template's FFTs (the batched path once per sky chunk)
+        const bool per_template = mode == RSF_MODE_PLAIN;
+        if (!per_template && (rc = resample_chunk()) != RSF_OK) return rc;
 
         // launches: (first sky of the chunk, skies, first spindown, spindowns)
         struct Launch {
@@ -889,6 +897,7 @@ int run_fstat(const rsf_plan* p, const rsf_segment* seg, const double* sky, int6
             for (int sk = 0; sk < sc; sk += per) launches.push_back({sk, std::min(per, sc - sk), 0, (int)n_fdot});
         }
         for (const Launch& q : launches) {
+            if (per_template && (rc = resample_chunk()) != RSF_OK) return rc;
             PassAArgs A{};
             A.n = p->n;
             A.n_fft = p->n_fft;
