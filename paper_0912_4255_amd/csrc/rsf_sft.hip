@@ -101,20 +101,28 @@ __global__ __launch_bounds__(kNormThreads) void rsf_sft_norm_k(SftNormArgs a) {
 }
 
 // Running median for windows of at most kNormRegMax bins: each thread slides
-// one window over kNormRun consecutive bins, holding it as a sorted array in
-// registers.  The array has kNormRegMax + 1 slots: the w values, (kNormRegMax - w) / 2
-// copies of -inf below and as many of +inf above, and one more +inf, so that
-// the median is always slot kNormRegMax / 2 (a constant index).  The first
-// window is sorted by a bitonic network; a step of the window removes the
-// outgoing value (every slot from its first copy on takes its upper
-// neighbour) and inserts the incoming one (slot i becomes
-// max(s[i-1], min(x, s[i])), i descending).  The powers of the workgroup's
-// bins are staged in LDS, and the gains go back through LDS so that the
-// scaled bins are written in order.
+// one window over kNormRun consecutive bins.  The window is a sorted array of
+// kNormRegMax + 1 slots: the w values, (kNormRegMax - w) / 2 copies of -inf
+// below and as many of +inf above, and one more +inf, so that the median is
+// always slot kNormRegMax / 2 (a constant index).  The first window is sorted
+// in registers by a bitonic network, and only the kNormBand slots centred on
+// the median are kept.  A step of the window removes the outgoing value y
+// (slot i becomes s[i] if s[i] < y, else s[i+1]) and inserts the incoming x
+// (slot i becomes max(s[i-1], min(x, s[i])), i descending), with +inf above
+// the band and -inf below it.  Both maps are monotone in the slots they read,
+// so a slot that held a lower (upper) bound of its true value still does, and
+// an exact slot stays exact while its neighbours are: each step turns at most
+// the band's outermost exact slot on either side into a bound.  The band holds
+// kNormRun - 1 slots on either side of the median, one per step of a run, so
+// the median slot is exact throughout.  The powers of the workgroup's bins are
+// staged in LDS, and the gains go back through LDS so that the scaled bins are
+// written in order.
 namespace {
 constexpr int kNormRegMax = 127;              // odd; slots kNormRegMax + 1 = 128 = 2^7
 constexpr int kNormRun = 15;                  // bins per thread (odd: conflict-free LDS strides)
 constexpr int kNormTile = kNormThreads * kNormRun;
+constexpr int kNormBandHalf = kNormRun - 1;   // steps of one run
+constexpr int kNormBand = 2 * kNormBandHalf + 1;
 
 __device__ __forceinline__ void cmp_swap(float& lo, float& hi) {
     const float a = fminf(lo, hi), b = fmaxf(lo, hi);
@@ -170,6 +178,9 @@ void rsf_sft_norm_reg_k(SftNormArgs a) {
             v[i] = (j < 0) ? -__builtin_inff() : ((j < w) ? pw[lo - base + j] : __builtin_inff());
         }
         sort_regs<7>(v);
+        float b[kNormBand];
+#pragma unroll
+        for (int i = 0; i < kNormBand; ++i) b[i] = v[kNormRegMax / 2 - kNormBandHalf + i];
 #pragma unroll 1
         for (int k = kt; k < min(kt + kNormRun, kend); ++k) {
             const int lk = lo_of(k);
@@ -177,13 +188,14 @@ void rsf_sft_norm_reg_k(SftNormArgs a) {
                 const float y = pw[lo - base];
                 const float x = pw[lo + w - base];
 #pragma unroll
-                for (int i = 0; i + 1 < S; ++i) v[i] = (v[i] < y) ? v[i] : v[i + 1];
+                for (int i = 0; i + 1 < kNormBand; ++i) b[i] = (b[i] < y) ? b[i] : b[i + 1];
+                b[kNormBand - 1] = (b[kNormBand - 1] < y) ? b[kNormBand - 1] : __builtin_inff();
 #pragma unroll
-                for (int i = S - 1; i > 0; --i) v[i] = fmaxf(v[i - 1], fminf(x, v[i]));
-                v[0] = fminf(x, v[0]);
+                for (int i = kNormBand - 1; i > 0; --i) b[i] = fmaxf(b[i - 1], fminf(x, b[i]));
+                b[0] = fminf(x, b[0]);
                 lo = lk;
             }
-            const float med = v[kNormRegMax / 2];
+            const float med = b[kNormBandHalf];
             gain[k - k0] = med > 0.f ? sqrtf(0.69314718055994531f / med) : 0.f;
         }
     }
@@ -304,27 +316,52 @@ __global__ __launch_bounds__(kMergeThreads) void rsf_sft_merge_k(SftMergeArgs a)
 // The DFT over the SFTs and the merge in one pass, without the tables in
 // HBM: workgroup g of a chunk takes its band bins u in [1024 g, 1024 g +
 // 1024).  The stored bins k those bins reach (k* of the first and last bin,
-// +- dk) come into LDS for every SFT of the chunk in one coalesced load; the
-// rows Y[k][.] are formed there and merged as in rsf_sft_merge_k.  The
-// phases W^{r alpha} are running products of W^r, the terms' sines come from
-// the hardware sine (argument in revolutions) and their reciprocals from
-// v_rcp_f32 (each within a few 1e-7 relative).  Chosen when every chunk fits
-// the LDS (sft_fused_lds).
+// +- dk) come into LDS for every SFT of the chunk in one coalesced load (each
+// thread with up to kFuseLoads loads in flight); the rows Y[k][.] are formed
+// there and merged as in rsf_sft_merge_k.  The phases W^{r alpha} are
+// running products of W^r, the terms' sines come from the hardware sine
+// (argument in revolutions) and their reciprocals from v_rcp_f32 (each within
+// a few 1e-7 relative).  The merge runs 2 DK + 1 terms without branches (a
+// term outside [-dk, dk] or the stored band reads a row in range and weighs
+// it by zero), so that its LDS reads are issued together.  Chosen when every
+// chunk fits the LDS (sft_fused_lds).
 namespace {
 constexpr int kFuseBins = 1024;
-}
+constexpr int kFuseLoads = 8;
 
+// q = x / d and x mod d for 0 <= x < 2^21, 0 < d: the float quotient
+// x * (1/d) is within one of the exact one, and one correction each way
+// makes it exact
+__device__ __forceinline__ int div_small(int x, int d, float inv_d, int* rem) {
+    int q = (int)((float)x * inv_d);
+    int r = x - q * d;
+    if (r < 0) {
+        --q;
+        r += d;
+    } else if (r >= d) {
+        ++q;
+        r -= d;
+    }
+    *rem = r;
+    return q;
+}
+}  // namespace
+
+template <int DK>
 __global__ __launch_bounds__(kMergeThreads) void rsf_sft_dftmerge_k(SftMergeArgs a) {
     extern __shared__ float2 sh[];
     const SftChunkDev c = a.chunks[sft_chunk_of<&SftChunkDev::fblk0>(a.chunks, a.n_chunks, blockIdx.x)];
     const int n = c.n, Mp = c.Mp, M = c.M;
     const int u0 = (int)((int64_t)blockIdx.x - c.fblk0) * kFuseBins;
     const int u1 = min(u0 + kFuseBins, n);
-    const int64_t ks_first = (c.b0 - n / 2 + u0) / Mp;
-    const int64_t ks_last = (c.b0 - n / 2 + u1 - 1) / Mp;
+    const int64_t bb = c.b0 - n / 2 + u0;  // band bin of u0 (b = k* M' + r >= 0)
+    const int64_t ks_first = bb / Mp;
+    const int r_first = (int)(bb - ks_first * Mp);
+    const int64_t ks_last = (bb + (u1 - 1 - u0)) / Mp;
     const int64_t k_min = max(ks_first - a.dk, a.k_lo);
     const int64_t k_max = min(ks_last + a.dk, a.k_lo + a.K - 1);
     const int rows = k_max >= k_min ? (int)(k_max - k_min + 1) : 0;
+    const float inv_mp = 1.0f / (float)Mp;
     float2* roots = sh;                // M'
     float2* Xt = roots + Mp;           // [M][rows]: X^_{a0 + alpha, k_min + kr}
     float2* Yt = Xt + M * rows;        // [rows][M']
@@ -334,14 +371,29 @@ __global__ __launch_bounds__(kMergeThreads) void rsf_sft_dftmerge_k(SftMergeArgs
         roots[i] = make_float2(co, -s);
     }
     const float2* xk = a.xh + (int64_t)c.a0 * a.K + (k_min - a.k_lo);
-    for (int i = threadIdx.x; i < M * rows; i += kMergeThreads) {
-        const int al = i / rows;
-        Xt[i] = xk[(int64_t)al * a.K + (i - al * rows)];
+    const int n_x = M * rows;
+    const float inv_rows = 1.0f / (float)max(rows, 1);
+    for (int i0 = 0; i0 < n_x; i0 += kMergeThreads * kFuseLoads) {
+        float2 v[kFuseLoads];
+#pragma unroll
+        for (int j = 0; j < kFuseLoads; ++j) {
+            const int i = i0 + j * kMergeThreads + (int)threadIdx.x;
+            if (i < n_x) {
+                int kr;
+                const int al = div_small(i, rows, inv_rows, &kr);
+                v[j] = xk[(int64_t)al * a.K + kr];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kFuseLoads; ++j) {
+            const int i = i0 + j * kMergeThreads + (int)threadIdx.x;
+            if (i < n_x) Xt[i] = v[j];
+        }
     }
     __syncthreads();
     for (int e = threadIdx.x; e < rows * Mp; e += kMergeThreads) {
-        const int kr = e / Mp;
-        const int r = e - kr * Mp;
+        int r;
+        const int kr = div_small(e, Mp, inv_mp, &r);
         // W_{M'}^{r alpha} by repeated products of W_{M'}^r (M <= M' factors,
         // a few ulp each): the threads of one k read the same X^ (one LDS
         // broadcast) and no table
@@ -357,33 +409,36 @@ __global__ __launch_bounds__(kMergeThreads) void rsf_sft_dftmerge_k(SftMergeArgs
         Yt[e] = acc;
     }
     __syncthreads();
-    const float inv_mp = 1.0f / (float)Mp;
+    if (rows == 0) {
+        for (int u = u0 + (int)threadIdx.x; u < u1; u += kMergeThreads) {
+            const int q = u - n / 2;
+            a.y[c.y_off + (q < 0 ? q + n : q)] = make_float2(0.f, 0.f);
+        }
+        return;
+    }
     for (int u = u0 + (int)threadIdx.x; u < u1; u += kMergeThreads) {
-        const int64_t b = c.b0 - n / 2 + u;
-        const int64_t ks = b / Mp;
-        const int r = (int)(b - ks * Mp);
+        int r;
+        const int64_t ks = ks_first + div_small(r_first + (u - u0), Mp, inv_mp, &r);
         const float fr = (float)r * inv_mp;                // r / M' in [0, 1)
         const float sy = __builtin_amdgcn_sinf(fr);        // sin(2 pi r / M')
         const float sh2 = __builtin_amdgcn_sinf(0.5f * fr);  // sin(pi r / M')
         const float omc = 2.0f * sh2 * sh2;                // 1 - cos y
         const int d_lo = (int)max((int64_t)-a.dk, a.k_lo - ks);
         const int d_hi = (int)min((int64_t)a.dk, a.k_lo + a.K - 1 - ks);
+        const int kr0 = (int)(ks - k_min);                 // row of d = 0
         float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
-        for (int t = 0; t < kSftMaxTerms; ++t) {
-            const int d = t - a.dk;
-            if (d >= d_lo && d <= d_hi) {
-                float2 P;
-                if (r == 0) {
-                    P = make_float2(d == 0 ? 1.f : 0.f, 0.f);
-                } else {
-                    const float inv = __builtin_amdgcn_rcpf(6.28318530717958648f * (fr - (float)d));
-                    P = make_float2(sy * inv, -omc * inv);
-                }
-                const float2 v = Yt[(ks + d - k_min) * Mp + r];
-                acc.x += v.x * P.x - v.y * P.y;
-                acc.y += v.x * P.y + v.y * P.x;
-            }
+        for (int t = 0; t <= 2 * DK; ++t) {
+            const int d = t - DK;
+            const float2 v = Yt[min(max(kr0 + d, 0), rows - 1) * Mp + r];
+            const float inv = __builtin_amdgcn_rcpf(6.28318530717958648f * (fr - (float)d));
+            float px = r == 0 ? (d == 0 ? 1.f : 0.f) : sy * inv;
+            float py = r == 0 ? 0.f : -omc * inv;
+            const bool on = d >= d_lo && d <= d_hi;
+            px = on ? px : 0.f;
+            py = on ? py : 0.f;
+            acc.x += v.x * px - v.y * py;
+            acc.y += v.x * py + v.y * px;
         }
         float wgt = 1.0f;
         if (a.taper > 0.f) {
@@ -592,7 +647,11 @@ size_t sft_fused_lds(int M, int Mp, int dk) {
 }
 
 hipError_t launch_sft_dftmerge(const SftMergeArgs& a, int64_t blocks, size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL(rsf_sft_dftmerge_k, dim3((unsigned)blocks), dim3(kMergeThreads), lds, s, a);
+    static_assert(2 * 16 + 1 == kSftMaxTerms, "the wide merge instance covers every dk");
+    if (a.dk <= 8)
+        hipLaunchKernelGGL(rsf_sft_dftmerge_k<8>, dim3((unsigned)blocks), dim3(kMergeThreads), lds, s, a);
+    else
+        hipLaunchKernelGGL(rsf_sft_dftmerge_k<16>, dim3((unsigned)blocks), dim3(kMergeThreads), lds, s, a);
     return hipGetLastError();
 }
 

@@ -106,6 +106,17 @@ def test_single_sft_chunks_and_few_dirichlet_terms(gpu_lib):
     assert np.max(np.abs(got - ref)) <= 1e-4 * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("dk", [9, 16])
+def test_many_dirichlet_terms(gpu_lib, dk):
+    """dk above 8 takes the merge instance with 33 unrolled terms (those
+    beyond dk weighted by zero); 16 is the largest dk."""
+    ss, X = _case([0, 1, 2, 4, 5, 6, 7, 8, 10], 11, seed=30 + dk, dk=dk)
+    ref, gref = _oracle(ss, X)
+    got, gaps = _gpu(gpu_lib, ss, X)
+    assert np.array_equal(gaps, gref)
+    assert np.max(np.abs(got - ref)) <= 1e-4 * np.max(np.abs(ref)), dk
+
+
 @pytest.mark.parametrize("median_window", [1, 127, 129, 131])
 def test_running_median_window_sizes(gpu_lib, median_window):
     """Windows up to 127 bins take the register running median, longer ones
