@@ -26,6 +26,7 @@ constexpr int kNormThreads = 256;
 constexpr int kNormSort = 1024;  // >= kNormThreads + kSftMaxWindow - 1, a power of two
 constexpr int kNT = kFftThreads;
 constexpr int kNTB = kPassBThreads;
+constexpr int kSftLoads = 8;     // global loads in flight per thread where a kernel stages its input in LDS
 }  // namespace
 
 // Running median for windows longer than kNormRegMax bins (the register
@@ -105,11 +106,12 @@ __global__ __launch_bounds__(kNormThreads) void rsf_sft_norm_k(SftNormArgs a) {
 // kNormRegMax + 1 slots: the w values, (kNormRegMax - w) / 2 copies of -inf
 // below and as many of +inf above, and one more +inf, so that the median is
 // always slot kNormRegMax / 2 (a constant index).  The first window is sorted
-// in registers by a bitonic network, and only the kNormBand slots centred on
+// in registers by a sorting network, and only the kNormBand slots centred on
 // the median are kept.  A step of the window removes the outgoing value y
 // (slot i becomes s[i] if s[i] < y, else s[i+1]) and inserts the incoming x
-// (slot i becomes max(s[i-1], min(x, s[i])), i descending), with +inf above
-// the band and -inf below it.  Both maps are monotone in the slots they read,
+// (slot i becomes max(s[i-1], min(x, s[i])), i descending: the median of
+// s[i-1], x and s[i], one v_med3_f32, since the band stays sorted), with +inf
+// above the band and -inf below it.  Both maps are monotone in the slots they read,
 // so a slot that held a lower (upper) bound of its true value still does, and
 // an exact slot stays exact while its neighbours are: each step turns at most
 // the band's outermost exact slot on either side into a bound.  The band holds
@@ -130,22 +132,29 @@ __device__ __forceinline__ void cmp_swap(float& lo, float& hi) {
     hi = b;
 }
 
-// ascending bitonic sort of N = 2^LOG2N values in registers
+// ascending sort of N = 2^LOG2N values in registers by Batcher's odd-even
+// merge sort: at merge level p = 2^LP (runs of p sorted values merged into
+// runs of 2p) and distance k = 2^LK = p, p/2, .., 1, slot a is compared with
+// a + k when both lie in one run of 2p and (a - k mod p) mod 2k < k.  One
+// instance per (p, k), so every bound is a compile-time constant and the
+// network unrolls to min/max pairs on fixed registers (1471 comparators for
+// N = 128, against 1792 for a bitonic network; those that feed no kept slot
+// are removed by the compiler).
+template <int LOG2N, int LP, int LK>
+__device__ __forceinline__ void oe_merge_sort(float (&v)[1 << LOG2N]) {
+    constexpr int N = 1 << LOG2N, p = 1 << LP, k = 1 << LK, r = k % p;
+#pragma unroll
+    for (int a = 0; a + k < N; ++a)
+        if (a >= r && (a - r) % (2 * k) < k && a / (2 * p) == (a + k) / (2 * p)) cmp_swap(v[a], v[a + k]);
+    if constexpr (LK > 0)
+        oe_merge_sort<LOG2N, LP, LK - 1>(v);
+    else if constexpr (LP + 1 < LOG2N)
+        oe_merge_sort<LOG2N, LP + 1, LP + 1>(v);
+}
+
 template <int LOG2N>
 __device__ __forceinline__ void sort_regs(float (&v)[1 << LOG2N]) {
-    constexpr int N = 1 << LOG2N;
-#pragma unroll
-    for (int ls = 1; ls <= LOG2N; ++ls)
-#pragma unroll
-        for (int lt = ls - 1; lt >= 0; --lt)
-#pragma unroll
-            for (int i = 0; i < N; ++i) {
-                const int l = i ^ (1 << lt);
-                if (l > i) {
-                    if ((i & (1 << ls)) == 0) cmp_swap(v[i], v[l]);
-                    else cmp_swap(v[l], v[i]);
-                }
-            }
+    oe_merge_sort<LOG2N, 0, 0>(v);
 }
 }  // namespace
 
@@ -191,7 +200,7 @@ void rsf_sft_norm_reg_k(SftNormArgs a) {
                 for (int i = 0; i + 1 < kNormBand; ++i) b[i] = (b[i] < y) ? b[i] : b[i + 1];
                 b[kNormBand - 1] = (b[kNormBand - 1] < y) ? b[kNormBand - 1] : __builtin_inff();
 #pragma unroll
-                for (int i = kNormBand - 1; i > 0; --i) b[i] = fmaxf(b[i - 1], fminf(x, b[i]));
+                for (int i = kNormBand - 1; i > 0; --i) b[i] = __builtin_amdgcn_fmed3f(b[i - 1], x, b[i]);
                 b[0] = fminf(x, b[0]);
                 lo = lk;
             }
@@ -317,7 +326,7 @@ __global__ __launch_bounds__(kMergeThreads) void rsf_sft_merge_k(SftMergeArgs a)
 // HBM: workgroup g of a chunk takes its band bins u in [1024 g, 1024 g +
 // 1024).  The stored bins k those bins reach (k* of the first and last bin,
 // +- dk) come into LDS for every SFT of the chunk in one coalesced load (each
-// thread with up to kFuseLoads loads in flight); the rows Y[k][.] are formed
+// thread with up to kSftLoads loads in flight); the rows Y[k][.] are formed
 // there and merged as in rsf_sft_merge_k.  The phases W^{r alpha} are
 // running products of W^r, the terms' sines come from the hardware sine
 // (argument in revolutions) and their reciprocals from v_rcp_f32 (each within
@@ -327,7 +336,6 @@ __global__ __launch_bounds__(kMergeThreads) void rsf_sft_merge_k(SftMergeArgs a)
 // chunk fits the LDS (sft_fused_lds).
 namespace {
 constexpr int kFuseBins = 1024;
-constexpr int kFuseLoads = 8;
 
 // q = x / d and x mod d for 0 <= x < 2^21, 0 < d: the float quotient
 // x * (1/d) is within one of the exact one, and one correction each way
@@ -373,10 +381,10 @@ __global__ __launch_bounds__(kMergeThreads) void rsf_sft_dftmerge_k(SftMergeArgs
     const float2* xk = a.xh + (int64_t)c.a0 * a.K + (k_min - a.k_lo);
     const int n_x = M * rows;
     const float inv_rows = 1.0f / (float)max(rows, 1);
-    for (int i0 = 0; i0 < n_x; i0 += kMergeThreads * kFuseLoads) {
-        float2 v[kFuseLoads];
+    for (int i0 = 0; i0 < n_x; i0 += kMergeThreads * kSftLoads) {
+        float2 v[kSftLoads];
 #pragma unroll
-        for (int j = 0; j < kFuseLoads; ++j) {
+        for (int j = 0; j < kSftLoads; ++j) {
             const int i = i0 + j * kMergeThreads + (int)threadIdx.x;
             if (i < n_x) {
                 int kr;
@@ -385,7 +393,7 @@ __global__ __launch_bounds__(kMergeThreads) void rsf_sft_dftmerge_k(SftMergeArgs
             }
         }
 #pragma unroll
-        for (int j = 0; j < kFuseLoads; ++j) {
+        for (int j = 0; j < kSftLoads; ++j) {
             const int i = i0 + j * kMergeThreads + (int)threadIdx.x;
             if (i < n_x) Xt[i] = v[j];
         }
@@ -519,13 +527,24 @@ __global__ __launch_bounds__(kNT) void rsf_sft_rows_k(SftRowsArgs A) {
     const float2* src = A.y + c.y_off;
     const float2* src2 = A.y + (pair ? A.chunks[A.ids[L.id0 + 2 * i + 1]].y_off : c.y_off);
     const int tid = threadIdx.x;
-    for (int e = tid; e < LA * RB; e += kNT) {
-        const int n_a = e / RB, b = e - n_a * RB;
-        const bool in = nb0 + b < LB;
-        const int64_t m = (int64_t)LB * n_a + nb0 + b;
-        const float2 v = in ? src[m] : make_float2(0.f, 0.f);
-        const float2 v2 = in && pair ? src2[m] : make_float2(0.f, 0.f);
-        lds[e] = make_float4(v.x, v.y, v2.x, v2.y);
+    // kSftLoads elements per thread in flight, then into LDS
+    for (int e0 = 0; e0 < LA * RB; e0 += kNT * kSftLoads) {
+        float4 v[kSftLoads];
+#pragma unroll
+        for (int j = 0; j < kSftLoads; ++j) {
+            const int e = e0 + j * kNT + tid;
+            const int n_a = e / RB, b = e - n_a * RB;
+            const bool in = e < LA * RB && nb0 + b < LB;
+            const int64_t m = (int64_t)LB * n_a + nb0 + b;
+            const float2 x1 = in ? src[m] : make_float2(0.f, 0.f);
+            const float2 x2 = in && pair ? src2[m] : make_float2(0.f, 0.f);
+            v[j] = make_float4(x1.x, x1.y, x2.x, x2.y);
+        }
+#pragma unroll
+        for (int j = 0; j < kSftLoads; ++j) {
+            const int e = e0 + j * kNT + tid;
+            if (e < LA * RB) lds[e] = v[j];
+        }
     }
     const int n_b = nb0 + tid % RB;
     const int64_t mb = ((int64_t)n_b * (tid / RB)) % n;
@@ -607,7 +626,19 @@ __global__ __launch_bounds__(kNTB) void rsf_sft_cols_k(SftColsArgs B) {
     const bool pair = 2 * i + 1 < L.nc;
     const SftChunkDev& ch2 = B.chunks[B.ids[L.id0 + (pair ? 2 * i + 1 : 2 * i)]];
     const float4* src = B.spill + ch.spill_off + (int64_t)c * blk;
-    for (int e = tid; e < blk; e += kNTB) lds[e] = src[e];
+    for (int e0 = 0; e0 < blk; e0 += kNTB * kSftLoads) {
+        float4 v[kSftLoads];
+#pragma unroll
+        for (int j = 0; j < kSftLoads; ++j) {
+            const int e = e0 + j * kNTB + tid;
+            v[j] = e < blk ? src[e] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int j = 0; j < kSftLoads; ++j) {
+            const int e = e0 + j * kNTB + tid;
+            if (e < blk) lds[e] = v[j];
+        }
+    }
     __syncthreads();
     const int r_last = st.n_stages ? st.radix[st.n_stages - 1] : 1;
     SeriesSink sink{B.x, B.n_out, LA, LB / r_last, c * CB, B.n_edge, SeriesOut{ch.j0, ch.n_keep, ch.corr},
