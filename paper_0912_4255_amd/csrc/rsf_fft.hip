@@ -198,6 +198,18 @@ __device__ __forceinline__ void wave_col_read(const float4* blk, int b, int lane
 // c' * 64 + (l ^ X(c')), X = 4 c' (K = 2) or c' (K = 3), so that the 16
 // lanes an LDS cycle serves read 16 different bank groups.  HALF: slots of
 // one complex value (float2, a 2 KB region), the two spectra in turn.
+// 16-byte LDS accesses as single vector loads and stores (not four dword
+// accesses merged later), so that each keeps the alias information of the
+// LDS array it addresses
+typedef float f4v __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ cp lds_read4(const cp* p) {
+    const f4v t = *reinterpret_cast<const f4v*>(p);
+    return make_float4(t.x, t.y, t.z, t.w);
+}
+__device__ __forceinline__ void lds_write4(cp* p, cp v) {
+    *reinterpret_cast<f4v*>(p) = f4v{v.x, v.y, v.z, v.w};
+}
+
 template <int E, int K, bool HALF = false>
 __device__ __forceinline__ void wave_exchange(cp* __restrict__ x, int lane, int c, int src0, int s, cp (&v)[E]) {
     constexpr int Q = E / 4;
@@ -235,11 +247,11 @@ __device__ __forceinline__ void wave_exchange(cp* __restrict__ x, int lane, int 
             }
         } else {
 #pragma unroll
-            for (int cc = 0; cc < 4; ++cc) x[cc * 64 + (lane ^ (K == 2 ? 4 * cc : cc))] = v[cc * Q + e];
+            for (int cc = 0; cc < 4; ++cc) lds_write4(x + cc * 64 + (lane ^ (K == 2 ? 4 * cc : cc)), v[cc * Q + e]);
             sync();
             const cp* row = x + c * 64;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) v[i * Q + e] = row[(src0 + i * s) ^ xr];
+            for (int i = 0; i < 4; ++i) v[i * Q + e] = lds_read4(row + ((src0 + i * s) ^ xr));
             sync();
         }
     }
@@ -504,12 +516,18 @@ __global__ __launch_bounds__(kWaveColsThreads) void rsf_fft_pass_b_wave_k(PassBA
     constexpr int LBW = 64 * E;
     constexpr bool kDirect = E == 16;
     static_assert(!kDirect || TOPK, "1024-point columns feed the top-k gate only");
+    // The block, the exchange slots, the 2F stage and the gate's state are
+    // LDS arrays of their own: the compiler then knows that the transform's
+    // LDS accesses cannot touch the block the next DMA is filling, and does
+    // not wait for that DMA before them.  Only the coefficients (read before
+    // the DMA is issued) are in the dynamic LDS.
+    __shared__ float4 blk[kPassBCols * LBW];                        // the block, 8 columns x LB
+    __shared__ cp xch[kPassBCols * (kDirect ? 2 : 4) * 64];         // 8 waves x 4 x 64 slots
+    __shared__ float st[kDirect ? 1 : LBW * kPassBCols];            // 2F stage [LB][8]
+    __shared__ WaveTopkLds tkl_s;
     extern __shared__ float4 lds[];
-    float4* blk = lds;                                              // the block, 8 columns x LB
-    cp* xch = lds + kPassBCols * LBW;                               // 8 waves x 4 x 64 slots
-    float* st = reinterpret_cast<float*>(xch + kPassBCols * (kDirect ? 2 : 4) * 64);  // 2F stage [LB][8]
-    float* cfl = kDirect ? st : st + LBW * kPassBCols;              // 4 per sky of the launch
-    WaveTopkLds* tkl = reinterpret_cast<WaveTopkLds*>(cfl + 4 * (B.n_sky_l > 64 ? B.n_sky_l : 64));
+    float* cfl = reinterpret_cast<float*>(lds);                     // 4 per sky of the launch
+    WaveTopkLds* tkl = &tkl_s;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int p = lane >> 4, q = (lane >> 2) & 3, r = lane & 3;
     for (int i = tid; i < 4 * B.n_sky_l; i += kWaveColsThreads) cfl[i] = B.coef[i];
@@ -540,13 +558,13 @@ __global__ __launch_bounds__(kWaveColsThreads) void rsf_fft_pass_b_wave_k(PassBA
             const bool live = (unit - t * B.n_groups) * kPassBCols + wave < B.LA;
             cp v[E];
             if (live) wave_col_read<E>(blk, wave, lane, v);
+            const int s_l = t / B.nf_l;
+            const float cA = cfl[4 * s_l], cB = cfl[4 * s_l + 1], cC = cfl[4 * s_l + 2];
             __syncthreads();  // the block buffer is free
             if (unit + G < n_units) wave_dma<NT>(B, unit + G, blk, wave, lane);
             float tf[E];
             if (live) {
                 wave_transform<E, true>(tw, x, lane, v);
-                const int s_l = t / B.nf_l;
-                const float cA = cfl[4 * s_l], cB = cfl[4 * s_l + 1], cC = cfl[4 * s_l + 2];
 #pragma unroll
                 for (int j = 0; j < E; ++j) tf[j] = two_f(v[j], cA, cB, cC);
             }
@@ -565,6 +583,8 @@ __global__ __launch_bounds__(kWaveColsThreads) void rsf_fft_pass_b_wave_k(PassBA
         const bool live = ka < B.LA;
         cp v[E];
         if (live) wave_col_read<E>(blk, wave, lane, v);
+        const int s_l = t / B.nf_l;
+        const float cA = cfl[4 * s_l], cB = cfl[4 * s_l + 1], cC = cfl[4 * s_l + 2];
         if (prev >= 0) {
             if constexpr (TOPK)
                 wave_topk<E>(B, prev, st, tid, hnf, nf, tkl);
@@ -575,8 +595,6 @@ __global__ __launch_bounds__(kWaveColsThreads) void rsf_fft_pass_b_wave_k(PassBA
         if (unit + G < n_units) wave_dma<NT>(B, unit + G, blk, wave, lane);
         if (live) {
             wave_transform<E>(tw, x, lane, v);
-            const int s_l = t / B.nf_l;
-            const float cA = cfl[4 * s_l], cB = cfl[4 * s_l + 1], cC = cfl[4 * s_l + 2];
 #pragma unroll
             for (int b1 = 0; b1 < 4; ++b1)
 #pragma unroll
@@ -719,9 +737,11 @@ int fft_pass_b_grid(const PassBArgs& b, int n_cu) {
 
 hipError_t launch_fft_pass_b(const PassBArgs& b, int n_cu, hipStream_t s) {
     const size_t lds = fft_pass_b_lds(b.LB, b.n_sky_l, b.topk != 0);
+    // the wave kernels' block, exchange slots, stage and gate state are static
+    const size_t lds_wave = (size_t)4 * std::max(b.n_sky_l, 64) * sizeof(float);
     const unsigned grid = (unsigned)fft_pass_b_grid(b, n_cu);
 #define RSF_PASS_B_WAVE1(EE, NTT, TK) \
-    hipLaunchKernelGGL((rsf_fft_pass_b_wave_k<EE, NTT, TK>), dim3(grid), dim3(kWaveColsThreads), lds, s, b)
+    hipLaunchKernelGGL((rsf_fft_pass_b_wave_k<EE, NTT, TK>), dim3(grid), dim3(kWaveColsThreads), lds_wave, s, b)
 #define RSF_PASS_B_WAVE(EE)                  \
     case EE:                                 \
         if (b.nt_spill) {                    \
@@ -762,15 +782,9 @@ hipError_t fft_set_lds_limits(size_t bytes) {
     // undo a larger one
     static size_t granted = 0;
     if (bytes <= granted) return hipSuccess;
-    const void* fns[] = {
-                         (const void*)rsf_fft_pass_b_k<false>,        (const void*)rsf_fft_pass_b_k<true>,
-                         (const void*)rsf_fft_pass_b_wave_k<4, false, false>, (const void*)rsf_fft_pass_b_wave_k<4, true, false>,
-                         (const void*)rsf_fft_pass_b_wave_k<8, false, false>, (const void*)rsf_fft_pass_b_wave_k<8, true, false>,
-                         (const void*)rsf_fft_pass_b_wave_k<12, false, false>, (const void*)rsf_fft_pass_b_wave_k<12, true, false>,
-                         (const void*)rsf_fft_pass_b_wave_k<4, false, true>, (const void*)rsf_fft_pass_b_wave_k<4, true, true>,
-                         (const void*)rsf_fft_pass_b_wave_k<8, false, true>, (const void*)rsf_fft_pass_b_wave_k<8, true, true>,
-                         (const void*)rsf_fft_pass_b_wave_k<12, false, true>, (const void*)rsf_fft_pass_b_wave_k<12, true, true>,
-                         (const void*)rsf_fft_pass_b_wave_k<16, false, true>, (const void*)rsf_fft_pass_b_wave_k<16, true, true>};
+    // (the wave kernels of the second pass hold their LDS statically and
+    // take 1 KB of dynamic LDS at most)
+    const void* fns[] = {(const void*)rsf_fft_pass_b_k<false>, (const void*)rsf_fft_pass_b_k<true>};
     hipError_t out = hipSuccess;
     auto set = [&](const void* f) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
