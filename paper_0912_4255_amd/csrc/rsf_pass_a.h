@@ -278,11 +278,17 @@ __global__ __launch_bounds__(kRowThreads) void rsf_fft_pass_a_k(PassAArgs A) {
     const int64_t ml = ((int64_t)n_b * lr) % A.n_fft;
     const float2 w_lr = c_mul(A.tw_hi[ml >> kTwSplitBits], A.tw_lo[ml & msk]);
 
+    // The spindowns are read as uniform values through the constant address
+    // space (scalar loads, counted apart from the vector memory operations):
+    // a vector load here would make the next template's first wait for it
+    // also wait for every spill store of the template before.
+    const __attribute__((address_space(4))) double* fdot_c =
+        (const __attribute__((address_space(4))) double*)A.fdot;
     for (int f = f_lo; f < f_hi; ++f) {
         const int t = s_l * A.nf_l + f;
         Spin<ORDER> fd;
 #pragma unroll
-        for (int j = 0; j < ORDER; ++j) fd.f[j] = A.fdot[(int64_t)f * ORDER + j];
+        for (int j = 0; j < ORDER; ++j) fd.f[j] = fdot_c[(int64_t)f * ORDER + j];
 #pragma unroll
         for (int q = 0; q < kInPer; ++q) {
             const int n_a = tid + q * kRowThreads;
